@@ -1,0 +1,221 @@
+"""LNV density-matrix functional, gradients and CG minimisation (dense FP64).
+
+Test infrastructure only (see the package docstring).  Every matrix here is a
+dense N_orb x N_orb numpy array; range truncation is a 0/1 orbital mask.
+
+Sec. II.C.2 of the paper defines the method:
+  * the density matrix is written through an auxiliary matrix L of restricted
+    range with the McWeeny form  K = 3LSL - 2LSLSL ;
+  * the band energy E = 2 Tr[KH] is minimised with respect to the elements of
+    L, using the gradient dE/dL, under a constraint on the electron number,
+    N = 2 Tr[KS] (spin-degenerate occupation, the same factor 2 as in E);
+  * K has the range of H; it is L whose range is restricted.
+Sec. V.C (gramicidin A run) states that the search direction of the density
+matrix minimisation is reset every 40 iterations.
+
+The paper does not spell out the electron-number scheme, the CG flavour, the
+line search or the initial L beyond naming their sources; the readings taken
+here are: gradient projection against dN/dL, Polak-Ribiere (clamped at zero)
+directions with the 40-step reset, exact minimisation of the cubic
+Omega(alpha) = (E - mu N)(L + alpha D), a cubic electron-number correction
+along dN/dL after each step, and L0 = lambda * T on L's range with lambda the
+smallest positive root of N(lambda T) = N_e.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def tr_prod(A, B):
+    """Tr[A B] = sum_ab A_ab B_ba."""
+    return float(np.einsum("ab,ba->", A, B))
+
+
+def dot(A, B):
+    """<A, B> = sum_ab A_ab B_ab."""
+    return float(np.sum(A * B))
+
+
+# ------------------------------------------------------------------ functional
+def mcweeny(L, S):
+    """K = 3LSL - 2LSLSL (Sec. II.C.2)."""
+    LSL = L @ S @ L
+    return 3.0 * LSL - 2.0 * (LSL @ S @ L)
+
+
+def evaluate(L, S, H, maskL):
+    """E = 2Tr[KH], N = 2Tr[KS], G = dE/dL and F = dN/dL on L's range.
+
+    With E = 6 Tr[LSLH] - 4 Tr[LSLSLH], differentiating each entry of L:
+      G = 2 [3 (SLH + HLS) - 2 (SLSLH + SLHLS + HLSLS)]
+      F = 12 (SLS - SLSLS)
+    both restricted to the range of L (the free variables).
+    """
+    K = mcweeny(L, S)
+    E = 2.0 * tr_prod(K, H)
+    N = 2.0 * tr_prod(K, S)
+    SLH = S @ L @ H
+    HLS = H @ L @ S
+    SLSLH = S @ L @ S @ L @ H
+    SLHLS = S @ L @ H @ L @ S
+    HLSLS = H @ L @ S @ L @ S
+    G = 2.0 * (3.0 * (SLH + HLS) - 2.0 * (SLSLH + SLHLS + HLSLS)) * maskL
+    SLS = S @ L @ S
+    SLSLS = S @ L @ S @ L @ S
+    F = 12.0 * (SLS - SLSLS) * maskL
+    return E, N, G, F
+
+
+def grad_S(L, S, H, maskS):
+    """dE/dS on S's range: 2 [3 LHL - 2 (LSLHL + LHLSL)]."""
+    LHL = L @ H @ L
+    return 2.0 * (3.0 * LHL - 2.0 * (L @ S @ LHL + LHL @ S @ L)) * maskS
+
+
+def grad_H(L, S, maskH):
+    """dE/dH on H's range: 2K (E = 2 Tr[KH] is linear in H)."""
+    return 2.0 * mcweeny(L, S) * maskH
+
+
+def k_coeffs(L, D, S):
+    """Matrix coefficients of K(L + a D) = K0 + a K1 + a^2 K2 + a^3 K3."""
+    LS, DS = L @ S, D @ S
+    K0 = 3.0 * (LS @ L) - 2.0 * (LS @ LS @ L)
+    K1 = 3.0 * (DS @ L + LS @ D) - 2.0 * (DS @ LS @ L + LS @ DS @ L + LS @ LS @ D)
+    K2 = 3.0 * (DS @ D) - 2.0 * (DS @ DS @ L + DS @ LS @ D + LS @ DS @ D)
+    K3 = -2.0 * (DS @ DS @ D)
+    return K0, K1, K2, K3
+
+
+def line_coeffs(L, D, S, M):
+    """c_m with 2 Tr[K(L + a D) M] = c0 + c1 a + c2 a^2 + c3 a^3."""
+    return np.array([2.0 * tr_prod(K, M) for K in k_coeffs(L, D, S)])
+
+
+# ------------------------------------------------------------------ scalar roots
+def cubic_min(c):
+    """Local minimum of c0 + c1 a + c2 a^2 + c3 a^3: the real root of
+    3 c3 a^2 + 2 c2 a + c1 = 0 where 2 c2 + 6 c3 a > 0; None if there is none."""
+    _, c1, c2, c3 = (float(x) for x in c)
+    if c3 == 0.0 and c2 == 0.0:
+        return None
+    r = np.roots([3.0 * c3, 2.0 * c2, c1])
+    best = None
+    for x in r:
+        if np.isreal(x):
+            x = float(np.real(x))
+            if 2.0 * c2 + 6.0 * c3 * x > 0.0:
+                best = x
+    return best
+
+
+def cubic_smallest_root(c, target):
+    """Real root of c0 + c1 d + c2 d^2 + c3 d^3 = target with the smallest |d|."""
+    c0, c1, c2, c3 = (float(x) for x in c)
+    coef = [c3, c2, c1, c0 - target]
+    while coef and coef[0] == 0.0:
+        coef = coef[1:]
+    if len(coef) < 2:
+        return None
+    r = [float(np.real(x)) for x in np.roots(coef) if np.isreal(x)]
+    if not r:
+        return None
+    return min(r, key=abs)
+
+
+# ------------------------------------------------------------------ initial L
+def initial_L(S, maskL, n_elec, T=None):
+    """L0 = lambda * T on L's range (T = identity by default), lambda the
+    smallest positive real root of N(lambda T) = N_e (a cubic in lambda)."""
+    Tm = (np.eye(S.shape[0]) if T is None else T) * maskL
+    c = line_coeffs(np.zeros_like(S), Tm, S, S)
+    coef = [c[3], c[2], c[1], c[0] - n_elec]
+    roots = [float(np.real(x)) for x in np.roots(coef) if np.isreal(x) and np.real(x) > 0]
+    if not roots:
+        raise ValueError("no positive lambda with N(lambda T) = N_e")
+    lam = min(roots)
+    return lam * Tm, lam
+
+
+# ------------------------------------------------------------------ CG
+def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
+       n_tol=1e-11, step_cap=0.1, stop_g=None, stop_de=None, n_atoms=None):
+    """Conjugate-gradient LNV minimisation; returns (L, history).
+
+    Iteration k at the current L:
+      1. E, N, G, F = evaluate(L)
+      2. metric: G_c = P_L(T G T), F_c = P_L(T F T) (identity when T is None)
+      3. mu = <G, F_c> / <F, F_c>;  g = G - mu F;  g_c = G_c - mu F_c
+      4. beta = 0 when k % reset_period == 0 or after a failed line search,
+         otherwise max(0, <g, g_c - g_c_prev> / <g_prev, g_c_prev>)
+      5. D = -g_c + beta D_prev;  D <- D - (<D, F> / <F, F_c>) F_c
+      6. alpha = local minimiser of Omega(L + alpha D), Omega = E - mu N
+         (an exact cubic); none -> alpha = 0 and a reset next iteration
+      7. L <- L + alpha D
+      8. if |N(L) - N_e| > n_tol N_e: delta = smallest-|delta| real root of
+         N(L + delta F_c) = N_e, applied when |delta| ||F_c|| <= step_cap ||L||
+    """
+    if L0 is None:
+        L, _ = initial_L(S, maskL, n_elec, T)
+    else:
+        L = L0.copy()
+    hist = []
+    D_prev = g_prev = gc_prev = None
+    force_reset = False
+    e_hist = []
+    for k in range(n_iter):
+        E, N, G, F = evaluate(L, S, H, maskL)
+        if T is None:
+            Gc, Fc = G, F
+        else:
+            Gc = (T @ G @ T) * maskL
+            Fc = (T @ F @ T) * maskL
+        FF = dot(F, Fc)
+        mu = dot(G, Fc) / FF
+        g = G - mu * F
+        gc = Gc - mu * Fc
+        if k % reset_period == 0 or force_reset or g_prev is None:
+            beta = 0.0
+        else:
+            beta = max(0.0, dot(g, gc - gc_prev) / dot(g_prev, gc_prev))
+        D = -gc + beta * D_prev if beta != 0.0 else -gc
+        D = D - (dot(D, F) / FF) * Fc
+        c = line_coeffs(L, D, S, H - mu * S)
+        alpha = cubic_min(c)
+        force_reset = alpha is None
+        if alpha is None:
+            alpha = 0.0
+        L = L + alpha * D
+        nc = line_coeffs(L, Fc, S, S)
+        N1 = nc[0]
+        delta = 0.0
+        if abs(N1 - n_elec) > n_tol * n_elec:
+            d = cubic_smallest_root(nc, n_elec)
+            if d is not None and abs(d) * np.sqrt(dot(Fc, Fc)) <= step_cap * np.sqrt(dot(L, L)):
+                delta = d
+                L = L + delta * Fc
+        g_prev, gc_prev, D_prev = g, gc, D
+        gnorm = float(np.sqrt(dot(g, g)))
+        hist.append(dict(k=k, E=E, N=N, mu=mu, beta=beta, alpha=alpha, delta=delta,
+                         c=c.tolist(), nc=nc.tolist(), gnorm=gnorm, N_after_step=N1))
+        if stop_g is not None and gnorm <= stop_g:
+            break
+        if stop_de is not None and n_atoms:
+            e_hist.append(E)
+            if len(e_hist) >= 4 and all(abs(e_hist[-m] - e_hist[-m - 1]) / n_atoms < stop_de
+                                        for m in (1, 2, 3)):
+                break
+    return L, hist
+
+
+# ------------------------------------------------------------------ exact reference
+def exact_density(H, S, n_elec):
+    """Exact diagonalisation at Gamma with step occupation (Sec. II.C.1):
+    H c = eps S c, K = sum_{n < N_e/2} c_n c_n^T, E = 2 sum_{n < N_e/2} eps_n."""
+    eps, C = sla.eigh(H, S)
+    nocc = n_elec // 2
+    K = C[:, :nocc] @ C[:, :nocc].T
+    E = 2.0 * float(np.sum(eps[:nocc]))
+    gap = float(eps[nocc] - eps[nocc - 1]) if nocc < len(eps) else float("inf")
+    return K, E, gap, eps

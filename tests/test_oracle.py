@@ -1,0 +1,272 @@
+"""Pins of the CPU oracle against mathematics, not against itself.
+
+Each test checks a property that the paper's definitions (Sec. II.C.2, Eq. for
+K = 3LSL - 2LSLSL, E = 2Tr[KH]) or plain mathematics fix independently of how
+the oracle is coded: finite differences, homogeneity, invariances, closed forms
+at special points, exact diagonalisation, lattice shell counts and the
+published SplitMix64 outputs.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.spatial import cKDTree
+
+import lnv_workloads as W
+from oracle import lnv
+from oracle import structure as st
+
+
+# ------------------------------------------------------------------ helpers
+def random_system(seed=0, n_atoms=6, nf=4, density=0.7):
+    rng = np.random.default_rng(seed)
+    n = n_atoms * nf
+    am = rng.random((n_atoms, n_atoms)) < density
+    am = am | am.T | np.eye(n_atoms, dtype=bool)
+    mask = np.kron(am.astype(float), np.ones((nf, nf)))
+    A = rng.standard_normal((n, n)) * 0.15
+    S = (A + A.T) * 0.5 * mask + 2.0 * np.eye(n)
+    assert np.linalg.eigvalsh(S).min() > 0.1
+    B = rng.standard_normal((n, n))
+    H = -(B + B.T) * 0.25 * mask
+    C = rng.standard_normal((n, n)) * 0.05
+    L = ((C + C.T) * 0.5 + 0.2 * np.eye(n)) * mask
+    return L, S, H, mask
+
+
+# ------------------------------------------------------------------ RNG
+def test_splitmix64_published_outputs():
+    # First outputs of SplitMix64 seeded with 0, as published with the
+    # reference implementation (Vigna's splitmix64.c / Steele-Lea-Flood).
+    x = W.splitmix64_at(0, np.arange(3))
+    assert [int(v) for v in x] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+
+
+# ------------------------------------------------------------------ neighbour lists
+def _diamond_shell_count(R, a):
+    """Number of diamond-lattice sites within R of a site, counted from exact
+    integer lattice vectors in units of a/4 (fcc vectors, plus (1,1,1) for the
+    other sublattice)."""
+    unit2 = (a / 4.0) ** 2
+    m = int(R / (a / 4.0)) + 2
+    cnt = 0
+    rng = range(-m, m + 1)
+    for x in rng:
+        for y in rng:
+            for z in rng:
+                same = x % 2 == 0 and y % 2 == 0 and z % 2 == 0 and (x + y + z) % 4 == 0
+                xs, ys, zs = x - 1, y - 1, z - 1
+                other = xs % 2 == 0 and ys % 2 == 0 and zs % 2 == 0 and (xs + ys + zs) % 4 == 0
+                if (same or other) and (x * x + y * y + z * z) * unit2 <= R * R:
+                    cnt += 1
+    return cnt
+
+
+def test_neighbours_perfect_diamond_shell_counts():
+    w = W.diamond_workload("perfect", (4, 4, 4), seed=1, disp=0.0)
+    for R, expect in ((12.0, 47), (14.0, 87), (16.0, 123)):
+        assert _diamond_shell_count(R, 10.26) == expect
+        rp, col = st.neighbours(w.pos, w.box, R)
+        assert np.all(np.diff(rp) == expect)
+
+
+@pytest.mark.parametrize("name", ["si64_4x4", "si8_4x4"])
+def test_neighbours_match_periodic_kdtree(name):
+    w = W.get(name)
+    tree = cKDTree(w.pos, boxsize=w.box)
+    for R in (w.R_S, w.R_H, w.R_L, 5.0):
+        rp, col = st.neighbours(w.pos, w.box, R)
+        for i in range(w.n):
+            got = set(col[rp[i]:rp[i + 1]].tolist())
+            ref = set(tree.query_ball_point(w.pos[i], R))
+            assert got == ref
+            assert np.all(np.diff(col[rp[i]:rp[i + 1]]) > 0)
+            assert i in got
+
+
+# ------------------------------------------------------------------ synthetic S, H
+def test_synthetic_matrices_structure():
+    w = W.get("si64_4x4")
+    sy = st.System(w)
+    S, H = sy.S, sy.H
+    assert np.array_equal(S, S.T) and np.array_equal(H, H.T)
+    ev = np.linalg.eigvalsh(S)
+    assert ev.min() > 0.5
+    # zero outside the range patterns
+    assert np.all(S[sy.maskS == 0] == 0) and np.all(H[sy.maskH == 0] == 0)
+    # image sum: a pair with two images in range (cell edge 20.52 < 2 R_S)
+    i = 0
+    found = False
+    for j in range(1, w.n):
+        dx = w.pos[j] - w.pos[i]
+        ds = []
+        for t in np.ndindex(5, 5, 5):
+            v = dx + (np.array(t) - 2) * w.box
+            d = math.sqrt(float(v @ v))
+            if d <= w.R_S:
+                ds.append(d)
+        if len(ds) >= 2:
+            found = True
+            wt = sum(math.exp(-d / 3.0) for d in ds)
+            Mref = st.random_block(w.seed, W.STREAM_S, i, j, 4, 4, w.scale)
+            got = S[0:4, 4 * j:4 * j + 4]
+            assert np.allclose(got, wt * Mref, rtol=1e-13, atol=0)
+            break
+    assert found
+
+
+# ------------------------------------------------------------------ functional and gradients
+def test_gradients_central_finite_differences():
+    L, S, H, mask = random_system(1)
+    E, N, G, F = lnv.evaluate(L, S, H, mask)
+    gS = lnv.grad_S(L, S, H, np.ones_like(S))
+    gH = lnv.grad_H(L, S, np.ones_like(S))
+    rng = np.random.default_rng(7)
+    idx = np.argwhere(mask > 0)
+    h = 1e-5
+    for a, b in idx[rng.choice(len(idx), 12, replace=False)]:
+        for Mname in ("L", "S", "H"):
+            Mp = {"L": L.copy(), "S": S.copy(), "H": H.copy()}
+            Mm = {"L": L.copy(), "S": S.copy(), "H": H.copy()}
+            Mp[Mname][a, b] += h
+            Mm[Mname][a, b] -= h
+            Ep, Np, _, _ = lnv.evaluate(Mp["L"], Mp["S"], Mp["H"], mask)
+            Em, Nm, _, _ = lnv.evaluate(Mm["L"], Mm["S"], Mm["H"], mask)
+            dE = (Ep - Em) / (2 * h)
+            dN = (Np - Nm) / (2 * h)
+            if Mname == "L":
+                assert abs(dE - G[a, b]) < 1e-7 * max(1, abs(G[a, b]))
+                assert abs(dN - F[a, b]) < 1e-7 * max(1, abs(F[a, b]))
+            elif Mname == "S":
+                assert abs(dE - gS[a, b]) < 1e-7 * max(1, abs(gS[a, b]))
+            else:
+                assert abs(dE - gH[a, b]) < 1e-7 * max(1, abs(gH[a, b]))
+
+
+def test_euler_homogeneity_identity():
+    # E = 6 Tr[LSLH] - 4 Tr[LSLSLH] has parts of degree 2 and 3 in L, so
+    # <L, dE/dL> = 12 Tr[LSLH] - 12 Tr[LSLSLH].
+    L, S, H, mask = random_system(2)
+    E, N, G, F = lnv.evaluate(L, S, H, mask)
+    t2 = np.trace(L @ S @ L @ H)
+    t3 = np.trace(L @ S @ L @ S @ L @ H)
+    assert abs(lnv.dot(G, L) - 12 * (t2 - t3)) < 1e-10 * abs(12 * t2)
+    assert abs(E - (6 * t2 - 4 * t3)) < 1e-12 * abs(E)
+
+
+def test_energy_with_H_equal_S_is_electron_number():
+    L, S, H, mask = random_system(3)
+    E, N, G, F = lnv.evaluate(L, S, S, mask)
+    assert abs(E - N) < 1e-12 * abs(N)
+    assert np.allclose(G, F, atol=1e-12 * np.abs(F).max())
+
+
+def test_per_atom_rotation_invariance():
+    L, S, H, mask = random_system(4)
+    rng = np.random.default_rng(5)
+    blocks = [np.linalg.qr(rng.standard_normal((4, 4)))[0] for _ in range(6)]
+    U = np.zeros_like(S)
+    for k, Q in enumerate(blocks):
+        U[4 * k:4 * k + 4, 4 * k:4 * k + 4] = Q
+    E, N, _, _ = lnv.evaluate(L, S, H, mask)
+    E2, N2, _, _ = lnv.evaluate(U.T @ L @ U, U.T @ S @ U, U.T @ H @ U, mask)
+    assert abs(E - E2) < 1e-13 * abs(E) and abs(N - N2) < 1e-13 * abs(N)
+
+
+def test_mcweeny_closed_forms():
+    L, S, H, mask = random_system(6)
+    Si = np.linalg.inv(S)
+    for c in (0.3, 0.5, 0.9):
+        K = lnv.mcweeny(c * Si, S)
+        assert np.allclose(K, (3 * c * c - 2 * c ** 3) * Si, atol=1e-12)
+    # S = I: K = V diag(3x^2 - 2x^3) V^T for L = V diag(x) V^T
+    rng = np.random.default_rng(8)
+    V = np.linalg.qr(rng.standard_normal((12, 12)))[0]
+    x = rng.uniform(-0.3, 1.2, 12)
+    K = lnv.mcweeny(V @ np.diag(x) @ V.T, np.eye(12))
+    assert np.allclose(K, V @ np.diag(3 * x * x - 2 * x ** 3) @ V.T, atol=1e-12)
+
+
+def test_exact_projector_is_stationary():
+    L, S, H, mask = random_system(9)
+    full = np.ones_like(S)
+    n_elec = 8
+    P, E, gap, eps = lnv.exact_density(H, S, n_elec)
+    assert np.allclose(lnv.mcweeny(P, S), P, atol=1e-11)
+    E2, N2, G, F = lnv.evaluate(P, S, H, full)
+    assert abs(E2 - E) < 1e-11 * abs(E)
+    assert abs(N2 - n_elec) < 1e-11
+    assert np.abs(G).max() < 1e-10 and np.abs(F).max() < 1e-10
+
+
+def test_line_coefficients_are_exact_cubic():
+    L, S, H, mask = random_system(10)
+    rng = np.random.default_rng(11)
+    C = rng.standard_normal(S.shape)
+    D = (C + C.T) * mask * 0.1
+    mu = -0.37
+    c = lnv.line_coeffs(L, D, S, H - mu * S)
+    E0, N0, G, F = lnv.evaluate(L, S, H, mask)
+    assert abs(c[0] - (E0 - mu * N0)) < 1e-12 * abs(c[0])
+    assert abs(c[1] - lnv.dot(G - mu * F, D)) < 1e-11 * max(1, abs(c[1]))
+    for a in (0.3, -0.7, 1.1, 2.5):
+        Ea, Na, _, _ = lnv.evaluate(L + a * D, S, H, mask)
+        poly = c[0] + c[1] * a + c[2] * a * a + c[3] * a ** 3
+        assert abs((Ea - mu * Na) - poly) < 1e-11 * max(1, abs(poly))
+
+
+def test_cubic_root_helpers():
+    # (a - 1)^2 (a + 2) = a^3 - 3a + 2: local min at a = 1
+    assert abs(lnv.cubic_min([2, -3, 0, 1]) - 1.0) < 1e-14
+    # -(a^3) + 3a: local min at a = -1
+    assert abs(lnv.cubic_min([0, 3, 0, -1]) + 1.0) < 1e-14
+    # convex quadratic (c3 = 0): min at -c1 / (2 c2)
+    assert abs(lnv.cubic_min([0, -4, 2, 0]) - 1.0) < 1e-14
+    # monotone cubic: no local minimum
+    assert lnv.cubic_min([0, 1, 0, 1]) is None
+    # (d - 0.1)(d - 2)(d + 3) roots 0.1, 2, -3 -> smallest |d| is 0.1
+    c = np.poly([0.1, 2.0, -3.0])[::-1]
+    assert abs(lnv.cubic_smallest_root(c, 0.0) - 0.1) < 1e-13
+
+
+def test_initial_L_has_target_electron_number():
+    w = W.get("si64_4x4")
+    sy = st.System(w)
+    L0, lam = lnv.initial_L(sy.S, sy.maskL, w.n_elec)
+    _, N, _, _ = lnv.evaluate(L0, sy.S, sy.H, sy.maskL)
+    assert abs(N - w.n_elec) < 1e-10 * w.n_elec
+    assert 0.2 < lam < 0.3
+
+
+def test_cg_projection_and_descent_si64():
+    w = W.get("si64_4x4")
+    sy = st.System(w)
+    L, hist = lnv.cg(sy.S, sy.H, sy.maskL, w.n_elec, 20)
+    E = [h["E"] for h in hist]
+    assert all(E[k + 1] < E[k] for k in range(len(E) - 1))
+    assert all(abs(h["N"] - w.n_elec) < 1e-9 for h in hist)
+    assert all(h["alpha"] > 0 for h in hist)
+    K, Ex, gap, _ = lnv.exact_density(sy.H, sy.S, w.n_elec)
+    # truncated range and 20 steps: above the exact energy, within 1e-3 Ha/atom
+    assert 0 < (E[-1] - Ex) / w.n < 1e-3
+
+
+def test_check_a_converged_lnv_equals_exact_diagonalisation():
+    """Untruncated L on the 8-atom cell with the exact inverse-overlap metric
+    reproduces the exact Gamma-point density matrix and band energy, and the
+    converged K is idempotent in the S metric with 2Tr[KS] = N_e."""
+    w = W.get("si8_4x4", R_L=1000.0)
+    sy = st.System(w)
+    K, Ex, gap, _ = lnv.exact_density(sy.H, sy.S, w.n_elec)
+    assert gap > 1e-2
+    T = np.linalg.inv(sy.S)
+    nnz = sy.maskL.sum()
+    L, hist = lnv.cg(sy.S, sy.H, sy.maskL, w.n_elec, 150, T=T,
+                     stop_g=1e-6 * math.sqrt(nnz), stop_de=1e-13, n_atoms=w.n)
+    assert len(hist) < 150
+    Kl = lnv.mcweeny(L, sy.S)
+    E, N, _, _ = lnv.evaluate(L, sy.S, sy.H, sy.maskL)
+    assert abs(E - Ex) / w.n < 1e-9
+    assert np.abs(Kl - K).max() < 1e-8
+    assert abs(2 * lnv.tr_prod(Kl, sy.S) - w.n_elec) <= 1e-9 * w.n_elec
+    assert np.abs(Kl @ sy.S @ Kl - Kl).max() < 1e-8
