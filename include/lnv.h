@@ -1,0 +1,311 @@
+/*
+ * lnv.h -- C ABI of the MI355X (gfx950) LNV density-matrix hot path.
+ *
+ * The method (Sec. II.C.2 of the paper, "Density matrix: linear scaling"):
+ * the density matrix in the support-function basis (Sec. II.B, rho = sum
+ * phi K phi) is written through an auxiliary matrix L of restricted range
+ * with the McWeeny form K = 3LSL - 2LSLSL; the band energy E = 2 Tr[KH] is
+ * minimised with respect to the elements of L using dE/dL, under the
+ * electron-number constraint N = 2 Tr[KS] = N_e.  All matrices are
+ * atom-blocked (rows and columns indexed by atom i and function alpha) and
+ * range truncated: a block (i, j) exists only when atoms i and j are closer
+ * than the matrix's cutoff, so every product is a block-sparse multiply and
+ * every cost is linear in the number of atoms.
+ *
+ * Conventions shared by every call
+ *  - Device pointers are HIP device memory owned by the caller; host
+ *    pointers are marked "host".  The library frees nothing.  Calls marked
+ *    "hot path" allocate nothing; set-up calls may allocate and free
+ *    temporaries with the stream-ordered allocator.
+ *  - Calls are enqueued on the given stream.  Set-up calls that report a
+ *    size to the host (nnz_out, n_items_out) synchronise that stream.
+ *  - Every call returns an lnv_status.  Argument and pattern errors are
+ *    detected on the host before anything is launched and leave every output
+ *    untouched.  A failing HIP call returns LNV_EHIP; lnv_last_hip_error()
+ *    gives its hipError_t.  Errors of already enqueued kernels surface at
+ *    the next synchronising call or at lnv_sync_check().
+ *  - Blocks are stored row-major, one after another in pattern order
+ *    (row by row, ascending column), blk*blk values per block.  The FP64
+ *    kernels of this version take blk == 4 (4 support functions per atom,
+ *    the SZ silicon basis of Sec. II.B); other block edges return
+ *    LNV_EUNSUPPORTED.
+ *  - Reductions (traces, dot products) are computed in FP64 with a fixed
+ *    order that does not depend on timing: results are bitwise
+ *    reproducible run to run on the same device and grid.
+ */
+#ifndef LNV_H
+#define LNV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lnv_status {
+  LNV_OK = 0,
+  LNV_EINVAL = 1,       /* bad argument (null pointer, negative size, ...) */
+  LNV_ECAPACITY = 2,    /* output buffer too small; *nnz_out = needed size */
+  LNV_EPATTERN = 3,     /* incompatible patterns or a missing index table */
+  LNV_EHIP = 4,         /* a HIP runtime call failed */
+  LNV_ENUMERIC = 5,     /* non-finite value or no admissible root */
+  LNV_EUNSUPPORTED = 6  /* valid request this build does not implement */
+} lnv_status;
+
+enum { LNV_F64 = 0 };
+
+/* Largest block-row count accepted by the set-up kernels (LDS bitmaps). */
+#define LNV_MAX_ATOMS 262144
+
+/*
+ * Atom-block sparsity pattern.  row_ptr/col is CSR over atoms with columns
+ * ascending in each row.  The optional index tables make a block findable in
+ * O(1): lut[i*n + j] is the position of block (i, j) or -1, lut_t[i*n + j] is
+ * the position of block (j, i) or -1 (n*n int32 each: 64 MiB at 4096 atoms,
+ * 1 GiB at 16384 -- the HBM of one MI355X holds them with room to spare).
+ * items lists the work pieces of the row-parallel kernels: item q covers row
+ * items[2q] from position items[2q+1] for up to 64 blocks (never past the
+ * end of the row).
+ */
+typedef struct lnv_pattern {
+  int32_t n;               /* atoms (block rows = block columns) */
+  int32_t n_items;         /* entries of items */
+  int64_t nnzb;            /* stored blocks */
+  const int32_t* row_ptr;  /* device [n+1] */
+  const int32_t* col;      /* device [nnzb] */
+  const int32_t* lut;      /* device [n*n] or NULL */
+  const int32_t* lut_t;    /* device [n*n] or NULL */
+  const int32_t* items;    /* device [2*n_items] or NULL */
+} lnv_pattern;
+
+/* Block-sparse matrix: a pattern (host descriptor) plus block values. */
+typedef struct lnv_bsm {
+  const lnv_pattern* pat;  /* host pointer */
+  int32_t blk;             /* block edge (stored values per block: blk*blk) */
+  int32_t dtype;           /* LNV_F64 */
+  void* val;               /* device [pat->nnzb * blk * blk] */
+} lnv_bsm;
+
+/* ------------------------------------------------------------ errors */
+const char* lnv_strerror(int status);
+int lnv_last_hip_error(void);
+/* Synchronise s and report any asynchronous kernel error as LNV_EHIP. */
+int lnv_sync_check(hipStream_t s);
+
+/* ------------------------------------------------------------ a0: ranges
+ * lnv_neighbours -- range pattern of one matrix (Sec. II.C.2: an element
+ * between atoms i and j is zero when their distance exceeds the cutoff R).
+ * Periodic orthorhombic cell (Sec. II.C.1 applies periodic boundary
+ * conditions): the distance is to the nearest image, per axis
+ *   dx = (x_j - x_i) - box * rint((x_j - x_i)/box),
+ *   d2 = (dx*dx + dy*dy) + dz*dz  (no fused multiply-add),
+ * and (i, j) is kept iff d2 <= R*R.  The self pair is always kept; columns
+ * are ascending.
+ *  pos      device [n][3] FP64 positions, each coordinate in [0, box)
+ *  box      host [3] cell edges
+ *  row_ptr  device [n+1], always written
+ *  col      device [cap] or NULL (count only)
+ *  nnz_out  host: number of pairs.  LNV_ECAPACITY if col != NULL and
+ *           cap < *nnz_out (col is then not written).
+ * Synchronises s.
+ */
+int lnv_neighbours(const double* pos, int32_t n, const double* box, double R,
+                   int32_t* row_ptr, int32_t* col, int64_t cap, int64_t* nnz_out,
+                   hipStream_t s);
+
+/* ------------------------------------------------------------ a2: products
+ * lnv_pattern_product -- pattern of a block-sparse product (the symbolic
+ * half of the linear-scaling multiplies of Sec. II.C.2).  Output row i holds
+ * every j with some k such that (i,k) in A and (k,j) in B (the natural range
+ * of A.B); with mask != NULL only the j in mask's row i are kept.
+ *  row_ptr      device [n+1], always written
+ *  col          device [cap] or NULL (count only)
+ *  nnz_out      host: output blocks (LNV_ECAPACITY as above)
+ *  row_triples  device [n+1] or NULL: exclusive prefix sums of the number of
+ *               (i,k,j) triples feeding each row's kept blocks (row i has
+ *               row_triples[i+1] - row_triples[i]; row_triples[n] = total)
+ *  triples_out  host or NULL: total triples (2*blk^3 flops each)
+ * A and B need row_ptr/col; mask (if given) too.  Synchronises s.
+ */
+int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
+                        const lnv_pattern* mask, int32_t* row_ptr, int32_t* col,
+                        int64_t cap, int64_t* nnz_out, int64_t* row_triples,
+                        int64_t* triples_out, hipStream_t s);
+
+/* lnv_pattern_lut -- fill the index tables of P (either may be NULL). */
+int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t, hipStream_t s);
+
+/* lnv_pattern_items -- work list of P: with items == NULL only counts.
+ *  n_items_out  host: number of items (LNV_ECAPACITY if cap is smaller).
+ * Synchronises s. */
+int lnv_pattern_items(const lnv_pattern* P, int32_t* items, int64_t cap,
+                      int32_t* n_items_out, hipStream_t s);
+
+/* ------------------------------------------------------------ a1: values
+ * lnv_synth_blocks -- synthetic overlap (kind 0) or Hamiltonian (kind 1)
+ * blocks on M's pattern, standing in for the grid integrals of Eq. (2):
+ *   S_ij = w(i,j) M_ij + 2 I delta_ij,   H_ij = -(w(i,j) M_ij),
+ *   w(i,j) = sum over images T of j with d_T^2 <= R^2 of exp(-(d_T/decay)),
+ * images enumerated with integer offsets t in [-m, m]^3 (tx outermost,
+ * m = ceil(R/box) + 1) and d_T^2 formed as in lnv_neighbours.  M_ij is a
+ * seeded random block: for i <= j element e = r*nj + c is
+ * scale*(u - 0.5), u = (SplitMix64 output number ctr of seed >> 11) * 2^-53,
+ * ctr = stream<<56 | i<<32 | j<<8 | e (stream 1 for S, 2 for H); M_ji = M_ij^T
+ * and diagonal blocks are (R + R^T) * 0.5.  Support functions per atom come
+ * from nfun (device [n], NULL: every atom has M->blk); entries of a padded
+ * block beyond nfun are zero.
+ */
+int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
+                     const lnv_bsm* M, int32_t kind, double R, double decay,
+                     uint64_t seed, double scale, hipStream_t s);
+
+/* ------------------------------------------------------------ a3: multiply
+ * lnv_bsm_multiply -- C = alpha * A * op(B) + beta * C on C's pattern only
+ * (blocks of the product outside C's pattern are not formed: a range
+ * truncated product).  op(B) = B (transB = 0) or B^T (transB = 1).
+ * Needs A.row_ptr/col, B.lut (transB = 0) or B.lut_t (transB = 1) and C.items.
+ * Hot path: allocates nothing.
+ */
+int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
+                     double beta, lnv_bsm* C, hipStream_t s);
+
+/* lnv_bsm_multiply_dot -- as lnv_bsm_multiply, and in the same pass
+ * out[d] = <M_d, C> for the given partners M_1, M_2 (NULL to skip; both on
+ * C's pattern); with store == 0 the product is not written back (only the
+ * traces are wanted).  partials: device [2 * C.n_items] scratch; out: device.
+ */
+int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
+                         double beta, lnv_bsm* C, int32_t store, const lnv_bsm* M1,
+                         const lnv_bsm* M2, double* partials, double* out, hipStream_t s);
+
+/* lnv_bsm_dot -- <A, B> = sum over A's blocks of A_ij . B_ij (Frobenius),
+ * with B_ij taken at the same position when B shares A's pattern object,
+ * otherwise through B.lut (absent blocks count as zero).
+ * partials: device [LNV_DOT_PARTIALS] scratch; out: device [1].  Hot path.
+ */
+#define LNV_DOT_PARTIALS 1024
+int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* out,
+                hipStream_t s);
+
+/* ------------------------------------------------------------ a4: evaluation
+ * Intermediates of one evaluation.  With A = LS (stored as its transpose
+ * SL), X = HLS and Z = SLS at their natural ranges:
+ *   E = 2 (3 <L, X> - 2 <L, P_L(X A)>)
+ *   N = 2 (3 <L, Z> - 2 <L, P_L(A^T Z)>)
+ *   G = dE/dL = 2 P_L[3 (X + X^T) - 2 (Y + Y^T + A^T X)],   Y = P_L(X A)
+ *   F = dN/dL = 12 P_L[Z - A^T Z]
+ * which follow from K = 3LSL - 2LSLSL and E = 2 Tr[KH] (Sec. II.C.2) by
+ * differentiating each stored entry of L.
+ *  SL  values on pat(S.L)   (pattern needs lut_t and items)
+ *  X   values on pat(H.L.S) (pattern needs lut, lut_t and items)
+ *  Z   values on pat(S.L.S) (pattern needs lut and items)
+ *  YT, W, V  device [nnzb_L * 16]: P_L(SLSLH), P_L(SLHLS), P_L(SLSLS)
+ *  partials  device [partials_len] scratch, partials_len >=
+ *            lnv_partials_len(n_items of L's pattern)
+ *  scalars   device [LNV_NSCALARS] FP64 (see LNV_SC_*)
+ */
+typedef struct lnv_eval_ws {
+  lnv_bsm SL;
+  lnv_bsm X;
+  lnv_bsm Z;
+  double* YT;
+  double* W;
+  double* V;
+  double* partials;
+  int64_t partials_len;
+  double* scalars;
+} lnv_eval_ws;
+
+#define LNV_NSLOTS 12
+int64_t lnv_partials_len(int32_t n_items_L);
+
+/* Device scalar block (doubles). */
+enum {
+  LNV_SC_E = 0, LNV_SC_N = 1, LNV_SC_MU = 2, LNV_SC_BETA = 3, LNV_SC_ALPHA = 4,
+  LNV_SC_DELTA = 5, LNV_SC_FF = 6, LNV_SC_GG = 7, LNV_SC_C1 = 8, LNV_SC_C2 = 9,
+  LNV_SC_C3 = 10, LNV_SC_N0 = 11, LNV_SC_N1 = 12, LNV_SC_N2 = 13, LNV_SC_N3 = 14,
+  LNV_SC_FORCE_RESET = 15, LNV_SC_SKIP_NCORR = 16, LNV_SC_GNORM = 17,
+  LNV_SC_N_AFTER = 18, LNV_SC_LAMBDA = 19, LNV_SC_STATUS = 20, LNV_SC_LL = 21,
+  LNV_SC_GF = 22, LNV_SC_DF = 23, LNV_SC_T0 = 24, LNV_SC_T1 = 25, LNV_SC_T2 = 26,
+  LNV_SC_T3 = 27, LNV_SC_T4 = 28, LNV_SC_T5 = 29, LNV_SC_GG_PREV = 30,
+  LNV_SC_GGP = 31,
+  LNV_NSCALARS = 40
+};
+/* LNV_SC_STATUS bits set by the device (sticky until cleared by the caller). */
+enum { LNV_ST_NONFINITE = 1, LNV_ST_NO_ALPHA = 2, LNV_ST_NO_DELTA = 4, LNV_ST_DELTA_CAPPED = 8 };
+
+/*
+ * lnv_eval -- E, N (written to EN[0], EN[1], device, and to
+ * scalars[LNV_SC_E/N]), G = dE/dL and F = dN/dL on L's pattern.  L, S, H,
+ * G, F are FP64 with blk 4; L's pattern needs lut and items, S's needs lut.
+ * Hot path: allocates nothing, no host synchronisation.
+ */
+int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
+             lnv_bsm* F, double* EN, const lnv_eval_ws* ws, hipStream_t s);
+
+/* ------------------------------------------------------------ a5-a7: CG
+ * Buffers of the conjugate-gradient minimisation (all on L's pattern unless
+ * stated).  g/g_prev and D/D_prev are swapped by lnv_cg_step after each step.
+ */
+typedef struct lnv_cg_ws {
+  lnv_eval_ws ev;
+  double* SL2;     /* second value buffer on pat(S.L) */
+  double* Hp;      /* [nnzb_H * 16]: H - mu S */
+  double* G;
+  double* F;
+  double* g;
+  double* g_prev;
+  double* D;
+  double* D_prev;
+} lnv_cg_ws;
+
+typedef struct lnv_opts {
+  int32_t reset_period;  /* search direction reset period (40) */
+  double n_tol;          /* relative electron-number tolerance (1e-11) */
+  double step_cap;       /* max |delta| ||F|| / ||L|| of the N correction (0.1) */
+} lnv_opts;
+
+/*
+ * lnv_cg_init -- L0 = lambda * I on L's pattern, lambda the smallest positive
+ * real root of N(lambda I) = n_elec (a cubic: -4 Tr[S^3] l^3 + 6 Tr[S^2] l^2).
+ * The paper starts from a generalised McWeeny purification of H; the scaled
+ * identity is the start used here.  Writes L and scalars[LNV_SC_LAMBDA].
+ */
+int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, double n_elec, lnv_cg_ws* ws, hipStream_t s);
+
+/*
+ * lnv_cg_step -- one conjugate-gradient iteration k (0-based) at the current L:
+ *  1. E, N, G, F = eval(L)
+ *  2. mu = <G,F>/<F,F>;  g = G - mu F
+ *  3. beta = 0 if k % reset_period == 0 or the previous line search failed,
+ *     else max(0, <g, g - g_prev> / <g_prev, g_prev>)  (Polak-Ribiere, >= 0)
+ *  4. D = -g + beta D_prev;  D <- D - (<D,F>/<F,F>) F
+ *  5. alpha = local minimiser of the exact cubic (E - mu N)(L + alpha D)
+ *     (none: alpha = 0 and a reset at the next step);  L += alpha D
+ *  6. if |N(L) - N_e| > n_tol N_e: delta = smallest-|delta| real root of
+ *     N(L + delta F) = N_e, applied when |delta| ||F|| <= step_cap ||L||
+ * Sec. V.C (density-matrix minimisation of gramicidin A) resets the search
+ * direction every 40 iterations; the other choices are readings of the
+ * method's electron-number constraint (Sec. II.C.2).  Every decision is
+ * taken on the device: the call never synchronises.  Diagnostics are in
+ * scalars (E, N at the start of the step, mu, beta, alpha, delta, ...).
+ */
+int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double n_elec,
+                int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);
+
+/* ------------------------------------------------------------ timing
+ * Optional HIP-event timing of the block multiply kernel: while enabled,
+ * every multiply launch is bracketed by events on its stream.
+ * lnv_timing_read synchronises the recorded events and returns the summed
+ * kernel time (ms) and launch count since the last reset. */
+int lnv_timing_enable(int32_t on);
+int lnv_timing_read(double* ms_total, int64_t* launches);
+int lnv_timing_reset(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LNV_H */

@@ -1,0 +1,83 @@
+// Internal helpers shared by the HIP translation units of liblnv.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/lnv.h"
+
+namespace lnv {
+
+// ---------------------------------------------------------------- errors
+void set_hip_error(hipError_t e);
+
+#define LNV_HIP(call)                          \
+  do {                                         \
+    hipError_t e_ = (call);                    \
+    if (e_ != hipSuccess) {                    \
+      ::lnv::set_hip_error(e_);                \
+      return LNV_EHIP;                         \
+    }                                          \
+  } while (0)
+
+#define LNV_LAUNCH_CHECK() LNV_HIP(hipGetLastError())
+
+#define LNV_TRY(expr)            \
+  do {                           \
+    int st_ = (expr);            \
+    if (st_ != LNV_OK) return st_; \
+  } while (0)
+
+// ---------------------------------------------------------------- launch shape
+constexpr int kWave = 64;
+constexpr int kNumXcd = 8;           // MI355X: 8 accelerator complex dies
+constexpr int kVecGrid = 1024;       // fixed grid of the pattern-vector kernels
+
+// Workgroups are dispatched round-robin over the XCDs (workgroup b runs on
+// XCD b % 8).  Remapping gives XCD x the contiguous logical range
+// [x*per, (x+1)*per), so neighbouring work items (spatially close atoms)
+// share one XCD's L2.  The grid must be a multiple of 8.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int per = nblocks / kNumXcd;
+  return (bid % kNumXcd) * per + bid / kNumXcd;
+}
+
+inline int round_up(int a, int b) { return (a + b - 1) / b * b; }
+
+// Fixed-order wavefront sum (butterfly): identical association every run.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Block sum of one value per thread (blockDim.x a multiple of 64, <= 1024).
+// Result valid in thread 0.  Fixed order.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int q = 0; q < nw; ++q) t += sh[q];
+  return t;
+}
+
+// ---------------------------------------------------------------- checks
+inline bool bsm_ok(const lnv_bsm* M) {
+  return M && M->pat && M->val && M->dtype == LNV_F64 && M->pat->n > 0;
+}
+
+// Internal multiply used by the public wrappers and by eval / CG.
+//  store: write C;  m1/m2: dot partners on C's pattern (values, may be null)
+//  partials: [2*C.n_items];  skip: device flag, kernel returns when != 0.
+int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
+                    double beta, const lnv_bsm* C, int store, const double* m1,
+                    const double* m2, double* partials, const double* skip,
+                    hipStream_t s);
+
+}  // namespace lnv

@@ -1,0 +1,824 @@
+// a4-a7: LNV evaluation and conjugate-gradient step on the device.
+//
+// Sec. II.C.2: K = 3LSL - 2LSLSL, E = 2 Tr[KH], minimised over the elements
+// of the range-restricted L with dE/dL under the electron-number constraint
+// N = 2 Tr[KS] = N_e.  With A = LS (stored transposed, SL), X = HLS and
+// Z = SLS at natural range, every trace and gradient needs six block-sparse
+// products; the three on L's pattern are formed with A^T on the left so the
+// left operand's range (that of LS) bounds the contraction.
+//
+// Every scalar decision (mu, beta, alpha, delta, resets) is taken by a
+// one-workgroup kernel from partial sums written by the vector kernels, so a
+// CG step is a fixed sequence of launches with no host synchronisation.
+// All reductions use a fixed association: results are reproducible bitwise.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <utility>
+
+#include "internal.h"
+
+namespace lnv {
+
+namespace {
+thread_local int g_last_hip = 0;
+}
+
+void set_hip_error(hipError_t e) { g_last_hip = (int)e; }
+
+namespace {
+
+// ------------------------------------------------------------------ reductions
+struct Red {
+  int off, count, stride, dst;
+};
+struct RedList {
+  Red r[8];
+  int nr;
+};
+
+enum Stage { ST_NONE = 0, ST_EVAL, ST_BETA, ST_PROJ, ST_ALPHA, ST_NCHK, ST_DELTA, ST_INIT };
+
+struct StageArgs {
+  double n_elec, n_tol, step_cap;
+  int reset;          // host: k % reset_period == 0
+  double* en_out;     // ST_EVAL: optional device [2]
+};
+
+// Real roots of a3 x^3 + a2 x^2 + a1 x + a0 (leading zero coefficients drop
+// the degree).  Cubic: Cardano / Viete trigonometric form on the normalised
+// polynomial, each root polished by two Newton steps.
+__device__ int real_roots(double a3, double a2, double a1, double a0, double* r) {
+  int nr = 0;
+  if (a3 == 0.0) {
+    if (a2 == 0.0) {
+      if (a1 == 0.0) return 0;
+      r[0] = -a0 / a1;
+      return 1;
+    }
+    const double disc = a1 * a1 - 4.0 * a2 * a0;
+    if (disc < 0.0) return 0;
+    const double q = -0.5 * (a1 + copysign(sqrt(disc), a1));
+    if (q == 0.0) {
+      r[0] = 0.0;
+      return 1;
+    }
+    r[0] = q / a2;
+    r[1] = a0 / q;
+    return 2;
+  }
+  const double B = a2 / a3, C = a1 / a3, D = a0 / a3;
+  const double Q = (B * B - 3.0 * C) / 9.0;
+  const double R = (2.0 * B * B * B - 9.0 * B * C + 27.0 * D) / 54.0;
+  const double Q3 = Q * Q * Q;
+  if (R * R < Q3) {
+    const double th = acos(R / sqrt(Q3));
+    const double s = -2.0 * sqrt(Q);
+    const double pi2 = 6.283185307179586476925286766559;
+    r[0] = s * cos(th / 3.0) - B / 3.0;
+    r[1] = s * cos((th + pi2) / 3.0) - B / 3.0;
+    r[2] = s * cos((th - pi2) / 3.0) - B / 3.0;
+    nr = 3;
+  } else {
+    const double Aq = -copysign(cbrt(fabs(R) + sqrt(R * R - Q3)), R);
+    const double Bq = Aq != 0.0 ? Q / Aq : 0.0;
+    r[0] = (Aq + Bq) - B / 3.0;
+    nr = 1;
+  }
+  for (int q = 0; q < nr; ++q)
+    for (int it = 0; it < 2; ++it) {
+      const double x = r[q];
+      const double f = ((a3 * x + a2) * x + a1) * x + a0;
+      const double df = (3.0 * a3 * x + 2.0 * a2) * x + a1;
+      if (df != 0.0) r[q] = x - f / df;
+    }
+  return nr;
+}
+
+// Local minimum of c0 + c1 a + c2 a^2 + c3 a^3: the root of
+// 3 c3 a^2 + 2 c2 a + c1 with positive curvature 2 c2 + 6 c3 a.
+__device__ bool cubic_min(double c1, double c2, double c3, double* alpha) {
+  if (c3 == 0.0) {
+    if (c2 > 0.0) {
+      *alpha = -c1 / (2.0 * c2);
+      return true;
+    }
+    return false;
+  }
+  const double disc = c2 * c2 - 3.0 * c3 * c1;
+  if (!(disc > 0.0)) return false;
+  const double sq = sqrt(disc);
+  *alpha = c2 > 0.0 ? -c1 / (c2 + sq) : (-c2 + sq) / (3.0 * c3);
+  return true;
+}
+
+__global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ partials,
+                                                RedList rl, double* __restrict__ sc,
+                                                int stage, StageArgs sa) {
+  __shared__ double sh[16];
+  for (int q = 0; q < rl.nr; ++q) {
+    const Red rd = rl.r[q];
+    double v = 0.0;
+    for (int t = threadIdx.x; t < rd.count; t += 256) v += partials[rd.off + (size_t)t * rd.stride];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) sc[rd.dst] = v;
+    __syncthreads();
+  }
+  if (threadIdx.x != 0 || stage == ST_NONE) return;
+  int status = (int)sc[LNV_SC_STATUS];
+  switch (stage) {
+    case ST_EVAL: {
+      const double E = 2.0 * (3.0 * sc[LNV_SC_T0] - 2.0 * sc[LNV_SC_T1]);
+      const double N = 2.0 * (3.0 * sc[LNV_SC_T2] - 2.0 * sc[LNV_SC_T3]);
+      sc[LNV_SC_E] = E;
+      sc[LNV_SC_N] = N;
+      const double FF = sc[LNV_SC_FF];
+      sc[LNV_SC_MU] = FF != 0.0 ? sc[LNV_SC_GF] / FF : 0.0;
+      if (sa.en_out) {
+        sa.en_out[0] = E;
+        sa.en_out[1] = N;
+      }
+      if (!isfinite(E) || !isfinite(N) || !isfinite(sc[LNV_SC_MU])) status |= LNV_ST_NONFINITE;
+      break;
+    }
+    case ST_BETA: {
+      const double gg = sc[LNV_SC_GG], ggp = sc[LNV_SC_GGP], gprev = sc[LNV_SC_GG_PREV];
+      double beta = 0.0;
+      if (!sa.reset && sc[LNV_SC_FORCE_RESET] == 0.0 && gprev != 0.0)
+        beta = fmax(0.0, (gg - ggp) / gprev);
+      sc[LNV_SC_BETA] = beta;
+      sc[LNV_SC_FORCE_RESET] = 0.0;
+      sc[LNV_SC_GNORM] = sqrt(gg);
+      sc[LNV_SC_GG_PREV] = gg;
+      break;
+    }
+    case ST_PROJ: {
+      const double FF = sc[LNV_SC_FF];
+      sc[LNV_SC_T5] = FF != 0.0 ? sc[LNV_SC_DF] / FF : 0.0;
+      break;
+    }
+    case ST_ALPHA: {
+      const double c1 = sc[LNV_SC_C1];
+      const double c2 = 2.0 * (3.0 * sc[LNV_SC_T0] - 2.0 * (2.0 * sc[LNV_SC_T1] + sc[LNV_SC_T3]));
+      const double c3 = -4.0 * sc[LNV_SC_T2];
+      sc[LNV_SC_C2] = c2;
+      sc[LNV_SC_C3] = c3;
+      double a = 0.0;
+      if (!cubic_min(c1, c2, c3, &a) || !isfinite(a)) {
+        a = 0.0;
+        sc[LNV_SC_FORCE_RESET] = 1.0;
+        status |= LNV_ST_NO_ALPHA;
+      }
+      if (!isfinite(c1) || !isfinite(c2) || !isfinite(c3)) status |= LNV_ST_NONFINITE;
+      sc[LNV_SC_ALPHA] = a;
+      break;
+    }
+    case ST_NCHK: {
+      const double N1 = 2.0 * (3.0 * sc[LNV_SC_T0] - 2.0 * sc[LNV_SC_T1]);
+      sc[LNV_SC_N_AFTER] = N1;
+      sc[LNV_SC_N0] = N1;
+      sc[LNV_SC_N1] = sc[LNV_SC_T2];
+      sc[LNV_SC_DELTA] = 0.0;
+      sc[LNV_SC_SKIP_NCORR] = fabs(N1 - sa.n_elec) > sa.n_tol * sa.n_elec ? 0.0 : 1.0;
+      if (!isfinite(N1)) status |= LNV_ST_NONFINITE;
+      break;
+    }
+    case ST_DELTA: {
+      if (sc[LNV_SC_SKIP_NCORR] != 0.0) break;
+      const double n2 = 2.0 * (3.0 * sc[LNV_SC_T0] - 2.0 * (2.0 * sc[LNV_SC_T1] + sc[LNV_SC_T3]));
+      const double n3 = -4.0 * sc[LNV_SC_T2];
+      sc[LNV_SC_N2] = n2;
+      sc[LNV_SC_N3] = n3;
+      double r[3];
+      const int nr = real_roots(n3, n2, sc[LNV_SC_N1], sc[LNV_SC_N0] - sa.n_elec, r);
+      double d = 0.0;
+      if (nr == 0) {
+        status |= LNV_ST_NO_DELTA;
+      } else {
+        d = r[0];
+        for (int q = 1; q < nr; ++q)
+          if (fabs(r[q]) < fabs(d)) d = r[q];
+        if (!(fabs(d) * sqrt(sc[LNV_SC_FF]) <= sa.step_cap * sqrt(sc[LNV_SC_LL]))) {
+          d = 0.0;
+          status |= LNV_ST_DELTA_CAPPED;
+        }
+      }
+      sc[LNV_SC_DELTA] = d;
+      break;
+    }
+    case ST_INIT: {
+      const double c2 = 6.0 * sc[LNV_SC_T0];
+      const double c3 = -4.0 * sc[LNV_SC_T2];
+      double r[3];
+      const int nr = real_roots(c3, c2, 0.0, -sa.n_elec, r);
+      double lam = 0.0;
+      bool found = false;
+      for (int q = 0; q < nr; ++q)
+        if (r[q] > 0.0 && (!found || r[q] < lam)) {
+          lam = r[q];
+          found = true;
+        }
+      if (!found) status |= LNV_ST_NO_DELTA;
+      sc[LNV_SC_LAMBDA] = lam;
+      break;
+    }
+    default:
+      break;
+  }
+  sc[LNV_SC_STATUS] = (double)status;
+}
+
+// ------------------------------------------------------------------ per-item kernels
+// Workgroup q handles item q of L's pattern: 64 blocks of one row, 4 threads
+// per block, thread (b, r) owns row r of block b (4 elements).
+
+// G, F and the trace partials of one evaluation.
+__global__ __launch_bounds__(256) void k_assemble(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
+    const int* __restrict__ col, const int* __restrict__ l_lut,
+    const double* __restrict__ L, const int* __restrict__ x_lut,
+    const double* __restrict__ X, const double* __restrict__ YT,
+    const double* __restrict__ Wv, const int* __restrict__ z_lut,
+    const double* __restrict__ Z, const double* __restrict__ V, double* __restrict__ G,
+    double* __restrict__ F, double* __restrict__ partials) {
+  __shared__ double sh[16];
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rp[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  if (b < cnt) {
+    const int p = c0 + b;
+    const int j = col[p];
+    const int xp = x_lut[(size_t)i * n + j];
+    const int xtp = x_lut[(size_t)j * n + i];
+    const int ytp = l_lut[(size_t)j * n + i];
+    const int zp = z_lut[(size_t)i * n + j];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int e = r * 4 + c, et = c * 4 + r;
+      const double x = xp >= 0 ? X[(size_t)xp * 16 + e] : 0.0;
+      const double xt = xtp >= 0 ? X[(size_t)xtp * 16 + et] : 0.0;
+      const double yt = YT[(size_t)p * 16 + e];
+      const double ytt = ytp >= 0 ? YT[(size_t)ytp * 16 + et] : 0.0;
+      const double w = Wv[(size_t)p * 16 + e];
+      const double z = zp >= 0 ? Z[(size_t)zp * 16 + e] : 0.0;
+      const double v = V[(size_t)p * 16 + e];
+      const double l = L[(size_t)p * 16 + e];
+      const double g = 2.0 * (3.0 * (x + xt) - 2.0 * (yt + ytt + w));
+      const double f = 12.0 * (z - v);
+      G[(size_t)p * 16 + e] = g;
+      F[(size_t)p * 16 + e] = f;
+      s[0] = fma(l, x, s[0]);
+      s[1] = fma(l, yt, s[1]);
+      s[2] = fma(l, z, s[2]);
+      s[3] = fma(l, v, s[3]);
+      s[4] = fma(f, f, s[4]);
+      s[5] = fma(g, f, s[5]);
+    }
+  }
+  for (int c = 0; c < 6; ++c) {
+    const double t = block_sum(s[c], sh);
+    if (threadIdx.x == 0) partials[(size_t)c * n_items + item] = t;
+  }
+}
+
+// Electron number at the current L: partials <L,Z>, <L,V>, <12(Z-V), F>, <L,L>.
+__global__ __launch_bounds__(256) void k_nassemble(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
+    const int* __restrict__ col, const double* __restrict__ L, const int* __restrict__ z_lut,
+    const double* __restrict__ Z, const double* __restrict__ V,
+    const double* __restrict__ Fc, double* __restrict__ partials) {
+  __shared__ double sh[16];
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rp[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  double s[4] = {0, 0, 0, 0};
+  if (b < cnt) {
+    const int p = c0 + b;
+    const int j = col[p];
+    const int zp = z_lut[(size_t)i * n + j];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int e = r * 4 + c;
+      const double z = zp >= 0 ? Z[(size_t)zp * 16 + e] : 0.0;
+      const double v = V[(size_t)p * 16 + e];
+      const double l = L[(size_t)p * 16 + e];
+      const double f1 = 12.0 * (z - v);
+      s[0] = fma(l, z, s[0]);
+      s[1] = fma(l, v, s[1]);
+      s[2] = fma(f1, Fc[(size_t)p * 16 + e], s[2]);
+      s[3] = fma(l, l, s[3]);
+    }
+  }
+  for (int c = 0; c < 4; ++c) {
+    const double t = block_sum(s[c], sh);
+    if (threadIdx.x == 0) partials[(size_t)c * n_items + item] = t;
+  }
+}
+
+// <A, B> with B located through B's index table (or at A's positions).
+__global__ __launch_bounds__(256) void k_dot_items(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
+    const int* __restrict__ col, const double* __restrict__ A, const int* __restrict__ b_lut,
+    const double* __restrict__ B, double* __restrict__ partials,
+    const double* __restrict__ skip) {
+  __shared__ double sh[16];
+  if (skip != nullptr && *skip != 0.0) return;
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  double s = 0.0;
+  for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const int i = items[2 * item], c0 = items[2 * item + 1];
+    const int cnt = min(kWave, rp[i + 1] - c0);
+    if (b < cnt) {
+      const int p = c0 + b;
+      const int q = b_lut ? b_lut[(size_t)i * n + col[p]] : p;
+      if (q >= 0)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          s = fma(A[(size_t)p * 16 + r * 4 + c], B[(size_t)q * 16 + r * 4 + c], s);
+    }
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// H' = H - mu S on H's pattern (S located through its index table).
+__global__ __launch_bounds__(256) void k_hprime(int n, const int* __restrict__ items,
+                                                const int* __restrict__ rp,
+                                                const int* __restrict__ col,
+                                                const double* __restrict__ H,
+                                                const int* __restrict__ s_lut,
+                                                const double* __restrict__ S,
+                                                const double* __restrict__ sc,
+                                                double* __restrict__ Hp) {
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rp[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  if (b >= cnt) return;
+  const double mu = sc[LNV_SC_MU];
+  const int p = c0 + b;
+  const int q = s_lut[(size_t)i * n + col[p]];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int e = r * 4 + c;
+    const double sv = q >= 0 ? S[(size_t)q * 16 + e] : 0.0;
+    Hp[(size_t)p * 16 + e] = H[(size_t)p * 16 + e] - mu * sv;
+  }
+}
+
+// Identity blocks on the diagonal of L's pattern, zero elsewhere.
+__global__ __launch_bounds__(256) void k_identity(const int* __restrict__ items,
+                                                  const int* __restrict__ rp,
+                                                  const int* __restrict__ col,
+                                                  double* __restrict__ D) {
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rp[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  if (b >= cnt) return;
+  const int p = c0 + b;
+  const bool diag = col[p] == i;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) D[(size_t)p * 16 + r * 4 + c] = (diag && r == c) ? 1.0 : 0.0;
+}
+
+// ------------------------------------------------------------------ vector kernels
+// Fixed grid of kVecGrid workgroups, grid-stride over the nv values of L's
+// pattern; partial q of component c goes to partials[c * kVecGrid + q].
+
+// g = G - mu F; partials <g,g>, <g,g_prev>
+__global__ __launch_bounds__(256) void k_vec_g(int64_t nv, const double* __restrict__ G,
+                                               const double* __restrict__ F,
+                                               const double* __restrict__ gprev,
+                                               const double* __restrict__ sc,
+                                               double* __restrict__ g,
+                                               double* __restrict__ partials) {
+  __shared__ double sh[16];
+  const double mu = sc[LNV_SC_MU];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+    const double v = G[q] - mu * F[q];
+    g[q] = v;
+    s0 = fma(v, v, s0);
+    s1 = fma(v, gprev[q], s1);
+  }
+  double t = block_sum(s0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  t = block_sum(s1, sh);
+  if (threadIdx.x == 0) partials[kVecGrid + blockIdx.x] = t;
+}
+
+// D = -g + beta D_prev; partial <D, F>
+__global__ __launch_bounds__(256) void k_vec_dir(int64_t nv, const double* __restrict__ g,
+                                                 const double* __restrict__ Dprev,
+                                                 const double* __restrict__ F,
+                                                 const double* __restrict__ sc,
+                                                 double* __restrict__ D,
+                                                 double* __restrict__ partials) {
+  __shared__ double sh[16];
+  const double beta = sc[LNV_SC_BETA];
+  double s0 = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+    const double v = beta != 0.0 ? -g[q] + beta * Dprev[q] : -g[q];
+    D[q] = v;
+    s0 = fma(v, F[q], s0);
+  }
+  const double t = block_sum(s0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// D <- D - coef F; partial <g, D>
+__global__ __launch_bounds__(256) void k_vec_proj(int64_t nv, const double* __restrict__ F,
+                                                  const double* __restrict__ g,
+                                                  const double* __restrict__ sc,
+                                                  double* __restrict__ D,
+                                                  double* __restrict__ partials) {
+  __shared__ double sh[16];
+  const double coef = sc[LNV_SC_T5];
+  double s0 = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+    const double v = D[q] - coef * F[q];
+    D[q] = v;
+    s0 = fma(g[q], v, s0);
+  }
+  const double t = block_sum(s0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// L += sc[idx] * D (skipped when skip != null and *skip != 0)
+__global__ __launch_bounds__(256) void k_vec_axpy(int64_t nv, const double* __restrict__ D,
+                                                  const double* __restrict__ sc, int idx,
+                                                  const double* __restrict__ skip,
+                                                  double* __restrict__ L) {
+  if (skip != nullptr && *skip != 0.0) return;
+  const double a = sc[idx];
+  if (a == 0.0) return;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256)
+    L[q] = L[q] + a * D[q];
+}
+
+// ------------------------------------------------------------------ host helpers
+int64_t slot_len(int n_items_L) {
+  const int64_t a = 8 * (int64_t)n_items_L, b = 8 * (int64_t)kVecGrid;
+  return a > b ? a : b;
+}
+
+int scalar_stage(const double* partials, const RedList& rl, double* sc, int stage,
+                 const StageArgs& sa, hipStream_t s) {
+  k_scalar<<<1, 256, 0, s>>>(partials, rl, sc, stage, sa);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+RedList reds() {
+  RedList r{};
+  r.nr = 0;
+  return r;
+}
+void add(RedList& rl, int64_t off, int count, int stride, int dst) {
+  rl.r[rl.nr++] = Red{(int)off, count, stride, dst};
+}
+
+bool pattern_ready(const lnv_pattern* p, bool lut, bool lut_t, bool items) {
+  return p && p->row_ptr && p->col && (!lut || p->lut) && (!lut_t || p->lut_t) &&
+         (!items || p->items);
+}
+
+int check_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* G,
+               const lnv_bsm* F, const lnv_eval_ws* ws) {
+  if (!bsm_ok(L) || !bsm_ok(S) || !bsm_ok(H) || !ws || !ws->YT || !ws->W || !ws->V ||
+      !ws->partials || !ws->scalars)
+    return LNV_EINVAL;
+  if ((G && !bsm_ok(G)) || (F && !bsm_ok(F))) return LNV_EINVAL;
+  if (!bsm_ok(&ws->SL) || !bsm_ok(&ws->X) || !bsm_ok(&ws->Z)) return LNV_EINVAL;
+  if (L->blk != 4 || S->blk != 4 || H->blk != 4) return LNV_EUNSUPPORTED;
+  const int n = L->pat->n;
+  if (S->pat->n != n || H->pat->n != n || ws->SL.pat->n != n || ws->X.pat->n != n ||
+      ws->Z.pat->n != n)
+    return LNV_EPATTERN;
+  if (G && G->pat != L->pat) return LNV_EPATTERN;
+  if (F && F->pat != L->pat) return LNV_EPATTERN;
+  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
+      !pattern_ready(H->pat, false, false, false) ||
+      !pattern_ready(ws->SL.pat, false, true, true) ||
+      !pattern_ready(ws->X.pat, true, true, true) || !pattern_ready(ws->Z.pat, true, false, true))
+    return LNV_EPATTERN;
+  if (ws->partials_len < lnv_partials_len(L->pat->n_items)) return LNV_EINVAL;
+  return LNV_OK;
+}
+
+// The six products, the assembly of G and F and the energy / electron traces.
+int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, double* F,
+              double* EN, const lnv_eval_ws* ws, hipStream_t s) {
+  const lnv_pattern* pl = L->pat;
+  lnv_bsm YT{pl, 4, LNV_F64, ws->YT}, Wm{pl, 4, LNV_F64, ws->W}, Vm{pl, 4, LNV_F64, ws->V};
+  LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &ws->SL, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, H, &ws->SL, 1, 0.0, &ws->X, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, S, &ws->SL, 1, 0.0, &ws->Z, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->X, 1, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->X, 0, 0.0, &Wm, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
+  const int ni = pl->n_items;
+  double* part = ws->partials;
+  k_assemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, pl->lut,
+                                static_cast<const double*>(L->val), ws->X.pat->lut,
+                                static_cast<const double*>(ws->X.val), ws->YT, ws->W,
+                                ws->Z.pat->lut, static_cast<const double*>(ws->Z.val), ws->V,
+                                G, F, part);
+  LNV_LAUNCH_CHECK();
+  RedList rl = reds();
+  add(rl, 0 * (int64_t)ni, ni, 1, LNV_SC_T0);
+  add(rl, 1 * (int64_t)ni, ni, 1, LNV_SC_T1);
+  add(rl, 2 * (int64_t)ni, ni, 1, LNV_SC_T2);
+  add(rl, 3 * (int64_t)ni, ni, 1, LNV_SC_T3);
+  add(rl, 4 * (int64_t)ni, ni, 1, LNV_SC_FF);
+  add(rl, 5 * (int64_t)ni, ni, 1, LNV_SC_GF);
+  StageArgs sa{};
+  sa.en_out = EN;
+  return scalar_stage(part, rl, ws->scalars, ST_EVAL, sa, s);
+}
+
+int vec_grid() { return kVecGrid; }
+
+}  // namespace
+}  // namespace lnv
+
+using namespace lnv;
+
+extern "C" const char* lnv_strerror(int st) {
+  switch (st) {
+    case LNV_OK: return "success";
+    case LNV_EINVAL: return "invalid argument";
+    case LNV_ECAPACITY: return "output capacity too small";
+    case LNV_EPATTERN: return "incompatible or incomplete sparsity pattern";
+    case LNV_EHIP: return "HIP runtime error";
+    case LNV_ENUMERIC: return "non-finite value or no admissible root";
+    case LNV_EUNSUPPORTED: return "unsupported request";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int lnv_last_hip_error(void) { return g_last_hip; }
+
+extern "C" int lnv_sync_check(hipStream_t s) {
+  LNV_HIP(hipStreamSynchronize(s));
+  LNV_HIP(hipGetLastError());
+  return LNV_OK;
+}
+
+extern "C" int64_t lnv_partials_len(int32_t n_items_L) {
+  return (int64_t)LNV_NSLOTS * slot_len(n_items_L);
+}
+
+extern "C" int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B,
+                                    int32_t transB, double beta, lnv_bsm* C, int32_t store,
+                                    const lnv_bsm* M1, const lnv_bsm* M2, double* partials,
+                                    double* out, hipStream_t s) {
+  if (!bsm_ok(C)) return LNV_EINVAL;
+  if ((M1 && (!bsm_ok(M1) || M1->pat != C->pat)) || (M2 && (!bsm_ok(M2) || M2->pat != C->pat)))
+    return LNV_EPATTERN;
+  if ((M1 || M2) && (!partials || !out)) return LNV_EINVAL;
+  if (M2 && !M1) return LNV_EINVAL;
+  const double* m1 = M1 ? static_cast<const double*>(M1->val) : nullptr;
+  const double* m2 = M2 ? static_cast<const double*>(M2->val) : nullptr;
+  LNV_TRY(multiply_launch(alpha, A, B, transB, beta, C, store, m1, m2, partials, nullptr, s));
+  if (!M1) return LNV_OK;
+  const int ni = C->pat->n_items;
+  // reduce the interleaved partials into out[0..1] (fixed order)
+  RedList rl = reds();
+  add(rl, 0, ni, 2, 0);
+  if (M2) add(rl, 1, ni, 2, 1);
+  StageArgs sa{};
+  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* out,
+                           hipStream_t s) {
+  if (!bsm_ok(A) || !bsm_ok(B) || !partials || !out) return LNV_EINVAL;
+  if (A->blk != 4 || B->blk != 4) return LNV_EUNSUPPORTED;
+  const lnv_pattern *pa = A->pat, *pb = B->pat;
+  if (pa->n != pb->n) return LNV_EPATTERN;
+  const bool same = pa == pb;
+  if (!pattern_ready(pa, false, false, true) || (!same && !pb->lut)) return LNV_EPATTERN;
+  const int ni = pa->n_items;
+  if (ni == 0) {
+    LNV_HIP(hipMemsetAsync(out, 0, sizeof(double), s));
+    return LNV_OK;
+  }
+  const int grid = ni < LNV_DOT_PARTIALS ? ni : LNV_DOT_PARTIALS;
+  k_dot_items<<<grid, 256, 0, s>>>(pa->n, ni, pa->items, pa->row_ptr, pa->col,
+                                   static_cast<const double*>(A->val), same ? nullptr : pb->lut,
+                                   static_cast<const double*>(B->val), partials, nullptr);
+  LNV_LAUNCH_CHECK();
+  RedList rl = reds();
+  add(rl, 0, grid, 1, 0);
+  StageArgs sa{};
+  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
+                        lnv_bsm* F, double* EN, const lnv_eval_ws* ws, hipStream_t s) {
+  if (!G || !F) return LNV_EINVAL;
+  LNV_TRY(check_eval(L, S, H, G, F, ws));
+  return eval_core(L, S, H, static_cast<double*>(G->val), static_cast<double*>(F->val), EN, ws,
+                   s);
+}
+
+namespace {
+
+int check_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_cg_ws* ws) {
+  if (!ws) return LNV_EINVAL;
+  LNV_TRY(check_eval(L, S, H, nullptr, nullptr, &ws->ev));
+  if (!ws->SL2 || !ws->Hp || !ws->G || !ws->F || !ws->g || !ws->g_prev || !ws->D ||
+      !ws->D_prev)
+    return LNV_EINVAL;
+  if (!pattern_ready(S->pat, true, false, false) || !pattern_ready(H->pat, false, false, true))
+    return LNV_EPATTERN;
+  if (ws->ev.X.pat->nnzb < ws->ev.Z.pat->nnzb) return LNV_EINVAL;  // Z_F reuses X's buffer
+  return LNV_OK;
+}
+
+// Traces of the cubic along direction P at the current L, with M the matrix
+// the trace is taken against (H' for the energy line, S for the electron
+// number).  A_P^T = S P (into buf), X_P = M A_P, then
+//   slotT0: <P, X_P>,  slot(1,2): <L, P_L(X_P A_P)>, <P, P_L(X_P A_P)>,
+//   slot3:  <P, P_L(X_P A)>  with A^T = SLcur.
+int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const double* P,
+                 double* buf, const lnv_pattern* sl_pat, const lnv_bsm* SLcur, lnv_bsm XP,
+                 bool xp_sym,
+                 double* partials, int64_t slot, const double* skip, hipStream_t s) {
+  const lnv_pattern* pl = L->pat;
+  lnv_bsm Pm{pl, 4, LNV_F64, const_cast<double*>(P)};
+  lnv_bsm APT{sl_pat, 4, LNV_F64, buf};
+  LNV_TRY(multiply_launch(1.0, S, &Pm, 0, 0.0, &APT, 1, nullptr, nullptr, nullptr, skip, s));
+  LNV_TRY(multiply_launch(1.0, M, &APT, 1, 0.0, &XP, 1, nullptr, nullptr, nullptr, skip, s));
+  const int ni = pl->n_items;
+  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, XP.pat->lut,
+                                 static_cast<const double*>(XP.val), partials + 0 * slot, skip);
+  // (one workgroup per item: partial q belongs to item q)
+  LNV_LAUNCH_CHECK();
+  // P_L(X_P A_P) = P_L(A_P^T X_P^T)^T ; its traces with symmetric L and P are
+  // those of the transpose.  X_P is symmetric when M = S (then no transpose).
+  const int tb = xp_sym ? 0 : 1;
+  lnv_bsm scratchC{pl, 4, LNV_F64, const_cast<double*>(P)};  // not written (store = 0)
+  LNV_TRY(multiply_launch(1.0, &APT, &XP, tb, 0.0, &scratchC, 0,
+                          static_cast<const double*>(L->val), P, partials + 1 * slot, skip, s));
+  if (SLcur)
+    LNV_TRY(multiply_launch(1.0, SLcur, &XP, tb, 0.0, &scratchC, 0, P, nullptr,
+                            partials + 2 * slot, skip, s));
+  return LNV_OK;
+}
+
+}  // namespace
+
+extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, double n_elec, lnv_cg_ws* ws,
+                           hipStream_t s) {
+  if (!bsm_ok(L) || !bsm_ok(S) || !ws || !(n_elec > 0.0)) return LNV_EINVAL;
+  if (L->blk != 4 || S->blk != 4) return LNV_EUNSUPPORTED;
+  const lnv_eval_ws& ev = ws->ev;
+  if (!ev.partials || !ev.scalars || !ws->D || !ws->D_prev || !ws->g_prev || !ws->SL2)
+    return LNV_EINVAL;
+  if (!bsm_ok(&ev.SL) || !bsm_ok(&ev.X) || !bsm_ok(&ev.Z)) return LNV_EINVAL;
+  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(ev.SL.pat, false, true, true) ||
+      !pattern_ready(ev.Z.pat, true, false, true))
+    return LNV_EPATTERN;
+  if (ev.partials_len < lnv_partials_len(L->pat->n_items)) return LNV_EINVAL;
+  const lnv_pattern* pl = L->pat;
+  const int64_t nv = pl->nnzb * 16;
+  const int ni = pl->n_items;
+  const int64_t slot = slot_len(ni);
+  double* part = ev.partials;
+  double* sc = ev.scalars;
+  LNV_HIP(hipMemsetAsync(sc, 0, sizeof(double) * LNV_NSCALARS, s));
+  LNV_HIP(hipMemsetAsync(ws->g_prev, 0, sizeof(double) * nv, s));
+  LNV_HIP(hipMemsetAsync(ws->D_prev, 0, sizeof(double) * nv, s));
+  LNV_HIP(hipMemsetAsync(L->val, 0, sizeof(double) * nv, s));
+  k_identity<<<ni, 256, 0, s>>>(pl->items, pl->row_ptr, pl->col, ws->D);
+  LNV_LAUNCH_CHECK();
+  // N(lambda I) = 6 Tr[S^2] lambda^2 - 4 Tr[S^3] lambda^3 at L = 0:
+  // A_D^T = S I, Z_D = S A_D = S^2,  <I, Z_D> and <I, P_L(Z_D A_D)>.
+  lnv_bsm ZD{ev.Z.pat, 4, LNV_F64, ev.Z.val};
+  LNV_TRY(cubic_traces(L, S, S, ws->D, ws->SL2, ev.SL.pat, nullptr, ZD, true, part, slot,
+                       nullptr, s));
+  RedList rl = reds();
+  add(rl, 0, ni, 1, LNV_SC_T0);
+  add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
+  StageArgs sa{};
+  sa.n_elec = n_elec;
+  LNV_TRY(scalar_stage(part, rl, sc, ST_INIT, sa, s));
+  k_vec_axpy<<<vec_grid(), 256, 0, s>>>(nv, ws->D, sc, LNV_SC_LAMBDA, nullptr,
+                                        static_cast<double*>(L->val));
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double n_elec,
+                           int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s) {
+  if (!opts || opts->reset_period <= 0 || !(n_elec > 0.0) || k < 0) return LNV_EINVAL;
+  LNV_TRY(check_cg(L, S, H, ws));
+  const lnv_eval_ws& ev = ws->ev;
+  const lnv_pattern* pl = L->pat;
+  const lnv_pattern* ph = H->pat;
+  const int64_t nv = pl->nnzb * 16;
+  const int ni = pl->n_items;
+  const int64_t slot = slot_len(ni);
+  double* part = ev.partials;
+  double* sc = ev.scalars;
+  double* Lv = static_cast<double*>(L->val);
+  StageArgs sa{};
+  sa.n_elec = n_elec;
+  sa.n_tol = opts->n_tol;
+  sa.step_cap = opts->step_cap;
+  sa.reset = (k % opts->reset_period) == 0;
+
+  // 1. E, N, G, F and mu
+  LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s));
+  // 2-3. g = G - mu F, Polak-Ribiere beta with resets
+  k_vec_g<<<kVecGrid, 256, 0, s>>>(nv, ws->G, ws->F, ws->g_prev, sc, ws->g, part);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0, kVecGrid, 1, LNV_SC_GG);
+    add(rl, kVecGrid, kVecGrid, 1, LNV_SC_GGP);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_BETA, sa, s));
+  }
+  // 4. D = -g + beta D_prev, projected orthogonal to F
+  k_vec_dir<<<kVecGrid, 256, 0, s>>>(nv, ws->g, ws->D_prev, ws->F, sc, ws->D, part);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0, kVecGrid, 1, LNV_SC_DF);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_PROJ, sa, s));
+  }
+  k_vec_proj<<<kVecGrid, 256, 0, s>>>(nv, ws->F, ws->g, sc, ws->D, part);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0, kVecGrid, 1, LNV_SC_C1);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_NONE, sa, s));
+  }
+  // 5. exact cubic line minimisation of E - mu N along D
+  k_hprime<<<ph->n_items, 256, 0, s>>>(ph->n, ph->items, ph->row_ptr, ph->col,
+                                       static_cast<const double*>(H->val), S->pat->lut,
+                                       static_cast<const double*>(S->val), sc, ws->Hp);
+  LNV_LAUNCH_CHECK();
+  lnv_bsm Hp{ph, 4, LNV_F64, ws->Hp};
+  lnv_bsm XD{ev.X.pat, 4, LNV_F64, ev.X.val};
+  LNV_TRY(cubic_traces(L, S, &Hp, ws->D, ws->SL2, ev.SL.pat, &ev.SL, XD, false, part, slot,
+                       nullptr, s));
+  {
+    RedList rl = reds();
+    add(rl, 0, ni, 1, LNV_SC_T0);
+    add(rl, 1 * slot + 0, ni, 2, LNV_SC_T1);
+    add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
+    add(rl, 2 * slot + 0, ni, 2, LNV_SC_T3);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_ALPHA, sa, s));
+  }
+  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv);
+  LNV_LAUNCH_CHECK();
+  // 6. electron number at the new L; cubic correction along F when needed
+  lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
+  lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
+  LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, S, &SL2, 1, 0.0, &ev.Z, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, &SL2, &ev.Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
+  k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, ev.Z.pat->lut,
+                                 static_cast<const double*>(ev.Z.val), ev.V, ws->F, part);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0 * (int64_t)ni, ni, 1, LNV_SC_T0);
+    add(rl, 1 * (int64_t)ni, ni, 1, LNV_SC_T1);
+    add(rl, 2 * (int64_t)ni, ni, 1, LNV_SC_T2);
+    add(rl, 3 * (int64_t)ni, ni, 1, LNV_SC_LL);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_NCHK, sa, s));
+  }
+  const double* skip = sc + LNV_SC_SKIP_NCORR;
+  lnv_bsm ZF{ev.Z.pat, 4, LNV_F64, ev.X.val};
+  // the old S.L buffer (ev.SL) is free now: A_F^T = S F goes there, and the
+  // products with A_new use S.L_new in SL2.
+  {
+    LNV_TRY(cubic_traces(L, S, S, ws->F, static_cast<double*>(ev.SL.val), ev.SL.pat, &SL2, ZF,
+                         true, part, slot, skip, s));
+    RedList rl = reds();
+    add(rl, 0, ni, 1, LNV_SC_T0);
+    add(rl, 1 * slot + 0, ni, 2, LNV_SC_T1);
+    add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
+    add(rl, 2 * slot + 0, ni, 2, LNV_SC_T3);
+    // the reductions read garbage partials when skipped; ST_DELTA ignores them
+    LNV_TRY(scalar_stage(part, rl, sc, ST_DELTA, sa, s));
+  }
+  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->F, sc, LNV_SC_DELTA, skip, Lv);
+  LNV_LAUNCH_CHECK();
+  std::swap(ws->g, ws->g_prev);
+  std::swap(ws->D, ws->D_prev);
+  return LNV_OK;
+}

@@ -1,0 +1,259 @@
+// a3: numeric block-sparse multiply, FP64, 4x4 atom blocks.
+//
+// C_ij = alpha * sum_k A_ik op(B)_kj + beta * C_ij for the blocks (i,j) of
+// C's pattern only -- the range-truncated sparse products through which
+// every LNV quantity is formed at linear cost (Sec. II.C.2).
+//
+// Mapping to CDNA4 (gfx950):
+//  * One wavefront owns up to 64 consecutive blocks (i, j_0..j_63) of one
+//    output row and keeps each lane's 4x4 accumulator in registers for the
+//    whole contraction (no atomics, fixed summation order).
+//  * The k loop runs over A's row i, identical for every lane, so the A block
+//    is wave-uniform and lives in scalar registers (one s_load per block,
+//    broadcast to all 64 lanes by the VALU's scalar operand).
+//  * Each lane finds B_kj in O(1) through the dense atom-pair index table of
+//    B's pattern (lut[k*n + j]) and streams the 128-byte block as 8 dwordx4
+//    loads; index loads run two steps ahead and block loads one step ahead.
+//  * Products are 64 v_fma_f64 per (i,k,j) triple on the FP64 VALU, which on
+//    MI355X has the same 78.6 TFLOP/s peak as the FP64 matrix cores; a 4x4
+//    block triple is far smaller than an MFMA tile and packing several atoms
+//    into a tile multiplies the flops of these range-limited patterns by ~5.
+//  * Workgroups of 4 wavefronts; logical workgroup ids are remapped so each
+//    XCD processes a contiguous range of rows (spatially close atoms share
+//    the B blocks in that XCD's L2).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+namespace lnv {
+namespace {
+
+template <int TRANS_B>
+__device__ __forceinline__ void block_fma(double (&acc)[16], const double (&a)[16],
+                                          const double (&b)[16]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const double bv = TRANS_B ? b[c * 4 + m] : b[m * 4 + c];
+        acc[r * 4 + c] = fma(a[r * 4 + m], bv, acc[r * 4 + c]);
+      }
+}
+
+__device__ __forceinline__ void load_block(double (&b)[16], const double* __restrict__ p) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int h = 0; h < 8; ++h) {
+    const double2 v = q[h];
+    b[2 * h] = v.x;
+    b[2 * h + 1] = v.y;
+  }
+}
+
+template <int TRANS_B, int STORE, int NDOT>
+__global__ __launch_bounds__(256) void k_mul44(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ a_rp,
+    const int* __restrict__ a_col, const double* __restrict__ a_val,
+    const int* __restrict__ b_lut, const double* __restrict__ b_val,
+    const int* __restrict__ c_rp, const int* __restrict__ c_col, double* __restrict__ c_val,
+    double alpha, double beta, const double* __restrict__ m1, const double* __restrict__ m2,
+    double* __restrict__ partials, const double* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0.0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (item >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const int i = items[2 * item];
+  const int c0 = items[2 * item + 1];
+  const int cnt = min(kWave, c_rp[i + 1] - c0);
+  const bool act = lane < cnt;
+  const int j = act ? c_col[c0 + lane] : 0;
+  const int* __restrict__ lcol = b_lut + j;
+  const size_t ns = (size_t)n;
+  const int t0 = a_rp[i], t1 = a_rp[i + 1];
+
+  double acc[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+
+  double bA[16], bB[16], a[16];
+  int pA = -1, pB = -1;
+  if (act && t0 < t1) pA = lcol[(size_t)a_col[t0] * ns];
+  if (act && t0 + 1 < t1) pB = lcol[(size_t)a_col[t0 + 1] * ns];
+  if (pA >= 0) load_block(bA, b_val + (size_t)pA * 16);
+
+  for (int t = t0; t < t1; t += 2) {
+    // step t: consume bA, fetch bB (step t+1) and the index of step t+2
+    int pA2 = -1;
+    if (act && t + 2 < t1) pA2 = lcol[(size_t)a_col[t + 2] * ns];
+    if (pB >= 0) load_block(bB, b_val + (size_t)pB * 16);
+    {
+      const double* ap = a_val + (size_t)t * 16;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = ap[q];
+      if (pA >= 0) block_fma<TRANS_B>(acc, a, bA);
+    }
+    if (t + 1 >= t1) break;
+    // step t+1: consume bB, fetch bA (step t+2) and the index of step t+3
+    int pB2 = -1;
+    if (act && t + 3 < t1) pB2 = lcol[(size_t)a_col[t + 3] * ns];
+    if (pA2 >= 0) load_block(bA, b_val + (size_t)pA2 * 16);
+    {
+      const double* ap = a_val + (size_t)(t + 1) * 16;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = ap[q];
+      if (pB >= 0) block_fma<TRANS_B>(acc, a, bB);
+    }
+    pA = pA2;
+    pB = pB2;
+  }
+
+  double d1 = 0.0, d2 = 0.0;
+  if (act) {
+    const size_t cp = (size_t)(c0 + lane) * 16;
+    double out[16];
+    if (beta != 0.0) {
+      double old[16];
+      load_block(old, c_val + cp);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[e] + beta * old[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[e];
+    }
+    if (STORE) {
+      double2* q = reinterpret_cast<double2*>(c_val + cp);
+#pragma unroll
+      for (int h = 0; h < 8; ++h) q[h] = make_double2(out[2 * h], out[2 * h + 1]);
+    }
+    if (NDOT >= 1) {
+      double mv[16];
+      load_block(mv, m1 + cp);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) d1 = fma(mv[e], out[e], d1);
+    }
+    if (NDOT >= 2) {
+      double mv[16];
+      load_block(mv, m2 + cp);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) d2 = fma(mv[e], out[e], d2);
+    }
+  }
+  if (NDOT >= 1) {
+    d1 = wave_sum(d1);
+    if (NDOT >= 2) d2 = wave_sum(d2);
+    if (lane == 0) {
+      partials[2 * item] = d1;
+      partials[2 * item + 1] = d2;
+    }
+  }
+}
+
+using KernelFn = void (*)(int, int, const int*, const int*, const int*, const double*,
+                          const int*, const double*, const int*, const int*, double*, double,
+                          double, const double*, const double*, double*, const double*);
+
+template <int TB>
+KernelFn pick_store(int store, int ndot) {
+  if (store) {
+    if (ndot == 0) return k_mul44<TB, 1, 0>;
+    if (ndot == 1) return k_mul44<TB, 1, 1>;
+    return k_mul44<TB, 1, 2>;
+  }
+  if (ndot == 1) return k_mul44<TB, 0, 1>;
+  return k_mul44<TB, 0, 2>;
+}
+
+// ------------------------------------------------------------------ timing
+struct Timer {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;
+};
+Timer g_timer;
+
+int timer_begin(hipStream_t s, hipEvent_t* stop) {
+  if (!g_timer.on) return LNV_OK;
+  if (g_timer.used == g_timer.ev.size()) {
+    hipEvent_t a, b;
+    LNV_HIP(hipEventCreate(&a));
+    LNV_HIP(hipEventCreate(&b));
+    g_timer.ev.emplace_back(a, b);
+  }
+  auto& pr = g_timer.ev[g_timer.used++];
+  LNV_HIP(hipEventRecord(pr.first, s));
+  *stop = pr.second;
+  return LNV_OK;
+}
+
+}  // namespace
+
+int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
+                    double beta, const lnv_bsm* C, int store, const double* m1,
+                    const double* m2, double* partials, const double* skip,
+                    hipStream_t s) {
+  if (!bsm_ok(A) || !bsm_ok(B) || !bsm_ok(C)) return LNV_EINVAL;
+  if (A->blk != 4 || B->blk != 4 || C->blk != 4) return LNV_EUNSUPPORTED;
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
+  if (pa->n != pb->n || pa->n != pc->n) return LNV_EPATTERN;
+  if (!pa->row_ptr || !pa->col || !pc->row_ptr || !pc->col || !pc->items) return LNV_EPATTERN;
+  const int32_t* lut = transB ? pb->lut_t : pb->lut;
+  if (!lut) return LNV_EPATTERN;
+  const int ndot = m2 ? 2 : (m1 ? 1 : 0);
+  if (m2 && !m1) return LNV_EINVAL;
+  if (ndot > 0 && !partials) return LNV_EINVAL;
+  if (!store && ndot == 0) return LNV_EINVAL;
+  if (pc->n_items == 0) return LNV_OK;
+  KernelFn fn = transB ? pick_store<1>(store, ndot) : pick_store<0>(store, ndot);
+  const int wgs = round_up((pc->n_items + 3) / 4, kNumXcd);
+  hipEvent_t stop = nullptr;
+  LNV_TRY(timer_begin(s, &stop));
+  fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_items, pc->items, pa->row_ptr, pa->col,
+                         static_cast<const double*>(A->val), lut,
+                         static_cast<const double*>(B->val), pc->row_ptr, pc->col,
+                         static_cast<double*>(C->val), alpha, beta, m1, m2, partials, skip);
+  LNV_LAUNCH_CHECK();
+  if (stop) LNV_HIP(hipEventRecord(stop, s));
+  return LNV_OK;
+}
+
+}  // namespace lnv
+
+using namespace lnv;
+
+extern "C" int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B,
+                                int32_t transB, double beta, lnv_bsm* C, hipStream_t s) {
+  return multiply_launch(alpha, A, B, transB, beta, C, 1, nullptr, nullptr, nullptr, nullptr,
+                         s);
+}
+
+extern "C" int lnv_timing_enable(int32_t on) {
+  g_timer.on = on != 0;
+  return LNV_OK;
+}
+
+extern "C" int lnv_timing_reset(void) {
+  g_timer.used = 0;
+  return LNV_OK;
+}
+
+extern "C" int lnv_timing_read(double* ms_total, int64_t* launches) {
+  if (!ms_total || !launches) return LNV_EINVAL;
+  double tot = 0.0;
+  for (size_t q = 0; q < g_timer.used; ++q) {
+    auto& pr = g_timer.ev[q];
+    LNV_HIP(hipEventSynchronize(pr.second));
+    float ms = 0.f;
+    LNV_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+    tot += ms;
+  }
+  *ms_total = tot;
+  *launches = (int64_t)g_timer.used;
+  return LNV_OK;
+}

@@ -1,0 +1,417 @@
+// Set-up kernels of the LNV hot path, run once per geometry:
+//   a0  range patterns (neighbour lists)            Sec. II.C.2 range rule
+//   a1  synthetic S and H blocks                    stand-in for Eq. (2)
+//   a2  patterns of block-sparse products           Sec. II.C.2 sparse products
+//   index tables and work lists of a pattern
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "internal.h"
+
+namespace lnv {
+namespace {
+
+// ------------------------------------------------------------------ scans
+// In-place exclusive scan of data[0..n) into data[0..n] (data[n] = total) by
+// one workgroup of 1024 threads; each thread scans a contiguous chunk.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_scan(T* __restrict__ data, int n) {
+  __shared__ T part[1024];
+  const int tid = threadIdx.x;
+  const int chunk = (n + 1023) / 1024;
+  const int b = min(n, tid * chunk), e = min(n, b + chunk);
+  T s = 0;
+  for (int q = b; q < e; ++q) s += data[q];
+  part[tid] = s;
+  __syncthreads();
+  if (tid == 0) {
+    T run = 0;
+    for (int q = 0; q < 1024; ++q) {
+      const T v = part[q];
+      part[q] = run;
+      run += v;
+    }
+    data[n] = run;
+  }
+  __syncthreads();
+  T run = part[tid];
+  for (int q = b; q < e; ++q) {
+    const T v = data[q];
+    data[q] = run;
+    run += v;
+  }
+}
+
+// ------------------------------------------------------------------ a0
+// One wavefront per row i scans every j in ascending order (so the columns
+// come out sorted) and compacts the in-range ones with a ballot.
+__global__ __launch_bounds__(256) void k_neighbours(const double* __restrict__ pos, int n,
+                                                    double bx, double by, double bz,
+                                                    double R2, int* __restrict__ counts,
+                                                    const int* __restrict__ row_ptr,
+                                                    int* __restrict__ col, int fill) {
+#pragma clang fp contract(off)
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int lane = threadIdx.x & 63;
+  const double xi = pos[3 * row], yi = pos[3 * row + 1], zi = pos[3 * row + 2];
+  const int base = fill ? row_ptr[row] : 0;
+  int cnt = 0;
+  for (int j0 = 0; j0 < n; j0 += kWave) {
+    const int j = j0 + lane;
+    bool ok = false;
+    if (j < n) {
+      double dx = pos[3 * j] - xi;
+      double dy = pos[3 * j + 1] - yi;
+      double dz = pos[3 * j + 2] - zi;
+      dx = dx - bx * rint(dx / bx);
+      dy = dy - by * rint(dy / by);
+      dz = dz - bz * rint(dz / bz);
+      double d2 = dx * dx + dy * dy;
+      d2 = d2 + dz * dz;
+      ok = d2 <= R2;
+    }
+    const uint64_t m = __ballot(ok);
+    if (fill && ok) col[base + cnt + __popcll(m & ((1ull << lane) - 1ull))] = j;
+    cnt += __popcll(m);
+  }
+  if (!fill && lane == 0) counts[row] = cnt;
+}
+
+// ------------------------------------------------------------------ a2
+// One workgroup per output row: the union of B's rows k over A's row i is
+// accumulated in an LDS bitmap of n bits (optionally intersected with the
+// mask row), then counted or emitted in ascending order.
+__global__ __launch_bounds__(256) void k_symbolic(
+    int n, const int* __restrict__ a_rp, const int* __restrict__ a_col,
+    const int* __restrict__ b_rp, const int* __restrict__ b_col,
+    const int* __restrict__ m_rp, const int* __restrict__ m_col, int* __restrict__ counts,
+    const int* __restrict__ out_rp, int* __restrict__ out_col,
+    long long* __restrict__ triples, int fill) {
+  extern __shared__ unsigned int sm[];
+  __shared__ long long scan[256];
+  const int W = (n + 31) >> 5;
+  unsigned int* bits = sm;
+  unsigned int* mbits = sm + W;
+  const int i = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int w = tid; w < W; w += 256) {
+    bits[w] = 0u;
+    mbits[w] = 0u;
+  }
+  __syncthreads();
+  if (m_rp)
+    for (int q = m_rp[i] + tid; q < m_rp[i + 1]; q += 256) {
+      const int j = m_col[q];
+      atomicOr(&mbits[j >> 5], 1u << (j & 31));
+    }
+  const int t0 = a_rp[i], t1 = a_rp[i + 1];
+  for (int t = t0 + wv; t < t1; t += 4) {
+    const int k = a_col[t];
+    for (int q = b_rp[k] + lane; q < b_rp[k + 1]; q += kWave) {
+      const int j = b_col[q];
+      atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+  }
+  __syncthreads();
+  if (m_rp)
+    for (int w = tid; w < W; w += 256) bits[w] &= mbits[w];
+  __syncthreads();
+  const int chunk = (W + 255) / 256;
+  const int w0 = min(W, tid * chunk), w1 = min(W, w0 + chunk);
+  long long mine = 0;
+  for (int w = w0; w < w1; ++w) mine += __popc(bits[w]);
+  scan[tid] = mine;
+  __syncthreads();
+  if (tid == 0) {
+    long long run = 0;
+    for (int q = 0; q < 256; ++q) {
+      const long long v = scan[q];
+      scan[q] = run;
+      run += v;
+    }
+    if (!fill) counts[i] = (int)run;
+  }
+  __syncthreads();
+  if (fill) {
+    int p = out_rp[i] + (int)scan[tid];
+    for (int w = w0; w < w1; ++w) {
+      unsigned int x = bits[w];
+      while (x) {
+        const int b = __ffs(x) - 1;
+        out_col[p++] = (w << 5) + b;
+        x &= x - 1u;
+      }
+    }
+  } else if (triples) {
+    long long tr = 0;
+    for (int t = t0 + wv; t < t1; t += 4) {
+      const int k = a_col[t];
+      for (int q = b_rp[k] + lane; q < b_rp[k + 1]; q += kWave) {
+        const int j = b_col[q];
+        tr += (bits[j >> 5] >> (j & 31)) & 1u;
+      }
+    }
+    __syncthreads();
+    scan[tid] = tr;
+    __syncthreads();
+    if (tid == 0) {
+      long long s = 0;
+      for (int q = 0; q < 256; ++q) s += scan[q];
+      triples[i] = s;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ index tables
+__global__ __launch_bounds__(256) void k_lut(int n, const int* __restrict__ rp,
+                                             const int* __restrict__ col, int* __restrict__ lut,
+                                             int* __restrict__ lut_t) {
+  const int i = blockIdx.x;
+  for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 256) {
+    const int j = col[p];
+    if (lut) lut[(size_t)i * n + j] = p;
+    if (lut_t) lut_t[(size_t)j * n + i] = p;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_items(int n, const int* __restrict__ rp,
+                                               int* __restrict__ counts,
+                                               const int* __restrict__ off,
+                                               int* __restrict__ items) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int len = rp[i + 1] - rp[i];
+  const int c = (len + kWave - 1) / kWave;
+  if (!items) {
+    counts[i] = c;
+    return;
+  }
+  const int o = off[i];
+  for (int q = 0; q < c; ++q) {
+    items[2 * (o + q)] = i;
+    items[2 * (o + q) + 1] = rp[i] + q * kWave;
+  }
+}
+
+// ------------------------------------------------------------------ a1
+// Counter-based SplitMix64: output number ctr of the stream seeded with seed
+// (Steele, Lea & Flood 2014): mix(seed + (ctr + 1) * golden gamma).
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t ctr) {
+  uint64_t z = seed + (ctr + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double rand_entry(uint64_t seed, uint64_t stream, uint64_t a,
+                                             uint64_t b, uint64_t e, double scale) {
+  const uint64_t ctr = (stream << 56) | (a << 32) | (b << 8) | e;
+  const double u = (double)(splitmix64_at(seed, ctr) >> 11) * 0x1.0p-53;
+  return scale * (u - 0.5);
+}
+
+__global__ __launch_bounds__(128) void k_synth(const double* __restrict__ pos, double bx,
+                                               double by, double bz,
+                                               const int* __restrict__ nfun, int blk,
+                                               const int* __restrict__ rp,
+                                               const int* __restrict__ col,
+                                               double* __restrict__ val, int kind, double R2,
+                                               double decay, int mx, int my, int mz,
+                                               uint64_t seed, double scale) {
+#pragma clang fp contract(off)
+  const int i = blockIdx.x;
+  const uint64_t stream = kind == 0 ? 1ull : 2ull;
+  const int ni = nfun ? nfun[i] : blk;
+  for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 128) {
+    const int j = col[p];
+    const int nj = nfun ? nfun[j] : blk;
+    const double dx = pos[3 * j] - pos[3 * i];
+    const double dy = pos[3 * j + 1] - pos[3 * i + 1];
+    const double dz = pos[3 * j + 2] - pos[3 * i + 2];
+    double w = 0.0;
+    for (int tx = -mx; tx <= mx; ++tx)
+      for (int ty = -my; ty <= my; ++ty)
+        for (int tz = -mz; tz <= mz; ++tz) {
+          const double x = dx + (double)tx * bx;
+          const double y = dy + (double)ty * by;
+          const double z = dz + (double)tz * bz;
+          double d2 = x * x + y * y;
+          d2 = d2 + z * z;
+          if (d2 <= R2) w = w + exp(-(sqrt(d2) / decay));
+        }
+    double* out = val + (size_t)p * blk * blk;
+    for (int r = 0; r < blk; ++r)
+      for (int c = 0; c < blk; ++c) {
+        double v = 0.0;
+        if (r < ni && c < nj) {
+          double m;
+          if (i == j) {
+            const double a = rand_entry(seed, stream, i, i, r * ni + c, scale);
+            const double b = rand_entry(seed, stream, i, i, c * ni + r, scale);
+            m = (a + b) * 0.5;
+          } else if (i < j) {
+            m = rand_entry(seed, stream, i, j, r * nj + c, scale);
+          } else {
+            m = rand_entry(seed, stream, j, i, c * ni + r, scale);
+          }
+          const double wm = w * m;
+          if (kind == 0)
+            v = (i == j && r == c) ? wm + 2.0 : wm;
+          else
+            v = -wm;
+        }
+        out[r * blk + c] = v;
+      }
+  }
+}
+
+int read_total_int(const int32_t* dev, int64_t* host, hipStream_t s) {
+  int32_t t = 0;
+  LNV_HIP(hipMemcpyAsync(&t, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  LNV_HIP(hipStreamSynchronize(s));
+  *host = t;
+  return LNV_OK;
+}
+
+}  // namespace
+}  // namespace lnv
+
+using namespace lnv;
+
+extern "C" int lnv_neighbours(const double* pos, int32_t n, const double* box, double R,
+                              int32_t* row_ptr, int32_t* col, int64_t cap,
+                              int64_t* nnz_out, hipStream_t s) {
+  if (!pos || !box || !row_ptr || !nnz_out || n <= 0 || n > LNV_MAX_ATOMS || !(R >= 0.0))
+    return LNV_EINVAL;
+  if (!(box[0] > 0.0 && box[1] > 0.0 && box[2] > 0.0)) return LNV_EINVAL;
+  const double R2 = R * R;
+  const int grid = (n + 3) / 4;
+  k_neighbours<<<grid, 256, 0, s>>>(pos, n, box[0], box[1], box[2], R2, row_ptr, nullptr,
+                                    nullptr, 0);
+  LNV_LAUNCH_CHECK();
+  k_scan<int32_t><<<1, 1024, 0, s>>>(row_ptr, n);
+  LNV_LAUNCH_CHECK();
+  LNV_TRY(read_total_int(row_ptr + n, nnz_out, s));
+  if (!col) return LNV_OK;
+  if (cap < *nnz_out) return LNV_ECAPACITY;
+  k_neighbours<<<grid, 256, 0, s>>>(pos, n, box[0], box[1], box[2], R2, nullptr, row_ptr,
+                                    col, 1);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
+                                   const lnv_pattern* mask, int32_t* row_ptr, int32_t* col,
+                                   int64_t cap, int64_t* nnz_out, int64_t* row_triples,
+                                   int64_t* triples_out, hipStream_t s) {
+  if (!A || !B || !row_ptr || !nnz_out) return LNV_EINVAL;
+  if (!A->row_ptr || !A->col || !B->row_ptr || !B->col) return LNV_EPATTERN;
+  const int n = A->n;
+  if (n <= 0 || n > LNV_MAX_ATOMS || B->n != n) return LNV_EPATTERN;
+  if (mask && (mask->n != n || !mask->row_ptr || !mask->col)) return LNV_EPATTERN;
+  if (triples_out && !row_triples) return LNV_EINVAL;
+  const size_t lds = 2 * (size_t)((n + 31) / 32) * sizeof(unsigned int);
+  const int* mrp = mask ? mask->row_ptr : nullptr;
+  const int* mcol = mask ? mask->col : nullptr;
+  k_symbolic<<<n, 256, lds, s>>>(n, A->row_ptr, A->col, B->row_ptr, B->col, mrp, mcol,
+                                 row_ptr, nullptr, nullptr,
+                                 reinterpret_cast<long long*>(row_triples), 0);
+  LNV_LAUNCH_CHECK();
+  k_scan<int32_t><<<1, 1024, 0, s>>>(row_ptr, n);
+  LNV_LAUNCH_CHECK();
+  if (row_triples) {
+    k_scan<long long><<<1, 1024, 0, s>>>(reinterpret_cast<long long*>(row_triples), n);
+    LNV_LAUNCH_CHECK();
+  }
+  LNV_TRY(read_total_int(row_ptr + n, nnz_out, s));
+  if (triples_out) {
+    LNV_HIP(hipMemcpyAsync(triples_out, row_triples + n, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s));
+    LNV_HIP(hipStreamSynchronize(s));
+  }
+  if (!col) return LNV_OK;
+  if (cap < *nnz_out) return LNV_ECAPACITY;
+  k_symbolic<<<n, 256, lds, s>>>(n, A->row_ptr, A->col, B->row_ptr, B->col, mrp, mcol,
+                                 nullptr, row_ptr, col, nullptr, 1);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t,
+                               hipStream_t s) {
+  if (!P || !P->row_ptr || !P->col || P->n <= 0) return LNV_EPATTERN;
+  if (!lut && !lut_t) return LNV_OK;
+  const size_t bytes = (size_t)P->n * (size_t)P->n * sizeof(int32_t);
+  if (lut) LNV_HIP(hipMemsetAsync(lut, 0xFF, bytes, s));
+  if (lut_t) LNV_HIP(hipMemsetAsync(lut_t, 0xFF, bytes, s));
+  k_lut<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, lut, lut_t);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_pattern_items(const lnv_pattern* P, int32_t* items, int64_t cap,
+                                 int32_t* n_items_out, hipStream_t s) {
+  if (!P || !P->row_ptr || P->n <= 0) return LNV_EPATTERN;
+  if (!n_items_out) return LNV_EINVAL;
+  const int n = P->n;
+  int32_t* cnt = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * (n + 1), s));
+  const int grid = (n + 255) / 256;
+  k_items<<<grid, 256, 0, s>>>(n, P->row_ptr, cnt, nullptr, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_scan<int32_t><<<1, 1024, 0, s>>>(cnt, n);
+    e = hipGetLastError();
+  }
+  int32_t total = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, cnt + n, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  int st = LNV_OK;
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    st = LNV_EHIP;
+  } else {
+    *n_items_out = total;
+    if (items) {
+      if (cap < total) {
+        st = LNV_ECAPACITY;
+      } else {
+        k_items<<<grid, 256, 0, s>>>(n, P->row_ptr, nullptr, cnt, items);
+        e = hipGetLastError();
+        if (e != hipSuccess) {
+          set_hip_error(e);
+          st = LNV_EHIP;
+        }
+      }
+    }
+  }
+  hipError_t ef = hipFreeAsync(cnt, s);
+  if (st == LNV_OK && ef != hipSuccess) {
+    set_hip_error(ef);
+    st = LNV_EHIP;
+  }
+  return st;
+}
+
+extern "C" int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
+                                const lnv_bsm* M, int32_t kind, double R, double decay,
+                                uint64_t seed, double scale, hipStream_t s) {
+  if (!pos || !box || !bsm_ok(M) || (kind != 0 && kind != 1) || !(R >= 0.0) ||
+      !(decay > 0.0))
+    return LNV_EINVAL;
+  if (!M->pat->row_ptr || !M->pat->col) return LNV_EPATTERN;
+  if (M->blk <= 0 || M->blk > 16) return LNV_EUNSUPPORTED;
+  const int n = M->pat->n;
+  if (n >= (1 << 24)) return LNV_EUNSUPPORTED;  // counter layout: 24-bit atom ids
+  const int mx = (int)std::ceil(R / box[0]) + 1;
+  const int my = (int)std::ceil(R / box[1]) + 1;
+  const int mz = (int)std::ceil(R / box[2]) + 1;
+  k_synth<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, M->blk, M->pat->row_ptr,
+                            M->pat->col, static_cast<double*>(M->val), kind, R * R, decay,
+                            mx, my, mz, seed, scale);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}

@@ -1,0 +1,124 @@
+"""ctypes binding of liblnv.so (the C ABI declared in include/lnv.h).
+
+Argument marshalling only: every computation happens in the HIP kernels of
+the library.  `load()` fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_int32, c_int64, c_uint64, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblnv.so")
+
+# status codes (lnv_status)
+OK, EINVAL, ECAPACITY, EPATTERN, EHIP, ENUMERIC, EUNSUPPORTED = range(7)
+F64 = 0
+DOT_PARTIALS = 1024
+NSLOTS = 12
+
+# device scalar block indices (LNV_SC_*)
+SC = dict(E=0, N=1, MU=2, BETA=3, ALPHA=4, DELTA=5, FF=6, GG=7, C1=8, C2=9, C3=10,
+          N0=11, N1=12, N2=13, N3=14, FORCE_RESET=15, SKIP_NCORR=16, GNORM=17,
+          N_AFTER=18, LAMBDA=19, STATUS=20, LL=21, GF=22, DF=23)
+NSCALARS = 40
+ST_NONFINITE, ST_NO_ALPHA, ST_NO_DELTA, ST_DELTA_CAPPED = 1, 2, 4, 8
+
+
+class LnvPattern(ctypes.Structure):
+    _fields_ = [("n", c_int32), ("n_items", c_int32), ("nnzb", c_int64),
+                ("row_ptr", c_void_p), ("col", c_void_p), ("lut", c_void_p),
+                ("lut_t", c_void_p), ("items", c_void_p)]
+
+
+class LnvBsm(ctypes.Structure):
+    _fields_ = [("pat", POINTER(LnvPattern)), ("blk", c_int32), ("dtype", c_int32),
+                ("val", c_void_p)]
+
+
+class LnvEvalWs(ctypes.Structure):
+    _fields_ = [("SL", LnvBsm), ("X", LnvBsm), ("Z", LnvBsm), ("YT", c_void_p),
+                ("W", c_void_p), ("V", c_void_p), ("partials", c_void_p),
+                ("partials_len", c_int64), ("scalars", c_void_p)]
+
+
+class LnvCgWs(ctypes.Structure):
+    _fields_ = [("ev", LnvEvalWs), ("SL2", c_void_p), ("Hp", c_void_p), ("G", c_void_p),
+                ("F", c_void_p), ("g", c_void_p), ("g_prev", c_void_p), ("D", c_void_p),
+                ("D_prev", c_void_p)]
+
+
+class LnvOpts(ctypes.Structure):
+    _fields_ = [("reset_period", c_int32), ("n_tol", c_double), ("step_cap", c_double)]
+
+
+PPat = POINTER(LnvPattern)
+PBsm = POINTER(LnvBsm)
+
+# name -> (restype, argtypes); the exported symbols of include/lnv.h
+SIGNATURES = {
+    "lnv_strerror": (c_char_p, [c_int]),
+    "lnv_last_hip_error": (c_int, []),
+    "lnv_sync_check": (c_int, [c_void_p]),
+    "lnv_neighbours": (c_int, [c_void_p, c_int32, POINTER(c_double), c_double, c_void_p,
+                               c_void_p, c_int64, POINTER(c_int64), c_void_p]),
+    "lnv_pattern_product": (c_int, [PPat, PPat, PPat, c_void_p, c_void_p, c_int64,
+                                    POINTER(c_int64), c_void_p, POINTER(c_int64), c_void_p]),
+    "lnv_pattern_lut": (c_int, [PPat, c_void_p, c_void_p, c_void_p]),
+    "lnv_pattern_items": (c_int, [PPat, c_void_p, c_int64, POINTER(c_int32), c_void_p]),
+    "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, PBsm, c_int32, c_double,
+                                 c_double, c_uint64, c_double, c_void_p]),
+    "lnv_bsm_multiply": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_void_p]),
+    "lnv_bsm_multiply_dot": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_int32,
+                                     PBsm, PBsm, c_void_p, c_void_p, c_void_p]),
+    "lnv_bsm_dot": (c_int, [PBsm, PBsm, c_void_p, c_void_p, c_void_p]),
+    "lnv_partials_len": (c_int64, [c_int32]),
+    "lnv_eval": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, c_void_p, POINTER(LnvEvalWs), c_void_p]),
+    "lnv_cg_init": (c_int, [PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
+    "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
+                            POINTER(LnvCgWs), c_void_p]),
+    "lnv_timing_enable": (c_int, [c_int32]),
+    "lnv_timing_read": (c_int, [POINTER(c_double), POINTER(c_int64)]),
+    "lnv_timing_reset": (c_int, []),
+}
+
+_LIB = None
+
+
+class LnvError(RuntimeError):
+    def __init__(self, fn, status, lib):
+        msg = lib.lnv_strerror(status).decode()
+        if status == EHIP:
+            msg += f" (hipError_t {lib.lnv_last_hip_error()})"
+        super().__init__(f"{fn} failed: {msg} [status {status}]")
+        self.status = status
+
+
+def load(path=None):
+    """Load liblnv.so once and declare its signatures; raises when missing."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _LIB = lib
+    return lib
+
+
+def check(lib, fn, status):
+    if status != OK:
+        raise LnvError(fn, status, lib)
+    return status
+
+
+def call(fn, *args):
+    lib = load()
+    return check(lib, fn, getattr(lib, fn)(*args))

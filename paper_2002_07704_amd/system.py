@@ -1,0 +1,310 @@
+"""Device-resident LNV system: patterns, matrices and workspaces.
+
+Builds, on one GPU, everything the hot path needs for one geometry -- range
+patterns of S, H and L (Sec. II.C.2), the synthetic S and H, the natural
+patterns of the products S.L, H.L.S and S.L.S with their index tables and
+work lists -- then exposes the evaluation and CG calls of liblnv.  Torch is
+used for device memory and the stream only; every step runs in the library's
+HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from ctypes import byref, c_double, c_int32, c_int64
+
+import numpy as np
+import torch
+
+from . import lib as L_
+
+BLK = 4
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Pattern:
+    """Atom-block CSR pattern on the device plus its optional tables."""
+
+    def __init__(self, n, row_ptr, col):
+        self.n = int(n)
+        self.row_ptr = row_ptr
+        self.col = col
+        self.lut = None
+        self.lut_t = None
+        self.items = None
+        self.triples = None
+        self.struct = L_.LnvPattern()
+        self._sync()
+
+    @property
+    def nnzb(self):
+        return int(self.col.numel())
+
+    def _sync(self):
+        s = self.struct
+        s.n = self.n
+        s.nnzb = self.nnzb
+        s.row_ptr = self.row_ptr.data_ptr()
+        s.col = self.col.data_ptr() if self.col.numel() else self.row_ptr.data_ptr()
+        s.lut = self.lut.data_ptr() if self.lut is not None else None
+        s.lut_t = self.lut_t.data_ptr() if self.lut_t is not None else None
+        s.items = self.items.data_ptr() if self.items is not None else None
+        s.n_items = 0 if self.items is None else self.items.numel() // 2
+
+    def build_lut(self, lut=True, lut_t=False):
+        dev = self.row_ptr.device
+        if lut and self.lut is None:
+            self.lut = torch.empty(self.n * self.n, dtype=torch.int32, device=dev)
+        if lut_t and self.lut_t is None:
+            self.lut_t = torch.empty(self.n * self.n, dtype=torch.int32, device=dev)
+        self._sync()
+        L_.call("lnv_pattern_lut", byref(self.struct), _ptr(self.lut) if lut else None,
+                _ptr(self.lut_t) if lut_t else None, _stream())
+        return self
+
+    def build_items(self):
+        cnt = c_int32(0)
+        L_.call("lnv_pattern_items", byref(self.struct), None, 0, byref(cnt), _stream())
+        self.items = torch.empty(max(1, 2 * cnt.value), dtype=torch.int32,
+                                 device=self.row_ptr.device)
+        L_.call("lnv_pattern_items", byref(self.struct), _ptr(self.items),
+                self.items.numel() // 2, byref(cnt), _stream())
+        self.items = self.items[:2 * cnt.value]
+        self._sync()
+        self.struct.n_items = cnt.value
+        return self
+
+    def host(self):
+        return self.row_ptr.cpu().numpy(), self.col.cpu().numpy()
+
+
+def neighbours(pos_dev, box, R):
+    """a0: range pattern for cutoff R (lnv_neighbours, two-phase)."""
+    n = pos_dev.shape[0]
+    box_c = (c_double * 3)(*[float(b) for b in box])
+    rp = torch.empty(n + 1, dtype=torch.int32, device=pos_dev.device)
+    nnz = c_int64(0)
+    L_.call("lnv_neighbours", _ptr(pos_dev), n, box_c, float(R), _ptr(rp), None, 0,
+            byref(nnz), _stream())
+    col = torch.empty(nnz.value, dtype=torch.int32, device=pos_dev.device)
+    L_.call("lnv_neighbours", _ptr(pos_dev), n, box_c, float(R), _ptr(rp), _ptr(col),
+            nnz.value, byref(nnz), _stream())
+    return Pattern(n, rp, col)
+
+
+def product_pattern(A, B, mask=None, triples=True):
+    """a2: pattern of A.B (natural range) or of P_mask(A.B), with triple count."""
+    n = A.n
+    dev = A.row_ptr.device
+    rp = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    rt = torch.empty(n + 1, dtype=torch.int64, device=dev) if triples else None
+    nnz = c_int64(0)
+    tr = c_int64(0)
+    mp = byref(mask.struct) if mask is not None else None
+    L_.call("lnv_pattern_product", byref(A.struct), byref(B.struct), mp, _ptr(rp), None, 0,
+            byref(nnz), _ptr(rt), byref(tr) if triples else None, _stream())
+    col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=dev)
+    L_.call("lnv_pattern_product", byref(A.struct), byref(B.struct), mp, _ptr(rp), _ptr(col),
+            col.numel(), byref(nnz), None, None, _stream())
+    P = Pattern(n, rp, col[:nnz.value])
+    P.triples = tr.value if triples else None
+    return P
+
+
+class Matrix:
+    """Block values on a pattern: tensor [nnzb, 4, 4] float64 plus lnv_bsm."""
+
+    def __init__(self, pattern, values=None):
+        self.pat = pattern
+        if values is None:
+            values = torch.zeros(max(1, pattern.nnzb), BLK, BLK, dtype=torch.float64,
+                                 device=pattern.row_ptr.device)
+        self.val = values
+        self.struct = L_.LnvBsm()
+        self.struct.pat = ctypes.pointer(pattern.struct)
+        self.struct.blk = BLK
+        self.struct.dtype = L_.F64
+        self.struct.val = values.data_ptr()
+
+    def rebind(self, values):
+        self.val = values
+        self.struct.val = values.data_ptr()
+        return self
+
+
+def bsm(pattern, tensor):
+    """lnv_bsm view of a raw value tensor on a pattern."""
+    return Matrix(pattern, tensor)
+
+
+def multiply(alpha, A, B, transB, beta, C):
+    L_.call("lnv_bsm_multiply", float(alpha), byref(A.struct), byref(B.struct), int(transB),
+            float(beta), byref(C.struct), _stream())
+    return C
+
+
+def multiply_dot(alpha, A, B, transB, beta, C, store, M1, M2=None):
+    dev = C.val.device
+    part = torch.empty(max(2, 2 * C.pat.struct.n_items), dtype=torch.float64, device=dev)
+    out = torch.zeros(2, dtype=torch.float64, device=dev)
+    L_.call("lnv_bsm_multiply_dot", float(alpha), byref(A.struct), byref(B.struct), int(transB),
+            float(beta), byref(C.struct), int(store), byref(M1.struct),
+            byref(M2.struct) if M2 is not None else None, _ptr(part), _ptr(out), _stream())
+    return out
+
+
+def dot(A, B):
+    dev = A.val.device
+    part = torch.empty(L_.DOT_PARTIALS, dtype=torch.float64, device=dev)
+    out = torch.zeros(1, dtype=torch.float64, device=dev)
+    L_.call("lnv_bsm_dot", byref(A.struct), byref(B.struct), _ptr(part), _ptr(out), _stream())
+    return out
+
+
+@dataclasses.dataclass
+class Opts:
+    reset_period: int = 40
+    n_tol: float = 1e-11
+    step_cap: float = 0.1
+
+
+class LNVSystem:
+    """One geometry on one GPU: patterns, S, H, L and the CG workspace."""
+
+    def __init__(self, w, device="cuda", R_L=None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("LNVSystem needs a GPU (HIP device)")
+        L_.load()
+        if int(np.max(w.nfun)) != BLK or int(np.min(w.nfun)) != BLK:
+            raise NotImplementedError("the FP64 path takes 4 support functions per atom")
+        self.w = w
+        self.n = w.n
+        self.n_elec = float(w.n_elec)
+        self.R_L = float(w.R_L if R_L is None else R_L)
+        dev = torch.device(device)
+        self.dev = dev
+        self.pos = torch.as_tensor(np.ascontiguousarray(w.pos), dtype=torch.float64, device=dev)
+        self.box = [float(b) for b in w.box]
+        # a0: range patterns
+        self.pS = neighbours(self.pos, self.box, w.R_S)
+        self.pH = neighbours(self.pos, self.box, w.R_H)
+        self.pL = neighbours(self.pos, self.box, self.R_L)
+        # a1: synthetic S, H
+        self.S = Matrix(self.pS)
+        self.H = Matrix(self.pH)
+        box_c = (c_double * 3)(*self.box)
+        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, None, byref(self.S.struct), 0,
+                float(w.R_S), 3.0, int(w.seed), float(w.scale), _stream())
+        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, None, byref(self.H.struct), 1,
+                float(w.R_H), 2.5, int(w.seed), float(w.scale), _stream())
+        # a2: natural product patterns (A = LS is stored as its transpose SL)
+        self.pSL = product_pattern(self.pS, self.pL)            # S.L
+        pLS = product_pattern(self.pL, self.pS)                 # L.S (row form of A)
+        self.pX = product_pattern(self.pH, pLS)                 # H.L.S
+        self.pZ = product_pattern(self.pS, pLS)                 # S.L.S
+        self.pXT = product_pattern(self.pSL, self.pH, triples=False)   # S.L.H = pat(X)^T
+        self.triples = dict(
+            SL=self.pSL.triples, X=self.pX.triples, Z=self.pZ.triples,
+            YT=product_pattern(self.pSL, self.pXT, mask=self.pL).triples,
+            W=product_pattern(self.pSL, self.pX, mask=self.pL).triples,
+            V=product_pattern(self.pSL, self.pZ, mask=self.pL).triples,
+        )
+        del pLS
+        self.pXT = None
+        # index tables and work lists
+        self.pL.build_lut(lut=True).build_items()
+        self.pS.build_lut(lut=True)
+        self.pH.build_items()
+        self.pSL.build_lut(lut=False, lut_t=True).build_items()
+        self.pX.build_lut(lut=True, lut_t=True).build_items()
+        self.pZ.build_lut(lut=True).build_items()
+        assert self.pX.nnzb >= self.pZ.nnzb
+        # buffers
+        nL = self.pL.nnzb
+
+        def lbuf():
+            return torch.zeros(nL, BLK, BLK, dtype=torch.float64, device=dev)
+
+        self.L = Matrix(self.pL)
+        self.G = Matrix(self.pL)
+        self.F = Matrix(self.pL)
+        self.SL = Matrix(self.pSL)
+        self.X = Matrix(self.pX)
+        self.Z = Matrix(self.pZ)
+        self.YT, self.W, self.V = lbuf(), lbuf(), lbuf()
+        self.SL2 = torch.zeros_like(self.SL.val)
+        self.Hp = torch.zeros_like(self.H.val)
+        self.g, self.g_prev, self.D, self.D_prev = lbuf(), lbuf(), lbuf(), lbuf()
+        plen = L_.load().lnv_partials_len(self.pL.struct.n_items)
+        self.partials = torch.zeros(plen, dtype=torch.float64, device=dev)
+        self.scalars = torch.zeros(L_.NSCALARS, dtype=torch.float64, device=dev)
+        self.EN = torch.zeros(2, dtype=torch.float64, device=dev)
+        self.ws = L_.LnvCgWs()
+        ev = self.ws.ev
+        ev.SL = self.SL.struct
+        ev.X = self.X.struct
+        ev.Z = self.Z.struct
+        ev.YT, ev.W, ev.V = self.YT.data_ptr(), self.W.data_ptr(), self.V.data_ptr()
+        ev.partials = self.partials.data_ptr()
+        ev.partials_len = plen
+        ev.scalars = self.scalars.data_ptr()
+        self.ws.SL2 = self.SL2.data_ptr()
+        self.ws.Hp = self.Hp.data_ptr()
+        self.ws.G = self.G.val.data_ptr()
+        self.ws.F = self.F.val.data_ptr()
+        self._bufs = {self.g.data_ptr(): self.g, self.g_prev.data_ptr(): self.g_prev,
+                      self.D.data_ptr(): self.D, self.D_prev.data_ptr(): self.D_prev}
+        self.ws.g, self.ws.g_prev = self.g.data_ptr(), self.g_prev.data_ptr()
+        self.ws.D, self.ws.D_prev = self.D.data_ptr(), self.D_prev.data_ptr()
+        self.opts = Opts()
+        self.k = 0
+        torch.cuda.synchronize()
+
+    # ----------------------------------------------------------- flop accounting
+    def flops(self, what="eval"):
+        """Algorithmic flops (2 n^3 per block triple) of one eval or CG step."""
+        t = self.triples
+        ev = t["SL"] + t["X"] + t["Z"] + t["YT"] + t["W"] + t["V"]
+        if what == "eval":
+            tot = ev
+        else:
+            line = t["SL"] + t["X"] + 2 * t["YT"]
+            nchk = t["SL"] + t["Z"] + t["V"]
+            ncor = t["SL"] + t["Z"] + 2 * t["V"]
+            tot = ev + line + nchk + ncor
+        return 2 * BLK ** 3 * tot
+
+    # ----------------------------------------------------------- hot path
+    def eval(self):
+        L_.call("lnv_eval", byref(self.L.struct), byref(self.S.struct), byref(self.H.struct),
+                byref(self.G.struct), byref(self.F.struct), _ptr(self.EN), byref(self.ws.ev),
+                _stream())
+        return self.EN
+
+    def cg_init(self):
+        L_.call("lnv_cg_init", byref(self.L.struct), byref(self.S.struct), self.n_elec,
+                byref(self.ws), _stream())
+        self.k = 0
+
+    def cg_step(self):
+        o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap)
+        L_.call("lnv_cg_step", byref(self.L.struct), byref(self.S.struct), byref(self.H.struct),
+                self.n_elec, self.k, byref(o), byref(self.ws), _stream())
+        self.k += 1
+
+    def scalar(self, name):
+        return float(self.scalars[L_.SC[name]].item())
+
+    def scalars_host(self):
+        v = self.scalars.cpu().numpy()
+        return {k: float(v[i]) for k, i in L_.SC.items()}
+
+    def buffer(self, ptr):
+        return self._bufs[ptr]

@@ -1,0 +1,243 @@
+"""GPU path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances: neighbour lists and product patterns are integer results and must
+be bit-exact; FP64 values follow the energy bar |dE| <= 1e-10 Ha/atom and a
+relative 1e-12 on matrices (FP64 with different summation orders: the
+rounding error of a k-term block sum is ~k * 1.1e-16 relative).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lnv_workloads as W
+from oracle import lnv as olnv
+from oracle import structure as ost
+
+pytestmark = pytest.mark.gpu
+
+
+def _dense(sysg, M, pat):
+    rp, col = pat.host()
+    return ost.blocks_to_dense(M.val.cpu().numpy(), rp, col, sysg.w.nfun)
+
+
+def _set(sysg, M, pat, A):
+    rp, col = pat.host()
+    M.val.copy_(torch.as_tensor(ost.dense_to_blocks(A, rp, col, sysg.w.nfun)))
+
+
+def _rand_sym(n, mask, seed, scale=0.05):
+    rng = np.random.default_rng(seed)
+    C = rng.standard_normal((n, n)) * scale
+    return ((C + C.T) * 0.5) * mask
+
+
+@pytest.fixture(scope="module")
+def si64(gpu):
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.get("si64_4x4")
+    return LNVSystem(w), ost.System(w)
+
+
+@pytest.fixture(scope="module")
+def si8(gpu):
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.get("si8_4x4", R_L=1000.0)
+    return LNVSystem(w), ost.System(w)
+
+
+# ------------------------------------------------------------------ a0
+@pytest.mark.parametrize("name", ["si64_4x4", "si8_4x4", "si4096_4x4"])
+def test_neighbours_bit_exact(gpu, name):
+    from paper_2002_07704_amd.system import neighbours
+    w = W.get(name)
+    pos = torch.as_tensor(w.pos, device="cuda")
+    for R in (w.R_S, w.R_H, w.R_L, 3.0, 25.0):
+        P = neighbours(pos, w.box, R)
+        rp, col = P.host()
+        rp0, col0 = ost.neighbours(w.pos, w.box, R)
+        assert np.array_equal(rp, rp0) and np.array_equal(col, col0), (name, R)
+
+
+def test_neighbours_ragged_subset(gpu):
+    from paper_2002_07704_amd.system import neighbours
+    w = W.get("si64_4x4")
+    for m in (1, 5, 37, 63):
+        pos = w.pos[:m].copy()
+        P = neighbours(torch.as_tensor(pos, device="cuda"), w.box, 9.5)
+        rp0, col0 = ost.neighbours(pos, w.box, 9.5)
+        rp, col = P.host()
+        assert np.array_equal(rp, rp0) and np.array_equal(col, col0), m
+
+
+def test_neighbours_capacity_protocol(gpu):
+    import ctypes
+    from paper_2002_07704_amd import lib as L
+    w = W.get("si64_4x4")
+    pos = torch.as_tensor(w.pos, device="cuda")
+    rp = torch.empty(w.n + 1, dtype=torch.int32, device="cuda")
+    col = torch.empty(10, dtype=torch.int32, device="cuda")
+    box = (ctypes.c_double * 3)(*w.box)
+    nnz = ctypes.c_int64(0)
+    st = L.load().lnv_neighbours(ctypes.c_void_p(pos.data_ptr()), w.n, box, 12.0,
+                                 ctypes.c_void_p(rp.data_ptr()), ctypes.c_void_p(col.data_ptr()),
+                                 10, ctypes.byref(nnz), None)
+    assert st == L.ECAPACITY and nnz.value == 44 * 64
+
+
+# ------------------------------------------------------------------ a1
+@pytest.mark.parametrize("fx", ["si64", "si8"])
+def test_synthetic_blocks(fx, request):
+    sysg, ref = request.getfixturevalue(fx)
+    for name, M, Mr in (("S", sysg.S, ref.Sb), ("H", sysg.H, ref.Hb)):
+        got = M.val.cpu().numpy()
+        assert got.shape == Mr.shape
+        err = np.abs(got - Mr).max()
+        assert err <= 4e-16 * np.abs(Mr).max() * 4, (name, err)
+
+
+# ------------------------------------------------------------------ a2
+@pytest.mark.parametrize("fx", ["si64", "si8"])
+def test_product_patterns_and_triples(fx, request):
+    sysg, ref = request.getfixturevalue(fx)
+    n = ref.n
+    S = ost.pattern_matrix(*ref.pat["S"], n)
+    H = ost.pattern_matrix(*ref.pat["H"], n)
+    Lp = ost.pattern_matrix(*ref.pat["L"], n)
+    SL, tSL = ost.pattern_product(S, Lp)
+    LS, _ = ost.pattern_product(Lp, S)
+    X, tX = ost.pattern_product(H, LS)
+    Z, tZ = ost.pattern_product(S, LS)
+    for P, R in ((sysg.pSL, SL), (sysg.pX, X), (sysg.pZ, Z)):
+        rp, col = P.host()
+        assert np.array_equal(rp, R.indptr) and np.array_equal(col, R.indices)
+    assert sysg.triples["SL"] == tSL and sysg.triples["X"] == tX and sysg.triples["Z"] == tZ
+    _, tW = ost.pattern_product(SL, X, Lp)
+    _, tYT = ost.pattern_product(SL, X.T.tocsr(), Lp)
+    _, tV = ost.pattern_product(SL, Z, Lp)
+    assert (sysg.triples["W"], sysg.triples["YT"], sysg.triples["V"]) == (tW, tYT, tV)
+
+
+# ------------------------------------------------------------------ a3
+def test_multiply_against_dense_masked_products(si64):
+    from paper_2002_07704_amd.system import Matrix, multiply, multiply_dot, dot
+    sysg, ref = si64
+    n = ref.S.shape[0]
+    Ld = _rand_sym(n, ref.maskL, 3)
+    _set(sysg, sysg.L, sysg.pL, Ld)
+    mSL = ost.block_mask(*sysg.pSL.host(), ref.nfun)
+    mX = ost.block_mask(*sysg.pX.host(), ref.nfun)
+    # SL = S.L on its natural pattern
+    multiply(1.0, sysg.S, sysg.L, 0, 0.0, sysg.SL)
+    SLr = ref.S @ Ld
+    got = _dense(sysg, sysg.SL, sysg.pSL)
+    assert np.abs(got - SLr * mSL).max() <= 1e-13 * np.abs(SLr).max()
+    assert np.abs(SLr * (1 - mSL)).max() == 0.0      # natural pattern holds the product
+    # X = H.(SL)^T with alpha/beta
+    multiply(1.0, sysg.H, sysg.SL, 1, 0.0, sysg.X)
+    X0 = _dense(sysg, sysg.X, sysg.pX)
+    multiply(0.7, sysg.H, sysg.SL, 1, 0.3, sysg.X)
+    Xr = ref.H @ Ld @ ref.S
+    got = _dense(sysg, sysg.X, sysg.pX)
+    assert np.abs(X0 - Xr * mX).max() <= 1e-13 * np.abs(Xr).max()
+    assert np.abs(got - (0.7 * Xr + 0.3 * Xr) * mX).max() <= 1e-13 * np.abs(Xr).max()
+    # restricted products on L's pattern, with and without transposed B
+    YT = Matrix(sysg.pL)
+    multiply(1.0, sysg.SL, sysg.X, 1, 0.0, YT)
+    SLd = ref.S @ Ld
+    want = (SLd @ Xr.T) * ref.maskL
+    assert np.abs(_dense(sysg, YT, sysg.pL) - want).max() <= 1e-13 * np.abs(want).max()
+    Wm = Matrix(sysg.pL)
+    multiply(1.0, sysg.SL, sysg.X, 0, 0.0, Wm)
+    want = (SLd @ Xr) * ref.maskL
+    assert np.abs(_dense(sysg, Wm, sysg.pL) - want).max() <= 1e-13 * np.abs(want).max()
+    # fused traces: <L, P_L(SL X)>, <W, P_L(SL X)>, product not stored
+    out = multiply_dot(1.0, sysg.SL, sysg.X, 0, 0.0, YT, 0, sysg.L, Wm).cpu().numpy()
+    assert abs(out[0] - np.sum(Ld * want)) <= 1e-12 * abs(np.sum(Ld * want))
+    assert abs(out[1] - np.sum(want * want)) <= 1e-12 * np.sum(want * want)
+    # plain dot over a common pattern and through an index table
+    d = dot(sysg.L, Wm).item()
+    assert abs(d - np.sum(Ld * want)) <= 1e-12 * abs(np.sum(Ld * want))
+    dX = dot(sysg.L, sysg.X).item()
+    assert abs(dX - np.sum(Ld * Xr)) <= 1e-12 * abs(np.sum(Ld * Xr))
+
+
+def test_multiply_ranges_cover_cell_equals_dense(si8):
+    """Check (c): with every range covering the cell the sparse product is
+    the plain dense product."""
+    from paper_2002_07704_amd.system import multiply
+    sysg, ref = si8
+    n = ref.S.shape[0]
+    assert ref.maskL.min() == 1.0
+    Ld = _rand_sym(n, ref.maskL, 4)
+    _set(sysg, sysg.L, sysg.pL, Ld)
+    multiply(1.0, sysg.S, sysg.L, 0, 0.0, sysg.SL)
+    multiply(1.0, sysg.S, sysg.SL, 1, 0.0, sysg.Z)
+    Zr = ref.S @ Ld @ ref.S
+    assert np.abs(_dense(sysg, sysg.Z, sysg.pZ) - Zr).max() <= 1e-13 * np.abs(Zr).max()
+
+
+# ------------------------------------------------------------------ a4
+@pytest.mark.parametrize("fx", ["si64", "si8"])
+def test_eval_matches_oracle(fx, request):
+    sysg, ref = request.getfixturevalue(fx)
+    n = ref.S.shape[0]
+    w = sysg.w
+    for seed in (None, 5):
+        if seed is None:
+            sysg.cg_init()
+            torch.cuda.synchronize()
+            Ld = _dense(sysg, sysg.L, sysg.pL)
+            L0, lam = olnv.initial_L(ref.S, ref.maskL, w.n_elec)
+            assert abs(sysg.scalar("LAMBDA") - lam) <= 1e-12 * lam
+            assert np.abs(Ld - L0).max() <= 1e-12
+        else:
+            Ld = _rand_sym(n, ref.maskL, seed) + 0.2 * np.eye(n) * ref.maskL
+            _set(sysg, sysg.L, sysg.pL, Ld)
+        sysg.eval()
+        torch.cuda.synchronize()
+        E, N = (float(x) for x in sysg.EN.cpu())
+        Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
+        assert abs(E - Er) / w.n <= 1e-10, (E, Er)
+        assert abs(N - Nr) / w.n <= 1e-10, (N, Nr)
+        G = _dense(sysg, sysg.G, sysg.pL)
+        F = _dense(sysg, sysg.F, sysg.pL)
+        assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
+        assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
+
+
+def test_eval_is_bitwise_reproducible(si64):
+    sysg, _ = si64
+    sysg.cg_init()
+    sysg.eval()
+    G1 = sysg.G.val.clone()
+    E1 = sysg.EN.clone()
+    sysg.eval()
+    torch.cuda.synchronize()
+    assert torch.equal(G1, sysg.G.val) and torch.equal(E1, sysg.EN)
+
+
+# ------------------------------------------------------------------ a5-a7
+def test_cg_trajectory_si64_20_steps(si64):
+    """Plain FP64 LNV on the 64-atom cell: 20 CG iterations, every iteration's
+    E, N, mu, beta, alpha and delta against the oracle's."""
+    sysg, ref = si64
+    w = sysg.w
+    _, hist = olnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, 20)
+    sysg.cg_init()
+    for k in range(20):
+        sysg.cg_step()
+        sc = sysg.scalars_host()
+        h = hist[k]
+        print(f"k={k} E/atom gpu {sc['E'] / w.n:.13f} oracle {h['E'] / w.n:.13f} "
+              f"alpha {sc['ALPHA']:.6e} delta {sc['DELTA']:.3e}", flush=True)
+        assert abs(sc["E"] - h["E"]) / w.n <= 1e-10, k
+        assert abs(sc["N"] - h["N"]) <= 1e-9, k
+        assert abs(sc["MU"] - h["mu"]) <= 1e-9 * max(1.0, abs(h["mu"])), k
+        assert abs(sc["BETA"] - h["beta"]) <= 1e-7, k
+        assert abs(sc["ALPHA"] - h["alpha"]) <= 1e-8 * abs(h["alpha"]), k
+        assert abs(sc["DELTA"] - h["delta"]) <= 1e-8 * max(abs(h["delta"]), 1e-6), k
+        assert int(sc["STATUS"]) == 0
+    Lg = _dense(sysg, sysg.L, sysg.pL)
+    Lo, _ = olnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, 20)
+    assert np.abs(Lg - Lo).max() <= 1e-9
