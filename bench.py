@@ -1,0 +1,183 @@
+"""Benchmark of the LNV hot path on one MI355X.
+
+Workload: 4096-atom periodic diamond-Si cell (8x8x8 conventional cubes,
+a = 10.26 bohr, +-0.1 bohr seeded displacements), 4 support functions per
+atom (FP64 4x4 blocks, 16384 orbitals), ranges S/H/L = 12/14/16 bohr,
+products at natural range, N_e = 16384.  One step = one full CG iteration:
+energy + gradient evaluation (six block-sparse products, fused traces),
+gradient projection, Polak-Ribiere direction, exact cubic line minimisation
+(four products) and the cubic electron-number correction (seven products).
+Inputs are resident in HBM before the timed region.
+
+Prints one JSON line; `value` is energy+gradient evaluations per second
+sustained by the CG loop (one evaluation per step).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "LNV energy+grad evals/s & block-sparse GFLOP/s, FP64 vs mixed at 1e-6 Ha/atom"
+PEAK_FP64 = 78.6e12     # MI355X FP64 vector (= FP64 matrix) peak, FLOP/s
+
+
+def cpu_baseline(w, Lb_host, patL, rows=48, budget_s=20.0):
+    """The row-wise oracle, as it stands, on a sample of atom rows of the same
+    workload; scaled to whole evaluations per second."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import rows as orows
+    from oracle import structure as ost
+    pS = ost.neighbours(w.pos, w.box, w.R_S)
+    pH = ost.neighbours(w.pos, w.box, w.R_H)
+    Sb = ost.synth_blocks(w, "S", *pS)
+    Hb = ost.synth_blocks(w, "H", *pH)
+    ro = orows.RowOracle(w, Sb, Hb, Lb_host, pS, pH, patL)
+    sample = np.linspace(0, w.n - 1, rows).astype(int)
+    done = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for i in sample:
+            ro.row(int(i))
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = time.perf_counter() - t0
+    per_row = dt / done
+    return {"value": 1.0 / (per_row * w.n), "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} of {w.n} atom rows of one evaluation (row-wise sparse oracle, "
+                      f"{per_row:.3f} s/row), scaled by {w.n}/{done}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="si4096_4x4")
+    ap.add_argument("--eval-reps", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import lnv_workloads as W
+    from paper_2002_07704_amd import lib as L_
+    from paper_2002_07704_amd.system import LNVSystem
+
+    lib = L_.load()
+    w = W.get(args.workload)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sysg = LNVSystem(w)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    sysg.cg_init()
+    print(f"[bench] setup {setup_s:.2f} s; triples {sysg.triples}", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        sysg.cg_step()
+    torch.cuda.synchronize()
+
+    # timed CG steps (no per-kernel events)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sysg.cg_step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt * 1e3 / args.steps
+    status = int(sysg.scalar("STATUS"))
+
+    # the same steps again with HIP events around every multiply launch
+    lib.lnv_timing_reset()
+    lib.lnv_timing_enable(1)
+    for _ in range(args.steps):
+        sysg.cg_step()
+    torch.cuda.synchronize()
+    lib.lnv_timing_enable(0)
+    import ctypes
+    ms_tot = ctypes.c_double(0.0)
+    launches = ctypes.c_int64(0)
+    L_.check(lib, "lnv_timing_read", lib.lnv_timing_read(ctypes.byref(ms_tot), ctypes.byref(launches)))
+    flops_step = sysg.flops("cg")
+    mul_flops = flops_step * args.steps
+    avg_launch_ms = ms_tot.value / max(1, launches.value)
+    achieved = mul_flops / (ms_tot.value * 1e-3)
+
+    # evaluation alone
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.eval_reps):
+        sysg.eval()
+    torch.cuda.synchronize()
+    ms_eval = (time.perf_counter() - t0) * 1e3 / args.eval_reps
+    flops_eval = sysg.flops("eval")
+
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            with open(args.traffic_json) as f:
+                tj = json.load(f)
+            traffic = tj.get(args.workload)
+        except (OSError, ValueError):
+            traffic = None
+
+    out = {
+        "metric": METRIC,
+        "value": 1e3 / ms_per_step,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{w.name}: {w.n}-atom diamond Si, 4x4 FP64 blocks ({w.n_orb} orbitals), "
+                        f"R_S/R_H/R_L {w.R_S:g}/{w.R_H:g}/{w.R_L:g} bohr, natural-range products",
+            "step": "one CG iteration (eval + projection + cubic line search + N correction)",
+            "atoms": w.n, "n_elec": w.n_elec,
+        },
+        "gflops_per_s": flops_step / (ms_per_step * 1e-3) / 1e9,
+        "gflop_per_step": flops_step / 1e9,
+        "eval_only": {"evals_per_s": 1e3 / ms_eval, "ms": ms_eval, "gflop": flops_eval / 1e9,
+                      "gflops_per_s": flops_eval / (ms_eval * 1e-3) / 1e9},
+        "setup_s": setup_s,
+        "device_status": status,
+        "roofline": {
+            "kernel": "k_mul44 (block SpGEMM, FP64 VALU)",
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_FP64 / 1e12,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64,
+            "traffic": traffic,
+            "avg_launch_ms": avg_launch_ms,
+            "launches": launches.value,
+            "flops_per_launch": mul_flops / max(1, launches.value),
+        },
+    }
+    if not args.no_cpu_baseline:
+        Lb = sysg.L.val.cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(w, Lb, sysg.pL.host())
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

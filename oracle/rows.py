@@ -1,0 +1,79 @@
+"""Row-wise oracle for cells too large for dense matrices -- test infrastructure.
+
+The same quantities as `lnv.evaluate` (Sec. II.C.2: K = 3LSL - 2LSLSL,
+E = 2Tr[KH], N = 2Tr[KS], G = dE/dL, F = dN/dL) for the orbital rows of a few
+sampled atoms i: each product chain is applied to the n_i x N_orb row panel
+of its leftmost factor with scipy sparse matrices, so the cost is a handful of
+panel-times-sparse products per sampled atom.
+
+  G_i = 2 [3 (SLH + HLS) - 2 (SLSLH + SLHLS + HLSLS)]_i  on L's row i
+  F_i = 12 [SLS - SLSLS]_i                                 on L's row i
+  e_i = 2 sum_{a in i} (KH)_aa,   n_i = 2 sum_{a in i} (KS)_aa
+so that sum_i e_i = E and sum_i n_i = N.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import structure as st
+
+
+def bsr(blocks, row_ptr, col, nfun):
+    """scipy CSR orbital matrix from stored blocks (uniform block size)."""
+    b = int(nfun[0])
+    assert np.all(nfun == b)
+    n = len(nfun)
+    M = sp.bsr_matrix((np.ascontiguousarray(blocks[:, :b, :b]), np.asarray(col),
+                       np.asarray(row_ptr)), shape=(n * b, n * b))
+    return M.tocsr()
+
+
+class RowOracle:
+    def __init__(self, w, Sb, Hb, Lb, patS, patH, patL):
+        self.w = w
+        self.nfun = w.nfun
+        self.off = st.offsets(w.nfun)
+        self.S = bsr(Sb, *patS, w.nfun)
+        self.H = bsr(Hb, *patH, w.nfun)
+        self.L = bsr(Lb, *patL, w.nfun)
+        self.patL = patL
+
+    def _panel(self, M, i):
+        a, b = self.off[i], self.off[i + 1]
+        return M[a:b].toarray()
+
+    def row(self, i):
+        """(e_i, n_i, G row blocks [m, b, b], F row blocks, columns of L's row)."""
+        S, H, L = self.S, self.H, self.L
+
+        def chain(P, *mats):
+            for M in mats:
+                P = np.asarray(P @ M)
+            return P
+
+        Si, Hi, Li = self._panel(S, i), self._panel(H, i), self._panel(L, i)
+        SL = chain(Si, L)
+        HL = chain(Hi, L)
+        SLH = chain(SL, H)
+        HLS = chain(HL, S)
+        SLS = chain(SL, S)
+        SLSL = chain(SLS, L)
+        SLSLH = chain(SLSL, H)
+        SLHLS = chain(SLH, L, S)
+        HLSLS = chain(HLS, L, S)
+        SLSLS = chain(SLSL, S)
+        LS = chain(Li, S)
+        LSL = chain(LS, L)
+        LSLSL = chain(LSL, S, L)
+        Ki = 3.0 * LSL - 2.0 * LSLSL
+        Gi = 2.0 * (3.0 * (SLH + HLS) - 2.0 * (SLSLH + SLHLS + HLSLS))
+        Fi = 12.0 * (SLS - SLSLS)
+        e = 2.0 * float(np.sum(Ki * Hi))
+        nn = 2.0 * float(np.sum(Ki * Si))
+        rp, col = self.patL
+        cols = col[rp[i]:rp[i + 1]]
+        b = self.off[i + 1] - self.off[i]
+        Gb = np.stack([Gi[:, self.off[j]:self.off[j + 1]] for j in cols]).reshape(len(cols), b, -1)
+        Fb = np.stack([Fi[:, self.off[j]:self.off[j + 1]] for j in cols]).reshape(len(cols), b, -1)
+        return e, nn, Gb, Fb, cols
