@@ -231,7 +231,7 @@ enum {
   LNV_SC_N_AFTER = 18, LNV_SC_LAMBDA = 19, LNV_SC_STATUS = 20, LNV_SC_LL = 21,
   LNV_SC_GF = 22, LNV_SC_DF = 23, LNV_SC_T0 = 24, LNV_SC_T1 = 25, LNV_SC_T2 = 26,
   LNV_SC_T3 = 27, LNV_SC_T4 = 28, LNV_SC_T5 = 29, LNV_SC_GG_PREV = 30,
-  LNV_SC_GGP = 31,
+  LNV_SC_GGP = 31, LNV_SC_FCFC = 32, LNV_SC_SIGMA = 33, LNV_SC_GGN = 34,
   LNV_NSCALARS = 40
 };
 /* LNV_SC_STATUS bits set by the device (sticky until cleared by the caller). */
@@ -248,16 +248,24 @@ int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
 
 /* ------------------------------------------------------------ a5-a7: CG
  * Buffers of the conjugate-gradient minimisation (all on L's pattern unless
- * stated).  g/g_prev and D/D_prev are swapped by lnv_cg_step after each step.
+ * stated).  gc/gc_prev (metric runs) or g/gc_prev (identity metric) and
+ * D/D_prev are swapped by lnv_cg_step after each step.
+ *  LL  values on pat(L.L) (pattern needs items): T G and T F of the metric
+ *      products.  May share memory with ev.X (dead at that point) when
+ *      pat(L.L) has no more blocks than pat(H.L.S).  Unused without a metric.
  */
 typedef struct lnv_cg_ws {
   lnv_eval_ws ev;
+  lnv_bsm LL;
   double* SL2;     /* second value buffer on pat(S.L) */
   double* Hp;      /* [nnzb_H * 16]: H - mu S */
   double* G;
   double* F;
+  double* Gc;      /* P_L(T G T) (metric runs) */
+  double* Fc;      /* P_L(T F T) (metric runs) */
   double* g;
-  double* g_prev;
+  double* gc;      /* metric runs */
+  double* gc_prev;
   double* D;
   double* D_prev;
 } lnv_cg_ws;
@@ -265,36 +273,51 @@ typedef struct lnv_cg_ws {
 typedef struct lnv_opts {
   int32_t reset_period;  /* search direction reset period (40) */
   double n_tol;          /* relative electron-number tolerance (1e-11) */
-  double step_cap;       /* max |delta| ||F|| / ||L|| of the N correction (0.1) */
+  double step_cap;       /* max |delta| ||F_c|| / ||L|| of the N correction (0.1) */
 } lnv_opts;
 
 /*
- * lnv_cg_init -- L0 = lambda * I on L's pattern, lambda the smallest positive
- * real root of N(lambda I) = n_elec (a cubic: -4 Tr[S^3] l^3 + 6 Tr[S^2] l^2).
- * The paper starts from a generalised McWeeny purification of H; the scaled
- * identity is the start used here.  Writes L and scalars[LNV_SC_LAMBDA].
+ * lnv_hotelling -- sparse approximate inverse of the overlap on T's pattern,
+ * the metric of the minimisation (Sec. II.C.2 uses an approximate sparse
+ * S^-1 from Hotelling's iteration):  T0 = sigma I with
+ * sigma = 1 / max_a sum_b |S_ab| (a Gershgorin bound, so ||I - T0 S|| < 1),
+ * T_{n+1} = P_T(2 T_n - T_n S T_n), n_iter steps.  T's pattern (L's in the
+ * CG) needs lut and items; scratch: ws->ev.SL (pattern pat(S.T) with lut),
+ * ws->Gc, ws->ev.partials, ws->ev.scalars (sigma in LNV_SC_SIGMA).
  */
-int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, double n_elec, lnv_cg_ws* ws, hipStream_t s);
+int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, hipStream_t s);
 
 /*
- * lnv_cg_step -- one conjugate-gradient iteration k (0-based) at the current L:
- *  1. E, N, G, F = eval(L)
- *  2. mu = <G,F>/<F,F>;  g = G - mu F
+ * lnv_cg_init -- L0 = lambda * T on L's pattern (T = NULL: the identity),
+ * lambda the smallest positive real root of N(lambda T) = n_elec, a cubic in
+ * lambda (6 Tr[TSTS] l^2 - 4 Tr[TSTSTS] l^3 = n_elec).  The paper starts
+ * from a generalised McWeeny purification of H; the scaled metric is the
+ * start used here.  Writes L and scalars[LNV_SC_LAMBDA].
+ */
+int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, lnv_cg_ws* ws,
+                hipStream_t s);
+
+/*
+ * lnv_cg_step -- one conjugate-gradient iteration k (0-based) at the current L,
+ * with metric T (NULL: identity; otherwise on L's pattern, e.g. from
+ * lnv_hotelling):
+ *  1. E, N, G, F = eval(L);  G_c = P_L(T G T), F_c = P_L(T F T)
+ *  2. mu = <G,F_c>/<F,F_c>;  g = G - mu F;  g_c = G_c - mu F_c
  *  3. beta = 0 if k % reset_period == 0 or the previous line search failed,
- *     else max(0, <g, g - g_prev> / <g_prev, g_prev>)  (Polak-Ribiere, >= 0)
- *  4. D = -g + beta D_prev;  D <- D - (<D,F>/<F,F>) F
+ *     else max(0, <g, g_c - g_c_prev> / <g_prev, g_c_prev>)  (Polak-Ribiere)
+ *  4. D = -g_c + beta D_prev;  D <- D - (<D,F>/<F,F_c>) F_c
  *  5. alpha = local minimiser of the exact cubic (E - mu N)(L + alpha D)
  *     (none: alpha = 0 and a reset at the next step);  L += alpha D
  *  6. if |N(L) - N_e| > n_tol N_e: delta = smallest-|delta| real root of
- *     N(L + delta F) = N_e, applied when |delta| ||F|| <= step_cap ||L||
+ *     N(L + delta F_c) = N_e, applied when |delta| ||F_c|| <= step_cap ||L||
  * Sec. V.C (density-matrix minimisation of gramicidin A) resets the search
  * direction every 40 iterations; the other choices are readings of the
  * method's electron-number constraint (Sec. II.C.2).  Every decision is
  * taken on the device: the call never synchronises.  Diagnostics are in
  * scalars (E, N at the start of the step, mu, beta, alpha, delta, ...).
  */
-int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double n_elec,
-                int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);
+int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
+                double n_elec, int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);
 
 /* ------------------------------------------------------------ timing
  * Optional HIP-event timing of the block multiply kernel: while enabled,

@@ -219,3 +219,23 @@ def exact_density(H, S, n_elec):
     E = 2.0 * float(np.sum(eps[:nocc]))
     gap = float(eps[nocc] - eps[nocc - 1]) if nocc < len(eps) else float("inf")
     return K, E, gap, eps
+
+
+# ------------------------------------------------------------------ metric
+def gershgorin_scale(S):
+    """sigma = 1 / max_a sum_b |S_ab|: 1/sigma bounds the spectrum of S from
+    above, so T0 = sigma I gives ||I - T0 S|| < 1 for SPD S."""
+    return 1.0 / float(np.max(np.sum(np.abs(S), axis=1)))
+
+
+def hotelling(S, mask, n_iter, sigma=None):
+    """Sparse approximate inverse of S by Hotelling's iteration, truncated to
+    the range pattern `mask` after every step (Sec. II.C.2 uses such an
+    approximate inverse overlap as the metric of the minimisation):
+        T0 = sigma I,   T_{n+1} = P_mask(2 T_n - T_n S T_n)."""
+    if sigma is None:
+        sigma = gershgorin_scale(S)
+    T = sigma * np.eye(S.shape[0]) * mask
+    for _ in range(n_iter):
+        T = (2.0 * T - T @ S @ T) * mask
+    return T

@@ -31,14 +31,16 @@ namespace {
 
 // ------------------------------------------------------------------ reductions
 struct Red {
-  int off, count, stride, dst;
+  int off, count, stride, dst, op;  // op 0: sum, 1: max
 };
 struct RedList {
   Red r[8];
   int nr;
 };
 
-enum Stage { ST_NONE = 0, ST_EVAL, ST_BETA, ST_PROJ, ST_ALPHA, ST_NCHK, ST_DELTA, ST_INIT };
+enum Stage {
+  ST_NONE = 0, ST_EVAL, ST_BETA, ST_PROJ, ST_ALPHA, ST_NCHK, ST_DELTA, ST_INIT, ST_MU, ST_SIGMA
+};
 
 struct StageArgs {
   double n_elec, n_tol, step_cap;
@@ -117,12 +119,26 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
                                                 RedList rl, double* __restrict__ sc,
                                                 int stage, StageArgs sa) {
   __shared__ double sh[16];
+  __shared__ double shm[256];
   for (int q = 0; q < rl.nr; ++q) {
     const Red rd = rl.r[q];
-    double v = 0.0;
-    for (int t = threadIdx.x; t < rd.count; t += 256) v += partials[rd.off + (size_t)t * rd.stride];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) sc[rd.dst] = v;
+    if (rd.op == 0) {
+      double v = 0.0;
+      for (int t = threadIdx.x; t < rd.count; t += 256) v += partials[rd.off + (size_t)t * rd.stride];
+      v = block_sum(v, sh);
+      if (threadIdx.x == 0) sc[rd.dst] = v;
+    } else {
+      double v = -INFINITY;
+      for (int t = threadIdx.x; t < rd.count; t += 256)
+        v = fmax(v, partials[rd.off + (size_t)t * rd.stride]);
+      shm[threadIdx.x] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double m = shm[0];
+        for (int t = 1; t < 256; ++t) m = fmax(m, shm[t]);
+        sc[rd.dst] = m;
+      }
+    }
     __syncthreads();
   }
   if (threadIdx.x != 0 || stage == ST_NONE) return;
@@ -135,6 +151,7 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
       sc[LNV_SC_N] = N;
       const double FF = sc[LNV_SC_FF];
       sc[LNV_SC_MU] = FF != 0.0 ? sc[LNV_SC_GF] / FF : 0.0;
+      sc[LNV_SC_FCFC] = FF;
       if (sa.en_out) {
         sa.en_out[0] = E;
         sa.en_out[1] = N;
@@ -142,15 +159,30 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
       if (!isfinite(E) || !isfinite(N) || !isfinite(sc[LNV_SC_MU])) status |= LNV_ST_NONFINITE;
       break;
     }
+    case ST_MU: {
+      // metric run: mu = <G, F_c> / <F, F_c>
+      const double FF = sc[LNV_SC_FF];
+      sc[LNV_SC_MU] = FF != 0.0 ? sc[LNV_SC_GF] / FF : 0.0;
+      if (!isfinite(sc[LNV_SC_MU])) status |= LNV_ST_NONFINITE;
+      break;
+    }
     case ST_BETA: {
+      // gg = <g, g_c>, ggp = <g, g_c_prev>, gprev = <g_prev, g_c_prev>
       const double gg = sc[LNV_SC_GG], ggp = sc[LNV_SC_GGP], gprev = sc[LNV_SC_GG_PREV];
       double beta = 0.0;
       if (!sa.reset && sc[LNV_SC_FORCE_RESET] == 0.0 && gprev != 0.0)
         beta = fmax(0.0, (gg - ggp) / gprev);
       sc[LNV_SC_BETA] = beta;
       sc[LNV_SC_FORCE_RESET] = 0.0;
-      sc[LNV_SC_GNORM] = sqrt(gg);
+      sc[LNV_SC_GNORM] = sqrt(sc[LNV_SC_GGN]);
       sc[LNV_SC_GG_PREV] = gg;
+      break;
+    }
+    case ST_SIGMA: {
+      // T[LNV_SC_T4] holds max_a sum_b |S_ab|
+      const double m = sc[LNV_SC_T4];
+      sc[LNV_SC_SIGMA] = m > 0.0 ? 1.0 / m : 0.0;
+      if (!(m > 0.0) || !isfinite(m)) status |= LNV_ST_NONFINITE;
       break;
     }
     case ST_PROJ: {
@@ -199,7 +231,7 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
         d = r[0];
         for (int q = 1; q < nr; ++q)
           if (fabs(r[q]) < fabs(d)) d = r[q];
-        if (!(fabs(d) * sqrt(sc[LNV_SC_FF]) <= sa.step_cap * sqrt(sc[LNV_SC_LL]))) {
+        if (!(fabs(d) * sqrt(sc[LNV_SC_FCFC]) <= sa.step_cap * sqrt(sc[LNV_SC_LL]))) {
           d = 0.0;
           status |= LNV_ST_DELTA_CAPPED;
         }
@@ -390,29 +422,102 @@ __global__ __launch_bounds__(256) void k_identity(const int* __restrict__ items,
 // Fixed grid of kVecGrid workgroups, grid-stride over the nv values of L's
 // pattern; partial q of component c goes to partials[c * kVecGrid + q].
 
-// g = G - mu F; partials <g,g>, <g,g_prev>
+// g = G - mu F and (metric runs) g_c = G_c - mu F_c;
+// partials <g, g_c>, <g, g_c_prev>, <g, g>
 __global__ __launch_bounds__(256) void k_vec_g(int64_t nv, const double* __restrict__ G,
                                                const double* __restrict__ F,
-                                               const double* __restrict__ gprev,
+                                               const double* __restrict__ Gc,
+                                               const double* __restrict__ Fc,
+                                               const double* __restrict__ gcprev,
                                                const double* __restrict__ sc,
-                                               double* __restrict__ g,
+                                               double* __restrict__ g, double* __restrict__ gc,
                                                double* __restrict__ partials) {
   __shared__ double sh[16];
   const double mu = sc[LNV_SC_MU];
-  double s0 = 0.0, s1 = 0.0;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
   for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
     const double v = G[q] - mu * F[q];
     g[q] = v;
-    s0 = fma(v, v, s0);
-    s1 = fma(v, gprev[q], s1);
+    double vc = v;
+    if (gc) {
+      vc = Gc[q] - mu * Fc[q];
+      gc[q] = vc;
+    }
+    s0 = fma(v, vc, s0);
+    s1 = fma(v, gcprev[q], s1);
+    s2 = fma(v, v, s2);
   }
   double t = block_sum(s0, sh);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
   t = block_sum(s1, sh);
   if (threadIdx.x == 0) partials[kVecGrid + blockIdx.x] = t;
+  t = block_sum(s2, sh);
+  if (threadIdx.x == 0) partials[2 * kVecGrid + blockIdx.x] = t;
 }
 
-// D = -g + beta D_prev; partial <D, F>
+// metric traces: <F, F_c>, <G, F_c>, <F_c, F_c>
+__global__ __launch_bounds__(256) void k_vec_metric_dots(int64_t nv, const double* __restrict__ G,
+                                                         const double* __restrict__ F,
+                                                         const double* __restrict__ Fc,
+                                                         double* __restrict__ partials) {
+  __shared__ double sh[16];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+    const double fc = Fc[q];
+    s0 = fma(F[q], fc, s0);
+    s1 = fma(G[q], fc, s1);
+    s2 = fma(fc, fc, s2);
+  }
+  double t = block_sum(s0, sh);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+  t = block_sum(s1, sh);
+  if (threadIdx.x == 0) partials[kVecGrid + blockIdx.x] = t;
+  t = block_sum(s2, sh);
+  if (threadIdx.x == 0) partials[2 * kVecGrid + blockIdx.x] = t;
+}
+
+// max over orbital rows a of sum_b |S_ab|: one workgroup per atom row,
+// thread (b, r) adds row r of blocks b, b+64, ...
+__global__ __launch_bounds__(256) void k_rowabs(const int* __restrict__ rp,
+                                                const double* __restrict__ S,
+                                                double* __restrict__ partials) {
+  __shared__ double sh[256];
+  const int i = blockIdx.x;
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  double v = 0.0;
+  for (int p = rp[i] + b; p < rp[i + 1]; p += 64)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) v += fabs(S[(size_t)p * 16 + r * 4 + c]);
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+    for (int q = threadIdx.x; q < 256; q += 4) t += sh[q];
+    sh[threadIdx.x] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) partials[i] = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+// sc[idx] * I on the diagonal blocks of a pattern
+__global__ __launch_bounds__(256) void k_identity_scaled(const int* __restrict__ items,
+                                                         const int* __restrict__ rp,
+                                                         const int* __restrict__ col,
+                                                         const double* __restrict__ sc, int idx,
+                                                         double* __restrict__ D) {
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rp[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  if (b >= cnt) return;
+  const int p = c0 + b;
+  const bool diag = col[p] == i;
+  const double v = sc[idx];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) D[(size_t)p * 16 + r * 4 + c] = (diag && r == c) ? v : 0.0;
+}
+
+// D = -g_c + beta D_prev; partial <D, F>
 __global__ __launch_bounds__(256) void k_vec_dir(int64_t nv, const double* __restrict__ g,
                                                  const double* __restrict__ Dprev,
                                                  const double* __restrict__ F,
@@ -479,8 +584,8 @@ RedList reds() {
   r.nr = 0;
   return r;
 }
-void add(RedList& rl, int64_t off, int count, int stride, int dst) {
-  rl.r[rl.nr++] = Red{(int)off, count, stride, dst};
+void add(RedList& rl, int64_t off, int count, int stride, int dst, int op = 0) {
+  rl.r[rl.nr++] = Red{(int)off, count, stride, dst, op};
 }
 
 bool pattern_ready(const lnv_pattern* p, bool lut, bool lut_t, bool items) {
@@ -634,36 +739,43 @@ extern "C" int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, ln
 
 namespace {
 
-int check_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_cg_ws* ws) {
+int check_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
+             const lnv_cg_ws* ws) {
   if (!ws) return LNV_EINVAL;
   LNV_TRY(check_eval(L, S, H, nullptr, nullptr, &ws->ev));
-  if (!ws->SL2 || !ws->Hp || !ws->G || !ws->F || !ws->g || !ws->g_prev || !ws->D ||
+  if (!ws->SL2 || !ws->Hp || !ws->G || !ws->F || !ws->g || !ws->gc_prev || !ws->D ||
       !ws->D_prev)
     return LNV_EINVAL;
   if (!pattern_ready(S->pat, true, false, false) || !pattern_ready(H->pat, false, false, true))
     return LNV_EPATTERN;
   if (ws->ev.X.pat->nnzb < ws->ev.Z.pat->nnzb) return LNV_EINVAL;  // Z_F reuses X's buffer
+  if (T) {
+    if (!bsm_ok(T) || T->pat != L->pat || T->blk != 4) return LNV_EPATTERN;
+    if (!ws->Gc || !ws->Fc || !ws->gc || !bsm_ok(&ws->LL)) return LNV_EINVAL;
+    if (ws->LL.pat->n != L->pat->n || !pattern_ready(ws->LL.pat, false, false, true))
+      return LNV_EPATTERN;
+  }
   return LNV_OK;
 }
 
 // Traces of the cubic along direction P at the current L, with M the matrix
 // the trace is taken against (H' for the energy line, S for the electron
 // number).  A_P^T = S P (into buf), X_P = M A_P, then
-//   slotT0: <P, X_P>,  slot(1,2): <L, P_L(X_P A_P)>, <P, P_L(X_P A_P)>,
-//   slot3:  <P, P_L(X_P A)>  with A^T = SLcur.
+//   slot 0: <P, X_P>,  slot 1 (pairs): <L, P_L(X_P A_P)>, <P, P_L(X_P A_P)>,
+//   slot 2: <P, P_L(X_P A)>  with A^T = SLcur (skipped when SLcur is null).
 int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const double* P,
                  double* buf, const lnv_pattern* sl_pat, const lnv_bsm* SLcur, lnv_bsm XP,
-                 bool xp_sym,
-                 double* partials, int64_t slot, const double* skip, hipStream_t s) {
+                 bool xp_sym, double* partials, int64_t slot, const double* skip,
+                 hipStream_t s) {
   const lnv_pattern* pl = L->pat;
   lnv_bsm Pm{pl, 4, LNV_F64, const_cast<double*>(P)};
   lnv_bsm APT{sl_pat, 4, LNV_F64, buf};
   LNV_TRY(multiply_launch(1.0, S, &Pm, 0, 0.0, &APT, 1, nullptr, nullptr, nullptr, skip, s));
   LNV_TRY(multiply_launch(1.0, M, &APT, 1, 0.0, &XP, 1, nullptr, nullptr, nullptr, skip, s));
   const int ni = pl->n_items;
+  // one workgroup per item: partial q belongs to item q
   k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, XP.pat->lut,
                                  static_cast<const double*>(XP.val), partials + 0 * slot, skip);
-  // (one workgroup per item: partial q belongs to item q)
   LNV_LAUNCH_CHECK();
   // P_L(X_P A_P) = P_L(A_P^T X_P^T)^T ; its traces with symmetric L and P are
   // those of the transpose.  X_P is symmetric when M = S (then no transpose).
@@ -677,19 +789,70 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const dou
   return LNV_OK;
 }
 
+// out = P_L(T V T) through the natural-range intermediate T V (in ws->LL).
+int metric_apply(const lnv_bsm* T, const double* V, double* out, lnv_cg_ws* ws, hipStream_t s) {
+  const lnv_pattern* pl = T->pat;
+  lnv_bsm Vm{pl, 4, LNV_F64, const_cast<double*>(V)};
+  lnv_bsm Om{pl, 4, LNV_F64, out};
+  LNV_TRY(multiply_launch(1.0, T, &Vm, 0, 0.0, &ws->LL, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, &ws->LL, T, 0, 0.0, &Om, 1, nullptr, nullptr, nullptr, nullptr, s));
+  return LNV_OK;
+}
+
 }  // namespace
 
-extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, double n_elec, lnv_cg_ws* ws,
-                           hipStream_t s) {
+extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws,
+                             hipStream_t s) {
+  if (!bsm_ok(S) || !bsm_ok(T) || !ws || n_iter < 0) return LNV_EINVAL;
+  if (S->blk != 4 || T->blk != 4) return LNV_EUNSUPPORTED;
+  const lnv_eval_ws& ev = ws->ev;
+  if (!ws->Gc || !ev.partials || !ev.scalars || !bsm_ok(&ev.SL)) return LNV_EINVAL;
+  const lnv_pattern* pt = T->pat;
+  if (S->pat->n != pt->n || ev.SL.pat->n != pt->n) return LNV_EPATTERN;
+  if (!pattern_ready(pt, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
+      !pattern_ready(ev.SL.pat, true, false, true))
+    return LNV_EPATTERN;
+  if (ev.partials_len < pt->n) return LNV_EINVAL;
+  double* part = ev.partials;
+  double* sc = ev.scalars;
+  const size_t bytes = sizeof(double) * (size_t)pt->nnzb * 16;
+  k_rowabs<<<S->pat->n, 256, 0, s>>>(S->pat->row_ptr, static_cast<const double*>(S->val), part);
+  LNV_LAUNCH_CHECK();
+  RedList rl = reds();
+  add(rl, 0, S->pat->n, 1, LNV_SC_T4, 1);
+  StageArgs sa{};
+  LNV_TRY(scalar_stage(part, rl, sc, ST_SIGMA, sa, s));
+  k_identity_scaled<<<pt->n_items, 256, 0, s>>>(pt->items, pt->row_ptr, pt->col, sc,
+                                                LNV_SC_SIGMA, static_cast<double*>(T->val));
+  LNV_LAUNCH_CHECK();
+  // T_{n+1} = 2 T_n - T_n (S T_n) on T's pattern; ST lives on pat(S.T)
+  lnv_bsm ST{ev.SL.pat, 4, LNV_F64, ev.SL.val};
+  double* cur = static_cast<double*>(T->val);
+  double* nxt = ws->Gc;
+  for (int it = 0; it < n_iter; ++it) {
+    lnv_bsm Tc{pt, 4, LNV_F64, cur};
+    lnv_bsm Tn{pt, 4, LNV_F64, nxt};
+    LNV_TRY(multiply_launch(1.0, S, &Tc, 0, 0.0, &ST, 1, nullptr, nullptr, nullptr, nullptr, s));
+    LNV_HIP(hipMemcpyAsync(nxt, cur, bytes, hipMemcpyDeviceToDevice, s));
+    LNV_TRY(multiply_launch(-1.0, &Tc, &ST, 0, 2.0, &Tn, 1, nullptr, nullptr, nullptr, nullptr, s));
+    std::swap(cur, nxt);
+  }
+  if (cur != T->val) LNV_HIP(hipMemcpyAsync(T->val, cur, bytes, hipMemcpyDeviceToDevice, s));
+  return LNV_OK;
+}
+
+extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec,
+                           lnv_cg_ws* ws, hipStream_t s) {
   if (!bsm_ok(L) || !bsm_ok(S) || !ws || !(n_elec > 0.0)) return LNV_EINVAL;
   if (L->blk != 4 || S->blk != 4) return LNV_EUNSUPPORTED;
   const lnv_eval_ws& ev = ws->ev;
-  if (!ev.partials || !ev.scalars || !ws->D || !ws->D_prev || !ws->g_prev || !ws->SL2)
+  if (!ev.partials || !ev.scalars || !ws->D || !ws->D_prev || !ws->gc_prev || !ws->SL2)
     return LNV_EINVAL;
   if (!bsm_ok(&ev.SL) || !bsm_ok(&ev.X) || !bsm_ok(&ev.Z)) return LNV_EINVAL;
   if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(ev.SL.pat, false, true, true) ||
       !pattern_ready(ev.Z.pat, true, false, true))
     return LNV_EPATTERN;
+  if (T && (!bsm_ok(T) || T->pat != L->pat || T->blk != 4)) return LNV_EPATTERN;
   if (ev.partials_len < lnv_partials_len(L->pat->n_items)) return LNV_EINVAL;
   const lnv_pattern* pl = L->pat;
   const int64_t nv = pl->nnzb * 16;
@@ -697,14 +860,21 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, double n_elec, lnv_cg_w
   const int64_t slot = slot_len(ni);
   double* part = ev.partials;
   double* sc = ev.scalars;
-  LNV_HIP(hipMemsetAsync(sc, 0, sizeof(double) * LNV_NSCALARS, s));
-  LNV_HIP(hipMemsetAsync(ws->g_prev, 0, sizeof(double) * nv, s));
+  // keep sigma (from lnv_hotelling) across the reset of the scalar block
+  LNV_HIP(hipMemsetAsync(sc, 0, sizeof(double) * LNV_SC_SIGMA, s));
+  LNV_HIP(hipMemsetAsync(sc + LNV_SC_SIGMA + 1, 0,
+                         sizeof(double) * (LNV_NSCALARS - LNV_SC_SIGMA - 1), s));
+  LNV_HIP(hipMemsetAsync(ws->gc_prev, 0, sizeof(double) * nv, s));
   LNV_HIP(hipMemsetAsync(ws->D_prev, 0, sizeof(double) * nv, s));
   LNV_HIP(hipMemsetAsync(L->val, 0, sizeof(double) * nv, s));
-  k_identity<<<ni, 256, 0, s>>>(pl->items, pl->row_ptr, pl->col, ws->D);
-  LNV_LAUNCH_CHECK();
-  // N(lambda I) = 6 Tr[S^2] lambda^2 - 4 Tr[S^3] lambda^3 at L = 0:
-  // A_D^T = S I, Z_D = S A_D = S^2,  <I, Z_D> and <I, P_L(Z_D A_D)>.
+  if (T) {
+    LNV_HIP(hipMemcpyAsync(ws->D, T->val, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+  } else {
+    k_identity<<<ni, 256, 0, s>>>(pl->items, pl->row_ptr, pl->col, ws->D);
+    LNV_LAUNCH_CHECK();
+  }
+  // N(lambda T) = 6 Tr[TSTS] lambda^2 - 4 Tr[TSTSTS] lambda^3 at L = 0:
+  // A_D^T = S T, Z_D = S A_D = S T S,  <T, Z_D> and <T, P_L(Z_D A_D)>.
   lnv_bsm ZD{ev.Z.pat, 4, LNV_F64, ev.Z.val};
   LNV_TRY(cubic_traces(L, S, S, ws->D, ws->SL2, ev.SL.pat, nullptr, ZD, true, part, slot,
                        nullptr, s));
@@ -720,10 +890,11 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, double n_elec, lnv_cg_w
   return LNV_OK;
 }
 
-extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double n_elec,
-                           int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s) {
+extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
+                           double n_elec, int64_t k, const lnv_opts* opts, lnv_cg_ws* ws,
+                           hipStream_t s) {
   if (!opts || opts->reset_period <= 0 || !(n_elec > 0.0) || k < 0) return LNV_EINVAL;
-  LNV_TRY(check_cg(L, S, H, ws));
+  LNV_TRY(check_cg(L, S, H, T, ws));
   const lnv_eval_ws& ev = ws->ev;
   const lnv_pattern* pl = L->pat;
   const lnv_pattern* ph = H->pat;
@@ -733,32 +904,52 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, doubl
   double* part = ev.partials;
   double* sc = ev.scalars;
   double* Lv = static_cast<double*>(L->val);
+  const bool metric = T != nullptr;
   StageArgs sa{};
   sa.n_elec = n_elec;
   sa.n_tol = opts->n_tol;
   sa.step_cap = opts->step_cap;
   sa.reset = (k % opts->reset_period) == 0;
 
-  // 1. E, N, G, F and mu
+  // 1. E, N, G, F; metric gradients G_c, F_c; mu
   LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s));
-  // 2-3. g = G - mu F, Polak-Ribiere beta with resets
-  k_vec_g<<<kVecGrid, 256, 0, s>>>(nv, ws->G, ws->F, ws->g_prev, sc, ws->g, part);
+  const double* Gc = ws->G;
+  const double* Fc = ws->F;
+  double* gcur = ws->g;
+  if (metric) {
+    LNV_TRY(metric_apply(T, ws->G, ws->Gc, ws, s));
+    LNV_TRY(metric_apply(T, ws->F, ws->Fc, ws, s));
+    Gc = ws->Gc;
+    Fc = ws->Fc;
+    gcur = ws->gc;
+    k_vec_metric_dots<<<kVecGrid, 256, 0, s>>>(nv, ws->G, ws->F, ws->Fc, part);
+    LNV_LAUNCH_CHECK();
+    RedList rl = reds();
+    add(rl, 0, kVecGrid, 1, LNV_SC_FF);
+    add(rl, kVecGrid, kVecGrid, 1, LNV_SC_GF);
+    add(rl, 2 * kVecGrid, kVecGrid, 1, LNV_SC_FCFC);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_MU, sa, s));
+  }
+  // 2-3. g = G - mu F, g_c = G_c - mu F_c, Polak-Ribiere beta with resets
+  k_vec_g<<<kVecGrid, 256, 0, s>>>(nv, ws->G, ws->F, Gc, Fc, ws->gc_prev, sc, ws->g,
+                                   metric ? ws->gc : nullptr, part);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
     add(rl, 0, kVecGrid, 1, LNV_SC_GG);
     add(rl, kVecGrid, kVecGrid, 1, LNV_SC_GGP);
+    add(rl, 2 * kVecGrid, kVecGrid, 1, LNV_SC_GGN);
     LNV_TRY(scalar_stage(part, rl, sc, ST_BETA, sa, s));
   }
-  // 4. D = -g + beta D_prev, projected orthogonal to F
-  k_vec_dir<<<kVecGrid, 256, 0, s>>>(nv, ws->g, ws->D_prev, ws->F, sc, ws->D, part);
+  // 4. D = -g_c + beta D_prev, projected: D <- D - (<D,F>/<F,F_c>) F_c
+  k_vec_dir<<<kVecGrid, 256, 0, s>>>(nv, gcur, ws->D_prev, ws->F, sc, ws->D, part);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
     add(rl, 0, kVecGrid, 1, LNV_SC_DF);
     LNV_TRY(scalar_stage(part, rl, sc, ST_PROJ, sa, s));
   }
-  k_vec_proj<<<kVecGrid, 256, 0, s>>>(nv, ws->F, ws->g, sc, ws->D, part);
+  k_vec_proj<<<kVecGrid, 256, 0, s>>>(nv, Fc, ws->g, sc, ws->D, part);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
@@ -784,14 +975,14 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, doubl
   }
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv);
   LNV_LAUNCH_CHECK();
-  // 6. electron number at the new L; cubic correction along F when needed
+  // 6. electron number at the new L; cubic correction along F_c when needed
   lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
   lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(multiply_launch(1.0, S, &SL2, 1, 0.0, &ev.Z, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(multiply_launch(1.0, &SL2, &ev.Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
   k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, ev.Z.pat->lut,
-                                 static_cast<const double*>(ev.Z.val), ev.V, ws->F, part);
+                                 static_cast<const double*>(ev.Z.val), ev.V, Fc, part);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
@@ -802,23 +993,26 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, doubl
     LNV_TRY(scalar_stage(part, rl, sc, ST_NCHK, sa, s));
   }
   const double* skip = sc + LNV_SC_SKIP_NCORR;
+  // the old S.L buffer (ev.SL) is free now: A_F^T = S F_c goes there, and the
+  // products with A_new use S.L_new in SL2; Z_F = S F_c S reuses X's buffer.
   lnv_bsm ZF{ev.Z.pat, 4, LNV_F64, ev.X.val};
-  // the old S.L buffer (ev.SL) is free now: A_F^T = S F goes there, and the
-  // products with A_new use S.L_new in SL2.
+  LNV_TRY(cubic_traces(L, S, S, Fc, static_cast<double*>(ev.SL.val), ev.SL.pat, &SL2, ZF, true,
+                       part, slot, skip, s));
   {
-    LNV_TRY(cubic_traces(L, S, S, ws->F, static_cast<double*>(ev.SL.val), ev.SL.pat, &SL2, ZF,
-                         true, part, slot, skip, s));
     RedList rl = reds();
     add(rl, 0, ni, 1, LNV_SC_T0);
     add(rl, 1 * slot + 0, ni, 2, LNV_SC_T1);
     add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
     add(rl, 2 * slot + 0, ni, 2, LNV_SC_T3);
-    // the reductions read garbage partials when skipped; ST_DELTA ignores them
+    // the reductions read stale partials when skipped; ST_DELTA ignores them
     LNV_TRY(scalar_stage(part, rl, sc, ST_DELTA, sa, s));
   }
-  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->F, sc, LNV_SC_DELTA, skip, Lv);
+  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, Fc, sc, LNV_SC_DELTA, skip, Lv);
   LNV_LAUNCH_CHECK();
-  std::swap(ws->g, ws->g_prev);
+  if (metric)
+    std::swap(ws->gc, ws->gc_prev);
+  else
+    std::swap(ws->g, ws->gc_prev);
   std::swap(ws->D, ws->D_prev);
   return LNV_OK;
 }

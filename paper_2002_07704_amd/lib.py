@@ -21,7 +21,7 @@ NSLOTS = 12
 # device scalar block indices (LNV_SC_*)
 SC = dict(E=0, N=1, MU=2, BETA=3, ALPHA=4, DELTA=5, FF=6, GG=7, C1=8, C2=9, C3=10,
           N0=11, N1=12, N2=13, N3=14, FORCE_RESET=15, SKIP_NCORR=16, GNORM=17,
-          N_AFTER=18, LAMBDA=19, STATUS=20, LL=21, GF=22, DF=23)
+          N_AFTER=18, LAMBDA=19, STATUS=20, LL=21, GF=22, DF=23, FCFC=32, SIGMA=33, GGN=34)
 NSCALARS = 40
 ST_NONFINITE, ST_NO_ALPHA, ST_NO_DELTA, ST_DELTA_CAPPED = 1, 2, 4, 8
 
@@ -44,8 +44,9 @@ class LnvEvalWs(ctypes.Structure):
 
 
 class LnvCgWs(ctypes.Structure):
-    _fields_ = [("ev", LnvEvalWs), ("SL2", c_void_p), ("Hp", c_void_p), ("G", c_void_p),
-                ("F", c_void_p), ("g", c_void_p), ("g_prev", c_void_p), ("D", c_void_p),
+    _fields_ = [("ev", LnvEvalWs), ("LL", LnvBsm), ("SL2", c_void_p), ("Hp", c_void_p),
+                ("G", c_void_p), ("F", c_void_p), ("Gc", c_void_p), ("Fc", c_void_p),
+                ("g", c_void_p), ("gc", c_void_p), ("gc_prev", c_void_p), ("D", c_void_p),
                 ("D_prev", c_void_p)]
 
 
@@ -75,8 +76,9 @@ SIGNATURES = {
     "lnv_bsm_dot": (c_int, [PBsm, PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_partials_len": (c_int64, [c_int32]),
     "lnv_eval": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, c_void_p, POINTER(LnvEvalWs), c_void_p]),
-    "lnv_cg_init": (c_int, [PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
-    "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
+    "lnv_hotelling": (c_int, [PBsm, PBsm, c_int32, POINTER(LnvCgWs), c_void_p]),
+    "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
+    "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
                             POINTER(LnvCgWs), c_void_p]),
     "lnv_timing_enable": (c_int, [c_int32]),
     "lnv_timing_read": (c_int, [POINTER(c_double), POINTER(c_int64)]),

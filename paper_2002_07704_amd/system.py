@@ -176,9 +176,13 @@ class Opts:
 
 
 class LNVSystem:
-    """One geometry on one GPU: patterns, S, H, L and the CG workspace."""
+    """One geometry on one GPU: patterns, S, H, L and the CG workspace.
 
-    def __init__(self, w, device="cuda", R_L=None):
+    metric: "hotelling" builds T ~ S^-1 on L's range (n_hotelling steps) and
+    runs the CG in that metric; None uses the identity.
+    """
+
+    def __init__(self, w, device="cuda", R_L=None, metric="hotelling", n_hotelling=16):
         if not torch.cuda.is_available():
             raise RuntimeError("LNVSystem needs a GPU (HIP device)")
         L_.load()
@@ -218,13 +222,20 @@ class LNVSystem:
         )
         del pLS
         self.pXT = None
+        self.metric = metric
+        if metric is not None:
+            self.pLL = product_pattern(self.pL, self.pL)          # T.G, T.F
+            self.triples["TG"] = self.pLL.triples
+            self.triples["TGT"] = product_pattern(self.pLL, self.pL, mask=self.pL).triples
         # index tables and work lists
         self.pL.build_lut(lut=True).build_items()
         self.pS.build_lut(lut=True)
         self.pH.build_items()
-        self.pSL.build_lut(lut=False, lut_t=True).build_items()
+        self.pSL.build_lut(lut=metric is not None, lut_t=True).build_items()
         self.pX.build_lut(lut=True, lut_t=True).build_items()
         self.pZ.build_lut(lut=True).build_items()
+        if metric is not None:
+            self.pLL.build_items()
         assert self.pX.nnzb >= self.pZ.nnzb
         # buffers
         nL = self.pL.nnzb
@@ -241,7 +252,18 @@ class LNVSystem:
         self.YT, self.W, self.V = lbuf(), lbuf(), lbuf()
         self.SL2 = torch.zeros_like(self.SL.val)
         self.Hp = torch.zeros_like(self.H.val)
-        self.g, self.g_prev, self.D, self.D_prev = lbuf(), lbuf(), lbuf(), lbuf()
+        self.g, self.gc_prev, self.D, self.D_prev = lbuf(), lbuf(), lbuf(), lbuf()
+        self.gc = lbuf() if metric is not None else None
+        self.Gc = Matrix(self.pL) if metric is not None else None
+        self.Fc = Matrix(self.pL) if metric is not None else None
+        self.T = Matrix(self.pL) if metric is not None else None
+        if metric is not None:
+            # T G lives in X's memory when it fits (X is dead at that point)
+            if self.pLL.nnzb <= self.pX.nnzb:
+                llv = self.X.val.view(-1)[:self.pLL.nnzb * BLK * BLK].view(-1, BLK, BLK)
+            else:
+                llv = torch.zeros(self.pLL.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
+            self.LL = Matrix(self.pLL, llv)
         plen = L_.load().lnv_partials_len(self.pL.struct.n_items)
         self.partials = torch.zeros(plen, dtype=torch.float64, device=dev)
         self.scalars = torch.zeros(L_.NSCALARS, dtype=torch.float64, device=dev)
@@ -259,10 +281,17 @@ class LNVSystem:
         self.ws.Hp = self.Hp.data_ptr()
         self.ws.G = self.G.val.data_ptr()
         self.ws.F = self.F.val.data_ptr()
-        self._bufs = {self.g.data_ptr(): self.g, self.g_prev.data_ptr(): self.g_prev,
-                      self.D.data_ptr(): self.D, self.D_prev.data_ptr(): self.D_prev}
-        self.ws.g, self.ws.g_prev = self.g.data_ptr(), self.g_prev.data_ptr()
+        self._bufs = {t.data_ptr(): t for t in (self.g, self.gc_prev, self.D, self.D_prev)}
+        self.ws.g, self.ws.gc_prev = self.g.data_ptr(), self.gc_prev.data_ptr()
         self.ws.D, self.ws.D_prev = self.D.data_ptr(), self.D_prev.data_ptr()
+        if metric is not None:
+            self.ws.LL = self.LL.struct
+            self.ws.Gc = self.Gc.val.data_ptr()
+            self.ws.Fc = self.Fc.val.data_ptr()
+            self.ws.gc = self.gc.data_ptr()
+            self._bufs[self.gc.data_ptr()] = self.gc
+            L_.call("lnv_hotelling", byref(self.S.struct), byref(self.T.struct),
+                    int(n_hotelling), byref(self.ws), _stream())
         self.opts = Opts()
         self.k = 0
         torch.cuda.synchronize()
@@ -278,7 +307,8 @@ class LNVSystem:
             line = t["SL"] + t["X"] + 2 * t["YT"]
             nchk = t["SL"] + t["Z"] + t["V"]
             ncor = t["SL"] + t["Z"] + 2 * t["V"]
-            tot = ev + line + nchk + ncor
+            met = 2 * (t["TG"] + t["TGT"]) if self.metric is not None else 0
+            tot = ev + met + line + nchk + ncor
         return 2 * BLK ** 3 * tot
 
     # ----------------------------------------------------------- hot path
@@ -288,15 +318,18 @@ class LNVSystem:
                 _stream())
         return self.EN
 
+    def _T(self):
+        return byref(self.T.struct) if self.metric is not None else None
+
     def cg_init(self):
-        L_.call("lnv_cg_init", byref(self.L.struct), byref(self.S.struct), self.n_elec,
-                byref(self.ws), _stream())
+        L_.call("lnv_cg_init", byref(self.L.struct), byref(self.S.struct), self._T(),
+                self.n_elec, byref(self.ws), _stream())
         self.k = 0
 
     def cg_step(self):
         o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap)
         L_.call("lnv_cg_step", byref(self.L.struct), byref(self.S.struct), byref(self.H.struct),
-                self.n_elec, self.k, byref(o), byref(self.ws), _stream())
+                self._T(), self.n_elec, self.k, byref(o), byref(self.ws), _stream())
         self.k += 1
 
     def scalar(self, name):

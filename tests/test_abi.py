@@ -59,9 +59,10 @@ def test_host_side_argument_errors(lib):
     assert lib.lnv_bsm_multiply(1.0, ctypes.byref(m), ctypes.byref(mq), 0, 0.0, ctypes.byref(m), None) == L.EPATTERN
     # CG step: bad options are rejected before anything else
     o = L.LnvOpts(0, 1e-11, 0.1)
-    assert lib.lnv_cg_step(None, None, None, 8.0, 0, ctypes.byref(o), None, None) == L.EINVAL
+    assert lib.lnv_cg_step(None, None, None, None, 8.0, 0, ctypes.byref(o), None, None) == L.EINVAL
     o = L.LnvOpts(40, 1e-11, 0.1)
-    assert lib.lnv_cg_step(ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), 8.0, 0, ctypes.byref(o), None, None) == L.EINVAL
+    assert lib.lnv_cg_step(ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), None, 8.0, 0, ctypes.byref(o), None, None) == L.EINVAL
+    assert lib.lnv_hotelling(ctypes.byref(m), ctypes.byref(m), -1, None, None) == L.EINVAL
     assert lib.lnv_partials_len(10) >= 12 * 8 * 1024
 
 

@@ -36,14 +36,30 @@ def _rand_sym(n, mask, seed, scale=0.05):
 def si64(gpu):
     from paper_2002_07704_amd.system import LNVSystem
     w = W.get("si64_4x4")
-    return LNVSystem(w), ost.System(w)
+    return LNVSystem(w, metric=None), ost.System(w)
+
+
+@pytest.fixture(scope="module")
+def si64m(gpu):
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.get("si64_4x4")
+    return LNVSystem(w, metric="hotelling", n_hotelling=16), ost.System(w)
+
+
+@pytest.fixture(scope="module")
+def si216m(gpu):
+    """3x3x3 cubes: rows of L's pattern hold 123 blocks, so every row-parallel
+    kernel runs several 64-block pieces per row."""
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.diamond_workload("si216", (3, 3, 3), seed=7)
+    return LNVSystem(w, metric="hotelling", n_hotelling=16), ost.System(w)
 
 
 @pytest.fixture(scope="module")
 def si8(gpu):
     from paper_2002_07704_amd.system import LNVSystem
     w = W.get("si8_4x4", R_L=1000.0)
-    return LNVSystem(w), ost.System(w)
+    return LNVSystem(w, metric=None), ost.System(w)
 
 
 # ------------------------------------------------------------------ a0
@@ -241,3 +257,44 @@ def test_cg_trajectory_si64_20_steps(si64):
     Lg = _dense(sysg, sysg.L, sysg.pL)
     Lo, _ = olnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, 20)
     assert np.abs(Lg - Lo).max() <= 1e-9
+
+
+# ------------------------------------------------------------------ metric CG
+@pytest.mark.parametrize("fx", ["si64m", "si216m"])
+def test_hotelling_metric_matches_oracle(fx, request):
+    sysg, ref = request.getfixturevalue(fx)
+    T = olnv.hotelling(ref.S, ref.maskL, 16)
+    Tg = _dense(sysg, sysg.T, sysg.pL)
+    assert np.abs(Tg - T).max() <= 1e-13 * np.abs(T).max()
+    assert abs(sysg.scalar("SIGMA") - olnv.gershgorin_scale(ref.S)) <= 1e-15 * olnv.gershgorin_scale(ref.S)
+
+
+@pytest.mark.parametrize("fx,steps", [("si64m", 12), ("si216m", 8)])
+def test_cg_trajectory_hotelling_metric(fx, steps, request):
+    """CG in the Hotelling metric (the paper's approximate S^-1): every
+    iteration's scalars against the oracle's, rows of several 64-block pieces
+    included (si216)."""
+    sysg, ref = request.getfixturevalue(fx)
+    w = sysg.w
+    Tg = _dense(sysg, sysg.T, sysg.pL)       # same T on both sides (pinned above)
+    T = olnv.hotelling(ref.S, ref.maskL, 16)
+    _, hist = olnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, steps, T=T)
+    sysg.cg_init()
+    torch.cuda.synchronize()
+    L0, lam = olnv.initial_L(ref.S, ref.maskL, w.n_elec, T)
+    assert abs(sysg.scalar("LAMBDA") - lam) <= 1e-11 * lam
+    assert np.abs(_dense(sysg, sysg.L, sysg.pL) - L0).max() <= 1e-12
+    for k in range(steps):
+        sysg.cg_step()
+        sc = sysg.scalars_host()
+        h = hist[k]
+        print(f"{fx} k={k} E/atom gpu {sc['E'] / w.n:.13f} oracle {h['E'] / w.n:.13f} "
+              f"alpha {sc['ALPHA']:.6e} delta {sc['DELTA']:.3e}", flush=True)
+        assert abs(sc["E"] - h["E"]) / w.n <= 1e-10, k
+        assert abs(sc["N"] - h["N"]) <= 1e-9 * max(1.0, w.n_elec / 64), k
+        assert abs(sc["MU"] - h["mu"]) <= 1e-9 * max(1.0, abs(h["mu"])), k
+        assert abs(sc["BETA"] - h["beta"]) <= 1e-7, k
+        assert abs(sc["ALPHA"] - h["alpha"]) <= 1e-8 * abs(h["alpha"]), k
+        assert abs(sc["DELTA"] - h["delta"]) <= 1e-8 * max(abs(h["delta"]), 1e-6), k
+        assert int(sc["STATUS"]) == 0
+    del Tg

@@ -270,3 +270,33 @@ def test_check_a_converged_lnv_equals_exact_diagonalisation():
     assert np.abs(Kl - K).max() < 1e-8
     assert abs(2 * lnv.tr_prod(Kl, sy.S) - w.n_elec) <= 1e-9 * w.n_elec
     assert np.abs(Kl @ sy.S @ Kl - Kl).max() < 1e-8
+
+
+# ------------------------------------------------------------------ metric
+def test_hotelling_reaches_inverse_when_range_covers_cell():
+    w = W.get("si8_4x4", R_L=1000.0)
+    sy = st.System(w)
+    T = lnv.hotelling(sy.S, sy.maskL, 16)
+    assert np.abs(T - np.linalg.inv(sy.S)).max() < 1e-12
+
+
+def test_hotelling_truncated_is_symmetric_approximate_inverse():
+    w = W.get("si64_4x4")
+    sy = st.System(w)
+    sig = lnv.gershgorin_scale(sy.S)
+    assert sig <= 1.0 / np.linalg.eigvalsh(sy.S).max()
+    T = lnv.hotelling(sy.S, sy.maskL, 16)
+    assert np.abs(T - T.T).max() < 1e-14
+    assert np.all(T[sy.maskL == 0] == 0)
+    assert np.abs((T @ sy.S - np.eye(len(T))) * sy.maskL).max() < 1e-3
+
+
+def test_cg_with_hotelling_metric_descends_si216():
+    w = W.diamond_workload("si216", (3, 3, 3), seed=7)
+    sy = st.System(w)
+    T = lnv.hotelling(sy.S, sy.maskL, 16)
+    L, hist = lnv.cg(sy.S, sy.H, sy.maskL, w.n_elec, 8, T=T)
+    E = [h["E"] for h in hist]
+    assert all(E[k + 1] < E[k] for k in range(len(E) - 1))
+    assert all(abs(h["N"] - w.n_elec) < 1e-9 for h in hist[1:])
+    assert all(h["alpha"] > 0 for h in hist)
