@@ -138,6 +138,12 @@ int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
 /* lnv_pattern_lut -- fill the index tables of P (either may be NULL). */
 int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t, hipStream_t s);
 
+/* lnv_pattern_transpose_map -- perm[p] = position in PT of the transpose of
+ * block p of P (PT must hold the transposed pattern and have its lut);
+ * LNV_EPATTERN when a block has no transpose in PT. */
+int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT, int32_t* perm,
+                              hipStream_t s);
+
 /* lnv_pattern_items -- work list of P: with items == NULL only counts.
  *  n_items_out  host: number of items (LNV_ECAPACITY if cap is smaller).
  * Synchronises s. */
@@ -181,6 +187,11 @@ int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32
                          double beta, lnv_bsm* C, int32_t store, const lnv_bsm* M1,
                          const lnv_bsm* M2, double* partials, double* out, hipStream_t s);
 
+/* lnv_bsm_transpose -- AT = A^T: block p of A, transposed, goes to position
+ * perm[p] of AT (perm from lnv_pattern_transpose_map).  Needs A.items.
+ * Hot path (HBM-bound copy). */
+int lnv_bsm_transpose(const lnv_bsm* A, const int32_t* perm, lnv_bsm* AT, hipStream_t s);
+
 /* lnv_bsm_dot -- <A, B> = sum over A's blocks of A_ij . B_ij (Frobenius),
  * with B_ij taken at the same position when B shares A's pattern object,
  * otherwise through B.lut (absent blocks count as zero).
@@ -191,17 +202,23 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
                 hipStream_t s);
 
 /* ------------------------------------------------------------ a4: evaluation
- * Intermediates of one evaluation.  With A = LS (stored as its transpose
- * SL), X = HLS and Z = SLS at their natural ranges:
+ * Intermediates of one evaluation.  With A = LS (stored in both orientations,
+ * SL and LS), X = HLS (stored with its transpose XT) and Z = SLS at their
+ * natural ranges:
  *   E = 2 (3 <L, X> - 2 <L, P_L(X A)>)
  *   N = 2 (3 <L, Z> - 2 <L, P_L(A^T Z)>)
  *   G = dE/dL = 2 P_L[3 (X + X^T) - 2 (Y + Y^T + A^T X)],   Y = P_L(X A)
  *   F = dN/dL = 12 P_L[Z - A^T Z]
  * which follow from K = 3LSL - 2LSLSL and E = 2 Tr[KH] (Sec. II.C.2) by
  * differentiating each stored entry of L.
- *  SL  values on pat(S.L)   (pattern needs lut_t and items)
- *  X   values on pat(H.L.S) (pattern needs lut, lut_t and items)
+ *  SL  values on pat(S.L)   (pattern needs items; lut for the metric)
+ *  LS  values on pat(L.S)   (pattern needs lut)
+ *  X   values on pat(H.L.S) (pattern needs lut and items)
+ *  XT  values on pat(S.L.H) (pattern needs lut)
  *  Z   values on pat(S.L.S) (pattern needs lut and items)
+ *  perm_SL, perm_X  transpose maps SL -> LS and X -> XT
+ * Every operand B of the products is read in its stored orientation: a
+ * transposed read would gather 64 blocks from 64 distant rows per step.
  *  YT, W, V  device [nnzb_L * 16]: P_L(SLSLH), P_L(SLHLS), P_L(SLSLS)
  *  partials  device [partials_len] scratch, partials_len >=
  *            lnv_partials_len(n_items of L's pattern)
@@ -209,8 +226,12 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  */
 typedef struct lnv_eval_ws {
   lnv_bsm SL;
+  lnv_bsm LS;
   lnv_bsm X;
+  lnv_bsm XT;
   lnv_bsm Z;
+  const int32_t* perm_SL;
+  const int32_t* perm_X;
   double* YT;
   double* W;
   double* V;
@@ -232,6 +253,7 @@ enum {
   LNV_SC_GF = 22, LNV_SC_DF = 23, LNV_SC_T0 = 24, LNV_SC_T1 = 25, LNV_SC_T2 = 26,
   LNV_SC_T3 = 27, LNV_SC_T4 = 28, LNV_SC_T5 = 29, LNV_SC_GG_PREV = 30,
   LNV_SC_GGP = 31, LNV_SC_FCFC = 32, LNV_SC_SIGMA = 33, LNV_SC_GGN = 34,
+  LNV_SC_NCORR = 35,  /* electron-number corrections computed (never reset by the library) */
   LNV_NSCALARS = 40
 };
 /* LNV_SC_STATUS bits set by the device (sticky until cleared by the caller). */
@@ -251,8 +273,8 @@ int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
  * stated).  gc/gc_prev (metric runs) or g/gc_prev (identity metric) and
  * D/D_prev are swapped by lnv_cg_step after each step.
  *  LL  values on pat(L.L) (pattern needs items): T G and T F of the metric
- *      products.  May share memory with ev.X (dead at that point) when
- *      pat(L.L) has no more blocks than pat(H.L.S).  Unused without a metric.
+ *      products.  May share memory with ev.XT (dead at that point) when
+ *      pat(L.L) has no more blocks than pat(S.L.H).  Unused without a metric.
  */
 typedef struct lnv_cg_ws {
   lnv_eval_ws ev;
@@ -282,8 +304,8 @@ typedef struct lnv_opts {
  * S^-1 from Hotelling's iteration):  T0 = sigma I with
  * sigma = 1 / max_a sum_b |S_ab| (a Gershgorin bound, so ||I - T0 S|| < 1),
  * T_{n+1} = P_T(2 T_n - T_n S T_n), n_iter steps.  T's pattern (L's in the
- * CG) needs lut and items; scratch: ws->ev.SL (pattern pat(S.T) with lut),
- * ws->Gc, ws->ev.partials, ws->ev.scalars (sigma in LNV_SC_SIGMA).
+ * CG) needs lut and items; scratch: ws->ev.SL (pattern pat(S.T) with lut and
+ * items), ws->Gc, ws->ev.partials, ws->ev.scalars (sigma in LNV_SC_SIGMA).
  */
 int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, hipStream_t s);
 

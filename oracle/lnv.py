@@ -110,6 +110,21 @@ def cubic_min(c):
     return best
 
 
+def newton_polish(coef, x, iters=8):
+    """Refine a root of the polynomial coef (highest degree first) with
+    Newton's method; eigenvalues of the companion matrix carry an absolute
+    error of order eps times the largest root, which is large relative to a
+    small root."""
+    p = np.poly1d(coef)
+    dp = p.deriv()
+    for _ in range(iters):
+        d = dp(x)
+        if d == 0.0:
+            break
+        x = x - p(x) / d
+    return float(x)
+
+
 def cubic_smallest_root(c, target):
     """Real root of c0 + c1 d + c2 d^2 + c3 d^3 = target with the smallest |d|."""
     c0, c1, c2, c3 = (float(x) for x in c)
@@ -121,7 +136,7 @@ def cubic_smallest_root(c, target):
     r = [float(np.real(x)) for x in np.roots(coef) if np.isreal(x)]
     if not r:
         return None
-    return min(r, key=abs)
+    return newton_polish(coef, min(r, key=abs))
 
 
 # ------------------------------------------------------------------ initial L
@@ -134,7 +149,7 @@ def initial_L(S, maskL, n_elec, T=None):
     roots = [float(np.real(x)) for x in np.roots(coef) if np.isreal(x) and np.real(x) > 0]
     if not roots:
         raise ValueError("no positive lambda with N(lambda T) = N_e")
-    lam = min(roots)
+    lam = newton_polish(coef, min(roots))
     return lam * Tm, lam
 
 

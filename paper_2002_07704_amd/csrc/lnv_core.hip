@@ -48,11 +48,36 @@ struct StageArgs {
   double* en_out;     // ST_EVAL: optional device [2]
 };
 
+// Newton's method on a3 x^3 + a2 x^2 + a1 x + a0 from x until the step is
+// below 4 ulp of x (at most 100 steps); returns false when it does not settle
+// on a root (residual above 1e-12 of the size of the terms).
+__device__ bool newton_cubic(double a3, double a2, double a1, double a0, double* x) {
+  double v = *x;
+  for (int it = 0; it < 100; ++it) {
+    const double f = ((a3 * v + a2) * v + a1) * v + a0;
+    const double df = (3.0 * a3 * v + 2.0 * a2) * v + a1;
+    if (df == 0.0 || !isfinite(f)) break;
+    const double nv = v - f / df;
+    const bool done = fabs(nv - v) <= 8.9e-16 * fabs(nv);
+    v = nv;
+    if (done) break;
+  }
+  const double f = ((a3 * v + a2) * v + a1) * v + a0;
+  const double scale = fabs(a3 * v * v * v) + fabs(a2 * v * v) + fabs(a1 * v) + fabs(a0);
+  *x = v;
+  return isfinite(v) && fabs(f) <= 1e-12 * scale;
+}
+
 // Real roots of a3 x^3 + a2 x^2 + a1 x + a0 (leading zero coefficients drop
-// the degree).  Cubic: Cardano / Viete trigonometric form on the normalised
-// polynomial, each root polished by two Newton steps.
+// the degree).  Candidates: the closed forms (stable quadratic formula;
+// Cardano / Viete trigonometric form for the cubic) and, for the root nearest
+// zero, Newton's method from the linear estimate -a0/a1.  Every candidate is
+// refined by Newton's method to full precision (the closed forms lose the
+// small roots to cancellation when the others are large) and kept only when
+// it satisfies the polynomial; duplicates are merged.
 __device__ int real_roots(double a3, double a2, double a1, double a0, double* r) {
-  int nr = 0;
+  double cand[4];
+  int nc = 0;
   if (a3 == 0.0) {
     if (a2 == 0.0) {
       if (a1 == 0.0) return 0;
@@ -63,38 +88,39 @@ __device__ int real_roots(double a3, double a2, double a1, double a0, double* r)
     if (disc < 0.0) return 0;
     const double q = -0.5 * (a1 + copysign(sqrt(disc), a1));
     if (q == 0.0) {
-      r[0] = 0.0;
-      return 1;
+      cand[nc++] = 0.0;
+    } else {
+      cand[nc++] = q / a2;
+      cand[nc++] = a0 / q;
     }
-    r[0] = q / a2;
-    r[1] = a0 / q;
-    return 2;
-  }
-  const double B = a2 / a3, C = a1 / a3, D = a0 / a3;
-  const double Q = (B * B - 3.0 * C) / 9.0;
-  const double R = (2.0 * B * B * B - 9.0 * B * C + 27.0 * D) / 54.0;
-  const double Q3 = Q * Q * Q;
-  if (R * R < Q3) {
-    const double th = acos(R / sqrt(Q3));
-    const double s = -2.0 * sqrt(Q);
-    const double pi2 = 6.283185307179586476925286766559;
-    r[0] = s * cos(th / 3.0) - B / 3.0;
-    r[1] = s * cos((th + pi2) / 3.0) - B / 3.0;
-    r[2] = s * cos((th - pi2) / 3.0) - B / 3.0;
-    nr = 3;
   } else {
-    const double Aq = -copysign(cbrt(fabs(R) + sqrt(R * R - Q3)), R);
-    const double Bq = Aq != 0.0 ? Q / Aq : 0.0;
-    r[0] = (Aq + Bq) - B / 3.0;
-    nr = 1;
-  }
-  for (int q = 0; q < nr; ++q)
-    for (int it = 0; it < 2; ++it) {
-      const double x = r[q];
-      const double f = ((a3 * x + a2) * x + a1) * x + a0;
-      const double df = (3.0 * a3 * x + 2.0 * a2) * x + a1;
-      if (df != 0.0) r[q] = x - f / df;
+    const double B = a2 / a3, C = a1 / a3, D = a0 / a3;
+    const double Q = (B * B - 3.0 * C) / 9.0;
+    const double R = (2.0 * B * B * B - 9.0 * B * C + 27.0 * D) / 54.0;
+    const double Q3 = Q * Q * Q;
+    if (R * R < Q3) {
+      const double th = acos(R / sqrt(Q3));
+      const double s = -2.0 * sqrt(Q);
+      const double pi2 = 6.283185307179586476925286766559;
+      cand[nc++] = s * cos(th / 3.0) - B / 3.0;
+      cand[nc++] = s * cos((th + pi2) / 3.0) - B / 3.0;
+      cand[nc++] = s * cos((th - pi2) / 3.0) - B / 3.0;
+    } else {
+      const double Aq = -copysign(cbrt(fabs(R) + sqrt(R * R - Q3)), R);
+      const double Bq = Aq != 0.0 ? Q / Aq : 0.0;
+      cand[nc++] = (Aq + Bq) - B / 3.0;
     }
+  }
+  if (a1 != 0.0) cand[nc++] = -a0 / a1;
+  int nr = 0;
+  for (int q = 0; q < nc; ++q) {
+    double x = cand[q];
+    if (!newton_cubic(a3, a2, a1, a0, &x)) continue;
+    bool dup = false;
+    for (int t = 0; t < nr; ++t)
+      if (fabs(r[t] - x) <= 1e-12 * fmax(fabs(x), 1e-300)) dup = true;
+    if (!dup && nr < 3) r[nr++] = x;
+  }
   return nr;
 }
 
@@ -218,6 +244,7 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
     }
     case ST_DELTA: {
       if (sc[LNV_SC_SKIP_NCORR] != 0.0) break;
+      sc[LNV_SC_NCORR] += 1.0;
       const double n2 = 2.0 * (3.0 * sc[LNV_SC_T0] - 2.0 * (2.0 * sc[LNV_SC_T1] + sc[LNV_SC_T3]));
       const double n3 = -4.0 * sc[LNV_SC_T2];
       sc[LNV_SC_N2] = n2;
@@ -270,7 +297,8 @@ __global__ __launch_bounds__(256) void k_assemble(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
     const int* __restrict__ col, const int* __restrict__ l_lut,
     const double* __restrict__ L, const int* __restrict__ x_lut,
-    const double* __restrict__ X, const double* __restrict__ YT,
+    const double* __restrict__ X, const int* __restrict__ xt_lut,
+    const double* __restrict__ XT, const double* __restrict__ YT,
     const double* __restrict__ Wv, const int* __restrict__ z_lut,
     const double* __restrict__ Z, const double* __restrict__ V, double* __restrict__ G,
     double* __restrict__ F, double* __restrict__ partials) {
@@ -284,14 +312,14 @@ __global__ __launch_bounds__(256) void k_assemble(
     const int p = c0 + b;
     const int j = col[p];
     const int xp = x_lut[(size_t)i * n + j];
-    const int xtp = x_lut[(size_t)j * n + i];
+    const int xtp = xt_lut[(size_t)i * n + j];
     const int ytp = l_lut[(size_t)j * n + i];
     const int zp = z_lut[(size_t)i * n + j];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int e = r * 4 + c, et = c * 4 + r;
       const double x = xp >= 0 ? X[(size_t)xp * 16 + e] : 0.0;
-      const double xt = xtp >= 0 ? X[(size_t)xtp * 16 + et] : 0.0;
+      const double xt = xtp >= 0 ? XT[(size_t)xtp * 16 + e] : 0.0;
       const double yt = YT[(size_t)p * 16 + e];
       const double ytt = ytp >= 0 ? YT[(size_t)ytp * 16 + et] : 0.0;
       const double w = Wv[(size_t)p * 16 + e];
@@ -416,6 +444,28 @@ __global__ __launch_bounds__(256) void k_identity(const int* __restrict__ items,
   const bool diag = col[p] == i;
 #pragma unroll
   for (int c = 0; c < 4; ++c) D[(size_t)p * 16 + r * 4 + c] = (diag && r == c) ? 1.0 : 0.0;
+}
+
+// AT[perm[p]] = A[p]^T for the blocks of item q of A's pattern.
+__global__ __launch_bounds__(256) void k_transpose(const int* __restrict__ items,
+                                                   const int* __restrict__ rp,
+                                                   const int* __restrict__ perm,
+                                                   const double* __restrict__ A,
+                                                   double* __restrict__ AT,
+                                                   const double* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0.0) return;
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rp[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  if (b >= cnt) return;
+  const int p = c0 + b;
+  const size_t q = (size_t)perm[p];
+  const double4 v = reinterpret_cast<const double4*>(A + (size_t)p * 16)[r];
+  AT[q * 16 + 0 * 4 + r] = v.x;
+  AT[q * 16 + 1 * 4 + r] = v.y;
+  AT[q * 16 + 2 * 4 + r] = v.z;
+  AT[q * 16 + 3 * 4 + r] = v.w;
 }
 
 // ------------------------------------------------------------------ vector kernels
@@ -593,24 +643,45 @@ bool pattern_ready(const lnv_pattern* p, bool lut, bool lut_t, bool items) {
          (!items || p->items);
 }
 
+int transpose_skip_launch(const lnv_bsm* A, const int32_t* perm, double* AT,
+                          const double* skip, hipStream_t s) {
+  const lnv_pattern* pa = A->pat;
+  if (pa->n_items == 0) return LNV_OK;
+  k_transpose<<<pa->n_items, 256, 0, s>>>(pa->items, pa->row_ptr, perm,
+                                          static_cast<const double*>(A->val), AT, skip);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+int transpose_launch(const lnv_bsm* A, const int32_t* perm, double* AT, hipStream_t s) {
+  return transpose_skip_launch(A, perm, AT, nullptr, s);
+}
+
 int check_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* G,
                const lnv_bsm* F, const lnv_eval_ws* ws) {
   if (!bsm_ok(L) || !bsm_ok(S) || !bsm_ok(H) || !ws || !ws->YT || !ws->W || !ws->V ||
-      !ws->partials || !ws->scalars)
+      !ws->partials || !ws->scalars || !ws->perm_SL || !ws->perm_X)
     return LNV_EINVAL;
   if ((G && !bsm_ok(G)) || (F && !bsm_ok(F))) return LNV_EINVAL;
-  if (!bsm_ok(&ws->SL) || !bsm_ok(&ws->X) || !bsm_ok(&ws->Z)) return LNV_EINVAL;
+  if (!bsm_ok(&ws->SL) || !bsm_ok(&ws->LS) || !bsm_ok(&ws->X) || !bsm_ok(&ws->XT) ||
+      !bsm_ok(&ws->Z))
+    return LNV_EINVAL;
   if (L->blk != 4 || S->blk != 4 || H->blk != 4) return LNV_EUNSUPPORTED;
   const int n = L->pat->n;
-  if (S->pat->n != n || H->pat->n != n || ws->SL.pat->n != n || ws->X.pat->n != n ||
-      ws->Z.pat->n != n)
+  if (S->pat->n != n || H->pat->n != n || ws->SL.pat->n != n || ws->LS.pat->n != n ||
+      ws->X.pat->n != n || ws->XT.pat->n != n || ws->Z.pat->n != n)
+    return LNV_EPATTERN;
+  if (ws->SL.pat->nnzb != ws->LS.pat->nnzb || ws->X.pat->nnzb != ws->XT.pat->nnzb)
     return LNV_EPATTERN;
   if (G && G->pat != L->pat) return LNV_EPATTERN;
   if (F && F->pat != L->pat) return LNV_EPATTERN;
   if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
       !pattern_ready(H->pat, false, false, false) ||
-      !pattern_ready(ws->SL.pat, false, true, true) ||
-      !pattern_ready(ws->X.pat, true, true, true) || !pattern_ready(ws->Z.pat, true, false, true))
+      !pattern_ready(ws->SL.pat, false, false, true) ||
+      !pattern_ready(ws->LS.pat, true, false, false) ||
+      !pattern_ready(ws->X.pat, true, false, true) ||
+      !pattern_ready(ws->XT.pat, true, false, false) ||
+      !pattern_ready(ws->Z.pat, true, false, true))
     return LNV_EPATTERN;
   if (ws->partials_len < lnv_partials_len(L->pat->n_items)) return LNV_EINVAL;
   return LNV_OK;
@@ -622,16 +693,19 @@ int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, d
   const lnv_pattern* pl = L->pat;
   lnv_bsm YT{pl, 4, LNV_F64, ws->YT}, Wm{pl, 4, LNV_F64, ws->W}, Vm{pl, 4, LNV_F64, ws->V};
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &ws->SL, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, H, &ws->SL, 1, 0.0, &ws->X, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, S, &ws->SL, 1, 0.0, &ws->Z, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->X, 1, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(transpose_launch(&ws->SL, ws->perm_SL, static_cast<double*>(ws->LS.val), s));
+  LNV_TRY(multiply_launch(1.0, H, &ws->LS, 0, 0.0, &ws->X, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, S, &ws->LS, 0, 0.0, &ws->Z, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(transpose_launch(&ws->X, ws->perm_X, static_cast<double*>(ws->XT.val), s));
+  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->XT, 0, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->X, 0, 0.0, &Wm, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
   const int ni = pl->n_items;
   double* part = ws->partials;
   k_assemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, pl->lut,
                                 static_cast<const double*>(L->val), ws->X.pat->lut,
-                                static_cast<const double*>(ws->X.val), ws->YT, ws->W,
+                                static_cast<const double*>(ws->X.val), ws->XT.pat->lut,
+                                static_cast<const double*>(ws->XT.val), ws->YT, ws->W,
                                 ws->Z.pat->lut, static_cast<const double*>(ws->Z.val), ws->V,
                                 G, F, part);
   LNV_LAUNCH_CHECK();
@@ -760,31 +834,39 @@ int check_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm
 
 // Traces of the cubic along direction P at the current L, with M the matrix
 // the trace is taken against (H' for the energy line, S for the electron
-// number).  A_P^T = S P (into buf), X_P = M A_P, then
+// number):  A_P^T = S P (into apt), A_P = its transpose (into ap),
+// X_P = M A_P, then
 //   slot 0: <P, X_P>,  slot 1 (pairs): <L, P_L(X_P A_P)>, <P, P_L(X_P A_P)>,
 //   slot 2: <P, P_L(X_P A)>  with A^T = SLcur (skipped when SLcur is null).
+// P_L(X_P A_P) is formed as P_L(A_P^T X_P^T), the transpose, whose traces
+// with the symmetric L and P are the same; X_P^T is X_P itself when M = S
+// (XPT null), otherwise the transpose copy into XPT.
 int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const double* P,
-                 double* buf, const lnv_pattern* sl_pat, const lnv_bsm* SLcur, lnv_bsm XP,
-                 bool xp_sym, double* partials, int64_t slot, const double* skip,
-                 hipStream_t s) {
+                 const lnv_eval_ws& ev, double* apt, double* ap, const lnv_bsm* SLcur,
+                 lnv_bsm XP, const lnv_bsm* XPT, double* partials, int64_t slot,
+                 const double* skip, hipStream_t s) {
   const lnv_pattern* pl = L->pat;
   lnv_bsm Pm{pl, 4, LNV_F64, const_cast<double*>(P)};
-  lnv_bsm APT{sl_pat, 4, LNV_F64, buf};
+  lnv_bsm APT{ev.SL.pat, 4, LNV_F64, apt};
+  lnv_bsm AP{ev.LS.pat, 4, LNV_F64, ap};
   LNV_TRY(multiply_launch(1.0, S, &Pm, 0, 0.0, &APT, 1, nullptr, nullptr, nullptr, skip, s));
-  LNV_TRY(multiply_launch(1.0, M, &APT, 1, 0.0, &XP, 1, nullptr, nullptr, nullptr, skip, s));
+  LNV_TRY(transpose_skip_launch(&APT, ev.perm_SL, ap, skip, s));
+  LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &XP, 1, nullptr, nullptr, nullptr, skip, s));
+  const lnv_bsm* B = &XP;
+  if (XPT) {
+    LNV_TRY(transpose_skip_launch(&XP, ev.perm_X, static_cast<double*>(XPT->val), skip, s));
+    B = XPT;
+  }
   const int ni = pl->n_items;
   // one workgroup per item: partial q belongs to item q
   k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, XP.pat->lut,
                                  static_cast<const double*>(XP.val), partials + 0 * slot, skip);
   LNV_LAUNCH_CHECK();
-  // P_L(X_P A_P) = P_L(A_P^T X_P^T)^T ; its traces with symmetric L and P are
-  // those of the transpose.  X_P is symmetric when M = S (then no transpose).
-  const int tb = xp_sym ? 0 : 1;
   lnv_bsm scratchC{pl, 4, LNV_F64, const_cast<double*>(P)};  // not written (store = 0)
-  LNV_TRY(multiply_launch(1.0, &APT, &XP, tb, 0.0, &scratchC, 0,
+  LNV_TRY(multiply_launch(1.0, &APT, B, 0, 0.0, &scratchC, 0,
                           static_cast<const double*>(L->val), P, partials + 1 * slot, skip, s));
   if (SLcur)
-    LNV_TRY(multiply_launch(1.0, SLcur, &XP, tb, 0.0, &scratchC, 0, P, nullptr,
+    LNV_TRY(multiply_launch(1.0, SLcur, B, 0, 0.0, &scratchC, 0, P, nullptr,
                             partials + 2 * slot, skip, s));
   return LNV_OK;
 }
@@ -848,9 +930,10 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   const lnv_eval_ws& ev = ws->ev;
   if (!ev.partials || !ev.scalars || !ws->D || !ws->D_prev || !ws->gc_prev || !ws->SL2)
     return LNV_EINVAL;
-  if (!bsm_ok(&ev.SL) || !bsm_ok(&ev.X) || !bsm_ok(&ev.Z)) return LNV_EINVAL;
-  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(ev.SL.pat, false, true, true) ||
-      !pattern_ready(ev.Z.pat, true, false, true))
+  if (!bsm_ok(&ev.SL) || !bsm_ok(&ev.LS) || !bsm_ok(&ev.X) || !bsm_ok(&ev.Z) || !ev.perm_SL)
+    return LNV_EINVAL;
+  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(ev.SL.pat, false, false, true) ||
+      !pattern_ready(ev.LS.pat, true, false, false) || !pattern_ready(ev.Z.pat, true, false, true))
     return LNV_EPATTERN;
   if (T && (!bsm_ok(T) || T->pat != L->pat || T->blk != 4)) return LNV_EPATTERN;
   if (ev.partials_len < lnv_partials_len(L->pat->n_items)) return LNV_EINVAL;
@@ -860,10 +943,11 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   const int64_t slot = slot_len(ni);
   double* part = ev.partials;
   double* sc = ev.scalars;
-  // keep sigma (from lnv_hotelling) across the reset of the scalar block
+  // keep sigma (from lnv_hotelling) and the counters across the reset
   LNV_HIP(hipMemsetAsync(sc, 0, sizeof(double) * LNV_SC_SIGMA, s));
-  LNV_HIP(hipMemsetAsync(sc + LNV_SC_SIGMA + 1, 0,
-                         sizeof(double) * (LNV_NSCALARS - LNV_SC_SIGMA - 1), s));
+  LNV_HIP(hipMemsetAsync(sc + LNV_SC_GGN, 0, sizeof(double), s));
+  LNV_HIP(hipMemsetAsync(sc + LNV_SC_NCORR + 1, 0,
+                         sizeof(double) * (LNV_NSCALARS - LNV_SC_NCORR - 1), s));
   LNV_HIP(hipMemsetAsync(ws->gc_prev, 0, sizeof(double) * nv, s));
   LNV_HIP(hipMemsetAsync(ws->D_prev, 0, sizeof(double) * nv, s));
   LNV_HIP(hipMemsetAsync(L->val, 0, sizeof(double) * nv, s));
@@ -876,8 +960,8 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   // N(lambda T) = 6 Tr[TSTS] lambda^2 - 4 Tr[TSTSTS] lambda^3 at L = 0:
   // A_D^T = S T, Z_D = S A_D = S T S,  <T, Z_D> and <T, P_L(Z_D A_D)>.
   lnv_bsm ZD{ev.Z.pat, 4, LNV_F64, ev.Z.val};
-  LNV_TRY(cubic_traces(L, S, S, ws->D, ws->SL2, ev.SL.pat, nullptr, ZD, true, part, slot,
-                       nullptr, s));
+  LNV_TRY(cubic_traces(L, S, S, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val), nullptr, ZD,
+                       nullptr, part, slot, nullptr, s));
   RedList rl = reds();
   add(rl, 0, ni, 1, LNV_SC_T0);
   add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
@@ -963,8 +1047,9 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   LNV_LAUNCH_CHECK();
   lnv_bsm Hp{ph, 4, LNV_F64, ws->Hp};
   lnv_bsm XD{ev.X.pat, 4, LNV_F64, ev.X.val};
-  LNV_TRY(cubic_traces(L, S, &Hp, ws->D, ws->SL2, ev.SL.pat, &ev.SL, XD, false, part, slot,
-                       nullptr, s));
+  lnv_bsm XDT{ev.XT.pat, 4, LNV_F64, ev.XT.val};
+  LNV_TRY(cubic_traces(L, S, &Hp, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val), &ev.SL,
+                       XD, &XDT, part, slot, nullptr, s));
   {
     RedList rl = reds();
     add(rl, 0, ni, 1, LNV_SC_T0);
@@ -979,7 +1064,8 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
   lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, S, &SL2, 1, 0.0, &ev.Z, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(transpose_launch(&SL2, ev.perm_SL, static_cast<double*>(ev.LS.val), s));
+  LNV_TRY(multiply_launch(1.0, S, &ev.LS, 0, 0.0, &ev.Z, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(multiply_launch(1.0, &SL2, &ev.Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
   k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, ev.Z.pat->lut,
                                  static_cast<const double*>(ev.Z.val), ev.V, Fc, part);
@@ -993,11 +1079,12 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     LNV_TRY(scalar_stage(part, rl, sc, ST_NCHK, sa, s));
   }
   const double* skip = sc + LNV_SC_SKIP_NCORR;
-  // the old S.L buffer (ev.SL) is free now: A_F^T = S F_c goes there, and the
-  // products with A_new use S.L_new in SL2; Z_F = S F_c S reuses X's buffer.
+  // the old S.L buffer (ev.SL) is free now: A_F^T = S F_c goes there (A_F in
+  // ev.LS), the products with A_new use S.L_new in SL2, and Z_F = S F_c S
+  // reuses X's buffer.
   lnv_bsm ZF{ev.Z.pat, 4, LNV_F64, ev.X.val};
-  LNV_TRY(cubic_traces(L, S, S, Fc, static_cast<double*>(ev.SL.val), ev.SL.pat, &SL2, ZF, true,
-                       part, slot, skip, s));
+  LNV_TRY(cubic_traces(L, S, S, Fc, ev, static_cast<double*>(ev.SL.val),
+                       static_cast<double*>(ev.LS.val), &SL2, ZF, nullptr, part, slot, skip, s));
   {
     RedList rl = reds();
     add(rl, 0, ni, 1, LNV_SC_T0);
@@ -1015,4 +1102,14 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     std::swap(ws->g, ws->gc_prev);
   std::swap(ws->D, ws->D_prev);
   return LNV_OK;
+}
+
+extern "C" int lnv_bsm_transpose(const lnv_bsm* A, const int32_t* perm, lnv_bsm* AT,
+                                 hipStream_t s) {
+  if (!bsm_ok(A) || !bsm_ok(AT) || !perm) return LNV_EINVAL;
+  if (A->blk != 4 || AT->blk != 4) return LNV_EUNSUPPORTED;
+  if (A->pat->n != AT->pat->n || A->pat->nnzb != AT->pat->nnzb || !A->pat->items ||
+      !A->pat->row_ptr)
+    return LNV_EPATTERN;
+  return transpose_launch(A, perm, static_cast<double*>(AT->val), s);
 }

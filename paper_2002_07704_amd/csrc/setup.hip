@@ -177,6 +177,20 @@ __global__ __launch_bounds__(256) void k_lut(int n, const int* __restrict__ rp,
   }
 }
 
+// perm[p] = position in PT of the transpose of block p of P; bad[0] set to
+// 1 when a block has no transpose.
+__global__ __launch_bounds__(256) void k_tmap(int n, const int* __restrict__ rp,
+                                              const int* __restrict__ col,
+                                              const int* __restrict__ lut_pt,
+                                              int* __restrict__ perm, int* __restrict__ bad) {
+  const int i = blockIdx.x;
+  for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 256) {
+    const int q = lut_pt[(size_t)col[p] * n + i];
+    perm[p] = q;
+    if (q < 0) bad[0] = 1;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_items(int n, const int* __restrict__ rp,
                                                int* __restrict__ counts,
                                                const int* __restrict__ off,
@@ -414,4 +428,32 @@ extern "C" int lnv_synth_blocks(const double* pos, const double* box, const int3
                             mx, my, mz, seed, scale);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
+}
+
+extern "C" int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT,
+                                         int32_t* perm, hipStream_t s) {
+  if (!P || !PT || !perm) return LNV_EINVAL;
+  if (!P->row_ptr || !P->col || !PT->lut || P->n != PT->n || P->n <= 0 ||
+      P->nnzb != PT->nnzb)
+    return LNV_EPATTERN;
+  int32_t* bad = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int32_t), s));
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+  if (e == hipSuccess) {
+    k_tmap<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, PT->lut, perm, bad);
+    e = hipGetLastError();
+  }
+  int32_t hbad = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  hipError_t ef = hipFreeAsync(bad, s);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return LNV_EHIP;
+  }
+  if (ef != hipSuccess) {
+    set_hip_error(ef);
+    return LNV_EHIP;
+  }
+  return hbad ? LNV_EPATTERN : LNV_OK;
 }

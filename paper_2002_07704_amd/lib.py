@@ -21,7 +21,7 @@ NSLOTS = 12
 # device scalar block indices (LNV_SC_*)
 SC = dict(E=0, N=1, MU=2, BETA=3, ALPHA=4, DELTA=5, FF=6, GG=7, C1=8, C2=9, C3=10,
           N0=11, N1=12, N2=13, N3=14, FORCE_RESET=15, SKIP_NCORR=16, GNORM=17,
-          N_AFTER=18, LAMBDA=19, STATUS=20, LL=21, GF=22, DF=23, FCFC=32, SIGMA=33, GGN=34)
+          N_AFTER=18, LAMBDA=19, STATUS=20, LL=21, GF=22, DF=23, FCFC=32, SIGMA=33, GGN=34, NCORR=35)
 NSCALARS = 40
 ST_NONFINITE, ST_NO_ALPHA, ST_NO_DELTA, ST_DELTA_CAPPED = 1, 2, 4, 8
 
@@ -38,7 +38,8 @@ class LnvBsm(ctypes.Structure):
 
 
 class LnvEvalWs(ctypes.Structure):
-    _fields_ = [("SL", LnvBsm), ("X", LnvBsm), ("Z", LnvBsm), ("YT", c_void_p),
+    _fields_ = [("SL", LnvBsm), ("LS", LnvBsm), ("X", LnvBsm), ("XT", LnvBsm), ("Z", LnvBsm),
+                ("perm_SL", c_void_p), ("perm_X", c_void_p), ("YT", c_void_p),
                 ("W", c_void_p), ("V", c_void_p), ("partials", c_void_p),
                 ("partials_len", c_int64), ("scalars", c_void_p)]
 
@@ -68,6 +69,8 @@ SIGNATURES = {
                                     POINTER(c_int64), c_void_p, POINTER(c_int64), c_void_p]),
     "lnv_pattern_lut": (c_int, [PPat, c_void_p, c_void_p, c_void_p]),
     "lnv_pattern_items": (c_int, [PPat, c_void_p, c_int64, POINTER(c_int32), c_void_p]),
+    "lnv_pattern_transpose_map": (c_int, [PPat, PPat, c_void_p, c_void_p]),
+    "lnv_bsm_transpose": (c_int, [PBsm, c_void_p, PBsm, c_void_p]),
     "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, PBsm, c_int32, c_double,
                                  c_double, c_uint64, c_double, c_void_p]),
     "lnv_bsm_multiply": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_void_p]),

@@ -139,6 +139,18 @@ class Matrix:
         return self
 
 
+def transpose_map(P, PT):
+    """perm[p] = position in PT of the transpose of block p of P."""
+    perm = torch.empty(max(1, P.nnzb), dtype=torch.int32, device=P.row_ptr.device)
+    L_.call("lnv_pattern_transpose_map", byref(P.struct), byref(PT.struct), _ptr(perm), _stream())
+    return perm
+
+
+def transpose(A, perm, AT):
+    L_.call("lnv_bsm_transpose", byref(A.struct), _ptr(perm), byref(AT.struct), _stream())
+    return AT
+
+
 def bsm(pattern, tensor):
     """lnv_bsm view of a raw value tensor on a pattern."""
     return Matrix(pattern, tensor)
@@ -210,9 +222,9 @@ class LNVSystem:
                 float(w.R_H), 2.5, int(w.seed), float(w.scale), _stream())
         # a2: natural product patterns (A = LS is stored as its transpose SL)
         self.pSL = product_pattern(self.pS, self.pL)            # S.L
-        pLS = product_pattern(self.pL, self.pS)                 # L.S (row form of A)
-        self.pX = product_pattern(self.pH, pLS)                 # H.L.S
-        self.pZ = product_pattern(self.pS, pLS)                 # S.L.S
+        self.pLS = product_pattern(self.pL, self.pS, triples=False)   # L.S (row form of A)
+        self.pX = product_pattern(self.pH, self.pLS)            # H.L.S
+        self.pZ = product_pattern(self.pS, self.pLS)            # S.L.S
         self.pXT = product_pattern(self.pSL, self.pH, triples=False)   # S.L.H = pat(X)^T
         self.triples = dict(
             SL=self.pSL.triples, X=self.pX.triples, Z=self.pZ.triples,
@@ -220,8 +232,6 @@ class LNVSystem:
             W=product_pattern(self.pSL, self.pX, mask=self.pL).triples,
             V=product_pattern(self.pSL, self.pZ, mask=self.pL).triples,
         )
-        del pLS
-        self.pXT = None
         self.metric = metric
         if metric is not None:
             self.pLL = product_pattern(self.pL, self.pL)          # T.G, T.F
@@ -231,12 +241,16 @@ class LNVSystem:
         self.pL.build_lut(lut=True).build_items()
         self.pS.build_lut(lut=True)
         self.pH.build_items()
-        self.pSL.build_lut(lut=metric is not None, lut_t=True).build_items()
-        self.pX.build_lut(lut=True, lut_t=True).build_items()
+        self.pSL.build_lut(lut=metric is not None).build_items()
+        self.pLS.build_lut(lut=True)
+        self.pX.build_lut(lut=True).build_items()
+        self.pXT.build_lut(lut=True)
         self.pZ.build_lut(lut=True).build_items()
         if metric is not None:
             self.pLL.build_items()
         assert self.pX.nnzb >= self.pZ.nnzb
+        self.perm_SL = transpose_map(self.pSL, self.pLS)
+        self.perm_X = transpose_map(self.pX, self.pXT)
         # buffers
         nL = self.pL.nnzb
 
@@ -247,7 +261,9 @@ class LNVSystem:
         self.G = Matrix(self.pL)
         self.F = Matrix(self.pL)
         self.SL = Matrix(self.pSL)
+        self.LS = Matrix(self.pLS)
         self.X = Matrix(self.pX)
+        self.XT = Matrix(self.pXT)
         self.Z = Matrix(self.pZ)
         self.YT, self.W, self.V = lbuf(), lbuf(), lbuf()
         self.SL2 = torch.zeros_like(self.SL.val)
@@ -258,9 +274,9 @@ class LNVSystem:
         self.Fc = Matrix(self.pL) if metric is not None else None
         self.T = Matrix(self.pL) if metric is not None else None
         if metric is not None:
-            # T G lives in X's memory when it fits (X is dead at that point)
-            if self.pLL.nnzb <= self.pX.nnzb:
-                llv = self.X.val.view(-1)[:self.pLL.nnzb * BLK * BLK].view(-1, BLK, BLK)
+            # T G lives in XT's memory when it fits (XT is dead at that point)
+            if self.pLL.nnzb <= self.pXT.nnzb:
+                llv = self.XT.val.view(-1)[:self.pLL.nnzb * BLK * BLK].view(-1, BLK, BLK)
             else:
                 llv = torch.zeros(self.pLL.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
             self.LL = Matrix(self.pLL, llv)
@@ -271,8 +287,12 @@ class LNVSystem:
         self.ws = L_.LnvCgWs()
         ev = self.ws.ev
         ev.SL = self.SL.struct
+        ev.LS = self.LS.struct
         ev.X = self.X.struct
+        ev.XT = self.XT.struct
         ev.Z = self.Z.struct
+        ev.perm_SL = self.perm_SL.data_ptr()
+        ev.perm_X = self.perm_X.data_ptr()
         ev.YT, ev.W, ev.V = self.YT.data_ptr(), self.W.data_ptr(), self.V.data_ptr()
         ev.partials = self.partials.data_ptr()
         ev.partials_len = plen
@@ -298,17 +318,18 @@ class LNVSystem:
 
     # ----------------------------------------------------------- flop accounting
     def flops(self, what="eval"):
-        """Algorithmic flops (2 n^3 per block triple) of one eval or CG step."""
+        """Algorithmic flops (2 n^3 per block triple, true block sizes) of one
+        piece of work: "eval", "init" (L0), "step_base" (a CG step without the
+        electron-number correction), "ncorr" (that correction), "step" (both)."""
         t = self.triples
         ev = t["SL"] + t["X"] + t["Z"] + t["YT"] + t["W"] + t["V"]
-        if what == "eval":
-            tot = ev
-        else:
-            line = t["SL"] + t["X"] + 2 * t["YT"]
-            nchk = t["SL"] + t["Z"] + t["V"]
-            ncor = t["SL"] + t["Z"] + 2 * t["V"]
-            met = 2 * (t["TG"] + t["TGT"]) if self.metric is not None else 0
-            tot = ev + met + line + nchk + ncor
+        line = t["SL"] + t["X"] + 2 * t["YT"]
+        nchk = t["SL"] + t["Z"] + t["V"]
+        ncor = t["SL"] + t["Z"] + 2 * t["V"]
+        met = 2 * (t["TG"] + t["TGT"]) if self.metric is not None else 0
+        tot = {"eval": ev, "init": t["SL"] + t["Z"] + t["V"],
+               "step_base": ev + met + line + nchk, "ncorr": ncor,
+               "step": ev + met + line + nchk + ncor}[what]
         return 2 * BLK ** 3 * tot
 
     # ----------------------------------------------------------- hot path

@@ -149,9 +149,16 @@ def test_multiply_against_dense_masked_products(si64):
     got = _dense(sysg, sysg.SL, sysg.pSL)
     assert np.abs(got - SLr * mSL).max() <= 1e-13 * np.abs(SLr).max()
     assert np.abs(SLr * (1 - mSL)).max() == 0.0      # natural pattern holds the product
-    # X = H.(SL)^T with alpha/beta
-    multiply(1.0, sysg.H, sysg.SL, 1, 0.0, sysg.X)
+    # block transpose SL -> LS through the transpose map
+    from paper_2002_07704_amd.system import transpose
+    transpose(sysg.SL, sysg.perm_SL, sysg.LS)
+    LSd = _dense(sysg, sysg.LS, sysg.pLS)
+    assert np.array_equal(LSd, got.T)
+    # X = H.LS in stored orientation, and H.(SL)^T through a transposed read
+    # (the transposed index table is built on demand) with alpha/beta
+    multiply(1.0, sysg.H, sysg.LS, 0, 0.0, sysg.X)
     X0 = _dense(sysg, sysg.X, sysg.pX)
+    sysg.pSL.build_lut(lut=sysg.pSL.lut is not None, lut_t=True)
     multiply(0.7, sysg.H, sysg.SL, 1, 0.3, sysg.X)
     Xr = ref.H @ Ld @ ref.S
     got = _dense(sysg, sysg.X, sysg.pX)
@@ -159,7 +166,12 @@ def test_multiply_against_dense_masked_products(si64):
     assert np.abs(got - (0.7 * Xr + 0.3 * Xr) * mX).max() <= 1e-13 * np.abs(Xr).max()
     # restricted products on L's pattern, with and without transposed B
     YT = Matrix(sysg.pL)
+    sysg.pX.build_lut(lut=True, lut_t=True)
     multiply(1.0, sysg.SL, sysg.X, 1, 0.0, YT)
+    YT2 = Matrix(sysg.pL)
+    transpose(sysg.X, sysg.perm_X, sysg.XT)
+    multiply(1.0, sysg.SL, sysg.XT, 0, 0.0, YT2)
+    assert np.abs(_dense(sysg, YT2, sysg.pL) - _dense(sysg, YT, sysg.pL)).max() <= 1e-13 * np.abs(Xr).max()
     SLd = ref.S @ Ld
     want = (SLd @ Xr.T) * ref.maskL
     assert np.abs(_dense(sysg, YT, sysg.pL) - want).max() <= 1e-13 * np.abs(want).max()
@@ -187,8 +199,10 @@ def test_multiply_ranges_cover_cell_equals_dense(si8):
     assert ref.maskL.min() == 1.0
     Ld = _rand_sym(n, ref.maskL, 4)
     _set(sysg, sysg.L, sysg.pL, Ld)
+    from paper_2002_07704_amd.system import transpose
     multiply(1.0, sysg.S, sysg.L, 0, 0.0, sysg.SL)
-    multiply(1.0, sysg.S, sysg.SL, 1, 0.0, sysg.Z)
+    transpose(sysg.SL, sysg.perm_SL, sysg.LS)
+    multiply(1.0, sysg.S, sysg.LS, 0, 0.0, sysg.Z)
     Zr = ref.S @ Ld @ ref.S
     assert np.abs(_dense(sysg, sysg.Z, sysg.pZ) - Zr).max() <= 1e-13 * np.abs(Zr).max()
 
