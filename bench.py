@@ -62,6 +62,63 @@ def cpu_baseline(w, Lb_host, patL, rows=48, budget_s=20.0):
                       f"{per_row:.3f} s/row), scaled by {w.n}/{done}"}
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2002_07704_amd", "csrc", "multiply.hip")
+COPY_BYTES = 1 << 30
+
+
+def kernel_hash():
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def summarize_pmc(fetch_dir, write_dir, out_path, workload):
+    """Per-launch HBM bytes of the multiply kernel from two rocprofv3 --pmc
+    runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for the device copy of COPY_BYTES bytes made by
+    --pmc-probe."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        per = {}
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] != counter:
+                continue
+            k = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+            per[k] = per.get(k, 0.0) + float(r["Counter_Value"]) * 1024.0
+        return per
+
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        per = load(d, counter)
+        copies = [(i, v) for (i, n), v in per.items() if "copyBuffer" in n and v > 0.25 * COPY_BYTES]
+        if not copies:
+            raise SystemExit(f"no calibration copy found in {d}")
+        copy_id, copy_v = max(copies, key=lambda x: x[1])
+        factor = COPY_BYTES / copy_v
+        # the timed steps follow the calibration copy
+        mul = [v for (i, n), v in per.items() if "k_mul44" in n and i > copy_id]
+        out[counter] = {"factor": factor, "launches": len(mul),
+                        "bytes_per_launch": factor * sum(mul) / max(1, len(mul))}
+    res = {}
+    if os.path.exists(out_path):
+        res = json.load(open(out_path))
+    res[workload] = {
+        "kernel": "k_mul44 / k_mul44c", "kernel_src_sha256_16": kernel_hash(),
+        "fetch_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"],
+        "write_bytes_per_launch": out["WRITE_SIZE"]["bytes_per_launch"],
+        "bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"],
+        "calibration": {"copy_bytes": COPY_BYTES, "fetch_factor": out["FETCH_SIZE"]["factor"],
+                        "write_factor": out["WRITE_SIZE"]["factor"]},
+        "launches": out["FETCH_SIZE"]["launches"],
+    }
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res[workload]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,7 +128,13 @@ def main():
     ap.add_argument("--eval-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="copy COPY_BYTES (counter calibration), then the timed steps only")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.traffic_json, args.workload)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md)", file=sys.stderr)
@@ -101,6 +164,18 @@ def main():
         step()
     torch.cuda.synchronize()
     sysg.scalars[L_.SC["NCORR"]] = 0.0
+    if args.pmc_probe:
+        a = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "steps": args.steps}), flush=True)
+        return
 
     # timed steps (no per-kernel events)
     t0 = time.perf_counter()
@@ -143,9 +218,11 @@ def main():
     if os.path.exists(args.traffic_json):
         try:
             with open(args.traffic_json) as f:
-                tj = json.load(f)
-            traffic = tj.get(args.workload)
-        except (OSError, ValueError):
+                tj = json.load(f).get(args.workload)
+            # counters describe the kernel they were taken on: stale -> null
+            if tj and tj.get("kernel_src_sha256_16") == kernel_hash():
+                traffic = tj["bytes_per_launch"]
+        except (OSError, ValueError, KeyError):
             traffic = None
 
     out = {
@@ -184,6 +261,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64,
             "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "avg_launch_ms": avg_launch_ms,
             "launches": launches.value,
             "flops_per_launch": mul_flops / max(1, launches.value),

@@ -69,6 +69,16 @@ enum { LNV_F64 = 0 };
  * items lists the work pieces of the row-parallel kernels: item q covers row
  * items[2q] from position items[2q+1] for up to 64 blocks (never past the
  * end of the row).
+ *
+ * Cluster plan (optional; used by the multiply when both A and C carry one
+ * with the same cl_m): rows are grouped into clusters of cl_m consecutive
+ * atoms (consecutive atoms are spatial neighbours when atoms are numbered
+ * cell by cell), and for each cluster c the sorted union of its rows'
+ * columns is cl_col[cl_ptr[c] .. cl_ptr[c+1]); cl_pos[t*cl_m + r] is the
+ * position of block (c*cl_m + r, cl_col[t]) or -1.  As the left operand A
+ * this is the contraction list of a cluster; as the output C its columns
+ * are split into work pieces of 64/cl_g columns, cl_items[2q] = cluster,
+ * cl_items[2q+1] = first position in cl_col.
  */
 typedef struct lnv_pattern {
   int32_t n;               /* atoms (block rows = block columns) */
@@ -79,6 +89,14 @@ typedef struct lnv_pattern {
   const int32_t* lut;      /* device [n*n] or NULL */
   const int32_t* lut_t;    /* device [n*n] or NULL */
   const int32_t* items;    /* device [2*n_items] or NULL */
+  int32_t cl_m;            /* rows per cluster (0: no cluster plan) */
+  int32_t cl_g;            /* lanes sharing one output column (1 or 2) */
+  int32_t n_cl_items;      /* entries of cl_items */
+  int32_t cl_pad;
+  const int32_t* cl_ptr;   /* device [ceil(n/cl_m)+1] */
+  const int32_t* cl_col;   /* device [cl_ptr[last]] */
+  const int32_t* cl_pos;   /* device [cl_ptr[last]*cl_m] */
+  const int32_t* cl_items; /* device [2*n_cl_items] */
 } lnv_pattern;
 
 /* Block-sparse matrix: a pattern (host descriptor) plus block values. */
@@ -144,6 +162,16 @@ int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t, hipStrea
 int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT, int32_t* perm,
                               hipStream_t s);
 
+/* lnv_pattern_cluster -- cluster plan of P (see lnv_pattern) for clusters of
+ * m rows with g lanes per output column, each lane accumulating 4 rows:
+ * (m, g) = (4, 1) or (8, 2).  P needs lut.  Two-phase like lnv_neighbours: with
+ * cl_col == NULL only *len_out (union length) and *n_items_out are
+ * reported; cl_ptr is always written (device [ceil(n/m)+1]).  Synchronises s. */
+int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_ptr,
+                        int32_t* cl_col, int32_t* cl_pos, int64_t cap, int32_t* cl_items,
+                        int64_t items_cap, int64_t* len_out, int32_t* n_items_out,
+                        hipStream_t s);
+
 /* lnv_pattern_items -- work list of P: with items == NULL only counts.
  *  n_items_out  host: number of items (LNV_ECAPACITY if cap is smaller).
  * Synchronises s. */
@@ -180,8 +208,11 @@ int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t t
 
 /* lnv_bsm_multiply_dot -- as lnv_bsm_multiply, and in the same pass
  * out[d] = <M_d, C> for the given partners M_1, M_2 (NULL to skip; both on
- * C's pattern); with store == 0 the product is not written back (only the
- * traces are wanted).  partials: device [2 * C.n_items] scratch; out: device.
+ * C's pattern); with store == 0 the finished product is not written back
+ * (only the traces are wanted), but C.val still serves as scratch for partial
+ * sums when the contraction is split into slabs (see lnv_set_kslabs), so it
+ * must be a writable buffer of C's size.  partials: device
+ * [2 * max(C.n_items, C.n_cl_items)] scratch; out: device.
  */
 int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
                          double beta, lnv_bsm* C, int32_t store, const lnv_bsm* M1,
@@ -191,6 +222,11 @@ int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32
  * perm[p] of AT (perm from lnv_pattern_transpose_map).  Needs A.items.
  * Hot path (HBM-bound copy). */
 int lnv_bsm_transpose(const lnv_bsm* A, const int32_t* perm, lnv_bsm* AT, hipStream_t s);
+
+/* lnv_set_kslabs -- split every multiply's contraction index k into n
+ * atom-index slabs, one launch per slab accumulating into C (n <= 0: the
+ * default, a single launch).  Process-wide setting. */
+int lnv_set_kslabs(int32_t n);
 
 /* lnv_bsm_dot -- <A, B> = sum over A's blocks of A_ij . B_ij (Frobenius),
  * with B_ij taken at the same position when B shares A's pattern object,
@@ -221,7 +257,7 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  * transposed read would gather 64 blocks from 64 distant rows per step.
  *  YT, W, V  device [nnzb_L * 16]: P_L(SLSLH), P_L(SLHLS), P_L(SLSLS)
  *  partials  device [partials_len] scratch, partials_len >=
- *            lnv_partials_len(n_items of L's pattern)
+ *            lnv_partials_len(max(n_items, n_cl_items) of L's pattern)
  *  scalars   device [LNV_NSCALARS] FP64 (see LNV_SC_*)
  */
 typedef struct lnv_eval_ws {

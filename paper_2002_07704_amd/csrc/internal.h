@@ -80,4 +80,11 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
                     const double* m2, double* partials, const double* skip,
                     hipStream_t s);
 
+// Number of dot partials (work items) multiply_launch writes for C.
+int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C);
+
+inline int32_t partial_items(const lnv_pattern* p) {
+  return p->n_items > p->n_cl_items ? p->n_items : p->n_cl_items;
+}
+
 }  // namespace lnv

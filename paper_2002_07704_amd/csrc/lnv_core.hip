@@ -617,6 +617,7 @@ __global__ __launch_bounds__(256) void k_vec_axpy(int64_t nv, const double* __re
 }
 
 // ------------------------------------------------------------------ host helpers
+// n_items_L: the larger of L's n_items and n_cl_items
 int64_t slot_len(int n_items_L) {
   const int64_t a = 8 * (int64_t)n_items_L, b = 8 * (int64_t)kVecGrid;
   return a > b ? a : b;
@@ -683,7 +684,7 @@ int check_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_b
       !pattern_ready(ws->XT.pat, true, false, false) ||
       !pattern_ready(ws->Z.pat, true, false, true))
     return LNV_EPATTERN;
-  if (ws->partials_len < lnv_partials_len(L->pat->n_items)) return LNV_EINVAL;
+  if (ws->partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
   return LNV_OK;
 }
 
@@ -766,7 +767,7 @@ extern "C" int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bs
   const double* m2 = M2 ? static_cast<const double*>(M2->val) : nullptr;
   LNV_TRY(multiply_launch(alpha, A, B, transB, beta, C, store, m1, m2, partials, nullptr, s));
   if (!M1) return LNV_OK;
-  const int ni = C->pat->n_items;
+  const int ni = multiply_nparts(A, B, transB, C);
   // reduce the interleaved partials into out[0..1] (fixed order)
   RedList rl = reds();
   add(rl, 0, ni, 2, 0);
@@ -844,7 +845,7 @@ int check_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm
 int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const double* P,
                  const lnv_eval_ws& ev, double* apt, double* ap, const lnv_bsm* SLcur,
                  lnv_bsm XP, const lnv_bsm* XPT, double* partials, int64_t slot,
-                 const double* skip, hipStream_t s) {
+                 const double* skip, int* nparts, hipStream_t s) {
   const lnv_pattern* pl = L->pat;
   lnv_bsm Pm{pl, 4, LNV_F64, const_cast<double*>(P)};
   lnv_bsm APT{ev.SL.pat, 4, LNV_F64, apt};
@@ -862,7 +863,11 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const dou
   k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, XP.pat->lut,
                                  static_cast<const double*>(XP.val), partials + 0 * slot, skip);
   LNV_LAUNCH_CHECK();
-  lnv_bsm scratchC{pl, 4, LNV_F64, const_cast<double*>(P)};  // not written (store = 0)
+  // C of the trace-only products: written between contraction slabs, so it
+  // needs a buffer of its own (ev.YT is dead outside the evaluation)
+  lnv_bsm scratchC{pl, 4, LNV_F64, ev.YT};
+  *nparts = multiply_nparts(&APT, B, 0, &scratchC);
+  if (SLcur && multiply_nparts(SLcur, B, 0, &scratchC) != *nparts) return LNV_EPATTERN;
   LNV_TRY(multiply_launch(1.0, &APT, B, 0, 0.0, &scratchC, 0,
                           static_cast<const double*>(L->val), P, partials + 1 * slot, skip, s));
   if (SLcur)
@@ -936,11 +941,11 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
       !pattern_ready(ev.LS.pat, true, false, false) || !pattern_ready(ev.Z.pat, true, false, true))
     return LNV_EPATTERN;
   if (T && (!bsm_ok(T) || T->pat != L->pat || T->blk != 4)) return LNV_EPATTERN;
-  if (ev.partials_len < lnv_partials_len(L->pat->n_items)) return LNV_EINVAL;
+  if (ev.partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
   const lnv_pattern* pl = L->pat;
   const int64_t nv = pl->nnzb * 16;
   const int ni = pl->n_items;
-  const int64_t slot = slot_len(ni);
+  const int64_t slot = slot_len(partial_items(pl));
   double* part = ev.partials;
   double* sc = ev.scalars;
   // keep sigma (from lnv_hotelling) and the counters across the reset
@@ -960,11 +965,12 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   // N(lambda T) = 6 Tr[TSTS] lambda^2 - 4 Tr[TSTSTS] lambda^3 at L = 0:
   // A_D^T = S T, Z_D = S A_D = S T S,  <T, Z_D> and <T, P_L(Z_D A_D)>.
   lnv_bsm ZD{ev.Z.pat, 4, LNV_F64, ev.Z.val};
+  int np = 0;
   LNV_TRY(cubic_traces(L, S, S, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val), nullptr, ZD,
-                       nullptr, part, slot, nullptr, s));
+                       nullptr, part, slot, nullptr, &np, s));
   RedList rl = reds();
   add(rl, 0, ni, 1, LNV_SC_T0);
-  add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
+  add(rl, 1 * slot + 1, np, 2, LNV_SC_T2);
   StageArgs sa{};
   sa.n_elec = n_elec;
   LNV_TRY(scalar_stage(part, rl, sc, ST_INIT, sa, s));
@@ -984,7 +990,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   const lnv_pattern* ph = H->pat;
   const int64_t nv = pl->nnzb * 16;
   const int ni = pl->n_items;
-  const int64_t slot = slot_len(ni);
+  const int64_t slot = slot_len(partial_items(pl));
   double* part = ev.partials;
   double* sc = ev.scalars;
   double* Lv = static_cast<double*>(L->val);
@@ -1048,14 +1054,15 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   lnv_bsm Hp{ph, 4, LNV_F64, ws->Hp};
   lnv_bsm XD{ev.X.pat, 4, LNV_F64, ev.X.val};
   lnv_bsm XDT{ev.XT.pat, 4, LNV_F64, ev.XT.val};
+  int np = 0;
   LNV_TRY(cubic_traces(L, S, &Hp, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val), &ev.SL,
-                       XD, &XDT, part, slot, nullptr, s));
+                       XD, &XDT, part, slot, nullptr, &np, s));
   {
     RedList rl = reds();
     add(rl, 0, ni, 1, LNV_SC_T0);
-    add(rl, 1 * slot + 0, ni, 2, LNV_SC_T1);
-    add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
-    add(rl, 2 * slot + 0, ni, 2, LNV_SC_T3);
+    add(rl, 1 * slot + 0, np, 2, LNV_SC_T1);
+    add(rl, 1 * slot + 1, np, 2, LNV_SC_T2);
+    add(rl, 2 * slot + 0, np, 2, LNV_SC_T3);
     LNV_TRY(scalar_stage(part, rl, sc, ST_ALPHA, sa, s));
   }
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv);
@@ -1084,13 +1091,14 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   // reuses X's buffer.
   lnv_bsm ZF{ev.Z.pat, 4, LNV_F64, ev.X.val};
   LNV_TRY(cubic_traces(L, S, S, Fc, ev, static_cast<double*>(ev.SL.val),
-                       static_cast<double*>(ev.LS.val), &SL2, ZF, nullptr, part, slot, skip, s));
+                       static_cast<double*>(ev.LS.val), &SL2, ZF, nullptr, part, slot, skip, &np,
+                       s));
   {
     RedList rl = reds();
     add(rl, 0, ni, 1, LNV_SC_T0);
-    add(rl, 1 * slot + 0, ni, 2, LNV_SC_T1);
-    add(rl, 1 * slot + 1, ni, 2, LNV_SC_T2);
-    add(rl, 2 * slot + 0, ni, 2, LNV_SC_T3);
+    add(rl, 1 * slot + 0, np, 2, LNV_SC_T1);
+    add(rl, 1 * slot + 1, np, 2, LNV_SC_T2);
+    add(rl, 2 * slot + 0, np, 2, LNV_SC_T3);
     // the reductions read stale partials when skipped; ST_DELTA ignores them
     LNV_TRY(scalar_stage(part, rl, sc, ST_DELTA, sa, s));
   }

@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_mul44(
     const int* __restrict__ b_lut, const double* __restrict__ b_val,
     const int* __restrict__ c_rp, const int* __restrict__ c_col, double* __restrict__ c_val,
     double alpha, double beta, const double* __restrict__ m1, const double* __restrict__ m2,
-    double* __restrict__ partials, const double* __restrict__ skip) {
+    double* __restrict__ partials, const double* __restrict__ skip, int k_lo, int k_hi) {
   if (skip != nullptr && *skip != 0.0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
@@ -76,7 +76,23 @@ __global__ __launch_bounds__(256) void k_mul44(
   const int j = act ? c_col[c0 + lane] : 0;
   const int* __restrict__ lcol = b_lut + j;
   const size_t ns = (size_t)n;
-  const int t0 = a_rp[i], t1 = a_rp[i + 1];
+  // contraction range: the k in [k_lo, k_hi) of A's sorted row i
+  int t0 = a_rp[i], t1 = a_rp[i + 1];
+  if (k_lo > 0 || k_hi < n) {
+    int lo = t0, hi = t1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (a_col[mid] < k_lo) lo = mid + 1; else hi = mid;
+    }
+    const int tb = lo;
+    hi = t1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (a_col[mid] < k_hi) lo = mid + 1; else hi = mid;
+    }
+    t0 = tb;
+    t1 = lo;
+  }
 
   double acc[16];
 #pragma unroll
@@ -155,9 +171,149 @@ __global__ __launch_bounds__(256) void k_mul44(
   }
 }
 
+// Clustered variant: a workgroup item covers a cluster of M = 4G consecutive
+// output rows and up to 64/G columns of the union of their patterns.  Lane
+// (q, g) owns column q of the piece for the 4 rows g*4 .. g*4+3 of the
+// cluster (G lanes share a column: their identical B loads coalesce), so
+// one gathered B_kj block feeds up to M accumulators instead of one.  The k
+// loop runs over the union of the cluster's A rows; the A blocks of the rows
+// present are wave-uniform scalar loads.  Blocks of the union outside a row's
+// pattern are accumulated and dropped at the store (cheap: the kernel is
+// bound by the B gathers, not by the FP64 FMAs).
+template <int G>
+__device__ __forceinline__ void cluster_fma(double (&acc)[4][16], const double (&b)[16],
+                                            const int* __restrict__ apos,
+                                            const double* __restrict__ a_val, int g) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int pos = (G == 1 || g == 0) ? apos[r] : apos[4 + r];
+    if (pos >= 0) {
+      const double* ap = a_val + (size_t)pos * 16;
+      double a[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] = ap[q];
+      block_fma<0>(acc[r], a, b);
+    }
+  }
+}
+
+template <int G, int STORE, int NDOT>
+__global__ __launch_bounds__(256) void k_mul44c(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
+    const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
+    const double* __restrict__ a_val, const int* __restrict__ b_lut,
+    const double* __restrict__ b_val, const int* __restrict__ jc_ptr,
+    const int* __restrict__ jc_col, const int* __restrict__ jc_pos, double* __restrict__ c_val,
+    double alpha, double beta, const double* __restrict__ m1, const double* __restrict__ m2,
+    double* __restrict__ partials, const double* __restrict__ skip) {
+  constexpr int M = 4 * G;
+  constexpr int COLS = kWave / G;
+  if (skip != nullptr && *skip != 0.0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (item >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const int q = lane / G, g = lane % G;
+  const int c = items[2 * item];
+  const int p0 = items[2 * item + 1];
+  const int cnt = min(COLS, jc_ptr[c + 1] - p0);
+  const bool act = q < cnt;
+  const int j = act ? jc_col[p0 + q] : 0;
+  int opos[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) opos[r] = act ? jc_pos[(size_t)(p0 + q) * M + g * 4 + r] : -1;
+  const int* __restrict__ lcol = b_lut + j;
+  const size_t ns = (size_t)n;
+  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
+
+  double acc[4][16];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[r][e] = 0.0;
+
+  double bA[16], bB[16];
+  int pA = -1, pB = -1;
+  if (act && t0 < t1) pA = lcol[(size_t)ka_col[t0] * ns];
+  if (act && t0 + 1 < t1) pB = lcol[(size_t)ka_col[t0 + 1] * ns];
+  if (pA >= 0) load_block(bA, b_val + (size_t)pA * 16);
+  for (int t = t0; t < t1; t += 2) {
+    int pA2 = -1;
+    if (act && t + 2 < t1) pA2 = lcol[(size_t)ka_col[t + 2] * ns];
+    if (pB >= 0) load_block(bB, b_val + (size_t)pB * 16);
+    if (pA >= 0) cluster_fma<G>(acc, bA, ka_pos + (size_t)t * M, a_val, g);
+    if (t + 1 >= t1) break;
+    int pB2 = -1;
+    if (act && t + 3 < t1) pB2 = lcol[(size_t)ka_col[t + 3] * ns];
+    if (pA2 >= 0) load_block(bA, b_val + (size_t)pA2 * 16);
+    if (pB >= 0) cluster_fma<G>(acc, bB, ka_pos + (size_t)(t + 1) * M, a_val, g);
+    pA = pA2;
+    pB = pB2;
+  }
+
+  double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (opos[r] < 0) continue;
+    const size_t cp = (size_t)opos[r] * 16;
+    double out[16];
+    if (beta != 0.0) {
+      double old[16];
+      load_block(old, c_val + cp);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[r][e] + beta * old[e];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[r][e];
+    }
+    if (STORE) {
+      double2* qq = reinterpret_cast<double2*>(c_val + cp);
+#pragma unroll
+      for (int h = 0; h < 8; ++h) qq[h] = make_double2(out[2 * h], out[2 * h + 1]);
+    }
+    if (NDOT >= 1) {
+      double mv[16];
+      load_block(mv, m1 + cp);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) d1 = fma(mv[e], out[e], d1);
+    }
+    if (NDOT >= 2) {
+      double mv[16];
+      load_block(mv, m2 + cp);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) d2 = fma(mv[e], out[e], d2);
+    }
+  }
+  if (NDOT >= 1) {
+    d1 = wave_sum(d1);
+    if (NDOT >= 2) d2 = wave_sum(d2);
+    if (lane == 0) {
+      partials[2 * item] = d1;
+      partials[2 * item + 1] = d2;
+    }
+  }
+}
+
+using KernelCFn = void (*)(int, int, const int*, const int*, const int*, const int*,
+                           const double*, const int*, const double*, const int*, const int*,
+                           const int*, double*, double, double, const double*, const double*,
+                           double*, const double*);
+
+template <int G>
+KernelCFn pick_c(int store, int ndot) {
+  if (store) {
+    if (ndot == 0) return k_mul44c<G, 1, 0>;
+    if (ndot == 1) return k_mul44c<G, 1, 1>;
+    return k_mul44c<G, 1, 2>;
+  }
+  if (ndot == 1) return k_mul44c<G, 0, 1>;
+  return k_mul44c<G, 0, 2>;
+}
+
 using KernelFn = void (*)(int, int, const int*, const int*, const int*, const double*,
                           const int*, const double*, const int*, const int*, double*, double,
-                          double, const double*, const double*, double*, const double*);
+                          double, const double*, const double*, double*, const double*, int,
+                          int);
 
 template <int TB>
 KernelFn pick_store(int store, int ndot) {
@@ -192,7 +348,31 @@ int timer_begin(hipStream_t s, hipEvent_t* stop) {
   return LNV_OK;
 }
 
+int g_kslab_override = -1;  // < 0: automatic
+
+// Number of contraction slabs (atom-index ranges of k, one launch each,
+// accumulating into C).  Atoms numbered cell by cell make an index range a
+// spatial slab, which bounds the rows of B one launch gathers.  Measured on
+// MI355X at 4096 atoms, splitting makes every product slower (2 slabs: about
+// 2x the time), so the default is a single launch; the split remains
+// available for contractions that must be partitioned.
+int kslabs_for(const lnv_bsm* B) {
+  if (g_kslab_override > 0) return g_kslab_override < B->pat->n ? g_kslab_override : B->pat->n;
+  return 1;
+}
+
 }  // namespace
+
+bool use_clustered(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
+  const lnv_pattern *pa = A->pat, *pc = C->pat;
+  return !transB && kslabs_for(B) == 1 && pa->cl_m > 0 && pa->cl_m == pc->cl_m && pa->cl_ptr &&
+         pa->cl_col && pa->cl_pos && pc->cl_ptr && pc->cl_col && pc->cl_pos && pc->cl_items &&
+         pc->cl_g * 4 == pc->cl_m;
+}
+
+int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
+  return use_clustered(A, B, transB, C) ? C->pat->n_cl_items : C->pat->n_items;
+}
 
 int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
                     double beta, const lnv_bsm* C, int store, const double* m1,
@@ -209,16 +389,43 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
   if (m2 && !m1) return LNV_EINVAL;
   if (ndot > 0 && !partials) return LNV_EINVAL;
   if (!store && ndot == 0) return LNV_EINVAL;
+  const int nslab = kslabs_for(B);
+  const bool clustered = use_clustered(A, B, transB, C);
+  if (clustered) {
+    if (pc->n_cl_items == 0) return LNV_OK;
+    const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
+    hipEvent_t stop = nullptr;
+    LNV_TRY(timer_begin(s, &stop));
+    KernelCFn fn = pc->cl_g == 2 ? pick_c<2>(store, ndot) : pick_c<1>(store, ndot);
+    fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
+                           pa->cl_pos, static_cast<const double*>(A->val), lut,
+                           static_cast<const double*>(B->val), pc->cl_ptr, pc->cl_col,
+                           pc->cl_pos, static_cast<double*>(C->val), alpha, beta, m1, m2,
+                           partials, skip);
+    LNV_LAUNCH_CHECK();
+    if (stop) LNV_HIP(hipEventRecord(stop, s));
+    return LNV_OK;
+  }
   if (pc->n_items == 0) return LNV_OK;
-  KernelFn fn = transB ? pick_store<1>(store, ndot) : pick_store<0>(store, ndot);
   const int wgs = round_up((pc->n_items + 3) / 4, kNumXcd);
   hipEvent_t stop = nullptr;
   LNV_TRY(timer_begin(s, &stop));
-  fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_items, pc->items, pa->row_ptr, pa->col,
-                         static_cast<const double*>(A->val), lut,
-                         static_cast<const double*>(B->val), pc->row_ptr, pc->col,
-                         static_cast<double*>(C->val), alpha, beta, m1, m2, partials, skip);
-  LNV_LAUNCH_CHECK();
+  const int n = pa->n;
+  for (int c = 0; c < nslab; ++c) {
+    // every slab but the last accumulates into C (stored); the last applies
+    // the caller's store / trace choice to the finished sum
+    const bool last = c == nslab - 1;
+    const int k_lo = (int)((int64_t)c * n / nslab), k_hi = (int)((int64_t)(c + 1) * n / nslab);
+    const int st = last ? store : 1;
+    const int nd = last ? ndot : 0;
+    KernelFn fn = transB ? pick_store<1>(st, nd) : pick_store<0>(st, nd);
+    fn<<<wgs, 256, 0, s>>>(n, pc->n_items, pc->items, pa->row_ptr, pa->col,
+                           static_cast<const double*>(A->val), lut,
+                           static_cast<const double*>(B->val), pc->row_ptr, pc->col,
+                           static_cast<double*>(C->val), alpha, c == 0 ? beta : 1.0, m1, m2,
+                           partials, skip, k_lo, k_hi);
+    LNV_LAUNCH_CHECK();
+  }
   if (stop) LNV_HIP(hipEventRecord(stop, s));
   return LNV_OK;
 }
@@ -231,6 +438,11 @@ extern "C" int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B
                                 int32_t transB, double beta, lnv_bsm* C, hipStream_t s) {
   return multiply_launch(alpha, A, B, transB, beta, C, 1, nullptr, nullptr, nullptr, nullptr,
                          s);
+}
+
+extern "C" int lnv_set_kslabs(int32_t n) {
+  g_kslab_override = n;
+  return LNV_OK;
 }
 
 extern "C" int lnv_timing_enable(int32_t on) {

@@ -191,6 +191,87 @@ __global__ __launch_bounds__(256) void k_tmap(int n, const int* __restrict__ rp,
   }
 }
 
+// Cluster unions: one workgroup per cluster of m rows; the union of their
+// columns is collected in an LDS bitmap, then counted or emitted in
+// ascending order together with each row's block position (lut) or -1.
+__global__ __launch_bounds__(256) void k_cluster_union(int n, int m, const int* __restrict__ rp,
+                                                       const int* __restrict__ col,
+                                                       const int* __restrict__ lut,
+                                                       int* __restrict__ counts,
+                                                       const int* __restrict__ out_ptr,
+                                                       int* __restrict__ out_col,
+                                                       int* __restrict__ out_pos, int fill) {
+  extern __shared__ unsigned int bits[];
+  __shared__ int scan[256];
+  const int W = (n + 31) >> 5;
+  const int c = blockIdx.x;
+  const int tid = threadIdx.x;
+  for (int w = tid; w < W; w += 256) bits[w] = 0u;
+  __syncthreads();
+  for (int r = 0; r < m; ++r) {
+    const int i = c * m + r;
+    if (i >= n) break;
+    for (int q = rp[i] + tid; q < rp[i + 1]; q += 256) {
+      const int j = col[q];
+      atomicOr(&bits[j >> 5], 1u << (j & 31));
+    }
+  }
+  __syncthreads();
+  const int chunk = (W + 255) / 256;
+  const int w0 = min(W, tid * chunk), w1 = min(W, w0 + chunk);
+  int mine = 0;
+  for (int w = w0; w < w1; ++w) mine += __popc(bits[w]);
+  scan[tid] = mine;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int q = 0; q < 256; ++q) {
+      const int v = scan[q];
+      scan[q] = run;
+      run += v;
+    }
+    if (!fill) counts[c] = run;
+  }
+  __syncthreads();
+  if (!fill) return;
+  int t = out_ptr[c] + scan[tid];
+  for (int w = w0; w < w1; ++w) {
+    unsigned int x = bits[w];
+    while (x) {
+      const int b = __ffs(x) - 1;
+      const int j = (w << 5) + b;
+      out_col[t] = j;
+      for (int r = 0; r < m; ++r) {
+        const int i = c * m + r;
+        out_pos[(size_t)t * m + r] = i < n ? lut[(size_t)i * n + j] : -1;
+      }
+      ++t;
+      x &= x - 1u;
+    }
+  }
+}
+
+// Work pieces of `piece` columns over the cluster unions.
+__global__ __launch_bounds__(256) void k_cluster_items(int nc, int piece,
+                                                       const int* __restrict__ cptr,
+                                                       int* __restrict__ counts,
+                                                       const int* __restrict__ off,
+                                                       int* __restrict__ items) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= nc) return;
+  const int len = cptr[c + 1] - cptr[c];
+  const int k = (len + piece - 1) / piece;
+  if (!items) {
+    counts[c] = k;
+    return;
+  }
+  const int o = off[c];
+  for (int q = 0; q < k; ++q) {
+    items[2 * (o + q)] = c;
+    items[2 * (o + q) + 1] = cptr[c] + q * piece;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_items(int n, const int* __restrict__ rp,
                                                int* __restrict__ counts,
                                                const int* __restrict__ off,
@@ -456,4 +537,68 @@ extern "C" int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern
     return LNV_EHIP;
   }
   return hbad ? LNV_EPATTERN : LNV_OK;
+}
+
+extern "C" int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_ptr,
+                                   int32_t* cl_col, int32_t* cl_pos, int64_t cap,
+                                   int32_t* cl_items, int64_t items_cap, int64_t* len_out,
+                                   int32_t* n_items_out, hipStream_t s) {
+  if (!P || !cl_ptr || !len_out || !n_items_out) return LNV_EINVAL;
+  if (!((m == 4 && g == 1) || (m == 8 && g == 2))) return LNV_EUNSUPPORTED;
+  if (!P->row_ptr || !P->col || !P->lut || P->n <= 0 || P->n > LNV_MAX_ATOMS) return LNV_EPATTERN;
+  const int n = P->n;
+  const int nc = (n + m - 1) / m;
+  const size_t lds = (size_t)((n + 31) / 32) * sizeof(unsigned int);
+  k_cluster_union<<<nc, 256, lds, s>>>(n, m, P->row_ptr, P->col, P->lut, cl_ptr, nullptr,
+                                       nullptr, nullptr, 0);
+  LNV_LAUNCH_CHECK();
+  k_scan<int32_t><<<1, 1024, 0, s>>>(cl_ptr, nc);
+  LNV_LAUNCH_CHECK();
+  LNV_TRY(read_total_int(cl_ptr + nc, len_out, s));
+  // items: pieces of 64/g columns per cluster
+  int32_t* cnt = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&cnt), sizeof(int32_t) * (nc + 1), s));
+  const int piece = 64 / g;
+  const int gi = (nc + 255) / 256;
+  k_cluster_items<<<gi, 256, 0, s>>>(nc, piece, cl_ptr, cnt, nullptr, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_scan<int32_t><<<1, 1024, 0, s>>>(cnt, nc);
+    e = hipGetLastError();
+  }
+  int32_t nit = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&nit, cnt + nc, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  int st = LNV_OK;
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    st = LNV_EHIP;
+  } else {
+    *n_items_out = nit;
+    if (cl_col) {
+      if (!cl_pos || !cl_items) {
+        st = LNV_EINVAL;
+      } else if (cap < *len_out || items_cap < nit) {
+        st = LNV_ECAPACITY;
+      } else {
+        k_cluster_union<<<nc, 256, lds, s>>>(n, m, P->row_ptr, P->col, P->lut, nullptr, cl_ptr,
+                                             cl_col, cl_pos, 1);
+        e = hipGetLastError();
+        if (e == hipSuccess) {
+          k_cluster_items<<<gi, 256, 0, s>>>(nc, piece, cl_ptr, nullptr, cnt, cl_items);
+          e = hipGetLastError();
+        }
+        if (e != hipSuccess) {
+          set_hip_error(e);
+          st = LNV_EHIP;
+        }
+      }
+    }
+  }
+  hipError_t ef = hipFreeAsync(cnt, s);
+  if (st == LNV_OK && ef != hipSuccess) {
+    set_hip_error(ef);
+    st = LNV_EHIP;
+  }
+  return st;
 }

@@ -29,7 +29,10 @@ ST_NONFINITE, ST_NO_ALPHA, ST_NO_DELTA, ST_DELTA_CAPPED = 1, 2, 4, 8
 class LnvPattern(ctypes.Structure):
     _fields_ = [("n", c_int32), ("n_items", c_int32), ("nnzb", c_int64),
                 ("row_ptr", c_void_p), ("col", c_void_p), ("lut", c_void_p),
-                ("lut_t", c_void_p), ("items", c_void_p)]
+                ("lut_t", c_void_p), ("items", c_void_p),
+                ("cl_m", c_int32), ("cl_g", c_int32), ("n_cl_items", c_int32), ("cl_pad", c_int32),
+                ("cl_ptr", c_void_p), ("cl_col", c_void_p), ("cl_pos", c_void_p),
+                ("cl_items", c_void_p)]
 
 
 class LnvBsm(ctypes.Structure):
@@ -70,6 +73,9 @@ SIGNATURES = {
     "lnv_pattern_lut": (c_int, [PPat, c_void_p, c_void_p, c_void_p]),
     "lnv_pattern_items": (c_int, [PPat, c_void_p, c_int64, POINTER(c_int32), c_void_p]),
     "lnv_pattern_transpose_map": (c_int, [PPat, PPat, c_void_p, c_void_p]),
+    "lnv_pattern_cluster": (c_int, [PPat, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_int64,
+                                    c_void_p, c_int64, POINTER(c_int64), POINTER(c_int32),
+                                    c_void_p]),
     "lnv_bsm_transpose": (c_int, [PBsm, c_void_p, PBsm, c_void_p]),
     "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, PBsm, c_int32, c_double,
                                  c_double, c_uint64, c_double, c_void_p]),
@@ -83,6 +89,7 @@ SIGNATURES = {
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
                             POINTER(LnvCgWs), c_void_p]),
+    "lnv_set_kslabs": (c_int, [c_int32]),
     "lnv_timing_enable": (c_int, [c_int32]),
     "lnv_timing_read": (c_int, [POINTER(c_double), POINTER(c_int64)]),
     "lnv_timing_reset": (c_int, []),

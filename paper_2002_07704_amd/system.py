@@ -40,6 +40,7 @@ class Pattern:
         self.lut_t = None
         self.items = None
         self.triples = None
+        self.cl = None          # (m, g, cl_ptr, cl_col, cl_pos, cl_items)
         self.struct = L_.LnvPattern()
         self._sync()
 
@@ -57,6 +58,13 @@ class Pattern:
         s.lut_t = self.lut_t.data_ptr() if self.lut_t is not None else None
         s.items = self.items.data_ptr() if self.items is not None else None
         s.n_items = 0 if self.items is None else self.items.numel() // 2
+        if self.cl is not None:
+            m, g, cptr, ccol, cpos, citems = self.cl
+            s.cl_m, s.cl_g, s.n_cl_items = m, g, citems.numel() // 2
+            s.cl_ptr, s.cl_col = cptr.data_ptr(), ccol.data_ptr()
+            s.cl_pos, s.cl_items = cpos.data_ptr(), citems.data_ptr()
+        else:
+            s.cl_m = s.cl_g = s.n_cl_items = 0
 
     def build_lut(self, lut=True, lut_t=False):
         dev = self.row_ptr.device
@@ -79,6 +87,24 @@ class Pattern:
         self.items = self.items[:2 * cnt.value]
         self._sync()
         self.struct.n_items = cnt.value
+        return self
+
+    def build_cluster(self, m, g):
+        """Cluster plan for clusters of m consecutive rows, g lanes per column."""
+        dev = self.row_ptr.device
+        nc = (self.n + m - 1) // m
+        cptr = torch.empty(nc + 1, dtype=torch.int32, device=dev)
+        ln = c_int64(0)
+        ni = c_int32(0)
+        L_.call("lnv_pattern_cluster", byref(self.struct), m, g, _ptr(cptr), None, None, 0, None, 0,
+                byref(ln), byref(ni), _stream())
+        ccol = torch.empty(max(1, ln.value), dtype=torch.int32, device=dev)
+        cpos = torch.empty(max(1, ln.value * m), dtype=torch.int32, device=dev)
+        citems = torch.empty(max(2, 2 * ni.value), dtype=torch.int32, device=dev)
+        L_.call("lnv_pattern_cluster", byref(self.struct), m, g, _ptr(cptr), _ptr(ccol), _ptr(cpos),
+                ccol.numel(), _ptr(citems), citems.numel() // 2, byref(ln), byref(ni), _stream())
+        self.cl = (m, g, cptr, ccol, cpos, citems[:2 * ni.value])
+        self._sync()
         return self
 
     def host(self):
@@ -194,7 +220,8 @@ class LNVSystem:
     runs the CG in that metric; None uses the identity.
     """
 
-    def __init__(self, w, device="cuda", R_L=None, metric="hotelling", n_hotelling=16):
+    def __init__(self, w, device="cuda", R_L=None, metric="hotelling", n_hotelling=16,
+                 cluster=(4, 1)):
         if not torch.cuda.is_available():
             raise RuntimeError("LNVSystem needs a GPU (HIP device)")
         L_.load()
@@ -249,6 +276,16 @@ class LNVSystem:
         if metric is not None:
             self.pLL.build_items()
         assert self.pX.nnzb >= self.pZ.nnzb
+        if cluster is not None:
+            # cluster plans of every pattern that is a left operand or an output
+            self.pH.build_lut(lut=True)
+            self.pSL.build_lut(lut=True)
+            pats = [self.pS, self.pH, self.pL, self.pSL, self.pX, self.pZ]
+            if metric is not None:
+                self.pLL.build_lut(lut=True)
+                pats.append(self.pLL)
+            for P in pats:
+                P.build_cluster(*cluster)
         self.perm_SL = transpose_map(self.pSL, self.pLS)
         self.perm_X = transpose_map(self.pX, self.pXT)
         # buffers
@@ -280,7 +317,7 @@ class LNVSystem:
             else:
                 llv = torch.zeros(self.pLL.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
             self.LL = Matrix(self.pLL, llv)
-        plen = L_.load().lnv_partials_len(self.pL.struct.n_items)
+        plen = L_.load().lnv_partials_len(max(self.pL.struct.n_items, self.pL.struct.n_cl_items))
         self.partials = torch.zeros(plen, dtype=torch.float64, device=dev)
         self.scalars = torch.zeros(L_.NSCALARS, dtype=torch.float64, device=dev)
         self.EN = torch.zeros(2, dtype=torch.float64, device=dev)
