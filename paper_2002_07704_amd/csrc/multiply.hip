@@ -180,20 +180,32 @@ __global__ __launch_bounds__(256) void k_mul44(
 // present are wave-uniform scalar loads.  Blocks of the union outside a row's
 // pattern are accumulated and dropped at the store (cheap: the kernel is
 // bound by the B gathers, not by the FP64 FMAs).
+// A-side of one contraction step: the 4 rows' A blocks are wave-uniform; they
+// are fetched two rows at a time (64 scalar registers) so that two scalar
+// round trips, not four, are exposed per step.
 template <int G>
 __device__ __forceinline__ void cluster_fma(double (&acc)[4][16], const double (&b)[16],
                                             const int* __restrict__ apos,
                                             const double* __restrict__ a_val, int g) {
+  int pos[4];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int pos = (G == 1 || g == 0) ? apos[r] : apos[4 + r];
-    if (pos >= 0) {
-      const double* ap = a_val + (size_t)pos * 16;
-      double a[16];
+  for (int r = 0; r < 4; ++r) pos[r] = (G == 1 || g == 0) ? apos[r] : apos[4 + r];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) a[q] = ap[q];
-      block_fma<0>(acc[r], a, b);
+  for (int h = 0; h < 2; ++h) {
+    const int p0 = pos[2 * h], p1 = pos[2 * h + 1];
+    double a0[16], a1[16];
+    if (p0 >= 0) {
+      const double* ap = a_val + (size_t)p0 * 16;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a0[q] = ap[q];
     }
+    if (p1 >= 0) {
+      const double* ap = a_val + (size_t)p1 * 16;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a1[q] = ap[q];
+    }
+    if (p0 >= 0) block_fma<0>(acc[2 * h], a0, b);
+    if (p1 >= 0) block_fma<0>(acc[2 * h + 1], a1, b);
   }
 }
 
@@ -232,23 +244,39 @@ __global__ __launch_bounds__(256) void k_mul44c(
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[r][e] = 0.0;
 
-  double bA[16], bB[16];
-  int pA = -1, pB = -1;
-  if (act && t0 < t1) pA = lcol[(size_t)ka_col[t0] * ns];
-  if (act && t0 + 1 < t1) pB = lcol[(size_t)ka_col[t0 + 1] * ns];
-  if (pA >= 0) load_block(bA, b_val + (size_t)pA * 16);
-  for (int t = t0; t < t1; t += 2) {
-    int pA2 = -1;
-    if (act && t + 2 < t1) pA2 = lcol[(size_t)ka_col[t + 2] * ns];
-    if (pB >= 0) load_block(bB, b_val + (size_t)pB * 16);
-    if (pA >= 0) cluster_fma<G>(acc, bA, ka_pos + (size_t)t * M, a_val, g);
+  // three rotating B buffers: while step t is consumed, the blocks of steps
+  // t+1 and t+2 are in flight; block indices run three steps ahead
+  double b0[16], b1[16], b2[16];
+  int p[3] = {-1, -1, -1};
+  int pn = -1;
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+    if (act && t0 + u < t1) p[u] = lcol[(size_t)ka_col[t0 + u] * ns];
+  if (act && t0 + 3 < t1) pn = lcol[(size_t)ka_col[t0 + 3] * ns];
+  if (p[0] >= 0) load_block(b0, b_val + (size_t)p[0] * 16);
+  if (p[1] >= 0) load_block(b1, b_val + (size_t)p[1] * 16);
+  for (int t = t0; t < t1; t += 3) {
+    // step t (b0), prefetch step t+2 into b2
+    if (p[2] >= 0) load_block(b2, b_val + (size_t)p[2] * 16);
+    int pn2 = -1;
+    if (act && t + 4 < t1) pn2 = lcol[(size_t)ka_col[t + 4] * ns];
+    if (p[0] >= 0) cluster_fma<G>(acc, b0, ka_pos + (size_t)t * M, a_val, g);
     if (t + 1 >= t1) break;
-    int pB2 = -1;
-    if (act && t + 3 < t1) pB2 = lcol[(size_t)ka_col[t + 3] * ns];
-    if (pA2 >= 0) load_block(bA, b_val + (size_t)pA2 * 16);
-    if (pB >= 0) cluster_fma<G>(acc, bB, ka_pos + (size_t)(t + 1) * M, a_val, g);
-    pA = pA2;
-    pB = pB2;
+    // step t+1 (b1), prefetch step t+3 into b0
+    if (pn >= 0) load_block(b0, b_val + (size_t)pn * 16);
+    int pn3 = -1;
+    if (act && t + 5 < t1) pn3 = lcol[(size_t)ka_col[t + 5] * ns];
+    if (p[1] >= 0) cluster_fma<G>(acc, b1, ka_pos + (size_t)(t + 1) * M, a_val, g);
+    if (t + 2 >= t1) break;
+    // step t+2 (b2), prefetch step t+4 into b1
+    if (pn2 >= 0) load_block(b1, b_val + (size_t)pn2 * 16);
+    int pn4 = -1;
+    if (act && t + 6 < t1) pn4 = lcol[(size_t)ka_col[t + 6] * ns];
+    if (p[2] >= 0) cluster_fma<G>(acc, b2, ka_pos + (size_t)(t + 2) * M, a_val, g);
+    p[0] = pn;
+    p[1] = pn2;
+    p[2] = pn3;
+    pn = pn4;
   }
 
   double d1 = 0.0, d2 = 0.0;
