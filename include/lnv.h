@@ -304,6 +304,33 @@ enum { LNV_ST_NONFINITE = 1, LNV_ST_NO_ALPHA = 2, LNV_ST_NO_DELTA = 4, LNV_ST_DE
 int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
              lnv_bsm* F, double* EN, const lnv_eval_ws* ws, hipStream_t s);
 
+/* ------------------------------------------------------------ adjoint
+ * lnv_adjoint -- derivatives of E = 2 Tr[KH], K = 3LSL - 2LSLSL (Sec. II.C.2,
+ * Eq. 4), with respect to each stored entry of H and of S at fixed L:
+ *   dH = dE/dH = 2 K on H's pattern          = P_H(6 L.SL - 4 LSL.SL)
+ *   dS = dE/dS = 2 [3 LHL - 2 (LSLHL + LHLSL)] on S's pattern
+ *              = P_S(6 L.HL) - 4 (Y + Y^T),  Y = P_S(LSL.HL)
+ * (dE/dL is lnv_eval's G).  L, S and H must be symmetric and stored in both
+ * triangles, as for lnv_eval.  The natural-range intermediates are formed
+ * anew on every call (nothing is carried over from lnv_eval):
+ *  SL   values on pat(S.L)   (pattern needs lut and items)
+ *  LSL  values on pat(L.S.L) (pattern needs items)
+ *  HL   values on pat(H.L)   (pattern needs lut and items; used only for dS)
+ *  YS   device [nnzb_S * 16] scratch (used only for dS)
+ * dS is on S's pattern (needs lut and items), dH on H's pattern (needs
+ * items); either may be NULL, not both.  FP64, blk 4.  Hot path: allocates
+ * nothing, no host synchronisation.
+ */
+typedef struct lnv_adj_ws {
+  lnv_bsm SL;
+  lnv_bsm LSL;
+  lnv_bsm HL;
+  double* YS;
+} lnv_adj_ws;
+
+int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* dS,
+                lnv_bsm* dH, const lnv_adj_ws* ws, hipStream_t s);
+
 /* ------------------------------------------------------------ a5-a7: CG
  * Buffers of the conjugate-gradient minimisation (all on L's pattern unless
  * stated).  gc/gc_prev (metric runs) or g/gc_prev (identity metric) and

@@ -54,6 +54,10 @@ class LnvCgWs(ctypes.Structure):
                 ("D_prev", c_void_p)]
 
 
+class LnvAdjWs(ctypes.Structure):
+    _fields_ = [("SL", LnvBsm), ("LSL", LnvBsm), ("HL", LnvBsm), ("YS", c_void_p)]
+
+
 class LnvOpts(ctypes.Structure):
     _fields_ = [("reset_period", c_int32), ("n_tol", c_double), ("step_cap", c_double)]
 
@@ -85,6 +89,7 @@ SIGNATURES = {
     "lnv_bsm_dot": (c_int, [PBsm, PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_partials_len": (c_int64, [c_int32]),
     "lnv_eval": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, c_void_p, POINTER(LnvEvalWs), c_void_p]),
+    "lnv_adjoint": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, POINTER(LnvAdjWs), c_void_p]),
     "lnv_hotelling": (c_int, [PBsm, PBsm, c_int32, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),

@@ -351,7 +351,79 @@ class LNVSystem:
                     int(n_hotelling), byref(self.ws), _stream())
         self.opts = Opts()
         self.k = 0
+        self.cluster = cluster
+        self.adj_ws = None
         torch.cuda.synchronize()
+
+    # ----------------------------------------------------------- adjoint set-up
+    def adjoint_setup(self):
+        """Patterns and buffers of lnv_adjoint: natural pat(L.S.L) and pat(H.L),
+        work lists of S's pattern, and the scratch on S's pattern.  The S.L
+        values share the evaluation's buffer (both are recomputed per call)."""
+        if self.adj_ws is not None:
+            return
+        dev = self.dev
+        self.pLSL = product_pattern(self.pL, self.pSL)           # L.S.L
+        self.pHL = product_pattern(self.pH, self.pL)             # H.L
+        self.triples.update(
+            LSL=self.pLSL.triples, HL=self.pHL.triples,
+            dH4=product_pattern(self.pLSL, self.pSL, mask=self.pH).triples,
+            dH6=product_pattern(self.pL, self.pSL, mask=self.pH).triples,
+            dS4=product_pattern(self.pLSL, self.pHL, mask=self.pS).triples,
+            dS6=product_pattern(self.pL, self.pHL, mask=self.pS).triples,
+        )
+        self.pSL.build_lut(lut=True)
+        self.pLSL.build_items()
+        self.pHL.build_lut(lut=True).build_items()
+        self.pS.build_lut(lut=True).build_items()
+        if self.cluster is not None:
+            # left operand L.S.L and output H.L take part in clustered products;
+            # L.S.L's index table is needed only while its plan is built
+            self.pLSL.build_lut(lut=True).build_cluster(*self.cluster)
+            self.pLSL.lut = None
+            self.pLSL._sync()
+            self.pHL.build_cluster(*self.cluster)
+            if self.pS.cl is None:
+                self.pS.build_cluster(*self.cluster)
+        self.LSL = Matrix(self.pLSL)
+        self.HL = Matrix(self.pHL)
+        self.YS = torch.zeros(self.pS.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
+        self.adj_ws = L_.LnvAdjWs()
+        self.adj_ws.SL = self.SL.struct
+        self.adj_ws.LSL = self.LSL.struct
+        self.adj_ws.HL = self.HL.struct
+        self.adj_ws.YS = self.YS.data_ptr()
+        torch.cuda.synchronize()
+
+    def adjoint_flops(self, dS=True, dH=True):
+        """Algorithmic flops of one lnv_adjoint call."""
+        t = self.triples
+        tot = t["SL"] + t["LSL"]
+        if dH:
+            tot += t["dH4"] + t["dH6"]
+        if dS:
+            tot += t["HL"] + t["dS4"] + t["dS6"]
+        return 2 * BLK ** 3 * tot
+
+    def adjoint(self, L, S, H, dS=None, dH=None):
+        """dE/dS (into dS, on S's pattern) and dE/dH (into dH, on H's pattern)
+        at the values L, S, H (tensors [nnzb, 4, 4] on this system's patterns)."""
+        self.adjoint_setup()
+        Lm, Sm, Hm = bsm(self.pL, L), bsm(self.pS, S), bsm(self.pH, H)
+        dSm = bsm(self.pS, dS) if dS is not None else None
+        dHm = bsm(self.pH, dH) if dH is not None else None
+        L_.call("lnv_adjoint", byref(Lm.struct), byref(Sm.struct), byref(Hm.struct),
+                byref(dSm.struct) if dSm is not None else None,
+                byref(dHm.struct) if dHm is not None else None, byref(self.adj_ws), _stream())
+        return dS, dH
+
+    def eval_values(self, L, S, H, G, F, EN):
+        """lnv_eval at the given value tensors (on this system's patterns)."""
+        Lm, Sm, Hm = bsm(self.pL, L), bsm(self.pS, S), bsm(self.pH, H)
+        Gm, Fm = bsm(self.pL, G), bsm(self.pL, F)
+        L_.call("lnv_eval", byref(Lm.struct), byref(Sm.struct), byref(Hm.struct),
+                byref(Gm.struct), byref(Fm.struct), _ptr(EN), byref(self.ws.ev), _stream())
+        return EN
 
     # ----------------------------------------------------------- flop accounting
     def flops(self, what="eval"):

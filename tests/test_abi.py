@@ -63,6 +63,10 @@ def test_host_side_argument_errors(lib):
     o = L.LnvOpts(40, 1e-11, 0.1)
     assert lib.lnv_cg_step(ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), None, 8.0, 0, ctypes.byref(o), None, None) == L.EINVAL
     assert lib.lnv_hotelling(ctypes.byref(m), ctypes.byref(m), -1, None, None) == L.EINVAL
+    assert lib.lnv_adjoint(None, None, None, None, None, None, None) == L.EINVAL
+    ws = L.LnvAdjWs()
+    assert lib.lnv_adjoint(ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), None, None,
+                           ctypes.byref(ws), None) == L.EINVAL
     assert lib.lnv_partials_len(10) >= 12 * 8 * 1024
 
 
@@ -76,12 +80,14 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("gcc or ROCm headers not available")
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "lnv.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu", sizeof(lnv_pattern), sizeof(lnv_bsm),'
-                   ' sizeof(lnv_eval_ws), sizeof(lnv_cg_ws), sizeof(lnv_opts)); return 0;}\n')
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu", sizeof(lnv_pattern), sizeof(lnv_bsm),'
+                   ' sizeof(lnv_eval_ws), sizeof(lnv_cg_ws), sizeof(lnv_opts),'
+                   ' sizeof(lnv_adj_ws)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
                     "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
-    want = [ctypes.sizeof(x) for x in (L.LnvPattern, L.LnvBsm, L.LnvEvalWs, L.LnvCgWs, L.LnvOpts)]
+    want = [ctypes.sizeof(x) for x in (L.LnvPattern, L.LnvBsm, L.LnvEvalWs, L.LnvCgWs, L.LnvOpts,
+                                           L.LnvAdjWs)]
     assert got == want
