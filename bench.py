@@ -214,6 +214,49 @@ def main():
     ms_eval = (time.perf_counter() - t0) * 1e3 / args.eval_reps
     flops_eval = sysg.flops("eval")
 
+    # mixed precision: FP32 products (FP32 or FP64 accumulation), FP64 traces,
+    # at the L of the last FP64 step, against the FP64 evaluation there
+    sysg.mixed_setup()
+    sysg.eval()
+    torch.cuda.synchronize()
+    E64, N64 = (float(x) for x in sysg.EN.cpu())
+    G64, F64 = sysg.G.val.clone(), sysg.F.val.clone()
+    mixed = {}
+    for acc, name in ((0, "fp32_accumulate"), (1, "fp64_accumulate")):
+        L_.call("lnv_set_f32_accumulation", acc)
+        sysg.eval_mixed()
+        torch.cuda.synchronize()
+        E32, N32 = (float(x) for x in sysg.EN.cpu())
+        dG = float(torch.linalg.vector_norm(sysg.G.val - G64) / torch.linalg.vector_norm(G64))
+        dF = float(torch.linalg.vector_norm(sysg.F.val - F64) / torch.linalg.vector_norm(F64))
+        t0 = time.perf_counter()
+        for _ in range(args.eval_reps):
+            sysg.eval_mixed()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.eval_reps
+        mixed[name] = {"evals_per_s": 1e3 / ms, "ms": ms,
+                       "gflops_per_s": flops_eval / (ms * 1e-3) / 1e9,
+                       "speedup_vs_fp64_eval": ms_eval / ms,
+                       "dE_per_atom": abs(E32 - E64) / w.n, "dN_rel": abs(N32 - N64) / N64,
+                       "dG_rel": dG, "dF_rel": dF,
+                       "within_1e-6_Ha_per_atom": abs(E32 - E64) / w.n <= 1e-6}
+    L_.call("lnv_set_f32_accumulation", 0)
+    del G64, F64
+
+    # adjoint: dE/dS and dE/dH at the same L (L.S.L and H.L recomputed)
+    sysg.adjoint_setup()
+    dS = torch.empty_like(sysg.S.val)
+    dH = torch.empty_like(sysg.H.val)
+    sysg.adjoint(sysg.L.val, sysg.S.val, sysg.H.val, dS=dS, dH=dH)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.eval_reps):
+        sysg.adjoint(sysg.L.val, sysg.S.val, sysg.H.val, dS=dS, dH=dH)
+    torch.cuda.synchronize()
+    ms_adj = (time.perf_counter() - t0) * 1e3 / args.eval_reps
+    flops_adj = sysg.adjoint_flops()
+    del dS, dH
+
     traffic = None
     if os.path.exists(args.traffic_json):
         try:
@@ -252,6 +295,9 @@ def main():
         "cg_status_bits": status,
         "eval_only": {"evals_per_s": 1e3 / ms_eval, "ms": ms_eval, "gflop": flops_eval / 1e9,
                       "gflops_per_s": flops_eval / (ms_eval * 1e-3) / 1e9},
+        "mixed": mixed,
+        "adjoint_dS_dH": {"ms": ms_adj, "gflop": flops_adj / 1e9,
+                          "gflops_per_s": flops_adj / (ms_adj * 1e-3) / 1e9},
         "setup_s": setup_s,
         "roofline": {
             "kernel": "k_mul44 (block SpGEMM, FP64 VALU)",

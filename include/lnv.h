@@ -55,7 +55,10 @@ typedef enum lnv_status {
   LNV_EUNSUPPORTED = 6  /* valid request this build does not implement */
 } lnv_status;
 
-enum { LNV_F64 = 0 };
+/* Value types of lnv_bsm.  FP32 matrices are accepted by the multiply, the
+ * transpose and the conversion calls and by the mixed-precision evaluation's
+ * workspace; every other call takes FP64. */
+enum { LNV_F64 = 0, LNV_F32 = 1 };
 
 /* Largest block-row count accepted by the set-up kernels (LDS bitmaps). */
 #define LNV_MAX_ATOMS 262144
@@ -103,7 +106,7 @@ typedef struct lnv_pattern {
 typedef struct lnv_bsm {
   const lnv_pattern* pat;  /* host pointer */
   int32_t blk;             /* block edge (stored values per block: blk*blk) */
-  int32_t dtype;           /* LNV_F64 */
+  int32_t dtype;           /* LNV_F64 or LNV_F32 */
   void* val;               /* device [pat->nnzb * blk * blk] */
 } lnv_bsm;
 
@@ -201,7 +204,8 @@ int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
  * (blocks of the product outside C's pattern are not formed: a range
  * truncated product).  op(B) = B (transB = 0) or B^T (transB = 1).
  * Needs A.row_ptr/col, B.lut (transB = 0) or B.lut_t (transB = 1) and C.items.
- * Hot path: allocates nothing.
+ * A, B and C share one dtype: FP64, or FP32 with FP32 products and FP32
+ * accumulation (LNV_EUNSUPPORTED for a mix).  Hot path: allocates nothing.
  */
 int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
                      double beta, lnv_bsm* C, hipStream_t s);
@@ -220,8 +224,22 @@ int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32
 
 /* lnv_bsm_transpose -- AT = A^T: block p of A, transposed, goes to position
  * perm[p] of AT (perm from lnv_pattern_transpose_map).  Needs A.items.
- * Hot path (HBM-bound copy). */
+ * A and AT of one dtype.  Hot path (HBM-bound copy). */
 int lnv_bsm_transpose(const lnv_bsm* A, const int32_t* perm, lnv_bsm* AT, hipStream_t s);
+
+/* lnv_bsm_convert -- B = A converted elementwise to B's dtype (FP64 <-> FP32,
+ * round to nearest), A and B on the same pattern (or patterns with the same
+ * number of blocks).  Hot path (HBM-bound). */
+int lnv_bsm_convert(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
+
+/* lnv_set_f32_accumulation -- arithmetic of the FP32 products (process-wide):
+ * LNV_ACC_F32 (the default): FP32 multiply-add into FP32 accumulators;
+ * LNV_ACC_F64: FP64 multiply-add into FP64 accumulators (the product of two
+ * FP32 values is exact in FP64, so only the sums round, in FP64), the result
+ * rounded once to FP32 at the store.  Either way the operands and the result
+ * are stored in FP32. */
+enum { LNV_ACC_F32 = 0, LNV_ACC_F64 = 1 };
+int lnv_set_f32_accumulation(int32_t acc);
 
 /* lnv_set_kslabs -- split every multiply's contraction index k into n
  * atom-index slabs, one launch per slab accumulating into C (n <= 0: the
@@ -303,6 +321,40 @@ enum { LNV_ST_NONFINITE = 1, LNV_ST_NO_ALPHA = 2, LNV_ST_NO_DELTA = 4, LNV_ST_DE
  */
 int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
              lnv_bsm* F, double* EN, const lnv_eval_ws* ws, hipStream_t s);
+
+/* ------------------------------------------------------------ a3/a4 mixed precision
+ * lnv_eval_mixed -- lnv_eval with the six block products in FP32 (FP32
+ * multiply-add, FP32 accumulation) and everything else in FP64: L, S and H
+ * are FP64 and are rounded to FP32 copies by the call; the assembly of G and
+ * F reads the FP32 intermediates and forms G, F, E, N and every trace in
+ * FP64, with the FP64 L on the left of each trace.  The workspace mirrors
+ * lnv_eval_ws with FP32 values (same patterns and tables):
+ *  L, S, H   FP32 copies on L's, S's and H's pattern objects (written)
+ *  SL .. Z   FP32 intermediates, patterns as in lnv_eval_ws
+ *  YT, W, V  device [nnzb_L * 16] FP32
+ * G, F FP64 on L's pattern.  Hot path: allocates nothing.
+ */
+typedef struct lnv_eval32_ws {
+  lnv_bsm L;
+  lnv_bsm S;
+  lnv_bsm H;
+  lnv_bsm SL;
+  lnv_bsm LS;
+  lnv_bsm X;
+  lnv_bsm XT;
+  lnv_bsm Z;
+  const int32_t* perm_SL;
+  const int32_t* perm_X;
+  float* YT;
+  float* W;
+  float* V;
+  double* partials;
+  int64_t partials_len;
+  double* scalars;
+} lnv_eval32_ws;
+
+int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
+                   lnv_bsm* F, double* EN, const lnv_eval32_ws* ws, hipStream_t s);
 
 /* ------------------------------------------------------------ adjoint
  * lnv_adjoint -- derivatives of E = 2 Tr[KH], K = 3LSL - 2LSLSL (Sec. II.C.2,

@@ -68,16 +68,25 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // ---------------------------------------------------------------- checks
+// FP64 matrix (every call but the multiply and transpose takes FP64 only).
 inline bool bsm_ok(const lnv_bsm* M) {
   return M && M->pat && M->val && M->dtype == LNV_F64 && M->pat->n > 0;
+}
+
+// FP64 or FP32 matrix.
+inline bool bsm_ok_any(const lnv_bsm* M) {
+  return M && M->pat && M->val && (M->dtype == LNV_F64 || M->dtype == LNV_F32) &&
+         M->pat->n > 0;
 }
 
 // Internal multiply used by the public wrappers and by eval / CG.
 //  store: write C;  m1/m2: dot partners on C's pattern (values, may be null)
 //  partials: [2*C.n_items];  skip: device flag, kernel returns when != 0.
+//  A, B, C share one dtype (FP64, or FP32 with FP32 accumulation); m1, m2
+//  have C's dtype; the trace partials are FP64 either way.
 int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
-                    double beta, const lnv_bsm* C, int store, const double* m1,
-                    const double* m2, double* partials, const double* skip,
+                    double beta, const lnv_bsm* C, int store, const void* m1,
+                    const void* m2, double* partials, const double* skip,
                     hipStream_t s);
 
 // Number of dot partials (work items) multiply_launch writes for C.

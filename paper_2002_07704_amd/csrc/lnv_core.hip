@@ -292,15 +292,18 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
 // Workgroup q handles item q of L's pattern: 64 blocks of one row, 4 threads
 // per block, thread (b, r) owns row r of block b (4 elements).
 
-// G, F and the trace partials of one evaluation.
+// G, F and the trace partials of one evaluation.  The intermediates are of
+// type T (FP64, or FP32 in the mixed-precision evaluation); G, F, L and every
+// trace are FP64.
+template <typename T>
 __global__ __launch_bounds__(256) void k_assemble(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
     const int* __restrict__ col, const int* __restrict__ l_lut,
     const double* __restrict__ L, const int* __restrict__ x_lut,
-    const double* __restrict__ X, const int* __restrict__ xt_lut,
-    const double* __restrict__ XT, const double* __restrict__ YT,
-    const double* __restrict__ Wv, const int* __restrict__ z_lut,
-    const double* __restrict__ Z, const double* __restrict__ V, double* __restrict__ G,
+    const T* __restrict__ X, const int* __restrict__ xt_lut,
+    const T* __restrict__ XT, const T* __restrict__ YT,
+    const T* __restrict__ Wv, const int* __restrict__ z_lut,
+    const T* __restrict__ Z, const T* __restrict__ V, double* __restrict__ G,
     double* __restrict__ F, double* __restrict__ partials) {
   __shared__ double sh[16];
   const int item = blockIdx.x;
@@ -318,13 +321,13 @@ __global__ __launch_bounds__(256) void k_assemble(
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int e = r * 4 + c, et = c * 4 + r;
-      const double x = xp >= 0 ? X[(size_t)xp * 16 + e] : 0.0;
-      const double xt = xtp >= 0 ? XT[(size_t)xtp * 16 + e] : 0.0;
-      const double yt = YT[(size_t)p * 16 + e];
-      const double ytt = ytp >= 0 ? YT[(size_t)ytp * 16 + et] : 0.0;
-      const double w = Wv[(size_t)p * 16 + e];
-      const double z = zp >= 0 ? Z[(size_t)zp * 16 + e] : 0.0;
-      const double v = V[(size_t)p * 16 + e];
+      const double x = xp >= 0 ? (double)X[(size_t)xp * 16 + e] : 0.0;
+      const double xt = xtp >= 0 ? (double)XT[(size_t)xtp * 16 + e] : 0.0;
+      const double yt = (double)YT[(size_t)p * 16 + e];
+      const double ytt = ytp >= 0 ? (double)YT[(size_t)ytp * 16 + et] : 0.0;
+      const double w = (double)Wv[(size_t)p * 16 + e];
+      const double z = zp >= 0 ? (double)Z[(size_t)zp * 16 + e] : 0.0;
+      const double v = (double)V[(size_t)p * 16 + e];
       const double l = L[(size_t)p * 16 + e];
       const double g = 2.0 * (3.0 * (x + xt) - 2.0 * (yt + ytt + w));
       const double f = 12.0 * (z - v);
@@ -447,11 +450,12 @@ __global__ __launch_bounds__(256) void k_identity(const int* __restrict__ items,
 }
 
 // AT[perm[p]] = A[p]^T for the blocks of item q of A's pattern.
+template <typename T>
 __global__ __launch_bounds__(256) void k_transpose(const int* __restrict__ items,
                                                    const int* __restrict__ rp,
                                                    const int* __restrict__ perm,
-                                                   const double* __restrict__ A,
-                                                   double* __restrict__ AT,
+                                                   const T* __restrict__ A,
+                                                   T* __restrict__ AT,
                                                    const double* __restrict__ skip) {
   if (skip != nullptr && *skip != 0.0) return;
   const int item = blockIdx.x;
@@ -461,11 +465,21 @@ __global__ __launch_bounds__(256) void k_transpose(const int* __restrict__ items
   if (b >= cnt) return;
   const int p = c0 + b;
   const size_t q = (size_t)perm[p];
-  const double4 v = reinterpret_cast<const double4*>(A + (size_t)p * 16)[r];
-  AT[q * 16 + 0 * 4 + r] = v.x;
-  AT[q * 16 + 1 * 4 + r] = v.y;
-  AT[q * 16 + 2 * 4 + r] = v.z;
-  AT[q * 16 + 3 * 4 + r] = v.w;
+  const T* a = A + (size_t)p * 16 + r * 4;
+  const T v0 = a[0], v1 = a[1], v2 = a[2], v3 = a[3];
+  AT[q * 16 + 0 * 4 + r] = v0;
+  AT[q * 16 + 1 * 4 + r] = v1;
+  AT[q * 16 + 2 * 4 + r] = v2;
+  AT[q * 16 + 3 * 4 + r] = v3;
+}
+
+// Elementwise dtype conversion of a value array (grid-stride).
+template <typename S, typename D>
+__global__ __launch_bounds__(256) void k_convert(int64_t nv, const S* __restrict__ src,
+                                                 D* __restrict__ dst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = (D)src[e];
 }
 
 // ------------------------------------------------------------------ vector kernels
@@ -644,17 +658,24 @@ bool pattern_ready(const lnv_pattern* p, bool lut, bool lut_t, bool items) {
          (!items || p->items);
 }
 
-int transpose_skip_launch(const lnv_bsm* A, const int32_t* perm, double* AT,
+// AT: values of A's dtype.
+int transpose_skip_launch(const lnv_bsm* A, const int32_t* perm, void* AT,
                           const double* skip, hipStream_t s) {
   const lnv_pattern* pa = A->pat;
   if (pa->n_items == 0) return LNV_OK;
-  k_transpose<<<pa->n_items, 256, 0, s>>>(pa->items, pa->row_ptr, perm,
-                                          static_cast<const double*>(A->val), AT, skip);
+  if (A->dtype == LNV_F32)
+    k_transpose<float><<<pa->n_items, 256, 0, s>>>(pa->items, pa->row_ptr, perm,
+                                                   static_cast<const float*>(A->val),
+                                                   static_cast<float*>(AT), skip);
+  else
+    k_transpose<double><<<pa->n_items, 256, 0, s>>>(pa->items, pa->row_ptr, perm,
+                                                    static_cast<const double*>(A->val),
+                                                    static_cast<double*>(AT), skip);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
 
-int transpose_launch(const lnv_bsm* A, const int32_t* perm, double* AT, hipStream_t s) {
+int transpose_launch(const lnv_bsm* A, const int32_t* perm, void* AT, hipStream_t s) {
   return transpose_skip_launch(A, perm, AT, nullptr, s);
 }
 
@@ -688,27 +709,41 @@ int check_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_b
   return LNV_OK;
 }
 
-// The six products, the assembly of G and F and the energy / electron traces.
-int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, double* F,
-              double* EN, const lnv_eval_ws* ws, hipStream_t s) {
-  const lnv_pattern* pl = L->pat;
-  lnv_bsm YT{pl, 4, LNV_F64, ws->YT}, Wm{pl, 4, LNV_F64, ws->W}, Vm{pl, 4, LNV_F64, ws->V};
-  LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &ws->SL, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(transpose_launch(&ws->SL, ws->perm_SL, static_cast<double*>(ws->LS.val), s));
-  LNV_TRY(multiply_launch(1.0, H, &ws->LS, 0, 0.0, &ws->X, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, S, &ws->LS, 0, 0.0, &ws->Z, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(transpose_launch(&ws->X, ws->perm_X, static_cast<double*>(ws->XT.val), s));
-  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->XT, 0, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->X, 0, 0.0, &Wm, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, &ws->SL, &ws->Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
+// Operands and intermediates of one evaluation, all of one dtype T.
+struct EvalOps {
+  const lnv_bsm *L, *S, *H;
+  const lnv_bsm *SL, *LS, *X, *XT, *Z;
+  const int32_t *perm_SL, *perm_X;
+  void *YT, *W, *V;
+  double* partials;
+  double* scalars;
+};
+
+// The six products (in T), the assembly of G and F and the energy / electron
+// traces (FP64, with the FP64 L64 on the left of every trace).
+template <typename T>
+int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, double* EN,
+                  hipStream_t s) {
+  const lnv_pattern* pl = L64->pat;
+  const int dt = o.SL->dtype;
+  lnv_bsm YT{pl, 4, dt, o.YT}, Wm{pl, 4, dt, o.W}, Vm{pl, 4, dt, o.V};
+  LNV_TRY(multiply_launch(1.0, o.S, o.L, 0, 0.0, o.SL, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(transpose_launch(o.SL, o.perm_SL, o.LS->val, s));
+  LNV_TRY(multiply_launch(1.0, o.H, o.LS, 0, 0.0, o.X, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, o.S, o.LS, 0, 0.0, o.Z, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(transpose_launch(o.X, o.perm_X, o.XT->val, s));
+  LNV_TRY(multiply_launch(1.0, o.SL, o.XT, 0, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, o.SL, o.X, 0, 0.0, &Wm, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, o.SL, o.Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
   const int ni = pl->n_items;
-  double* part = ws->partials;
-  k_assemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, pl->lut,
-                                static_cast<const double*>(L->val), ws->X.pat->lut,
-                                static_cast<const double*>(ws->X.val), ws->XT.pat->lut,
-                                static_cast<const double*>(ws->XT.val), ws->YT, ws->W,
-                                ws->Z.pat->lut, static_cast<const double*>(ws->Z.val), ws->V,
-                                G, F, part);
+  double* part = o.partials;
+  k_assemble<T><<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, pl->lut,
+                                   static_cast<const double*>(L64->val), o.X->pat->lut,
+                                   static_cast<const T*>(o.X->val), o.XT->pat->lut,
+                                   static_cast<const T*>(o.XT->val),
+                                   static_cast<const T*>(o.YT), static_cast<const T*>(o.W),
+                                   o.Z->pat->lut, static_cast<const T*>(o.Z->val),
+                                   static_cast<const T*>(o.V), G, F, part);
   LNV_LAUNCH_CHECK();
   RedList rl = reds();
   add(rl, 0 * (int64_t)ni, ni, 1, LNV_SC_T0);
@@ -719,7 +754,69 @@ int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, d
   add(rl, 5 * (int64_t)ni, ni, 1, LNV_SC_GF);
   StageArgs sa{};
   sa.en_out = EN;
-  return scalar_stage(part, rl, ws->scalars, ST_EVAL, sa, s);
+  return scalar_stage(part, rl, o.scalars, ST_EVAL, sa, s);
+}
+
+int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, double* F,
+              double* EN, const lnv_eval_ws* ws, hipStream_t s) {
+  EvalOps o{L,       S,           H,          &ws->SL, &ws->LS, &ws->X, &ws->XT,
+            &ws->Z,  ws->perm_SL, ws->perm_X, ws->YT,  ws->W,   ws->V,  ws->partials,
+            ws->scalars};
+  return eval_products<double>(L, o, G, F, EN, s);
+}
+
+int convert_launch(const lnv_bsm* A, lnv_bsm* B, hipStream_t s) {
+  const int64_t nv = A->pat->nnzb * (int64_t)A->blk * A->blk;
+  if (nv == 0) return LNV_OK;
+  int64_t g = (nv + 255) / 256;
+  const int grid = (int)(g < 4 * kVecGrid ? g : 4 * kVecGrid);
+  if (A->dtype == LNV_F64 && B->dtype == LNV_F32)
+    k_convert<double, float><<<grid, 256, 0, s>>>(nv, static_cast<const double*>(A->val),
+                                                  static_cast<float*>(B->val));
+  else if (A->dtype == LNV_F32 && B->dtype == LNV_F64)
+    k_convert<float, double><<<grid, 256, 0, s>>>(nv, static_cast<const float*>(A->val),
+                                                  static_cast<double*>(B->val));
+  else if (A->dtype == LNV_F64)
+    k_convert<double, double><<<grid, 256, 0, s>>>(nv, static_cast<const double*>(A->val),
+                                                   static_cast<double*>(B->val));
+  else
+    k_convert<float, float><<<grid, 256, 0, s>>>(nv, static_cast<const float*>(A->val),
+                                                 static_cast<float*>(B->val));
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+bool f32_ok(const lnv_bsm* M) { return bsm_ok_any(M) && M->dtype == LNV_F32 && M->blk == 4; }
+
+int check_eval32(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* G,
+                 const lnv_bsm* F, const lnv_eval32_ws* ws) {
+  if (!bsm_ok(L) || !bsm_ok(S) || !bsm_ok(H) || !ws || !G || !F || !bsm_ok(G) || !bsm_ok(F))
+    return LNV_EINVAL;
+  if (!ws->YT || !ws->W || !ws->V || !ws->partials || !ws->scalars || !ws->perm_SL ||
+      !ws->perm_X)
+    return LNV_EINVAL;
+  if (!f32_ok(&ws->L) || !f32_ok(&ws->S) || !f32_ok(&ws->H) || !f32_ok(&ws->SL) ||
+      !f32_ok(&ws->LS) || !f32_ok(&ws->X) || !f32_ok(&ws->XT) || !f32_ok(&ws->Z))
+    return LNV_EINVAL;
+  if (L->blk != 4 || S->blk != 4 || H->blk != 4) return LNV_EUNSUPPORTED;
+  if (ws->L.pat != L->pat || ws->S.pat != S->pat || ws->H.pat != H->pat) return LNV_EPATTERN;
+  if (G->pat != L->pat || F->pat != L->pat) return LNV_EPATTERN;
+  const int n = L->pat->n;
+  if (S->pat->n != n || H->pat->n != n || ws->SL.pat->n != n || ws->LS.pat->n != n ||
+      ws->X.pat->n != n || ws->XT.pat->n != n || ws->Z.pat->n != n)
+    return LNV_EPATTERN;
+  if (ws->SL.pat->nnzb != ws->LS.pat->nnzb || ws->X.pat->nnzb != ws->XT.pat->nnzb)
+    return LNV_EPATTERN;
+  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
+      !pattern_ready(H->pat, false, false, false) ||
+      !pattern_ready(ws->SL.pat, false, false, true) ||
+      !pattern_ready(ws->LS.pat, true, false, false) ||
+      !pattern_ready(ws->X.pat, true, false, true) ||
+      !pattern_ready(ws->XT.pat, true, false, false) ||
+      !pattern_ready(ws->Z.pat, true, false, true))
+    return LNV_EPATTERN;
+  if (ws->partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
+  return LNV_OK;
 }
 
 int vec_grid() { return kVecGrid; }
@@ -758,13 +855,15 @@ extern "C" int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bs
                                     int32_t transB, double beta, lnv_bsm* C, int32_t store,
                                     const lnv_bsm* M1, const lnv_bsm* M2, double* partials,
                                     double* out, hipStream_t s) {
-  if (!bsm_ok(C)) return LNV_EINVAL;
-  if ((M1 && (!bsm_ok(M1) || M1->pat != C->pat)) || (M2 && (!bsm_ok(M2) || M2->pat != C->pat)))
+  if (!bsm_ok_any(C)) return LNV_EINVAL;
+  if ((M1 && (!bsm_ok_any(M1) || M1->pat != C->pat)) ||
+      (M2 && (!bsm_ok_any(M2) || M2->pat != C->pat)))
     return LNV_EPATTERN;
+  if ((M1 && M1->dtype != C->dtype) || (M2 && M2->dtype != C->dtype)) return LNV_EUNSUPPORTED;
   if ((M1 || M2) && (!partials || !out)) return LNV_EINVAL;
   if (M2 && !M1) return LNV_EINVAL;
-  const double* m1 = M1 ? static_cast<const double*>(M1->val) : nullptr;
-  const double* m2 = M2 ? static_cast<const double*>(M2->val) : nullptr;
+  const void* m1 = M1 ? M1->val : nullptr;
+  const void* m2 = M2 ? M2->val : nullptr;
   LNV_TRY(multiply_launch(alpha, A, B, transB, beta, C, store, m1, m2, partials, nullptr, s));
   if (!M1) return LNV_OK;
   const int ni = multiply_nparts(A, B, transB, C);
@@ -810,6 +909,27 @@ extern "C" int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, ln
   LNV_TRY(check_eval(L, S, H, G, F, ws));
   return eval_core(L, S, H, static_cast<double*>(G->val), static_cast<double*>(F->val), EN, ws,
                    s);
+}
+
+extern "C" int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
+                              lnv_bsm* F, double* EN, const lnv_eval32_ws* ws, hipStream_t s) {
+  LNV_TRY(check_eval32(L, S, H, G, F, ws));
+  lnv_bsm L32 = ws->L, S32 = ws->S, H32 = ws->H;
+  LNV_TRY(convert_launch(L, &L32, s));
+  LNV_TRY(convert_launch(S, &S32, s));
+  LNV_TRY(convert_launch(H, &H32, s));
+  EvalOps o{&L32,   &S32,        &H32,       &ws->SL, &ws->LS, &ws->X, &ws->XT,
+            &ws->Z, ws->perm_SL, ws->perm_X, ws->YT,  ws->W,   ws->V,  ws->partials,
+            ws->scalars};
+  return eval_products<float>(L, o, static_cast<double*>(G->val), static_cast<double*>(F->val),
+                              EN, s);
+}
+
+extern "C" int lnv_bsm_convert(const lnv_bsm* A, lnv_bsm* B, hipStream_t s) {
+  if (!bsm_ok_any(A) || !bsm_ok_any(B)) return LNV_EINVAL;
+  if (A->blk != B->blk) return LNV_EPATTERN;
+  if (A->pat != B->pat && A->pat->nnzb != B->pat->nnzb) return LNV_EPATTERN;
+  return convert_launch(A, B, s);
 }
 
 namespace {
@@ -1114,10 +1234,10 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
 
 extern "C" int lnv_bsm_transpose(const lnv_bsm* A, const int32_t* perm, lnv_bsm* AT,
                                  hipStream_t s) {
-  if (!bsm_ok(A) || !bsm_ok(AT) || !perm) return LNV_EINVAL;
-  if (A->blk != 4 || AT->blk != 4) return LNV_EUNSUPPORTED;
+  if (!bsm_ok_any(A) || !bsm_ok_any(AT) || !perm) return LNV_EINVAL;
+  if (A->blk != 4 || AT->blk != 4 || A->dtype != AT->dtype) return LNV_EUNSUPPORTED;
   if (A->pat->n != AT->pat->n || A->pat->nnzb != AT->pat->nnzb || !A->pat->items ||
       !A->pat->row_ptr)
     return LNV_EPATTERN;
-  return transpose_launch(A, perm, static_cast<double*>(AT->val), s);
+  return transpose_launch(A, perm, AT->val, s);
 }

@@ -32,20 +32,24 @@
 namespace lnv {
 namespace {
 
-template <int TRANS_B>
-__device__ __forceinline__ void block_fma(double (&acc)[16], const double (&a)[16],
-                                          const double (&b)[16]) {
+// Values are stored as T; products and sums are formed in Acc: FP64 / FP64,
+// or for the mixed-precision products FP32 values with FP32 multiply-add
+// (Acc = float) or with FP64 multiply-add (Acc = double: the product of two
+// FP32 values is exact in FP64, so only the sums round).
+template <int TRANS_B, typename T, typename Acc>
+__device__ __forceinline__ void block_fma(Acc (&acc)[16], const T (&a)[16], const T (&b)[16]) {
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
-        const double bv = TRANS_B ? b[c * 4 + m] : b[m * 4 + c];
-        acc[r * 4 + c] = fma(a[r * 4 + m], bv, acc[r * 4 + c]);
+        const T bv = TRANS_B ? b[c * 4 + m] : b[m * 4 + c];
+        acc[r * 4 + c] = fma((Acc)a[r * 4 + m], (Acc)bv, acc[r * 4 + c]);
       }
 }
 
+// One 4x4 block as 16-byte vector loads / stores (8 for FP64, 4 for FP32).
 __device__ __forceinline__ void load_block(double (&b)[16], const double* __restrict__ p) {
   const double2* q = reinterpret_cast<const double2*>(p);
 #pragma unroll
@@ -56,13 +60,70 @@ __device__ __forceinline__ void load_block(double (&b)[16], const double* __rest
   }
 }
 
-template <int TRANS_B, int STORE, int NDOT>
+__device__ __forceinline__ void load_block(float (&b)[16], const float* __restrict__ p) {
+  const float4* q = reinterpret_cast<const float4*>(p);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const float4 v = q[h];
+    b[4 * h] = v.x;
+    b[4 * h + 1] = v.y;
+    b[4 * h + 2] = v.z;
+    b[4 * h + 3] = v.w;
+  }
+}
+
+__device__ __forceinline__ void store_block(double* __restrict__ p, const double (&o)[16]) {
+  double2* q = reinterpret_cast<double2*>(p);
+#pragma unroll
+  for (int h = 0; h < 8; ++h) q[h] = make_double2(o[2 * h], o[2 * h + 1]);
+}
+
+__device__ __forceinline__ void store_block(float* __restrict__ p, const float (&o)[16]) {
+  float4* q = reinterpret_cast<float4*>(p);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) q[h] = make_float4(o[4 * h], o[4 * h + 1], o[4 * h + 2], o[4 * h + 3]);
+}
+
+// Epilogue of one output block: out = alpha acc + beta C_old, optional store,
+// and the FP64 trace contributions <m1, out>, <m2, out>.
+template <int STORE, int NDOT, typename T, typename Acc>
+__device__ __forceinline__ void finish_block(const Acc (&acc)[16], T* __restrict__ c_val,
+                                             size_t cp, double alpha, double beta,
+                                             const T* __restrict__ m1,
+                                             const T* __restrict__ m2, double& d1, double& d2) {
+  T out[16];
+  const Acc al = (Acc)alpha, be = (Acc)beta;
+  if (beta != 0.0) {
+    T old[16];
+    load_block(old, c_val + cp);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) out[e] = (T)(al * acc[e] + be * (Acc)old[e]);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 16; ++e) out[e] = (T)(al * acc[e]);
+  }
+  if (STORE) store_block(c_val + cp, out);
+  if (NDOT >= 1) {
+    T mv[16];
+    load_block(mv, m1 + cp);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) d1 = fma((double)mv[e], (double)out[e], d1);
+  }
+  if (NDOT >= 2) {
+    T mv[16];
+    load_block(mv, m2 + cp);
+#pragma unroll
+    for (int e = 0; e < 16; ++e) d2 = fma((double)mv[e], (double)out[e], d2);
+  }
+}
+
+template <int TRANS_B, int STORE, int NDOT, typename T, typename Acc>
 __global__ __launch_bounds__(256) void k_mul44(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ a_rp,
-    const int* __restrict__ a_col, const double* __restrict__ a_val,
-    const int* __restrict__ b_lut, const double* __restrict__ b_val,
-    const int* __restrict__ c_rp, const int* __restrict__ c_col, double* __restrict__ c_val,
-    double alpha, double beta, const double* __restrict__ m1, const double* __restrict__ m2,
+    const int* __restrict__ a_col, const T* __restrict__ a_val,
+    const int* __restrict__ b_lut, const T* __restrict__ b_val,
+    const int* __restrict__ c_rp, const int* __restrict__ c_col, T* __restrict__ c_val,
+    double alpha, double beta, const T* __restrict__ m1, const T* __restrict__ m2,
     double* __restrict__ partials, const double* __restrict__ skip, int k_lo, int k_hi) {
   if (skip != nullptr && *skip != 0.0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -94,11 +155,11 @@ __global__ __launch_bounds__(256) void k_mul44(
     t1 = lo;
   }
 
-  double acc[16];
+  Acc acc[16];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+  for (int e = 0; e < 16; ++e) acc[e] = 0;
 
-  double bA[16], bB[16], a[16];
+  T bA[16], bB[16], a[16];
   int pA = -1, pB = -1;
   if (act && t0 < t1) pA = lcol[(size_t)a_col[t0] * ns];
   if (act && t0 + 1 < t1) pB = lcol[(size_t)a_col[t0 + 1] * ns];
@@ -110,7 +171,7 @@ __global__ __launch_bounds__(256) void k_mul44(
     if (act && t + 2 < t1) pA2 = lcol[(size_t)a_col[t + 2] * ns];
     if (pB >= 0) load_block(bB, b_val + (size_t)pB * 16);
     {
-      const double* ap = a_val + (size_t)t * 16;
+      const T* ap = a_val + (size_t)t * 16;
 #pragma unroll
       for (int q = 0; q < 16; ++q) a[q] = ap[q];
       if (pA >= 0) block_fma<TRANS_B>(acc, a, bA);
@@ -121,7 +182,7 @@ __global__ __launch_bounds__(256) void k_mul44(
     if (act && t + 3 < t1) pB2 = lcol[(size_t)a_col[t + 3] * ns];
     if (pA2 >= 0) load_block(bA, b_val + (size_t)pA2 * 16);
     {
-      const double* ap = a_val + (size_t)(t + 1) * 16;
+      const T* ap = a_val + (size_t)(t + 1) * 16;
 #pragma unroll
       for (int q = 0; q < 16; ++q) a[q] = ap[q];
       if (pB >= 0) block_fma<TRANS_B>(acc, a, bB);
@@ -131,36 +192,7 @@ __global__ __launch_bounds__(256) void k_mul44(
   }
 
   double d1 = 0.0, d2 = 0.0;
-  if (act) {
-    const size_t cp = (size_t)(c0 + lane) * 16;
-    double out[16];
-    if (beta != 0.0) {
-      double old[16];
-      load_block(old, c_val + cp);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[e] + beta * old[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[e];
-    }
-    if (STORE) {
-      double2* q = reinterpret_cast<double2*>(c_val + cp);
-#pragma unroll
-      for (int h = 0; h < 8; ++h) q[h] = make_double2(out[2 * h], out[2 * h + 1]);
-    }
-    if (NDOT >= 1) {
-      double mv[16];
-      load_block(mv, m1 + cp);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) d1 = fma(mv[e], out[e], d1);
-    }
-    if (NDOT >= 2) {
-      double mv[16];
-      load_block(mv, m2 + cp);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) d2 = fma(mv[e], out[e], d2);
-    }
-  }
+  if (act) finish_block<STORE, NDOT>(acc, c_val, (size_t)(c0 + lane) * 16, alpha, beta, m1, m2, d1, d2);
   if (NDOT >= 1) {
     d1 = wave_sum(d1);
     if (NDOT >= 2) d2 = wave_sum(d2);
@@ -183,24 +215,24 @@ __global__ __launch_bounds__(256) void k_mul44(
 // A-side of one contraction step: the 4 rows' A blocks are wave-uniform; they
 // are fetched two rows at a time (64 scalar registers) so that two scalar
 // round trips, not four, are exposed per step.
-template <int G>
-__device__ __forceinline__ void cluster_fma(double (&acc)[4][16], const double (&b)[16],
+template <int G, typename T, typename Acc>
+__device__ __forceinline__ void cluster_fma(Acc (&acc)[4][16], const T (&b)[16],
                                             const int* __restrict__ apos,
-                                            const double* __restrict__ a_val, int g) {
+                                            const T* __restrict__ a_val, int g) {
   int pos[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) pos[r] = (G == 1 || g == 0) ? apos[r] : apos[4 + r];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int p0 = pos[2 * h], p1 = pos[2 * h + 1];
-    double a0[16], a1[16];
+    T a0[16], a1[16];
     if (p0 >= 0) {
-      const double* ap = a_val + (size_t)p0 * 16;
+      const T* ap = a_val + (size_t)p0 * 16;
 #pragma unroll
       for (int q = 0; q < 16; ++q) a0[q] = ap[q];
     }
     if (p1 >= 0) {
-      const double* ap = a_val + (size_t)p1 * 16;
+      const T* ap = a_val + (size_t)p1 * 16;
 #pragma unroll
       for (int q = 0; q < 16; ++q) a1[q] = ap[q];
     }
@@ -209,14 +241,14 @@ __device__ __forceinline__ void cluster_fma(double (&acc)[4][16], const double (
   }
 }
 
-template <int G, int STORE, int NDOT>
+template <int G, int STORE, int NDOT, typename T, typename Acc>
 __global__ __launch_bounds__(256) void k_mul44c(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
     const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
-    const double* __restrict__ a_val, const int* __restrict__ b_lut,
-    const double* __restrict__ b_val, const int* __restrict__ jc_ptr,
-    const int* __restrict__ jc_col, const int* __restrict__ jc_pos, double* __restrict__ c_val,
-    double alpha, double beta, const double* __restrict__ m1, const double* __restrict__ m2,
+    const T* __restrict__ a_val, const int* __restrict__ b_lut,
+    const T* __restrict__ b_val, const int* __restrict__ jc_ptr,
+    const int* __restrict__ jc_col, const int* __restrict__ jc_pos, T* __restrict__ c_val,
+    double alpha, double beta, const T* __restrict__ m1, const T* __restrict__ m2,
     double* __restrict__ partials, const double* __restrict__ skip) {
   constexpr int M = 4 * G;
   constexpr int COLS = kWave / G;
@@ -238,15 +270,15 @@ __global__ __launch_bounds__(256) void k_mul44c(
   const size_t ns = (size_t)n;
   const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
 
-  double acc[4][16];
+  Acc acc[4][16];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[r][e] = 0.0;
+    for (int e = 0; e < 16; ++e) acc[r][e] = 0;
 
   // three rotating B buffers: while step t is consumed, the blocks of steps
   // t+1 and t+2 are in flight; block indices run three steps ahead
-  double b0[16], b1[16], b2[16];
+  T b0[16], b1[16], b2[16];
   int p[3] = {-1, -1, -1};
   int pn = -1;
 #pragma unroll
@@ -281,37 +313,9 @@ __global__ __launch_bounds__(256) void k_mul44c(
 
   double d1 = 0.0, d2 = 0.0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    if (opos[r] < 0) continue;
-    const size_t cp = (size_t)opos[r] * 16;
-    double out[16];
-    if (beta != 0.0) {
-      double old[16];
-      load_block(old, c_val + cp);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[r][e] + beta * old[e];
-    } else {
-#pragma unroll
-      for (int e = 0; e < 16; ++e) out[e] = alpha * acc[r][e];
-    }
-    if (STORE) {
-      double2* qq = reinterpret_cast<double2*>(c_val + cp);
-#pragma unroll
-      for (int h = 0; h < 8; ++h) qq[h] = make_double2(out[2 * h], out[2 * h + 1]);
-    }
-    if (NDOT >= 1) {
-      double mv[16];
-      load_block(mv, m1 + cp);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) d1 = fma(mv[e], out[e], d1);
-    }
-    if (NDOT >= 2) {
-      double mv[16];
-      load_block(mv, m2 + cp);
-#pragma unroll
-      for (int e = 0; e < 16; ++e) d2 = fma(mv[e], out[e], d2);
-    }
-  }
+  for (int r = 0; r < 4; ++r)
+    if (opos[r] >= 0)
+      finish_block<STORE, NDOT>(acc[r], c_val, (size_t)opos[r] * 16, alpha, beta, m1, m2, d1, d2);
   if (NDOT >= 1) {
     d1 = wave_sum(d1);
     if (NDOT >= 2) d2 = wave_sum(d2);
@@ -322,36 +326,36 @@ __global__ __launch_bounds__(256) void k_mul44c(
   }
 }
 
-using KernelCFn = void (*)(int, int, const int*, const int*, const int*, const int*,
-                           const double*, const int*, const double*, const int*, const int*,
-                           const int*, double*, double, double, const double*, const double*,
-                           double*, const double*);
+template <typename T>
+using KernelCFn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
+                           const int*, const T*, const int*, const int*, const int*, T*, double,
+                           double, const T*, const T*, double*, const double*);
 
-template <int G>
-KernelCFn pick_c(int store, int ndot) {
+template <int G, typename T, typename Acc>
+KernelCFn<T> pick_c(int store, int ndot) {
   if (store) {
-    if (ndot == 0) return k_mul44c<G, 1, 0>;
-    if (ndot == 1) return k_mul44c<G, 1, 1>;
-    return k_mul44c<G, 1, 2>;
+    if (ndot == 0) return k_mul44c<G, 1, 0, T, Acc>;
+    if (ndot == 1) return k_mul44c<G, 1, 1, T, Acc>;
+    return k_mul44c<G, 1, 2, T, Acc>;
   }
-  if (ndot == 1) return k_mul44c<G, 0, 1>;
-  return k_mul44c<G, 0, 2>;
+  if (ndot == 1) return k_mul44c<G, 0, 1, T, Acc>;
+  return k_mul44c<G, 0, 2, T, Acc>;
 }
 
-using KernelFn = void (*)(int, int, const int*, const int*, const int*, const double*,
-                          const int*, const double*, const int*, const int*, double*, double,
-                          double, const double*, const double*, double*, const double*, int,
-                          int);
+template <typename T>
+using KernelFn = void (*)(int, int, const int*, const int*, const int*, const T*, const int*,
+                          const T*, const int*, const int*, T*, double, double, const T*,
+                          const T*, double*, const double*, int, int);
 
-template <int TB>
-KernelFn pick_store(int store, int ndot) {
+template <int TB, typename T, typename Acc>
+KernelFn<T> pick_store(int store, int ndot) {
   if (store) {
-    if (ndot == 0) return k_mul44<TB, 1, 0>;
-    if (ndot == 1) return k_mul44<TB, 1, 1>;
-    return k_mul44<TB, 1, 2>;
+    if (ndot == 0) return k_mul44<TB, 1, 0, T, Acc>;
+    if (ndot == 1) return k_mul44<TB, 1, 1, T, Acc>;
+    return k_mul44<TB, 1, 2, T, Acc>;
   }
-  if (ndot == 1) return k_mul44<TB, 0, 1>;
-  return k_mul44<TB, 0, 2>;
+  if (ndot == 1) return k_mul44<TB, 0, 1, T, Acc>;
+  return k_mul44<TB, 0, 2, T, Acc>;
 }
 
 // ------------------------------------------------------------------ timing
@@ -377,6 +381,7 @@ int timer_begin(hipStream_t s, hipEvent_t* stop) {
 }
 
 int g_kslab_override = -1;  // < 0: automatic
+int g_f32_acc = LNV_ACC_F32;  // accumulation of the FP32 products
 
 // Number of contraction slabs (atom-index ranges of k, one launch each,
 // accumulating into C).  Atoms numbered cell by cell make an index range a
@@ -402,34 +407,30 @@ int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bs
   return use_clustered(A, B, transB, C) ? C->pat->n_cl_items : C->pat->n_items;
 }
 
-int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
-                    double beta, const lnv_bsm* C, int store, const double* m1,
-                    const double* m2, double* partials, const double* skip,
-                    hipStream_t s) {
-  if (!bsm_ok(A) || !bsm_ok(B) || !bsm_ok(C)) return LNV_EINVAL;
-  if (A->blk != 4 || B->blk != 4 || C->blk != 4) return LNV_EUNSUPPORTED;
-  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
-  if (pa->n != pb->n || pa->n != pc->n) return LNV_EPATTERN;
-  if (!pa->row_ptr || !pa->col || !pc->row_ptr || !pc->col || !pc->items) return LNV_EPATTERN;
-  const int32_t* lut = transB ? pb->lut_t : pb->lut;
-  if (!lut) return LNV_EPATTERN;
-  const int ndot = m2 ? 2 : (m1 ? 1 : 0);
-  if (m2 && !m1) return LNV_EINVAL;
-  if (ndot > 0 && !partials) return LNV_EINVAL;
-  if (!store && ndot == 0) return LNV_EINVAL;
+namespace {
+
+template <typename T, typename Acc>
+int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, double beta,
+                 const lnv_bsm* C, int store, const void* m1v, const void* m2v,
+                 double* partials, const double* skip, int ndot, const int32_t* lut,
+                 hipStream_t s) {
+  const lnv_pattern *pa = A->pat, *pc = C->pat;
+  const T* av = static_cast<const T*>(A->val);
+  const T* bv = static_cast<const T*>(B->val);
+  T* cv = static_cast<T*>(C->val);
+  const T* m1 = static_cast<const T*>(m1v);
+  const T* m2 = static_cast<const T*>(m2v);
   const int nslab = kslabs_for(B);
-  const bool clustered = use_clustered(A, B, transB, C);
-  if (clustered) {
+  if (use_clustered(A, B, transB, C)) {
     if (pc->n_cl_items == 0) return LNV_OK;
     const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
     hipEvent_t stop = nullptr;
     LNV_TRY(timer_begin(s, &stop));
-    KernelCFn fn = pc->cl_g == 2 ? pick_c<2>(store, ndot) : pick_c<1>(store, ndot);
+    KernelCFn<T> fn =
+        pc->cl_g == 2 ? pick_c<2, T, Acc>(store, ndot) : pick_c<1, T, Acc>(store, ndot);
     fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
-                           pa->cl_pos, static_cast<const double*>(A->val), lut,
-                           static_cast<const double*>(B->val), pc->cl_ptr, pc->cl_col,
-                           pc->cl_pos, static_cast<double*>(C->val), alpha, beta, m1, m2,
-                           partials, skip);
+                           pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
+                           alpha, beta, m1, m2, partials, skip);
     LNV_LAUNCH_CHECK();
     if (stop) LNV_HIP(hipEventRecord(stop, s));
     return LNV_OK;
@@ -446,16 +447,43 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
     const int k_lo = (int)((int64_t)c * n / nslab), k_hi = (int)((int64_t)(c + 1) * n / nslab);
     const int st = last ? store : 1;
     const int nd = last ? ndot : 0;
-    KernelFn fn = transB ? pick_store<1>(st, nd) : pick_store<0>(st, nd);
-    fn<<<wgs, 256, 0, s>>>(n, pc->n_items, pc->items, pa->row_ptr, pa->col,
-                           static_cast<const double*>(A->val), lut,
-                           static_cast<const double*>(B->val), pc->row_ptr, pc->col,
-                           static_cast<double*>(C->val), alpha, c == 0 ? beta : 1.0, m1, m2,
+    KernelFn<T> fn = transB ? pick_store<1, T, Acc>(st, nd) : pick_store<0, T, Acc>(st, nd);
+    fn<<<wgs, 256, 0, s>>>(n, pc->n_items, pc->items, pa->row_ptr, pa->col, av, lut, bv,
+                           pc->row_ptr, pc->col, cv, alpha, c == 0 ? beta : 1.0, m1, m2,
                            partials, skip, k_lo, k_hi);
     LNV_LAUNCH_CHECK();
   }
   if (stop) LNV_HIP(hipEventRecord(stop, s));
   return LNV_OK;
+}
+
+}  // namespace
+
+int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
+                    double beta, const lnv_bsm* C, int store, const void* m1,
+                    const void* m2, double* partials, const double* skip,
+                    hipStream_t s) {
+  if (!bsm_ok_any(A) || !bsm_ok_any(B) || !bsm_ok_any(C)) return LNV_EINVAL;
+  if (A->dtype != C->dtype || B->dtype != C->dtype) return LNV_EUNSUPPORTED;
+  if (A->blk != 4 || B->blk != 4 || C->blk != 4) return LNV_EUNSUPPORTED;
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
+  if (pa->n != pb->n || pa->n != pc->n) return LNV_EPATTERN;
+  if (!pa->row_ptr || !pa->col || !pc->row_ptr || !pc->col || !pc->items) return LNV_EPATTERN;
+  const int32_t* lut = transB ? pb->lut_t : pb->lut;
+  if (!lut) return LNV_EPATTERN;
+  const int ndot = m2 ? 2 : (m1 ? 1 : 0);
+  if (m2 && !m1) return LNV_EINVAL;
+  if (ndot > 0 && !partials) return LNV_EINVAL;
+  if (!store && ndot == 0) return LNV_EINVAL;
+  if (C->dtype == LNV_F32) {
+    if (g_f32_acc == LNV_ACC_F64)
+      return launch_typed<float, double>(alpha, A, B, transB, beta, C, store, m1, m2, partials,
+                                         skip, ndot, lut, s);
+    return launch_typed<float, float>(alpha, A, B, transB, beta, C, store, m1, m2, partials,
+                                      skip, ndot, lut, s);
+  }
+  return launch_typed<double, double>(alpha, A, B, transB, beta, C, store, m1, m2, partials,
+                                      skip, ndot, lut, s);
 }
 
 }  // namespace lnv
@@ -466,6 +494,12 @@ extern "C" int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B
                                 int32_t transB, double beta, lnv_bsm* C, hipStream_t s) {
   return multiply_launch(alpha, A, B, transB, beta, C, 1, nullptr, nullptr, nullptr, nullptr,
                          s);
+}
+
+extern "C" int lnv_set_f32_accumulation(int32_t acc) {
+  if (acc != LNV_ACC_F32 && acc != LNV_ACC_F64) return LNV_EINVAL;
+  g_f32_acc = acc;
+  return LNV_OK;
 }
 
 extern "C" int lnv_set_kslabs(int32_t n) {

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "liblnv.so")
 # status codes (lnv_status)
 OK, EINVAL, ECAPACITY, EPATTERN, EHIP, ENUMERIC, EUNSUPPORTED = range(7)
 F64 = 0
+F32 = 1
 DOT_PARTIALS = 1024
 NSLOTS = 12
 
@@ -54,6 +55,13 @@ class LnvCgWs(ctypes.Structure):
                 ("D_prev", c_void_p)]
 
 
+class LnvEval32Ws(ctypes.Structure):
+    _fields_ = [("L", LnvBsm), ("S", LnvBsm), ("H", LnvBsm), ("SL", LnvBsm), ("LS", LnvBsm),
+                ("X", LnvBsm), ("XT", LnvBsm), ("Z", LnvBsm), ("perm_SL", c_void_p),
+                ("perm_X", c_void_p), ("YT", c_void_p), ("W", c_void_p), ("V", c_void_p),
+                ("partials", c_void_p), ("partials_len", c_int64), ("scalars", c_void_p)]
+
+
 class LnvAdjWs(ctypes.Structure):
     _fields_ = [("SL", LnvBsm), ("LSL", LnvBsm), ("HL", LnvBsm), ("YS", c_void_p)]
 
@@ -89,12 +97,16 @@ SIGNATURES = {
     "lnv_bsm_dot": (c_int, [PBsm, PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_partials_len": (c_int64, [c_int32]),
     "lnv_eval": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, c_void_p, POINTER(LnvEvalWs), c_void_p]),
+    "lnv_eval_mixed": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, c_void_p, POINTER(LnvEval32Ws),
+                               c_void_p]),
+    "lnv_bsm_convert": (c_int, [PBsm, PBsm, c_void_p]),
     "lnv_adjoint": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, POINTER(LnvAdjWs), c_void_p]),
     "lnv_hotelling": (c_int, [PBsm, PBsm, c_int32, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
                             POINTER(LnvCgWs), c_void_p]),
     "lnv_set_kslabs": (c_int, [c_int32]),
+    "lnv_set_f32_accumulation": (c_int, [c_int32]),
     "lnv_timing_enable": (c_int, [c_int32]),
     "lnv_timing_read": (c_int, [POINTER(c_double), POINTER(c_int64)]),
     "lnv_timing_reset": (c_int, []),

@@ -145,23 +145,27 @@ def product_pattern(A, B, mask=None, triples=True):
 
 
 class Matrix:
-    """Block values on a pattern: tensor [nnzb, 4, 4] float64 plus lnv_bsm."""
+    """Block values on a pattern: tensor [nnzb, 4, 4] (float64, or float32 for
+    the mixed-precision products) plus lnv_bsm."""
 
-    def __init__(self, pattern, values=None):
+    def __init__(self, pattern, values=None, dtype=torch.float64):
         self.pat = pattern
         if values is None:
-            values = torch.zeros(max(1, pattern.nnzb), BLK, BLK, dtype=torch.float64,
+            values = torch.zeros(max(1, pattern.nnzb), BLK, BLK, dtype=dtype,
                                  device=pattern.row_ptr.device)
+        if values.dtype not in (torch.float64, torch.float32):
+            raise ValueError("block values must be float64 or float32")
         self.val = values
         self.struct = L_.LnvBsm()
         self.struct.pat = ctypes.pointer(pattern.struct)
         self.struct.blk = BLK
-        self.struct.dtype = L_.F64
+        self.struct.dtype = L_.F32 if values.dtype == torch.float32 else L_.F64
         self.struct.val = values.data_ptr()
 
     def rebind(self, values):
         self.val = values
         self.struct.val = values.data_ptr()
+        self.struct.dtype = L_.F32 if values.dtype == torch.float32 else L_.F64
         return self
 
 
@@ -353,7 +357,45 @@ class LNVSystem:
         self.k = 0
         self.cluster = cluster
         self.adj_ws = None
+        self.ws32 = None
         torch.cuda.synchronize()
+
+    # ----------------------------------------------------------- mixed precision
+    def mixed_setup(self):
+        """FP32 copies of L, S, H and FP32 intermediates for lnv_eval_mixed
+        (same patterns, tables and transpose maps as the FP64 evaluation)."""
+        if self.ws32 is not None:
+            return
+
+        def f32(pat):
+            return Matrix(pat, dtype=torch.float32)
+
+        self.L32, self.S32, self.H32 = f32(self.pL), f32(self.pS), f32(self.pH)
+        self.SL32, self.LS32 = f32(self.pSL), f32(self.pLS)
+        self.X32, self.XT32, self.Z32 = f32(self.pX), f32(self.pXT), f32(self.pZ)
+        nL = self.pL.nnzb
+        self.YT32, self.W32, self.V32 = (torch.zeros(nL, BLK, BLK, dtype=torch.float32,
+                                                     device=self.dev) for _ in range(3))
+        ws = L_.LnvEval32Ws()
+        ws.L, ws.S, ws.H = self.L32.struct, self.S32.struct, self.H32.struct
+        ws.SL, ws.LS = self.SL32.struct, self.LS32.struct
+        ws.X, ws.XT, ws.Z = self.X32.struct, self.XT32.struct, self.Z32.struct
+        ws.perm_SL, ws.perm_X = self.perm_SL.data_ptr(), self.perm_X.data_ptr()
+        ws.YT, ws.W, ws.V = self.YT32.data_ptr(), self.W32.data_ptr(), self.V32.data_ptr()
+        ws.partials = self.partials.data_ptr()
+        ws.partials_len = self.ws.ev.partials_len
+        ws.scalars = self.scalars.data_ptr()
+        self.ws32 = ws
+        torch.cuda.synchronize()
+
+    def eval_mixed(self):
+        """lnv_eval_mixed at the current L: FP32 products, FP64 assembly and
+        traces; writes G, F, EN like eval()."""
+        self.mixed_setup()
+        L_.call("lnv_eval_mixed", byref(self.L.struct), byref(self.S.struct),
+                byref(self.H.struct), byref(self.G.struct), byref(self.F.struct), _ptr(self.EN),
+                byref(self.ws32), _stream())
+        return self.EN
 
     # ----------------------------------------------------------- adjoint set-up
     def adjoint_setup(self):

@@ -80,14 +80,14 @@ def test_struct_layouts_match_header(tmp_path):
         pytest.skip("gcc or ROCm headers not available")
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include "lnv.h"\n'
-                   'int main(){printf("%zu %zu %zu %zu %zu %zu", sizeof(lnv_pattern), sizeof(lnv_bsm),'
+                   'int main(){printf("%zu %zu %zu %zu %zu %zu %zu", sizeof(lnv_pattern), sizeof(lnv_bsm),'
                    ' sizeof(lnv_eval_ws), sizeof(lnv_cg_ws), sizeof(lnv_opts),'
-                   ' sizeof(lnv_adj_ws)); return 0;}\n')
+                   ' sizeof(lnv_adj_ws), sizeof(lnv_eval32_ws)); return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
                     "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
                                           check=True).stdout.split()]
     want = [ctypes.sizeof(x) for x in (L.LnvPattern, L.LnvBsm, L.LnvEvalWs, L.LnvCgWs, L.LnvOpts,
-                                           L.LnvAdjWs)]
+                                           L.LnvAdjWs, L.LnvEval32Ws)]
     assert got == want

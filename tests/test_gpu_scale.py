@@ -102,3 +102,41 @@ def test_cg_step_at_scale_properties(gpu):
         assert abs(h[k]["N"] - w.n_elec) <= 1e-9 * w.n_elec, (k, h[k]["N"])
     assert int(h[1]["STATUS"]) == 0
     assert [r["E"] for r in runs[0]] == [r["E"] for r in runs[1]]
+
+
+@pytest.mark.parametrize("acc", [0, 1], ids=["acc32", "acc64"])
+def test_eval_mixed_against_fp64_at_scale(gpu, acc):
+    """Mixed-precision evaluation (FP32 products, FP64 traces) against the FP64
+    path at the 4096-atom cell, at L0 and at the L of one CG step: the energy
+    within 1e-6 Ha/atom (the FP64 path itself is pinned to the oracle above);
+    N, G, F within 3 sqrt(k) u relative, k the longest contraction (the FP32
+    summation error of one entry)."""
+    from paper_2002_07704_amd import lib as L
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.get("si4096_4x4")
+    s = LNVSystem(w)
+    k = 4 * int(np.diff(s.pSL.row_ptr.cpu().numpy()).max())
+    tol = 3.0 * np.sqrt(k) * 2.0 ** -24
+    L.call("lnv_set_f32_accumulation", acc)
+    try:
+        s.cg_init()
+        for step in range(2):
+            if step == 1:
+                s.cg_step()
+            s.eval()
+            torch.cuda.synchronize()
+            E64, N64 = (float(x) for x in s.EN.cpu())
+            G64, F64 = s.G.val.clone(), s.F.val.clone()
+            s.eval_mixed()
+            torch.cuda.synchronize()
+            E32, N32 = (float(x) for x in s.EN.cpu())
+            eG = float(torch.linalg.vector_norm(s.G.val - G64) / torch.linalg.vector_norm(G64))
+            eF = float(torch.linalg.vector_norm(s.F.val - F64) / torch.linalg.vector_norm(F64))
+            print(f"acc{32 * (acc + 1)} step {step}: |dE|/atom {abs(E32 - E64) / w.n:.2e} "
+                  f"|dN|/N {abs(N32 - N64) / N64:.2e} |dG|/|G| {eG:.2e} |dF|/|F| {eF:.2e} "
+                  f"(bound {tol:.1e})", flush=True)
+            assert abs(E32 - E64) / w.n <= 1e-6
+            assert abs(N32 - N64) <= tol * N64
+            assert eG <= tol and eF <= tol
+    finally:
+        L.call("lnv_set_f32_accumulation", 0)
