@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="copy COPY_BYTES (counter calibration), then the timed steps only")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--markers", action="store_true",
+                    help="launch a short spin kernel before the timed steps and after the "
+                         "event-timed steps, so a kernel trace can be cut to them")
     args = ap.parse_args()
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.traffic_json, args.workload)
@@ -177,6 +180,9 @@ def main():
         print(json.dumps({"pmc_probe": True, "steps": args.steps}), flush=True)
         return
 
+    if args.markers:
+        torch.cuda._sleep(1000)
+        torch.cuda.synchronize()
     # timed steps (no per-kernel events)
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -197,6 +203,9 @@ def main():
         step()
     torch.cuda.synchronize()
     lib.lnv_timing_enable(0)
+    if args.markers:
+        torch.cuda._sleep(1000)
+        torch.cuda.synchronize()
     import ctypes
     ms_tot = ctypes.c_double(0.0)
     launches = ctypes.c_int64(0)
