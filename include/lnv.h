@@ -192,12 +192,21 @@ int lnv_pattern_items(const lnv_pattern* P, int32_t* items, int64_t cap,
  * scale*(u - 0.5), u = (SplitMix64 output number ctr of seed >> 11) * 2^-53,
  * ctr = stream<<56 | i<<32 | j<<8 | e (stream 1 for S, 2 for H); M_ji = M_ij^T
  * and diagonal blocks are (R + R^T) * 0.5.  Support functions per atom come
- * from nfun (device [n], NULL: every atom has M->blk); entries of a padded
- * block beyond nfun are zero.
+ * from nfun (device, indexed by atom; NULL: every atom has M->blk); entries
+ * of a block beyond nfun are zero.
+ * Atoms with more support functions than blk (9 or 13 with blk 4) span
+ * several stored rows: with atom_of / off_of (device [n], both or neither)
+ * stored row i holds rows off_of[i] .. off_of[i]+blk-1 of atom atom_of[i]'s
+ * functions, pos is then per stored row (the atom's position repeated), and
+ * the counters above use the atom pair and the element's index in the atom
+ * block, so the values do not depend on the split.  Such padded rows and
+ * columns are zero in S and H; the CG's identity and Hotelling start leave
+ * them at zero (see lnv_cg_init).
  */
 int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
-                     const lnv_bsm* M, int32_t kind, double R, double decay,
-                     uint64_t seed, double scale, hipStream_t s);
+                     const int32_t* atom_of, const int32_t* off_of, const lnv_bsm* M,
+                     int32_t kind, double R, double decay, uint64_t seed, double scale,
+                     hipStream_t s);
 
 /* ------------------------------------------------------------ a3: multiply
  * lnv_bsm_multiply -- C = alpha * A * op(B) + beta * C on C's pattern only
@@ -415,6 +424,7 @@ typedef struct lnv_opts {
 
 /*
  * lnv_hotelling -- sparse approximate inverse of the overlap on T's pattern,
+ * (identity of the orbitals present, as in lnv_cg_init; S's pattern needs lut),
  * the metric of the minimisation (Sec. II.C.2 uses an approximate sparse
  * S^-1 from Hotelling's iteration):  T0 = sigma I with
  * sigma = 1 / max_a sum_b |S_ab| (a Gershgorin bound, so ||I - T0 S|| < 1),
@@ -429,7 +439,10 @@ int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, h
  * lambda the smallest positive real root of N(lambda T) = n_elec, a cubic in
  * lambda (6 Tr[TSTS] l^2 - 4 Tr[TSTSTS] l^3 = n_elec).  The paper starts
  * from a generalised McWeeny purification of H; the scaled metric is the
- * start used here.  Writes L and scalars[LNV_SC_LAMBDA].
+ * start used here.  Writes L and scalars[LNV_SC_LAMBDA].  The identity is
+ * that of the orbitals present: diagonal entries whose S_aa is zero (padded
+ * rows, see lnv_synth_blocks) are left at zero, and so stay zero through the
+ * CG (their gradient vanishes).  S's pattern needs lut.
  */
 int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, lnv_cg_ws* ws,
                 hipStream_t s);

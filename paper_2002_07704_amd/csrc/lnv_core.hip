@@ -433,10 +433,16 @@ __global__ __launch_bounds__(256) void k_hprime(int n, const int* __restrict__ i
   }
 }
 
-// Identity blocks on the diagonal of L's pattern, zero elsewhere.
-__global__ __launch_bounds__(256) void k_identity(const int* __restrict__ items,
+// v * I on the diagonal of L's pattern, zero elsewhere.  The identity is that
+// of the orbitals present: a diagonal entry whose S_aa is zero (a padded
+// row of an atom split over several stored rows) stays zero, so the
+// minimisation never moves such rows.  v = sc[idx] (sc == nullptr: 1).
+__global__ __launch_bounds__(256) void k_identity(int n, const int* __restrict__ items,
                                                   const int* __restrict__ rp,
                                                   const int* __restrict__ col,
+                                                  const int* __restrict__ s_lut,
+                                                  const double* __restrict__ S,
+                                                  const double* __restrict__ sc, int idx,
                                                   double* __restrict__ D) {
   const int item = blockIdx.x;
   const int i = items[2 * item], c0 = items[2 * item + 1];
@@ -445,8 +451,15 @@ __global__ __launch_bounds__(256) void k_identity(const int* __restrict__ items,
   if (b >= cnt) return;
   const int p = c0 + b;
   const bool diag = col[p] == i;
+  const double v = sc ? sc[idx] : 1.0;
+  bool present = false;
+  if (diag) {
+    const int q = s_lut[(size_t)i * n + i];
+    present = q >= 0 && S[(size_t)q * 16 + r * 5] != 0.0;
+  }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) D[(size_t)p * 16 + r * 4 + c] = (diag && r == c) ? 1.0 : 0.0;
+  for (int c = 0; c < 4; ++c)
+    D[(size_t)p * 16 + r * 4 + c] = (present && r == c) ? v : 0.0;
 }
 
 // AT[perm[p]] = A[p]^T for the blocks of item q of A's pattern.
@@ -564,22 +577,6 @@ __global__ __launch_bounds__(256) void k_rowabs(const int* __restrict__ rp,
 }
 
 // sc[idx] * I on the diagonal blocks of a pattern
-__global__ __launch_bounds__(256) void k_identity_scaled(const int* __restrict__ items,
-                                                         const int* __restrict__ rp,
-                                                         const int* __restrict__ col,
-                                                         const double* __restrict__ sc, int idx,
-                                                         double* __restrict__ D) {
-  const int item = blockIdx.x;
-  const int i = items[2 * item], c0 = items[2 * item + 1];
-  const int cnt = min(kWave, rp[i + 1] - c0);
-  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
-  if (b >= cnt) return;
-  const int p = c0 + b;
-  const bool diag = col[p] == i;
-  const double v = sc[idx];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) D[(size_t)p * 16 + r * 4 + c] = (diag && r == c) ? v : 0.0;
-}
 
 // D = -g_c + beta D_prev; partial <D, F>
 __global__ __launch_bounds__(256) void k_vec_dir(int64_t nv, const double* __restrict__ g,
@@ -1016,7 +1013,7 @@ extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_c
   if (!ws->Gc || !ev.partials || !ev.scalars || !bsm_ok(&ev.SL)) return LNV_EINVAL;
   const lnv_pattern* pt = T->pat;
   if (S->pat->n != pt->n || ev.SL.pat->n != pt->n) return LNV_EPATTERN;
-  if (!pattern_ready(pt, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
+  if (!pattern_ready(pt, true, false, true) || !pattern_ready(S->pat, true, false, false) ||
       !pattern_ready(ev.SL.pat, true, false, true))
     return LNV_EPATTERN;
   if (ev.partials_len < pt->n) return LNV_EINVAL;
@@ -1029,8 +1026,9 @@ extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_c
   add(rl, 0, S->pat->n, 1, LNV_SC_T4, 1);
   StageArgs sa{};
   LNV_TRY(scalar_stage(part, rl, sc, ST_SIGMA, sa, s));
-  k_identity_scaled<<<pt->n_items, 256, 0, s>>>(pt->items, pt->row_ptr, pt->col, sc,
-                                                LNV_SC_SIGMA, static_cast<double*>(T->val));
+  k_identity<<<pt->n_items, 256, 0, s>>>(pt->n, pt->items, pt->row_ptr, pt->col, S->pat->lut,
+                                         static_cast<const double*>(S->val), sc, LNV_SC_SIGMA,
+                                         static_cast<double*>(T->val));
   LNV_LAUNCH_CHECK();
   // T_{n+1} = 2 T_n - T_n (S T_n) on T's pattern; ST lives on pat(S.T)
   lnv_bsm ST{ev.SL.pat, 4, LNV_F64, ev.SL.val};
@@ -1058,7 +1056,8 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   if (!bsm_ok(&ev.SL) || !bsm_ok(&ev.LS) || !bsm_ok(&ev.X) || !bsm_ok(&ev.Z) || !ev.perm_SL)
     return LNV_EINVAL;
   if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(ev.SL.pat, false, false, true) ||
-      !pattern_ready(ev.LS.pat, true, false, false) || !pattern_ready(ev.Z.pat, true, false, true))
+      !pattern_ready(ev.LS.pat, true, false, false) || !pattern_ready(ev.Z.pat, true, false, true) ||
+      !pattern_ready(S->pat, true, false, false))
     return LNV_EPATTERN;
   if (T && (!bsm_ok(T) || T->pat != L->pat || T->blk != 4)) return LNV_EPATTERN;
   if (ev.partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
@@ -1079,7 +1078,8 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   if (T) {
     LNV_HIP(hipMemcpyAsync(ws->D, T->val, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
   } else {
-    k_identity<<<ni, 256, 0, s>>>(pl->items, pl->row_ptr, pl->col, ws->D);
+    k_identity<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, S->pat->lut,
+                                  static_cast<const double*>(S->val), nullptr, 0, ws->D);
     LNV_LAUNCH_CHECK();
   }
   // N(lambda T) = 6 Tr[TSTS] lambda^2 - 4 Tr[TSTSTS] lambda^3 at L = 0:

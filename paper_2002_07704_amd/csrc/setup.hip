@@ -308,9 +308,17 @@ __device__ __forceinline__ double rand_entry(uint64_t seed, uint64_t stream, uin
   return scale * (u - 0.5);
 }
 
+// Row i of the stored matrix is rows off_of[i] .. off_of[i]+blk-1 of atom
+// atom_of[i]'s block (identity maps when atom_of is null): an atom with more
+// support functions than blk spans several stored rows, and entries past the
+// atom's function count are zero.  The random entries are keyed by the atom
+// pair and the element's index in the atom block, so the values do not depend
+// on how atoms are split into stored rows.
 __global__ __launch_bounds__(128) void k_synth(const double* __restrict__ pos, double bx,
                                                double by, double bz,
-                                               const int* __restrict__ nfun, int blk,
+                                               const int* __restrict__ nfun,
+                                               const int* __restrict__ atom_of,
+                                               const int* __restrict__ off_of, int blk,
                                                const int* __restrict__ rp,
                                                const int* __restrict__ col,
                                                double* __restrict__ val, int kind, double R2,
@@ -319,10 +327,14 @@ __global__ __launch_bounds__(128) void k_synth(const double* __restrict__ pos, d
 #pragma clang fp contract(off)
   const int i = blockIdx.x;
   const uint64_t stream = kind == 0 ? 1ull : 2ull;
-  const int ni = nfun ? nfun[i] : blk;
+  const int ai = atom_of ? atom_of[i] : i;
+  const int oi = off_of ? off_of[i] : 0;
+  const int ni = nfun ? nfun[ai] : blk;
   for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 128) {
     const int j = col[p];
-    const int nj = nfun ? nfun[j] : blk;
+    const int aj = atom_of ? atom_of[j] : j;
+    const int oj = off_of ? off_of[j] : 0;
+    const int nj = nfun ? nfun[aj] : blk;
     const double dx = pos[3 * j] - pos[3 * i];
     const double dy = pos[3 * j + 1] - pos[3 * i + 1];
     const double dz = pos[3 * j + 2] - pos[3 * i + 2];
@@ -340,21 +352,22 @@ __global__ __launch_bounds__(128) void k_synth(const double* __restrict__ pos, d
     double* out = val + (size_t)p * blk * blk;
     for (int r = 0; r < blk; ++r)
       for (int c = 0; c < blk; ++c) {
+        const int R = oi + r, C = oj + c;  // element of the atom block
         double v = 0.0;
-        if (r < ni && c < nj) {
+        if (R < ni && C < nj) {
           double m;
-          if (i == j) {
-            const double a = rand_entry(seed, stream, i, i, r * ni + c, scale);
-            const double b = rand_entry(seed, stream, i, i, c * ni + r, scale);
+          if (ai == aj) {
+            const double a = rand_entry(seed, stream, ai, ai, R * ni + C, scale);
+            const double b = rand_entry(seed, stream, ai, ai, C * ni + R, scale);
             m = (a + b) * 0.5;
-          } else if (i < j) {
-            m = rand_entry(seed, stream, i, j, r * nj + c, scale);
+          } else if (ai < aj) {
+            m = rand_entry(seed, stream, ai, aj, R * nj + C, scale);
           } else {
-            m = rand_entry(seed, stream, j, i, c * ni + r, scale);
+            m = rand_entry(seed, stream, aj, ai, C * ni + R, scale);
           }
           const double wm = w * m;
           if (kind == 0)
-            v = (i == j && r == c) ? wm + 2.0 : wm;
+            v = (ai == aj && R == C) ? wm + 2.0 : wm;
           else
             v = -wm;
         }
@@ -492,19 +505,22 @@ extern "C" int lnv_pattern_items(const lnv_pattern* P, int32_t* items, int64_t c
 }
 
 extern "C" int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
-                                const lnv_bsm* M, int32_t kind, double R, double decay,
-                                uint64_t seed, double scale, hipStream_t s) {
+                                const int32_t* atom_of, const int32_t* off_of, const lnv_bsm* M,
+                                int32_t kind, double R, double decay, uint64_t seed,
+                                double scale, hipStream_t s) {
   if (!pos || !box || !bsm_ok(M) || (kind != 0 && kind != 1) || !(R >= 0.0) ||
       !(decay > 0.0))
     return LNV_EINVAL;
   if (!M->pat->row_ptr || !M->pat->col) return LNV_EPATTERN;
   if (M->blk <= 0 || M->blk > 16) return LNV_EUNSUPPORTED;
+  if ((atom_of == nullptr) != (off_of == nullptr)) return LNV_EINVAL;
   const int n = M->pat->n;
   if (n >= (1 << 24)) return LNV_EUNSUPPORTED;  // counter layout: 24-bit atom ids
   const int mx = (int)std::ceil(R / box[0]) + 1;
   const int my = (int)std::ceil(R / box[1]) + 1;
   const int mz = (int)std::ceil(R / box[2]) + 1;
-  k_synth<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, M->blk, M->pat->row_ptr,
+  k_synth<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, atom_of, off_of, M->blk,
+                            M->pat->row_ptr,
                             M->pat->col, static_cast<double*>(M->val), kind, R * R, decay,
                             mx, my, mz, seed, scale);
   LNV_LAUNCH_CHECK();

@@ -89,8 +89,8 @@ SIGNATURES = {
                                     c_void_p, c_int64, POINTER(c_int64), POINTER(c_int32),
                                     c_void_p]),
     "lnv_bsm_transpose": (c_int, [PBsm, c_void_p, PBsm, c_void_p]),
-    "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, PBsm, c_int32, c_double,
-                                 c_double, c_uint64, c_double, c_void_p]),
+    "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, c_void_p, c_void_p, PBsm,
+                                 c_int32, c_double, c_double, c_uint64, c_double, c_void_p]),
     "lnv_bsm_multiply": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_void_p]),
     "lnv_bsm_multiply_dot": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_int32,
                                      PBsm, PBsm, c_void_p, c_void_p, c_void_p]),

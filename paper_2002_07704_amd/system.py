@@ -111,6 +111,19 @@ class Pattern:
         return self.row_ptr.cpu().numpy(), self.col.cpu().numpy()
 
 
+def split_rows(nfun, blk=BLK):
+    """Stored-row layout of atoms with nfun support functions in blk x blk
+    blocks: atom a spans ceil(nfun[a]/blk) consecutive rows; row i holds the
+    atom's functions off_of[i] .. off_of[i]+blk-1 (those past nfun[a] are
+    padding).  Returns (atom_of, off_of), int32 [n_rows]."""
+    nfun = np.asarray(nfun, dtype=np.int64)
+    nsub = (nfun + blk - 1) // blk
+    atom_of = np.repeat(np.arange(len(nfun)), nsub)
+    first = np.repeat(np.cumsum(nsub) - nsub, nsub)
+    off_of = (np.arange(int(nsub.sum())) - first) * blk
+    return atom_of.astype(np.int32), off_of.astype(np.int32)
+
+
 def neighbours(pos_dev, box, R):
     """a0: range pattern for cutoff R (lnv_neighbours, two-phase)."""
     n = pos_dev.shape[0]
@@ -229,16 +242,27 @@ class LNVSystem:
         if not torch.cuda.is_available():
             raise RuntimeError("LNVSystem needs a GPU (HIP device)")
         L_.load()
-        if int(np.max(w.nfun)) != BLK or int(np.min(w.nfun)) != BLK:
-            raise NotImplementedError("the FP64 path takes 4 support functions per atom")
         self.w = w
         self.n = w.n
         self.n_elec = float(w.n_elec)
         self.R_L = float(w.R_L if R_L is None else R_L)
         dev = torch.device(device)
         self.dev = dev
-        self.pos = torch.as_tensor(np.ascontiguousarray(w.pos), dtype=torch.float64, device=dev)
         self.box = [float(b) for b in w.box]
+        nfun = np.asarray(w.nfun, dtype=np.int32)
+        # atoms with other than 4 support functions span several 4x4-blocked rows
+        self.split = bool(np.any(nfun != BLK))
+        if self.split:
+            atom_of, off_of = split_rows(nfun)
+            self.atom_of = torch.as_tensor(atom_of, device=dev)
+            self.off_of = torch.as_tensor(off_of, device=dev)
+            self.nfun = torch.as_tensor(nfun, device=dev)
+            pos_rows = np.ascontiguousarray(w.pos[atom_of])
+        else:
+            self.atom_of = self.off_of = self.nfun = None
+            pos_rows = np.ascontiguousarray(w.pos)
+        self.n_rows = int(pos_rows.shape[0])
+        self.pos = torch.as_tensor(pos_rows, dtype=torch.float64, device=dev)
         # a0: range patterns
         self.pS = neighbours(self.pos, self.box, w.R_S)
         self.pH = neighbours(self.pos, self.box, w.R_H)
@@ -247,9 +271,10 @@ class LNVSystem:
         self.S = Matrix(self.pS)
         self.H = Matrix(self.pH)
         box_c = (c_double * 3)(*self.box)
-        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, None, byref(self.S.struct), 0,
+        maps = (_ptr(self.nfun), _ptr(self.atom_of), _ptr(self.off_of))
+        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, *maps, byref(self.S.struct), 0,
                 float(w.R_S), 3.0, int(w.seed), float(w.scale), _stream())
-        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, None, byref(self.H.struct), 1,
+        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, *maps, byref(self.H.struct), 1,
                 float(w.R_H), 2.5, int(w.seed), float(w.scale), _stream())
         # a2: natural product patterns (A = LS is stored as its transpose SL)
         self.pSL = product_pattern(self.pS, self.pL)            # S.L

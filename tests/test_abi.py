@@ -91,3 +91,22 @@ def test_struct_layouts_match_header(tmp_path):
     want = [ctypes.sizeof(x) for x in (L.LnvPattern, L.LnvBsm, L.LnvEvalWs, L.LnvCgWs, L.LnvOpts,
                                            L.LnvAdjWs, L.LnvEval32Ws)]
     assert got == want
+
+
+def test_split_rows_cover_every_function_once():
+    """Stored-row layout of atoms with 13/9/4 (and odd) function counts: each
+    function of each atom lands in exactly one (row, slot), rows of an atom
+    are consecutive, and only the last row of an atom is padded."""
+    import numpy as np
+    from paper_2002_07704_amd.system import split_rows
+    nfun = np.array([13, 4, 9, 4, 1, 16, 5])
+    atom_of, off_of = split_rows(nfun)
+    seen = {}
+    for i, (a, o) in enumerate(zip(atom_of, off_of)):
+        for r in range(4):
+            if o + r < nfun[a]:
+                seen.setdefault((a, o + r), []).append((i, r))
+    assert sorted(seen) == [(a, f) for a in range(len(nfun)) for f in range(nfun[a])]
+    assert all(len(v) == 1 for v in seen.values())
+    assert np.all(np.diff(atom_of) >= 0)
+    assert list(np.bincount(atom_of)) == [4, 1, 3, 1, 1, 4, 2]
