@@ -156,6 +156,14 @@ int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
                         int64_t cap, int64_t* nnz_out, int64_t* row_triples,
                         int64_t* triples_out, hipStream_t s);
 
+/* lnv_pattern_flops -- algorithmic flops of the product A.B on its natural
+ * pattern (mask == NULL) or on mask: sum over the kept triples (i,k,j) of
+ * 2 f_i f_k f_j, f = row_fun (device [n]: support functions present in each
+ * stored row, so padded rows count only what they hold).  Host result in
+ * *flops_out.  Set-up call: allocates temporaries, synchronises s. */
+int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B, const lnv_pattern* mask,
+                      const int32_t* row_fun, int64_t* flops_out, hipStream_t s);
+
 /* lnv_pattern_lut -- fill the index tables of P (either may be NULL). */
 int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t, hipStream_t s);
 

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void k_symbolic(
     const int* __restrict__ b_rp, const int* __restrict__ b_col,
     const int* __restrict__ m_rp, const int* __restrict__ m_col, int* __restrict__ counts,
     const int* __restrict__ out_rp, int* __restrict__ out_col,
-    long long* __restrict__ triples, int fill) {
+    long long* __restrict__ triples, int fill, const int* __restrict__ wts) {
   extern __shared__ unsigned int sm[];
   __shared__ long long scan[256];
   const int W = (n + 31) >> 5;
@@ -146,12 +146,15 @@ __global__ __launch_bounds__(256) void k_symbolic(
       }
     }
   } else if (triples) {
+    // kept triples (i,k,j), each weighted by w_i w_k w_j when wts is given
     long long tr = 0;
     for (int t = t0 + wv; t < t1; t += 4) {
       const int k = a_col[t];
+      const long long wk = wts ? wts[k] : 1;
       for (int q = b_rp[k] + lane; q < b_rp[k + 1]; q += kWave) {
         const int j = b_col[q];
-        tr += (bits[j >> 5] >> (j & 31)) & 1u;
+        const long long hit = (bits[j >> 5] >> (j & 31)) & 1u;
+        tr += hit * (wts ? wk * wts[j] : 1);
       }
     }
     __syncthreads();
@@ -160,7 +163,7 @@ __global__ __launch_bounds__(256) void k_symbolic(
     if (tid == 0) {
       long long s = 0;
       for (int q = 0; q < 256; ++q) s += scan[q];
-      triples[i] = s;
+      triples[i] = wts ? s * wts[i] : s;
     }
   }
 }
@@ -426,7 +429,7 @@ extern "C" int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
   const int* mcol = mask ? mask->col : nullptr;
   k_symbolic<<<n, 256, lds, s>>>(n, A->row_ptr, A->col, B->row_ptr, B->col, mrp, mcol,
                                  row_ptr, nullptr, nullptr,
-                                 reinterpret_cast<long long*>(row_triples), 0);
+                                 reinterpret_cast<long long*>(row_triples), 0, nullptr);
   LNV_LAUNCH_CHECK();
   k_scan<int32_t><<<1, 1024, 0, s>>>(row_ptr, n);
   LNV_LAUNCH_CHECK();
@@ -443,8 +446,44 @@ extern "C" int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
   if (!col) return LNV_OK;
   if (cap < *nnz_out) return LNV_ECAPACITY;
   k_symbolic<<<n, 256, lds, s>>>(n, A->row_ptr, A->col, B->row_ptr, B->col, mrp, mcol,
-                                 nullptr, row_ptr, col, nullptr, 1);
+                                 nullptr, row_ptr, col, nullptr, 1, nullptr);
   LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B,
+                                 const lnv_pattern* mask, const int32_t* row_fun,
+                                 int64_t* flops_out, hipStream_t s) {
+  if (!A || !B || !row_fun || !flops_out) return LNV_EINVAL;
+  if (!A->row_ptr || !A->col || !B->row_ptr || !B->col) return LNV_EPATTERN;
+  const int n = A->n;
+  if (n <= 0 || n > LNV_MAX_ATOMS || B->n != n) return LNV_EPATTERN;
+  if (mask && (mask->n != n || !mask->row_ptr || !mask->col)) return LNV_EPATTERN;
+  const size_t lds = 2 * (size_t)((n + 31) / 32) * sizeof(unsigned int);
+  int32_t* counts = nullptr;
+  long long* tr = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&counts), sizeof(int32_t) * (n + 1), s));
+  hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&tr), sizeof(long long) * (n + 1), s);
+  if (e == hipSuccess) {
+    k_symbolic<<<n, 256, lds, s>>>(n, A->row_ptr, A->col, B->row_ptr, B->col,
+                                   mask ? mask->row_ptr : nullptr, mask ? mask->col : nullptr,
+                                   counts, nullptr, nullptr, tr, 0, row_fun);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    k_scan<long long><<<1, 1024, 0, s>>>(tr, n);
+    e = hipGetLastError();
+  }
+  long long total = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, tr + n, sizeof(long long), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (tr) (void)hipFreeAsync(tr, s);
+  (void)hipFreeAsync(counts, s);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return LNV_EHIP;
+  }
+  *flops_out = 2 * total;
   return LNV_OK;
 }
 

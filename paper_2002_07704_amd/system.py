@@ -124,6 +124,20 @@ def split_rows(nfun, blk=BLK):
     return atom_of.astype(np.int32), off_of.astype(np.int32)
 
 
+def cell_order(pos, box, edge=10.26):
+    """Atoms ordered cell by cell (cubic cells of about `edge` bohr, x slowest,
+    z fastest), stable within a cell: neighbouring rows are then spatial
+    neighbours, which the 4-row clusters and the per-XCD row ranges of the
+    multiply rely on.  Diamond cells generated cube by cube are already
+    nearly in this order (up to atoms displaced across a cube face)."""
+    pos = np.asarray(pos)
+    box = np.asarray(box, dtype=np.float64)
+    m = np.maximum(1, np.round(box / edge)).astype(np.int64)
+    c = np.minimum((pos / (box / m)).astype(np.int64), m - 1)
+    key = (c[:, 0] * m[1] + c[:, 1]) * m[2] + c[:, 2]
+    return np.argsort(key, kind="stable")
+
+
 def neighbours(pos_dev, box, R):
     """a0: range pattern for cutoff R (lnv_neighbours, two-phase)."""
     n = pos_dev.shape[0]
@@ -238,7 +252,7 @@ class LNVSystem:
     """
 
     def __init__(self, w, device="cuda", R_L=None, metric="hotelling", n_hotelling=16,
-                 cluster=(4, 1)):
+                 cluster=(4, 1), reorder=None):
         if not torch.cuda.is_available():
             raise RuntimeError("LNVSystem needs a GPU (HIP device)")
         L_.load()
@@ -250,10 +264,18 @@ class LNVSystem:
         self.dev = dev
         self.box = [float(b) for b in w.box]
         nfun = np.asarray(w.nfun, dtype=np.int32)
-        # atoms with other than 4 support functions span several 4x4-blocked rows
+        # atoms with other than 4 support functions span several 4x4-blocked
+        # rows; rows follow the atoms in spatial-cell order (reorder=None: for
+        # split systems only -- diamond cells are generated in that order)
         self.split = bool(np.any(nfun != BLK))
+        if reorder is None:
+            reorder = self.split
+        if reorder and not self.split:
+            raise ValueError("reordering applies to the split row layout")
         if self.split:
-            atom_of, off_of = split_rows(nfun)
+            order = cell_order(w.pos, w.box) if reorder else np.arange(w.n)
+            sub, off_of = split_rows(nfun[order])
+            atom_of = order[sub].astype(np.int32)
             self.atom_of = torch.as_tensor(atom_of, device=dev)
             self.off_of = torch.as_tensor(off_of, device=dev)
             self.nfun = torch.as_tensor(nfun, device=dev)
@@ -462,15 +484,15 @@ class LNVSystem:
         self.adj_ws.YS = self.YS.data_ptr()
         torch.cuda.synchronize()
 
-    def adjoint_flops(self, dS=True, dH=True):
+    def adjoint_flops(self, dS=True, dH=True, padded=False):
         """Algorithmic flops of one lnv_adjoint call."""
-        t = self.triples
+        t = self._weights(padded)
         tot = t["SL"] + t["LSL"]
         if dH:
             tot += t["dH4"] + t["dH6"]
         if dS:
             tot += t["HL"] + t["dS4"] + t["dS6"]
-        return 2 * BLK ** 3 * tot
+        return tot
 
     def adjoint(self, L, S, H, dS=None, dH=None):
         """dE/dS (into dS, on S's pattern) and dE/dH (into dH, on H's pattern)
@@ -493,11 +515,43 @@ class LNVSystem:
         return EN
 
     # ----------------------------------------------------------- flop accounting
-    def flops(self, what="eval"):
-        """Algorithmic flops (2 n^3 per block triple, true block sizes) of one
-        piece of work: "eval", "init" (L0), "step_base" (a CG step without the
-        electron-number correction), "ncorr" (that correction), "step" (both)."""
-        t = self.triples
+    def _weights(self, padded):
+        """Flops per product: 2 * 4^3 per stored block triple (padded), or the
+        algorithmic count with the functions each stored row holds."""
+        if padded or not self.split:
+            return {k: 2 * BLK ** 3 * v for k, v in self.triples.items()}
+        return self._alg_flops()
+
+    def _alg_flops(self):
+        if getattr(self, "_alg", None) is None:
+            self._alg = {}
+        specs = {"SL": (self.pS, self.pL, None), "X": (self.pH, self.pLS, None),
+                 "Z": (self.pS, self.pLS, None), "YT": (self.pSL, self.pXT, self.pL),
+                 "W": (self.pSL, self.pX, self.pL), "V": (self.pSL, self.pZ, self.pL)}
+        if self.metric is not None:
+            specs.update(TG=(self.pL, self.pL, None), TGT=(self.pLL, self.pL, self.pL))
+        if self.adj_ws is not None:
+            specs.update(LSL=(self.pL, self.pSL, None), HL=(self.pH, self.pL, None),
+                         dH4=(self.pLSL, self.pSL, self.pH), dH6=(self.pL, self.pSL, self.pH),
+                         dS4=(self.pLSL, self.pHL, self.pS), dS6=(self.pL, self.pHL, self.pS))
+        fun = (torch.minimum(torch.full_like(self.off_of, BLK),
+                             self.nfun[self.atom_of.long()] - self.off_of)).to(torch.int32)
+        for k, (A, B, M) in specs.items():
+            if k not in self._alg:
+                f = c_int64(0)
+                L_.call("lnv_pattern_flops", byref(A.struct), byref(B.struct),
+                        byref(M.struct) if M is not None else None, _ptr(fun), byref(f),
+                        _stream())
+                self._alg[k] = f.value
+        return self._alg
+
+    def flops(self, what="eval", padded=False):
+        """Algorithmic flops (2 n_i n_k n_j per block triple, the functions
+        present) of one piece of work: "eval", "init" (L0), "step_base" (a CG
+        step without the electron-number correction), "ncorr" (that
+        correction), "step" (both).  padded=True: 2 * 4^3 per stored triple,
+        the arithmetic the kernels do (the same unless atoms are split)."""
+        t = self._weights(padded)
         ev = t["SL"] + t["X"] + t["Z"] + t["YT"] + t["W"] + t["V"]
         line = t["SL"] + t["X"] + 2 * t["YT"]
         nchk = t["SL"] + t["Z"] + t["V"]
@@ -506,7 +560,7 @@ class LNVSystem:
         tot = {"eval": ev, "init": t["SL"] + t["Z"] + t["V"],
                "step_base": ev + met + line + nchk, "ncorr": ncor,
                "step": ev + met + line + nchk + ncor}[what]
-        return 2 * BLK ** 3 * tot
+        return tot
 
     # ----------------------------------------------------------- hot path
     def eval(self):
