@@ -119,6 +119,58 @@ def summarize_pmc(fetch_dir, write_dir, out_path, workload):
     print(json.dumps(res[workload]))
 
 
+def extra_configs(reps):
+    """Evaluation rates of the cells with 13 and 13/9/4 support functions
+    (atoms split into 4x4-blocked rows): FP64 and mixed-precision evaluation
+    at L0 of the Hotelling metric, with the mixed energy error."""
+    import torch
+
+    import lnv_workloads as W
+    from paper_2002_07704_amd.system import LNVSystem
+    cells = [
+        ("si8192_13f", W.diamond_workload("si8192_13f", (16, 16, 4), seed=3, nfun=13,
+                                          R=(12.0, 14.0, 10.0)),
+         "13 functions/atom (the mixed-precision workload's basis and ranges, 1/4 of its "
+         "32768 atoms: the dense index tables of 131072 rows would not fit)"),
+        ("siOH8192_mixed", W.get("siOH8192_mixed"),
+         "amorphous Si/O/H 40/40/20 %, 13/9/4 functions/atom, rho 0.0074 bohr^-3"),
+    ]
+    res = {}
+    for name, w, what in cells:
+        t0 = time.perf_counter()
+        s = LNVSystem(w)
+        s.cg_init()
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t1) * 1e3 / reps
+
+        ms64 = timed(s.eval)
+        E64 = float(s.EN[0])
+        s.mixed_setup()
+        ms32 = timed(s.eval_mixed)
+        E32 = float(s.EN[0])
+        f_alg, f_pad = s.flops("eval"), s.flops("eval", padded=True)
+        res[name] = {"what": what, "atoms": w.n, "orbitals": int(w.nfun.sum()),
+                     "rows": s.n_rows, "setup_s": setup,
+                     "eval_ms": ms64, "evals_per_s": 1e3 / ms64,
+                     "gflop_algorithmic": f_alg / 1e9, "gflop_padded": f_pad / 1e9,
+                     "tflops_algorithmic": f_alg / (ms64 * 1e-3) / 1e12,
+                     "mixed_eval_ms": ms32, "mixed_evals_per_s": 1e3 / ms32,
+                     "mixed_dE_per_atom": abs(E32 - E64) / w.n}
+        print(f"[bench] {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
+        del s
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -127,6 +179,8 @@ def main():
     ap.add_argument("--workload", default="si4096_4x4")
     ap.add_argument("--eval-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra-configs", action="store_true",
+                    help="skip the evaluations of the 13-function and Si/O/H cells")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
     ap.add_argument("--pmc-probe", action="store_true",
                     help="copy COPY_BYTES (counter calibration), then the timed steps only")
@@ -325,6 +379,10 @@ def main():
     if not args.no_cpu_baseline:
         Lb = sysg.L.val.cpu().numpy()
         out["cpu_baseline"] = cpu_baseline(w, Lb, sysg.pL.host())
+    if not args.no_extra_configs:
+        del sysg
+        torch.cuda.empty_cache()
+        out["other_configs"] = extra_configs(args.eval_reps)
     print(json.dumps(out), flush=True)
 
 

@@ -20,12 +20,32 @@ from . import structure as st
 
 
 def bsr(blocks, row_ptr, col, nfun):
-    """scipy CSR orbital matrix from stored blocks (uniform block size)."""
-    b = int(nfun[0])
-    assert np.all(nfun == b)
+    """scipy CSR orbital matrix from stored blocks [nnzb, p, p] (block (i, j)
+    is the leading nfun[i] x nfun[j] corner)."""
+    nfun = np.asarray(nfun)
     n = len(nfun)
-    M = sp.bsr_matrix((np.ascontiguousarray(blocks[:, :b, :b]), np.asarray(col),
-                       np.asarray(row_ptr)), shape=(n * b, n * b))
+    b = int(nfun[0])
+    if np.all(nfun == b):
+        M = sp.bsr_matrix((np.ascontiguousarray(blocks[:, :b, :b]), np.asarray(col),
+                           np.asarray(row_ptr)), shape=(n * b, n * b))
+        return M.tocsr()
+    off = st.offsets(nfun)
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    col = np.asarray(col)
+    parts_r, parts_c, parts_v = [], [], []
+    for ni in np.unique(nfun):
+        for nj in np.unique(nfun):
+            sel = np.nonzero((nfun[rows] == ni) & (nfun[col] == nj))[0]
+            if len(sel) == 0:
+                continue
+            rr = off[rows[sel]][:, None, None] + np.arange(ni)[None, :, None]
+            cc = off[col[sel]][:, None, None] + np.arange(nj)[None, None, :]
+            parts_r.append(np.broadcast_to(rr, (len(sel), ni, nj)).ravel())
+            parts_c.append(np.broadcast_to(cc, (len(sel), ni, nj)).ravel())
+            parts_v.append(blocks[sel, :ni, :nj].ravel())
+    N = int(off[-1])
+    M = sp.coo_matrix((np.concatenate(parts_v), (np.concatenate(parts_r),
+                                                 np.concatenate(parts_c))), shape=(N, N))
     return M.tocsr()
 
 
@@ -44,7 +64,9 @@ class RowOracle:
         return M[a:b].toarray()
 
     def row(self, i):
-        """(e_i, n_i, G row blocks [m, b, b], F row blocks, columns of L's row)."""
+        """(e_i, n_i, G row blocks [m, n_i, p], F row blocks, columns of L's
+        row); block t holds atom col[t]'s n_j columns, zero padded to
+        p = max nfun."""
         S, H, L = self.S, self.H, self.L
 
         def chain(P, *mats):
@@ -74,6 +96,11 @@ class RowOracle:
         rp, col = self.patL
         cols = col[rp[i]:rp[i + 1]]
         b = self.off[i + 1] - self.off[i]
-        Gb = np.stack([Gi[:, self.off[j]:self.off[j + 1]] for j in cols]).reshape(len(cols), b, -1)
-        Fb = np.stack([Fi[:, self.off[j]:self.off[j + 1]] for j in cols]).reshape(len(cols), b, -1)
+        p = int(np.max(self.nfun))
+        Gb = np.zeros((len(cols), b, p))
+        Fb = np.zeros((len(cols), b, p))
+        for t, j in enumerate(cols):
+            nj = self.off[j + 1] - self.off[j]
+            Gb[t, :, :nj] = Gi[:, self.off[j]:self.off[j + 1]]
+            Fb[t, :, :nj] = Fi[:, self.off[j]:self.off[j + 1]]
         return e, nn, Gb, Fb, cols

@@ -160,26 +160,47 @@ def random_block(seed, stream, i, j, ni, nj, scale):
 
 
 def synth_blocks(w, kind, row_ptr, col, pad=None):
-    """Stored blocks [nnzb, p, p] of the synthetic S (kind='S') or H ('H')."""
+    """Stored blocks [nnzb, p, p] of the synthetic S (kind='S') or H ('H').
+
+    Entry by entry this is random_block's definition (pinned against it in
+    the tests); the uniforms of all blocks of one row with the same column
+    block size are drawn in one vectorised call."""
     stream, decay, R = ((W.STREAM_S, 3.0, w.R_S) if kind == "S"
                         else (W.STREAM_H, 2.5, w.R_H))
     n = w.n
-    nf = w.nfun
+    nf = np.asarray(w.nfun)
     p = pad or int(nf.max())
     out = np.zeros((len(col), p, p))
     for i in range(n):
-        js = col[row_ptr[i]:row_ptr[i + 1]]
+        r0 = row_ptr[i]
+        js = np.asarray(col[r0:row_ptr[i + 1]], dtype=np.int64)
         dx = w.pos[js] - w.pos[i]
         wt = image_weight(dx, w.box, R, decay)
-        for t, j in enumerate(js):
-            M = random_block(w.seed, stream, i, int(j), int(nf[i]), int(nf[j]), w.scale)
+        ni = int(nf[i])
+        for nj in np.unique(nf[js]):
+            nj = int(nj)
+            sel = np.nonzero(nf[js] == nj)[0]
+            j = js[sel]
+            r = np.arange(ni)[:, None]
+            c = np.arange(nj)[None, :]
+            M = np.empty((len(j), ni, nj))
+            up, lo, dg = j > i, j < i, j == i
+            if up.any():       # M_ij = scale (U(i, j, r*nj + c) - 1/2)
+                M[up] = w.scale * (W.uniform01(w.seed, stream, i, j[up][:, None, None],
+                                               (r * nj + c)[None]) - 0.5)
+            if lo.any():       # M_ij = M_ji^T, M_ji = scale (U(j, i, c*ni + r) - 1/2)
+                M[lo] = w.scale * (W.uniform01(w.seed, stream, j[lo][:, None, None], i,
+                                               (c * ni + r)[None]) - 0.5)
+            if dg.any():       # (R + R^T) / 2 on the diagonal block
+                Mab = w.scale * (W.uniform01(w.seed, stream, i, i, r * ni + c) - 0.5)
+                M[dg] = (Mab + Mab.T) * 0.5
+            blk = wt[sel][:, None, None] * M
             if kind == "S":
-                blk = wt[t] * M
-                if i == j:
-                    blk = blk + 2.0 * np.eye(nf[i])
+                if dg.any():
+                    blk[dg] += 2.0 * np.eye(ni)
             else:
-                blk = -(wt[t] * M)
-            out[row_ptr[i] + t, :nf[i], :nf[j]] = blk
+                blk = -blk
+            out[r0 + sel, :ni, :nj] = blk
     return out
 
 

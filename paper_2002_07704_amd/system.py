@@ -407,6 +407,16 @@ class LNVSystem:
         self.ws32 = None
         torch.cuda.synchronize()
 
+    def synth_values(self, kind, pat, R, decay, seed, scale=None):
+        """Synthetic blocks (kind 0: overlap-like w M + 2I, 1: -w M) on one of
+        this system's patterns, in its row layout (lnv_synth_blocks)."""
+        M = Matrix(pat)
+        box_c = (c_double * 3)(*self.box)
+        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, _ptr(self.nfun), _ptr(self.atom_of),
+                _ptr(self.off_of), byref(M.struct), int(kind), float(R), float(decay), int(seed),
+                float(self.w.scale if scale is None else scale), _stream())
+        return M
+
     # ----------------------------------------------------------- mixed precision
     def mixed_setup(self):
         """FP32 copies of L, S, H and FP32 intermediates for lnv_eval_mixed

@@ -6,6 +6,13 @@ RAM and tens of minutes on 8 cores per CG step, which is why its values are
 stored instead of recomputed inside the GPU tests.
 
 usage: python tests/golden/make_golden.py si4096_4x4 [n_cg_steps]
+       python tests/golden/make_golden.py rows siOH8192_mixed
+
+The second form writes <workload>_rows.npz: the row-wise oracle's G and F
+rows (and per-atom energy / electron contributions) of a few sampled atoms at
+the seeded test matrix L = 0.1 (w M + 2I) on L's range -- the synthetic
+overlap generator with master seed + 1000, range R_L and decay 3 bohr -- for
+the 78646-orbital Si/O/H cell, where no dense matrix fits.
 """
 from __future__ import annotations
 
@@ -24,7 +31,52 @@ from oracle import lnv as olnv  # noqa: E402
 from oracle import structure as ost  # noqa: E402
 
 
+L_SEED_OFFSET = 1000
+L_SCALE = 0.1
+
+
+def test_L_blocks(w, patL):
+    """The seeded L of the sampled-row tests (oracle side)."""
+    import dataclasses
+    w2 = dataclasses.replace(w, seed=w.seed + L_SEED_OFFSET, R_S=w.R_L)
+    return L_SCALE * ost.synth_blocks(w2, "S", *patL)
+
+
+def sample_atoms(w):
+    """The first atom of each species and three seeded picks (stream 4)."""
+    at = [int(np.nonzero(w.species == s)[0][0]) for s in np.unique(w.species)]
+    u = W.uniform01(w.seed, W.STREAM_FD, 99, np.arange(3), 0)
+    at += [int(x) for x in (u * w.n).astype(int)]
+    return sorted(set(at))
+
+
+def rows_main(name):
+    from oracle import rows as orows
+    w = W.get(name)
+    t0 = time.time()
+    pS = ost.neighbours(w.pos, w.box, w.R_S)
+    pH = ost.neighbours(w.pos, w.box, w.R_H)
+    pL = ost.neighbours(w.pos, w.box, w.R_L)
+    ro = orows.RowOracle(w, ost.synth_blocks(w, "S", *pS), ost.synth_blocks(w, "H", *pH),
+                         test_L_blocks(w, pL), pS, pH, pL)
+    print(f"set-up {time.time() - t0:.1f}s", flush=True)
+    atoms = sample_atoms(w)
+    out = {"atoms": np.array(atoms), "e": [], "n": []}
+    for i in atoms:
+        e, nn, Gb, Fb, cols = ro.row(i)
+        out["e"].append(e)
+        out["n"].append(nn)
+        out[f"G_{i}"], out[f"F_{i}"], out[f"cols_{i}"] = Gb, Fb, cols
+        print(f"atom {i} (nfun {w.nfun[i]}) {time.time() - t0:.1f}s", flush=True)
+    out["e"], out["n"] = np.array(out["e"]), np.array(out["n"])
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_rows.npz")
+    np.savez_compressed(path, **out)
+    print("wrote", path, flush=True)
+
+
 def main():
+    if len(sys.argv) > 2 and sys.argv[1] == "rows":
+        return rows_main(sys.argv[2])
     name = sys.argv[1] if len(sys.argv) > 1 else "si4096_4x4"
     steps = int(sys.argv[2]) if len(sys.argv) > 2 else 2
     w = W.get(name)

@@ -300,3 +300,57 @@ def test_cg_with_hotelling_metric_descends_si216():
     assert all(E[k + 1] < E[k] for k in range(len(E) - 1))
     assert all(abs(h["N"] - w.n_elec) < 1e-9 for h in hist[1:])
     assert all(h["alpha"] > 0 for h in hist)
+
+
+@pytest.mark.parametrize("name", ["si8_4x4", "siOH24"])
+def test_synth_blocks_follow_random_block_definition(name):
+    """The vectorised generator gives, bit for bit, w(d) M_ij (+ 2I on the S
+    diagonal, negated for H) with M_ij from random_block's per-block
+    definition, for uniform and for mixed 13/9/4 block sizes."""
+    w = W.amorphous_workload("siOH24", 24, seed=5) if name == "siOH24" else W.get(name)
+    nf = w.nfun
+    for kind, stream, decay, R in (("S", W.STREAM_S, 3.0, w.R_S), ("H", W.STREAM_H, 2.5, w.R_H)):
+        rp, col = st.neighbours(w.pos, w.box, R)
+        got = st.synth_blocks(w, kind, rp, col)
+        for i in range(w.n):
+            for t in range(rp[i], rp[i + 1]):
+                j = int(col[t])
+                M = st.random_block(w.seed, stream, i, j, int(nf[i]), int(nf[j]), w.scale)
+                wt = st.image_weight((w.pos[j] - w.pos[i])[None], w.box, R, decay)[0]
+                want = wt * M + (2.0 * np.eye(nf[i]) if (kind == "S" and i == j) else 0.0)
+                if kind == "H":
+                    want = -(wt * M)
+                assert np.array_equal(got[t, :nf[i], :nf[j]], want), (kind, i, j)
+                assert not got[t, nf[i]:, :].any() and not got[t, :, nf[j]:].any()
+
+
+@pytest.mark.parametrize("name", ["si64_4x4", "siOH24"])
+def test_row_oracle_equals_dense_oracle(name):
+    """The row-wise oracle (sparse row panels, for cells too large to be
+    dense) reproduces the dense evaluation: per-atom energy and electron
+    contributions sum to E and N, and every row of G and F matches."""
+    from oracle import rows as orows
+    w = W.amorphous_workload("siOH24", 24, seed=5) if name == "siOH24" else W.get(name)
+    sysd = st.System(w)
+    n_orb = sysd.S.shape[0]
+    rng = np.random.default_rng(3)
+    C = rng.standard_normal((n_orb, n_orb)) * 0.05
+    Ld = ((C + C.T) * 0.5 + 0.2 * np.eye(n_orb)) * sysd.maskL
+    E, N, G, F = lnv.evaluate(Ld, sysd.S, sysd.H, sysd.maskL)
+    pL = sysd.pat["L"]
+    ro = orows.RowOracle(w, sysd.Sb, sysd.Hb, sysd.blocks(Ld, "L"), sysd.pat["S"],
+                         sysd.pat["H"], pL)
+    off = st.offsets(w.nfun)
+    es = ns = 0.0
+    for i in range(w.n):
+        e, nn, Gb, Fb, cols = ro.row(i)
+        es += e
+        ns += nn
+        assert np.array_equal(cols, pL[1][pL[0][i]:pL[0][i + 1]])
+        for t, j in enumerate(cols):
+            nj = w.nfun[j]
+            ref_g = G[off[i]:off[i + 1], off[j]:off[j + 1]]
+            ref_f = F[off[i]:off[i + 1], off[j]:off[j + 1]]
+            assert np.abs(Gb[t, :, :nj] - ref_g).max() <= 1e-12 * np.abs(G).max()
+            assert np.abs(Fb[t, :, :nj] - ref_f).max() <= 1e-12 * np.abs(F).max()
+    assert abs(es - E) <= 1e-11 * abs(E) and abs(ns - N) <= 1e-11 * abs(N)
