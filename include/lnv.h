@@ -339,6 +339,40 @@ enum { LNV_ST_NONFINITE = 1, LNV_ST_NO_ALPHA = 2, LNV_ST_NO_DELTA = 4, LNV_ST_DE
 int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
              lnv_bsm* F, double* EN, const lnv_eval_ws* ws, hipStream_t s);
 
+/* ------------------------------------------------------------ batches of cells
+ * A batch of independent periodic cells is one block-diagonal system: the
+ * rows of cell c are cell_start[c] .. cell_start[c+1]-1 (cell_of[row] = c),
+ * its box is boxes[3c .. 3c+2] and its master seed seeds[c].  Every kernel of
+ * the evaluation then serves all cells in one launch per product; only the
+ * range patterns, the synthetic matrices and the traces need the cells.
+ *
+ * lnv_neighbours_cells -- lnv_neighbours with each row tested only against
+ * the rows of its own cell, in its cell's box (device arrays: cell_start
+ * [n_cells+1], cell_of [n], boxes [n_cells*3]).  Same two-phase protocol.
+ */
+int lnv_neighbours_cells(const double* pos, int32_t n, int32_t n_cells,
+                         const int32_t* cell_start, const int32_t* cell_of, const double* boxes,
+                         double R, int32_t* row_ptr, int32_t* col, int64_t cap,
+                         int64_t* nnz_out, hipStream_t s);
+
+/* lnv_synth_blocks_cells -- lnv_synth_blocks for a batch: row i uses its
+ * cell's box and seed (cell_of, boxes, seeds: device), atom_of[i] is the
+ * row's atom index within its cell (the counter key), fun_of[i] that atom's
+ * function count and off_of[i] the row's first function (all device [n]). */
+int lnv_synth_blocks_cells(const double* pos, const int32_t* cell_of, const double* boxes,
+                           const uint64_t* seeds, const int32_t* atom_of, const int32_t* fun_of,
+                           const int32_t* off_of, const lnv_bsm* M, int32_t kind, double R,
+                           double decay, double scale, hipStream_t s);
+
+/* lnv_cell_traces -- per-cell E and N (EN_cells[2c], EN_cells[2c+1], device)
+ * from the trace partials that lnv_eval or lnv_eval_mixed left in
+ * ws->partials; call it right after that evaluation, on the same stream and
+ * workspace.  cell_item_ptr (device [n_cells+1]): the work items of L's
+ * pattern that belong to each cell (items are in row order, so each cell's
+ * items are one range).  Fixed reduction order. */
+int lnv_cell_traces(const lnv_pattern* PL, const lnv_eval_ws* ws, int32_t n_cells,
+                    const int32_t* cell_item_ptr, double* EN_cells, hipStream_t s);
+
 /* ------------------------------------------------------------ a3/a4 mixed precision
  * lnv_eval_mixed -- lnv_eval with the six block products in FP32 (FP32
  * multiply-add, FP32 accumulation) and everything else in FP64: L, S and H

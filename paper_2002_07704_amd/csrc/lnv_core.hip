@@ -382,6 +382,29 @@ __global__ __launch_bounds__(256) void k_nassemble(
   }
 }
 
+// Per-cell energy and electron number of a batch of independent cells from
+// the trace partials k_assemble leaves (slots 0..3 = <L,X>, <L,Y>, <L,Z>,
+// <L,V> per item of L's pattern): workgroup c sums the items of cell c,
+// items cell_item_ptr[c] .. cell_item_ptr[c+1]-1, in a fixed order.
+__global__ __launch_bounds__(256) void k_cell_traces(const double* __restrict__ partials,
+                                                     int n_items,
+                                                     const int* __restrict__ cell_item_ptr,
+                                                     double* __restrict__ en) {
+  __shared__ double sh[16];
+  const int c = blockIdx.x;
+  const int q0 = cell_item_ptr[c], q1 = cell_item_ptr[c + 1];
+  double t[4];
+  for (int k = 0; k < 4; ++k) {
+    double v = 0.0;
+    for (int q = q0 + threadIdx.x; q < q1; q += blockDim.x) v += partials[(size_t)k * n_items + q];
+    t[k] = block_sum(v, sh);
+  }
+  if (threadIdx.x == 0) {
+    en[2 * c] = 2.0 * (3.0 * t[0] - 2.0 * t[1]);
+    en[2 * c + 1] = 2.0 * (3.0 * t[2] - 2.0 * t[3]);
+  }
+}
+
 // <A, B> with B located through B's index table (or at A's positions).
 __global__ __launch_bounds__(256) void k_dot_items(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
@@ -920,6 +943,16 @@ extern "C" int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm*
             ws->scalars};
   return eval_products<float>(L, o, static_cast<double*>(G->val), static_cast<double*>(F->val),
                               EN, s);
+}
+
+extern "C" int lnv_cell_traces(const lnv_pattern* PL, const lnv_eval_ws* ws, int32_t n_cells,
+                               const int32_t* cell_item_ptr, double* EN_cells, hipStream_t s) {
+  if (!PL || !ws || !ws->partials || !cell_item_ptr || !EN_cells || n_cells <= 0)
+    return LNV_EINVAL;
+  if (PL->n_items <= 0) return LNV_EPATTERN;
+  k_cell_traces<<<n_cells, 256, 0, s>>>(ws->partials, PL->n_items, cell_item_ptr, EN_cells);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
 }
 
 extern "C" int lnv_bsm_convert(const lnv_bsm* A, lnv_bsm* B, hipStream_t s) {

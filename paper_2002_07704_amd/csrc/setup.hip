@@ -47,8 +47,14 @@ __global__ __launch_bounds__(1024) void k_scan(T* __restrict__ data, int n) {
 // ------------------------------------------------------------------ a0
 // One wavefront per row i scans every j in ascending order (so the columns
 // come out sorted) and compacts the in-range ones with a ballot.
+// With cells (cell_of != null): row i belongs to cell c = cell_of[i], whose
+// rows are cell_start[c] .. cell_start[c+1]-1 and whose periodic box is
+// boxes[3c .. 3c+2]; only rows of the same cell are tested.
 __global__ __launch_bounds__(256) void k_neighbours(const double* __restrict__ pos, int n,
                                                     double bx, double by, double bz,
+                                                    const int* __restrict__ cell_of,
+                                                    const int* __restrict__ cell_start,
+                                                    const double* __restrict__ boxes,
                                                     double R2, int* __restrict__ counts,
                                                     const int* __restrict__ row_ptr,
                                                     int* __restrict__ col, int fill) {
@@ -56,13 +62,22 @@ __global__ __launch_bounds__(256) void k_neighbours(const double* __restrict__ p
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= n) return;
   const int lane = threadIdx.x & 63;
+  int jlo = 0, jhi = n;
+  if (cell_of) {
+    const int c = cell_of[row];
+    jlo = cell_start[c];
+    jhi = cell_start[c + 1];
+    bx = boxes[3 * c];
+    by = boxes[3 * c + 1];
+    bz = boxes[3 * c + 2];
+  }
   const double xi = pos[3 * row], yi = pos[3 * row + 1], zi = pos[3 * row + 2];
   const int base = fill ? row_ptr[row] : 0;
   int cnt = 0;
-  for (int j0 = 0; j0 < n; j0 += kWave) {
+  for (int j0 = jlo; j0 < jhi; j0 += kWave) {
     const int j = j0 + lane;
     bool ok = false;
-    if (j < n) {
+    if (j < jhi) {
       double dx = pos[3 * j] - xi;
       double dy = pos[3 * j + 1] - yi;
       double dz = pos[3 * j + 2] - zi;
@@ -317,27 +332,43 @@ __device__ __forceinline__ double rand_entry(uint64_t seed, uint64_t stream, uin
 // atom's function count are zero.  The random entries are keyed by the atom
 // pair and the element's index in the atom block, so the values do not depend
 // on how atoms are split into stored rows.
+// Independent cells (cell_of != null): row i belongs to cell c = cell_of[i]
+// with periodic box boxes[3c..3c+2] and master seed seeds[c]; atom_of then
+// holds each row's atom index within its cell (the counter key) and fun_of
+// its atom's function count.
 __global__ __launch_bounds__(128) void k_synth(const double* __restrict__ pos, double bx,
                                                double by, double bz,
+                                               const int* __restrict__ cell_of,
+                                               const double* __restrict__ boxes,
+                                               const uint64_t* __restrict__ seeds,
+                                               const int* __restrict__ fun_of,
                                                const int* __restrict__ nfun,
                                                const int* __restrict__ atom_of,
                                                const int* __restrict__ off_of, int blk,
                                                const int* __restrict__ rp,
                                                const int* __restrict__ col,
-                                               double* __restrict__ val, int kind, double R2,
-                                               double decay, int mx, int my, int mz,
-                                               uint64_t seed, double scale) {
+                                               double* __restrict__ val, int kind, double R,
+                                               double decay, uint64_t seed, double scale) {
 #pragma clang fp contract(off)
   const int i = blockIdx.x;
   const uint64_t stream = kind == 0 ? 1ull : 2ull;
+  if (cell_of) {
+    const int c = cell_of[i];
+    bx = boxes[3 * c];
+    by = boxes[3 * c + 1];
+    bz = boxes[3 * c + 2];
+    seed = seeds[c];
+  }
+  const double R2 = R * R;
+  const int mx = (int)ceil(R / bx) + 1, my = (int)ceil(R / by) + 1, mz = (int)ceil(R / bz) + 1;
   const int ai = atom_of ? atom_of[i] : i;
   const int oi = off_of ? off_of[i] : 0;
-  const int ni = nfun ? nfun[ai] : blk;
+  const int ni = fun_of ? fun_of[i] : (nfun ? nfun[ai] : blk);
   for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 128) {
     const int j = col[p];
     const int aj = atom_of ? atom_of[j] : j;
     const int oj = off_of ? off_of[j] : 0;
-    const int nj = nfun ? nfun[aj] : blk;
+    const int nj = fun_of ? fun_of[j] : (nfun ? nfun[aj] : blk);
     const double dx = pos[3 * j] - pos[3 * i];
     const double dy = pos[3 * j + 1] - pos[3 * i + 1];
     const double dz = pos[3 * j + 2] - pos[3 * i + 2];
@@ -400,16 +431,40 @@ extern "C" int lnv_neighbours(const double* pos, int32_t n, const double* box, d
   if (!(box[0] > 0.0 && box[1] > 0.0 && box[2] > 0.0)) return LNV_EINVAL;
   const double R2 = R * R;
   const int grid = (n + 3) / 4;
-  k_neighbours<<<grid, 256, 0, s>>>(pos, n, box[0], box[1], box[2], R2, row_ptr, nullptr,
-                                    nullptr, 0);
+  k_neighbours<<<grid, 256, 0, s>>>(pos, n, box[0], box[1], box[2], nullptr, nullptr, nullptr,
+                                    R2, row_ptr, nullptr, nullptr, 0);
   LNV_LAUNCH_CHECK();
   k_scan<int32_t><<<1, 1024, 0, s>>>(row_ptr, n);
   LNV_LAUNCH_CHECK();
   LNV_TRY(read_total_int(row_ptr + n, nnz_out, s));
   if (!col) return LNV_OK;
   if (cap < *nnz_out) return LNV_ECAPACITY;
-  k_neighbours<<<grid, 256, 0, s>>>(pos, n, box[0], box[1], box[2], R2, nullptr, row_ptr,
-                                    col, 1);
+  k_neighbours<<<grid, 256, 0, s>>>(pos, n, box[0], box[1], box[2], nullptr, nullptr, nullptr,
+                                    R2, nullptr, row_ptr, col, 1);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_neighbours_cells(const double* pos, int32_t n, int32_t n_cells,
+                                    const int32_t* cell_start, const int32_t* cell_of,
+                                    const double* boxes, double R, int32_t* row_ptr,
+                                    int32_t* col, int64_t cap, int64_t* nnz_out,
+                                    hipStream_t s) {
+  if (!pos || !cell_start || !cell_of || !boxes || !row_ptr || !nnz_out || n <= 0 ||
+      n > LNV_MAX_ATOMS || n_cells <= 0 || !(R >= 0.0))
+    return LNV_EINVAL;
+  const double R2 = R * R;
+  const int grid = (n + 3) / 4;
+  k_neighbours<<<grid, 256, 0, s>>>(pos, n, 1.0, 1.0, 1.0, cell_of, cell_start, boxes, R2,
+                                    row_ptr, nullptr, nullptr, 0);
+  LNV_LAUNCH_CHECK();
+  k_scan<int32_t><<<1, 1024, 0, s>>>(row_ptr, n);
+  LNV_LAUNCH_CHECK();
+  LNV_TRY(read_total_int(row_ptr + n, nnz_out, s));
+  if (!col) return LNV_OK;
+  if (cap < *nnz_out) return LNV_ECAPACITY;
+  k_neighbours<<<grid, 256, 0, s>>>(pos, n, 1.0, 1.0, 1.0, cell_of, cell_start, boxes, R2,
+                                    nullptr, row_ptr, col, 1);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
@@ -555,13 +610,27 @@ extern "C" int lnv_synth_blocks(const double* pos, const double* box, const int3
   if ((atom_of == nullptr) != (off_of == nullptr)) return LNV_EINVAL;
   const int n = M->pat->n;
   if (n >= (1 << 24)) return LNV_EUNSUPPORTED;  // counter layout: 24-bit atom ids
-  const int mx = (int)std::ceil(R / box[0]) + 1;
-  const int my = (int)std::ceil(R / box[1]) + 1;
-  const int mz = (int)std::ceil(R / box[2]) + 1;
-  k_synth<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, atom_of, off_of, M->blk,
-                            M->pat->row_ptr,
-                            M->pat->col, static_cast<double*>(M->val), kind, R * R, decay,
-                            mx, my, mz, seed, scale);
+  k_synth<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nullptr, nullptr, nullptr, nullptr,
+                            nfun, atom_of, off_of, M->blk, M->pat->row_ptr, M->pat->col,
+                            static_cast<double*>(M->val), kind, R, decay, seed, scale);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_synth_blocks_cells(const double* pos, const int32_t* cell_of,
+                                      const double* boxes, const uint64_t* seeds,
+                                      const int32_t* atom_of, const int32_t* fun_of,
+                                      const int32_t* off_of, const lnv_bsm* M, int32_t kind,
+                                      double R, double decay, double scale, hipStream_t s) {
+  if (!pos || !cell_of || !boxes || !seeds || !atom_of || !fun_of || !off_of || !bsm_ok(M) ||
+      (kind != 0 && kind != 1) || !(R >= 0.0) || !(decay > 0.0))
+    return LNV_EINVAL;
+  if (!M->pat->row_ptr || !M->pat->col) return LNV_EPATTERN;
+  if (M->blk <= 0 || M->blk > 16) return LNV_EUNSUPPORTED;
+  const int n = M->pat->n;
+  k_synth<<<n, 128, 0, s>>>(pos, 1.0, 1.0, 1.0, cell_of, boxes, seeds, fun_of, nullptr, atom_of,
+                            off_of, M->blk, M->pat->row_ptr, M->pat->col,
+                            static_cast<double*>(M->val), kind, R, decay, 0ull, scale);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }

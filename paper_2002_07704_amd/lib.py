@@ -101,6 +101,13 @@ SIGNATURES = {
     "lnv_eval_mixed": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, c_void_p, POINTER(LnvEval32Ws),
                                c_void_p]),
     "lnv_bsm_convert": (c_int, [PBsm, PBsm, c_void_p]),
+    "lnv_neighbours_cells": (c_int, [c_void_p, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                     c_double, c_void_p, c_void_p, c_int64, POINTER(c_int64),
+                                     c_void_p]),
+    "lnv_synth_blocks_cells": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       c_void_p, PBsm, c_int32, c_double, c_double, c_double,
+                                       c_void_p]),
+    "lnv_cell_traces": (c_int, [PPat, POINTER(LnvEvalWs), c_int32, c_void_p, c_void_p, c_void_p]),
     "lnv_adjoint": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, POINTER(LnvAdjWs), c_void_p]),
     "lnv_hotelling": (c_int, [PBsm, PBsm, c_int32, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),

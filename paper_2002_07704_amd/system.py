@@ -256,48 +256,13 @@ class LNVSystem:
         if not torch.cuda.is_available():
             raise RuntimeError("LNVSystem needs a GPU (HIP device)")
         L_.load()
-        self.w = w
-        self.n = w.n
-        self.n_elec = float(w.n_elec)
-        self.R_L = float(w.R_L if R_L is None else R_L)
         dev = torch.device(device)
         self.dev = dev
-        self.box = [float(b) for b in w.box]
-        nfun = np.asarray(w.nfun, dtype=np.int32)
-        # atoms with other than 4 support functions span several 4x4-blocked
-        # rows; rows follow the atoms in spatial-cell order (reorder=None: for
-        # split systems only -- diamond cells are generated in that order)
-        self.split = bool(np.any(nfun != BLK))
-        if reorder is None:
-            reorder = self.split
-        if reorder and not self.split:
-            raise ValueError("reordering applies to the split row layout")
-        if self.split:
-            order = cell_order(w.pos, w.box) if reorder else np.arange(w.n)
-            sub, off_of = split_rows(nfun[order])
-            atom_of = order[sub].astype(np.int32)
-            self.atom_of = torch.as_tensor(atom_of, device=dev)
-            self.off_of = torch.as_tensor(off_of, device=dev)
-            self.nfun = torch.as_tensor(nfun, device=dev)
-            pos_rows = np.ascontiguousarray(w.pos[atom_of])
+        self.cells = list(w) if isinstance(w, (list, tuple)) else None
+        if self.cells is not None:
+            self._layout_cells(self.cells, R_L)
         else:
-            self.atom_of = self.off_of = self.nfun = None
-            pos_rows = np.ascontiguousarray(w.pos)
-        self.n_rows = int(pos_rows.shape[0])
-        self.pos = torch.as_tensor(pos_rows, dtype=torch.float64, device=dev)
-        # a0: range patterns
-        self.pS = neighbours(self.pos, self.box, w.R_S)
-        self.pH = neighbours(self.pos, self.box, w.R_H)
-        self.pL = neighbours(self.pos, self.box, self.R_L)
-        # a1: synthetic S, H
-        self.S = Matrix(self.pS)
-        self.H = Matrix(self.pH)
-        box_c = (c_double * 3)(*self.box)
-        maps = (_ptr(self.nfun), _ptr(self.atom_of), _ptr(self.off_of))
-        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, *maps, byref(self.S.struct), 0,
-                float(w.R_S), 3.0, int(w.seed), float(w.scale), _stream())
-        L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, *maps, byref(self.H.struct), 1,
-                float(w.R_H), 2.5, int(w.seed), float(w.scale), _stream())
+            self._layout_single(w, R_L, reorder)
         # a2: natural product patterns (A = LS is stored as its transpose SL)
         self.pSL = product_pattern(self.pS, self.pL)            # S.L
         self.pLS = product_pattern(self.pL, self.pS, triples=False)   # L.S (row form of A)
@@ -407,14 +372,25 @@ class LNVSystem:
         self.ws32 = None
         torch.cuda.synchronize()
 
-    def synth_values(self, kind, pat, R, decay, seed, scale=None):
+    def synth_values(self, kind, pat, R, decay, seed=None, scale=None, seed_offset=0):
         """Synthetic blocks (kind 0: overlap-like w M + 2I, 1: -w M) on one of
-        this system's patterns, in its row layout (lnv_synth_blocks)."""
+        this system's patterns, in its row layout (lnv_synth_blocks, or
+        lnv_synth_blocks_cells); seed None: the master seed (each cell's own
+        in a batch), plus seed_offset."""
         M = Matrix(pat)
+        scale = float(self.scale if scale is None else scale)
+        if self.cells is not None:
+            seeds = (self.seeds if seed is None else torch.full_like(self.seeds, int(seed)))
+            seeds = seeds + int(seed_offset)
+            L_.call("lnv_synth_blocks_cells", _ptr(self.pos), _ptr(self.cell_of), _ptr(self.boxes),
+                    _ptr(seeds), _ptr(self.atom_of), _ptr(self.fun_of), _ptr(self.off_of),
+                    byref(M.struct), int(kind), float(R), float(decay), scale, _stream())
+            return M
         box_c = (c_double * 3)(*self.box)
+        seed = (self.seed if seed is None else int(seed)) + int(seed_offset)
         L_.call("lnv_synth_blocks", _ptr(self.pos), box_c, _ptr(self.nfun), _ptr(self.atom_of),
-                _ptr(self.off_of), byref(M.struct), int(kind), float(R), float(decay), int(seed),
-                float(self.w.scale if scale is None else scale), _stream())
+                _ptr(self.off_of), byref(M.struct), int(kind), float(R), float(decay), seed,
+                scale, _stream())
         return M
 
     # ----------------------------------------------------------- mixed precision
@@ -453,6 +429,128 @@ class LNVSystem:
                 byref(self.H.struct), byref(self.G.struct), byref(self.F.struct), _ptr(self.EN),
                 byref(self.ws32), _stream())
         return self.EN
+
+    # ----------------------------------------------------------- row layout
+    def _layout_single(self, w, R_L, reorder):
+        """a0/a1 of one periodic cell: range patterns and synthetic S, H."""
+        dev = self.dev
+        self.w = w
+        self.n = w.n
+        self.n_elec = float(w.n_elec)
+        self.R_S, self.R_H = float(w.R_S), float(w.R_H)
+        self.R_L = float(w.R_L if R_L is None else R_L)
+        self.seed, self.scale = int(w.seed), float(w.scale)
+        self.box = [float(b) for b in w.box]
+        nfun = np.asarray(w.nfun, dtype=np.int32)
+        # atoms with other than 4 support functions span several 4x4-blocked
+        # rows; rows follow the atoms in spatial-cell order (reorder=None: for
+        # split systems only -- diamond cells are generated in that order)
+        self.split = bool(np.any(nfun != BLK))
+        if reorder is None:
+            reorder = self.split
+        if reorder and not self.split:
+            raise ValueError("reordering applies to the split row layout")
+        if self.split:
+            order = cell_order(w.pos, w.box) if reorder else np.arange(w.n)
+            sub, off_of = split_rows(nfun[order])
+            atom_of = order[sub].astype(np.int32)
+            self.atom_of = torch.as_tensor(atom_of, device=dev)
+            self.off_of = torch.as_tensor(off_of, device=dev)
+            self.nfun = torch.as_tensor(nfun, device=dev)
+            self.fun_rows = torch.as_tensor(np.minimum(BLK, nfun[atom_of] - off_of)
+                                            .astype(np.int32), device=dev)
+            pos_rows = np.ascontiguousarray(w.pos[atom_of])
+        else:
+            self.atom_of = self.off_of = self.nfun = self.fun_rows = None
+            pos_rows = np.ascontiguousarray(w.pos)
+        self.n_rows = int(pos_rows.shape[0])
+        self.pos = torch.as_tensor(pos_rows, dtype=torch.float64, device=dev)
+        # a0: range patterns
+        self.pS = neighbours(self.pos, self.box, self.R_S)
+        self.pH = neighbours(self.pos, self.box, self.R_H)
+        self.pL = neighbours(self.pos, self.box, self.R_L)
+        # a1: synthetic S, H
+        self.S = self.synth_values(0, self.pS, self.R_S, 3.0, self.seed)
+        self.H = self.synth_values(1, self.pH, self.R_H, 2.5, self.seed)
+
+    def _layout_cells(self, cells, R_L):
+        """a0/a1 of a batch of independent cells: one block-diagonal system
+        whose rows are the cells' rows one cell after another (each cell's
+        atoms in spatial-cell order, split into 4x4-blocked rows)."""
+        dev = self.dev
+        w0 = cells[0]
+        for c in cells:
+            if (c.R_S, c.R_H, c.R_L, c.scale) != (w0.R_S, w0.R_H, w0.R_L, w0.scale):
+                raise ValueError("cells of a batch share ranges and entry scale")
+        self.w = None
+        self.n = int(sum(c.n for c in cells))
+        self.n_elec = float(sum(c.n_elec for c in cells))
+        self.R_S, self.R_H = float(w0.R_S), float(w0.R_H)
+        self.R_L = float(w0.R_L if R_L is None else R_L)
+        self.seed, self.scale = None, float(w0.scale)
+        self.box = None
+        self.split = True
+        atom, off, fun, cell, pos = [], [], [], [], []
+        start = [0]
+        for ci, c in enumerate(cells):
+            nfun = np.asarray(c.nfun, dtype=np.int32)
+            order = cell_order(c.pos, c.box)
+            sub, off_c = split_rows(nfun[order])
+            a = order[sub]
+            atom.append(a)
+            off.append(off_c)
+            fun.append(nfun[a])
+            cell.append(np.full(len(a), ci))
+            pos.append(c.pos[a])
+            start.append(start[-1] + len(a))
+        i32 = lambda x: torch.as_tensor(np.concatenate(x).astype(np.int32), device=dev)  # noqa
+        self.atom_of, self.off_of, self.fun_of, self.cell_of = i32(atom), i32(off), i32(fun), i32(cell)
+        self.nfun = None
+        self.fun_rows = torch.minimum(torch.full_like(self.off_of, BLK), self.fun_of - self.off_of)
+        self.cell_start = torch.as_tensor(np.array(start, dtype=np.int32), device=dev)
+        self.cell_rows = np.array(start)
+        self.boxes = torch.as_tensor(np.array([c.box for c in cells], dtype=np.float64), device=dev)
+        self.seeds = torch.as_tensor(np.array([c.seed for c in cells], dtype=np.uint64)
+                                     .view(np.int64), device=dev)
+        self.pos = torch.as_tensor(np.ascontiguousarray(np.concatenate(pos)), dtype=torch.float64,
+                                   device=dev)
+        self.n_rows = int(self.pos.shape[0])
+        self.pS = self._neighbours_cells(self.R_S)
+        self.pH = self._neighbours_cells(self.R_H)
+        self.pL = self._neighbours_cells(self.R_L)
+        self.S = self.synth_values(0, self.pS, self.R_S, 3.0, None)
+        self.H = self.synth_values(1, self.pH, self.R_H, 2.5, None)
+
+    def _neighbours_cells(self, R):
+        n, nc = self.n_rows, len(self.cells)
+        rp = torch.empty(n + 1, dtype=torch.int32, device=self.dev)
+        nnz = c_int64(0)
+        args = (_ptr(self.pos), n, nc, _ptr(self.cell_start), _ptr(self.cell_of), _ptr(self.boxes),
+                float(R))
+        L_.call("lnv_neighbours_cells", *args, _ptr(rp), None, 0, byref(nnz), _stream())
+        col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=self.dev)
+        L_.call("lnv_neighbours_cells", *args, _ptr(rp), _ptr(col), nnz.value, byref(nnz),
+                _stream())
+        return Pattern(n, rp, col[:nnz.value])
+
+    def cell_item_ptr(self):
+        """Work items of L's pattern per cell (device [n_cells+1])."""
+        if getattr(self, "_cell_items", None) is None:
+            rows = self.pL.items.view(-1, 2)[:, 0].cpu().numpy()
+            ptr = np.searchsorted(rows, self.cell_rows, side="left").astype(np.int32)
+            self._cell_items = torch.as_tensor(ptr, device=self.dev)
+        return self._cell_items
+
+    def cell_energies(self, mixed=False):
+        """Per-cell (E, N) of a batch at the current L: one evaluation of the
+        whole batch (lnv_eval or lnv_eval_mixed), then lnv_cell_traces."""
+        if self.cells is None:
+            raise ValueError("not a batch of cells")
+        self.eval_mixed() if mixed else self.eval()
+        out = torch.empty(len(self.cells), 2, dtype=torch.float64, device=self.dev)
+        L_.call("lnv_cell_traces", byref(self.pL.struct), byref(self.ws.ev), len(self.cells),
+                _ptr(self.cell_item_ptr()), _ptr(out), _stream())
+        return out
 
     # ----------------------------------------------------------- adjoint set-up
     def adjoint_setup(self):
@@ -544,8 +642,7 @@ class LNVSystem:
             specs.update(LSL=(self.pL, self.pSL, None), HL=(self.pH, self.pL, None),
                          dH4=(self.pLSL, self.pSL, self.pH), dH6=(self.pL, self.pSL, self.pH),
                          dS4=(self.pLSL, self.pHL, self.pS), dS6=(self.pL, self.pHL, self.pS))
-        fun = (torch.minimum(torch.full_like(self.off_of, BLK),
-                             self.nfun[self.atom_of.long()] - self.off_of)).to(torch.int32)
+        fun = self.fun_rows
         for k, (A, B, M) in specs.items():
             if k not in self._alg:
                 f = c_int64(0)
@@ -588,6 +685,8 @@ class LNVSystem:
         self.k = 0
 
     def cg_step(self):
+        if self.cells is not None:
+            raise NotImplementedError("a batch of cells is evaluated, not minimised, as one system")
         o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap)
         L_.call("lnv_cg_step", byref(self.L.struct), byref(self.S.struct), byref(self.H.struct),
                 self._T(), self.n_elec, self.k, byref(o), byref(self.ws), _stream())

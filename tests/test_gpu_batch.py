@@ -1,0 +1,114 @@
+"""Batched evaluation of independent cells on the GPU.
+
+A batch is one block-diagonal system (the cells' rows one cell after
+another); every product is one launch for all cells, and lnv_cell_traces
+splits the energy and electron-number traces by cell.  Each cell is checked
+against the dense oracle of that cell alone, on the same seeded inputs: the
+S and H blocks, per-cell E and N at a seeded L (0.1 (w M + 2I) on L's range,
+the overlap generator with the cell's master seed + 1000, generated on each
+side), G and F, and the mixed-precision energy.  A batch with rows of
+different cells never couples them: the patterns are checked block-diagonal.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+import lnv_workloads as W
+from oracle import lnv as olnv
+from oracle import structure as ost
+
+pytestmark = pytest.mark.gpu
+
+
+def _cell_dense(sysg, V, pat, c, cw, check_padding=True):
+    """Dense orbital matrix of cell c from stored blocks of the batch."""
+    rp, col = pat.host()
+    V = V.detach().cpu().double().numpy()
+    r0, r1 = int(sysg.cell_rows[c]), int(sysg.cell_rows[c + 1])
+    atom = sysg.atom_of.cpu().numpy()
+    off_of = sysg.off_of.cpu().numpy()
+    off = ost.offsets(cw.nfun)
+    base = off[atom[r0:r1]] + off_of[r0:r1]
+    nv = np.minimum(4, np.asarray(cw.nfun)[atom[r0:r1]] - off_of[r0:r1])
+    A = np.zeros((int(off[-1]),) * 2)
+    for i in range(r0, r1):
+        for p in range(rp[i], rp[i + 1]):
+            j = int(col[p])
+            assert r0 <= j < r1, "rows of different cells coupled"
+            bi, ni = base[i - r0], nv[i - r0]
+            bj, nj = base[j - r0], nv[j - r0]
+            A[bi:bi + ni, bj:bj + nj] = V[p, :ni, :nj]
+            if check_padding:
+                blk = V[p].copy()
+                blk[:ni, :nj] = 0.0
+                assert not blk.any()
+    return A
+
+
+def _seeded_L(sysg):
+    Lm = sysg.synth_values(0, sysg.pL, sysg.R_L, 3.0, seed_offset=1000)
+    sysg.L.val.copy_(0.1 * Lm.val)
+
+
+def _oracle_L(cw, ref):
+    w2 = dataclasses.replace(cw, seed=cw.seed + 1000, R_S=cw.R_L)
+    rp, col = ref.pat["L"]
+    return ost.blocks_to_dense(0.1 * ost.synth_blocks(w2, "S", rp, col), rp, col, cw.nfun)
+
+
+@pytest.fixture(scope="module")
+def batch6(gpu):
+    from paper_2002_07704_amd.system import LNVSystem
+    cells = W.batch_cells("b6", 6, seed=9, n_lo=16, n_hi=48)
+    return LNVSystem(cells, metric=None), cells
+
+
+def test_batch_cells_match_oracle(batch6):
+    sysg, cells = batch6
+    _seeded_L(sysg)
+    EN = sysg.cell_energies().cpu().numpy()
+    G, F = sysg.G.val.clone(), sysg.F.val.clone()
+    EN32 = sysg.cell_energies(mixed=True).cpu().numpy()
+    torch.cuda.synchronize()
+    for c, cw in enumerate(cells):
+        ref = ost.System(cw)
+        for M, pat, R in ((sysg.S, sysg.pS, ref.S), (sysg.H, sysg.pH, ref.H)):
+            assert np.abs(_cell_dense(sysg, M.val, pat, c, cw) - R).max() <= \
+                16 * 2.0 ** -52 * np.abs(R).max()
+        Ld = _oracle_L(cw, ref)
+        assert np.abs(_cell_dense(sysg, sysg.L.val, sysg.pL, c, cw) - Ld).max() <= \
+            4 * 2.0 ** -52 * np.abs(Ld).max()
+        Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
+        print(f"cell {c} ({cw.n} atoms): E/atom gpu {EN[c, 0] / cw.n:.13f} oracle "
+              f"{Er / cw.n:.13f}  mixed {EN32[c, 0] / cw.n:.13f}", flush=True)
+        assert abs(EN[c, 0] - Er) / cw.n <= 1e-10
+        assert abs(EN[c, 1] - Nr) / cw.n <= 1e-10
+        assert abs(EN32[c, 0] - Er) / cw.n <= 1e-6
+        assert np.abs(_cell_dense(sysg, G, sysg.pL, c, cw) - Gr).max() <= 1e-12 * np.abs(Gr).max()
+        assert np.abs(_cell_dense(sysg, F, sysg.pL, c, cw) - Fr).max() <= 1e-12 * np.abs(Fr).max()
+
+
+def test_batch_of_32_cells(gpu):
+    """The 32-cell batch (64-512 atoms per cell, 10943 atoms): per-cell E and
+    N of the smallest, the largest and one more cell against the dense oracle
+    of each; the per-cell sums add up to the batch totals."""
+    from paper_2002_07704_amd.system import LNVSystem
+    cells = W.get_batch("siOH_batch32")
+    sysg = LNVSystem(cells, metric=None)
+    _seeded_L(sysg)
+    EN = sysg.cell_energies().cpu().numpy()
+    tot = sysg.EN.cpu().numpy()
+    assert abs(EN[:, 0].sum() - tot[0]) <= 1e-12 * np.abs(EN[:, 0]).sum()
+    assert abs(EN[:, 1].sum() - tot[1]) <= 1e-12 * np.abs(EN[:, 1]).sum()
+    sizes = np.array([c.n for c in cells])
+    for c in sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 5}):
+        cw = cells[c]
+        ref = ost.System(cw)
+        Ld = _oracle_L(cw, ref)
+        Er, Nr, _, _ = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
+        print(f"cell {c} ({cw.n} atoms): E/atom gpu {EN[c, 0] / cw.n:.13f} oracle "
+              f"{Er / cw.n:.13f}", flush=True)
+        assert abs(EN[c, 0] - Er) / cw.n <= 1e-10
+        assert abs(EN[c, 1] - Nr) / cw.n <= 1e-10
