@@ -121,11 +121,14 @@ def summarize_pmc(fetch_dir, write_dir, out_path, workload):
 
 def extra_configs(reps):
     """Evaluation rates of the cells with 13 and 13/9/4 support functions
-    (atoms split into 4x4-blocked rows): FP64 and mixed-precision evaluation
-    at L0 of the Hotelling metric, with the mixed energy error."""
+    (atoms split into 4x4-blocked rows) and of a batch of 32 independent
+    cells: FP64 and mixed-precision evaluation at L0 (for the batch: per-cell
+    E and N, identity start), with the mixed energy error per atom; the
+    multiply's row-cluster shape is chosen by the autotuner first."""
     import torch
 
     import lnv_workloads as W
+    from paper_2002_07704_amd import autotune
     from paper_2002_07704_amd.system import LNVSystem
     cells = [
         ("si8192_13f", W.diamond_workload("si8192_13f", (16, 16, 4), seed=3, nfun=13,
@@ -134,14 +137,19 @@ def extra_configs(reps):
          "32768 atoms: the dense index tables of 131072 rows would not fit)"),
         ("siOH8192_mixed", W.get("siOH8192_mixed"),
          "amorphous Si/O/H 40/40/20 %, 13/9/4 functions/atom, rho 0.0074 bohr^-3"),
+        ("siOH_batch32", W.get_batch("siOH_batch32"),
+         "32 independent amorphous Si/O/H cells of 64-512 atoms (13/9/4 functions), one "
+         "block-diagonal system, one launch per product for all cells"),
     ]
     res = {}
     for name, w, what in cells:
         t0 = time.perf_counter()
-        s = LNVSystem(w)
+        batch = isinstance(w, list)
+        s = LNVSystem(w, metric=None if batch else "hotelling")
         s.cg_init()
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
+        shape, tried = autotune.tune(s)
 
         def timed(fn):
             fn()
@@ -152,19 +160,28 @@ def extra_configs(reps):
             torch.cuda.synchronize()
             return (time.perf_counter() - t1) * 1e3 / reps
 
-        ms64 = timed(s.eval)
-        E64 = float(s.EN[0])
-        s.mixed_setup()
-        ms32 = timed(s.eval_mixed)
+        if batch:
+            ms64 = timed(lambda: s.cell_energies())
+            E64 = float(s.EN[0])
+            s.mixed_setup()
+            ms32 = timed(lambda: s.cell_energies(mixed=True))
+        else:
+            ms64 = timed(s.eval)
+            E64 = float(s.EN[0])
+            s.mixed_setup()
+            ms32 = timed(s.eval_mixed)
         E32 = float(s.EN[0])
         f_alg, f_pad = s.flops("eval"), s.flops("eval", padded=True)
-        res[name] = {"what": what, "atoms": w.n, "orbitals": int(w.nfun.sum()),
+        res[name] = {"what": what, "atoms": s.n,
+                     "orbitals": int(sum(int(c.nfun.sum()) for c in (w if batch else [w]))),
                      "rows": s.n_rows, "setup_s": setup,
+                     "cluster_shape": str(shape),
+                     "autotune_eval_ms": {str(k): v for k, v in tried.items()},
                      "eval_ms": ms64, "evals_per_s": 1e3 / ms64,
                      "gflop_algorithmic": f_alg / 1e9, "gflop_padded": f_pad / 1e9,
                      "tflops_algorithmic": f_alg / (ms64 * 1e-3) / 1e12,
                      "mixed_eval_ms": ms32, "mixed_evals_per_s": 1e3 / ms32,
-                     "mixed_dE_per_atom": abs(E32 - E64) / w.n}
+                     "mixed_dE_per_atom": abs(E32 - E64) / s.n}
         print(f"[bench] {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
         del s
         torch.cuda.empty_cache()

@@ -292,16 +292,9 @@ class LNVSystem:
         if metric is not None:
             self.pLL.build_items()
         assert self.pX.nnzb >= self.pZ.nnzb
+        self.cluster = None
         if cluster is not None:
-            # cluster plans of every pattern that is a left operand or an output
-            self.pH.build_lut(lut=True)
-            self.pSL.build_lut(lut=True)
-            pats = [self.pS, self.pH, self.pL, self.pSL, self.pX, self.pZ]
-            if metric is not None:
-                self.pLL.build_lut(lut=True)
-                pats.append(self.pLL)
-            for P in pats:
-                P.build_cluster(*cluster)
+            self.set_cluster(cluster)
         self.perm_SL = transpose_map(self.pSL, self.pLS)
         self.perm_X = transpose_map(self.pX, self.pXT)
         # buffers
@@ -367,7 +360,6 @@ class LNVSystem:
                     int(n_hotelling), byref(self.ws), _stream())
         self.opts = Opts()
         self.k = 0
-        self.cluster = cluster
         self.adj_ws = None
         self.ws32 = None
         torch.cuda.synchronize()
@@ -429,6 +421,35 @@ class LNVSystem:
                 byref(self.H.struct), byref(self.G.struct), byref(self.F.struct), _ptr(self.EN),
                 byref(self.ws32), _stream())
         return self.EN
+
+    # ----------------------------------------------------------- work decomposition
+    def _cluster_patterns(self):
+        """Patterns that are a left operand or an output of some multiply."""
+        pats = [self.pS, self.pH, self.pL, self.pSL, self.pX, self.pZ]
+        if self.metric is not None:
+            pats.append(self.pLL)
+        if getattr(self, "adj_ws", None) is not None:
+            pats += [self.pLSL, self.pHL]
+        return pats
+
+    def set_cluster(self, shape):
+        """Row-cluster shape of the multiply: (4, 1) (4 rows per wave, one lane
+        per output column), (8, 2) (8 rows, two lanes per column), or None
+        (one row per wave).  Rebuilds the cluster plans in place."""
+        for P in self._cluster_patterns():
+            if shape is None:
+                P.cl = None
+                P._sync()
+                continue
+            tmp = P.lut is None
+            if tmp:
+                P.build_lut(lut=True)
+            P.build_cluster(*shape)
+            if tmp:
+                P.lut = None
+                P._sync()
+        self.cluster = shape
+        torch.cuda.synchronize()
 
     # ----------------------------------------------------------- row layout
     def _layout_single(self, w, R_L, reorder):
@@ -580,8 +601,6 @@ class LNVSystem:
             self.pLSL.lut = None
             self.pLSL._sync()
             self.pHL.build_cluster(*self.cluster)
-            if self.pS.cl is None:
-                self.pS.build_cluster(*self.cluster)
         self.LSL = Matrix(self.pLSL)
         self.HL = Matrix(self.pHL)
         self.YS = torch.zeros(self.pS.nnzb, BLK, BLK, dtype=torch.float64, device=dev)

@@ -178,3 +178,26 @@ def test_split_adjoint_and_mixed(fx, request):
     Er = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)[0]
     print(f"{fx}: mixed |dE|/atom {abs(E - Er) / w.n:.2e}", flush=True)
     assert abs(E - Er) / w.n <= 1e-6
+
+
+def test_cluster_shapes_agree_and_autotune(sioh48):
+    """Every row-cluster shape of the multiply gives the same evaluation (the
+    per-entry summation order is the same: contraction index ascending), and
+    the autotuner leaves the system on the shape it timed fastest."""
+    from paper_2002_07704_amd import autotune
+    sysg, ref, lay = sioh48
+    n = lay.n_orb
+    Ld = _rand_sym(n, ref.maskL, 13) + 0.2 * np.eye(n) * ref.maskL
+    sysg.L.val.copy_(lay.to_blocks(Ld, sysg.pL))
+    out = {}
+    for shape in ((4, 1), (8, 2), None):
+        sysg.set_cluster(shape)
+        sysg.eval()
+        torch.cuda.synchronize()
+        out[shape] = (sysg.EN.clone(), sysg.G.val.clone())
+    E0, G0 = out[(4, 1)]
+    for shape, (E, G) in out.items():
+        assert torch.equal(E, E0) and torch.equal(G, G0), shape
+    best, res = autotune.tune(sysg)
+    assert best == min(res, key=res.get) and sysg.cluster == best
+    sysg.set_cluster((4, 1))
