@@ -421,8 +421,10 @@ int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm
  *  HL   values on pat(H.L)   (pattern needs lut and items; used only for dS)
  *  YS   device [nnzb_S * 16] scratch (used only for dS)
  * dS is on S's pattern (needs lut and items), dH on H's pattern (needs
- * items); either may be NULL, not both.  FP64, blk 4.  Hot path: allocates
- * nothing, no host synchronisation.
+ * items); dNS = dN/dS = 12 P_S(LSL - LSLSL) on S's pattern (N = 2 Tr[KS],
+ * for forces under the electron-number constraint).  Any of the three may be
+ * NULL, not all.  FP64, blk 4.  Hot path: allocates nothing, no host
+ * synchronisation.
  */
 typedef struct lnv_adj_ws {
   lnv_bsm SL;
@@ -432,7 +434,31 @@ typedef struct lnv_adj_ws {
 } lnv_adj_ws;
 
 int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* dS,
-                lnv_bsm* dH, const lnv_adj_ws* ws, hipStream_t s);
+                lnv_bsm* dH, lnv_bsm* dNS, const lnv_adj_ws* ws, hipStream_t s);
+
+/*
+ * lnv_forces -- forces on the atoms from the synthetic matrices' dependence
+ * on the positions (the paper's forces are the exact derivative of the
+ * energy, Sec. III.A; here S and H depend on the positions through the image
+ * weights of lnv_synth_blocks, S_ab = w_S M^S_ab + 2I, H_ab = -w_H M^H_ab):
+ *   F_a = -sum over stored blocks of <GS - mu GNS, dS/dx_a> + <GH, dH/dx_a>
+ * with dw/dx_a = sum_T exp(-d_T/decay)/decay (x_b - x_a + T)/d_T over the
+ * in-range images.  GS = dE/dS and GH = dE/dH (lnv_adjoint) give -dE/dx at
+ * fixed L; with GNS = dN/dS and mu the chemical potential of a minimum under
+ * N = N_e, the force of that constrained minimum.  GNS may be NULL.
+ *  pos, box, nfun, atom_of, off_of, seed, scale: as given to lnv_synth_blocks
+ *  GS, GNS on S's pattern, GH on H's pattern (FP64; patterns need lut)
+ *  seg_ptr, seg_atom (device [n_seg+1], [n_seg]): atom seg_atom[s] owns the
+ *      stored rows seg_ptr[s] .. seg_ptr[s+1]-1
+ *  acc: device [3 n] scratch;  F: device [3 n_atoms] output (Hartree/bohr)
+ * Fixed summation order.  Hot path for molecular dynamics: allocates nothing.
+ */
+int lnv_forces(const double* pos, const double* box, const int32_t* nfun,
+               const int32_t* atom_of, const int32_t* off_of, uint64_t seed, double scale,
+               const lnv_bsm* GS, const lnv_bsm* GNS, double mu, double R_S, double decay_S,
+               const lnv_bsm* GH, double R_H, double decay_H, int32_t n_seg,
+               const int32_t* seg_ptr, const int32_t* seg_atom, double* acc, double* F,
+               hipStream_t s);
 
 /* ------------------------------------------------------------ a5-a7: CG
  * Buffers of the conjugate-gradient minimisation (all on L's pattern unless

@@ -73,6 +73,13 @@ def grad_S(L, S, H, maskS):
     return 2.0 * (3.0 * LHL - 2.0 * (L @ S @ LHL + LHL @ S @ L)) * maskS
 
 
+def grad_N_S(L, S, maskS):
+    """dN/dS on S's range: N = 2 Tr[KS] = 6 Tr[LSLS] - 4 Tr[LSLSLS], so
+    dN/dS = 12 (LSL - LSLSL)."""
+    LSL = L @ S @ L
+    return 12.0 * (LSL - LSL @ S @ L) * maskS
+
+
 def grad_H(L, S, maskH):
     """dE/dH on H's range: 2K (E = 2 Tr[KH] is linear in H)."""
     return 2.0 * mcweeny(L, S) * maskH

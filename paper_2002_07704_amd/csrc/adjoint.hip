@@ -9,6 +9,8 @@
 // rather than kept from the evaluation (SL = S.L, LSL = L.SL, HL = H.L):
 //   dE/dH = P_H(6 L.SL - 4 LSL.SL)
 //   dE/dS = P_S(6 L.HL) - 4 (Y + Y^T),   Y = P_S(LSL.HL),  Y^T = P_S(LHLSL)
+// and, for forces at a constrained minimum, the electron-number derivative
+//   dN/dS = 12 (LSL - LSLSL) = P_S(12 L.SL - 12 LSL.SL)   (N = 2 Tr[KS])
 // so every product reads its right operand in stored orientation and the
 // transposed term costs one gather on S's own (symmetric) pattern.
 #include <hip/hip_runtime.h>
@@ -49,10 +51,12 @@ bool has(const lnv_pattern* p, bool lut, bool items) {
 }
 
 int check_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* dS,
-                  const lnv_bsm* dH, const lnv_adj_ws* ws) {
+                  const lnv_bsm* dH, const lnv_bsm* dNS, const lnv_adj_ws* ws) {
   if (!bsm_ok(L) || !bsm_ok(S) || !bsm_ok(H) || !ws) return LNV_EINVAL;
-  if (!dS && !dH) return LNV_EINVAL;
-  if ((dS && !bsm_ok(dS)) || (dH && !bsm_ok(dH))) return LNV_EINVAL;
+  if (!dS && !dH && !dNS) return LNV_EINVAL;
+  if ((dS && !bsm_ok(dS)) || (dH && !bsm_ok(dH)) || (dNS && !bsm_ok(dNS))) return LNV_EINVAL;
+  if (dNS && (dNS->blk != 4 || dNS->pat != S->pat || !has(S->pat, false, true)))
+    return LNV_EPATTERN;
   if (!bsm_ok(&ws->SL) || !bsm_ok(&ws->LSL)) return LNV_EINVAL;
   if (dS && (!bsm_ok(&ws->HL) || !ws->YS)) return LNV_EINVAL;
   if (L->blk != 4 || S->blk != 4 || H->blk != 4 || ws->SL.blk != 4 || ws->LSL.blk != 4 ||
@@ -79,8 +83,8 @@ int check_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const ln
 using namespace lnv;
 
 extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* dS,
-                           lnv_bsm* dH, const lnv_adj_ws* ws, hipStream_t s) {
-  LNV_TRY(check_adjoint(L, S, H, dS, dH, ws));
+                           lnv_bsm* dH, lnv_bsm* dNS, const lnv_adj_ws* ws, hipStream_t s) {
+  LNV_TRY(check_adjoint(L, S, H, dS, dH, dNS, ws));
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &ws->SL, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(multiply_launch(1.0, L, &ws->SL, 0, 0.0, &ws->LSL, 1, nullptr, nullptr, nullptr,
                           nullptr, s));
@@ -88,6 +92,12 @@ extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
     LNV_TRY(multiply_launch(-4.0, &ws->LSL, &ws->SL, 0, 0.0, dH, 1, nullptr, nullptr, nullptr,
                             nullptr, s));
     LNV_TRY(multiply_launch(6.0, L, &ws->SL, 0, 1.0, dH, 1, nullptr, nullptr, nullptr, nullptr,
+                            s));
+  }
+  if (dNS) {
+    LNV_TRY(multiply_launch(-12.0, &ws->LSL, &ws->SL, 0, 0.0, dNS, 1, nullptr, nullptr, nullptr,
+                            nullptr, s));
+    LNV_TRY(multiply_launch(12.0, L, &ws->SL, 0, 1.0, dNS, 1, nullptr, nullptr, nullptr, nullptr,
                             s));
   }
   if (dS) {

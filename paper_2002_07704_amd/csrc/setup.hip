@@ -410,6 +410,105 @@ __global__ __launch_bounds__(128) void k_synth(const double* __restrict__ pos, d
   }
 }
 
+// Position derivative of a synthetic matrix contracted with a gradient on its
+// pattern: for stored row i (atom a = atom_of[i]) and each block (i, j) of
+// another atom b,
+//   c = sum_rc (G_ij[r][c] - mu GN_ij[r][c] + G_ji[c][r] - mu GN_ji[c][r]) M_ab[R][C]
+//   acc_i += sign * c * dw(a,b)/dx_a,  dw/dx_a = sum_T exp(-d_T/decay)/decay (x_b - x_a + T)/d_T
+// (R, C: the entries' indices in the atom block, M from the generator's
+// counters; G_ji through G's index table; sign -1 for the Hamiltonian,
+// whose blocks are -w M).  acc (device [n][3]) accumulates: one workgroup per
+// row, fixed order.  Diagonal atom blocks do not depend on the positions.
+__global__ __launch_bounds__(128) void k_pos_grad(
+    const double* __restrict__ pos, double bx, double by, double bz,
+    const int* __restrict__ nfun, const int* __restrict__ atom_of, const int* __restrict__ off_of,
+    int blk, int n, const int* __restrict__ rp, const int* __restrict__ col,
+    const int* __restrict__ lut, const double* __restrict__ G, const double* __restrict__ GN,
+    double mu, int kind, double R, double decay, uint64_t seed, double scale,
+    double* __restrict__ acc) {
+#pragma clang fp contract(off)
+  __shared__ double sh[16];
+  const int i = blockIdx.x;
+  const uint64_t stream = kind == 0 ? 1ull : 2ull;
+  const double sign = kind == 0 ? 1.0 : -1.0;
+  const double R2 = R * R;
+  const int mx = (int)ceil(R / bx) + 1, my = (int)ceil(R / by) + 1, mz = (int)ceil(R / bz) + 1;
+  const int ai = atom_of ? atom_of[i] : i;
+  const int oi = off_of ? off_of[i] : 0;
+  const int ni = nfun ? nfun[ai] : blk;
+  double g[3] = {0.0, 0.0, 0.0};
+  for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 128) {
+    const int j = col[p];
+    const int aj = atom_of ? atom_of[j] : j;
+    if (aj == ai) continue;
+    const int oj = off_of ? off_of[j] : 0;
+    const int nj = nfun ? nfun[aj] : blk;
+    const int q = lut[(size_t)j * n + i];
+    double c = 0.0;
+    for (int r = 0; r < blk; ++r)
+      for (int cc = 0; cc < blk; ++cc) {
+        const int Rr = oi + r, Cc = oj + cc;
+        if (Rr >= ni || Cc >= nj) continue;
+        const double m = ai < aj ? rand_entry(seed, stream, ai, aj, Rr * nj + Cc, scale)
+                                 : rand_entry(seed, stream, aj, ai, Cc * ni + Rr, scale);
+        double gv = G[(size_t)p * blk * blk + r * blk + cc];
+        if (GN) gv = gv - mu * GN[(size_t)p * blk * blk + r * blk + cc];
+        if (q >= 0) {
+          double gt = G[(size_t)q * blk * blk + cc * blk + r];
+          if (GN) gt = gt - mu * GN[(size_t)q * blk * blk + cc * blk + r];
+          gv = gv + gt;
+        }
+        c = c + gv * m;
+      }
+    const double dx = pos[3 * j] - pos[3 * i];
+    const double dy = pos[3 * j + 1] - pos[3 * i + 1];
+    const double dz = pos[3 * j + 2] - pos[3 * i + 2];
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int tx = -mx; tx <= mx; ++tx)
+      for (int ty = -my; ty <= my; ++ty)
+        for (int tz = -mz; tz <= mz; ++tz) {
+          const double x = dx + (double)tx * bx;
+          const double y = dy + (double)ty * by;
+          const double z = dz + (double)tz * bz;
+          double d2 = x * x + y * y;
+          d2 = d2 + z * z;
+          if (d2 <= R2 && d2 > 0.0) {
+            const double d = sqrt(d2);
+            const double f = exp(-(d / decay)) / decay / d;
+            gx = gx + f * x;
+            gy = gy + f * y;
+            gz = gz + f * z;
+          }
+        }
+    g[0] = g[0] + sign * c * gx;
+    g[1] = g[1] + sign * c * gy;
+    g[2] = g[2] + sign * c * gz;
+  }
+  for (int k = 0; k < 3; ++k) {
+    double v = g[k];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) acc[3 * i + k] = acc[3 * i + k] + (sh[0] + sh[1]);
+  }
+}
+
+// F[seg_atom[s]] = -(sum of acc over rows seg_ptr[s] .. seg_ptr[s+1]-1).
+__global__ __launch_bounds__(64) void k_seg_force(int n_seg, const int* __restrict__ seg_ptr,
+                                                  const int* __restrict__ seg_atom,
+                                                  const double* __restrict__ acc,
+                                                  double* __restrict__ F) {
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= n_seg) return;
+  double f[3] = {0.0, 0.0, 0.0};
+  for (int r = seg_ptr[s]; r < seg_ptr[s + 1]; ++r)
+    for (int k = 0; k < 3; ++k) f[k] += acc[3 * r + k];
+  const int a = seg_atom[s];
+  for (int k = 0; k < 3; ++k) F[3 * a + k] = -f[k];
+}
+
 int read_total_int(const int32_t* dev, int64_t* host, hipStream_t s) {
   int32_t t = 0;
   LNV_HIP(hipMemcpyAsync(&t, dev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -613,6 +712,36 @@ extern "C" int lnv_synth_blocks(const double* pos, const double* box, const int3
   k_synth<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nullptr, nullptr, nullptr, nullptr,
                             nfun, atom_of, off_of, M->blk, M->pat->row_ptr, M->pat->col,
                             static_cast<double*>(M->val), kind, R, decay, seed, scale);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_forces(const double* pos, const double* box, const int32_t* nfun,
+                          const int32_t* atom_of, const int32_t* off_of, uint64_t seed,
+                          double scale, const lnv_bsm* GS, const lnv_bsm* GNS, double mu,
+                          double R_S, double decay_S, const lnv_bsm* GH, double R_H,
+                          double decay_H, int32_t n_seg, const int32_t* seg_ptr,
+                          const int32_t* seg_atom, double* acc, double* F, hipStream_t s) {
+  if (!pos || !box || !bsm_ok(GS) || !bsm_ok(GH) || !seg_ptr || !seg_atom || !acc || !F ||
+      n_seg <= 0 || !(decay_S > 0.0) || !(decay_H > 0.0))
+    return LNV_EINVAL;
+  if ((atom_of == nullptr) != (off_of == nullptr)) return LNV_EINVAL;
+  if (GNS && (!bsm_ok(GNS) || GNS->pat != GS->pat)) return LNV_EPATTERN;
+  const lnv_pattern *ps = GS->pat, *ph = GH->pat;
+  if (GS->blk != GH->blk || GS->blk <= 0 || GS->blk > 16) return LNV_EUNSUPPORTED;
+  if (ps->n != ph->n || !ps->lut || !ph->lut || !ps->row_ptr || !ph->row_ptr) return LNV_EPATTERN;
+  const int n = ps->n;
+  LNV_HIP(hipMemsetAsync(acc, 0, sizeof(double) * 3 * (size_t)n, s));
+  k_pos_grad<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, atom_of, off_of, GS->blk, n,
+                               ps->row_ptr, ps->col, ps->lut, static_cast<const double*>(GS->val),
+                               GNS ? static_cast<const double*>(GNS->val) : nullptr, mu, 0, R_S,
+                               decay_S, seed, scale, acc);
+  LNV_LAUNCH_CHECK();
+  k_pos_grad<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, atom_of, off_of, GH->blk, n,
+                               ph->row_ptr, ph->col, ph->lut, static_cast<const double*>(GH->val),
+                               nullptr, 0.0, 1, R_H, decay_H, seed, scale, acc);
+  LNV_LAUNCH_CHECK();
+  k_seg_force<<<(n_seg + 63) / 64, 64, 0, s>>>(n_seg, seg_ptr, seg_atom, acc, F);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }

@@ -108,7 +108,10 @@ SIGNATURES = {
                                        c_void_p, PBsm, c_int32, c_double, c_double, c_double,
                                        c_void_p]),
     "lnv_cell_traces": (c_int, [PPat, POINTER(LnvEvalWs), c_int32, c_void_p, c_void_p, c_void_p]),
-    "lnv_adjoint": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, POINTER(LnvAdjWs), c_void_p]),
+    "lnv_adjoint": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, PBsm, POINTER(LnvAdjWs), c_void_p]),
+    "lnv_forces": (c_int, [c_void_p, POINTER(c_double), c_void_p, c_void_p, c_void_p, c_uint64,
+                           c_double, PBsm, PBsm, c_double, c_double, c_double, PBsm, c_double,
+                           c_double, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "lnv_hotelling": (c_int, [PBsm, PBsm, c_int32, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),

@@ -621,17 +621,76 @@ class LNVSystem:
             tot += t["HL"] + t["dS4"] + t["dS6"]
         return tot
 
-    def adjoint(self, L, S, H, dS=None, dH=None):
-        """dE/dS (into dS, on S's pattern) and dE/dH (into dH, on H's pattern)
-        at the values L, S, H (tensors [nnzb, 4, 4] on this system's patterns)."""
+    def adjoint(self, L, S, H, dS=None, dH=None, dNS=None):
+        """dE/dS (into dS, on S's pattern), dE/dH (into dH, on H's pattern) and
+        dN/dS (into dNS) at the values L, S, H (tensors [nnzb, 4, 4] on this
+        system's patterns)."""
         self.adjoint_setup()
         Lm, Sm, Hm = bsm(self.pL, L), bsm(self.pS, S), bsm(self.pH, H)
-        dSm = bsm(self.pS, dS) if dS is not None else None
-        dHm = bsm(self.pH, dH) if dH is not None else None
-        L_.call("lnv_adjoint", byref(Lm.struct), byref(Sm.struct), byref(Hm.struct),
-                byref(dSm.struct) if dSm is not None else None,
-                byref(dHm.struct) if dHm is not None else None, byref(self.adj_ws), _stream())
+        ref = [byref(bsm(P, t).struct) if t is not None else None
+               for P, t in ((self.pS, dS), (self.pH, dH), (self.pS, dNS))]
+        L_.call("lnv_adjoint", byref(Lm.struct), byref(Sm.struct), byref(Hm.struct), *ref,
+                byref(self.adj_ws), _stream())
         return dS, dH
+
+    # ----------------------------------------------------------- forces
+    def _segments(self):
+        """Stored rows of each atom (consecutive): (seg_ptr, seg_atom) on device."""
+        if getattr(self, "_seg", None) is None:
+            if self.atom_of is None:
+                atom = np.arange(self.n_rows)
+            else:
+                atom = self.atom_of.cpu().numpy()
+            first = np.concatenate([[True], atom[1:] != atom[:-1]])
+            starts = np.nonzero(first)[0]
+            seg_ptr = np.append(starts, len(atom)).astype(np.int32)
+            seg_atom = atom[starts].astype(np.int32)
+            assert len(np.unique(seg_atom)) == len(seg_atom) == self.n
+            self._seg = (torch.as_tensor(seg_ptr, device=self.dev),
+                         torch.as_tensor(seg_atom, device=self.dev))
+        return self._seg
+
+    def forces(self, L=None, mu=None):
+        """Forces on the atoms [n_atoms, 3] (Hartree/bohr, original atom order)
+        from the synthetic S(x), H(x) at fixed L (default: the current L):
+        -dE/dx, or with mu the force of a minimum under N = N_e, -(dE/dx -
+        mu dN/dx).  Adjoint (lnv_adjoint) plus lnv_forces."""
+        if self.cells is not None:
+            raise NotImplementedError("forces of a batch of cells")
+        self.adjoint_setup()
+        if self.pH.lut is None:
+            self.pH.build_lut(lut=True)
+        Lv = self.L.val if L is None else L
+        dS = torch.empty_like(self.S.val)
+        dH = torch.empty_like(self.H.val)
+        dNS = torch.empty_like(self.S.val) if mu is not None else None
+        self.adjoint(Lv, self.S.val, self.H.val, dS=dS, dH=dH, dNS=dNS)
+        seg_ptr, seg_atom = self._segments()
+        acc = torch.empty(self.n_rows * 3, dtype=torch.float64, device=self.dev)
+        F = torch.empty(self.n, 3, dtype=torch.float64, device=self.dev)
+        box_c = (c_double * 3)(*self.box)
+        gS, gH = bsm(self.pS, dS), bsm(self.pH, dH)
+        gN = bsm(self.pS, dNS) if dNS is not None else None
+        L_.call("lnv_forces", _ptr(self.pos), box_c, _ptr(self.nfun), _ptr(self.atom_of),
+                _ptr(self.off_of), int(self.seed), float(self.scale), byref(gS.struct),
+                byref(gN.struct) if gN is not None else None, float(mu or 0.0),
+                float(self.R_S), 3.0, byref(gH.struct), float(self.R_H), 2.5,
+                int(seg_ptr.numel() - 1), _ptr(seg_ptr), _ptr(seg_atom), _ptr(acc), _ptr(F),
+                _stream())
+        return F
+
+    def move_atoms(self, pos):
+        """New atomic positions [n_atoms, 3] (original order): S and H are
+        generated again at the new positions on the existing range patterns
+        (the caller keeps the displacement below the distance of every pair
+        from its cutoff, or builds a new system)."""
+        if self.cells is not None:
+            raise NotImplementedError("moving the atoms of a batch of cells")
+        pos = np.ascontiguousarray(pos, dtype=np.float64)
+        rows = pos if self.atom_of is None else pos[self.atom_of.cpu().numpy()]
+        self.pos.copy_(torch.as_tensor(np.ascontiguousarray(rows)))
+        self.S.rebind(self.synth_values(0, self.pS, self.R_S, 3.0).val)
+        self.H.rebind(self.synth_values(1, self.pH, self.R_H, 2.5).val)
 
     def eval_values(self, L, S, H, G, F, EN):
         """lnv_eval at the given value tensors (on this system's patterns)."""

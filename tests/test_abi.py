@@ -63,10 +63,13 @@ def test_host_side_argument_errors(lib):
     o = L.LnvOpts(40, 1e-11, 0.1)
     assert lib.lnv_cg_step(ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), None, 8.0, 0, ctypes.byref(o), None, None) == L.EINVAL
     assert lib.lnv_hotelling(ctypes.byref(m), ctypes.byref(m), -1, None, None) == L.EINVAL
-    assert lib.lnv_adjoint(None, None, None, None, None, None, None) == L.EINVAL
+    assert lib.lnv_adjoint(None, None, None, None, None, None, None, None) == L.EINVAL
     ws = L.LnvAdjWs()
-    assert lib.lnv_adjoint(ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), None, None,
+    assert lib.lnv_adjoint(ctypes.byref(m), ctypes.byref(m), ctypes.byref(m), None, None, None,
                            ctypes.byref(ws), None) == L.EINVAL
+    box = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    assert lib.lnv_forces(None, box, None, None, None, 1, 1.0, None, None, 0.0, 12.0, 3.0, None,
+                          14.0, 2.5, 1, None, None, None, None, None) == L.EINVAL
     assert lib.lnv_partials_len(10) >= 12 * 8 * 1024
 
 

@@ -354,3 +354,55 @@ def test_row_oracle_equals_dense_oracle(name):
             assert np.abs(Gb[t, :, :nj] - ref_g).max() <= 1e-12 * np.abs(G).max()
             assert np.abs(Fb[t, :, :nj] - ref_f).max() <= 1e-12 * np.abs(F).max()
     assert abs(es - E) <= 1e-11 * abs(E) and abs(ns - N) <= 1e-11 * abs(N)
+
+
+@pytest.mark.parametrize("name", ["si8_4x4", "siOH24"])
+def test_synthetic_forces_central_differences(name):
+    """dE/dx at fixed L (oracle.forces) against central differences of the
+    dense energy with S and H regenerated at displaced positions; the 8-atom
+    cell has many periodic images of each pair inside the ranges."""
+    import dataclasses
+    from oracle import forces as of
+    w = W.amorphous_workload("siOH24", 24, seed=5) if name == "siOH24" else W.get(name)
+    sysd = st.System(w)
+    n = sysd.S.shape[0]
+    rng = np.random.default_rng(7)
+    C = rng.standard_normal((n, n)) * 0.05
+    L = ((C + C.T) * 0.5 + 0.2 * np.eye(n)) * sysd.maskL
+    gS = lnv.grad_S(L, sysd.S, sysd.H, sysd.maskS)
+    gH = lnv.grad_H(L, sysd.S, sysd.maskH)
+    dEdx = of.energy_gradient_positions(w, gS, gH)
+    h = 1e-5
+    for a in (0, 3, w.n - 1):
+        for k in range(3):
+            E = []
+            for sg in (1.0, -1.0):
+                pos = w.pos.copy()
+                pos[a, k] += sg * h
+                w2 = dataclasses.replace(w, pos=pos)
+                s2 = st.System(w2)
+                for key in ("S", "H", "L"):
+                    assert all(np.array_equal(x, y) for x, y in zip(s2.pat[key], sysd.pat[key]))
+                E.append(lnv.evaluate(L, s2.S, s2.H, sysd.maskL)[0])
+            fd = (E[0] - E[1]) / (2 * h)
+            assert abs(fd - dEdx[a, k]) <= 1e-7 * max(1.0, np.abs(dEdx).max()), (a, k, fd, dEdx[a, k])
+    # translation invariance: the gradient sums to zero
+    assert np.abs(dEdx.sum(axis=0)).max() <= 1e-11 * np.abs(dEdx).max()
+
+
+def test_dN_dS_central_differences():
+    w = W.get("si8_4x4")
+    sysd = st.System(w)
+    n = sysd.S.shape[0]
+    rng = np.random.default_rng(11)
+    C = rng.standard_normal((n, n)) * 0.05
+    L = ((C + C.T) * 0.5 + 0.2 * np.eye(n)) * sysd.maskL
+    g = lnv.grad_N_S(L, sysd.S, sysd.maskS)
+    h = 1e-6
+    for (a, b) in ((0, 0), (1, 5), (7, 30), (12, 3)):
+        Sp, Sm = sysd.S.copy(), sysd.S.copy()
+        Sp[a, b] += h
+        Sm[a, b] -= h
+        fd = (lnv.evaluate(L, Sp, sysd.H, sysd.maskL)[1]
+              - lnv.evaluate(L, Sm, sysd.H, sysd.maskL)[1]) / (2 * h)
+        assert abs(fd - g[a, b]) <= 1e-7 * max(1.0, abs(g[a, b])), (a, b, fd, g[a, b])
