@@ -249,6 +249,16 @@ int lnv_bsm_transpose(const lnv_bsm* A, const int32_t* perm, lnv_bsm* AT, hipStr
  * number of blocks).  Hot path (HBM-bound). */
 int lnv_bsm_convert(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
 
+/* lnv_bsm_lincomb -- out = a X + b Y + c Z elementwise on one pattern (Y, Z
+ * may be NULL; out may alias any input).  FP64.  Hot path (HBM-bound). */
+int lnv_bsm_lincomb(double a, const lnv_bsm* X, double b, const lnv_bsm* Y, double c,
+                    const lnv_bsm* Z, lnv_bsm* out, hipStream_t s);
+
+/* lnv_bsm_norm_inf -- out[0] = max_a sum_b |A_ab| (the matrix infinity norm,
+ * over orbital rows).  partials: device [A.pat->n] scratch; out: device.
+ * FP64, blk 4. */
+int lnv_bsm_norm_inf(const lnv_bsm* A, double* partials, double* out, hipStream_t s);
+
 /* lnv_set_f32_accumulation -- arithmetic of the FP32 products (process-wide):
  * LNV_ACC_F32 (the default): FP32 multiply-add into FP32 accumulators;
  * LNV_ACC_F64: FP64 multiply-add into FP64 accumulators (the product of two

@@ -382,6 +382,20 @@ __global__ __launch_bounds__(256) void k_nassemble(
   }
 }
 
+// out = a X + b Y + c Z elementwise (Y, Z nullable), grid-stride.
+__global__ __launch_bounds__(256) void k_lincomb(int64_t nv, double a, const double* __restrict__ X,
+                                                 double b, const double* __restrict__ Y, double c,
+                                                 const double* __restrict__ Z,
+                                                 double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = a * X[e];
+    if (Y) v = fma(b, Y[e], v);
+    if (Z) v = fma(c, Z[e], v);
+    out[e] = v;
+  }
+}
+
 // Per-cell energy and electron number of a batch of independent cells from
 // the trace partials k_assemble leaves (slots 0..3 = <L,X>, <L,Y>, <L,Z>,
 // <L,V> per item of L's pattern): workgroup c sums the items of cell c,
@@ -943,6 +957,38 @@ extern "C" int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm*
             ws->scalars};
   return eval_products<float>(L, o, static_cast<double*>(G->val), static_cast<double*>(F->val),
                               EN, s);
+}
+
+extern "C" int lnv_bsm_lincomb(double a, const lnv_bsm* X, double b, const lnv_bsm* Y, double c,
+                               const lnv_bsm* Z, lnv_bsm* out, hipStream_t s) {
+  if (!bsm_ok(X) || !bsm_ok(out) || (Y && !bsm_ok(Y)) || (Z && !bsm_ok(Z))) return LNV_EINVAL;
+  const int64_t nb = X->pat->nnzb;
+  if (out->pat->nnzb != nb || (Y && Y->pat->nnzb != nb) || (Z && Z->pat->nnzb != nb) ||
+      X->blk != out->blk || (Y && Y->blk != X->blk) || (Z && Z->blk != X->blk))
+    return LNV_EPATTERN;
+  const int64_t nv = nb * X->blk * X->blk;
+  if (nv == 0) return LNV_OK;
+  k_lincomb<<<vec_grid(), 256, 0, s>>>(nv, a, static_cast<const double*>(X->val), b,
+                                       Y ? static_cast<const double*>(Y->val) : nullptr, c,
+                                       Z ? static_cast<const double*>(Z->val) : nullptr,
+                                       static_cast<double*>(out->val));
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_bsm_norm_inf(const lnv_bsm* A, double* partials, double* out, hipStream_t s) {
+  if (!bsm_ok(A) || !partials || !out) return LNV_EINVAL;
+  if (A->blk != 4) return LNV_EUNSUPPORTED;
+  const lnv_pattern* pa = A->pat;
+  if (!pa->row_ptr) return LNV_EPATTERN;
+  k_rowabs<<<pa->n, 256, 0, s>>>(pa->row_ptr, static_cast<const double*>(A->val), partials);
+  LNV_LAUNCH_CHECK();
+  RedList rl = reds();
+  add(rl, 0, pa->n, 1, 0, 1);
+  StageArgs sa{};
+  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
 }
 
 extern "C" int lnv_cell_traces(const lnv_pattern* PL, const lnv_eval_ws* ws, int32_t n_cells,

@@ -116,6 +116,8 @@ SIGNATURES = {
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
                             POINTER(LnvCgWs), c_void_p]),
+    "lnv_bsm_lincomb": (c_int, [c_double, PBsm, c_double, PBsm, c_double, PBsm, PBsm, c_void_p]),
+    "lnv_bsm_norm_inf": (c_int, [PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_set_kslabs": (c_int, [c_int32]),
     "lnv_set_f32_accumulation": (c_int, [c_int32]),
     "lnv_timing_enable": (c_int, [c_int32]),

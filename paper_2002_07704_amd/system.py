@@ -762,6 +762,14 @@ class LNVSystem:
                 self.n_elec, byref(self.ws), _stream())
         self.k = 0
 
+    def cg_restart(self):
+        """Start a new minimisation from the current L (e.g. a purified start):
+        the next step is iteration 0 (steepest descent, no history) with the
+        status bits cleared."""
+        self.scalars[L_.SC["STATUS"]] = 0.0
+        self.scalars[L_.SC["FORCE_RESET"]] = 0.0
+        self.k = 0
+
     def cg_step(self):
         if self.cells is not None:
             raise NotImplementedError("a batch of cells is evaluated, not minimised, as one system")

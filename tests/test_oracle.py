@@ -406,3 +406,23 @@ def test_dN_dS_central_differences():
         fd = (lnv.evaluate(L, Sp, sysd.H, sysd.maskL)[1]
               - lnv.evaluate(L, Sm, sysd.H, sysd.maskL)[1]) / (2 * h)
         assert abs(fd - g[a, b]) <= 1e-7 * max(1.0, abs(g[a, b])), (a, b, fd, g[a, b])
+
+
+def test_purification_reaches_exact_density_untruncated():
+    """Canonical purification (oracle/pm.py) with T = S^-1 and L covering the
+    8-atom cube: K becomes the exact Gamma-point density matrix (the theta
+    lowest generalised eigenvectors), so 2 Tr[KS] = N_e, KSK = K, E = 2 Tr[KH]
+    is the exact band energy and the LNV gradient vanishes there."""
+    from oracle import pm as opm
+    w = W.get("si8_4x4", R_L=1000.0)
+    sy = st.System(w, R_L=1000.0)
+    T = np.linalg.inv(sy.S)
+    K, hist, info = opm.purify(sy.S, sy.H, T, sy.maskL, w.n_elec, 200)
+    Kx, Ex, gap, _ = lnv.exact_density(sy.H, sy.S, w.n_elec)
+    assert gap >= 1e-2 and hist[-1]["c"] is None and len(hist) < 60
+    assert np.abs(K - Kx).max() <= 1e-10
+    assert abs(2.0 * np.sum(K * sy.S) - w.n_elec) <= 1e-10 * w.n_elec
+    assert np.abs(K @ sy.S @ K - K).max() <= 1e-10
+    E, N, G, F = lnv.evaluate(K, sy.S, sy.H, sy.maskL)
+    assert abs(E - Ex) <= 1e-10 * abs(Ex) and np.abs(G).max() <= 1e-9
+    assert all(h["c"] is None or 0.0 <= h["c"] <= 1.0 for h in hist)
