@@ -4,14 +4,14 @@ Workload: 4096-atom periodic diamond-Si cell (8x8x8 conventional cubes,
 a = 10.26 bohr, +-0.1 bohr seeded displacements), 4 support functions per
 atom (FP64 4x4 blocks, 16384 orbitals), ranges S/H/L = 12/14/16 bohr,
 products at natural range, N_e = 16384, Hotelling metric T ~ S^-1 on L's
-range.  One step = the initial L0 = lambda T followed by one full CG
-iteration: energy + gradient evaluation (six block-sparse products with fused
-traces), metric gradients P_L(TGT), P_L(TFT), projection, Polak-Ribiere
-direction, exact cubic line minimisation and the cubic electron-number
-correction.  Starting every step from L0 makes every timed step do the whole
-hot path: on this synthetic Hamiltonian (no gap at half filling) the LNV
-functional has runaway directions after a few iterations, where the CG
-stalls with a zero step and skips the correction.
+range.  The minimisation starts from the purified density matrix (canonical
+purification with the metric, 60 steps, outside the timed region); the
+timed run is K consecutive CG iterations from it (the workload's "one
+evaluation plus 10 CG steps" with K = 10).  One step = energy + gradient
+evaluation (six block-sparse products with fused traces), metric gradients
+P_L(TGT), P_L(TFT), projection, Polak-Ribiere direction, exact cubic line
+minimisation and the cubic electron-number correction.  Warm-up steps and
+the second (event-timed) pass restart from the same purified L.
 Inputs are resident in HBM before the timed region.
 
 Prints one JSON line; `value` is energy+gradient evaluations per second
@@ -227,15 +227,27 @@ def main():
     sysg = LNVSystem(w)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    sysg.cg_init()
     print(f"[bench] setup {setup_s:.2f} s; triples {sysg.triples}", file=sys.stderr, flush=True)
+    from paper_2002_07704_amd.pm import pm_initial_L
+    t0 = time.perf_counter()
+    pm_hist, _ = pm_initial_L(sysg, 60)
+    torch.cuda.synchronize()
+    pm_s = time.perf_counter() - t0
+    L_start = sysg.L.val.clone()
+    sysg.eval()
+    e_start = float(sysg.EN[0].item())
+
+    def restart():
+        sysg.L.val.copy_(L_start)
+        sysg.cg_restart()
 
     def step():
-        sysg.cg_init()
         sysg.cg_step()
 
+    restart()
     for _ in range(args.warmup):
         step()
+    restart()
     torch.cuda.synchronize()
     sysg.scalars[L_.SC["NCORR"]] = 0.0
     if args.pmc_probe:
@@ -263,11 +275,14 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     status = int(sysg.scalar("STATUS"))
     n_corr = int(sysg.scalar("NCORR"))
-    flops_run = (args.steps * (sysg.flops("init") + sysg.flops("step_base"))
-                 + n_corr * sysg.flops("ncorr"))
+    flops_run = args.steps * sysg.flops("step_base") + n_corr * sysg.flops("ncorr")
     flops_step = flops_run / args.steps
+    sysg.eval()
+    torch.cuda.synchronize()
+    e_end = float(sysg.EN[0])
 
     # the same steps again with HIP events around every multiply launch
+    restart()
     lib.lnv_timing_reset()
     lib.lnv_timing_enable(1)
     for _ in range(args.steps):
@@ -364,10 +379,14 @@ def main():
         "config": {
             "workload": f"{w.name}: {w.n}-atom diamond Si, 4x4 FP64 blocks ({w.n_orb} orbitals), "
                         f"R_S/R_H/R_L {w.R_S:g}/{w.R_H:g}/{w.R_L:g} bohr, natural-range products",
-            "step": "L0 = lambda*T, then one CG iteration: eval (6 products) + metric P_L(TGT), "
-                    "P_L(TFT) + projection + exact cubic line search + electron-number correction",
+            "step": "one CG iteration: eval (6 products) + metric P_L(TGT), P_L(TFT) + "
+                    "projection + exact cubic line search + electron-number correction; "
+                    f"{args.steps} consecutive iterations from the purified start",
             "metric": "Hotelling T ~ S^-1 on L's range (16 steps, once per geometry)",
+            "start": f"canonical purification, {len(pm_hist)} steps, {pm_s:.2f} s (not timed)",
             "n_corrections": n_corr,
+            "E_per_atom_start": e_start / w.n,
+            "E_per_atom_after_steps": e_end / w.n,
             "atoms": w.n, "n_elec": w.n_elec,
         },
         "gflops_per_s": flops_step / (ms_per_step * 1e-3) / 1e9,

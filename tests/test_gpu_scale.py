@@ -140,3 +140,31 @@ def test_eval_mixed_against_fp64_at_scale(gpu, acc):
             assert eG <= tol and eF <= tol
     finally:
         L.call("lnv_set_f32_accumulation", 0)
+
+
+def test_cg_from_purified_start_at_scale(gpu):
+    """The 4096-atom cell from the canonical-purification start: the CG
+    descends at every step with an admissible line minimum, and the electron
+    number is exact after every step (the correction is applied), as in the
+    benchmark's timed run.  From L0 = lambda T the same CG stalls after two
+    steps (no local minimum of the line cubic), which is why the start matters."""
+    from paper_2002_07704_amd.pm import pm_initial_L
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.get("si4096_4x4")
+    s = LNVSystem(w)
+    hist, _ = pm_initial_L(s, 60)
+    assert all(h["c"] is None or 0.0 <= h["c"] <= 1.0 for h in hist)
+    s.cg_restart()
+    E = []
+    for k in range(6):
+        s.cg_step()
+        sc = s.scalars_host()
+        E.append(sc["E"])
+        assert int(sc["STATUS"]) == 0, (k, sc["STATUS"])
+        assert sc["ALPHA"] > 0.0
+    s.eval()
+    torch.cuda.synchronize()
+    E.append(float(s.EN[0]))
+    assert abs(float(s.EN[1]) - w.n_elec) <= 1e-9 * w.n_elec
+    assert all(b < a for a, b in zip(E[1:], E[2:])), [e / w.n for e in E]
+    print("E/atom from the purified start:", [round(e / w.n, 10) for e in E], flush=True)
