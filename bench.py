@@ -172,6 +172,28 @@ def extra_configs(reps):
             ms32 = timed(s.eval_mixed)
         E32 = float(s.EN[0])
         f_alg, f_pad = s.flops("eval"), s.flops("eval", padded=True)
+        cg = None
+        if not batch:
+            # CG iterations from the canonical-purification start
+            from paper_2002_07704_amd.pm import pm_initial_L
+            t1 = time.perf_counter()
+            pm_hist, _ = pm_initial_L(s, 60)
+            pm_s = time.perf_counter() - t1
+            s.cg_restart()
+            s.cg_step()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            n_cg = 3
+            for _ in range(n_cg):
+                s.cg_step()
+            torch.cuda.synchronize()
+            ms_cg = (time.perf_counter() - t1) * 1e3 / n_cg
+            s.eval()
+            torch.cuda.synchronize()
+            cg = {"purification_steps": len(pm_hist), "purification_s": pm_s,
+                  "cg_step_ms": ms_cg, "cg_steps_per_s": 1e3 / ms_cg,
+                  "E_per_atom_after_4_steps": float(s.EN[0]) / s.n,
+                  "N_after_4_steps": float(s.EN[1]), "n_elec": s.n_elec}
         res[name] = {"what": what, "atoms": s.n,
                      "orbitals": int(sum(int(c.nfun.sum()) for c in (w if batch else [w]))),
                      "rows": s.n_rows, "setup_s": setup,
@@ -181,7 +203,8 @@ def extra_configs(reps):
                      "gflop_algorithmic": f_alg / 1e9, "gflop_padded": f_pad / 1e9,
                      "tflops_algorithmic": f_alg / (ms64 * 1e-3) / 1e12,
                      "mixed_eval_ms": ms32, "mixed_evals_per_s": 1e3 / ms32,
-                     "mixed_dE_per_atom": abs(E32 - E64) / s.n}
+                     "mixed_dE_per_atom": abs(E32 - E64) / s.n,
+                     "cg_from_purified_start": cg}
         print(f"[bench] {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
         del s
         torch.cuda.empty_cache()
