@@ -254,6 +254,11 @@ int lnv_bsm_convert(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
 int lnv_bsm_lincomb(double a, const lnv_bsm* X, double b, const lnv_bsm* Y, double c,
                     const lnv_bsm* Z, lnv_bsm* out, hipStream_t s);
 
+/* lnv_bsm_remap -- B = A carried over to B's pattern (same atoms, e.g. the
+ * range pattern of a new geometry): blocks of B present in A's pattern are
+ * copied, the others are zero.  A's pattern needs lut.  FP64, blk 4. */
+int lnv_bsm_remap(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
+
 /* lnv_bsm_norm_inf -- out[0] = max_a sum_b |A_ab| (the matrix infinity norm,
  * over orbital rows).  partials: device [A.pat->n] scratch; out: device.
  * FP64, blk 4. */

@@ -58,13 +58,13 @@ def energy_gradient_positions(w, gS, gH):
                                             ("H", gH, W.STREAM_H, 2.5, w.R_H, -1.0)):
         rp, col = st.neighbours(w.pos, w.box, R)
         for i in range(w.n):
-            for j in col[rp[i]:rp[i + 1]]:
-                j = int(j)
-                if j == i:
-                    continue
+            js = [int(j) for j in col[rp[i]:rp[i + 1]] if j != i]
+            if not js:
+                continue
+            dws = weight_grad(w.pos[js] - w.pos[i], w.box, R, decay)
+            for j, dw in zip(js, dws):
                 M = st.random_block(w.seed, stream, i, j, int(nf[i]), int(nf[j]), w.scale)
                 c = sign * float(np.sum(g[off[i]:off[i + 1], off[j]:off[j + 1]] * M))
-                dw = weight_grad(w.pos[j] - w.pos[i], w.box, R, decay)
                 # block (i, j) depends on x_i through dw and on x_j through -dw
                 out[i] += c * dw
                 out[j] -= c * dw

@@ -382,6 +382,22 @@ __global__ __launch_bounds__(256) void k_nassemble(
   }
 }
 
+// B on its own pattern from A on another pattern of the same atoms: blocks
+// present in both are copied, the others set to zero.  Workgroup per row of
+// B, 16 threads per block.
+__global__ __launch_bounds__(256) void k_remap(int n, const int* __restrict__ b_rp,
+                                               const int* __restrict__ b_col,
+                                               const int* __restrict__ a_lut,
+                                               const double* __restrict__ A,
+                                               double* __restrict__ B) {
+  const int i = blockIdx.x;
+  const int e = threadIdx.x & 15;
+  for (int p = b_rp[i] + (threadIdx.x >> 4); p < b_rp[i + 1]; p += 16) {
+    const int q = a_lut[(size_t)i * n + b_col[p]];
+    B[(size_t)p * 16 + e] = q >= 0 ? A[(size_t)q * 16 + e] : 0.0;
+  }
+}
+
 // out = a X + b Y + c Z elementwise (Y, Z nullable), grid-stride.
 __global__ __launch_bounds__(256) void k_lincomb(int64_t nv, double a, const double* __restrict__ X,
                                                  double b, const double* __restrict__ Y, double c,
@@ -972,6 +988,18 @@ extern "C" int lnv_bsm_lincomb(double a, const lnv_bsm* X, double b, const lnv_b
                                        Y ? static_cast<const double*>(Y->val) : nullptr, c,
                                        Z ? static_cast<const double*>(Z->val) : nullptr,
                                        static_cast<double*>(out->val));
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_bsm_remap(const lnv_bsm* A, lnv_bsm* B, hipStream_t s) {
+  if (!bsm_ok(A) || !bsm_ok(B)) return LNV_EINVAL;
+  if (A->blk != 4 || B->blk != 4) return LNV_EUNSUPPORTED;
+  if (A->pat->n != B->pat->n || !A->pat->lut || !B->pat->row_ptr || !B->pat->col)
+    return LNV_EPATTERN;
+  k_remap<<<B->pat->n, 256, 0, s>>>(B->pat->n, B->pat->row_ptr, B->pat->col, A->pat->lut,
+                                    static_cast<const double*>(A->val),
+                                    static_cast<double*>(B->val));
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }

@@ -118,6 +118,7 @@ SIGNATURES = {
                             POINTER(LnvCgWs), c_void_p]),
     "lnv_bsm_lincomb": (c_int, [c_double, PBsm, c_double, PBsm, c_double, PBsm, PBsm, c_void_p]),
     "lnv_bsm_norm_inf": (c_int, [PBsm, c_void_p, c_void_p, c_void_p]),
+    "lnv_bsm_remap": (c_int, [PBsm, PBsm, c_void_p]),
     "lnv_set_kslabs": (c_int, [c_int32]),
     "lnv_set_f32_accumulation": (c_int, [c_int32]),
     "lnv_timing_enable": (c_int, [c_int32]),

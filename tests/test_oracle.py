@@ -426,3 +426,40 @@ def test_purification_reaches_exact_density_untruncated():
     E, N, G, F = lnv.evaluate(K, sy.S, sy.H, sy.maskL)
     assert abs(E - Ex) <= 1e-10 * abs(Ex) and np.abs(G).max() <= 1e-9
     assert all(h["c"] is None or 0.0 <= h["c"] <= 1.0 for h in hist)
+
+
+def test_xlbomd_recursion_properties():
+    """The X recursion of oracle/xlbomd.py: a constant history at the harmonic
+    centre stays there (the dissipation coefficients sum to zero); without
+    dissipation the recursion is time reversible (X(t+dt) + X(t-dt) depends
+    only on X(t) and LS); the dissipation vanishes on a history linear in
+    time (sum c_m = sum m c_m = 0) and the K = 5 coefficients are the
+    published ones."""
+    from oracle import xlbomd as ox
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((6, 6))
+    assert np.allclose(ox.propagate([A] * 6, A), A, atol=1e-14)
+    X0, X1, LS = (rng.standard_normal((6, 6)) for _ in range(3))
+    hist = [X1, X0] + [X0] * 4
+    fwd = ox.propagate(hist, LS, alpha=0.0)
+    back = ox.propagate([X1, fwd] + [X0] * 4, LS, alpha=0.0)
+    assert np.allclose(back, X0, atol=1e-12)
+    c = np.array(ox.COEFFS)
+    assert c.sum() == 0.0 and (np.arange(6) * c).sum() == 0.0
+    assert (ox.KAPPA, ox.ALPHA) == (1.82, 0.018)
+
+
+def test_xlbomd_conserves_energy_si64():
+    """Three velocity-Verlet steps of XLBOMD on the 64-atom cell at 300 K with
+    25 CG iterations per step: the total energy (band energy + kinetic) stays
+    within 1% of the kinetic energy exchanged, which wrong forces (a sign, a
+    missing term) would violate by order one."""
+    from oracle import xlbomd as ox
+    w = W.get("si64_4x4")
+    out = ox.run(w, W.masses(w), W.thermal_velocities(w, 300.0, 1), 20.0, 3, cg_steps=25)
+    e0 = out[0]["E"] + out[0]["ekin"]
+    dk = abs(out[-1]["ekin"] - out[0]["ekin"])
+    assert dk > 1e-4
+    for o in out:
+        assert abs(o["N"] - w.n_elec) <= 1e-9 * w.n_elec
+        assert abs(o["E"] + o["ekin"] - e0) <= 0.01 * dk
