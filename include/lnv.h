@@ -164,6 +164,11 @@ int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
 int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B, const lnv_pattern* mask,
                       const int32_t* row_fun, int64_t* flops_out, hipStream_t s);
 
+/* lnv_pattern_upper -- upper triangle of P (row i keeps its columns j >= i);
+ * two-phase like lnv_neighbours (col == NULL counts).  Synchronises s. */
+int lnv_pattern_upper(const lnv_pattern* P, int32_t* row_ptr, int32_t* col, int64_t cap,
+                      int64_t* nnz_out, hipStream_t s);
+
 /* lnv_pattern_lut -- fill the index tables of P (either may be NULL). */
 int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t, hipStream_t s);
 
@@ -309,6 +314,17 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  *  partials  device [partials_len] scratch, partials_len >=
  *            lnv_partials_len(max(n_items, n_cl_items) of L's pattern)
  *  scalars   device [LNV_NSCALARS] FP64 (see LNV_SC_*)
+ * Symmetric products (optional, val == NULL: not used): Z = SLS, W = P_L(SLHLS)
+ * and V = P_L(SLSLS) are symmetric for symmetric L, S, H, so only their
+ * upper-triangle blocks (j >= i) need forming; the rest is their transpose.
+ *  Zu  values on the upper triangle of Z's pattern (lnv_pattern_upper; needs
+ *      items, and the cluster plan of the other outputs), dtype of Z
+ *  Lu  values on the upper triangle of L's pattern (same needs): W's upper
+ *      blocks; Vu (device [nnzb of Lu * 16], dtype of W) V's
+ * Z, W, V are then filled by a transposing copy (Z's and L's patterns need
+ * lut and items and must be symmetric; a block whose transpose is missing
+ * comes out NaN).  lnv_cg_step uses the same buffers for the electron-number
+ * check (Z, V at the new L) and Lu for the metric products P_L(T G T).
  */
 typedef struct lnv_eval_ws {
   lnv_bsm SL;
@@ -324,6 +340,9 @@ typedef struct lnv_eval_ws {
   double* partials;
   int64_t partials_len;
   double* scalars;
+  lnv_bsm Zu;
+  lnv_bsm Lu;
+  void* Vu;
 } lnv_eval_ws;
 
 #define LNV_NSLOTS 12
@@ -417,6 +436,9 @@ typedef struct lnv_eval32_ws {
   double* partials;
   int64_t partials_len;
   double* scalars;
+  lnv_bsm Zu;   /* optional upper-triangle products, as in lnv_eval_ws (FP32) */
+  lnv_bsm Lu;
+  void* Vu;
 } lnv_eval32_ws;
 
 int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,

@@ -398,6 +398,46 @@ __global__ __launch_bounds__(256) void k_remap(int n, const int* __restrict__ b_
   }
 }
 
+// Full symmetric matrix F from its upper-triangle blocks U (pattern of U =
+// blocks j >= i of F's symmetric pattern): F_ij = U_ij for j > i, U_ji^T for
+// j < i, (U_ii + U_ii^T)/2 on the diagonal.  The position of (i, j), j >= i, in U is its position in F shifted
+// by the lower-triangle blocks of row i: rpU[i] + posF(i,j) - (rpF[i+1] -
+// (rpU[i+1] - rpU[i])).  Workgroup per item of F, 16 threads per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mirror(int n, const int* __restrict__ items,
+                                                const int* __restrict__ rpF,
+                                                const int* __restrict__ colF,
+                                                const int* __restrict__ lutF,
+                                                const int* __restrict__ rpU,
+                                                const T* __restrict__ U, T* __restrict__ F) {
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rpF[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  if (b >= cnt) return;
+  const int p = c0 + b;
+  const int j = colF[p];
+  // block (i, j) of F is block (min, max) of U, transposed when j < i; the
+  // upper part of a row is the tail of its row in F
+  const bool tr = j < i;
+  const int a = tr ? j : i;
+  const int pa = tr ? lutF[(size_t)j * n + i] : p;
+  const int q = pa < 0 ? -1 : rpU[a] + pa - (rpF[a + 1] - (rpU[a + 1] - rpU[a]));
+  if (q < rpU[a] || q >= rpU[a + 1]) {  // F's pattern not symmetric: poison the block
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = T(NAN);
+    return;
+  }
+  const T* u = U + (size_t)q * 16;
+  if (j == i) {  // diagonal block: its symmetric part (the rest is rounding)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = T(0.5) * (u[r * 4 + c] + u[c * 4 + r]);
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = tr ? u[c * 4 + r] : u[r * 4 + c];
+}
+
 // out = a X + b Y + c Z elementwise (Y, Z nullable), grid-stride.
 __global__ __launch_bounds__(256) void k_lincomb(int64_t nv, double a, const double* __restrict__ X,
                                                  double b, const double* __restrict__ Y, double c,
@@ -760,6 +800,7 @@ int check_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_b
 }
 
 // Operands and intermediates of one evaluation, all of one dtype T.
+// Zu / Lu (val != NULL): upper-triangle patterns for the symmetric products.
 struct EvalOps {
   const lnv_bsm *L, *S, *H;
   const lnv_bsm *SL, *LS, *X, *XT, *Z;
@@ -767,7 +808,37 @@ struct EvalOps {
   void *YT, *W, *V;
   double* partials;
   double* scalars;
+  const lnv_bsm *Zu, *Lu;
+  void* Vu;
 };
+
+bool sym_ready(const lnv_bsm* U, const lnv_bsm* C) {
+  return U && U->val && U->pat && U->pat->n == C->pat->n && U->pat->items && U->pat->row_ptr &&
+         U->dtype == C->dtype && C->pat->lut && C->pat->items;
+}
+
+// C = A.B on C's (symmetric) pattern for a product known to be symmetric.
+// With an upper-triangle buffer U (sym_ready) only the blocks j >= i are
+// multiplied, into U, and C is filled from them by a transposing copy;
+// otherwise C is formed in full.
+int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_bsm* U,
+                hipStream_t s) {
+  if (!sym_ready(U, C))
+    return multiply_launch(1.0, A, B, 0, 0.0, C, 1, nullptr, nullptr, nullptr, nullptr, s);
+  LNV_TRY(multiply_launch(1.0, A, B, 0, 0.0, U, 1, nullptr, nullptr, nullptr, nullptr, s));
+  const lnv_pattern *pf = C->pat, *pu = U->pat;
+  if (pf->n_items == 0) return LNV_OK;
+  if (C->dtype == LNV_F32)
+    k_mirror<float><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pf->lut,
+                                                pu->row_ptr, static_cast<const float*>(U->val),
+                                                static_cast<float*>(C->val));
+  else
+    k_mirror<double><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pf->lut,
+                                                 pu->row_ptr, static_cast<const double*>(U->val),
+                                                 static_cast<double*>(C->val));
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
 
 // The six products (in T), the assembly of G and F and the energy / electron
 // traces (FP64, with the FP64 L64 on the left of every trace).
@@ -780,11 +851,15 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
   LNV_TRY(multiply_launch(1.0, o.S, o.L, 0, 0.0, o.SL, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(transpose_launch(o.SL, o.perm_SL, o.LS->val, s));
   LNV_TRY(multiply_launch(1.0, o.H, o.LS, 0, 0.0, o.X, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, o.S, o.LS, 0, 0.0, o.Z, 1, nullptr, nullptr, nullptr, nullptr, s));
+  // Z = SLS, W = P_L(SLHLS) and V = P_L(SLSLS) are symmetric (upper halves
+  // when the workspace carries them); YT = P_L(SLSLH) is not
+  const lnv_bsm* Lu = o.Lu;
+  lnv_bsm Vu{Lu ? Lu->pat : nullptr, 4, dt, o.Vu};
+  LNV_TRY(sym_product(o.S, o.LS, o.Z, o.Zu, s));
   LNV_TRY(transpose_launch(o.X, o.perm_X, o.XT->val, s));
   LNV_TRY(multiply_launch(1.0, o.SL, o.XT, 0, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, o.SL, o.X, 0, 0.0, &Wm, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, o.SL, o.Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(sym_product(o.SL, o.X, &Wm, Lu, s));
+  LNV_TRY(sym_product(o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
   const int ni = pl->n_items;
   double* part = o.partials;
   k_assemble<T><<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, pl->lut,
@@ -809,9 +884,9 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
 
 int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, double* F,
               double* EN, const lnv_eval_ws* ws, hipStream_t s) {
-  EvalOps o{L,       S,           H,          &ws->SL, &ws->LS, &ws->X, &ws->XT,
-            &ws->Z,  ws->perm_SL, ws->perm_X, ws->YT,  ws->W,   ws->V,  ws->partials,
-            ws->scalars};
+  EvalOps o{L,       S,           H,          &ws->SL,     &ws->LS, &ws->X,
+            &ws->XT, &ws->Z,      ws->perm_SL, ws->perm_X,  ws->YT,  ws->W,
+            ws->V,   ws->partials, ws->scalars, &ws->Zu,    &ws->Lu, ws->Vu};
   return eval_products<double>(L, o, G, F, EN, s);
 }
 
@@ -968,9 +1043,9 @@ extern "C" int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm*
   LNV_TRY(convert_launch(L, &L32, s));
   LNV_TRY(convert_launch(S, &S32, s));
   LNV_TRY(convert_launch(H, &H32, s));
-  EvalOps o{&L32,   &S32,        &H32,       &ws->SL, &ws->LS, &ws->X, &ws->XT,
-            &ws->Z, ws->perm_SL, ws->perm_X, ws->YT,  ws->W,   ws->V,  ws->partials,
-            ws->scalars};
+  EvalOps o{&L32,    &S32,         &H32,        &ws->SL,     &ws->LS, &ws->X,
+            &ws->XT, &ws->Z,       ws->perm_SL, ws->perm_X,  ws->YT,  ws->W,
+            ws->V,   ws->partials, ws->scalars, &ws->Zu,     &ws->Lu, ws->Vu};
   return eval_products<float>(L, o, static_cast<double*>(G->val), static_cast<double*>(F->val),
                               EN, s);
 }
@@ -1106,7 +1181,8 @@ int metric_apply(const lnv_bsm* T, const double* V, double* out, lnv_cg_ws* ws, 
   lnv_bsm Vm{pl, 4, LNV_F64, const_cast<double*>(V)};
   lnv_bsm Om{pl, 4, LNV_F64, out};
   LNV_TRY(multiply_launch(1.0, T, &Vm, 0, 0.0, &ws->LL, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, &ws->LL, T, 0, 0.0, &Om, 1, nullptr, nullptr, nullptr, nullptr, s));
+  // P_L(T V T) is symmetric for symmetric T and V
+  LNV_TRY(sym_product(&ws->LL, T, &Om, &ws->ev.Lu, s));
   return LNV_OK;
 }
 
@@ -1299,8 +1375,9 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(transpose_launch(&SL2, ev.perm_SL, static_cast<double*>(ev.LS.val), s));
-  LNV_TRY(multiply_launch(1.0, S, &ev.LS, 0, 0.0, &ev.Z, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, &SL2, &ev.Z, 0, 0.0, &Vm, 1, nullptr, nullptr, nullptr, nullptr, s));
+  lnv_bsm Vu{ev.Lu.pat, 4, LNV_F64, ev.Vu};
+  LNV_TRY(sym_product(S, &ev.LS, &ev.Z, &ev.Zu, s));
+  LNV_TRY(sym_product(&SL2, &ev.Z, &Vm, &Vu, s));
   k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, ev.Z.pat->lut,
                                  static_cast<const double*>(ev.Z.val), ev.V, Fc, part);
   LNV_LAUNCH_CHECK();

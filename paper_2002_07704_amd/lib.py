@@ -45,7 +45,8 @@ class LnvEvalWs(ctypes.Structure):
     _fields_ = [("SL", LnvBsm), ("LS", LnvBsm), ("X", LnvBsm), ("XT", LnvBsm), ("Z", LnvBsm),
                 ("perm_SL", c_void_p), ("perm_X", c_void_p), ("YT", c_void_p),
                 ("W", c_void_p), ("V", c_void_p), ("partials", c_void_p),
-                ("partials_len", c_int64), ("scalars", c_void_p)]
+                ("partials_len", c_int64), ("scalars", c_void_p), ("Zu", LnvBsm), ("Lu", LnvBsm),
+                ("Vu", c_void_p)]
 
 
 class LnvCgWs(ctypes.Structure):
@@ -59,7 +60,8 @@ class LnvEval32Ws(ctypes.Structure):
     _fields_ = [("L", LnvBsm), ("S", LnvBsm), ("H", LnvBsm), ("SL", LnvBsm), ("LS", LnvBsm),
                 ("X", LnvBsm), ("XT", LnvBsm), ("Z", LnvBsm), ("perm_SL", c_void_p),
                 ("perm_X", c_void_p), ("YT", c_void_p), ("W", c_void_p), ("V", c_void_p),
-                ("partials", c_void_p), ("partials_len", c_int64), ("scalars", c_void_p)]
+                ("partials", c_void_p), ("partials_len", c_int64), ("scalars", c_void_p),
+                ("Zu", LnvBsm), ("Lu", LnvBsm), ("Vu", c_void_p)]
 
 
 class LnvAdjWs(ctypes.Structure):
@@ -83,6 +85,7 @@ SIGNATURES = {
     "lnv_pattern_product": (c_int, [PPat, PPat, PPat, c_void_p, c_void_p, c_int64,
                                     POINTER(c_int64), c_void_p, POINTER(c_int64), c_void_p]),
     "lnv_pattern_lut": (c_int, [PPat, c_void_p, c_void_p, c_void_p]),
+    "lnv_pattern_upper": (c_int, [PPat, c_void_p, c_void_p, c_int64, POINTER(c_int64), c_void_p]),
     "lnv_pattern_flops": (c_int, [PPat, PPat, PPat, c_void_p, POINTER(c_int64), c_void_p]),
     "lnv_pattern_items": (c_int, [PPat, c_void_p, c_int64, POINTER(c_int32), c_void_p]),
     "lnv_pattern_transpose_map": (c_int, [PPat, PPat, c_void_p, c_void_p]),

@@ -171,6 +171,27 @@ def product_pattern(A, B, mask=None, triples=True):
     return P
 
 
+def upper_pattern(P):
+    """Upper triangle of the symmetric pattern P (blocks j >= i), with its
+    work list."""
+    dev = P.row_ptr.device
+    rp = torch.empty(P.n + 1, dtype=torch.int32, device=dev)
+    nnz = c_int64(0)
+    L_.call("lnv_pattern_upper", byref(P.struct), _ptr(rp), None, 0, byref(nnz), _stream())
+    col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=dev)
+    L_.call("lnv_pattern_upper", byref(P.struct), _ptr(rp), _ptr(col), col.numel(), byref(nnz),
+            _stream())
+    return Pattern(P.n, rp, col[:nnz.value]).build_items()
+
+
+def is_symmetric(P):
+    rp, col = P.host()
+    rows = np.repeat(np.arange(P.n), np.diff(rp))
+    a = np.lexsort((col, rows))
+    b = np.lexsort((rows, col))
+    return bool(np.array_equal(rows[a], col[b]) and np.array_equal(col[a], rows[b]))
+
+
 class Matrix:
     """Block values on a pattern: tensor [nnzb, 4, 4] (float64, or float32 for
     the mixed-precision products) plus lnv_bsm."""
@@ -248,11 +269,14 @@ class LNVSystem:
     """One geometry on one GPU: patterns, S, H, L and the CG workspace.
 
     metric: "hotelling" builds T ~ S^-1 on L's range (n_hotelling steps) and
-    runs the CG in that metric; None uses the identity.
+    runs the CG in that metric; None uses the identity.  symmetric: form only
+    the upper-triangle blocks of the symmetric products SLS, P_L(SLHLS),
+    P_L(SLSLS) and P_L(TGT) and copy the rest transposed (needs symmetric
+    patterns, which L, S, H have).
     """
 
     def __init__(self, w, device="cuda", R_L=None, metric="hotelling", n_hotelling=16,
-                 cluster=(4, 1), reorder=None):
+                 cluster=(4, 1), reorder=None, symmetric=True):
         if not torch.cuda.is_available():
             raise RuntimeError("LNVSystem needs a GPU (HIP device)")
         L_.load()
@@ -280,6 +304,19 @@ class LNVSystem:
             self.pLL = product_pattern(self.pL, self.pL)          # T.G, T.F
             self.triples["TG"] = self.pLL.triples
             self.triples["TGT"] = product_pattern(self.pLL, self.pL, mask=self.pL).triples
+        # symmetric products Z, W, V (and P_L(TGT)): upper-triangle halves
+        self.symmetric = bool(symmetric) and is_symmetric(self.pL) and is_symmetric(self.pZ)
+        self.pZu = self.pLu = None
+        if self.symmetric:
+            self.pZu, self.pLu = upper_pattern(self.pZ), upper_pattern(self.pL)
+            # block triples of the upper halves (what the kernels multiply)
+            self.triples_upper = dict(
+                Z=product_pattern(self.pS, self.pLS, mask=self.pZu).triples,
+                W=product_pattern(self.pSL, self.pX, mask=self.pLu).triples,
+                V=product_pattern(self.pSL, self.pZ, mask=self.pLu).triples)
+            if metric is not None:
+                self.triples_upper["TGT"] = product_pattern(self.pLL, self.pL,
+                                                            mask=self.pLu).triples
         # index tables and work lists
         self.pL.build_lut(lut=True).build_items()
         self.pS.build_lut(lut=True)
@@ -312,6 +349,9 @@ class LNVSystem:
         self.XT = Matrix(self.pXT)
         self.Z = Matrix(self.pZ)
         self.YT, self.W, self.V = lbuf(), lbuf(), lbuf()
+        if self.symmetric:
+            self.Zu, self.Lu = Matrix(self.pZu), Matrix(self.pLu)
+            self.Vu = torch.zeros_like(self.Lu.val)
         self.SL2 = torch.zeros_like(self.SL.val)
         self.Hp = torch.zeros_like(self.H.val)
         self.g, self.gc_prev, self.D, self.D_prev = lbuf(), lbuf(), lbuf(), lbuf()
@@ -343,6 +383,8 @@ class LNVSystem:
         ev.partials = self.partials.data_ptr()
         ev.partials_len = plen
         ev.scalars = self.scalars.data_ptr()
+        if self.symmetric:
+            ev.Zu, ev.Lu, ev.Vu = self.Zu.struct, self.Lu.struct, self.Vu.data_ptr()
         self.ws.SL2 = self.SL2.data_ptr()
         self.ws.Hp = self.Hp.data_ptr()
         self.ws.G = self.G.val.data_ptr()
@@ -410,6 +452,10 @@ class LNVSystem:
         ws.partials = self.partials.data_ptr()
         ws.partials_len = self.ws.ev.partials_len
         ws.scalars = self.scalars.data_ptr()
+        if self.symmetric:
+            self.Zu32, self.Lu32 = f32(self.pZu), f32(self.pLu)
+            self.Vu32 = torch.zeros_like(self.Lu32.val)
+            ws.Zu, ws.Lu, ws.Vu = self.Zu32.struct, self.Lu32.struct, self.Vu32.data_ptr()
         self.ws32 = ws
         torch.cuda.synchronize()
 
@@ -426,6 +472,8 @@ class LNVSystem:
     def _cluster_patterns(self):
         """Patterns that are a left operand or an output of some multiply."""
         pats = [self.pS, self.pH, self.pL, self.pSL, self.pX, self.pZ]
+        if getattr(self, "symmetric", False):
+            pats += [self.pZu, self.pLu]
         if self.metric is not None:
             pats.append(self.pLL)
         if getattr(self, "adj_ws", None) is not None:
@@ -705,17 +753,21 @@ class LNVSystem:
         """Flops per product: 2 * 4^3 per stored block triple (padded), or the
         algorithmic count with the functions each stored row holds."""
         if padded or not self.split:
-            return {k: 2 * BLK ** 3 * v for k, v in self.triples.items()}
+            t = dict(self.triples)
+            if self.symmetric:
+                t.update(self.triples_upper)
+            return {k: 2 * BLK ** 3 * v for k, v in t.items()}
         return self._alg_flops()
 
     def _alg_flops(self):
         if getattr(self, "_alg", None) is None:
             self._alg = {}
+        up = self.pLu if self.symmetric else self.pL     # symmetric products: upper halves
         specs = {"SL": (self.pS, self.pL, None), "X": (self.pH, self.pLS, None),
-                 "Z": (self.pS, self.pLS, None), "YT": (self.pSL, self.pXT, self.pL),
-                 "W": (self.pSL, self.pX, self.pL), "V": (self.pSL, self.pZ, self.pL)}
+                 "Z": (self.pS, self.pLS, self.pZu), "YT": (self.pSL, self.pXT, self.pL),
+                 "W": (self.pSL, self.pX, up), "V": (self.pSL, self.pZ, up)}
         if self.metric is not None:
-            specs.update(TG=(self.pL, self.pL, None), TGT=(self.pLL, self.pL, self.pL))
+            specs.update(TG=(self.pL, self.pL, None), TGT=(self.pLL, self.pL, up))
         if self.adj_ws is not None:
             specs.update(LSL=(self.pL, self.pSL, None), HL=(self.pH, self.pL, None),
                          dH4=(self.pLSL, self.pSL, self.pH), dH6=(self.pL, self.pSL, self.pH),

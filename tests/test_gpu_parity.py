@@ -132,6 +132,17 @@ def test_product_patterns_and_triples(fx, request):
     _, tYT = ost.pattern_product(SL, X.T.tocsr(), Lp)
     _, tV = ost.pattern_product(SL, Z, Lp)
     assert (sysg.triples["W"], sysg.triples["YT"], sysg.triples["V"]) == (tW, tYT, tV)
+    # upper-triangle halves of the symmetric products (blocks j >= i)
+    import scipy.sparse as sps
+    Zu, Lu = sps.triu(Z).tocsr(), sps.triu(Lp).tocsr()
+    for P, R in ((sysg.pZu, Zu), (sysg.pLu, Lu)):
+        R.sort_indices()
+        rp, col = P.host()
+        assert np.array_equal(rp, R.indptr) and np.array_equal(col, R.indices)
+    tu = sysg.triples_upper
+    assert tu["Z"] == ost.pattern_product(S, LS, Zu)[1]
+    assert tu["W"] == ost.pattern_product(SL, X, Lu)[1]
+    assert tu["V"] == ost.pattern_product(SL, Z, Lu)[1]
 
 
 # ------------------------------------------------------------------ a3
@@ -312,3 +323,51 @@ def test_cg_trajectory_hotelling_metric(fx, steps, request):
         assert abs(sc["DELTA"] - h["delta"]) <= 1e-8 * max(abs(h["delta"]), 1e-6), k
         assert int(sc["STATUS"]) == 0
     del Tg
+
+
+# ------------------------------------------------------------------ symmetric products
+def test_symmetric_products_upper_half(gpu):
+    """Z = SLS, W = P_L(SLHLS), V = P_L(SLSLS) and P_L(TGT) formed from their
+    upper-triangle blocks only (the default) against the same system with
+    every block multiplied: the full products are symmetric, so both paths
+    agree to FP64 rounding, and the upper-half path gives exactly symmetric
+    matrices.  Eval, a Hotelling-metric CG trajectory and the mixed-precision
+    evaluation; 3x3x3 cubes, so rows span several 64-block pieces."""
+    from paper_2002_07704_amd.system import LNVSystem, transpose, transpose_map, Matrix
+    w = W.diamond_workload("si216", (3, 3, 3), seed=7)
+    a = LNVSystem(w, metric="hotelling", n_hotelling=16)
+    b = LNVSystem(w, metric="hotelling", n_hotelling=16, symmetric=False)
+    assert a.symmetric and not b.symmetric
+    assert a.flops("step") < b.flops("step")
+    for s in (a, b):
+        s.cg_init()
+        s.eval()
+    torch.cuda.synchronize()
+    assert torch.allclose(a.EN, b.EN, rtol=1e-13, atol=0)
+    for name in ("G", "F"):
+        x, y = getattr(a, name).val, getattr(b, name).val
+        assert (x - y).abs().max() <= 1e-12 * y.abs().max(), name
+    permL = transpose_map(a.pL, a.pL)
+    for M in (a.W, a.V):
+        Mt = torch.empty_like(M)
+        transpose(Matrix(a.pL, M), permL, Matrix(a.pL, Mt))
+        torch.cuda.synchronize()
+        assert torch.equal(M, Mt)
+    Zt = Matrix(a.pZ)
+    transpose(a.Z, transpose_map(a.pZ, a.pZ), Zt)
+    torch.cuda.synchronize()
+    assert torch.equal(a.Z.val, Zt.val)
+    for k in range(6):
+        a.cg_step()
+        b.cg_step()
+        sa, sb = a.scalars_host(), b.scalars_host()
+        assert abs(sa["E"] - sb["E"]) / w.n <= 1e-11, k
+        assert abs(sa["N"] - sb["N"]) <= 1e-9, k
+        assert abs(sa["ALPHA"] - sb["ALPHA"]) <= 1e-7 * abs(sb["ALPHA"]), k
+        assert int(sa["STATUS"]) & 3 == 0
+    b.L.val.copy_(a.L.val)
+    for s in (a, b):
+        s.eval_mixed()
+    torch.cuda.synchronize()
+    assert abs(float(a.EN[0]) - float(b.EN[0])) / w.n <= 1e-6
+    assert abs(float(a.EN[1]) - float(b.EN[1])) / w.n <= 1e-6
