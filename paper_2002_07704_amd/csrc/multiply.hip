@@ -326,6 +326,147 @@ __global__ __launch_bounds__(256) void k_mul44c(
   }
 }
 
+// Clustered variant with one lane per column (G = 1), software-pipelined so
+// that the only memory round trips a contraction step exposes are its A
+// blocks' (scalar loads, shared by the 4 waves of a cluster).  Per step t a
+// wave issues, in this order: one index load (lanes 0-3: the 4 rows' A
+// positions of step t+1, lanes 4-7: those of step t+3, the other lanes: k of
+// step t+4), the B index (lut entry) of step t+3, the B block of step t+2 and
+// a vector load of the 4 A blocks of step t+2 (one element per lane; it only
+// brings them into L2 ahead of the scalar loads, which then hit there); it
+// then multiplies B(t) into the rows present.  Every vector load is issued
+// unconditionally -- steps before the first or past the last read clamped
+// indices, idle lanes column 0's entry, missing B blocks block 0 -- so each
+// iteration issues the same loads in the same order and the waits count them
+// exactly: step t waits for the previous step's index loads and for B(t),
+// never for B(t+1), B(t+2) in flight.  The loop starts two steps early, so
+// the first blocks are fetched by the loop body itself.
+template <typename T, typename Acc>
+__device__ __forceinline__ void rows_fma(Acc (&acc)[4][16], const T (&b)[16], const int (&pos)[4],
+                                         const T* __restrict__ a_val) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int p0 = pos[2 * h], p1 = pos[2 * h + 1];
+    T a0[16], a1[16];
+    if (p0 >= 0) {
+      const T* ap = a_val + (size_t)p0 * 16;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a0[q] = ap[q];
+    }
+    if (p1 >= 0) {
+      const T* ap = a_val + (size_t)p1 * 16;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a1[q] = ap[q];
+    }
+    if (p0 >= 0) block_fma<0>(acc[2 * h], a0, b);
+    if (p1 >= 0) block_fma<0>(acc[2 * h + 1], a1, b);
+  }
+}
+
+template <int STORE, int NDOT, typename T, typename Acc>
+__global__ __launch_bounds__(256) void k_mul44c1(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
+    const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
+    const T* __restrict__ a_val, const int* __restrict__ b_lut,
+    const T* __restrict__ b_val, const int* __restrict__ jc_ptr,
+    const int* __restrict__ jc_col, const int* __restrict__ jc_pos, T* __restrict__ c_val,
+    double alpha, double beta, const T* __restrict__ m1, const T* __restrict__ m2,
+    double* __restrict__ partials, const double* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0.0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (item >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const int c = items[2 * item];
+  const int p0 = items[2 * item + 1];
+  const int cnt = min(kWave, jc_ptr[c + 1] - p0);
+  const bool act = lane < cnt;
+  const int j = act ? jc_col[p0 + lane] : 0;
+  int opos[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) opos[r] = act ? jc_pos[(size_t)(p0 + lane) * 4 + r] : -1;
+  const int* __restrict__ lcol = b_lut + j;
+  const size_t ns = (size_t)n;
+  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
+
+  Acc acc[4][16];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) acc[r][e] = 0;
+
+  if (t0 < t1) {
+    const int tl = t1 - 1;
+    // index loads of step t: A positions of steps t+1 (lanes 0-3) and t+3
+    // (lanes 4-7), k of step t+4 (lanes 8-63)
+    auto idx_src = [&](int t) -> const int* {
+      return lane < 4   ? ka_pos + (size_t)min(max(t + 1, t0), tl) * 4 + lane
+             : lane < 8 ? ka_pos + (size_t)min(max(t + 3, t0), tl) * 4 + (lane - 4)
+                        : ka_col + min(t + 4, tl);
+    };
+    // A element of step t+2 this lane loads ahead (row lane/16, entry lane%16)
+    const int ar = (lane >> 4) & 3, ae = lane & 15;
+    const int ts = t0 - 2;
+    // the loads of the step before the first: B index of step t0 (as L2),
+    // the index vector (k of step t0+1 in lanes 8-63) and a B block into b1
+    // (block 0, never used).  The block's offset is an opaque zero computed
+    // from the index vector, so it is issued last, as in every loop step, and
+    // the counts of loads in flight at the loop head agree on both paths.
+    int l0 = -1, l1 = -1;                      // B indices (raw lut entries)
+    int l2 = lcol[(size_t)ka_col[t0] * ns];
+    int iv = *idx_src(ts - 1);
+    T b0[16], b1[16], b2[16];
+    int zero = 0;
+    asm volatile("" : "+v"(zero) : "v"(iv));
+    load_block(b1, b_val + (size_t)zero * 16);
+    T x0 = a_val[zero], x1 = x0, x2 = x0;
+
+// step t: consume BC = B(t) (index LC), issue B(t+2) into BN from index L2,
+// overwrite LC with the index of step t+3
+#define LNV_C1_STEP(t, BC, BN, LC, L2, XC)                                     \
+  {                                                                            \
+    const int ivn = *idx_src(t);                                               \
+    const int k3 = __builtin_amdgcn_readlane(iv, 8);                           \
+    int pos[4], pf[4];                                                         \
+    _Pragma("unroll") for (int r = 0; r < 4; ++r) {                            \
+      pos[r] = __builtin_amdgcn_readlane(iv, r);                               \
+      pf[r] = __builtin_amdgcn_readlane(iv, 4 + r);                            \
+    }                                                                          \
+    const bool use = act && (t) >= t0 && (t) < t1 && LC >= 0;                  \
+    LC = lcol[(size_t)k3 * ns];                                                \
+    load_block(BN, b_val + (size_t)max(L2, 0) * 16);                           \
+    asm volatile("" ::"v"(XC));                                                \
+    {                                                                          \
+      const int pa = ar == 0 ? pf[0] : ar == 1 ? pf[1] : ar == 2 ? pf[2] : pf[3]; \
+      XC = a_val[(size_t)max(pa, 0) * 16 + ae];                                \
+    }                                                                          \
+    if ((t) >= t0 && (t) < t1 && use) rows_fma(acc, BC, pos, a_val);          \
+    iv = ivn;                                                                  \
+  }
+    for (int t = ts; t < t1; t += 3) {
+      LNV_C1_STEP(t, b0, b2, l0, l2, x0)
+      LNV_C1_STEP(t + 1, b1, b0, l1, l0, x1)
+      LNV_C1_STEP(t + 2, b2, b1, l2, l1, x2)
+    }
+    asm volatile("" ::"v"(x0), "v"(x1), "v"(x2));
+#undef LNV_C1_STEP
+  }
+
+  double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+    if (opos[r] >= 0)
+      finish_block<STORE, NDOT>(acc[r], c_val, (size_t)opos[r] * 16, alpha, beta, m1, m2, d1, d2);
+  if (NDOT >= 1) {
+    d1 = wave_sum(d1);
+    if (NDOT >= 2) d2 = wave_sum(d2);
+    if (lane == 0) {
+      partials[2 * item] = d1;
+      partials[2 * item + 1] = d2;
+    }
+  }
+}
+
 template <typename T>
 using KernelCFn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
                            const int*, const T*, const int*, const int*, const int*, T*, double,
@@ -340,6 +481,17 @@ KernelCFn<T> pick_c(int store, int ndot) {
   }
   if (ndot == 1) return k_mul44c<G, 0, 1, T, Acc>;
   return k_mul44c<G, 0, 2, T, Acc>;
+}
+
+template <typename T, typename Acc>
+KernelCFn<T> pick_c1(int store, int ndot) {
+  if (store) {
+    if (ndot == 0) return k_mul44c1<1, 0, T, Acc>;
+    if (ndot == 1) return k_mul44c1<1, 1, T, Acc>;
+    return k_mul44c1<1, 2, T, Acc>;
+  }
+  if (ndot == 1) return k_mul44c1<0, 1, T, Acc>;
+  return k_mul44c1<0, 2, T, Acc>;
 }
 
 template <typename T>
@@ -426,8 +578,10 @@ int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
     const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
     hipEvent_t stop = nullptr;
     LNV_TRY(timer_begin(s, &stop));
-    KernelCFn<T> fn =
-        pc->cl_g == 2 ? pick_c<2, T, Acc>(store, ndot) : pick_c<1, T, Acc>(store, ndot);
+    // the pipelined kernel reads block 0 of B in place of missing blocks
+    KernelCFn<T> fn = pc->cl_g == 2      ? pick_c<2, T, Acc>(store, ndot)
+                      : B->pat->nnzb > 0 ? pick_c1<T, Acc>(store, ndot)
+                                         : pick_c<1, T, Acc>(store, ndot);
     fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
                            pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
                            alpha, beta, m1, m2, partials, skip);
