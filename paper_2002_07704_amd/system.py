@@ -242,7 +242,9 @@ def multiply(alpha, A, B, transB, beta, C):
 
 def multiply_dot(alpha, A, B, transB, beta, C, store, M1, M2=None):
     dev = C.val.device
-    part = torch.empty(max(2, 2 * C.pat.struct.n_items), dtype=torch.float64, device=dev)
+    st = C.pat.struct       # one partial pair per work piece (row or cluster pieces)
+    part = torch.empty(max(2, 2 * max(st.n_items, st.n_cl_items)), dtype=torch.float64,
+                       device=dev)
     out = torch.zeros(2, dtype=torch.float64, device=dev)
     L_.call("lnv_bsm_multiply_dot", float(alpha), byref(A.struct), byref(B.struct), int(transB),
             float(beta), byref(C.struct), int(store), byref(M1.struct),
