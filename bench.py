@@ -361,6 +361,30 @@ def main():
     L_.call("lnv_set_f32_accumulation", 0)
     del G64, F64
 
+    # mixed-precision CG: the same iterations from the same start with FP32
+    # block products in each step's evaluation (metric, line search and
+    # electron-number products FP64); the energy after them in FP64
+    sysg.opts.mixed = True
+    restart()
+    step()
+    restart()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_mcg = (time.perf_counter() - t0) * 1e3 / args.steps
+    status_m = int(sysg.scalar("STATUS"))
+    sysg.opts.mixed = False
+    sysg.eval()
+    torch.cuda.synchronize()
+    e_mcg, n_mcg = (float(x) for x in sysg.EN.cpu())
+    mixed_cg = {"ms_per_step": ms_mcg, "steps_per_s": 1e3 / ms_mcg,
+                "speedup_vs_fp64_step": ms_per_step / ms_mcg,
+                "E_per_atom_after_steps": e_mcg / w.n,
+                "dE_per_atom_vs_fp64_cg": abs(e_mcg - e_end) / w.n,
+                "N_after_steps": n_mcg, "cg_status_bits": status_m}
+
     # adjoint: dE/dS and dE/dH at the same L (L.S.L and H.L recomputed)
     sysg.adjoint_setup()
     dS = torch.empty_like(sysg.S.val)
@@ -418,6 +442,7 @@ def main():
         "eval_only": {"evals_per_s": 1e3 / ms_eval, "ms": ms_eval, "gflop": flops_eval / 1e9,
                       "gflops_per_s": flops_eval / (ms_eval * 1e-3) / 1e9},
         "mixed": mixed,
+        "mixed_cg": mixed_cg,
         "adjoint_dS_dH": {"ms": ms_adj, "gflop": flops_adj / 1e9,
                           "gflops_per_s": flops_adj / (ms_adj * 1e-3) / 1e9},
         "setup_s": setup_s,

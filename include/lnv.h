@@ -525,6 +525,13 @@ typedef struct lnv_opts {
   int32_t reset_period;  /* search direction reset period (40) */
   double n_tol;          /* relative electron-number tolerance (1e-11) */
   double step_cap;       /* max |delta| ||F_c|| / ||L|| of the N correction (0.1) */
+  /* NULL: the step's evaluation (E, N, G, F) in FP64.  Otherwise it runs as
+   * lnv_eval_mixed on this workspace (FP32 block products under the FP32
+   * accumulation mode, FP64 assembly and traces; its partials and scalars
+   * are not used: the step's own are), and S.L is widened to FP64 from the
+   * FP32 product for the line search; every other product of the step stays
+   * FP64. */
+  const struct lnv_eval32_ws* eval32;
 } lnv_opts;
 
 /*

@@ -1304,8 +1304,25 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   sa.step_cap = opts->step_cap;
   sa.reset = (k % opts->reset_period) == 0;
 
-  // 1. E, N, G, F; metric gradients G_c, F_c; mu
-  LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s));
+  // 1. E, N, G, F (FP64, or FP32 products); metric gradients G_c, F_c; mu
+  if (opts->eval32) {
+    const lnv_eval32_ws* w32 = opts->eval32;
+    lnv_bsm Gm{pl, 4, LNV_F64, ws->G}, Fm{pl, 4, LNV_F64, ws->F};
+    LNV_TRY(check_eval32(L, S, H, &Gm, &Fm, w32));
+    if (w32->SL.pat != ev.SL.pat) return LNV_EPATTERN;
+    lnv_bsm L32 = w32->L, S32 = w32->S, H32 = w32->H;
+    LNV_TRY(convert_launch(L, &L32, s));
+    LNV_TRY(convert_launch(S, &S32, s));
+    LNV_TRY(convert_launch(H, &H32, s));
+    EvalOps o{&L32,     &S32,     &H32,         &w32->SL,     &w32->LS, &w32->X,
+              &w32->XT, &w32->Z,  w32->perm_SL, w32->perm_X,  w32->YT,  w32->W,
+              w32->V,   part,     sc,           &w32->Zu,     &w32->Lu, w32->Vu};
+    LNV_TRY(eval_products<float>(L, o, ws->G, ws->F, nullptr, s));
+    lnv_bsm SL64 = ev.SL;
+    LNV_TRY(convert_launch(&w32->SL, &SL64, s));
+  } else {
+    LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s));
+  }
   const double* Gc = ws->G;
   const double* Fc = ws->F;
   double* gcur = ws->g;

@@ -69,7 +69,8 @@ class LnvAdjWs(ctypes.Structure):
 
 
 class LnvOpts(ctypes.Structure):
-    _fields_ = [("reset_period", c_int32), ("n_tol", c_double), ("step_cap", c_double)]
+    _fields_ = [("reset_period", c_int32), ("n_tol", c_double), ("step_cap", c_double),
+                ("eval32", c_void_p)]
 
 
 PPat = POINTER(LnvPattern)

@@ -265,6 +265,7 @@ class Opts:
     reset_period: int = 40
     n_tol: float = 1e-11
     step_cap: float = 0.1
+    mixed: bool = False      # the step's evaluation with FP32 block products
 
 
 class LNVSystem:
@@ -827,7 +828,10 @@ class LNVSystem:
     def cg_step(self):
         if self.cells is not None:
             raise NotImplementedError("a batch of cells is evaluated, not minimised, as one system")
-        o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap)
+        o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap, None)
+        if self.opts.mixed:
+            self.mixed_setup()
+            o.eval32 = ctypes.addressof(self.ws32)
         L_.call("lnv_cg_step", byref(self.L.struct), byref(self.S.struct), byref(self.H.struct),
                 self._T(), self.n_elec, self.k, byref(o), byref(self.ws), _stream())
         self.k += 1

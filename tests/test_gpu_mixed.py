@@ -156,3 +156,39 @@ def test_eval_mixed_against_oracle(fx, acc, request):
         assert abs(E - Er) / w.n <= 1e-6
         assert abs(N - Nr) <= tol * abs(Nr)
         assert eG <= tol and eF <= tol
+
+
+def test_mixed_cg_tracks_fp64():
+    """CG iterations whose evaluation runs with FP32 block products (the
+    metric, line search and electron-number products stay FP64) against the
+    same iterations in FP64, Hotelling metric, 3x3x3 cubes: the first step's
+    energy is the mixed evaluation's at the same L, and every step's energy
+    stays within the 1e-6 Ha/atom target of the FP64 trajectory; the
+    electron number is corrected in FP64, so it stays at N_e to the
+    correction's tolerance."""
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.diamond_workload("si216", (3, 3, 3), seed=7)
+    a = LNVSystem(w, metric="hotelling", n_hotelling=16)
+    b = LNVSystem(w, metric="hotelling", n_hotelling=16)
+    b.opts.mixed = True
+    for s in (a, b):
+        s.cg_init()
+    b.eval_mixed()
+    torch.cuda.synchronize()
+    e_mixed0 = float(b.EN[0])
+    for k in range(8):
+        a.cg_step()
+        b.cg_step()
+        sa, sb = a.scalars_host(), b.scalars_host()
+        if k == 0:
+            assert sb["E"] == e_mixed0
+        print(f"k={k} E/atom fp64 {sa['E'] / w.n:.12f} mixed {sb['E'] / w.n:.12f} "
+              f"N {sb['N']:.9f}", flush=True)
+        assert abs(sa["E"] - sb["E"]) / w.n <= 1e-6, k
+        assert int(sb["STATUS"]) & 3 == 0, k
+    for s in (a, b):
+        s.opts.mixed = False
+        s.eval()
+    torch.cuda.synchronize()
+    assert abs(float(a.EN[0]) - float(b.EN[0])) / w.n <= 1e-6
+    assert abs(float(b.EN[1]) - w.n_elec) <= 1e-9 * w.n_elec
