@@ -89,6 +89,14 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
                     const void* m2, double* partials, const double* skip,
                     hipStream_t s);
 
+// C1 = A1.B1 and C2 = A2.B2 (alpha 1, beta 0) in one launch when A1, A2 share
+// a pattern and C1, C2 share a pattern with 4-row cluster plans; otherwise
+// two multiply_launch calls.  Traces as in multiply_launch, per product.
+int multiply_pair_launch(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1,
+                         const lnv_bsm* A2, const lnv_bsm* B2, const lnv_bsm* C2, int store,
+                         const void* m11, const void* m12, double* part1, const void* m21,
+                         const void* m22, double* part2, const double* skip, hipStream_t s);
+
 // Number of dot partials (work items) multiply_launch writes for C.
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C);
 

@@ -821,11 +821,8 @@ bool sym_ready(const lnv_bsm* U, const lnv_bsm* C) {
 // With an upper-triangle buffer U (sym_ready) only the blocks j >= i are
 // multiplied, into U, and C is filled from them by a transposing copy;
 // otherwise C is formed in full.
-int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_bsm* U,
-                hipStream_t s) {
-  if (!sym_ready(U, C))
-    return multiply_launch(1.0, A, B, 0, 0.0, C, 1, nullptr, nullptr, nullptr, nullptr, s);
-  LNV_TRY(multiply_launch(1.0, A, B, 0, 0.0, U, 1, nullptr, nullptr, nullptr, nullptr, s));
+// C (full symmetric pattern) from its upper-triangle blocks U.
+int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s) {
   const lnv_pattern *pf = C->pat, *pu = U->pat;
   if (pf->n_items == 0) return LNV_OK;
   if (C->dtype == LNV_F32)
@@ -838,6 +835,29 @@ int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_
                                                  static_cast<double*>(C->val));
   LNV_LAUNCH_CHECK();
   return LNV_OK;
+}
+
+int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_bsm* U,
+                hipStream_t s) {
+  if (!sym_ready(U, C))
+    return multiply_launch(1.0, A, B, 0, 0.0, C, 1, nullptr, nullptr, nullptr, nullptr, s);
+  LNV_TRY(multiply_launch(1.0, A, B, 0, 0.0, U, 1, nullptr, nullptr, nullptr, nullptr, s));
+  return mirror_launch(U, C, s);
+}
+
+// Two symmetric products C1 = A1.B1, C2 = A2.B2 with the same output pattern
+// (upper halves U1, U2 on one pattern): one paired launch, then the mirrors.
+int sym_product_pair(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1, const lnv_bsm* U1,
+                     const lnv_bsm* A2, const lnv_bsm* B2, const lnv_bsm* C2, const lnv_bsm* U2,
+                     hipStream_t s) {
+  if (!sym_ready(U1, C1) || !sym_ready(U2, C2) || U1->pat != U2->pat) {
+    LNV_TRY(sym_product(A1, B1, C1, U1, s));
+    return sym_product(A2, B2, C2, U2, s);
+  }
+  LNV_TRY(multiply_pair_launch(A1, B1, U1, A2, B2, U2, 1, nullptr, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, s));
+  LNV_TRY(mirror_launch(U1, C1, s));
+  return mirror_launch(U2, C2, s);
 }
 
 // The six products (in T), the assembly of G and F and the energy / electron
@@ -858,8 +878,7 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
   LNV_TRY(sym_product(o.S, o.LS, o.Z, o.Zu, s));
   LNV_TRY(transpose_launch(o.X, o.perm_X, o.XT->val, s));
   LNV_TRY(multiply_launch(1.0, o.SL, o.XT, 0, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(sym_product(o.SL, o.X, &Wm, Lu, s));
-  LNV_TRY(sym_product(o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
+  LNV_TRY(sym_product_pair(o.SL, o.X, &Wm, Lu, o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
   const int ni = pl->n_items;
   double* part = o.partials;
   k_assemble<T><<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, pl->lut,
@@ -1167,12 +1186,14 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const dou
   lnv_bsm scratchC{pl, 4, LNV_F64, ev.YT};
   *nparts = multiply_nparts(&APT, B, 0, &scratchC);
   if (SLcur && multiply_nparts(SLcur, B, 0, &scratchC) != *nparts) return LNV_EPATTERN;
-  LNV_TRY(multiply_launch(1.0, &APT, B, 0, 0.0, &scratchC, 0,
-                          static_cast<const double*>(L->val), P, partials + 1 * slot, skip, s));
-  if (SLcur)
-    LNV_TRY(multiply_launch(1.0, SLcur, B, 0, 0.0, &scratchC, 0, P, nullptr,
-                            partials + 2 * slot, skip, s));
-  return LNV_OK;
+  if (!SLcur)
+    return multiply_launch(1.0, &APT, B, 0, 0.0, &scratchC, 0,
+                           static_cast<const double*>(L->val), P, partials + 1 * slot, skip, s);
+  // both trace products in one launch (the second's second trace, <P, .>
+  // again, lands in the unused odd partials of its slot)
+  return multiply_pair_launch(&APT, B, &scratchC, SLcur, B, &scratchC, 0,
+                              static_cast<const double*>(L->val), P, partials + 1 * slot, P, P,
+                              partials + 2 * slot, skip, s);
 }
 
 // out = P_L(T V T) through the natural-range intermediate T V (in ws->LL).
@@ -1184,6 +1205,29 @@ int metric_apply(const lnv_bsm* T, const double* V, double* out, lnv_cg_ws* ws, 
   // P_L(T V T) is symmetric for symmetric T and V
   LNV_TRY(sym_product(&ws->LL, T, &Om, &ws->ev.Lu, s));
   return LNV_OK;
+}
+
+// out1 = P_L(T V1 T), out2 = P_L(T V2 T) as paired launches: T.V1 into LL,
+// T.V2 into X's buffer (free between the evaluation and the line search)
+// when pat(L.L) fits there, the upper halves into Lu's and Vu's buffers;
+// otherwise one after the other.
+int metric_apply_pair(const lnv_bsm* T, const double* V1, double* out1, const double* V2,
+                      double* out2, lnv_cg_ws* ws, hipStream_t s) {
+  const lnv_eval_ws& ev = ws->ev;
+  const lnv_pattern* pl = T->pat;
+  const bool room = ws->LL.pat && ev.X.pat && ws->LL.pat->nnzb <= ev.X.pat->nnzb && ev.X.val &&
+                    ev.Vu && ev.Lu.val && ev.Lu.pat;
+  if (!room) {
+    LNV_TRY(metric_apply(T, V1, out1, ws, s));
+    return metric_apply(T, V2, out2, ws, s);
+  }
+  lnv_bsm V1m{pl, 4, LNV_F64, const_cast<double*>(V1)}, V2m{pl, 4, LNV_F64, const_cast<double*>(V2)};
+  lnv_bsm O1{pl, 4, LNV_F64, out1}, O2{pl, 4, LNV_F64, out2};
+  lnv_bsm LL2{ws->LL.pat, 4, LNV_F64, ev.X.val};
+  lnv_bsm U2{ev.Lu.pat, 4, LNV_F64, ev.Vu};
+  LNV_TRY(multiply_pair_launch(T, &V1m, &ws->LL, T, &V2m, &LL2, 1, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, s));
+  return sym_product_pair(&ws->LL, T, &O1, &ev.Lu, &LL2, T, &O2, &U2, s);
 }
 
 }  // namespace
@@ -1327,8 +1371,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   const double* Fc = ws->F;
   double* gcur = ws->g;
   if (metric) {
-    LNV_TRY(metric_apply(T, ws->G, ws->Gc, ws, s));
-    LNV_TRY(metric_apply(T, ws->F, ws->Fc, ws, s));
+    LNV_TRY(metric_apply_pair(T, ws->G, ws->Gc, ws->F, ws->Fc, ws, s));
     Gc = ws->Gc;
     Fc = ws->Fc;
     gcur = ws->gc;

@@ -363,16 +363,31 @@ __device__ __forceinline__ void rows_fma(Acc (&acc)[4][16], const T (&b)[16], co
   }
 }
 
-template <int STORE, int NDOT, typename T, typename Acc>
+// PAIR: a second product in the same launch, selected by blockIdx.y, with
+// the same A and C patterns (so the same cluster plans and pieces) and its
+// own values, B and traces (all from kernel arguments, so the A blocks stay
+// on the scalar path).
+template <int PAIR, int STORE, int NDOT, typename T, typename Acc>
 __global__ __launch_bounds__(256) void k_mul44c1(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
     const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
-    const T* __restrict__ a_val, const int* __restrict__ b_lut,
-    const T* __restrict__ b_val, const int* __restrict__ jc_ptr,
-    const int* __restrict__ jc_col, const int* __restrict__ jc_pos, T* __restrict__ c_val,
-    double alpha, double beta, const T* __restrict__ m1, const T* __restrict__ m2,
-    double* __restrict__ partials, const double* __restrict__ skip) {
+    const T* __restrict__ a_val1, const int* __restrict__ b_lut1,
+    const T* __restrict__ b_val1, const int* __restrict__ jc_ptr,
+    const int* __restrict__ jc_col, const int* __restrict__ jc_pos, T* __restrict__ c_val1,
+    double alpha, double beta, const T* __restrict__ m1_1, const T* __restrict__ m2_1,
+    double* __restrict__ partials1, const double* __restrict__ skip,
+    const T* __restrict__ a_val2, const int* __restrict__ b_lut2,
+    const T* __restrict__ b_val2, T* __restrict__ c_val2, const T* __restrict__ m1_2,
+    const T* __restrict__ m2_2, double* __restrict__ partials2) {
   if (skip != nullptr && *skip != 0.0) return;
+  const bool second = PAIR && blockIdx.y != 0;
+  const T* __restrict__ a_val = second ? a_val2 : a_val1;
+  const int* __restrict__ b_lut = second ? b_lut2 : b_lut1;
+  const T* __restrict__ b_val = second ? b_val2 : b_val1;
+  T* __restrict__ c_val = second ? c_val2 : c_val1;
+  const T* __restrict__ m1 = second ? m1_2 : m1_1;
+  const T* __restrict__ m2 = second ? m2_2 : m2_1;
+  double* __restrict__ partials = second ? partials2 : partials1;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
   if (item >= n_items) return;
@@ -483,15 +498,21 @@ KernelCFn<T> pick_c(int store, int ndot) {
   return k_mul44c<G, 0, 2, T, Acc>;
 }
 
-template <typename T, typename Acc>
-KernelCFn<T> pick_c1(int store, int ndot) {
+template <typename T>
+using KernelC1Fn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
+                            const int*, const T*, const int*, const int*, const int*, T*, double,
+                            double, const T*, const T*, double*, const double*, const T*,
+                            const int*, const T*, T*, const T*, const T*, double*);
+
+template <int PAIR, typename T, typename Acc>
+KernelC1Fn<T> pick_c1(int store, int ndot) {
   if (store) {
-    if (ndot == 0) return k_mul44c1<1, 0, T, Acc>;
-    if (ndot == 1) return k_mul44c1<1, 1, T, Acc>;
-    return k_mul44c1<1, 2, T, Acc>;
+    if (ndot == 0) return k_mul44c1<PAIR, 1, 0, T, Acc>;
+    if (ndot == 1) return k_mul44c1<PAIR, 1, 1, T, Acc>;
+    return k_mul44c1<PAIR, 1, 2, T, Acc>;
   }
-  if (ndot == 1) return k_mul44c1<0, 1, T, Acc>;
-  return k_mul44c1<0, 2, T, Acc>;
+  if (ndot == 1) return k_mul44c1<PAIR, 0, 1, T, Acc>;
+  return k_mul44c1<PAIR, 0, 2, T, Acc>;
 }
 
 template <typename T>
@@ -579,12 +600,19 @@ int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
     hipEvent_t stop = nullptr;
     LNV_TRY(timer_begin(s, &stop));
     // the pipelined kernel reads block 0 of B in place of missing blocks
-    KernelCFn<T> fn = pc->cl_g == 2      ? pick_c<2, T, Acc>(store, ndot)
-                      : B->pat->nnzb > 0 ? pick_c1<T, Acc>(store, ndot)
-                                         : pick_c<1, T, Acc>(store, ndot);
-    fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
-                           pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
-                           alpha, beta, m1, m2, partials, skip);
+    if (pc->cl_g == 1 && B->pat->nnzb > 0) {
+      KernelC1Fn<T> fn = pick_c1<0, T, Acc>(store, ndot);
+      fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
+                             pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
+                             alpha, beta, m1, m2, partials, skip, nullptr, nullptr, nullptr,
+                             nullptr, nullptr, nullptr, nullptr);
+    } else {
+      KernelCFn<T> fn =
+          pc->cl_g == 2 ? pick_c<2, T, Acc>(store, ndot) : pick_c<1, T, Acc>(store, ndot);
+      fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
+                             pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
+                             alpha, beta, m1, m2, partials, skip);
+    }
     LNV_LAUNCH_CHECK();
     if (stop) LNV_HIP(hipEventRecord(stop, s));
     return LNV_OK;
@@ -611,7 +639,63 @@ int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
   return LNV_OK;
 }
 
+// Two products C1 = A1.B1, C2 = A2.B2 in one launch of the pipelined kernel
+// (A1, A2 on one pattern, C1, C2 on one pattern with a 4-row cluster plan):
+// the pieces of both fill the device together (grid y = product).
+template <typename T, typename Acc>
+int launch_pair_typed(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1,
+                      const lnv_bsm* A2, const lnv_bsm* B2, const lnv_bsm* C2, int store,
+                      const void* m11, const void* m12, double* part1, const void* m21,
+                      const void* m22, double* part2, const double* skip, int ndot,
+                      hipStream_t s) {
+  const lnv_pattern *pa = A1->pat, *pc = C1->pat;
+  if (pc->n_cl_items == 0) return LNV_OK;
+  const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
+  hipEvent_t stop = nullptr;
+  LNV_TRY(timer_begin(s, &stop));
+  KernelC1Fn<T> fn = pick_c1<1, T, Acc>(store, ndot);
+  fn<<<dim3(wgs, 2), 256, 0, s>>>(
+      pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col, pa->cl_pos,
+      static_cast<const T*>(A1->val), B1->pat->lut, static_cast<const T*>(B1->val), pc->cl_ptr,
+      pc->cl_col, pc->cl_pos, static_cast<T*>(C1->val), 1.0, 0.0, static_cast<const T*>(m11),
+      static_cast<const T*>(m12), part1, skip, static_cast<const T*>(A2->val), B2->pat->lut,
+      static_cast<const T*>(B2->val), static_cast<T*>(C2->val), static_cast<const T*>(m21),
+      static_cast<const T*>(m22), part2);
+  LNV_LAUNCH_CHECK();
+  if (stop) LNV_HIP(hipEventRecord(stop, s));
+  return LNV_OK;
+}
+
 }  // namespace
+
+int multiply_pair_launch(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1,
+                         const lnv_bsm* A2, const lnv_bsm* B2, const lnv_bsm* C2, int store,
+                         const void* m11, const void* m12, double* part1, const void* m21,
+                         const void* m22, double* part2, const double* skip, hipStream_t s) {
+  const int ndot = m12 ? 2 : (m11 ? 1 : 0);
+  const bool pairable =
+      bsm_ok_any(A1) && bsm_ok_any(B1) && bsm_ok_any(C1) && bsm_ok_any(A2) && bsm_ok_any(B2) &&
+      bsm_ok_any(C2) && A1->pat == A2->pat && C1->pat == C2->pat && A1->dtype == C1->dtype &&
+      B1->dtype == C1->dtype && A2->dtype == C1->dtype && B2->dtype == C1->dtype &&
+      C2->dtype == C1->dtype && A1->blk == 4 && B1->blk == 4 && C1->blk == 4 && B2->blk == 4 &&
+      use_clustered(A1, B1, 0, C1) && use_clustered(A2, B2, 0, C2) && C1->pat->cl_g == 1 &&
+      B1->pat->nnzb > 0 && B2->pat->nnzb > 0 && B1->pat->lut && B2->pat->lut &&
+      B1->pat->n == C1->pat->n && B2->pat->n == C1->pat->n &&
+      ndot == (m22 ? 2 : (m21 ? 1 : 0)) && (ndot == 0 || (part1 && part2)) && (store || ndot > 0);
+  if (!pairable) {  // two launches
+    LNV_TRY(multiply_launch(1.0, A1, B1, 0, 0.0, C1, store, m11, m12, part1, skip, s));
+    return multiply_launch(1.0, A2, B2, 0, 0.0, C2, store, m21, m22, part2, skip, s);
+  }
+  if (C1->dtype == LNV_F32) {
+    if (g_f32_acc == LNV_ACC_F64)
+      return launch_pair_typed<float, double>(A1, B1, C1, A2, B2, C2, store, m11, m12, part1,
+                                              m21, m22, part2, skip, ndot, s);
+    return launch_pair_typed<float, float>(A1, B1, C1, A2, B2, C2, store, m11, m12, part1, m21,
+                                           m22, part2, skip, ndot, s);
+  }
+  return launch_pair_typed<double, double>(A1, B1, C1, A2, B2, C2, store, m11, m12, part1, m21,
+                                           m22, part2, skip, ndot, s);
+}
 
 int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
                     double beta, const lnv_bsm* C, int store, const void* m1,
