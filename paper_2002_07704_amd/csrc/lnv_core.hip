@@ -409,7 +409,9 @@ __global__ __launch_bounds__(256) void k_mirror(int n, const int* __restrict__ i
                                                 const int* __restrict__ colF,
                                                 const int* __restrict__ lutF,
                                                 const int* __restrict__ rpU,
-                                                const T* __restrict__ U, T* __restrict__ F) {
+                                                const T* __restrict__ U, T* __restrict__ F,
+                                                const double* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0.0) return;
   const int item = blockIdx.x;
   const int i = items[2 * item], c0 = items[2 * item + 1];
   const int cnt = min(kWave, rpF[i + 1] - c0);
@@ -821,18 +823,20 @@ bool sym_ready(const lnv_bsm* U, const lnv_bsm* C) {
 // With an upper-triangle buffer U (sym_ready) only the blocks j >= i are
 // multiplied, into U, and C is filled from them by a transposing copy;
 // otherwise C is formed in full.
-// C (full symmetric pattern) from its upper-triangle blocks U.
-int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s) {
+// C (full symmetric pattern) from its upper-triangle blocks U (skip: as in
+// the multiply, a device flag that turns the launch into a no-op).
+int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
+                  const double* skip = nullptr) {
   const lnv_pattern *pf = C->pat, *pu = U->pat;
   if (pf->n_items == 0) return LNV_OK;
   if (C->dtype == LNV_F32)
     k_mirror<float><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pf->lut,
                                                 pu->row_ptr, static_cast<const float*>(U->val),
-                                                static_cast<float*>(C->val));
+                                                static_cast<float*>(C->val), skip);
   else
     k_mirror<double><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pf->lut,
                                                  pu->row_ptr, static_cast<const double*>(U->val),
-                                                 static_cast<double*>(C->val));
+                                                 static_cast<double*>(C->val), skip);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
@@ -1170,7 +1174,13 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const dou
   lnv_bsm AP{ev.LS.pat, 4, LNV_F64, ap};
   LNV_TRY(multiply_launch(1.0, S, &Pm, 0, 0.0, &APT, 1, nullptr, nullptr, nullptr, skip, s));
   LNV_TRY(transpose_skip_launch(&APT, ev.perm_SL, ap, skip, s));
-  LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &XP, 1, nullptr, nullptr, nullptr, skip, s));
+  if (!XPT && XP.pat == ev.Z.pat && sym_ready(&ev.Zu, &XP)) {
+    // M = S: X_P = S P S is symmetric, formed from its upper blocks
+    LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &ev.Zu, 1, nullptr, nullptr, nullptr, skip, s));
+    LNV_TRY(mirror_launch(&ev.Zu, &XP, s, skip));
+  } else {
+    LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &XP, 1, nullptr, nullptr, nullptr, skip, s));
+  }
   const lnv_bsm* B = &XP;
   if (XPT) {
     LNV_TRY(transpose_skip_launch(&XP, ev.perm_X, static_cast<double*>(XPT->val), skip, s));

@@ -757,6 +757,7 @@ class LNVSystem:
         algorithmic count with the functions each stored row holds."""
         if padded or not self.split:
             t = dict(self.triples)
+            t["Vf"] = t["V"]               # P_L(SL.Z) in full (trace products)
             if self.symmetric:
                 t.update(self.triples_upper)
             return {k: 2 * BLK ** 3 * v for k, v in t.items()}
@@ -768,7 +769,8 @@ class LNVSystem:
         up = self.pLu if self.symmetric else self.pL     # symmetric products: upper halves
         specs = {"SL": (self.pS, self.pL, None), "X": (self.pH, self.pLS, None),
                  "Z": (self.pS, self.pLS, self.pZu), "YT": (self.pSL, self.pXT, self.pL),
-                 "W": (self.pSL, self.pX, up), "V": (self.pSL, self.pZ, up)}
+                 "W": (self.pSL, self.pX, up), "V": (self.pSL, self.pZ, up),
+                 "Vf": (self.pSL, self.pZ, self.pL)}
         if self.metric is not None:
             specs.update(TG=(self.pL, self.pL, None), TGT=(self.pLL, self.pL, up))
         if self.adj_ws is not None:
@@ -795,9 +797,9 @@ class LNVSystem:
         ev = t["SL"] + t["X"] + t["Z"] + t["YT"] + t["W"] + t["V"]
         line = t["SL"] + t["X"] + 2 * t["YT"]
         nchk = t["SL"] + t["Z"] + t["V"]
-        ncor = t["SL"] + t["Z"] + 2 * t["V"]
+        ncor = t["SL"] + t["Z"] + 2 * t["Vf"]
         met = 2 * (t["TG"] + t["TGT"]) if self.metric is not None else 0
-        tot = {"eval": ev, "init": t["SL"] + t["Z"] + t["V"],
+        tot = {"eval": ev, "init": t["SL"] + t["Z"] + t["Vf"],
                "step_base": ev + met + line + nchk, "ncorr": ncor,
                "step": ev + met + line + nchk + ncor}[what]
         return tot
