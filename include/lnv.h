@@ -462,12 +462,24 @@ int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm
  * for forces under the electron-number constraint).  Any of the three may be
  * NULL, not all.  FP64, blk 4.  Hot path: allocates nothing, no host
  * synchronisation.
+ * Symmetric products (optional, val == NULL: formed in full): LSL, the
+ * symmetric parts 6 LSL - 4 LSLSL of dH and 12 (LSL - LSLSL) of dN/dS, and
+ * 6 LHL of dS are formed from their upper-triangle blocks (j >= i) and
+ * mirrored, as in lnv_eval_ws:
+ *  LSLu  values on the upper triangle of pat(L.S.L) (LSL's pattern then
+ *        needs lut)
+ *  Hu    values on the upper triangle of H's pattern (H's pattern: lut)
+ *  Su    values on the upper triangle of S's pattern
+ * (each upper pattern with items and the cluster plan of the other outputs).
  */
 typedef struct lnv_adj_ws {
   lnv_bsm SL;
   lnv_bsm LSL;
   lnv_bsm HL;
   double* YS;
+  lnv_bsm LSLu;
+  lnv_bsm Hu;
+  lnv_bsm Su;
 } lnv_adj_ws;
 
 int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* dS,

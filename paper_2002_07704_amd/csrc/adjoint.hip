@@ -12,7 +12,9 @@
 // and, for forces at a constrained minimum, the electron-number derivative
 //   dN/dS = 12 (LSL - LSLSL) = P_S(12 L.SL - 12 LSL.SL)   (N = 2 Tr[KS])
 // so every product reads its right operand in stored orientation and the
-// transposed term costs one gather on S's own (symmetric) pattern.
+// transposed term costs one gather on S's own (symmetric) pattern.  LSL, the
+// two-term symmetric combinations of dH and dN/dS and L.HL are formed from
+// their upper-triangle blocks when the workspace provides the buffers.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -86,28 +88,41 @@ extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
                            lnv_bsm* dH, lnv_bsm* dNS, const lnv_adj_ws* ws, hipStream_t s) {
   LNV_TRY(check_adjoint(L, S, H, dS, dH, dNS, ws));
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &ws->SL, 1, nullptr, nullptr, nullptr, nullptr, s));
-  LNV_TRY(multiply_launch(1.0, L, &ws->SL, 0, 0.0, &ws->LSL, 1, nullptr, nullptr, nullptr,
-                          nullptr, s));
-  if (dH) {
-    LNV_TRY(multiply_launch(-4.0, &ws->LSL, &ws->SL, 0, 0.0, dH, 1, nullptr, nullptr, nullptr,
+  // LSL = L S L is symmetric: its upper blocks, then the mirror
+  if (sym_ready(&ws->LSLu, &ws->LSL)) {
+    LNV_TRY(multiply_launch(1.0, L, &ws->SL, 0, 0.0, &ws->LSLu, 1, nullptr, nullptr, nullptr,
                             nullptr, s));
-    LNV_TRY(multiply_launch(6.0, L, &ws->SL, 0, 1.0, dH, 1, nullptr, nullptr, nullptr, nullptr,
-                            s));
-  }
-  if (dNS) {
-    LNV_TRY(multiply_launch(-12.0, &ws->LSL, &ws->SL, 0, 0.0, dNS, 1, nullptr, nullptr, nullptr,
+    LNV_TRY(mirror_launch(&ws->LSLu, &ws->LSL, s));
+  } else {
+    LNV_TRY(multiply_launch(1.0, L, &ws->SL, 0, 0.0, &ws->LSL, 1, nullptr, nullptr, nullptr,
                             nullptr, s));
-    LNV_TRY(multiply_launch(12.0, L, &ws->SL, 0, 1.0, dNS, 1, nullptr, nullptr, nullptr, nullptr,
-                            s));
   }
+  // a L.SL + b LSL.SL on the symmetric output pattern of D (= a LSL + b LSLSL)
+  auto two_terms = [&](double a, double b, lnv_bsm* D, const lnv_bsm* U) -> int {
+    const lnv_bsm* out = sym_ready(U, D) ? U : D;
+    LNV_TRY(multiply_launch(b, &ws->LSL, &ws->SL, 0, 0.0, out, 1, nullptr, nullptr, nullptr,
+                            nullptr, s));
+    LNV_TRY(multiply_launch(a, L, &ws->SL, 0, 1.0, out, 1, nullptr, nullptr, nullptr, nullptr,
+                            s));
+    return out == U ? mirror_launch(U, D, s) : LNV_OK;
+  };
+  if (dH) LNV_TRY(two_terms(6.0, -4.0, dH, &ws->Hu));
+  if (dNS) LNV_TRY(two_terms(12.0, -12.0, dNS, &ws->Su));
   if (dS) {
     const lnv_pattern* ps = S->pat;
     lnv_bsm Y{ps, 4, LNV_F64, ws->YS};
     LNV_TRY(multiply_launch(1.0, H, L, 0, 0.0, &ws->HL, 1, nullptr, nullptr, nullptr, nullptr, s));
     LNV_TRY(multiply_launch(1.0, &ws->LSL, &ws->HL, 0, 0.0, &Y, 1, nullptr, nullptr, nullptr,
                             nullptr, s));
-    LNV_TRY(multiply_launch(6.0, L, &ws->HL, 0, 0.0, dS, 1, nullptr, nullptr, nullptr, nullptr,
-                            s));
+    // 6 L H L is symmetric; Y = LSLHL is not
+    if (sym_ready(&ws->Su, dS)) {
+      LNV_TRY(multiply_launch(6.0, L, &ws->HL, 0, 0.0, &ws->Su, 1, nullptr, nullptr, nullptr,
+                              nullptr, s));
+      LNV_TRY(mirror_launch(&ws->Su, dS, s));
+    } else {
+      LNV_TRY(multiply_launch(6.0, L, &ws->HL, 0, 0.0, dS, 1, nullptr, nullptr, nullptr, nullptr,
+                              s));
+    }
     if (ps->n_items > 0) {
       k_sym_update<<<ps->n_items, 256, 0, s>>>(ps->n, ps->items, ps->row_ptr, ps->col, ps->lut,
                                                ws->YS, -4.0, static_cast<double*>(dS->val));

@@ -97,6 +97,14 @@ int multiply_pair_launch(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1
                          const void* m11, const void* m12, double* part1, const void* m21,
                          const void* m22, double* part2, const double* skip, hipStream_t s);
 
+// Symmetric products: U holds the upper-triangle blocks (j >= i) of C, whose
+// pattern is symmetric with lut and items.  mirror_launch fills C from U
+// (C_ij = U_ji^T below the diagonal, the symmetric part of U_ii on it);
+// skip as in multiply_launch.
+bool sym_ready(const lnv_bsm* U, const lnv_bsm* C);
+int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
+                  const double* skip = nullptr);
+
 // Number of dot partials (work items) multiply_launch writes for C.
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C);
 

@@ -814,19 +814,16 @@ struct EvalOps {
   void* Vu;
 };
 
+}  // namespace
+
 bool sym_ready(const lnv_bsm* U, const lnv_bsm* C) {
   return U && U->val && U->pat && U->pat->n == C->pat->n && U->pat->items && U->pat->row_ptr &&
          U->dtype == C->dtype && C->pat->lut && C->pat->items;
 }
 
-// C = A.B on C's (symmetric) pattern for a product known to be symmetric.
-// With an upper-triangle buffer U (sym_ready) only the blocks j >= i are
-// multiplied, into U, and C is filled from them by a transposing copy;
-// otherwise C is formed in full.
 // C (full symmetric pattern) from its upper-triangle blocks U (skip: as in
 // the multiply, a device flag that turns the launch into a no-op).
-int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
-                  const double* skip = nullptr) {
+int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s, const double* skip) {
   const lnv_pattern *pf = C->pat, *pu = U->pat;
   if (pf->n_items == 0) return LNV_OK;
   if (C->dtype == LNV_F32)
@@ -841,6 +838,12 @@ int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
   return LNV_OK;
 }
 
+namespace {
+
+// C = A.B on C's (symmetric) pattern for a product known to be symmetric.
+// With an upper-triangle buffer U (sym_ready) only the blocks j >= i are
+// multiplied, into U, and C is filled from them by a transposing copy;
+// otherwise C is formed in full.
 int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_bsm* U,
                 hipStream_t s) {
   if (!sym_ready(U, C))

@@ -65,7 +65,8 @@ class LnvEval32Ws(ctypes.Structure):
 
 
 class LnvAdjWs(ctypes.Structure):
-    _fields_ = [("SL", LnvBsm), ("LSL", LnvBsm), ("HL", LnvBsm), ("YS", c_void_p)]
+    _fields_ = [("SL", LnvBsm), ("LSL", LnvBsm), ("HL", LnvBsm), ("YS", c_void_p),
+                ("LSLu", LnvBsm), ("Hu", LnvBsm), ("Su", LnvBsm)]
 
 
 class LnvOpts(ctypes.Structure):

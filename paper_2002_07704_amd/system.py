@@ -481,6 +481,8 @@ class LNVSystem:
             pats.append(self.pLL)
         if getattr(self, "adj_ws", None) is not None:
             pats += [self.pLSL, self.pHL]
+            if self.symmetric:
+                pats += [self.pLSLu, self.pHu, self.pSu]
         return pats
 
     def set_cluster(self, shape):
@@ -645,13 +647,34 @@ class LNVSystem:
         self.pLSL.build_items()
         self.pHL.build_lut(lut=True).build_items()
         self.pS.build_lut(lut=True).build_items()
+        adj_upper = []
+        if self.symmetric:
+            # upper halves of the symmetric adjoint products (L.S.L keeps its
+            # index table for the mirror, H's pattern gets one)
+            self.pLSL.build_lut(lut=True)
+            self.pH.build_lut(lut=True)
+            self.pLSLu, self.pHu, self.pSu = (upper_pattern(P) for P in
+                                              (self.pLSL, self.pH, self.pS))
+            adj_upper = [self.pLSLu, self.pHu, self.pSu]
+            self.triples_upper.update(
+                LSL=product_pattern(self.pL, self.pSL, mask=self.pLSLu).triples,
+                dH4=product_pattern(self.pLSL, self.pSL, mask=self.pHu).triples,
+                dH6=product_pattern(self.pL, self.pSL, mask=self.pHu).triples,
+                dS6=product_pattern(self.pL, self.pHL, mask=self.pSu).triples)
         if self.cluster is not None:
-            # left operand L.S.L and output H.L take part in clustered products;
-            # L.S.L's index table is needed only while its plan is built
+            # left operand L.S.L and outputs H.L (and the upper halves) take
+            # part in clustered products; without the halves L.S.L's index
+            # table is needed only while its plan is built
+            tmp = self.pLSL.lut is None
             self.pLSL.build_lut(lut=True).build_cluster(*self.cluster)
-            self.pLSL.lut = None
-            self.pLSL._sync()
+            if tmp:
+                self.pLSL.lut = None
+                self.pLSL._sync()
             self.pHL.build_cluster(*self.cluster)
+            for P in adj_upper:
+                P.build_lut(lut=True).build_cluster(*self.cluster)
+                P.lut = None
+                P._sync()
         self.LSL = Matrix(self.pLSL)
         self.HL = Matrix(self.pHL)
         self.YS = torch.zeros(self.pS.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
@@ -660,6 +683,11 @@ class LNVSystem:
         self.adj_ws.LSL = self.LSL.struct
         self.adj_ws.HL = self.HL.struct
         self.adj_ws.YS = self.YS.data_ptr()
+        if self.symmetric:
+            self.LSLu, self.Hu, self.Su = (Matrix(P) for P in adj_upper)
+            self.adj_ws.LSLu = self.LSLu.struct
+            self.adj_ws.Hu = self.Hu.struct
+            self.adj_ws.Su = self.Su.struct
         torch.cuda.synchronize()
 
     def adjoint_flops(self, dS=True, dH=True, padded=False):
@@ -774,9 +802,11 @@ class LNVSystem:
         if self.metric is not None:
             specs.update(TG=(self.pL, self.pL, None), TGT=(self.pLL, self.pL, up))
         if self.adj_ws is not None:
-            specs.update(LSL=(self.pL, self.pSL, None), HL=(self.pH, self.pL, None),
-                         dH4=(self.pLSL, self.pSL, self.pH), dH6=(self.pL, self.pSL, self.pH),
-                         dS4=(self.pLSL, self.pHL, self.pS), dS6=(self.pL, self.pHL, self.pS))
+            sym = self.symmetric
+            mL, mH, mS = ((self.pLSLu, self.pHu, self.pSu) if sym else (None, self.pH, self.pS))
+            specs.update(LSL=(self.pL, self.pSL, mL), HL=(self.pH, self.pL, None),
+                         dH4=(self.pLSL, self.pSL, mH), dH6=(self.pL, self.pSL, mH),
+                         dS4=(self.pLSL, self.pHL, self.pS), dS6=(self.pL, self.pHL, mS))
         fun = self.fun_rows
         for k, (A, B, M) in specs.items():
             if k not in self._alg:
