@@ -185,11 +185,17 @@ def upper_pattern(P):
 
 
 def is_symmetric(P):
-    rp, col = P.host()
-    rows = np.repeat(np.arange(P.n), np.diff(rp))
-    a = np.lexsort((col, rows))
-    b = np.lexsort((rows, col))
-    return bool(np.array_equal(rows[a], col[b]) and np.array_equal(col[a], rows[b]))
+    """Whether every block (i, j) of P has its transpose (j, i) in P (on the
+    device, through the transpose map of P onto itself; builds P's lut)."""
+    if P.lut is None:
+        P.build_lut(lut=True)
+    try:
+        transpose_map(P, P)
+    except L_.LnvError as e:
+        if e.status == L_.EPATTERN:
+            return False
+        raise
+    return True
 
 
 class Matrix:

@@ -339,6 +339,11 @@ def test_symmetric_products_upper_half(gpu):
     b = LNVSystem(w, metric="hotelling", n_hotelling=16, symmetric=False)
     assert a.symmetric and not b.symmetric
     assert a.flops("step") < b.flops("step")
+    from paper_2002_07704_amd.system import Pattern, is_symmetric
+    rp = torch.tensor([0, 2, 3], dtype=torch.int32, device="cuda")
+    col = torch.tensor([0, 1, 1], dtype=torch.int32, device="cuda")
+    assert not is_symmetric(Pattern(2, rp, col))          # (0,1) without (1,0)
+    assert is_symmetric(a.pL) and is_symmetric(a.pZ)
     for s in (a, b):
         s.cg_init()
         s.eval()
