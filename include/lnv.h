@@ -82,6 +82,12 @@ enum { LNV_F64 = 0, LNV_F32 = 1 };
  * this is the contraction list of a cluster; as the output C its columns
  * are split into work pieces of 64/cl_g columns, cl_items[2q] = cluster,
  * cl_items[2q+1] = first position in cl_col.
+ *
+ * Atom tiles: atoms with 13 support functions are stored as 4 consecutive
+ * 4x4-blocked rows (see lnv_synth_blocks), so an atom pair is a dense 16x16
+ * tile.  With 16-row cluster plans (cl_m = 16: 4 such atoms) on A and C and
+ * tile4 set on A and B, the multiply forms whole 16x16x16 atom products on
+ * the matrix cores (lnv_pattern_cluster, lnv_pattern_tile4).
  */
 typedef struct lnv_pattern {
   int32_t n;               /* atoms (block rows = block columns) */
@@ -95,7 +101,7 @@ typedef struct lnv_pattern {
   int32_t cl_m;            /* rows per cluster (0: no cluster plan) */
   int32_t cl_g;            /* lanes sharing one output column (1 or 2) */
   int32_t n_cl_items;      /* entries of cl_items */
-  int32_t cl_pad;
+  int32_t tile4;           /* 1: P is a tile4 pattern (lnv_pattern_tile4), else 0 */
   const int32_t* cl_ptr;   /* device [ceil(n/cl_m)+1] */
   const int32_t* cl_col;   /* device [cl_ptr[last]] */
   const int32_t* cl_pos;   /* device [cl_ptr[last]*cl_m] */
@@ -180,13 +186,27 @@ int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT, int32
 
 /* lnv_pattern_cluster -- cluster plan of P (see lnv_pattern) for clusters of
  * m rows with g lanes per output column, each lane accumulating 4 rows:
- * (m, g) = (4, 1) or (8, 2).  P needs lut.  Two-phase like lnv_neighbours: with
+ * (m, g) = (4, 1) or (8, 2); or atom-tile plans, m = 16 (4 atoms of 4 rows)
+ * with pieces of 64/g = 16 or 8 union columns (4 or 2 column atoms per
+ * wavefront), (m, g) = (16, 4) or (16, 8).  The atom-tile multiply needs the
+ * unions in aligned runs of 4 columns, which holds for tile4 patterns and
+ * for the upper triangles of symmetric tile4 patterns.  P needs lut.  Two-phase like lnv_neighbours: with
  * cl_col == NULL only *len_out (union length) and *n_items_out are
  * reported; cl_ptr is always written (device [ceil(n/m)+1]).  Synchronises s. */
 int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_ptr,
                         int32_t* cl_col, int32_t* cl_pos, int64_t cap, int32_t* cl_items,
                         int64_t items_cap, int64_t* len_out, int32_t* n_items_out,
                         hipStream_t s);
+
+/* lnv_pattern_tile4 -- *ok_out (host) = 1 when P is a tile4 pattern: n is a
+ * multiple of 4, rows 4a..4a+3 hold the same columns, and every row's
+ * columns come in aligned runs 4b, 4b+1, 4b+2, 4b+3 -- the layout of atoms
+ * stored as 4 rows each with patterns built from atom distances.  Then the
+ * 16 blocks of an atom tile are found from the position p of its first one
+ * as p + s*len + t (sub-row s, sub-column t, len the row length).  Patterns
+ * with mixed atom sizes or upper-triangle patterns give 0.  Set-up call:
+ * allocates a flag, synchronises s. */
+int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStream_t s);
 
 /* lnv_pattern_items -- work list of P: with items == NULL only counts.
  *  n_items_out  host: number of items (LNV_ECAPACITY if cap is smaller).
@@ -270,12 +290,17 @@ int lnv_bsm_remap(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
 int lnv_bsm_norm_inf(const lnv_bsm* A, double* partials, double* out, hipStream_t s);
 
 /* lnv_set_f32_accumulation -- arithmetic of the FP32 products (process-wide):
- * LNV_ACC_F32 (the default): FP32 multiply-add into FP32 accumulators;
+ * LNV_ACC_F32 (the default): FP32 multiply-add into FP32 accumulators (the
+ * atom-tile multiply: v_mfma_f32_16x16x4_f32);
  * LNV_ACC_F64: FP64 multiply-add into FP64 accumulators (the product of two
  * FP32 values is exact in FP64, so only the sums round, in FP64), the result
- * rounded once to FP32 at the store.  Either way the operands and the result
- * are stored in FP32. */
-enum { LNV_ACC_F32 = 0, LNV_ACC_F64 = 1 };
+ * rounded once to FP32 at the store;
+ * LNV_ACC_F16X3: atom-tile multiplies split each operand as x*2^8 = hi + lo
+ * in FP16 and form Ah.Bh + Ah.Bl + Al.Bh on v_mfma_f32_16x16x16_f16 with
+ * FP32 accumulation (about FP32 accuracy for |x| >= 5e-4; entries must stay
+ * below 255 in magnitude); the 4x4 multiplies run as LNV_ACC_F32.
+ * Either way the operands and the result are stored in FP32. */
+enum { LNV_ACC_F32 = 0, LNV_ACC_F64 = 1, LNV_ACC_F16X3 = 2 };
 int lnv_set_f32_accumulation(int32_t acc);
 
 /* lnv_set_kslabs -- split every multiply's contraction index k into n

@@ -2,12 +2,15 @@
 
 The multiply's one tunable is the row-cluster shape of its output-stationary
 work decomposition (how many output rows a wavefront accumulates per
-gathered right-operand block, and how many lanes share a column).  Which one
-is fastest depends on the register budget of the value type and on how
-similar the rows of a cluster are (the cluster's contraction list is the
-union of its rows'), so the tuner times a full evaluation with each
-candidate on the actual system and keeps the fastest.  Results are cached per
-pattern signature for the life of the process.
+gathered right-operand block, and how many lanes share a column), and, for
+cells whose atoms all carry 13 support functions (4 stored rows each), the
+atom-tile shapes that multiply whole 16x16 atom tiles on the matrix cores.
+Which one is fastest depends on the register budget of the value type, the
+arithmetic mode and on how similar the rows of a cluster are (the cluster's
+contraction list is the union of its rows'), so the tuner times a full
+evaluation with each candidate on the actual system and keeps the fastest.
+Results are cached per pattern signature and accumulation mode for the life
+of the process.
 """
 from __future__ import annotations
 
@@ -19,14 +22,20 @@ CANDIDATES = ((4, 1), (8, 2), None)
 _CACHE: dict = {}
 
 
-def signature(system, mixed):
-    return (system.n_rows, system.pL.nnzb, system.pS.nnzb, system.pH.nnzb, bool(mixed))
+def signature(system, mixed, acc=0):
+    return (system.n_rows, system.pL.nnzb, system.pS.nnzb, system.pH.nnzb, bool(mixed),
+            int(acc))
 
 
-def tune(system, candidates=CANDIDATES, reps=3, mixed=False):
-    """Time one evaluation (FP64, or mixed precision) per cluster shape, leave
-    the system on the fastest; returns (shape, {shape: ms})."""
-    key = signature(system, mixed)
+def tune(system, candidates=None, reps=3, mixed=False, acc=0):
+    """Time one evaluation (FP64, or mixed precision) per cluster shape
+    (default: the row clusters plus the system's atom-tile shapes), leave the
+    system on the fastest; returns (shape, {shape: ms}).  acc: the FP32
+    accumulation mode the caller has set (lnv_set_f32_accumulation), part of
+    the cache key."""
+    if candidates is None:
+        candidates = CANDIDATES + system.tile_shapes()
+    key = signature(system, mixed, acc)
     if key in _CACHE:
         best, res = _CACHE[key]
         system.set_cluster(best)

@@ -24,6 +24,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -482,6 +483,302 @@ __global__ __launch_bounds__(256) void k_mul44c1(
   }
 }
 
+// ------------------------------------------------------------------ atom tiles
+// Atoms with 13 support functions (the DZP-like silicon basis) are stored as
+// 4 consecutive 4x4-blocked rows each (padded to 16 functions), so the block
+// of an atom pair is a dense 16x16 tile and an atom triple (i,k,j) is a dense
+// 16x16x16 contraction: the shape of the matrix-core (MFMA) instructions.
+// Requirements (checked on the host): A's and B's patterns are "tile4" (the 4
+// rows of an atom hold the same columns, in aligned runs 4b..4b+3, so a tile's
+// 16 sub-blocks sit at pos(sub-row 0) + s*len + t), A and C carry 16-row
+// cluster plans (4 atoms per cluster, the union of their columns in aligned
+// runs of 4), B carries lut.
+//
+// A wavefront owns 4 cluster atoms x NB column atoms, i.e. 4*NB accumulator
+// tiles (4 values per lane per tile), and runs the k loop over the cluster's
+// union of A columns one atom (4 union entries) per step; each A tile is used
+// for NB outputs, each B tile for the 4 cluster atoms.  Tiles missing from A,
+// B or the output are skipped with wave-uniform branches.
+//
+// Operand layout (all modes): lane l = i + 16c holds row i of A's tile at
+// k = 4c..4c+3 (one 4-value row of a 4x4 block: a 16-byte load in FP32) and
+// column i of B's tile at k = 4c..4c+3 (four values 16 bytes apart).
+// Arithmetic modes (MODE):
+//  TM_F32    v_mfma_f32_16x16x4_f32, four per tile and step: instruction p
+//            takes the p-th of each lane's four values, i.e. contracts
+//            k = 4c + p over the lane groups c (the instruction's 16x4 by
+//            4x16 operands with k permuted; the sum over p covers all 16 k).
+//  TM_F64    v_mfma_f64_16x16x4_f64, the same in FP64 (FP64 storage, or FP32
+//            storage widened exactly: FP64 products and sums).
+//  TM_F16X3  FP16 hi/lo split on v_mfma_f32_16x16x16_f16 (whose operands are
+//            exactly these four-value rows and columns): x*2^8 = hi + lo with
+//            hi = fp16(x*2^8), lo = fp16(x*2^8 - hi) (22 significant bits in
+//            all), and A.B formed as Ah.Bh + Ah.Bl + Al.Bh (the dropped Al.Bl
+//            is ~2^-22 of a term), then scaled by 2^-16.  The 2^8 scaling
+//            keeps lo out of FP16's subnormal range for |x| >= 5e-4 and
+//            overflows for |x| >= 255 (far above any entry of S, H, L or
+//            their products here).
+// Output tile: lane l = n + 16g holds column n, rows 4g..4g+3 (FP32
+// accumulators) or rows g, g+4, g+8, g+12 (FP64), as measured on gfx950.
+// Index pipeline (as in k_mul44c1): per step one vector load fetches, for two
+// steps ahead, the 4 cluster atoms' A positions (lanes 0-3), B's row pointers
+// of that step's k (lanes 4-5), the k of three steps ahead (lane 6) and the
+// NB B positions from B's lut (lanes 8..); the fragments of the next step are
+// loaded before the current step's products, all unconditionally from clamped
+// positions, so the compiler's wait counts stay exact.
+enum { TM_F32 = 0, TM_F64 = 1, TM_F16X3 = 2 };
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
+
+template <int MODE>
+struct TileAcc {
+  using type = f32x4_t;
+};
+template <>
+struct TileAcc<TM_F64> {
+  using type = f64x4_t;
+};
+
+constexpr float kF16Scale = 256.0f;               // 2^8 per operand
+constexpr double kF16Unscale = 1.0 / 65536.0;     // 2^-16 on the product
+
+__device__ __forceinline__ void split_f16(const float (&x)[4], f16x4_t& hi, f16x4_t& lo) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const float s = x[e] * kF16Scale;
+    const _Float16 h = (_Float16)s;
+    hi[e] = h;
+    lo[e] = (_Float16)(s - (float)h);
+  }
+}
+
+// Fragments of one step: a[ar][.] for the 4 cluster atoms, b[q][.] for the NB
+// column atoms (block positions pa / pb of sub-row 0, -1 when the tile is
+// missing; rowA[ar] = (lane's sub-row) * A's row length of that atom).  Lane
+// l = i + 16c holds a[ar][w] = A[i][4c + w] (row i of the tile: one 4-value
+// row of block (i>>2, c)) and b[q][w] = B[4c + w][i] (column i of block
+// (c, i>>2)), w = 0..3.
+template <int NB, typename T>
+__device__ __forceinline__ void tile_load(T (&a)[4][4], T (&b)[NB][4], const int (&pa)[4],
+                                          const int (&pb)[NB], int lenB,
+                                          const T* __restrict__ a_val,
+                                          const T* __restrict__ b_val, const int (&rowA)[4],
+                                          int li, int lq, int amax, int bmax) {
+#pragma unroll
+  for (int ar = 0; ar < 4; ++ar) {
+    const int blk = min(max(pa[ar], 0) + rowA[ar] + lq, amax);
+    const T* ap = a_val + (size_t)blk * 16 + (li & 3) * 4;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) a[ar][w] = ap[w];
+  }
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int blk = min(max(pb[q], 0) + lq * lenB + (li >> 2), bmax);
+    const T* bp = b_val + (size_t)blk * 16 + (li & 3);
+#pragma unroll
+    for (int w = 0; w < 4; ++w) b[q][w] = bp[w * 4];
+  }
+}
+
+template <int MODE, int NB, typename T, typename AccT>
+__device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
+                                         const T (&b)[NB][4], const int (&pa)[4],
+                                         const int (&pb)[NB], uint64_t cmask) {
+  if constexpr (MODE == TM_F16X3) {
+    f16x4_t ah[4], al[4], bh[NB], bl[NB];
+#pragma unroll
+    for (int ar = 0; ar < 4; ++ar) split_f16(a[ar], ah[ar], al[ar]);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) split_f16(b[q], bh[q], bl[q]);
+#pragma unroll
+    for (int ar = 0; ar < 4; ++ar) {
+      if (pa[ar] < 0) continue;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (pb[q] < 0 || !((cmask >> (4 * q + ar)) & 1u)) continue;
+        // the step's three products start from zero and join the running sum
+        // through a rounded VALU add, so rounding in the matrix unit's own
+        // accumulation does not build up over the contraction
+        f32x4_t t = {0.f, 0.f, 0.f, 0.f};
+        t = __builtin_amdgcn_mfma_f32_16x16x16f16(al[ar], bh[q], t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[ar], bl[q], t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x16f16(ah[ar], bh[q], t, 0, 0, 0);
+        acc[ar][q] += t;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int ar = 0; ar < 4; ++ar) {
+      if (pa[ar] < 0) continue;
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        if (pb[q] < 0 || !((cmask >> (4 * q + ar)) & 1u)) continue;
+        // instruction p contracts k = 4c + p over the lane groups c
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          if constexpr (MODE == TM_F64)
+            acc[ar][q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[ar][p], (double)b[q][p],
+                                                             acc[ar][q], 0, 0, 0);
+          else
+            acc[ar][q] = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a[ar][p], (float)b[q][p],
+                                                             acc[ar][q], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+template <int NB, int MODE, int STORE, int NDOT, typename T>
+__global__ __launch_bounds__(256) void k_tile16(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
+    const int* __restrict__ ka_col, const int* __restrict__ ka_pos, const int* __restrict__ a_rp,
+    const T* __restrict__ a_val, int a_nnzb, const int* __restrict__ b_rp,
+    const int* __restrict__ b_lut, const T* __restrict__ b_val, int b_nnzb,
+    const int* __restrict__ jc_ptr, const int* __restrict__ jc_col,
+    const int* __restrict__ jc_pos, T* __restrict__ c_val, double alpha, double beta,
+    const T* __restrict__ m1, const T* __restrict__ m2, double* __restrict__ partials,
+    const double* __restrict__ skip) {
+  using AccT = typename TileAcc<MODE>::type;
+  if (skip != nullptr && *skip != 0.0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (item >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int c = items[2 * item];
+  const int p0 = items[2 * item + 1];
+  const int ncol = min(4 * NB, jc_ptr[c + 1] - p0);
+  const int r0 = c * 16;
+  // output tiles present (bit 4q + ar): sub-row 0 / sub-column 0 of the tile
+  // is present whenever any of its blocks is (full or upper-triangle patterns)
+  int here = 0;
+  if (lane < 4 * NB) {
+    const int ar = lane & 3, q = lane >> 2;
+    here = 4 * q < ncol && jc_pos[(size_t)(p0 + 4 * q) * 16 + 4 * ar] >= 0;
+  }
+  const uint64_t cmask = __ballot(here);
+  // this lane's column atom for the lut lanes (4b, the first of its rows)
+  const int my_b = (lane >= 8 && lane < 8 + NB && 4 * (lane - 8) < ncol)
+                       ? jc_col[p0 + 4 * (lane - 8)] : 0;
+  int rowA[4];
+#pragma unroll
+  for (int ar = 0; ar < 4; ++ar) {
+    const int r = r0 + 4 * ar;
+    const int len = r < n ? a_rp[r + 1] - a_rp[r] : 0;
+    rowA[ar] = (li >> 2) * len;  // this lane's sub-row of the tile
+  }
+  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
+  const int amax = a_nnzb - 1, bmax = b_nnzb - 1;
+
+  AccT acc[4][NB];
+#pragma unroll
+  for (int ar = 0; ar < 4; ++ar)
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[ar][q][v] = 0;
+
+  const int nsteps = (t1 - t0) >> 2;  // atoms of the contraction union
+  if (nsteps > 0) {
+    const int tl = t0 + 4 * (nsteps - 1);
+    // index vector for the step whose entries start at te (k row 4k = kk)
+    auto iv_src = [&](int te, int kk) -> const int* {
+      const int tc = min(max(te, t0), tl);
+      if (lane < 4) return ka_pos + (size_t)tc * 16 + 4 * lane;
+      if (lane < 6) return b_rp + kk + (lane - 4);
+      if (lane == 6) return ka_col + min(max(te + 4, t0), tl);
+      if (lane >= 8 && lane < 8 + NB) return b_lut + (size_t)kk * n + my_b;
+      return ka_col + tl;
+    };
+    // before the first iteration: the index vector of step -1 (clamped to
+    // step 0's entries; never multiplied), whose lane 6 gives step 0's k
+    int ivp = *iv_src(t0 - 4, ka_col[t0]);
+    int pa0[4], pb0[NB];
+#pragma unroll
+    for (int ar = 0; ar < 4; ++ar) pa0[ar] = -1;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) pb0[q] = -1;
+    T fa0[4][4] = {}, fb0[NB][4] = {}, fa1[4][4], fb1[NB][4];
+    // iteration u: read the indices of step u+1 (issued at u-1), issue those
+    // of step u+2, load the fragments of step u+1, multiply step u
+#define LNV_T16_STEP(u, FC_A, FC_B, FN_A, FN_B)                                  \
+  {                                                                              \
+    int pa1[4], pb1[NB];                                                         \
+    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) pa1[ar] =                   \
+        __builtin_amdgcn_readlane(ivp, ar);                                      \
+    const int lenB1 = __builtin_amdgcn_readlane(ivp, 5) - __builtin_amdgcn_readlane(ivp, 4); \
+    const int kk2 = __builtin_amdgcn_readlane(ivp, 6);                           \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) pb1[q] =                      \
+        __builtin_amdgcn_readlane(ivp, 8 + q);                                   \
+    const int ivn = *iv_src(t0 + 4 * ((u) + 2), kk2);                            \
+    tile_load<NB, T>(FN_A, FN_B, pa1, pb1, lenB1, a_val, b_val, rowA, li, lq, amax, bmax); \
+    if ((u) >= 0 && (u) < nsteps) tile_mma<MODE, NB>(acc, FC_A, FC_B, pa0, pb0, cmask); \
+    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) pa0[ar] = pa1[ar];          \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) pb0[q] = pb1[q];              \
+    ivp = ivn;                                                                   \
+  }
+    for (int u = -2; u < nsteps; u += 2) {
+      LNV_T16_STEP(u, fa0, fb0, fa1, fb1)
+      LNV_T16_STEP(u + 1, fa1, fb1, fa0, fb0)
+    }
+#undef LNV_T16_STEP
+  }
+
+  // epilogue: lane (n + 16g) holds column n of each tile (column n&3 of
+  // block n>>2), in register v the tile row 4g + v (FP32 accumulators) or
+  // 4v + g (v_mfma_f64_16x16x4_f64), i.e. sub-row (row >> 2), row (row & 3)
+  // of that 4x4 block
+  const double sc = MODE == TM_F16X3 ? kF16Unscale : 1.0;
+  const int g = lq, nn = li;
+  double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+  for (int ar = 0; ar < 4; ++ar)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = p0 + 4 * q + (nn >> 2);
+      if (!((cmask >> (4 * q + ar)) & 1u) || e >= p0 + ncol) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = MODE == TM_F64 ? 4 * v + g : 4 * g + v;
+        const int pos = jc_pos[(size_t)e * 16 + 4 * ar + (row >> 2)];
+        if (pos < 0) continue;
+        const size_t at = (size_t)pos * 16 + (row & 3) * 4 + (nn & 3);
+        const double val = alpha * (sc * (double)acc[ar][q][v]);
+        const T out = (T)(beta != 0.0 ? val + beta * (double)c_val[at] : val);
+        if (STORE) c_val[at] = out;
+        if (NDOT >= 1) d1 = fma((double)m1[at], (double)out, d1);
+        if (NDOT >= 2) d2 = fma((double)m2[at], (double)out, d2);
+      }
+    }
+  if (NDOT >= 1) {
+    d1 = wave_sum(d1);
+    if (NDOT >= 2) d2 = wave_sum(d2);
+    if (lane == 0) {
+      partials[2 * item] = d1;
+      partials[2 * item + 1] = d2;
+    }
+  }
+}
+
+template <typename T>
+using KernelT16Fn = void (*)(int, int, const int*, const int*, const int*, const int*,
+                             const int*, const T*, int, const int*, const int*, const T*, int,
+                             const int*, const int*, const int*, T*, double, double, const T*,
+                             const T*, double*, const double*);
+
+template <int NB, int MODE, typename T>
+KernelT16Fn<T> pick_t16(int store, int ndot) {
+  if (store) {
+    if (ndot == 0) return k_tile16<NB, MODE, 1, 0, T>;
+    if (ndot == 1) return k_tile16<NB, MODE, 1, 1, T>;
+    return k_tile16<NB, MODE, 1, 2, T>;
+  }
+  if (ndot == 1) return k_tile16<NB, MODE, 0, 1, T>;
+  return k_tile16<NB, MODE, 0, 2, T>;
+}
+
 template <typename T>
 using KernelCFn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
                            const int*, const T*, const int*, const int*, const int*, T*, double,
@@ -571,16 +868,70 @@ int kslabs_for(const lnv_bsm* B) {
 
 bool use_clustered(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
   const lnv_pattern *pa = A->pat, *pc = C->pat;
-  return !transB && kslabs_for(B) == 1 && pa->cl_m > 0 && pa->cl_m == pc->cl_m && pa->cl_ptr &&
+  return !transB && kslabs_for(B) == 1 && pa->cl_m > 0 && pa->cl_m != 16 &&
+         pa->cl_m == pc->cl_m && pa->cl_ptr &&
          pa->cl_col && pa->cl_pos && pc->cl_ptr && pc->cl_col && pc->cl_pos && pc->cl_items &&
          pc->cl_g * 4 == pc->cl_m;
 }
 
+// Atom-tile (MFMA) multiply: 16-row cluster plans on A and C, tile4 patterns
+// on A and B (see k_tile16), B's lut, row count a multiple of 4.
+bool use_tiles(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
+  return !transB && kslabs_for(B) == 1 && pa->cl_m == 16 && pc->cl_m == 16 &&
+         (pc->cl_g == 4 || pc->cl_g == 8) && pa->tile4 == 1 && pb->tile4 == 1 && pb->lut &&
+         pa->n % 4 == 0 && pa->cl_ptr && pa->cl_col && pa->cl_pos && pc->cl_ptr &&
+         pc->cl_col && pc->cl_pos && pc->cl_items && pa->row_ptr && pb->row_ptr &&
+         pa->nnzb > 0 && pb->nnzb > 0 && pa->nnzb < INT32_MAX && pb->nnzb < INT32_MAX;
+}
+
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
-  return use_clustered(A, B, transB, C) ? C->pat->n_cl_items : C->pat->n_items;
+  return use_clustered(A, B, transB, C) || use_tiles(A, B, transB, C) ? C->pat->n_cl_items
+                                                                      : C->pat->n_items;
 }
 
 namespace {
+
+// Arithmetic of the atom-tile multiply for storage type T: FP64 storage runs
+// FP64 MFMA; FP32 storage follows the process-wide accumulation mode.
+template <typename T>
+int tile_mode() {
+  if (std::is_same<T, double>::value || g_f32_acc == LNV_ACC_F64) return TM_F64;
+  return g_f32_acc == LNV_ACC_F16X3 ? TM_F16X3 : TM_F32;
+}
+
+template <typename T>
+int launch_tiles(double alpha, const lnv_bsm* A, const lnv_bsm* B, double beta,
+                 const lnv_bsm* C, int store, const T* m1, const T* m2, double* partials,
+                 const double* skip, int ndot, hipStream_t s) {
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
+  if (pc->n_cl_items == 0) return LNV_OK;
+  const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
+  const bool nb4 = pc->cl_g == 4;  // 4 column atoms per wave (cl_g 8: 2)
+  KernelT16Fn<T> fn = nullptr;
+  const int mode = tile_mode<T>();
+  if (mode == TM_F64) {
+    fn = nb4 ? pick_t16<4, TM_F64, T>(store, ndot) : pick_t16<2, TM_F64, T>(store, ndot);
+  } else {
+    if constexpr (std::is_same<T, float>::value) {
+      if (mode == TM_F16X3)
+        fn = nb4 ? pick_t16<4, TM_F16X3, T>(store, ndot) : pick_t16<2, TM_F16X3, T>(store, ndot);
+      else
+        fn = nb4 ? pick_t16<4, TM_F32, T>(store, ndot) : pick_t16<2, TM_F32, T>(store, ndot);
+    }
+  }
+  if (!fn) return LNV_EUNSUPPORTED;
+  hipEvent_t stop = nullptr;
+  LNV_TRY(timer_begin(s, &stop));
+  fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
+                         pa->cl_pos, pa->row_ptr, static_cast<const T*>(A->val), (int)pa->nnzb,
+                         pb->row_ptr, pb->lut, static_cast<const T*>(B->val), (int)pb->nnzb,
+                         pc->cl_ptr, pc->cl_col, pc->cl_pos, static_cast<T*>(C->val), alpha,
+                         beta, m1, m2, partials, skip);
+  LNV_LAUNCH_CHECK();
+  if (stop) LNV_HIP(hipEventRecord(stop, s));
+  return LNV_OK;
+}
 
 template <typename T, typename Acc>
 int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, double beta,
@@ -594,6 +945,8 @@ int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
   const T* m1 = static_cast<const T*>(m1v);
   const T* m2 = static_cast<const T*>(m2v);
   const int nslab = kslabs_for(B);
+  if (use_tiles(A, B, transB, C))
+    return launch_tiles<T>(alpha, A, B, beta, C, store, m1, m2, partials, skip, ndot, s);
   if (use_clustered(A, B, transB, C)) {
     if (pc->n_cl_items == 0) return LNV_OK;
     const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
@@ -735,7 +1088,7 @@ extern "C" int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B
 }
 
 extern "C" int lnv_set_f32_accumulation(int32_t acc) {
-  if (acc != LNV_ACC_F32 && acc != LNV_ACC_F64) return LNV_EINVAL;
+  if (acc != LNV_ACC_F32 && acc != LNV_ACC_F64 && acc != LNV_ACC_F16X3) return LNV_EINVAL;
   g_f32_acc = acc;
   return LNV_OK;
 }

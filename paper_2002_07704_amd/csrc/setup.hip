@@ -311,6 +311,26 @@ __global__ __launch_bounds__(256) void k_cluster_items(int nc, int piece,
   }
 }
 
+// tile4 check, one workgroup per row r: same length and columns as row
+// 4(r/4), columns in aligned runs 4b..4b+3.  Any violation sets *bad (a
+// vector atomic; the flag only ever goes from 0 to 1).
+__global__ __launch_bounds__(256) void k_tile4(int n, const int* __restrict__ rp,
+                                               const int* __restrict__ col, int* __restrict__ bad) {
+  const int r = blockIdx.x;
+  const int r4 = r & ~3;
+  const int p0 = rp[r], len = rp[r + 1] - p0;
+  const int q0 = rp[r4], len4 = rp[r4 + 1] - q0;
+  if (len != len4 || (len & 3) != 0) {
+    if (threadIdx.x == 0) atomicOr(bad, 1);
+    return;
+  }
+  for (int t = threadIdx.x; t < len; t += 256) {
+    const int j = col[p0 + t];
+    const bool ok = j == col[q0 + t] && (j & 3) == (t & 3) && j - (t & 3) == col[p0 + (t & ~3)];
+    if (!ok) atomicOr(bad, 1);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_items(int n, const int* __restrict__ rp,
                                                int* __restrict__ counts,
                                                const int* __restrict__ off,
@@ -692,6 +712,33 @@ extern "C" int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_
   return LNV_OK;
 }
 
+extern "C" int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStream_t s) {
+  if (!P || !ok_out) return LNV_EINVAL;
+  if (!P->row_ptr || !P->col || P->n <= 0) return LNV_EPATTERN;
+  if (P->n % 4 != 0) {
+    *ok_out = 0;
+    return LNV_OK;
+  }
+  int32_t* bad = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int32_t), s));
+  int32_t hbad = 1;
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+  if (e == hipSuccess) {
+    k_tile4<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t ef = hipFreeAsync(bad, s);
+  if (e == hipSuccess) e = ef;
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return LNV_EHIP;
+  }
+  *ok_out = hbad == 0 ? 1 : 0;
+  return LNV_OK;
+}
+
 extern "C" int lnv_pattern_items(const lnv_pattern* P, int32_t* items, int64_t cap,
                                  int32_t* n_items_out, hipStream_t s) {
   if (!P || !P->row_ptr || P->n <= 0) return LNV_EPATTERN;
@@ -836,7 +883,8 @@ extern "C" int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, i
                                    int32_t* cl_items, int64_t items_cap, int64_t* len_out,
                                    int32_t* n_items_out, hipStream_t s) {
   if (!P || !cl_ptr || !len_out || !n_items_out) return LNV_EINVAL;
-  if (!((m == 4 && g == 1) || (m == 8 && g == 2))) return LNV_EUNSUPPORTED;
+  if (!((m == 4 && g == 1) || (m == 8 && g == 2) || (m == 16 && (g == 4 || g == 8))))
+    return LNV_EUNSUPPORTED;
   if (!P->row_ptr || !P->col || !P->lut || P->n <= 0 || P->n > LNV_MAX_ATOMS) return LNV_EPATTERN;
   const int n = P->n;
   const int nc = (n + m - 1) / m;

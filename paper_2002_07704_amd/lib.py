@@ -31,7 +31,7 @@ class LnvPattern(ctypes.Structure):
     _fields_ = [("n", c_int32), ("n_items", c_int32), ("nnzb", c_int64),
                 ("row_ptr", c_void_p), ("col", c_void_p), ("lut", c_void_p),
                 ("lut_t", c_void_p), ("items", c_void_p),
-                ("cl_m", c_int32), ("cl_g", c_int32), ("n_cl_items", c_int32), ("cl_pad", c_int32),
+                ("cl_m", c_int32), ("cl_g", c_int32), ("n_cl_items", c_int32), ("tile4", c_int32),
                 ("cl_ptr", c_void_p), ("cl_col", c_void_p), ("cl_pos", c_void_p),
                 ("cl_items", c_void_p)]
 
@@ -94,6 +94,7 @@ SIGNATURES = {
     "lnv_pattern_cluster": (c_int, [PPat, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_int64,
                                     c_void_p, c_int64, POINTER(c_int64), POINTER(c_int32),
                                     c_void_p]),
+    "lnv_pattern_tile4": (c_int, [PPat, POINTER(c_int32), c_void_p]),
     "lnv_bsm_transpose": (c_int, [PBsm, c_void_p, PBsm, c_void_p]),
     "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, c_void_p, c_void_p, PBsm,
                                  c_int32, c_double, c_double, c_uint64, c_double, c_void_p]),

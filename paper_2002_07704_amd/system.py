@@ -41,6 +41,7 @@ class Pattern:
         self.items = None
         self.triples = None
         self.cl = None          # (m, g, cl_ptr, cl_col, cl_pos, cl_items)
+        self.tile4 = 0          # lnv_pattern_tile4 result (atoms stored as 4 rows)
         self.struct = L_.LnvPattern()
         self._sync()
 
@@ -65,6 +66,16 @@ class Pattern:
             s.cl_pos, s.cl_items = cpos.data_ptr(), citems.data_ptr()
         else:
             s.cl_m = s.cl_g = s.n_cl_items = 0
+        s.tile4 = self.tile4
+
+    def check_tile4(self):
+        """lnv_pattern_tile4: may the atom-tile multiply read this pattern by
+        tiles (4 rows per atom, columns in aligned runs of 4)?"""
+        ok = c_int32(0)
+        L_.call("lnv_pattern_tile4", byref(self.struct), byref(ok), _stream())
+        self.tile4 = int(ok.value)
+        self._sync()
+        return self.tile4
 
     def build_lut(self, lut=True, lut_t=False):
         dev = self.row_ptr.device
@@ -105,6 +116,8 @@ class Pattern:
                 ccol.numel(), _ptr(citems), citems.numel() // 2, byref(ln), byref(ni), _stream())
         self.cl = (m, g, cptr, ccol, cpos, citems[:2 * ni.value])
         self._sync()
+        if m == 16:
+            self.check_tile4()
         return self
 
     def host(self):
@@ -491,10 +504,27 @@ class LNVSystem:
                 pats += [self.pLSLu, self.pHu, self.pSu]
         return pats
 
+    def tile_shapes(self):
+        """Atom-tile shapes ((16, 4): 4 x 4 atom tiles per wave, (16, 8):
+        4 x 2) when every atom is stored as 4 rows (13 support functions),
+        else ()."""
+        if self.cells is None and self.n_rows == 4 * self.n and self.pL.check_tile4():
+            return ((16, 4), (16, 8))
+        return ()
+
+    def _all_patterns(self):
+        return [v for v in vars(self).values() if isinstance(v, Pattern)]
+
     def set_cluster(self, shape):
         """Row-cluster shape of the multiply: (4, 1) (4 rows per wave, one lane
-        per output column), (8, 2) (8 rows, two lanes per column), or None
-        (one row per wave).  Rebuilds the cluster plans in place."""
+        per output column), (8, 2) (8 rows, two lanes per column), None
+        (one row per wave), or the atom tiles (16, 4) / (16, 8) (16-row
+        plans: 4 atoms of 4 rows, products of whole 16x16 atom tiles on the
+        matrix cores; right operands need tile4).  Rebuilds the plans in
+        place."""
+        if shape is not None and shape[0] == 16:
+            for P in self._all_patterns():
+                P.check_tile4()
         for P in self._cluster_patterns():
             if shape is None:
                 P.cl = None
@@ -508,7 +538,23 @@ class LNVSystem:
                 P.lut = None
                 P._sync()
         self.cluster = shape
+        self._size_partials()
         torch.cuda.synchronize()
+
+    def _size_partials(self):
+        """Trace partials: one pair per work piece of L's pattern (row items or
+        cluster pieces, whichever are more); grown when a plan needs more."""
+        st = self.pL.struct
+        need = L_.load().lnv_partials_len(max(st.n_items, st.n_cl_items))
+        if getattr(self, "partials", None) is not None and self.partials.numel() >= need:
+            return
+        self.partials = torch.zeros(need, dtype=torch.float64, device=self.dev)
+        if getattr(self, "ws", None) is not None:
+            self.ws.ev.partials = self.partials.data_ptr()
+            self.ws.ev.partials_len = need
+        if getattr(self, "ws32", None) is not None:
+            self.ws32.partials = self.partials.data_ptr()
+            self.ws32.partials_len = need
 
     # ----------------------------------------------------------- row layout
     def _layout_single(self, w, R_L, reorder):
@@ -677,6 +723,8 @@ class LNVSystem:
                 self.pLSL.lut = None
                 self.pLSL._sync()
             self.pHL.build_cluster(*self.cluster)
+            if self.cluster[0] == 16:
+                self.pSL.check_tile4()
             for P in adj_upper:
                 P.build_lut(lut=True).build_cluster(*self.cluster)
                 P.lut = None

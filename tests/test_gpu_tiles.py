@@ -1,0 +1,228 @@
+"""Atom-tile multiply: atoms with 13 support functions (stored as 4 rows of 4,
+padded to 16) multiplied as whole 16x16 atom tiles on the matrix cores.
+
+Cells, each with every atom at 13 functions and the 13-function workload's
+ranges (S 12, H 14, L 10 bohr):
+* 64-atom diamond Si (16 clusters of 4 atoms);
+* 22 atoms of an amorphous cell (the last 4-atom cluster holds 2 atoms);
+* one atom in a small periodic cell (one cluster holding one atom, every
+  block a sum over many images).
+
+Checks: with each tile shape, E, N, G, F against the oracle at a seeded L
+(|dE|, |dN| <= 1e-10 per atom, G and F 1e-12 relative, padding exactly zero)
+and against the 4x4 path on the same L; Hotelling-metric CG iterations and the
+adjoint against the oracle; the three mixed-precision modes of the tiles
+(FP32 MFMA, FP32 storage with FP64 MFMA, FP16 hi/lo split) within 1e-6 Ha/atom
+of the oracle's energy, N, G and F within the FP32 rounding bound 3 sqrt(k) u
+(u = 2^-22 for the hi/lo split).  At 8192 atoms (the 13-function workload at a quarter
+of its size) the tile evaluation is compared with the 4x4 path's.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import lnv_workloads as W
+from oracle import lnv as olnv
+from oracle import structure as ost
+from paper_2002_07704_amd import lib as L_
+from test_gpu_split import Layout, _rand_sym
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(16, 4), (16, 8)]
+ACC_F32, ACC_F64, ACC_F16X3 = 0, 1, 2
+
+
+def _w13(name, pos, box, seed):
+    n = pos.shape[0]
+    return W.Workload(name=name, pos=np.mod(pos, box), box=np.asarray(box, dtype=np.float64),
+                      nfun=np.full(n, 13, dtype=np.int32), species=np.zeros(n, dtype=np.int8),
+                      R_S=12.0, R_H=14.0, R_L=10.0, n_elec=4 * n, seed=seed,
+                      scale=math.sqrt(4.0 / 13.0), blk_pad=16)
+
+
+def _cells():
+    pos22, box22 = W.amorphous_positions(22, 0.0074, 3.0, seed=31)
+    return {
+        "si64_13": W.diamond_workload("si64_13f", (2, 2, 2), seed=3, nfun=13,
+                                      R=(12.0, 14.0, 10.0)),
+        "am22_13": _w13("am22_13f", pos22, box22, 31),
+        "one13": _w13("one13f", np.array([[1.0, 2.0, 3.0]]), np.array([7.0, 7.5, 8.0]), 41),
+    }
+
+
+NAMES = ["si64_13", "am22_13", "one13"]
+
+
+@pytest.fixture(scope="module")
+def cells(gpu):
+    from paper_2002_07704_amd.system import LNVSystem
+    out = {}
+    for name, w in _cells().items():
+        s = LNVSystem(w, metric="hotelling", n_hotelling=16)
+        out[name] = (s, ost.System(w), Layout(s))
+    yield out
+    L_.call("lnv_set_f32_accumulation", ACC_F32)
+
+
+def _tol(s, acc):
+    """3 sqrt(k) u relative: the rounding bound of one FP32-accumulated entry
+    over a contraction of k = 4 x the longest row of pat(S.L) terms, with u
+    the operands' unit roundoff (2^-24 in FP32; 2^-22 for the FP16 hi/lo
+    split's 11 + 11 significant bits)."""
+    rp = s.pSL.row_ptr.cpu().numpy()
+    k = 4 * int(np.diff(rp).max())
+    u = 2.0 ** -22 if acc == ACC_F16X3 else 2.0 ** -24
+    return 3.0 * math.sqrt(k) * u
+
+
+def _seeded_L(s, ref, lay, seed):
+    n = lay.n_orb
+    Ld = _rand_sym(n, ref.maskL, seed) + 0.2 * np.eye(n) * ref.maskL
+    s.L.val.copy_(lay.to_blocks(Ld, s.pL))
+    return Ld
+
+
+@pytest.mark.parametrize("name", NAMES)
+def test_tile_shapes_offered(cells, name):
+    s, _, _ = cells[name]
+    assert s.tile_shapes() == tuple(SHAPES)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("name", NAMES)
+def test_tile_eval_matches_oracle(cells, name, shape):
+    s, ref, lay = cells[name]
+    w = s.w
+    Ld = _seeded_L(s, ref, lay, 5)
+    s.set_cluster((4, 1))
+    s.eval()
+    torch.cuda.synchronize()
+    EN4, G4 = s.EN.clone(), s.G.val.clone()
+    s.set_cluster(shape)
+    assert s.pS.cl[0] == 16 and s.pS.tile4 == 1 and s.pLS.tile4 == 1 and s.pX.tile4 == 1
+    print(f"{name} {shape}: {s.n} atoms, {s.n_rows} rows, pieces of L {s.pL.struct.n_cl_items}",
+          flush=True)
+    s.eval()
+    torch.cuda.synchronize()
+    E, N = (float(x) for x in s.EN.cpu())
+    Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
+    print(f"{name} {shape}: |dE|/atom {abs(E - Er) / w.n:.2e} |dN|/atom {abs(N - Nr) / w.n:.2e}",
+          flush=True)
+    assert abs(E - Er) / w.n <= 1e-10, (E, Er)
+    assert abs(N - Nr) / w.n <= 1e-10, (N, Nr)
+    G = lay.to_dense(s.G.val, s.pL)          # padding exactly zero
+    F = lay.to_dense(s.F.val, s.pL)
+    assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
+    assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
+    # the same evaluation on the 4x4 kernels (other summation order)
+    assert torch.allclose(s.EN, EN4, rtol=1e-13, atol=0.0)
+    assert (s.G.val - G4).abs().max() <= 1e-13 * G4.abs().max()
+    s.set_cluster((4, 1))
+
+
+def test_tile_cg_trajectory(cells):
+    s, ref, lay = cells["si64_13"]
+    w = s.w
+    steps = 6
+    T = olnv.hotelling(ref.S, ref.maskL, 16)
+    _, hist = olnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, steps, T=T)
+    s.set_cluster((16, 4))
+    s.cg_init()
+    for k in range(steps):
+        s.cg_step()
+        sc = s.scalars_host()
+        h = hist[k]
+        print(f"tiles k={k} E/atom gpu {sc['E'] / w.n:.13f} oracle {h['E'] / w.n:.13f}",
+              flush=True)
+        assert abs(sc["E"] - h["E"]) / w.n <= 1e-10, k
+        assert abs(sc["N"] - h["N"]) <= 1e-9 * max(1.0, w.n_elec / 64), k
+        assert abs(sc["ALPHA"] - h["alpha"]) <= 1e-8 * abs(h["alpha"]), k
+        assert abs(sc["DELTA"] - h["delta"]) <= 1e-8 * max(abs(h["delta"]), 1e-6), k
+        assert int(sc["STATUS"]) & 3 == 0
+    torch.cuda.synchronize()
+    lay.to_dense(s.L.val, s.pL)
+    s.set_cluster((4, 1))
+
+
+def test_tile_adjoint(cells):
+    s, ref, lay = cells["si64_13"]
+    s.set_cluster((16, 4))
+    Ld = _seeded_L(s, ref, lay, 9)
+    dS = torch.empty_like(s.S.val)
+    dH = torch.empty_like(s.H.val)
+    s.adjoint(s.L.val, s.S.val, s.H.val, dS=dS, dH=dH)
+    torch.cuda.synchronize()
+    gS = olnv.grad_S(Ld, ref.S, ref.H, ref.maskS)
+    gH = olnv.grad_H(Ld, ref.S, ref.maskH)
+    assert np.abs(lay.to_dense(dS, s.pS) - gS).max() <= 1e-12 * np.abs(gS).max()
+    assert np.abs(lay.to_dense(dH, s.pH) - gH).max() <= 1e-12 * np.abs(gH).max()
+    s.set_cluster((4, 1))
+
+
+@pytest.mark.parametrize("acc", [ACC_F32, ACC_F64, ACC_F16X3])
+@pytest.mark.parametrize("name", ["si64_13", "am22_13"])
+def test_tile_mixed_modes(cells, gpu, name, acc):
+    s, ref, lay = cells[name]
+    w = s.w
+    Ld = _seeded_L(s, ref, lay, 7)
+    Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
+    s.set_cluster((16, 4))
+    L_.call("lnv_set_f32_accumulation", acc)
+    try:
+        s.eval_mixed()
+        torch.cuda.synchronize()
+    finally:
+        L_.call("lnv_set_f32_accumulation", ACC_F32)
+    E, N = (float(x) for x in s.EN.cpu())
+    G = lay.to_dense(s.G.val, s.pL)
+    F = lay.to_dense(s.F.val, s.pL)
+    eG = np.abs(G - Gr).max() / np.abs(Gr).max()
+    eF = np.abs(F - Fr).max() / np.abs(Fr).max()
+    print(f"{name} acc={acc}: |dE|/atom {abs(E - Er) / w.n:.2e} |dN|/atom "
+          f"{abs(N - Nr) / w.n:.2e} dG {eG:.2e} dF {eF:.2e}", flush=True)
+    tol = _tol(s, acc)
+    assert abs(E - Er) / w.n <= 1e-6
+    assert abs(N - Nr) <= tol * abs(Nr)
+    assert eG <= tol and eF <= tol
+    s.set_cluster((4, 1))
+
+
+def test_tile_eval_at_scale(gpu):
+    """8192 atoms with 13 functions (32768 rows): tile evaluations against the
+    4x4 path's FP64 evaluation at the CG start."""
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.diamond_workload("si8192_13f", (16, 16, 4), seed=3, nfun=13, R=(12.0, 14.0, 10.0))
+    s = LNVSystem(w, metric="hotelling")
+    s.cg_init()
+    s.eval()
+    torch.cuda.synchronize()
+    E4, N4 = (float(x) for x in s.EN.cpu())
+    G4 = s.G.val.clone()
+    for shape in SHAPES:
+        s.set_cluster(shape)
+        s.eval()
+        torch.cuda.synchronize()
+        E, N = (float(x) for x in s.EN.cpu())
+        dG = float((s.G.val - G4).abs().max() / G4.abs().max())
+        print(f"si8192_13f {shape}: E/atom {E / w.n:.14f} (4x4 {E4 / w.n:.14f}) dG {dG:.1e}",
+              flush=True)
+        assert abs(E - E4) / w.n <= 1e-12 and abs(N - N4) / w.n <= 1e-12
+        assert dG <= 1e-12
+    s.mixed_setup()
+    for acc in (ACC_F32, ACC_F16X3):
+        L_.call("lnv_set_f32_accumulation", acc)
+        try:
+            s.eval_mixed()
+            torch.cuda.synchronize()
+        finally:
+            L_.call("lnv_set_f32_accumulation", ACC_F32)
+        E, N = (float(x) for x in s.EN.cpu())
+        dG = float((s.G.val - G4).abs().max() / G4.abs().max())
+        print(f"si8192_13f mixed acc={acc}: |dE|/atom {abs(E - E4) / w.n:.2e} "
+              f"|dN|/atom {abs(N - N4) / w.n:.2e} dG {dG:.1e}", flush=True)
+        tol = _tol(s, acc)
+        assert abs(E - E4) / w.n <= 1e-6 and abs(N - N4) <= tol * abs(N4)
+        assert dG <= tol
