@@ -129,7 +129,9 @@ def extra_configs(reps):
 
     import lnv_workloads as W
     from paper_2002_07704_amd import autotune
+    from paper_2002_07704_amd import lib as L_
     from paper_2002_07704_amd.system import LNVSystem
+    lib = L_.load()
     cells = [
         ("si8192_13f", W.diamond_workload("si8192_13f", (16, 16, 4), seed=3, nfun=13,
                                           R=(12.0, 14.0, 10.0)),
@@ -160,6 +162,7 @@ def extra_configs(reps):
             torch.cuda.synchronize()
             return (time.perf_counter() - t1) * 1e3 / reps
 
+        tiles = None
         if batch:
             ms64 = timed(lambda: s.cell_energies())
             E64 = float(s.EN[0])
@@ -167,10 +170,32 @@ def extra_configs(reps):
             ms32 = timed(lambda: s.cell_energies(mixed=True))
         else:
             ms64 = timed(s.eval)
-            E64 = float(s.EN[0])
+            E64, N64 = (float(x) for x in s.EN.cpu())
+            G64 = s.G.val.clone()
             s.mixed_setup()
+            shape32, tried32 = autotune.tune(s, mixed=True)
             ms32 = timed(s.eval_mixed)
+            if s.tile_shapes():
+                # the atom-tile multiply in each arithmetic mode (16x16 atom
+                # tiles on the matrix cores), errors against the FP64 evaluation
+                tiles = {"mixed_cluster_shape": str(shape32),
+                         "autotune_mixed_eval_ms": {str(k): v for k, v in tried32.items()}}
+                for acc, label in ((0, "fp32_mfma"), (2, "fp16_hilo_mfma"), (1, "fp64_mfma_fp32_storage")):
+                    lib.lnv_set_f32_accumulation(acc)
+                    for tshape in s.tile_shapes():
+                        s.set_cluster(tshape)
+                        ms = timed(s.eval_mixed)
+                        E, N = (float(x) for x in s.EN.cpu())
+                        dG = float((s.G.val - G64).abs().max() / G64.abs().max())
+                        tiles[f"{label}_{tshape[0]}x{tshape[1]}"] = {
+                            "eval_ms": ms, "evals_per_s": 1e3 / ms,
+                            "dE_per_atom": abs(E - E64) / s.n, "dN_rel": abs(N - N64) / N64,
+                            "dG_rel": dG}
+                lib.lnv_set_f32_accumulation(0)
+                s.set_cluster(shape32)
+                s.eval_mixed()
         E32 = float(s.EN[0])
+        s.set_cluster(shape)
         f_alg, f_pad = s.flops("eval"), s.flops("eval", padded=True)
         cg = None
         if not batch:
@@ -204,11 +229,34 @@ def extra_configs(reps):
                      "tflops_algorithmic": f_alg / (ms64 * 1e-3) / 1e12,
                      "mixed_eval_ms": ms32, "mixed_evals_per_s": 1e3 / ms32,
                      "mixed_dE_per_atom": abs(E32 - E64) / s.n,
+                     "atom_tiles": tiles,
                      "cg_from_purified_start": cg}
         print(f"[bench] {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
         del s
         torch.cuda.empty_cache()
     return res
+
+
+def profile_tiles(acc, reps=3):
+    """Three evaluations of the 13-function cell on the atom-tile multiply."""
+    import torch
+
+    import lnv_workloads as W
+    from paper_2002_07704_amd import lib as L_
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.diamond_workload("si8192_13f", (16, 16, 4), seed=3, nfun=13, R=(12.0, 14.0, 10.0))
+    s = LNVSystem(w, metric="hotelling")
+    s.cg_init()
+    s.set_cluster((16, 4))
+    if acc >= 0:
+        s.mixed_setup()
+        L_.call("lnv_set_f32_accumulation", acc)
+    for _ in range(reps):
+        s.eval_mixed() if acc >= 0 else s.eval()
+    torch.cuda.synchronize()
+    L_.call("lnv_set_f32_accumulation", 0)
+    print(json.dumps({"profile_tiles": acc, "E": float(s.EN[0]), "N": float(s.EN[1])}),
+          flush=True)
 
 
 def main():
@@ -228,7 +276,15 @@ def main():
     ap.add_argument("--markers", action="store_true",
                     help="launch a short spin kernel before the timed steps and after the "
                          "event-timed steps, so a kernel trace can be cut to them")
+    ap.add_argument("--profile-tiles", type=int, default=None, metavar="ACC",
+                    help="only build the 8192-atom 13-function cell and run 3 evaluations "
+                         "on the atom-tile multiply (16, 4): ACC -1 FP64, 0 FP32 MFMA, "
+                         "1 FP64 MFMA on FP32 storage, 2 FP16 hi/lo (a short program "
+                         "for rocprofv3)")
     args = ap.parse_args()
+    if args.profile_tiles is not None:
+        profile_tiles(args.profile_tiles)
+        return
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.traffic_json, args.workload)
         return
