@@ -170,10 +170,18 @@ int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
 int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B, const lnv_pattern* mask,
                       const int32_t* row_fun, int64_t* flops_out, hipStream_t s);
 
-/* lnv_pattern_upper -- upper triangle of P (row i keeps its columns j >= i);
- * two-phase like lnv_neighbours (col == NULL counts).  Synchronises s. */
-int lnv_pattern_upper(const lnv_pattern* P, int32_t* row_ptr, int32_t* col, int64_t cap,
-                      int64_t* nnz_out, hipStream_t s);
+/* lnv_pattern_half -- the half of a symmetric pattern P that holds each pair
+ * {i, j} once, balanced over the rows: rows are grouped in fours (singly when
+ * n is not a multiple of 4); block (i, j) is kept when i and j fall in one
+ * group and j >= i, or, for groups A != B of m groups, when the cyclic offset
+ * D = (B - A) mod m has 2D < m (ties 2D = m: A < B).  Every row keeps about
+ * half of its columns (the upper triangle j >= i of a periodic cell keeps
+ * nearly all of an early row's columns and few of a late one's, which leaves
+ * the multiply's last wave of work pieces nearly empty), and atoms stored as
+ * 4 rows keep or drop whole 16x16 tiles.  Columns ascending; two-phase like
+ * lnv_neighbours (col == NULL counts).  Synchronises s. */
+int lnv_pattern_half(const lnv_pattern* P, int32_t* row_ptr, int32_t* col, int64_t cap,
+                     int64_t* nnz_out, hipStream_t s);
 
 /* lnv_pattern_lut -- fill the index tables of P (either may be NULL). */
 int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t, hipStream_t s);
@@ -190,7 +198,7 @@ int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT, int32
  * with pieces of 64/g = 16 or 8 union columns (4 or 2 column atoms per
  * wavefront), (m, g) = (16, 4) or (16, 8).  The atom-tile multiply needs the
  * unions in aligned runs of 4 columns, which holds for tile4 patterns and
- * for the upper triangles of symmetric tile4 patterns.  P needs lut.  Two-phase like lnv_neighbours: with
+ * for the halves (lnv_pattern_half) of symmetric tile4 patterns.  P needs lut.  Two-phase like lnv_neighbours: with
  * cl_col == NULL only *len_out (union length) and *n_items_out are
  * reported; cl_ptr is always written (device [ceil(n/m)+1]).  Synchronises s. */
 int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_ptr,
@@ -204,7 +212,7 @@ int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_
  * stored as 4 rows each with patterns built from atom distances.  Then the
  * 16 blocks of an atom tile are found from the position p of its first one
  * as p + s*len + t (sub-row s, sub-column t, len the row length).  Patterns
- * with mixed atom sizes or upper-triangle patterns give 0.  Set-up call:
+ * with mixed atom sizes or halves of symmetric patterns give 0.  Set-up call:
  * allocates a flag, synchronises s. */
 int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStream_t s);
 
@@ -341,14 +349,15 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  *  scalars   device [LNV_NSCALARS] FP64 (see LNV_SC_*)
  * Symmetric products (optional, val == NULL: not used): Z = SLS, W = P_L(SLHLS)
  * and V = P_L(SLSLS) are symmetric for symmetric L, S, H, so only their
- * upper-triangle blocks (j >= i) need forming; the rest is their transpose.
- *  Zu  values on the upper triangle of Z's pattern (lnv_pattern_upper; needs
+ * blocks in one half of their pattern need forming; the rest is their
+ * transpose.
+ *  Zu  values on the half of Z's pattern (lnv_pattern_half; needs lut,
  *      items, and the cluster plan of the other outputs), dtype of Z
- *  Lu  values on the upper triangle of L's pattern (same needs): W's upper
- *      blocks; Vu (device [nnzb of Lu * 16], dtype of W) V's
+ *  Lu  values on the half of L's pattern (same needs): W's blocks there;
+ *      Vu (device [nnzb of Lu * 16], dtype of W) V's
  * Z, W, V are then filled by a transposing copy (Z's and L's patterns need
- * lut and items and must be symmetric; a block whose transpose is missing
- * comes out NaN).  lnv_cg_step uses the same buffers for the electron-number
+ * items and must be symmetric; a block whose transpose is missing comes out
+ * NaN).  lnv_cg_step uses the same buffers for the electron-number
  * check (Z, V at the new L) and Lu for the metric products P_L(T G T).
  */
 typedef struct lnv_eval_ws {
@@ -461,7 +470,7 @@ typedef struct lnv_eval32_ws {
   double* partials;
   int64_t partials_len;
   double* scalars;
-  lnv_bsm Zu;   /* optional upper-triangle products, as in lnv_eval_ws (FP32) */
+  lnv_bsm Zu;   /* optional half products, as in lnv_eval_ws (FP32) */
   lnv_bsm Lu;
   void* Vu;
 } lnv_eval32_ws;
@@ -489,13 +498,13 @@ int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm
  * synchronisation.
  * Symmetric products (optional, val == NULL: formed in full): LSL, the
  * symmetric parts 6 LSL - 4 LSLSL of dH and 12 (LSL - LSLSL) of dN/dS, and
- * 6 LHL of dS are formed from their upper-triangle blocks (j >= i) and
- * mirrored, as in lnv_eval_ws:
- *  LSLu  values on the upper triangle of pat(L.S.L) (LSL's pattern then
- *        needs lut)
- *  Hu    values on the upper triangle of H's pattern (H's pattern: lut)
- *  Su    values on the upper triangle of S's pattern
- * (each upper pattern with items and the cluster plan of the other outputs).
+ * 6 LHL of dS are formed from the blocks of their halves (lnv_pattern_half)
+ * and mirrored, as in lnv_eval_ws:
+ *  LSLu  values on the half of pat(L.S.L)
+ *  Hu    values on the half of H's pattern
+ *  Su    values on the half of S's pattern
+ * (each half pattern with lut, items and the cluster plan of the other
+ * outputs).
  */
 typedef struct lnv_adj_ws {
   lnv_bsm SL;

@@ -14,7 +14,8 @@
 // so every product reads its right operand in stored orientation and the
 // transposed term costs one gather on S's own (symmetric) pattern.  LSL, the
 // two-term symmetric combinations of dH and dN/dS and L.HL are formed from
-// their upper-triangle blocks when the workspace provides the buffers.
+// the blocks of their symmetric halves when the workspace provides the
+// buffers.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -88,7 +89,7 @@ extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
                            lnv_bsm* dH, lnv_bsm* dNS, const lnv_adj_ws* ws, hipStream_t s) {
   LNV_TRY(check_adjoint(L, S, H, dS, dH, dNS, ws));
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &ws->SL, 1, nullptr, nullptr, nullptr, nullptr, s));
-  // LSL = L S L is symmetric: its upper blocks, then the mirror
+  // LSL = L S L is symmetric: the blocks of its half, then the mirror
   if (sym_ready(&ws->LSLu, &ws->LSL)) {
     LNV_TRY(multiply_launch(1.0, L, &ws->SL, 0, 0.0, &ws->LSLu, 1, nullptr, nullptr, nullptr,
                             nullptr, s));

@@ -67,6 +67,24 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// ---------------------------------------------------------------- symmetric halves
+// Half of a symmetric pattern holding each pair {r, c} once, balanced over the
+// rows.  Rows are grouped in fours (singly when n is not a multiple of 4); in
+// one group the block is kept when c >= r; for groups A != B (m groups) when
+// the cyclic group offset D = (B - A) mod m has 2D < m, ties 2D = m by A < B.
+// Every row keeps about half of its columns (the plain upper triangle c >= r
+// keeps nearly all of an early row's columns and few of a late row's), and an
+// atom stored as 4 rows keeps or drops a whole 4x4-blocked tile with another
+// atom.
+__host__ __device__ inline bool in_half(int n, int r, int c) {
+  const int g = (n & 3) == 0 ? 2 : 0;
+  const int A = r >> g, B = c >> g, m = n >> g;
+  if (A == B) return c >= r;
+  int D = B - A;
+  if (D < 0) D += m;
+  return 2 * D < m || (2 * D == m && A < B);
+}
+
 // ---------------------------------------------------------------- checks
 // FP64 matrix (every call but the multiply and transpose takes FP64 only).
 inline bool bsm_ok(const lnv_bsm* M) {
@@ -97,10 +115,11 @@ int multiply_pair_launch(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1
                          const void* m11, const void* m12, double* part1, const void* m21,
                          const void* m22, double* part2, const double* skip, hipStream_t s);
 
-// Symmetric products: U holds the upper-triangle blocks (j >= i) of C, whose
-// pattern is symmetric with lut and items.  mirror_launch fills C from U
-// (C_ij = U_ji^T below the diagonal, the symmetric part of U_ii on it);
-// skip as in multiply_launch.
+// Symmetric products: U holds the blocks of C's symmetric pattern in the half
+// in_half (pattern from lnv_pattern_half, with its own lut), C's pattern has
+// lut and items.  mirror_launch fills C from U (C_ij = U_ij in the half,
+// U_ji^T outside it, the symmetric part of U_ii on the diagonal); skip as in
+// multiply_launch.
 bool sym_ready(const lnv_bsm* U, const lnv_bsm* C);
 int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
                   const double* skip = nullptr);

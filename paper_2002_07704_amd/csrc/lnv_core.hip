@@ -398,17 +398,15 @@ __global__ __launch_bounds__(256) void k_remap(int n, const int* __restrict__ b_
   }
 }
 
-// Full symmetric matrix F from its upper-triangle blocks U (pattern of U =
-// blocks j >= i of F's symmetric pattern): F_ij = U_ij for j > i, U_ji^T for
-// j < i, (U_ii + U_ii^T)/2 on the diagonal.  The position of (i, j), j >= i, in U is its position in F shifted
-// by the lower-triangle blocks of row i: rpU[i] + posF(i,j) - (rpF[i+1] -
-// (rpU[i+1] - rpU[i])).  Workgroup per item of F, 16 threads per block.
+// Full symmetric matrix F from the blocks U of its half (in_half): F_ij =
+// U_ij when (i, j) is in the half, U_ji^T otherwise, (U_ii + U_ii^T)/2 on the
+// diagonal; U's blocks are found through U's own lut.  Workgroup per item of
+// F, 4 threads per block (thread r writes row r).
 template <typename T>
 __global__ __launch_bounds__(256) void k_mirror(int n, const int* __restrict__ items,
                                                 const int* __restrict__ rpF,
                                                 const int* __restrict__ colF,
-                                                const int* __restrict__ lutF,
-                                                const int* __restrict__ rpU,
+                                                const int* __restrict__ lutU,
                                                 const T* __restrict__ U, T* __restrict__ F,
                                                 const double* __restrict__ skip) {
   if (skip != nullptr && *skip != 0.0) return;
@@ -419,13 +417,9 @@ __global__ __launch_bounds__(256) void k_mirror(int n, const int* __restrict__ i
   if (b >= cnt) return;
   const int p = c0 + b;
   const int j = colF[p];
-  // block (i, j) of F is block (min, max) of U, transposed when j < i; the
-  // upper part of a row is the tail of its row in F
-  const bool tr = j < i;
-  const int a = tr ? j : i;
-  const int pa = tr ? lutF[(size_t)j * n + i] : p;
-  const int q = pa < 0 ? -1 : rpU[a] + pa - (rpF[a + 1] - (rpU[a + 1] - rpU[a]));
-  if (q < rpU[a] || q >= rpU[a + 1]) {  // F's pattern not symmetric: poison the block
+  const bool tr = !in_half(n, i, j);
+  const int q = tr ? lutU[(size_t)j * n + i] : lutU[(size_t)i * n + j];
+  if (q < 0) {  // F's pattern not symmetric: poison the block
 #pragma unroll
     for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = T(NAN);
     return;
@@ -802,7 +796,7 @@ int check_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_b
 }
 
 // Operands and intermediates of one evaluation, all of one dtype T.
-// Zu / Lu (val != NULL): upper-triangle patterns for the symmetric products.
+// Zu / Lu (val != NULL): half patterns (in_half) for the symmetric products.
 struct EvalOps {
   const lnv_bsm *L, *S, *H;
   const lnv_bsm *SL, *LS, *X, *XT, *Z;
@@ -818,21 +812,21 @@ struct EvalOps {
 
 bool sym_ready(const lnv_bsm* U, const lnv_bsm* C) {
   return U && U->val && U->pat && U->pat->n == C->pat->n && U->pat->items && U->pat->row_ptr &&
-         U->dtype == C->dtype && C->pat->lut && C->pat->items;
+         U->pat->lut && U->dtype == C->dtype && C->pat->items;
 }
 
-// C (full symmetric pattern) from its upper-triangle blocks U (skip: as in
+// C (full symmetric pattern) from the blocks U of its half (skip: as in
 // the multiply, a device flag that turns the launch into a no-op).
 int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s, const double* skip) {
   const lnv_pattern *pf = C->pat, *pu = U->pat;
   if (pf->n_items == 0) return LNV_OK;
   if (C->dtype == LNV_F32)
-    k_mirror<float><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pf->lut,
-                                                pu->row_ptr, static_cast<const float*>(U->val),
+    k_mirror<float><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pu->lut,
+                                                static_cast<const float*>(U->val),
                                                 static_cast<float*>(C->val), skip);
   else
-    k_mirror<double><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pf->lut,
-                                                 pu->row_ptr, static_cast<const double*>(U->val),
+    k_mirror<double><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pu->lut,
+                                                 static_cast<const double*>(U->val),
                                                  static_cast<double*>(C->val), skip);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
@@ -841,7 +835,7 @@ int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s, const doubl
 namespace {
 
 // C = A.B on C's (symmetric) pattern for a product known to be symmetric.
-// With an upper-triangle buffer U (sym_ready) only the blocks j >= i are
+// With a half buffer U (sym_ready) only the blocks of the half in_half are
 // multiplied, into U, and C is filled from them by a transposing copy;
 // otherwise C is formed in full.
 int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_bsm* U,
@@ -853,7 +847,7 @@ int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_
 }
 
 // Two symmetric products C1 = A1.B1, C2 = A2.B2 with the same output pattern
-// (upper halves U1, U2 on one pattern): one paired launch, then the mirrors.
+// (halves U1, U2 on one pattern): one paired launch, then the mirrors.
 int sym_product_pair(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1, const lnv_bsm* U1,
                      const lnv_bsm* A2, const lnv_bsm* B2, const lnv_bsm* C2, const lnv_bsm* U2,
                      hipStream_t s) {
@@ -878,8 +872,8 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
   LNV_TRY(multiply_launch(1.0, o.S, o.L, 0, 0.0, o.SL, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(transpose_launch(o.SL, o.perm_SL, o.LS->val, s));
   LNV_TRY(multiply_launch(1.0, o.H, o.LS, 0, 0.0, o.X, 1, nullptr, nullptr, nullptr, nullptr, s));
-  // Z = SLS, W = P_L(SLHLS) and V = P_L(SLSLS) are symmetric (upper halves
-  // when the workspace carries them); YT = P_L(SLSLH) is not
+  // Z = SLS, W = P_L(SLHLS) and V = P_L(SLSLS) are symmetric (formed on
+  // their halves when the workspace carries them); YT = P_L(SLSLH) is not
   const lnv_bsm* Lu = o.Lu;
   lnv_bsm Vu{Lu ? Lu->pat : nullptr, 4, dt, o.Vu};
   LNV_TRY(sym_product(o.S, o.LS, o.Z, o.Zu, s));
@@ -1178,7 +1172,7 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const dou
   LNV_TRY(multiply_launch(1.0, S, &Pm, 0, 0.0, &APT, 1, nullptr, nullptr, nullptr, skip, s));
   LNV_TRY(transpose_skip_launch(&APT, ev.perm_SL, ap, skip, s));
   if (!XPT && XP.pat == ev.Z.pat && sym_ready(&ev.Zu, &XP)) {
-    // M = S: X_P = S P S is symmetric, formed from its upper blocks
+    // M = S: X_P = S P S is symmetric, formed from its half
     LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &ev.Zu, 1, nullptr, nullptr, nullptr, skip, s));
     LNV_TRY(mirror_launch(&ev.Zu, &XP, s, skip));
   } else {
@@ -1222,7 +1216,7 @@ int metric_apply(const lnv_bsm* T, const double* V, double* out, lnv_cg_ws* ws, 
 
 // out1 = P_L(T V1 T), out2 = P_L(T V2 T) as paired launches: T.V1 into LL,
 // T.V2 into X's buffer (free between the evaluation and the line search)
-// when pat(L.L) fits there, the upper halves into Lu's and Vu's buffers;
+// when pat(L.L) fits there, the halves into Lu's and Vu's buffers;
 // otherwise one after the other.
 int metric_apply_pair(const lnv_bsm* T, const double* V1, double* out1, const double* V2,
                       double* out2, lnv_cg_ws* ws, hipStream_t s) {

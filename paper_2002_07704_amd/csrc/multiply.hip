@@ -652,7 +652,7 @@ __global__ __launch_bounds__(256) void k_tile16(
   const int ncol = min(4 * NB, jc_ptr[c + 1] - p0);
   const int r0 = c * 16;
   // output tiles present (bit 4q + ar): sub-row 0 / sub-column 0 of the tile
-  // is present whenever any of its blocks is (full or upper-triangle patterns)
+  // is present whenever any of its blocks is (full patterns or their halves)
   int here = 0;
   if (lane < 4 * NB) {
     const int ar = lane & 3, q = lane >> 2;

@@ -183,25 +183,24 @@ __global__ __launch_bounds__(256) void k_symbolic(
   }
 }
 
-// Upper triangle of a pattern: row i keeps its columns j >= i.
-__global__ __launch_bounds__(256) void k_upper(int n, const int* __restrict__ rp,
-                                               const int* __restrict__ col,
-                                               int* __restrict__ counts,
-                                               const int* __restrict__ out_rp,
-                                               int* __restrict__ out_col) {
+// Symmetric half of a pattern (in_half): one thread per row, columns kept in
+// their ascending order.
+__global__ __launch_bounds__(256) void k_half(int n, const int* __restrict__ rp,
+                                              const int* __restrict__ col,
+                                              int* __restrict__ counts,
+                                              const int* __restrict__ out_rp,
+                                              int* __restrict__ out_col) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  int lo = rp[i], hi = rp[i + 1];
-  const int end = hi;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (col[mid] < i) lo = mid + 1; else hi = mid;
-  }
   if (!out_col) {
-    counts[i] = end - lo;
+    int c = 0;
+    for (int p = rp[i]; p < rp[i + 1]; ++p) c += in_half(n, i, col[p]) ? 1 : 0;
+    counts[i] = c;
     return;
   }
-  for (int p = lo, q = out_rp[i]; p < end; ++p, ++q) out_col[q] = col[p];
+  int q = out_rp[i];
+  for (int p = rp[i]; p < rp[i + 1]; ++p)
+    if (in_half(n, i, col[p])) out_col[q++] = col[p];
 }
 
 // ------------------------------------------------------------------ index tables
@@ -682,20 +681,20 @@ extern "C" int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B,
   return LNV_OK;
 }
 
-extern "C" int lnv_pattern_upper(const lnv_pattern* P, int32_t* row_ptr, int32_t* col,
+extern "C" int lnv_pattern_half(const lnv_pattern* P, int32_t* row_ptr, int32_t* col,
                                  int64_t cap, int64_t* nnz_out, hipStream_t s) {
   if (!P || !row_ptr || !nnz_out) return LNV_EINVAL;
   if (!P->row_ptr || !P->col || P->n <= 0) return LNV_EPATTERN;
   const int n = P->n;
   const int grid = (n + 255) / 256;
-  k_upper<<<grid, 256, 0, s>>>(n, P->row_ptr, P->col, row_ptr, nullptr, nullptr);
+  k_half<<<grid, 256, 0, s>>>(n, P->row_ptr, P->col, row_ptr, nullptr, nullptr);
   LNV_LAUNCH_CHECK();
   k_scan<int32_t><<<1, 1024, 0, s>>>(row_ptr, n);
   LNV_LAUNCH_CHECK();
   LNV_TRY(read_total_int(row_ptr + n, nnz_out, s));
   if (!col) return LNV_OK;
   if (cap < *nnz_out) return LNV_ECAPACITY;
-  k_upper<<<grid, 256, 0, s>>>(n, P->row_ptr, P->col, nullptr, row_ptr, col);
+  k_half<<<grid, 256, 0, s>>>(n, P->row_ptr, P->col, nullptr, row_ptr, col);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }

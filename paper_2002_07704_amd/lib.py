@@ -87,7 +87,7 @@ SIGNATURES = {
     "lnv_pattern_product": (c_int, [PPat, PPat, PPat, c_void_p, c_void_p, c_int64,
                                     POINTER(c_int64), c_void_p, POINTER(c_int64), c_void_p]),
     "lnv_pattern_lut": (c_int, [PPat, c_void_p, c_void_p, c_void_p]),
-    "lnv_pattern_upper": (c_int, [PPat, c_void_p, c_void_p, c_int64, POINTER(c_int64), c_void_p]),
+    "lnv_pattern_half": (c_int, [PPat, c_void_p, c_void_p, c_int64, POINTER(c_int64), c_void_p]),
     "lnv_pattern_flops": (c_int, [PPat, PPat, PPat, c_void_p, POINTER(c_int64), c_void_p]),
     "lnv_pattern_items": (c_int, [PPat, c_void_p, c_int64, POINTER(c_int32), c_void_p]),
     "lnv_pattern_transpose_map": (c_int, [PPat, PPat, c_void_p, c_void_p]),

@@ -184,17 +184,18 @@ def product_pattern(A, B, mask=None, triples=True):
     return P
 
 
-def upper_pattern(P):
-    """Upper triangle of the symmetric pattern P (blocks j >= i), with its
-    work list."""
+def half_pattern(P):
+    """The half of the symmetric pattern P that holds each pair of blocks
+    once, balanced over the rows (lnv_pattern_half), with its work list and
+    index table (the mirror finds its blocks through it)."""
     dev = P.row_ptr.device
     rp = torch.empty(P.n + 1, dtype=torch.int32, device=dev)
     nnz = c_int64(0)
-    L_.call("lnv_pattern_upper", byref(P.struct), _ptr(rp), None, 0, byref(nnz), _stream())
+    L_.call("lnv_pattern_half", byref(P.struct), _ptr(rp), None, 0, byref(nnz), _stream())
     col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=dev)
-    L_.call("lnv_pattern_upper", byref(P.struct), _ptr(rp), _ptr(col), col.numel(), byref(nnz),
+    L_.call("lnv_pattern_half", byref(P.struct), _ptr(rp), _ptr(col), col.numel(), byref(nnz),
             _stream())
-    return Pattern(P.n, rp, col[:nnz.value]).build_items()
+    return Pattern(P.n, rp, col[:nnz.value]).build_items().build_lut(lut=True)
 
 
 def is_symmetric(P):
@@ -292,9 +293,9 @@ class LNVSystem:
 
     metric: "hotelling" builds T ~ S^-1 on L's range (n_hotelling steps) and
     runs the CG in that metric; None uses the identity.  symmetric: form only
-    the upper-triangle blocks of the symmetric products SLS, P_L(SLHLS),
-    P_L(SLSLS) and P_L(TGT) and copy the rest transposed (needs symmetric
-    patterns, which L, S, H have).
+    the blocks of one half (half_pattern) of the symmetric products SLS,
+    P_L(SLHLS), P_L(SLSLS) and P_L(TGT) and copy the rest transposed (needs
+    symmetric patterns, which L, S, H have).
     """
 
     def __init__(self, w, device="cuda", R_L=None, metric="hotelling", n_hotelling=16,
@@ -326,12 +327,12 @@ class LNVSystem:
             self.pLL = product_pattern(self.pL, self.pL)          # T.G, T.F
             self.triples["TG"] = self.pLL.triples
             self.triples["TGT"] = product_pattern(self.pLL, self.pL, mask=self.pL).triples
-        # symmetric products Z, W, V (and P_L(TGT)): upper-triangle halves
+        # symmetric products Z, W, V (and P_L(TGT)): balanced halves
         self.symmetric = bool(symmetric) and is_symmetric(self.pL) and is_symmetric(self.pZ)
         self.pZu = self.pLu = None
         if self.symmetric:
-            self.pZu, self.pLu = upper_pattern(self.pZ), upper_pattern(self.pL)
-            # block triples of the upper halves (what the kernels multiply)
+            self.pZu, self.pLu = half_pattern(self.pZ), half_pattern(self.pL)
+            # block triples of the halves (what the kernels multiply)
             self.triples_upper = dict(
                 Z=product_pattern(self.pS, self.pLS, mask=self.pZu).triples,
                 W=product_pattern(self.pSL, self.pX, mask=self.pLu).triples,
@@ -701,11 +702,11 @@ class LNVSystem:
         self.pS.build_lut(lut=True).build_items()
         adj_upper = []
         if self.symmetric:
-            # upper halves of the symmetric adjoint products (L.S.L keeps its
-            # index table for the mirror, H's pattern gets one)
+            # halves of the symmetric adjoint products (L.S.L and H get index
+            # tables)
             self.pLSL.build_lut(lut=True)
             self.pH.build_lut(lut=True)
-            self.pLSLu, self.pHu, self.pSu = (upper_pattern(P) for P in
+            self.pLSLu, self.pHu, self.pSu = (half_pattern(P) for P in
                                               (self.pLSL, self.pH, self.pS))
             adj_upper = [self.pLSLu, self.pHu, self.pSu]
             self.triples_upper.update(
@@ -714,7 +715,7 @@ class LNVSystem:
                 dH6=product_pattern(self.pL, self.pSL, mask=self.pHu).triples,
                 dS6=product_pattern(self.pL, self.pHL, mask=self.pSu).triples)
         if self.cluster is not None:
-            # left operand L.S.L and outputs H.L (and the upper halves) take
+            # left operand L.S.L and outputs H.L (and the halves) take
             # part in clustered products; without the halves L.S.L's index
             # table is needed only while its plan is built
             tmp = self.pLSL.lut is None
@@ -726,9 +727,7 @@ class LNVSystem:
             if self.cluster[0] == 16:
                 self.pSL.check_tile4()
             for P in adj_upper:
-                P.build_lut(lut=True).build_cluster(*self.cluster)
-                P.lut = None
-                P._sync()
+                P.build_cluster(*self.cluster)
         self.LSL = Matrix(self.pLSL)
         self.HL = Matrix(self.pHL)
         self.YS = torch.zeros(self.pS.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
@@ -848,7 +847,7 @@ class LNVSystem:
     def _alg_flops(self):
         if getattr(self, "_alg", None) is None:
             self._alg = {}
-        up = self.pLu if self.symmetric else self.pL     # symmetric products: upper halves
+        up = self.pLu if self.symmetric else self.pL     # symmetric products: halves
         specs = {"SL": (self.pS, self.pL, None), "X": (self.pH, self.pLS, None),
                  "Z": (self.pS, self.pLS, self.pZu), "YT": (self.pSL, self.pXT, self.pL),
                  "W": (self.pSL, self.pX, up), "V": (self.pSL, self.pZ, up),

@@ -132,13 +132,33 @@ def test_product_patterns_and_triples(fx, request):
     _, tYT = ost.pattern_product(SL, X.T.tocsr(), Lp)
     _, tV = ost.pattern_product(SL, Z, Lp)
     assert (sysg.triples["W"], sysg.triples["YT"], sysg.triples["V"]) == (tW, tYT, tV)
-    # upper-triangle halves of the symmetric products (blocks j >= i)
+    # balanced halves of the symmetric products: rows in groups of 4 (m
+    # groups); one group keeps j >= i, groups A != B keep 2((B - A) mod m) < m,
+    # ties A < B
     import scipy.sparse as sps
-    Zu, Lu = sps.triu(Z).tocsr(), sps.triu(Lp).tocsr()
+
+    def half(R):
+        R = R.tocoo()
+        n = R.shape[0]
+        g = 4 if n % 4 == 0 else 1
+        A, B, m = R.row // g, R.col // g, n // g
+        D = (B - A) % m
+        keep = np.where(A == B, R.col >= R.row, (2 * D < m) | ((2 * D == m) & (A < B)))
+        H = sps.csr_matrix((np.ones(int(keep.sum())), (R.row[keep], R.col[keep])), shape=R.shape)
+        # each symmetric pair once, the diagonal once
+        full = set(zip(R.row.tolist(), R.col.tolist()))
+        kept = set(zip(R.row[keep].tolist(), R.col[keep].tolist()))
+        for i, j in full:
+            assert ((i, j) in kept) != ((j, i) in kept) or (i == j and (i, j) in kept)
+        return H
+
+    Zu, Lu = half(Z), half(Lp)
     for P, R in ((sysg.pZu, Zu), (sysg.pLu, Lu)):
         R.sort_indices()
         rp, col = P.host()
         assert np.array_equal(rp, R.indptr) and np.array_equal(col, R.indices)
+    # balance: no row of L's half holds more than 60 % of its row in L
+    assert (np.diff(Lu.indptr) <= 0.6 * np.diff(Lp.tocsr().indptr) + 4).all()
     tu = sysg.triples_upper
     assert tu["Z"] == ost.pattern_product(S, LS, Zu)[1]
     assert tu["W"] == ost.pattern_product(SL, X, Lu)[1]
@@ -326,11 +346,11 @@ def test_cg_trajectory_hotelling_metric(fx, steps, request):
 
 
 # ------------------------------------------------------------------ symmetric products
-def test_symmetric_products_upper_half(gpu):
-    """Z = SLS, W = P_L(SLHLS), V = P_L(SLSLS) and P_L(TGT) formed from their
-    upper-triangle blocks only (the default) against the same system with
-    every block multiplied: the full products are symmetric, so both paths
-    agree to FP64 rounding, and the upper-half path gives exactly symmetric
+def test_symmetric_products_half(gpu):
+    """Z = SLS, W = P_L(SLHLS), V = P_L(SLSLS) and P_L(TGT) formed from the
+    blocks of one half of their patterns only (the default) against the same
+    system with every block multiplied: the full products are symmetric, so
+    both paths agree to FP64 rounding, and the half path gives exactly symmetric
     matrices.  Eval, a Hotelling-metric CG trajectory and the mixed-precision
     evaluation; 3x3x3 cubes, so rows span several 64-block pieces."""
     from paper_2002_07704_amd.system import LNVSystem, transpose, transpose_map, Matrix
