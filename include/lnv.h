@@ -313,7 +313,9 @@ int lnv_set_f32_accumulation(int32_t acc);
 
 /* lnv_set_kslabs -- split every multiply's contraction index k into n
  * atom-index slabs, one launch per slab accumulating into C (n <= 0: the
- * default, a single launch).  Process-wide setting. */
+ * default, a single launch; the atom-tile multiply always runs whole).
+ * Trace-only products (multiply_dot with store == 0) then use C's buffer
+ * for the partial sums.  Process-wide setting. */
 int lnv_set_kslabs(int32_t n);
 
 /* lnv_bsm_dot -- <A, B> = sum over A's blocks of A_ij . B_ij (Frobenius),

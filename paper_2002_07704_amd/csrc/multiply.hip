@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_mul44c1(
     double* __restrict__ partials1, const double* __restrict__ skip,
     const T* __restrict__ a_val2, const int* __restrict__ b_lut2,
     const T* __restrict__ b_val2, T* __restrict__ c_val2, const T* __restrict__ m1_2,
-    const T* __restrict__ m2_2, double* __restrict__ partials2) {
+    const T* __restrict__ m2_2, double* __restrict__ partials2, int k_lo, int k_hi) {
   if (skip != nullptr && *skip != 0.0) return;
   const bool second = PAIR && blockIdx.y != 0;
   const T* __restrict__ a_val = second ? a_val2 : a_val1;
@@ -403,7 +403,23 @@ __global__ __launch_bounds__(256) void k_mul44c1(
   for (int r = 0; r < 4; ++r) opos[r] = act ? jc_pos[(size_t)(p0 + lane) * 4 + r] : -1;
   const int* __restrict__ lcol = b_lut + j;
   const size_t ns = (size_t)n;
-  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
+  int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
+  if (k_lo > 0 || k_hi < n) {
+    // contraction slab: the union entries with k in [k_lo, k_hi) (ascending)
+    int lo = t0, hi = t1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ka_col[mid] < k_lo) lo = mid + 1; else hi = mid;
+    }
+    const int tb = lo;
+    hi = t1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ka_col[mid] < k_hi) lo = mid + 1; else hi = mid;
+    }
+    t0 = tb;
+    t1 = lo;
+  }
 
   Acc acc[4][16];
 #pragma unroll
@@ -799,7 +815,7 @@ template <typename T>
 using KernelC1Fn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
                             const int*, const T*, const int*, const int*, const int*, T*, double,
                             double, const T*, const T*, double*, const double*, const T*,
-                            const int*, const T*, T*, const T*, const T*, double*);
+                            const int*, const T*, T*, const T*, const T*, double*, int, int);
 
 template <int PAIR, typename T, typename Acc>
 KernelC1Fn<T> pick_c1(int store, int ndot) {
@@ -855,10 +871,13 @@ int g_f32_acc = LNV_ACC_F32;  // accumulation of the FP32 products
 
 // Number of contraction slabs (atom-index ranges of k, one launch each,
 // accumulating into C).  Atoms numbered cell by cell make an index range a
-// spatial slab, which bounds the rows of B one launch gathers.  Measured on
-// MI355X at 4096 atoms, splitting makes every product slower (2 slabs: about
-// 2x the time), so the default is a single launch; the split remains
-// available for contractions that must be partitioned.
+// spatial slab, which bounds the rows of B one launch gathers (for the
+// 256 MB Infinity Cache).  Measured on MI355X at 4096 atoms with the
+// pipelined clustered kernel, a CG iteration takes 1.8x (2 slabs), 2.5x (4)
+// and 3.1x (8) the single-launch time: the clusters far from a slab have no
+// work in it, so every launch keeps only part of the device busy.  The
+// default is a single launch; the split remains available for contractions
+// that must be partitioned.
 int kslabs_for(const lnv_bsm* B) {
   if (g_kslab_override > 0) return g_kslab_override < B->pat->n ? g_kslab_override : B->pat->n;
   return 1;
@@ -868,7 +887,7 @@ int kslabs_for(const lnv_bsm* B) {
 
 bool use_clustered(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
   const lnv_pattern *pa = A->pat, *pc = C->pat;
-  return !transB && kslabs_for(B) == 1 && pa->cl_m > 0 && pa->cl_m != 16 &&
+  return !transB && (kslabs_for(B) == 1 || C->pat->cl_g == 1) && pa->cl_m > 0 && pa->cl_m != 16 &&
          pa->cl_m == pc->cl_m && pa->cl_ptr &&
          pa->cl_col && pa->cl_pos && pc->cl_ptr && pc->cl_col && pc->cl_pos && pc->cl_items &&
          pc->cl_g * 4 == pc->cl_m;
@@ -954,11 +973,18 @@ int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
     LNV_TRY(timer_begin(s, &stop));
     // the pipelined kernel reads block 0 of B in place of missing blocks
     if (pc->cl_g == 1 && B->pat->nnzb > 0) {
-      KernelC1Fn<T> fn = pick_c1<0, T, Acc>(store, ndot);
-      fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
-                             pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
-                             alpha, beta, m1, m2, partials, skip, nullptr, nullptr, nullptr,
-                             nullptr, nullptr, nullptr, nullptr);
+      const int n = pa->n;
+      for (int c = 0; c < nslab; ++c) {
+        // slabs of k accumulate into C; the last applies the store / traces
+        const bool last = c == nslab - 1;
+        const int k_lo = (int)((int64_t)c * n / nslab), k_hi = (int)((int64_t)(c + 1) * n / nslab);
+        KernelC1Fn<T> fn = pick_c1<0, T, Acc>(last ? store : 1, last ? ndot : 0);
+        fn<<<wgs, 256, 0, s>>>(n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
+                               pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
+                               alpha, c == 0 ? beta : 1.0, m1, m2, partials, skip, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, k_lo, k_hi);
+        LNV_LAUNCH_CHECK();
+      }
     } else {
       KernelCFn<T> fn =
           pc->cl_g == 2 ? pick_c<2, T, Acc>(store, ndot) : pick_c<1, T, Acc>(store, ndot);
@@ -1006,15 +1032,22 @@ int launch_pair_typed(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1,
   const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
   hipEvent_t stop = nullptr;
   LNV_TRY(timer_begin(s, &stop));
-  KernelC1Fn<T> fn = pick_c1<1, T, Acc>(store, ndot);
-  fn<<<dim3(wgs, 2), 256, 0, s>>>(
-      pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col, pa->cl_pos,
-      static_cast<const T*>(A1->val), B1->pat->lut, static_cast<const T*>(B1->val), pc->cl_ptr,
-      pc->cl_col, pc->cl_pos, static_cast<T*>(C1->val), 1.0, 0.0, static_cast<const T*>(m11),
-      static_cast<const T*>(m12), part1, skip, static_cast<const T*>(A2->val), B2->pat->lut,
-      static_cast<const T*>(B2->val), static_cast<T*>(C2->val), static_cast<const T*>(m21),
-      static_cast<const T*>(m22), part2);
-  LNV_LAUNCH_CHECK();
+  const int n = pa->n;
+  const int nslab = kslabs_for(B1);
+  for (int c = 0; c < nslab; ++c) {
+    const bool last = c == nslab - 1;
+    const int k_lo = (int)((int64_t)c * n / nslab), k_hi = (int)((int64_t)(c + 1) * n / nslab);
+    KernelC1Fn<T> fn = pick_c1<1, T, Acc>(last ? store : 1, last ? ndot : 0);
+    fn<<<dim3(wgs, 2), 256, 0, s>>>(
+        n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col, pa->cl_pos,
+        static_cast<const T*>(A1->val), B1->pat->lut, static_cast<const T*>(B1->val),
+        pc->cl_ptr, pc->cl_col, pc->cl_pos, static_cast<T*>(C1->val), 1.0, c == 0 ? 0.0 : 1.0,
+        static_cast<const T*>(m11), static_cast<const T*>(m12), part1, skip,
+        static_cast<const T*>(A2->val), B2->pat->lut, static_cast<const T*>(B2->val),
+        static_cast<T*>(C2->val), static_cast<const T*>(m21), static_cast<const T*>(m22), part2,
+        k_lo, k_hi);
+    LNV_LAUNCH_CHECK();
+  }
   if (stop) LNV_HIP(hipEventRecord(stop, s));
   return LNV_OK;
 }
@@ -1034,7 +1067,8 @@ int multiply_pair_launch(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1
       use_clustered(A1, B1, 0, C1) && use_clustered(A2, B2, 0, C2) && C1->pat->cl_g == 1 &&
       B1->pat->nnzb > 0 && B2->pat->nnzb > 0 && B1->pat->lut && B2->pat->lut &&
       B1->pat->n == C1->pat->n && B2->pat->n == C1->pat->n &&
-      ndot == (m22 ? 2 : (m21 ? 1 : 0)) && (ndot == 0 || (part1 && part2)) && (store || ndot > 0);
+      ndot == (m22 ? 2 : (m21 ? 1 : 0)) && (ndot == 0 || (part1 && part2)) && (store || ndot > 0) &&
+      (store || kslabs_for(B1) == 1 || C1->val != C2->val);
   if (!pairable) {  // two launches
     LNV_TRY(multiply_launch(1.0, A1, B1, 0, 0.0, C1, store, m11, m12, part1, skip, s));
     return multiply_launch(1.0, A2, B2, 0, 0.0, C2, store, m21, m22, part2, skip, s);

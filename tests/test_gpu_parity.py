@@ -396,3 +396,39 @@ def test_symmetric_products_half(gpu):
     torch.cuda.synchronize()
     assert abs(float(a.EN[0]) - float(b.EN[0])) / w.n <= 1e-6
     assert abs(float(a.EN[1]) - float(b.EN[1])) / w.n <= 1e-6
+
+
+def test_contraction_slabs_agree(gpu):
+    """Every multiply split into 3 contraction slabs (k ranges accumulated into
+    C; paired launches slab by slab; trace-only products through C's buffer)
+    against single launches: evaluation and 3 Hotelling-metric CG iterations
+    from the same start agree to FP64 rounding."""
+    from paper_2002_07704_amd import lib as L
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.diamond_workload("si216", (3, 3, 3), seed=7)
+    s = LNVSystem(w, metric="hotelling", n_hotelling=16)
+    s.cg_init()
+    L0 = s.L.val.clone()
+    out = {}
+    try:
+        for nslab in (0, 3):
+            L.call("lnv_set_kslabs", nslab)
+            s.L.val.copy_(L0)
+            s.cg_restart()
+            s.eval()
+            torch.cuda.synchronize()
+            hist = [(s.EN.clone(), s.G.val.clone())]
+            for _ in range(3):
+                s.cg_step()
+                hist.append(s.scalars_host())
+            out[nslab] = hist
+    finally:
+        L.call("lnv_set_kslabs", 0)
+    (EN1, G1), (EN3, G3) = out[0][0], out[3][0]
+    assert torch.allclose(EN3, EN1, rtol=1e-13, atol=0.0)
+    assert (G3 - G1).abs().max() <= 1e-12 * G1.abs().max()
+    for a, b in zip(out[0][1:], out[3][1:]):
+        assert abs(a["E"] - b["E"]) / w.n <= 1e-11
+        assert abs(a["N"] - b["N"]) <= 1e-9
+        assert abs(a["ALPHA"] - b["ALPHA"]) <= 1e-7 * abs(a["ALPHA"])
+        assert int(b["STATUS"]) & 3 == 0
