@@ -85,9 +85,12 @@ enum { LNV_F64 = 0, LNV_F32 = 1 };
  *
  * Atom tiles: atoms with 13 support functions are stored as 4 consecutive
  * 4x4-blocked rows (see lnv_synth_blocks), so an atom pair is a dense 16x16
- * tile.  With 16-row cluster plans (cl_m = 16: 4 such atoms) on A and C and
- * tile4 set on A and B, the multiply forms whole 16x16x16 atom products on
- * the matrix cores (lnv_pattern_cluster, lnv_pattern_tile4).
+ * tile.  With 16-row cluster plans (cl_m = 16: 4 such atoms) on A and C,
+ * tile4 = 1 on A and B and tile4 >= 1 on C, the multiply forms whole
+ * 16x16x16 atom products on the matrix cores (lnv_pattern_cluster,
+ * lnv_pattern_tile4); with 16-row plans on other patterns (4-function
+ * atoms) it multiplies 16x16 tiles of 4 x 4 atom blocks (16 atoms per
+ * wavefront).
  */
 typedef struct lnv_pattern {
   int32_t n;               /* atoms (block rows = block columns) */
@@ -101,7 +104,7 @@ typedef struct lnv_pattern {
   int32_t cl_m;            /* rows per cluster (0: no cluster plan) */
   int32_t cl_g;            /* lanes sharing one output column (1 or 2) */
   int32_t n_cl_items;      /* entries of cl_items */
-  int32_t tile4;           /* 1: P is a tile4 pattern (lnv_pattern_tile4), else 0 */
+  int32_t tile4;           /* grade from lnv_pattern_tile4 (1 tile4, 2 tile-complete, 0) */
   const int32_t* cl_ptr;   /* device [ceil(n/cl_m)+1] */
   const int32_t* cl_col;   /* device [cl_ptr[last]] */
   const int32_t* cl_pos;   /* device [cl_ptr[last]*cl_m] */
@@ -206,14 +209,18 @@ int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_
                         int64_t items_cap, int64_t* len_out, int32_t* n_items_out,
                         hipStream_t s);
 
-/* lnv_pattern_tile4 -- *ok_out (host) = 1 when P is a tile4 pattern: n is a
- * multiple of 4, rows 4a..4a+3 hold the same columns, and every row's
- * columns come in aligned runs 4b, 4b+1, 4b+2, 4b+3 -- the layout of atoms
- * stored as 4 rows each with patterns built from atom distances.  Then the
- * 16 blocks of an atom tile are found from the position p of its first one
- * as p + s*len + t (sub-row s, sub-column t, len the row length).  Patterns
- * with mixed atom sizes or halves of symmetric patterns give 0.  Set-up call:
- * allocates a flag, synchronises s. */
+/* lnv_pattern_tile4 -- grade of P for the atom-tile multiply, in *ok_out
+ * (host): 1 when P is a tile4 pattern: n is a multiple of 4, rows 4a..4a+3
+ * hold the same columns, and every row's columns come in aligned runs 4b,
+ * 4b+1, 4b+2, 4b+3 -- the layout of atoms stored as 4 rows each with
+ * patterns built from atom distances; then the 16 blocks of an atom tile are
+ * found from the position p of its first one as p + s*len + t (sub-row s,
+ * sub-column t, len the row length), as operands need.  2 when P is only
+ * tile-complete (as outputs need): a column c in any row r brings the whole
+ * run (c & ~3) .. (c & ~3) + 3 into row r & ~3 -- the halves of symmetric
+ * tile4 patterns (lnv_pattern_half).  0 otherwise (4-function atoms, mixed
+ * atom sizes).  The value belongs in lnv_pattern.tile4.  Set-up call:
+ * allocates flags, synchronises s. */
 int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStream_t s);
 
 /* lnv_pattern_items -- work list of P: with items == NULL only counts.

@@ -795,6 +795,183 @@ KernelT16Fn<T> pick_t16(int store, int ndot) {
   return k_tile16<NB, MODE, 0, 2, T>;
 }
 
+// Atom quads: 4-function atoms (4x4 blocks) multiplied 16 atom rows at a
+// time on the matrix cores.  A 16x16 MFMA tile holds 4 x 4 atom blocks: row
+// tile ar = cluster atoms 4ar..4ar+3 (16-row cluster plans: 16 atoms), column
+// group q = 4 consecutive entries of the output union; one contraction step
+// is one atom k (one union entry of A's plan), i.e. one 16x16x4 instruction
+// per (ar, q).  A wavefront keeps 4 x NB tiles in the accumulation registers
+// (the VALU kernel's 4-row clusters hold 64 accumulators per lane in
+// ordinary registers already), so every gathered B block feeds 16 rows
+// instead of 4.  Blocks missing from A or B enter as zeros; (ar, q) tiles
+// with no block of A, of B or of the output at a step are skipped by
+// wave-uniform branches.  Positions: lanes 0-15 of the step's index vector
+// hold the 16 cluster atoms' A positions, lanes 16.. the B positions of the
+// piece's column atoms (lut lookups), lane 15 + 4 NB + 1 the k of a later
+// step; each lane then picks its block's position by a lane permute.
+// Operand layout of v_mfma_*_16x16x4: lane l = i + 16c supplies A[i][c] and
+// B[c][i]; here row i = 4u + r is function r of tile atom u (A block
+// (4ar + u, k), element (r, c)), and column i = 4t + c' of group q is function
+// c' of column atom t (B block (k, col), element (c, c')).
+template <int NB, int MODE, int STORE, int NDOT, typename T>
+__global__ __launch_bounds__(256) void k_quad16(
+    int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
+    const int* __restrict__ ka_col, const int* __restrict__ ka_pos, const int* __restrict__ a_rp,
+    const T* __restrict__ a_val, int a_nnzb, const int* __restrict__ b_rp,
+    const int* __restrict__ b_lut, const T* __restrict__ b_val, int b_nnzb,
+    const int* __restrict__ jc_ptr, const int* __restrict__ jc_col,
+    const int* __restrict__ jc_pos, T* __restrict__ c_val, double alpha, double beta,
+    const T* __restrict__ m1, const T* __restrict__ m2, double* __restrict__ partials,
+    const double* __restrict__ skip) {
+  using AccT = typename TileAcc<MODE>::type;
+  using E = typename std::conditional<MODE == TM_F64, double, float>::type;
+  constexpr int KL = 16 + 4 * NB;  // index-vector lane holding the k of a later step
+  if (skip != nullptr && *skip != 0.0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+  if (item >= n_items) return;
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+  const int c = items[2 * item];
+  const int p0 = items[2 * item + 1];
+  const int ncol = min(4 * NB, jc_ptr[c + 1] - p0);
+  // output tiles present: lane l checks row atom (l & 15) against the 4
+  // entries of group l >> 4 (bit 16q + 4ar + u of the ballot)
+  int here = 0;
+  if (lq < NB) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = 4 * lq + t;
+      here |= (e < ncol && jc_pos[(size_t)(p0 + e) * 16 + li] >= 0) ? 1 : 0;
+    }
+  }
+  const uint64_t cb = __ballot(here);
+  uint32_t cmask = 0;  // bit 4q + ar
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int ar = 0; ar < 4; ++ar)
+      if ((cb >> (16 * q + 4 * ar)) & 0xFull) cmask |= 1u << (4 * q + ar);
+  // the lut lanes' column atoms (entries 0 .. 4NB-1 of the piece)
+  const int my_e = lane - 16;
+  const bool b_lane = lane >= 16 && lane < 16 + 4 * NB;
+  const int my_col = (b_lane && my_e < ncol) ? jc_col[p0 + my_e] : 0;
+  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
+  const int amax = a_nnzb - 1, bmax = b_nnzb - 1;
+
+  AccT acc[4][NB];
+#pragma unroll
+  for (int ar = 0; ar < 4; ++ar)
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[ar][q][v] = 0;
+
+  const int nsteps = t1 - t0;
+  if (nsteps > 0) {
+    const int tl = t1 - 1;
+    // index vector of the step at union entry t (its k = kk)
+    auto iv_src = [&](int t, int kk) -> const int* {
+      const int tc = min(max(t, t0), tl);
+      if (lane < 16) return ka_pos + (size_t)tc * 16 + lane;
+      if (b_lane) return b_lut + (size_t)kk * n + my_col;
+      if (lane == KL) return ka_col + min(max(t + 1, t0), tl);
+      return ka_col + tl;
+    };
+    int ivp = *iv_src(t0 - 1, ka_col[t0]);
+    int pa0 = -1, pb0 = -1;            // this lane's A and B positions, current step
+    uint32_t am0 = 0, bm0 = 0;         // present A tiles (bit ar), B groups (bit q)
+    E fa0[4] = {}, fb0[NB] = {}, fa1[4], fb1[NB];
+    const int ua = li >> 2;            // tile atom of this lane's A row / B column
+#define LNV_Q16_STEP(u, FCA, FCB, FNA, FNB)                                      \
+  {                                                                              \
+    const uint64_t ok = __ballot(ivp >= 0 && (lane < 16 || (b_lane && my_e < ncol))); \
+    uint32_t am1 = 0, bm1 = 0;                                                   \
+    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) if ((ok >> (4 * ar)) & 0xFull) am1 |= 1u << ar; \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) if ((ok >> (16 + 4 * q)) & 0xFull) bm1 |= 1u << q; \
+    const int kk2 = __builtin_amdgcn_readlane(ivp, KL);                          \
+    const int ivn = *iv_src(t0 + (u) + 2, kk2);                                  \
+    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) {                           \
+      const int pa = __shfl(ivp, 4 * ar + ua, kWave);                            \
+      const T v = a_val[(size_t)min(max(pa, 0), amax) * 16 + (li & 3) * 4 + lq]; \
+      FNA[ar] = pa >= 0 ? (E)v : (E)0;                                           \
+    }                                                                            \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) {                             \
+      const int pb = __shfl(ivp, 16 + 4 * q + ua, kWave);                        \
+      const bool okb = pb >= 0 && 4 * q + ua < ncol;                             \
+      const T v = b_val[(size_t)min(max(pb, 0), bmax) * 16 + lq * 4 + (li & 3)]; \
+      FNB[q] = okb ? (E)v : (E)0;                                                \
+    }                                                                            \
+    if ((u) >= 0 && (u) < nsteps) {                                              \
+      _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) {                         \
+        if (!((am0 >> ar) & 1u)) continue;                                       \
+        _Pragma("unroll") for (int q = 0; q < NB; ++q) {                         \
+          if (!((bm0 >> q) & 1u) || !((cmask >> (4 * q + ar)) & 1u)) continue;   \
+          if constexpr (MODE == TM_F64)                                          \
+            acc[ar][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(FCA[ar], FCB[q], acc[ar][q], 0, 0, 0); \
+          else                                                                   \
+            acc[ar][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(FCA[ar], FCB[q], acc[ar][q], 0, 0, 0); \
+        }                                                                        \
+      }                                                                          \
+    }                                                                            \
+    am0 = am1;                                                                   \
+    bm0 = bm1;                                                                   \
+    ivp = ivn;                                                                   \
+  }
+    for (int u = -2; u < nsteps; u += 2) {
+      LNV_Q16_STEP(u, fa0, fb0, fa1, fb1)
+      LNV_Q16_STEP(u + 1, fa1, fb1, fa0, fb0)
+    }
+#undef LNV_Q16_STEP
+    (void)pa0;
+    (void)pb0;
+  }
+
+  // epilogue as in k_tile16: lane (n + 16g) holds column n of each tile
+  // (column n&3 of the block of entry 4q + (n>>2)), register v the tile row
+  // 4g + v (FP32) or 4v + g (FP64): row atom (row >> 2), row (row & 3)
+  const int g = lq, nn = li;
+  double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+  for (int ar = 0; ar < 4; ++ar)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = p0 + 4 * q + (nn >> 2);
+      if (!((cmask >> (4 * q + ar)) & 1u) || e >= p0 + ncol) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = MODE == TM_F64 ? 4 * v + g : 4 * g + v;
+        const int pos = jc_pos[(size_t)e * 16 + 4 * ar + (row >> 2)];
+        if (pos < 0) continue;
+        const size_t at = (size_t)pos * 16 + (row & 3) * 4 + (nn & 3);
+        const double val = alpha * (double)acc[ar][q][v];
+        const T out = (T)(beta != 0.0 ? val + beta * (double)c_val[at] : val);
+        if (STORE) c_val[at] = out;
+        if (NDOT >= 1) d1 = fma((double)m1[at], (double)out, d1);
+        if (NDOT >= 2) d2 = fma((double)m2[at], (double)out, d2);
+      }
+    }
+  if (NDOT >= 1) {
+    d1 = wave_sum(d1);
+    if (NDOT >= 2) d2 = wave_sum(d2);
+    if (lane == 0) {
+      partials[2 * item] = d1;
+      partials[2 * item + 1] = d2;
+    }
+  }
+}
+
+template <int NB, int MODE, typename T>
+KernelT16Fn<T> pick_q16(int store, int ndot) {
+  if (store) {
+    if (ndot == 0) return k_quad16<NB, MODE, 1, 0, T>;
+    if (ndot == 1) return k_quad16<NB, MODE, 1, 1, T>;
+    return k_quad16<NB, MODE, 1, 2, T>;
+  }
+  if (ndot == 1) return k_quad16<NB, MODE, 0, 1, T>;
+  return k_quad16<NB, MODE, 0, 2, T>;
+}
+
 template <typename T>
 using KernelCFn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
                            const int*, const T*, const int*, const int*, const int*, T*, double,
@@ -894,19 +1071,34 @@ bool use_clustered(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm
 }
 
 // Atom-tile (MFMA) multiply: 16-row cluster plans on A and C, tile4 patterns
-// on A and B (see k_tile16), B's lut, row count a multiple of 4.
+// on A and B and a tile-complete C (lnv_pattern_tile4 grade 1 or 2; see
+// k_tile16), B's lut, row count a multiple of 4.
 bool use_tiles(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
   const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
   return !transB && kslabs_for(B) == 1 && pa->cl_m == 16 && pc->cl_m == 16 &&
-         (pc->cl_g == 4 || pc->cl_g == 8) && pa->tile4 == 1 && pb->tile4 == 1 && pb->lut &&
+         (pc->cl_g == 4 || pc->cl_g == 8) && pa->tile4 == 1 && pb->tile4 == 1 &&
+         (pc->tile4 == 1 || pc->tile4 == 2) && pb->lut &&
          pa->n % 4 == 0 && pa->cl_ptr && pa->cl_col && pa->cl_pos && pc->cl_ptr &&
          pc->cl_col && pc->cl_pos && pc->cl_items && pa->row_ptr && pb->row_ptr &&
          pa->nnzb > 0 && pb->nnzb > 0 && pa->nnzb < INT32_MAX && pb->nnzb < INT32_MAX;
 }
 
+// Atom-quad (MFMA) multiply of 4-function atoms: 16-row cluster plans on A
+// and C on patterns that are not tile4, B's lut (see k_quad16).
+bool use_quads(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
+  return !transB && kslabs_for(B) == 1 && pa->cl_m == 16 && pc->cl_m == 16 &&
+         (pc->cl_g == 4 || pc->cl_g == 8) && !use_tiles(A, B, transB, C) && pb->lut &&
+         pa->cl_ptr && pa->cl_col && pa->cl_pos && pc->cl_ptr && pc->cl_col && pc->cl_pos &&
+         pc->cl_items && pa->nnzb > 0 && pb->nnzb > 0 && pa->nnzb < INT32_MAX &&
+         pb->nnzb < INT32_MAX;
+}
+
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
-  return use_clustered(A, B, transB, C) || use_tiles(A, B, transB, C) ? C->pat->n_cl_items
-                                                                      : C->pat->n_items;
+  return use_clustered(A, B, transB, C) || use_tiles(A, B, transB, C) ||
+                 use_quads(A, B, transB, C)
+             ? C->pat->n_cl_items
+             : C->pat->n_items;
 }
 
 namespace {
@@ -922,14 +1114,20 @@ int tile_mode() {
 template <typename T>
 int launch_tiles(double alpha, const lnv_bsm* A, const lnv_bsm* B, double beta,
                  const lnv_bsm* C, int store, const T* m1, const T* m2, double* partials,
-                 const double* skip, int ndot, hipStream_t s) {
+                 const double* skip, int ndot, hipStream_t s, bool quads = false) {
   const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
   if (pc->n_cl_items == 0) return LNV_OK;
   const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
   const bool nb4 = pc->cl_g == 4;  // 4 column atoms per wave (cl_g 8: 2)
   KernelT16Fn<T> fn = nullptr;
   const int mode = tile_mode<T>();
-  if (mode == TM_F64) {
+  if (quads) {
+    // 4-function atoms: FP64 or FP32 matrix instructions (no FP16 split)
+    if (mode == TM_F64)
+      fn = nb4 ? pick_q16<4, TM_F64, T>(store, ndot) : pick_q16<2, TM_F64, T>(store, ndot);
+    else if constexpr (std::is_same<T, float>::value)
+      fn = nb4 ? pick_q16<4, TM_F32, T>(store, ndot) : pick_q16<2, TM_F32, T>(store, ndot);
+  } else if (mode == TM_F64) {
     fn = nb4 ? pick_t16<4, TM_F64, T>(store, ndot) : pick_t16<2, TM_F64, T>(store, ndot);
   } else {
     if constexpr (std::is_same<T, float>::value) {
@@ -966,6 +1164,8 @@ int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
   const int nslab = kslabs_for(B);
   if (use_tiles(A, B, transB, C))
     return launch_tiles<T>(alpha, A, B, beta, C, store, m1, m2, partials, skip, ndot, s);
+  if (use_quads(A, B, transB, C))
+    return launch_tiles<T>(alpha, A, B, beta, C, store, m1, m2, partials, skip, ndot, s, true);
   if (use_clustered(A, B, transB, C)) {
     if (pc->n_cl_items == 0) return LNV_OK;
     const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);

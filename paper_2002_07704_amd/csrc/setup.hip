@@ -330,6 +330,30 @@ __global__ __launch_bounds__(256) void k_tile4(int n, const int* __restrict__ rp
   }
 }
 
+// Output-grade tile check, one workgroup per row r: every column c of row r
+// has the whole run (c & ~3) .. (c & ~3) + 3 in row r & ~3 (the first row
+// of r's group).  Any violation sets *bad.
+__global__ __launch_bounds__(256) void k_tile4_out(int n, const int* __restrict__ rp,
+                                                   const int* __restrict__ col,
+                                                   int* __restrict__ bad) {
+  const int r = blockIdx.x;
+  const int r0 = r & ~3;
+  const int q0 = rp[r0], q1 = rp[r0 + 1];
+  for (int p = rp[r] + threadIdx.x; p < rp[r + 1]; p += 256) {
+    const int c0 = col[p] & ~3;
+    bool ok = c0 + 3 < n;
+    for (int t = 0; t < 4 && ok; ++t) {
+      int lo = q0, hi = q1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < c0 + t) lo = mid + 1; else hi = mid;
+      }
+      ok = lo < q1 && col[lo] == c0 + t;
+    }
+    if (!ok) atomicOr(bad, 1);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_items(int n, const int* __restrict__ rp,
                                                int* __restrict__ counts,
                                                const int* __restrict__ off,
@@ -718,15 +742,19 @@ extern "C" int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStrea
     *ok_out = 0;
     return LNV_OK;
   }
-  int32_t* bad = nullptr;
-  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int32_t), s));
-  int32_t hbad = 1;
-  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+  int32_t* bad = nullptr;  // [0]: operand grade fails, [1]: output grade fails
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), 2 * sizeof(int32_t), s));
+  int32_t hbad[2] = {1, 1};
+  hipError_t e = hipMemsetAsync(bad, 0, 2 * sizeof(int32_t), s);
   if (e == hipSuccess) {
     k_tile4<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, bad);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) {
+    k_tile4_out<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, bad + 1);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(hbad, bad, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   const hipError_t ef = hipFreeAsync(bad, s);
   if (e == hipSuccess) e = ef;
@@ -734,7 +762,7 @@ extern "C" int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStrea
     set_hip_error(e);
     return LNV_EHIP;
   }
-  *ok_out = hbad == 0 ? 1 : 0;
+  *ok_out = hbad[0] == 0 ? 1 : (hbad[1] == 0 ? 2 : 0);
   return LNV_OK;
 }
 

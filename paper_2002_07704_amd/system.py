@@ -41,7 +41,7 @@ class Pattern:
         self.items = None
         self.triples = None
         self.cl = None          # (m, g, cl_ptr, cl_col, cl_pos, cl_items)
-        self.tile4 = 0          # lnv_pattern_tile4 result (atoms stored as 4 rows)
+        self.tile4 = 0          # lnv_pattern_tile4 grade (1 tile4, 2 tile-complete, 0)
         self.struct = L_.LnvPattern()
         self._sync()
 
@@ -70,7 +70,8 @@ class Pattern:
 
     def check_tile4(self):
         """lnv_pattern_tile4: may the atom-tile multiply read this pattern by
-        tiles (4 rows per atom, columns in aligned runs of 4)?"""
+        tiles (1: 4 rows per atom, columns in aligned runs of 4) or write it
+        (1, or 2: tile-complete, e.g. the half of a tile4 pattern)?"""
         ok = c_int32(0)
         L_.call("lnv_pattern_tile4", byref(self.struct), byref(ok), _stream())
         self.tile4 = int(ok.value)
@@ -509,7 +510,7 @@ class LNVSystem:
         """Atom-tile shapes ((16, 4): 4 x 4 atom tiles per wave, (16, 8):
         4 x 2) when every atom is stored as 4 rows (13 support functions),
         else ()."""
-        if self.cells is None and self.n_rows == 4 * self.n and self.pL.check_tile4():
+        if self.cells is None and self.n_rows == 4 * self.n and self.pL.check_tile4() == 1:
             return ((16, 4), (16, 8))
         return ()
 
