@@ -402,10 +402,21 @@ enum {
   LNV_SC_T3 = 27, LNV_SC_T4 = 28, LNV_SC_T5 = 29, LNV_SC_GG_PREV = 30,
   LNV_SC_GGP = 31, LNV_SC_FCFC = 32, LNV_SC_SIGMA = 33, LNV_SC_GGN = 34,
   LNV_SC_NCORR = 35,  /* electron-number corrections computed (never reset by the library) */
-  LNV_NSCALARS = 40
+  LNV_SC_E_PREV = 36,   /* runaway guard: E of the previous iteration (NaN after a start) */
+  LNV_SC_RISES = 37,    /* consecutive rises of E */
+  LNV_SC_GUARD_K = 38,  /* iteration of the last guard trip */
+  LNV_SC_OCC_MIN = 39,  /* occupation bounds of L S from the last check */
+  LNV_SC_OCC_MAX = 40,
+  LNV_NSCALARS = 48
 };
-/* LNV_SC_STATUS bits set by the device (sticky until cleared by the caller). */
-enum { LNV_ST_NONFINITE = 1, LNV_ST_NO_ALPHA = 2, LNV_ST_NO_DELTA = 4, LNV_ST_DELTA_CAPPED = 8 };
+/* LNV_SC_STATUS bits set by the device (sticky until cleared by the caller).
+ * LNV_ST_GUARD: the runaway guard restarted the direction at least once;
+ * LNV_ST_RUNAWAY: it tripped twice within one reset period -- the
+ * minimisation is running away and should be stopped (lnv_cg_check). */
+enum {
+  LNV_ST_NONFINITE = 1, LNV_ST_NO_ALPHA = 2, LNV_ST_NO_DELTA = 4, LNV_ST_DELTA_CAPPED = 8,
+  LNV_ST_GUARD = 16, LNV_ST_RUNAWAY = 32
+};
 
 /*
  * lnv_eval -- E, N (written to EN[0], EN[1], device, and to
@@ -552,6 +563,25 @@ int lnv_forces(const double* pos, const double* box, const int32_t* nfun,
                const int32_t* seg_ptr, const int32_t* seg_atom, double* acc, double* F,
                hipStream_t s);
 
+/* lnv_occupation_bounds -- bounds of the occupation numbers, the
+ * eigenvalues of L S (K = 3LSL - 2LSLSL of Sec. II.C.2 is idempotent when
+ * they are 0 or 1; the McWeeny form runs away outside [0, 1]): the extreme
+ * eigenvalues of the tridiagonal matrix of `steps` (1..64) Lanczos steps on
+ * L S in the inner product x^T S y, from a fixed pseudo-random start.  They
+ * lie inside the spectrum and approach its ends as steps grow.  out: device
+ * [2] (smallest, largest; NaN for a zero start in the S norm); work: device
+ * [lnv_lanczos_len(n)].  FP64, blk 4.  Hot path: allocates nothing, no host
+ * synchronisation. */
+int64_t lnv_lanczos_len(int32_t n_rows);
+int lnv_occupation_bounds(const lnv_bsm* L, const lnv_bsm* S, int32_t steps, double* work,
+                          double* out, hipStream_t s);
+
+/* lnv_cg_check -- synchronise s and report the sticky status of a
+ * minimisation (scalars: device [LNV_NSCALARS]): LNV_ENUMERIC when
+ * LNV_ST_NONFINITE or LNV_ST_RUNAWAY is set, else LNV_OK; *status_out
+ * (host, may be NULL) receives the bits. */
+int lnv_cg_check(const double* scalars, int32_t* status_out, hipStream_t s);
+
 /* ------------------------------------------------------------ a5-a7: CG
  * Buffers of the conjugate-gradient minimisation (all on L's pattern unless
  * stated).  gc/gc_prev (metric runs) or g/gc_prev (identity metric) and
@@ -574,6 +604,7 @@ typedef struct lnv_cg_ws {
   double* gc_prev;
   double* D;
   double* D_prev;
+  double* lanczos; /* device [lnv_lanczos_len(n)] or NULL (no occupation checks) */
 } lnv_cg_ws;
 
 typedef struct lnv_opts {
@@ -587,6 +618,14 @@ typedef struct lnv_opts {
    * FP32 product for the line search; every other product of the step stays
    * FP64. */
   const struct lnv_eval32_ws* eval32;
+  /* Runaway guard (always on): two consecutive rises of E by more than
+   * 1e-11 |E|, or occupation bounds of L S outside [-0.5, 1.5], restart the
+   * direction (beta = 0, LNV_ST_GUARD); a second trip within reset_period
+   * iterations sets LNV_ST_RUNAWAY.  Occupation bounds (lnv_occupation_bounds,
+   * occ_iter Lanczos steps, 1..64) are taken every occ_every-th iteration
+   * (0: never) when the workspace has lanczos, into LNV_SC_OCC_MIN/MAX. */
+  int32_t occ_every;
+  int32_t occ_iter;
 } lnv_opts;
 
 /*

@@ -18,8 +18,12 @@ line search or the initial L beyond naming their sources; the readings taken
 here are: gradient projection against dN/dL, Polak-Ribiere (clamped at zero)
 directions with the 40-step reset, exact minimisation of the cubic
 Omega(alpha) = (E - mu N)(L + alpha D), a cubic electron-number correction
-along dN/dL after each step, and L0 = lambda * T on L's range with lambda the
-smallest positive root of N(lambda T) = N_e.
+along dN/dL after each step, L0 = lambda * T on L's range with lambda the
+smallest positive root of N(lambda T) = N_e, and a runaway guard: two
+consecutive rises of E, or occupation numbers (eigenvalues of L S) outside
+[-0.5, 1.5], restart the direction, and a second trip within one reset
+period marks the minimisation as running away (the McWeeny form 3x^2 - 2x^3
+is bounded only for occupations x near [0, 1]).
 """
 from __future__ import annotations
 
@@ -161,8 +165,39 @@ def initial_L(S, maskL, n_elec, T=None):
 
 
 # ------------------------------------------------------------------ CG
+def occupations(L, S):
+    """Occupation numbers: the eigenvalues of L S, ascending.  L S is similar
+    to C^T L C with S = C C^T (Cholesky), which is symmetric."""
+    C = np.linalg.cholesky(S)
+    return np.linalg.eigvalsh(C.T @ L @ C)
+
+
+RISE_TOL = 1e-11          # a rise of E beyond this fraction of |E| counts
+OCC_RANGE = (-0.5, 1.5)   # occupations outside trip the guard
+
+
+def guard_step(state, k, E, occ, reset_period):
+    """Runaway guard of the CG (reading of the paper's silence on divergence):
+    two consecutive rises of E, or occupation bounds occ = (min, max) outside
+    OCC_RANGE, restart the direction; a second trip within reset_period
+    iterations of the last one marks the run as running away.  state: dict
+    with E_prev, rises, guard_k (updated in place).  Returns (reset, runaway)."""
+    Ep = state["E_prev"]
+    rises = state["rises"] + 1 if (Ep is not None and E > Ep + RISE_TOL * max(1.0, abs(Ep))) else 0
+    occ_bad = occ is not None and not (occ[0] >= OCC_RANGE[0] and occ[1] <= OCC_RANGE[1])
+    reset = runaway = False
+    if rises >= 2 or occ_bad:
+        runaway = k - state["guard_k"] <= reset_period
+        reset = True
+        state["guard_k"] = k
+        rises = 0
+    state["rises"] = rises
+    state["E_prev"] = E
+    return reset, runaway
+
+
 def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
-       n_tol=1e-11, step_cap=0.1, stop_g=None, stop_de=None, n_atoms=None):
+       n_tol=1e-11, step_cap=0.1, stop_g=None, stop_de=None, n_atoms=None, occ_every=0):
     """Conjugate-gradient LNV minimisation; returns (L, history).
 
     Iteration k at the current L:
@@ -177,6 +212,9 @@ def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
       7. L <- L + alpha D
       8. if |N(L) - N_e| > n_tol N_e: delta = smallest-|delta| real root of
          N(L + delta F_c) = N_e, applied when |delta| ||F_c|| <= step_cap ||L||
+    Between 3 and 4 the runaway guard (guard_step) may force beta = 0, with
+    the exact occupations of L S every occ_every-th iteration (0: never).
+    History entries carry guard (the direction was restarted) and runaway.
     """
     if L0 is None:
         L, _ = initial_L(S, maskL, n_elec, T)
@@ -186,8 +224,13 @@ def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
     D_prev = g_prev = gc_prev = None
     force_reset = False
     e_hist = []
+    gstate = dict(E_prev=None, rises=0, guard_k=-10 ** 9)
     for k in range(n_iter):
         E, N, G, F = evaluate(L, S, H, maskL)
+        occ = None
+        if occ_every and k % occ_every == 0:
+            ev = occupations(L, S)
+            occ = (float(ev[0]), float(ev[-1]))
         if T is None:
             Gc, Fc = G, F
         else:
@@ -197,7 +240,8 @@ def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
         mu = dot(G, Fc) / FF
         g = G - mu * F
         gc = Gc - mu * Fc
-        if k % reset_period == 0 or force_reset or g_prev is None:
+        guard, runaway = guard_step(gstate, k, E, occ, reset_period)
+        if k % reset_period == 0 or force_reset or guard or g_prev is None:
             beta = 0.0
         else:
             beta = max(0.0, dot(g, gc - gc_prev) / dot(g_prev, gc_prev))
@@ -220,7 +264,8 @@ def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
         g_prev, gc_prev, D_prev = g, gc, D
         gnorm = float(np.sqrt(dot(g, g)))
         hist.append(dict(k=k, E=E, N=N, mu=mu, beta=beta, alpha=alpha, delta=delta,
-                         c=c.tolist(), nc=nc.tolist(), gnorm=gnorm, N_after_step=N1))
+                         c=c.tolist(), nc=nc.tolist(), gnorm=gnorm, N_after_step=N1,
+                         guard=guard, runaway=runaway, occ=occ))
         if stop_g is not None and gnorm <= stop_g:
             break
         if stop_de is not None and n_atoms:

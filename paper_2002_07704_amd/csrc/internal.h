@@ -127,6 +127,12 @@ int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
 // Number of dot partials (work items) multiply_launch writes for C.
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C);
 
+// Extreme eigenvalues of L S (occupation numbers) from `steps` Lanczos steps
+// in the S inner product: out[0] <= out[1] (device), work: device
+// [lnv_lanczos_len(n)].  No allocation, no host synchronisation.
+int occupation_bounds(const lnv_bsm* L, const lnv_bsm* S, int steps, double* work, double* out,
+                      hipStream_t s);
+
 inline int32_t partial_items(const lnv_pattern* p) {
   return p->n_items > p->n_cl_items ? p->n_items : p->n_cl_items;
 }

@@ -46,7 +46,15 @@ struct StageArgs {
   double n_elec, n_tol, step_cap;
   int reset;          // host: k % reset_period == 0
   double* en_out;     // ST_EVAL: optional device [2]
+  int k;              // ST_BETA: iteration index
+  int reset_period;   // ST_BETA: guard repeat window
+  int occ_checked;    // ST_BETA: occupation bounds computed this iteration
 };
+
+// Runaway guard (ST_BETA): a rise of E beyond this fraction of |E| counts
+// as a rise; occupations outside [kOccLo, kOccHi] trip the guard.
+constexpr double kRiseTol = 1e-11;
+constexpr double kOccLo = -0.5, kOccHi = 1.5;
 
 // Newton's method on a3 x^3 + a2 x^2 + a1 x + a0 from x until the step is
 // below 4 ulp of x (at most 100 steps); returns false when it does not settle
@@ -195,6 +203,25 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
     case ST_BETA: {
       // gg = <g, g_c>, ggp = <g, g_c_prev>, gprev = <g_prev, g_c_prev>
       const double gg = sc[LNV_SC_GG], ggp = sc[LNV_SC_GGP], gprev = sc[LNV_SC_GG_PREV];
+      // runaway guard: two consecutive rises of E, or occupations of L S
+      // outside [-0.5, 1.5], restart the direction (beta = 0); a second trip
+      // within one reset period marks the run as running away
+      {
+        const double E = sc[LNV_SC_E], Ep = sc[LNV_SC_E_PREV];
+        double rises = E > Ep + kRiseTol * fmax(1.0, fabs(Ep)) ? sc[LNV_SC_RISES] + 1.0 : 0.0;
+        const bool occ_bad = sa.occ_checked &&
+                             !(sc[LNV_SC_OCC_MIN] >= kOccLo && sc[LNV_SC_OCC_MAX] <= kOccHi);
+        if (rises >= 2.0 || occ_bad) {
+          if ((double)sa.k - sc[LNV_SC_GUARD_K] <= (double)sa.reset_period)
+            status |= LNV_ST_RUNAWAY;
+          status |= LNV_ST_GUARD;
+          sc[LNV_SC_FORCE_RESET] = 1.0;
+          sc[LNV_SC_GUARD_K] = (double)sa.k;
+          rises = 0.0;
+        }
+        sc[LNV_SC_RISES] = rises;
+        sc[LNV_SC_E_PREV] = E;
+      }
       double beta = 0.0;
       if (!sa.reset && sc[LNV_SC_FORCE_RESET] == 0.0 && gprev != 0.0)
         beta = fmax(0.0, (gg - ggp) / gprev);
@@ -280,6 +307,10 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
         }
       if (!found) status |= LNV_ST_NO_DELTA;
       sc[LNV_SC_LAMBDA] = lam;
+      // a new minimisation: no previous energy, no guard trip yet
+      sc[LNV_SC_E_PREV] = NAN;
+      sc[LNV_SC_RISES] = 0.0;
+      sc[LNV_SC_GUARD_K] = -1e9;
       break;
     }
     default:
@@ -992,6 +1023,16 @@ extern "C" int lnv_sync_check(hipStream_t s) {
   return LNV_OK;
 }
 
+extern "C" int lnv_cg_check(const double* scalars, int32_t* status_out, hipStream_t s) {
+  if (!scalars) return LNV_EINVAL;
+  double st = 0.0;
+  LNV_HIP(hipMemcpyAsync(&st, scalars + LNV_SC_STATUS, sizeof(double), hipMemcpyDeviceToHost, s));
+  LNV_HIP(hipStreamSynchronize(s));
+  const int bits = (int)st;
+  if (status_out) *status_out = bits;
+  return (bits & (LNV_ST_NONFINITE | LNV_ST_RUNAWAY)) ? LNV_ENUMERIC : LNV_OK;
+}
+
 extern "C" int64_t lnv_partials_len(int32_t n_items_L) {
   return (int64_t)LNV_NSLOTS * slot_len(n_items_L);
 }
@@ -1354,6 +1395,8 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   sa.n_tol = opts->n_tol;
   sa.step_cap = opts->step_cap;
   sa.reset = (k % opts->reset_period) == 0;
+  sa.k = (int)k;
+  sa.reset_period = opts->reset_period;
 
   // 1. E, N, G, F (FP64, or FP32 products); metric gradients G_c, F_c; mu
   if (opts->eval32) {
@@ -1373,6 +1416,12 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     LNV_TRY(convert_launch(&w32->SL, &SL64, s));
   } else {
     LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s));
+  }
+  // occupation bounds of L S for the runaway guard (every occ_every-th step)
+  if (opts->occ_every > 0 && ws->lanczos && k % opts->occ_every == 0) {
+    const int steps = opts->occ_iter > 0 ? (opts->occ_iter < 64 ? opts->occ_iter : 64) : 16;
+    LNV_TRY(occupation_bounds(L, S, steps, ws->lanczos, sc + LNV_SC_OCC_MIN, s));
+    sa.occ_checked = 1;
   }
   const double* Gc = ws->G;
   const double* Fc = ws->F;

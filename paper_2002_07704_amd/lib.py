@@ -22,9 +22,11 @@ NSLOTS = 12
 # device scalar block indices (LNV_SC_*)
 SC = dict(E=0, N=1, MU=2, BETA=3, ALPHA=4, DELTA=5, FF=6, GG=7, C1=8, C2=9, C3=10,
           N0=11, N1=12, N2=13, N3=14, FORCE_RESET=15, SKIP_NCORR=16, GNORM=17,
-          N_AFTER=18, LAMBDA=19, STATUS=20, LL=21, GF=22, DF=23, FCFC=32, SIGMA=33, GGN=34, NCORR=35)
-NSCALARS = 40
+          N_AFTER=18, LAMBDA=19, STATUS=20, LL=21, GF=22, DF=23, FCFC=32, SIGMA=33, GGN=34, NCORR=35,
+          E_PREV=36, RISES=37, GUARD_K=38, OCC_MIN=39, OCC_MAX=40)
+NSCALARS = 48
 ST_NONFINITE, ST_NO_ALPHA, ST_NO_DELTA, ST_DELTA_CAPPED = 1, 2, 4, 8
+ST_GUARD, ST_RUNAWAY = 16, 32
 
 
 class LnvPattern(ctypes.Structure):
@@ -53,7 +55,7 @@ class LnvCgWs(ctypes.Structure):
     _fields_ = [("ev", LnvEvalWs), ("LL", LnvBsm), ("SL2", c_void_p), ("Hp", c_void_p),
                 ("G", c_void_p), ("F", c_void_p), ("Gc", c_void_p), ("Fc", c_void_p),
                 ("g", c_void_p), ("gc", c_void_p), ("gc_prev", c_void_p), ("D", c_void_p),
-                ("D_prev", c_void_p)]
+                ("D_prev", c_void_p), ("lanczos", c_void_p)]
 
 
 class LnvEval32Ws(ctypes.Structure):
@@ -71,7 +73,7 @@ class LnvAdjWs(ctypes.Structure):
 
 class LnvOpts(ctypes.Structure):
     _fields_ = [("reset_period", c_int32), ("n_tol", c_double), ("step_cap", c_double),
-                ("eval32", c_void_p)]
+                ("eval32", c_void_p), ("occ_every", c_int32), ("occ_iter", c_int32)]
 
 
 PPat = POINTER(LnvPattern)
@@ -82,6 +84,9 @@ SIGNATURES = {
     "lnv_strerror": (c_char_p, [c_int]),
     "lnv_last_hip_error": (c_int, []),
     "lnv_sync_check": (c_int, [c_void_p]),
+    "lnv_cg_check": (c_int, [c_void_p, POINTER(c_int32), c_void_p]),
+    "lnv_lanczos_len": (c_int64, [c_int32]),
+    "lnv_occupation_bounds": (c_int, [PBsm, PBsm, c_int32, c_void_p, c_void_p, c_void_p]),
     "lnv_neighbours": (c_int, [c_void_p, c_int32, POINTER(c_double), c_double, c_void_p,
                                c_void_p, c_int64, POINTER(c_int64), c_void_p]),
     "lnv_pattern_product": (c_int, [PPat, PPat, PPat, c_void_p, c_void_p, c_int64,

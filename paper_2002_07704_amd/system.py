@@ -287,6 +287,8 @@ class Opts:
     n_tol: float = 1e-11
     step_cap: float = 0.1
     mixed: bool = False      # the step's evaluation with FP32 block products
+    occ_every: int = 10      # occupation bounds of L S every occ_every-th iteration (0: never)
+    occ_iter: int = 16       # Lanczos steps of each bound
 
 
 class LNVSystem:
@@ -416,6 +418,9 @@ class LNVSystem:
         self._bufs = {t.data_ptr(): t for t in (self.g, self.gc_prev, self.D, self.D_prev)}
         self.ws.g, self.ws.gc_prev = self.g.data_ptr(), self.gc_prev.data_ptr()
         self.ws.D, self.ws.D_prev = self.D.data_ptr(), self.D_prev.data_ptr()
+        self.lanczos = torch.zeros(int(L_.load().lnv_lanczos_len(self.pL.n)), dtype=torch.float64,
+                                   device=dev)
+        self.ws.lanczos = self.lanczos.data_ptr()
         if metric is not None:
             self.ws.LL = self.LL.struct
             self.ws.Gc = self.Gc.val.data_ptr()
@@ -909,12 +914,33 @@ class LNVSystem:
         status bits cleared."""
         self.scalars[L_.SC["STATUS"]] = 0.0
         self.scalars[L_.SC["FORCE_RESET"]] = 0.0
+        self.scalars[L_.SC["E_PREV"]] = float("nan")
+        self.scalars[L_.SC["RISES"]] = 0.0
+        self.scalars[L_.SC["GUARD_K"]] = -1e9
         self.k = 0
+
+    def cg_check(self):
+        """Synchronise and raise LnvError (LNV_ENUMERIC) when the minimisation
+        produced a non-finite value or its runaway guard tripped twice within a
+        reset period; returns the status bits otherwise."""
+        bits = c_int32(0)
+        L_.call("lnv_cg_check", _ptr(self.scalars), byref(bits), _stream())
+        return bits.value
+
+    def occupation_bounds(self, steps=32, L=None):
+        """(smallest, largest) occupation number of L S from `steps` Lanczos
+        steps (lnv_occupation_bounds); L: the current L by default."""
+        out = torch.zeros(2, dtype=torch.float64, device=self.dev)
+        M = self.L if L is None else Matrix(self.pL, L)
+        L_.call("lnv_occupation_bounds", byref(M.struct), byref(self.S.struct), int(steps),
+                _ptr(self.lanczos), _ptr(out), _stream())
+        return tuple(float(x) for x in out.cpu())
 
     def cg_step(self):
         if self.cells is not None:
             raise NotImplementedError("a batch of cells is evaluated, not minimised, as one system")
-        o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap, None)
+        o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap, None,
+                       int(self.opts.occ_every), int(self.opts.occ_iter))
         if self.opts.mixed:
             self.mixed_setup()
             o.eval32 = ctypes.addressof(self.ws32)

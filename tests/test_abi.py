@@ -71,6 +71,15 @@ def test_host_side_argument_errors(lib):
     assert lib.lnv_forces(None, box, None, None, None, 1, 1.0, None, None, 0.0, 12.0, 3.0, None,
                           14.0, 2.5, 1, None, None, None, None, None) == L.EINVAL
     assert lib.lnv_partials_len(10) >= 12 * 8 * 1024
+    # occupation bounds: missing work/out, steps outside [1, 64], block edge
+    work = ctypes.c_void_p(8)
+    assert lib.lnv_occupation_bounds(ctypes.byref(m), ctypes.byref(m), 16, None, work, None) == L.EINVAL
+    assert lib.lnv_occupation_bounds(ctypes.byref(m), ctypes.byref(m), 0, work, work, None) == L.EINVAL
+    assert lib.lnv_occupation_bounds(ctypes.byref(m), ctypes.byref(m), 65, work, work, None) == L.EINVAL
+    assert lib.lnv_occupation_bounds(ctypes.byref(m5), ctypes.byref(m), 16, work, work, None) == L.EUNSUPPORTED
+    assert lib.lnv_occupation_bounds(ctypes.byref(m), ctypes.byref(mq), 16, work, work, None) == L.EPATTERN
+    assert lib.lnv_lanczos_len(0) == 0 and lib.lnv_lanczos_len(10) >= 5 * 40 + 128
+    assert lib.lnv_cg_check(None, None, None) == L.EINVAL
 
 
 def test_struct_layouts_match_header(tmp_path):

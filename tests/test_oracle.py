@@ -463,3 +463,52 @@ def test_xlbomd_conserves_energy_si64():
     for o in out:
         assert abs(o["N"] - w.n_elec) <= 1e-9 * w.n_elec
         assert abs(o["E"] + o["ekin"] - e0) <= 0.01 * dk
+
+
+# ------------------------------------------------------------------ runaway guard
+def test_occupations_closed_forms():
+    """Occupations (eigenvalues of L S): L = c S^-1 gives L S = c I; the exact
+    Gamma-point density matrix K of the 8-atom cell satisfies K S K = K, so
+    its occupations are exactly 0 (empty states) and 1 (N_e / 2 of them)."""
+    w = W.get("si8_4x4")
+    ref = st.System(w)
+    Si = np.linalg.inv(ref.S)
+    occ = lnv.occupations(0.37 * Si, ref.S)
+    assert np.abs(occ - 0.37).max() <= 1e-12
+    K, _, _, _ = lnv.exact_density(ref.H, ref.S, w.n_elec)
+    occ = lnv.occupations(K, ref.S)
+    nocc = w.n_elec // 2
+    assert np.abs(occ[-nocc:] - 1.0).max() <= 1e-10
+    assert np.abs(occ[:-nocc]).max() <= 1e-10
+
+
+def test_guard_rule():
+    """Two consecutive rises of E restart the direction; a trip within one
+    reset period of the last is a runaway; occupations outside [-0.5, 1.5]
+    trip at once; a descent clears the count of rises."""
+    st = dict(E_prev=None, rises=0, guard_k=-10 ** 9)
+    seq = [(-1.0, None), (-2.0, None), (-1.5, None), (-1.2, None), (-1.3, None),
+           (-1.1, None), (-1.0, None), (-2.0, (-0.6, 1.0)), (-3.0, (0.0, 1.0))]
+    got = [lnv.guard_step(st, k, E, occ, 40) for k, (E, occ) in enumerate(seq)]
+    assert got == [(False, False), (False, False), (False, False), (True, False),
+                   (False, False), (False, False), (True, True), (True, True), (False, False)]
+    st = dict(E_prev=None, rises=0, guard_k=-10 ** 9)
+    lnv.guard_step(st, 0, 0.0, (0.0, 1.6), 40)
+    assert lnv.guard_step(st, 41, -1.0, (0.0, 1.6), 40) == (True, False)   # 41 > 40 apart
+
+
+def test_guard_trips_on_the_runaway_identity_metric_cell():
+    """The 8-atom cell minimised with the identity metric drifts to
+    occupations below -0.5 (the non-physical state the plain LNV functional
+    admits): the guard restarts the direction at iteration 9 and flags the
+    runaway at 10.  With the Hotelling metric it never trips."""
+    w = W.get("si8_4x4")
+    ref = st.System(w)
+    _, hist = lnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, 12, occ_every=1)
+    trips = [h["k"] for h in hist if h["guard"]]
+    runaway = [h["k"] for h in hist if h["runaway"]]
+    assert trips[:2] == [9, 10] and runaway[0] == 10
+    assert hist[9]["occ"][0] < -0.5 and hist[8]["occ"][0] > -0.5
+    T = lnv.hotelling(ref.S, ref.maskL, 16)
+    _, hist = lnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, 30, T=T, occ_every=1)
+    assert not any(h["guard"] for h in hist)
