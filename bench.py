@@ -33,6 +33,27 @@ METRIC = "LNV energy+grad evals/s & block-sparse GFLOP/s, FP64 vs mixed at 1e-6 
 PEAK_FP64 = 78.6e12     # MI355X FP64 vector (= FP64 matrix) peak, FLOP/s
 
 
+def atom_order(rp, col, blocks, atom_of):
+    """A block pattern and its 4x4 blocks with rows in the atoms' own order
+    (one row per atom, row r holding atom atom_of[r])."""
+    import numpy as np
+    n = len(rp) - 1
+    lens = np.diff(rp)
+    inv = np.empty(n, dtype=np.int64)
+    inv[atom_of] = np.arange(n)
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    rp2[1:] = np.cumsum(lens[inv])
+    col2 = np.empty_like(col)
+    out = np.empty_like(blocks)
+    for a in range(n):
+        r = inv[a]
+        c = atom_of[col[rp[r]:rp[r + 1]]]
+        o = np.argsort(c, kind="stable")
+        col2[rp2[a]:rp2[a + 1]] = c[o]
+        out[rp2[a]:rp2[a + 1]] = blocks[rp[r]:rp[r + 1]][o]
+    return rp2.astype(rp.dtype), col2, out
+
+
 def cpu_baseline(w, Lb_host, patL, rows=48, budget_s=20.0):
     """The row-wise oracle, as it stands, on a sample of atom rows of the same
     workload; scaled to whole evaluations per second."""
@@ -72,7 +93,7 @@ def kernel_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def summarize_pmc(fetch_dir, write_dir, out_path, workload):
+def summarize_pmc(fetch_dir, write_dir, out_path, workload, row_order):
     """Per-launch HBM bytes of the multiply kernel from two rocprofv3 --pmc
     runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled by what the
     same counter reads for the device copy of COPY_BYTES bytes made by
@@ -107,6 +128,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, workload):
         res = json.load(open(out_path))
     res[workload] = {
         "kernel": "k_mul44c1 (clustered multiply launches)", "kernel_src_sha256_16": kernel_hash(),
+        "row_order": row_order,
         "fetch_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"],
         "write_bytes_per_launch": out["WRITE_SIZE"]["bytes_per_launch"],
         "bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"],
@@ -147,7 +169,9 @@ def extra_configs(reps):
     for name, w, what in cells:
         t0 = time.perf_counter()
         batch = isinstance(w, list)
-        s = LNVSystem(w, metric=None if batch else "hotelling")
+        # diamond cells: rows in groups of four bonded atoms; other cells by spatial cell
+        order = "bonds" if not batch and getattr(w, "groups", None) is not None else None
+        s = LNVSystem(w, metric=None if batch else "hotelling", reorder=order)
         s.cg_init()
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
@@ -221,7 +245,7 @@ def extra_configs(reps):
                   "N_after_4_steps": float(s.EN[1]), "n_elec": s.n_elec}
         res[name] = {"what": what, "atoms": s.n,
                      "orbitals": int(sum(int(c.nfun.sum()) for c in (w if batch else [w]))),
-                     "rows": s.n_rows, "setup_s": setup,
+                     "rows": s.n_rows, "setup_s": setup, "row_order": order or "cell",
                      "cluster_shape": str(shape),
                      "autotune_eval_ms": {str(k): v for k, v in tried.items()},
                      "eval_ms": ms64, "evals_per_s": 1e3 / ms64,
@@ -265,6 +289,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="si4096_4x4")
+    ap.add_argument("--row-order", default="bonds", choices=("bonds", "cell", "atoms"),
+                    help="order of the atoms along the matrix rows (bonds: groups of four "
+                         "bonded atoms, so each 4-row cluster of the multiply is compact)")
     ap.add_argument("--eval-reps", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra-configs", action="store_true",
@@ -286,7 +313,7 @@ def main():
         profile_tiles(args.profile_tiles)
         return
     if args.summarize_pmc:
-        summarize_pmc(*args.summarize_pmc, args.traffic_json, args.workload)
+        summarize_pmc(*args.summarize_pmc, args.traffic_json, args.workload, args.row_order)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -303,7 +330,7 @@ def main():
     w = W.get(args.workload)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sysg = LNVSystem(w)
+    sysg = LNVSystem(w, reorder=False if args.row_order == "atoms" else args.row_order)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     print(f"[bench] setup {setup_s:.2f} s; triples {sysg.triples}", file=sys.stderr, flush=True)
@@ -460,8 +487,10 @@ def main():
         try:
             with open(args.traffic_json) as f:
                 tj = json.load(f).get(args.workload)
-            # counters describe the kernel they were taken on: stale -> null
-            if tj and tj.get("kernel_src_sha256_16") == kernel_hash():
+            # counters describe the kernel and the row layout they were taken
+            # on: stale -> null
+            if (tj and tj.get("kernel_src_sha256_16") == kernel_hash()
+                    and tj.get("row_order", "atoms") == args.row_order):
                 traffic = tj["bytes_per_launch"]
         except (OSError, ValueError, KeyError):
             traffic = None
@@ -486,6 +515,7 @@ def main():
                     "projection + exact cubic line search + electron-number correction; "
                     f"{args.steps} consecutive iterations from the purified start",
             "metric": "Hotelling T ~ S^-1 on L's range (16 steps, once per geometry)",
+            "row_order": args.row_order,
             "start": f"canonical purification, {len(pm_hist)} steps, {pm_s:.2f} s (not timed)",
             "n_corrections": n_corr,
             "E_per_atom_start": e_start / w.n,
@@ -517,8 +547,11 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
+        rp, col = sysg.pL.host()
         Lb = sysg.L.val.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(w, Lb, sysg.pL.host())
+        if sysg.atom_of is not None:
+            rp, col, Lb = atom_order(rp, col, Lb, sysg.atom_of.cpu().numpy())
+        out["cpu_baseline"] = cpu_baseline(w, Lb, (rp, col))
     if not args.no_extra_configs:
         del sysg
         torch.cuda.empty_cache()
