@@ -83,14 +83,19 @@ def cpu_baseline(w, Lb_host, patL, rows=48, budget_s=20.0):
                       f"{per_row:.3f} s/row), scaled by {w.n}/{done}"}
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2002_07704_amd", "csrc", "multiply.hip")
+# the multiply kernels and the CG step that decides which products it launches
+KERNEL_SRC = [os.path.join(ROOT, "paper_2002_07704_amd", "csrc", f)
+              for f in ("multiply.hip", "lnv_core.hip")]
 COPY_BYTES = 1 << 30
 
 
 def kernel_hash():
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRC:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def summarize_pmc(fetch_dir, write_dir, out_path, workload, row_order):

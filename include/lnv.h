@@ -367,7 +367,12 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  * Z, W, V are then filled by a transposing copy (Z's and L's patterns need
  * items and must be symmetric; a block whose transpose is missing comes out
  * NaN).  lnv_cg_step uses the same buffers for the electron-number
- * check (Z, V at the new L) and Lu for the metric products P_L(T G T).
+ * check (Z, V at the new L) and Lu for the metric products P_L(T G T); in
+ * the line search and the electron-number correction Lu and Vu hold L and
+ * the direction on the half (weight 2 off the diagonal), the partners of
+ * the traces of the symmetric product S P M P S formed on that half (the
+ * CG step's cubics, Sec. II.C.2).  Without them these products are formed
+ * in full.
  */
 typedef struct lnv_eval_ws {
   lnv_bsm SL;

@@ -465,6 +465,41 @@ __global__ __launch_bounds__(256) void k_mirror(int n, const int* __restrict__ i
   for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = tr ? u[c * 4 + r] : u[r * 4 + c];
 }
 
+// Weighted halves of two matrices on L's (symmetric) pattern: for every block
+// (i, j) of the half in_half, at position q of U's pattern, dst[q] = w src[p]
+// with p its position in the full pattern and w = 1 on the diagonal, 2 off
+// it.  For symmetric X and a symmetric product Q formed only on the half,
+// sum over the half of <dst_q, Q_q> is the full <X, Q>: the blocks left out
+// are the transposes of those kept.
+__global__ __launch_bounds__(256) void k_half_weighted(int n, const int* __restrict__ items,
+                                                       const int* __restrict__ rpF,
+                                                       const int* __restrict__ colF,
+                                                       const int* __restrict__ lutU,
+                                                       const double* __restrict__ src1,
+                                                       const double* __restrict__ src2,
+                                                       double* __restrict__ dst1,
+                                                       double* __restrict__ dst2,
+                                                       const double* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0.0) return;
+  const int item = blockIdx.x;
+  const int i = items[2 * item], c0 = items[2 * item + 1];
+  const int cnt = min(kWave, rpF[i + 1] - c0);
+  const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
+  if (b >= cnt) return;
+  const int p = c0 + b;
+  const int j = colF[p];
+  if (!in_half(n, i, j)) return;
+  const int q = lutU[(size_t)i * n + j];
+  if (q < 0) return;  // U's pattern misses a block of the half: checked on the host
+  const double w = j == i ? 1.0 : 2.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const size_t e = (size_t)r * 4 + c;
+    dst1[(size_t)q * 16 + e] = w * src1[(size_t)p * 16 + e];
+    dst2[(size_t)q * 16 + e] = w * src2[(size_t)p * 16 + e];
+  }
+}
+
 // out = a X + b Y + c Z elementwise (Y, Z nullable), grid-stride.
 __global__ __launch_bounds__(256) void k_lincomb(int64_t nv, double a, const double* __restrict__ X,
                                                  double b, const double* __restrict__ Y, double c,
@@ -1193,50 +1228,114 @@ int check_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm
   return LNV_OK;
 }
 
-// Traces of the cubic along direction P at the current L, with M the matrix
-// the trace is taken against (H' for the energy line, S for the electron
-// number):  A_P^T = S P (into apt), A_P = its transpose (into ap),
-// X_P = M A_P, then
-//   slot 0: <P, X_P>,  slot 1 (pairs): <L, P_L(X_P A_P)>, <P, P_L(X_P A_P)>,
-//   slot 2: <P, P_L(X_P A)>  with A^T = SLcur (skipped when SLcur is null).
-// P_L(X_P A_P) is formed as P_L(A_P^T X_P^T), the transpose, whose traces
-// with the symmetric L and P are the same; X_P^T is X_P itself when M = S
-// (XPT null), otherwise the transpose copy into XPT.
-int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, const double* P,
-                 const lnv_eval_ws& ev, double* apt, double* ap, const lnv_bsm* SLcur,
-                 lnv_bsm XP, const lnv_bsm* XPT, double* partials, int64_t slot,
-                 const double* skip, int* nparts, hipStream_t s) {
+// Partial sums of the traces T0..T3 written by cubic_traces: trace t is the
+// sum of n[t] partials at off[t], off[t] + stride[t], ...
+struct TraceParts {
+  int64_t off[4];
+  int n[4];
+  int stride[4];
+};
+
+// Traces of the cubic along direction P at the current L, with M the
+// (symmetric) matrix the trace is taken against: H' = H - mu S for the
+// energy line, S for the electron number (m_is_s).  With A_P^T = S P (into
+// apt), A_P = its transpose (into ap) and X_P = M A_P:
+//   T0 = <P, X_P>           = Tr[P M P S]
+//   T1 = Tr[L S P S P M],   T2 = Tr[P S P S P M],   T3 = Tr[P S L S P M]
+// (the energy's cubic has c2 = 2(3 T0 - 2(2 T1 + T3)), c3 = -4 T2; T1 = T3
+// when M = S).  Q = A_P^T X_P = S P M P S is symmetric, and by cyclic shifts
+// and transposition of the traces of products of symmetric matrices
+//   T3 = <L, Q>,  T2 = <P, Q>,  T1 = <P, S L X_P>  (S L = SLcur).
+// With the workspace's half of L's pattern (ev.Lu, ev.Vu) Q is formed only
+// on the half, traced against weighted halves of L and P (k_half_weighted),
+// and S L X_P on L's pattern reads X_P as stored; without it, the products
+// P_L(X_P A_P) (as P_L(A_P^T X_P^T), X_P^T transposed into XPT unless
+// M = S) and P_L(X_P A) are formed in full.
+int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, bool m_is_s,
+                 const double* P, const lnv_eval_ws& ev, double* apt, double* ap,
+                 const lnv_bsm* SLcur, lnv_bsm XP, const lnv_bsm* XPT, double* partials,
+                 int64_t slot, const double* skip, TraceParts* tp, hipStream_t s) {
   const lnv_pattern* pl = L->pat;
   lnv_bsm Pm{pl, 4, LNV_F64, const_cast<double*>(P)};
   lnv_bsm APT{ev.SL.pat, 4, LNV_F64, apt};
   lnv_bsm AP{ev.LS.pat, 4, LNV_F64, ap};
   LNV_TRY(multiply_launch(1.0, S, &Pm, 0, 0.0, &APT, 1, nullptr, nullptr, nullptr, skip, s));
   LNV_TRY(transpose_skip_launch(&APT, ev.perm_SL, ap, skip, s));
-  if (!XPT && XP.pat == ev.Z.pat && sym_ready(&ev.Zu, &XP)) {
+  if (m_is_s && XP.pat == ev.Z.pat && sym_ready(&ev.Zu, &XP)) {
     // M = S: X_P = S P S is symmetric, formed from its half
     LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &ev.Zu, 1, nullptr, nullptr, nullptr, skip, s));
     LNV_TRY(mirror_launch(&ev.Zu, &XP, s, skip));
   } else {
     LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &XP, 1, nullptr, nullptr, nullptr, skip, s));
   }
-  const lnv_bsm* B = &XP;
-  if (XPT) {
-    LNV_TRY(transpose_skip_launch(&XP, ev.perm_X, static_cast<double*>(XPT->val), skip, s));
-    B = XPT;
-  }
   const int ni = pl->n_items;
   // one workgroup per item: partial q belongs to item q
   k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, XP.pat->lut,
                                  static_cast<const double*>(XP.val), partials + 0 * slot, skip);
   LNV_LAUNCH_CHECK();
+  tp->off[0] = 0;
+  tp->n[0] = ni;
+  tp->stride[0] = 1;
   // C of the trace-only products: written between contraction slabs, so it
   // needs a buffer of its own (ev.YT is dead outside the evaluation)
   lnv_bsm scratchC{pl, 4, LNV_F64, ev.YT};
-  *nparts = multiply_nparts(&APT, B, 0, &scratchC);
-  if (SLcur && multiply_nparts(SLcur, B, 0, &scratchC) != *nparts) return LNV_EPATTERN;
-  if (!SLcur)
+  const lnv_pattern* pu = ev.Lu.pat;
+  const bool half = pu && ev.Lu.val && ev.Vu && pu->n == pl->n && pu->lut && pu->row_ptr &&
+                    pu->col && pl->items && ev.Lu.dtype == LNV_F64 &&
+                    2 * pu->nnzb == pl->nnzb + pl->n && (m_is_s || SLcur);
+  if (half) {
+    lnv_bsm Qh{pu, 4, LNV_F64, ev.YT};
+    const int nq = multiply_nparts(&APT, &XP, 0, &Qh);
+    const int nr = m_is_s ? 0 : multiply_nparts(SLcur, &XP, 0, &scratchC);
+    if (2 * (int64_t)nq <= slot && 2 * (int64_t)nr <= slot) {
+      double* Lh = static_cast<double*>(ev.Lu.val);
+      double* Ph = static_cast<double*>(ev.Vu);
+      k_half_weighted<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, pu->lut,
+                                         static_cast<const double*>(L->val), P, Lh, Ph, skip);
+      LNV_LAUNCH_CHECK();
+      // <L, Q> -> T3 (even partials), <P, Q> -> T2 (odd)
+      LNV_TRY(multiply_launch(1.0, &APT, &XP, 0, 0.0, &Qh, 0, Lh, Ph, partials + 1 * slot, skip,
+                              s));
+      tp->off[3] = 1 * slot;
+      tp->off[2] = 1 * slot + 1;
+      tp->n[2] = tp->n[3] = nq;
+      tp->stride[2] = tp->stride[3] = 2;
+      if (m_is_s) {
+        tp->off[1] = tp->off[3];
+        tp->n[1] = nq;
+        tp->stride[1] = 2;
+        return LNV_OK;
+      }
+      // T1 = <P, S L X_P>
+      LNV_TRY(multiply_launch(1.0, SLcur, &XP, 0, 0.0, &scratchC, 0, P, nullptr,
+                              partials + 2 * slot, skip, s));
+      tp->off[1] = 2 * slot;
+      tp->n[1] = nr;
+      tp->stride[1] = 2;
+      return LNV_OK;
+    }
+  }
+  const lnv_bsm* B = &XP;
+  if (XPT && !m_is_s) {
+    LNV_TRY(transpose_skip_launch(&XP, ev.perm_X, static_cast<double*>(XPT->val), skip, s));
+    B = XPT;
+  } else if (!m_is_s) {
+    return LNV_EINVAL;   // X_P^T needs a buffer
+  }
+  const int np = multiply_nparts(&APT, B, 0, &scratchC);
+  tp->off[1] = 1 * slot;
+  tp->off[2] = 1 * slot + 1;
+  tp->off[3] = 2 * slot;
+  for (int t = 1; t < 4; ++t) {
+    tp->n[t] = np;
+    tp->stride[t] = 2;
+  }
+  if (SLcur && multiply_nparts(SLcur, B, 0, &scratchC) != np) return LNV_EPATTERN;
+  if (!SLcur) {
+    tp->off[3] = tp->off[1];   // T3 = T1 when M = S
     return multiply_launch(1.0, &APT, B, 0, 0.0, &scratchC, 0,
                            static_cast<const double*>(L->val), P, partials + 1 * slot, skip, s);
+  }
   // both trace products in one launch (the second's second trace, <P, .>
   // again, lands in the unused odd partials of its slot)
   return multiply_pair_launch(&APT, B, &scratchC, SLcur, B, &scratchC, 0,
@@ -1360,12 +1459,12 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   // N(lambda T) = 6 Tr[TSTS] lambda^2 - 4 Tr[TSTSTS] lambda^3 at L = 0:
   // A_D^T = S T, Z_D = S A_D = S T S,  <T, Z_D> and <T, P_L(Z_D A_D)>.
   lnv_bsm ZD{ev.Z.pat, 4, LNV_F64, ev.Z.val};
-  int np = 0;
-  LNV_TRY(cubic_traces(L, S, S, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val), nullptr, ZD,
-                       nullptr, part, slot, nullptr, &np, s));
+  TraceParts tp{};
+  LNV_TRY(cubic_traces(L, S, S, true, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val), nullptr,
+                       ZD, nullptr, part, slot, nullptr, &tp, s));
   RedList rl = reds();
-  add(rl, 0, ni, 1, LNV_SC_T0);
-  add(rl, 1 * slot + 1, np, 2, LNV_SC_T2);
+  add(rl, tp.off[0], tp.n[0], tp.stride[0], LNV_SC_T0);
+  add(rl, tp.off[2], tp.n[2], tp.stride[2], LNV_SC_T2);
   StageArgs sa{};
   sa.n_elec = n_elec;
   LNV_TRY(scalar_stage(part, rl, sc, ST_INIT, sa, s));
@@ -1473,15 +1572,12 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   lnv_bsm Hp{ph, 4, LNV_F64, ws->Hp};
   lnv_bsm XD{ev.X.pat, 4, LNV_F64, ev.X.val};
   lnv_bsm XDT{ev.XT.pat, 4, LNV_F64, ev.XT.val};
-  int np = 0;
-  LNV_TRY(cubic_traces(L, S, &Hp, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val), &ev.SL,
-                       XD, &XDT, part, slot, nullptr, &np, s));
+  TraceParts tp{};
+  LNV_TRY(cubic_traces(L, S, &Hp, false, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val),
+                       &ev.SL, XD, &XDT, part, slot, nullptr, &tp, s));
   {
     RedList rl = reds();
-    add(rl, 0, ni, 1, LNV_SC_T0);
-    add(rl, 1 * slot + 0, np, 2, LNV_SC_T1);
-    add(rl, 1 * slot + 1, np, 2, LNV_SC_T2);
-    add(rl, 2 * slot + 0, np, 2, LNV_SC_T3);
+    for (int t = 0; t < 4; ++t) add(rl, tp.off[t], tp.n[t], tp.stride[t], LNV_SC_T0 + t);
     LNV_TRY(scalar_stage(part, rl, sc, ST_ALPHA, sa, s));
   }
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv);
@@ -1510,15 +1606,12 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   // ev.LS), the products with A_new use S.L_new in SL2, and Z_F = S F_c S
   // reuses X's buffer.
   lnv_bsm ZF{ev.Z.pat, 4, LNV_F64, ev.X.val};
-  LNV_TRY(cubic_traces(L, S, S, Fc, ev, static_cast<double*>(ev.SL.val),
-                       static_cast<double*>(ev.LS.val), &SL2, ZF, nullptr, part, slot, skip, &np,
+  LNV_TRY(cubic_traces(L, S, S, true, Fc, ev, static_cast<double*>(ev.SL.val),
+                       static_cast<double*>(ev.LS.val), &SL2, ZF, nullptr, part, slot, skip, &tp,
                        s));
   {
     RedList rl = reds();
-    add(rl, 0, ni, 1, LNV_SC_T0);
-    add(rl, 1 * slot + 0, np, 2, LNV_SC_T1);
-    add(rl, 1 * slot + 1, np, 2, LNV_SC_T2);
-    add(rl, 2 * slot + 0, np, 2, LNV_SC_T3);
+    for (int t = 0; t < 4; ++t) add(rl, tp.off[t], tp.n[t], tp.stride[t], LNV_SC_T0 + t);
     // the reductions read stale partials when skipped; ST_DELTA ignores them
     LNV_TRY(scalar_stage(part, rl, sc, ST_DELTA, sa, s));
   }

@@ -875,6 +875,7 @@ class LNVSystem:
         if padded or not self.split:
             t = dict(self.triples)
             t["Vf"] = t["V"]               # P_L(SL.Z) in full (trace products)
+            t["Wf"] = t["W"]               # P_L(SL.X) in full (trace product)
             if self.symmetric:
                 t.update(self.triples_upper)
             return {k: 2 * BLK ** 3 * v for k, v in t.items()}
@@ -887,7 +888,7 @@ class LNVSystem:
         specs = {"SL": (self.pS, self.pL, None), "X": (self.pH, self.pLS, None),
                  "Z": (self.pS, self.pLS, self.pZu), "YT": (self.pSL, self.pXT, self.pL),
                  "W": (self.pSL, self.pX, up), "V": (self.pSL, self.pZ, up),
-                 "Vf": (self.pSL, self.pZ, self.pL)}
+                 "Vf": (self.pSL, self.pZ, self.pL), "Wf": (self.pSL, self.pX, self.pL)}
         if self.metric is not None:
             specs.update(TG=(self.pL, self.pL, None), TGT=(self.pLL, self.pL, up))
         if self.adj_ws is not None:
@@ -914,11 +915,19 @@ class LNVSystem:
         the arithmetic the kernels do (the same unless atoms are split)."""
         t = self._weights(padded)
         ev = t["SL"] + t["X"] + t["Z"] + t["YT"] + t["W"] + t["V"]
-        line = t["SL"] + t["X"] + 2 * t["YT"]
         nchk = t["SL"] + t["Z"] + t["V"]
-        ncor = t["SL"] + t["Z"] + 2 * t["Vf"]
+        if self.symmetric:
+            # traces of the cubics: the symmetric A_P^T X_P on the half of L's
+            # pattern, plus (energy line) S L X_P in full
+            line = t["SL"] + t["X"] + t["W"] + t["Wf"]
+            ncor = t["SL"] + t["Z"] + t["V"]
+            init = t["SL"] + t["Z"] + t["V"]
+        else:
+            line = t["SL"] + t["X"] + 2 * t["YT"]
+            ncor = t["SL"] + t["Z"] + 2 * t["Vf"]
+            init = t["SL"] + t["Z"] + t["Vf"]
         met = 2 * (t["TG"] + t["TGT"]) if self.metric is not None else 0
-        tot = {"eval": ev, "init": t["SL"] + t["Z"] + t["Vf"],
+        tot = {"eval": ev, "init": init,
                "step_base": ev + met + line + nchk, "ncorr": ncor,
                "step": ev + met + line + nchk + ncor}[what]
         return tot
