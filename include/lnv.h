@@ -591,9 +591,12 @@ int lnv_cg_check(const double* scalars, int32_t* status_out, hipStream_t s);
  * Buffers of the conjugate-gradient minimisation (all on L's pattern unless
  * stated).  gc/gc_prev (metric runs) or g/gc_prev (identity metric) and
  * D/D_prev are swapped by lnv_cg_step after each step.
- *  LL  values on pat(L.L) (pattern needs items): T G and T F of the metric
- *      products.  May share memory with ev.XT (dead at that point) when
- *      pat(L.L) has no more blocks than pat(S.L.H).  Unused without a metric.
+ *  LL  values on pat(L.L) (pattern needs items): G T and F T of the metric
+ *      products P_L(T (G T)), P_L(T (F T)) when the pattern has lut (T G and
+ *      T F of P_L((T G) T) otherwise: the same triples, but the restricted
+ *      product then contracts over the long rows of T G).  May share memory
+ *      with ev.XT (dead at that point) when pat(L.L) has no more blocks than
+ *      pat(S.L.H).  Unused without a metric.
  */
 typedef struct lnv_cg_ws {
   lnv_eval_ws ev;

@@ -1343,21 +1343,32 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, bool m_is
                               partials + 2 * slot, skip, s);
 }
 
-// out = P_L(T V T) through the natural-range intermediate T V (in ws->LL).
+// out = P_L(T V T) through the natural-range intermediate on pat(L.L) (in
+// ws->LL).  With an index table on pat(L.L) it is formed as P_L(T (V T)):
+// the restricted product then contracts over T's short rows (range R_L)
+// with the natural-range V T on the right, the orientation in which nearly
+// every lane of a 64-column piece finds its block; (T V) T would contract
+// over the long rows of T V against T's short rows (about a tenth of the
+// lanes busy).  The triples are the same either way.
 int metric_apply(const lnv_bsm* T, const double* V, double* out, lnv_cg_ws* ws, hipStream_t s) {
   const lnv_pattern* pl = T->pat;
   lnv_bsm Vm{pl, 4, LNV_F64, const_cast<double*>(V)};
   lnv_bsm Om{pl, 4, LNV_F64, out};
-  LNV_TRY(multiply_launch(1.0, T, &Vm, 0, 0.0, &ws->LL, 1, nullptr, nullptr, nullptr, nullptr, s));
   // P_L(T V T) is symmetric for symmetric T and V
-  LNV_TRY(sym_product(&ws->LL, T, &Om, &ws->ev.Lu, s));
-  return LNV_OK;
+  if (ws->LL.pat->lut) {
+    LNV_TRY(multiply_launch(1.0, &Vm, T, 0, 0.0, &ws->LL, 1, nullptr, nullptr, nullptr, nullptr,
+                            s));
+    return sym_product(T, &ws->LL, &Om, &ws->ev.Lu, s);
+  }
+  LNV_TRY(multiply_launch(1.0, T, &Vm, 0, 0.0, &ws->LL, 1, nullptr, nullptr, nullptr, nullptr, s));
+  return sym_product(&ws->LL, T, &Om, &ws->ev.Lu, s);
 }
 
-// out1 = P_L(T V1 T), out2 = P_L(T V2 T) as paired launches: T.V1 into LL,
-// T.V2 into X's buffer (free between the evaluation and the line search)
-// when pat(L.L) fits there, the halves into Lu's and Vu's buffers;
-// otherwise one after the other.
+// out1 = P_L(T V1 T), out2 = P_L(T V2 T) as paired launches: the natural
+// intermediates (V1 T, V2 T; or T V1, T V2) into LL and into X's buffer
+// (free between the evaluation and the line search) when pat(L.L) fits
+// there, the halves into Lu's and Vu's buffers; otherwise one after the
+// other.
 int metric_apply_pair(const lnv_bsm* T, const double* V1, double* out1, const double* V2,
                       double* out2, lnv_cg_ws* ws, hipStream_t s) {
   const lnv_eval_ws& ev = ws->ev;
@@ -1372,6 +1383,11 @@ int metric_apply_pair(const lnv_bsm* T, const double* V1, double* out1, const do
   lnv_bsm O1{pl, 4, LNV_F64, out1}, O2{pl, 4, LNV_F64, out2};
   lnv_bsm LL2{ws->LL.pat, 4, LNV_F64, ev.X.val};
   lnv_bsm U2{ev.Lu.pat, 4, LNV_F64, ev.Vu};
+  if (ws->LL.pat->lut) {
+    LNV_TRY(multiply_pair_launch(&V1m, T, &ws->LL, &V2m, T, &LL2, 1, nullptr, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, nullptr, s));
+    return sym_product_pair(T, &ws->LL, &O1, &ev.Lu, T, &LL2, &O2, &U2, s);
+  }
   LNV_TRY(multiply_pair_launch(T, &V1m, &ws->LL, T, &V2m, &LL2, 1, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr, nullptr, s));
   return sym_product_pair(&ws->LL, T, &O1, &ev.Lu, &LL2, T, &O2, &U2, s);

@@ -364,7 +364,8 @@ class LNVSystem:
         if metric is not None:
             self.pLL = product_pattern(self.pL, self.pL)          # T.G, T.F
             self.triples["TG"] = self.pLL.triples
-            self.triples["TGT"] = product_pattern(self.pLL, self.pL, mask=self.pL).triples
+            # P_L(T (G T)): T on the left of the restricted product
+            self.triples["TGT"] = product_pattern(self.pL, self.pLL, mask=self.pL).triples
         # symmetric products Z, W, V (and P_L(TGT)): balanced halves
         self.symmetric = bool(symmetric) and is_symmetric(self.pL) and is_symmetric(self.pZ)
         self.pZu = self.pLu = None
@@ -376,7 +377,7 @@ class LNVSystem:
                 W=product_pattern(self.pSL, self.pX, mask=self.pLu).triples,
                 V=product_pattern(self.pSL, self.pZ, mask=self.pLu).triples)
             if metric is not None:
-                self.triples_upper["TGT"] = product_pattern(self.pLL, self.pL,
+                self.triples_upper["TGT"] = product_pattern(self.pL, self.pLL,
                                                             mask=self.pLu).triples
         # index tables and work lists
         self.pL.build_lut(lut=True).build_items()
@@ -388,7 +389,7 @@ class LNVSystem:
         self.pXT.build_lut(lut=True)
         self.pZ.build_lut(lut=True).build_items()
         if metric is not None:
-            self.pLL.build_items()
+            self.pLL.build_lut(lut=True).build_items()
         assert self.pX.nnzb >= self.pZ.nnzb
         self.cluster = None
         if cluster is not None:
@@ -890,7 +891,7 @@ class LNVSystem:
                  "W": (self.pSL, self.pX, up), "V": (self.pSL, self.pZ, up),
                  "Vf": (self.pSL, self.pZ, self.pL), "Wf": (self.pSL, self.pX, self.pL)}
         if self.metric is not None:
-            specs.update(TG=(self.pL, self.pL, None), TGT=(self.pLL, self.pL, up))
+            specs.update(TG=(self.pL, self.pL, None), TGT=(self.pL, self.pLL, up))
         if self.adj_ws is not None:
             sym = self.symmetric
             mL, mH, mS = ((self.pLSLu, self.pHu, self.pSu) if sym else (None, self.pH, self.pS))
