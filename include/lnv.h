@@ -539,6 +539,19 @@ typedef struct lnv_adj_ws {
   lnv_bsm LSLu;
   lnv_bsm Hu;
   lnv_bsm Su;
+  /* Optional (val NULL: not used): S.L transposed (values on pat(L.S), with
+   * perm_SL from lnv_pattern_transpose_map(pat(S.L), pat(L.S))) and H.L
+   * transposed (pat(L.H), perm_HL likewise).  With them the restricted
+   * products put the shorter range on the left: P_H(LS.LSL) for P_H(LSL.SL)
+   * (the same matrix L S L S L) and P_S(LH.LSL) = Y^T for Y = P_S(LSL.HL)
+   * (dS takes Y + Y^T), so the contraction runs over LS's or LH's rows with
+   * the natural-range L.S.L on the right, whose pattern then needs lut; the
+   * left patterns need items (and the cluster plans of the other left
+   * operands). */
+  lnv_bsm LS;
+  const int32_t* perm_SL;
+  lnv_bsm LH;
+  const int32_t* perm_HL;
 } lnv_adj_ws;
 
 int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* dS,

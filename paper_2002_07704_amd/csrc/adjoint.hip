@@ -15,7 +15,12 @@
 // transposed term costs one gather on S's own (symmetric) pattern.  LSL, the
 // two-term symmetric combinations of dH and dN/dS and L.HL are formed from
 // the blocks of their symmetric halves when the workspace provides the
-// buffers.
+// buffers.  With the transposes LS = (SL)^T and LH = (HL)^T in the workspace,
+// the restricted products with the long-range L.S.L are taken with it on the
+// right: P(LS.LSL) (the same L S L S L as LSL.SL) and Y^T = P_S(LH.LSL) (dS
+// needs only Y + Y^T).  The contraction then runs over the rows of LS or LH
+// (ranges R_L + R_S, R_L + R_H) instead of those of L.S.L (2 R_L + R_S),
+// and nearly every lane of a 64-column piece finds its block.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -77,6 +82,19 @@ int check_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const ln
              !has(H->pat, false, false)))
     return LNV_EPATTERN;
   if (dH && !has(H->pat, false, true)) return LNV_EPATTERN;
+  // optional transposes: checked only when given
+  if (ws->LS.val) {
+    if (!bsm_ok(&ws->LS) || !ws->perm_SL) return LNV_EINVAL;
+    if (ws->LS.blk != 4) return LNV_EUNSUPPORTED;
+    if (ws->LS.pat->n != n || !has(ws->LS.pat, false, false) || !ws->LSL.pat->lut)
+      return LNV_EPATTERN;
+  }
+  if (ws->LH.val && dS) {
+    if (!bsm_ok(&ws->LH) || !ws->perm_HL) return LNV_EINVAL;
+    if (ws->LH.blk != 4) return LNV_EUNSUPPORTED;
+    if (ws->LH.pat->n != n || !has(ws->LH.pat, false, false) || !ws->LSL.pat->lut)
+      return LNV_EPATTERN;
+  }
   return LNV_OK;
 }
 
@@ -88,7 +106,10 @@ using namespace lnv;
 extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* dS,
                            lnv_bsm* dH, lnv_bsm* dNS, const lnv_adj_ws* ws, hipStream_t s) {
   LNV_TRY(check_adjoint(L, S, H, dS, dH, dNS, ws));
+  const bool use_ls = ws->LS.val != nullptr;
+  const bool use_lh = ws->LH.val != nullptr && dS != nullptr;
   LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &ws->SL, 1, nullptr, nullptr, nullptr, nullptr, s));
+  if (use_ls) LNV_TRY(transpose_values(&ws->SL, ws->perm_SL, ws->LS.val, s));
   // LSL = L S L is symmetric: the blocks of its half, then the mirror
   if (sym_ready(&ws->LSLu, &ws->LSL)) {
     LNV_TRY(multiply_launch(1.0, L, &ws->SL, 0, 0.0, &ws->LSLu, 1, nullptr, nullptr, nullptr,
@@ -101,8 +122,12 @@ extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
   // a L.SL + b LSL.SL on the symmetric output pattern of D (= a LSL + b LSLSL)
   auto two_terms = [&](double a, double b, lnv_bsm* D, const lnv_bsm* U) -> int {
     const lnv_bsm* out = sym_ready(U, D) ? U : D;
-    LNV_TRY(multiply_launch(b, &ws->LSL, &ws->SL, 0, 0.0, out, 1, nullptr, nullptr, nullptr,
-                            nullptr, s));
+    if (use_ls)
+      LNV_TRY(multiply_launch(b, &ws->LS, &ws->LSL, 0, 0.0, out, 1, nullptr, nullptr, nullptr,
+                              nullptr, s));
+    else
+      LNV_TRY(multiply_launch(b, &ws->LSL, &ws->SL, 0, 0.0, out, 1, nullptr, nullptr, nullptr,
+                              nullptr, s));
     LNV_TRY(multiply_launch(a, L, &ws->SL, 0, 1.0, out, 1, nullptr, nullptr, nullptr, nullptr,
                             s));
     return out == U ? mirror_launch(U, D, s) : LNV_OK;
@@ -113,8 +138,15 @@ extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
     const lnv_pattern* ps = S->pat;
     lnv_bsm Y{ps, 4, LNV_F64, ws->YS};
     LNV_TRY(multiply_launch(1.0, H, L, 0, 0.0, &ws->HL, 1, nullptr, nullptr, nullptr, nullptr, s));
-    LNV_TRY(multiply_launch(1.0, &ws->LSL, &ws->HL, 0, 0.0, &Y, 1, nullptr, nullptr, nullptr,
-                            nullptr, s));
+    if (use_lh) {
+      // Y^T = P_S(LH.LSL): k_sym_update takes Y + Y^T either way
+      LNV_TRY(transpose_values(&ws->HL, ws->perm_HL, ws->LH.val, s));
+      LNV_TRY(multiply_launch(1.0, &ws->LH, &ws->LSL, 0, 0.0, &Y, 1, nullptr, nullptr, nullptr,
+                              nullptr, s));
+    } else {
+      LNV_TRY(multiply_launch(1.0, &ws->LSL, &ws->HL, 0, 0.0, &Y, 1, nullptr, nullptr, nullptr,
+                              nullptr, s));
+    }
     // 6 L H L is symmetric; Y = LSLHL is not
     if (sym_ready(&ws->Su, dS)) {
       LNV_TRY(multiply_launch(6.0, L, &ws->HL, 0, 0.0, &ws->Su, 1, nullptr, nullptr, nullptr,

@@ -29,25 +29,34 @@ namespace {
 constexpr int kLzMax = 64;      // most Lanczos steps
 constexpr int kRedThreads = 1024;
 
-// y = A x for 4x4-blocked A on its pattern: thread (row i, r) of a workgroup
-// of 64 rows accumulates row r of block row i over the row's blocks in
-// order (fixed summation order).
+// y = A x for 4x4-blocked A on its pattern: one wavefront per block row i;
+// lane l takes the row's blocks l, l + 64, ... in order and the four row
+// sums are reduced across the wave by the fixed butterfly (the same
+// summation order every run).
 __global__ __launch_bounds__(256) void k_bsr_mv(int n, const int* __restrict__ rp,
                                                 const int* __restrict__ col,
                                                 const double* __restrict__ A,
                                                 const double* __restrict__ x,
                                                 double* __restrict__ y) {
-  const int i = blockIdx.x * 64 + (threadIdx.x >> 2);
-  const int r = threadIdx.x & 3;
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  double acc = 0.0;
-  for (int p = rp[i]; p < rp[i + 1]; ++p) {
-    const double* a = A + (size_t)p * 16 + r * 4;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int p = rp[i] + lane; p < rp[i + 1]; p += kWave) {
+    const double* a = A + (size_t)p * 16;
     const double* xv = x + (size_t)col[p] * 4;
+    const double x0 = xv[0], x1 = xv[1], x2 = xv[2], x3 = xv[3];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc = fma(a[c], xv[c], acc);
+    for (int r = 0; r < 4; ++r)
+      acc[r] = fma(a[r * 4 + 3], x3, fma(a[r * 4 + 2], x2, fma(a[r * 4 + 1], x1,
+                                                              fma(a[r * 4], x0, acc[r]))));
   }
-  y[(size_t)i * 4 + r] = acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = wave_sum(acc[r]);
+  if (lane == 0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) y[(size_t)i * 4 + r] = acc[r];
+  }
 }
 
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
@@ -198,7 +207,7 @@ int occupation_bounds(const lnv_bsm* L, const lnv_bsm* S, int steps, double* wor
   double* Su = u + m;
   double* ab = Su + m;           // [2 * kLzMax]: a_j, b_j
   double* sc = ab + 2 * kLzMax;  // [1]: |start|_S
-  const int mvg = (n + 63) / 64;
+  const int mvg = (n + 3) / 4;   // four block rows (wavefronts) per workgroup
   const int vg = (int)((m + 255) / 256 < 1024 ? (m + 255) / 256 : 1024);
   const double* Lv = static_cast<const double*>(L->val);
   const double* Sval = static_cast<const double*>(S->val);

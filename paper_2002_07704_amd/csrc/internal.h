@@ -124,6 +124,10 @@ bool sym_ready(const lnv_bsm* U, const lnv_bsm* C);
 int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
                   const double* skip = nullptr);
 
+// AT (values on the pattern of A's transpose) = A^T block by block: block p
+// of A goes, transposed, to position perm[p] (lnv_pattern_transpose_map).
+int transpose_values(const lnv_bsm* A, const int32_t* perm, void* AT, hipStream_t s);
+
 // Number of dot partials (work items) multiply_launch writes for C.
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C);
 

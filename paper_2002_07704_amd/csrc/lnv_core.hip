@@ -876,6 +876,10 @@ struct EvalOps {
 
 }  // namespace
 
+int transpose_values(const lnv_bsm* A, const int32_t* perm, void* AT, hipStream_t s) {
+  return transpose_launch(A, perm, AT, s);
+}
+
 bool sym_ready(const lnv_bsm* U, const lnv_bsm* C) {
   return U && U->val && U->pat && U->pat->n == C->pat->n && U->pat->items && U->pat->row_ptr &&
          U->pat->lut && U->dtype == C->dtype && C->pat->items;

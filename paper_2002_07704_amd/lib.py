@@ -68,7 +68,8 @@ class LnvEval32Ws(ctypes.Structure):
 
 class LnvAdjWs(ctypes.Structure):
     _fields_ = [("SL", LnvBsm), ("LSL", LnvBsm), ("HL", LnvBsm), ("YS", c_void_p),
-                ("LSLu", LnvBsm), ("Hu", LnvBsm), ("Su", LnvBsm)]
+                ("LSLu", LnvBsm), ("Hu", LnvBsm), ("Su", LnvBsm),
+                ("LS", LnvBsm), ("perm_SL", c_void_p), ("LH", LnvBsm), ("perm_HL", c_void_p)]
 
 
 class LnvOpts(ctypes.Structure):

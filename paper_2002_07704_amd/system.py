@@ -542,7 +542,7 @@ class LNVSystem:
         if self.metric is not None:
             pats.append(self.pLL)
         if getattr(self, "adj_ws", None) is not None:
-            pats += [self.pLSL, self.pHL]
+            pats += [self.pLSL, self.pHL, self.pLS, self.pLH]
             if self.symmetric:
                 pats += [self.pLSLu, self.pHu, self.pSu]
         return pats
@@ -726,15 +726,22 @@ class LNVSystem:
         dev = self.dev
         self.pLSL = product_pattern(self.pL, self.pSL)           # L.S.L
         self.pHL = product_pattern(self.pH, self.pL)             # H.L
+        self.pLH = product_pattern(self.pL, self.pH, triples=False)   # L.H = pat(H.L)^T
+        self.pLH.build_lut(lut=True)      # for the transpose map and the plan only
+        self.perm_HL = transpose_map(self.pHL, self.pLH)
+        # the restricted products with L.S.L take it on the right: P_H(LS.LSL),
+        # P_S(LH.LSL) (the transposes LS, LH are formed per call)
         self.triples.update(
             LSL=self.pLSL.triples, HL=self.pHL.triples,
-            dH4=product_pattern(self.pLSL, self.pSL, mask=self.pH).triples,
+            dH4=product_pattern(self.pLS, self.pLSL, mask=self.pH).triples,
             dH6=product_pattern(self.pL, self.pSL, mask=self.pH).triples,
-            dS4=product_pattern(self.pLSL, self.pHL, mask=self.pS).triples,
+            dS4=product_pattern(self.pLH, self.pLSL, mask=self.pS).triples,
             dS6=product_pattern(self.pL, self.pHL, mask=self.pS).triples,
         )
         self.pSL.build_lut(lut=True)
-        self.pLSL.build_items()
+        self.pLSL.build_lut(lut=True).build_items()
+        self.pLS.build_items()
+        self.pLH.build_items()
         self.pHL.build_lut(lut=True).build_items()
         self.pS.build_lut(lut=True).build_items()
         adj_upper = []
@@ -748,23 +755,22 @@ class LNVSystem:
             adj_upper = [self.pLSLu, self.pHu, self.pSu]
             self.triples_upper.update(
                 LSL=product_pattern(self.pL, self.pSL, mask=self.pLSLu).triples,
-                dH4=product_pattern(self.pLSL, self.pSL, mask=self.pHu).triples,
+                dH4=product_pattern(self.pLS, self.pLSL, mask=self.pHu).triples,
                 dH6=product_pattern(self.pL, self.pSL, mask=self.pHu).triples,
                 dS6=product_pattern(self.pL, self.pHL, mask=self.pSu).triples)
         if self.cluster is not None:
-            # left operand L.S.L and outputs H.L (and the halves) take
-            # part in clustered products; without the halves L.S.L's index
-            # table is needed only while its plan is built
-            tmp = self.pLSL.lut is None
-            self.pLSL.build_lut(lut=True).build_cluster(*self.cluster)
-            if tmp:
-                self.pLSL.lut = None
-                self.pLSL._sync()
+            # left operands L.S.L, L.S, L.H and outputs H.L (and the halves)
+            # take part in clustered products
+            self.pLSL.build_cluster(*self.cluster)
             self.pHL.build_cluster(*self.cluster)
+            self.pLS.build_cluster(*self.cluster)
+            self.pLH.build_cluster(*self.cluster)
             if self.cluster[0] == 16:
                 self.pSL.check_tile4()
             for P in adj_upper:
                 P.build_cluster(*self.cluster)
+        self.pLH.lut = None
+        self.pLH._sync()
         self.LSL = Matrix(self.pLSL)
         self.HL = Matrix(self.pHL)
         self.YS = torch.zeros(self.pS.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
@@ -773,6 +779,13 @@ class LNVSystem:
         self.adj_ws.LSL = self.LSL.struct
         self.adj_ws.HL = self.HL.struct
         self.adj_ws.YS = self.YS.data_ptr()
+        # transposes of S.L (the evaluation's L.S buffer, recomputed per call)
+        # and of H.L
+        self.LH = Matrix(self.pLH)
+        self.adj_ws.LS = self.LS.struct
+        self.adj_ws.perm_SL = self.perm_SL.data_ptr()
+        self.adj_ws.LH = self.LH.struct
+        self.adj_ws.perm_HL = self.perm_HL.data_ptr()
         if self.symmetric:
             self.LSLu, self.Hu, self.Su = (Matrix(P) for P in adj_upper)
             self.adj_ws.LSLu = self.LSLu.struct
@@ -896,8 +909,8 @@ class LNVSystem:
             sym = self.symmetric
             mL, mH, mS = ((self.pLSLu, self.pHu, self.pSu) if sym else (None, self.pH, self.pS))
             specs.update(LSL=(self.pL, self.pSL, mL), HL=(self.pH, self.pL, None),
-                         dH4=(self.pLSL, self.pSL, mH), dH6=(self.pL, self.pSL, mH),
-                         dS4=(self.pLSL, self.pHL, self.pS), dS6=(self.pL, self.pHL, mS))
+                         dH4=(self.pLS, self.pLSL, mH), dH6=(self.pL, self.pSL, mH),
+                         dS4=(self.pLH, self.pLSL, self.pS), dS6=(self.pL, self.pHL, mS))
         fun = self.fun_rows
         for k, (A, B, M) in specs.items():
             if k not in self._alg:

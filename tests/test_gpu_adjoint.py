@@ -85,6 +85,37 @@ def test_adjoint_matches_oracle(fx, request):
         assert torch.equal(dS1, dS) and torch.equal(dH1, dH)
 
 
+def test_adjoint_without_transposes_agrees(si64):
+    """The workspace's optional transposes LS, LH only change which operand
+    of the restricted products carries the long range (P_H(LS.LSL) for
+    P_H(LSL.SL), Y^T for Y): without them the adjoint takes the other
+    association, and the results agree to rounding; dN/dS too."""
+    from paper_2002_07704_amd import lib as L_
+    sysg, ref = si64
+    n = ref.S.shape[0]
+    Ld = _rand_sym(n, ref.maskL, 7) + 0.2 * np.eye(n) * ref.maskL
+    _set(sysg, sysg.L, sysg.pL, Ld)
+    out = []
+    ws = sysg.adj_ws if sysg.adj_ws is not None else (sysg.adjoint_setup(), sysg.adj_ws)[1]
+    saved = (ws.LS, ws.perm_SL, ws.LH, ws.perm_HL)
+    try:
+        for with_t in (True, False):
+            if not with_t:
+                ws.LS, ws.perm_SL, ws.LH, ws.perm_HL = L_.LnvBsm(), None, L_.LnvBsm(), None
+            dS = torch.empty_like(sysg.S.val)
+            dH = torch.empty_like(sysg.H.val)
+            dN = torch.empty_like(sysg.S.val)
+            sysg.adjoint(sysg.L.val, sysg.S.val, sysg.H.val, dS=dS, dH=dH, dNS=dN)
+            torch.cuda.synchronize()
+            out.append((dS, dH, dN))
+    finally:
+        ws.LS, ws.perm_SL, ws.LH, ws.perm_HL = saved
+    for a, b in zip(*out):
+        assert float((a - b).abs().max()) <= 1e-12 * float(b.abs().max())
+    gS = olnv.grad_S(Ld, ref.S, ref.H, ref.maskS)
+    assert np.abs(_dense(sysg, out[0][0], sysg.pS) - gS).max() <= 1e-12 * np.abs(gS).max()
+
+
 def test_lnv_energy_autograd(si64):
     from paper_2002_07704_amd.autograd import LNVEnergy
     sysg, ref = si64
