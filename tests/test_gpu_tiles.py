@@ -53,15 +53,20 @@ def _cells():
     }
 
 
-NAMES = ["si64_13", "am22_13", "one13"]
+NAMES = ["si64_13", "si64_13b", "am22_13", "one13"]
 
 
 @pytest.fixture(scope="module")
 def cells(gpu):
+    """The cells in spatial-cell row order; si64_13b: the diamond cell with
+    its rows in groups of four bonded atoms (the benchmark's layout)."""
     from paper_2002_07704_amd.system import LNVSystem
     out = {}
-    for name, w in _cells().items():
-        s = LNVSystem(w, metric="hotelling", n_hotelling=16)
+    ws = _cells()
+    ws["si64_13b"] = ws["si64_13"]
+    for name, w in ws.items():
+        order = "bonds" if name.endswith("b") else None
+        s = LNVSystem(w, metric="hotelling", n_hotelling=16, reorder=order)
         out[name] = (s, ost.System(w), Layout(s))
     yield out
     L_.call("lnv_set_f32_accumulation", ACC_F32)
@@ -124,8 +129,9 @@ def test_tile_eval_matches_oracle(cells, name, shape):
     s.set_cluster((4, 1))
 
 
-def test_tile_cg_trajectory(cells):
-    s, ref, lay = cells["si64_13"]
+@pytest.mark.parametrize("name", ["si64_13", "si64_13b"])
+def test_tile_cg_trajectory(cells, name):
+    s, ref, lay = cells[name]
     w = s.w
     steps = 6
     T = olnv.hotelling(ref.S, ref.maskL, 16)
@@ -191,12 +197,14 @@ def test_tile_mixed_modes(cells, gpu, name, acc):
     s.set_cluster((4, 1))
 
 
-def test_tile_eval_at_scale(gpu):
+@pytest.mark.parametrize("order", ["cell", "bonds"])
+def test_tile_eval_at_scale(gpu, order):
     """8192 atoms with 13 functions (32768 rows): tile evaluations against the
-    4x4 path's FP64 evaluation at the CG start."""
+    4x4 path's FP64 evaluation at the CG start, with the rows in spatial cells
+    and in groups of four bonded atoms (the benchmark's layout)."""
     from paper_2002_07704_amd.system import LNVSystem
     w = W.diamond_workload("si8192_13f", (16, 16, 4), seed=3, nfun=13, R=(12.0, 14.0, 10.0))
-    s = LNVSystem(w, metric="hotelling")
+    s = LNVSystem(w, metric="hotelling", reorder=order)
     s.cg_init()
     s.eval()
     torch.cuda.synchronize()
