@@ -155,3 +155,41 @@ def test_bonded_layout_cg_from_purified_start_at_scale(gpu):
     Eb, Ea = runs["bonds"], runs[False]
     assert all(b < a for a, b in zip(Eb, Eb[1:]))
     assert max(abs(a - b) for a, b in zip(Ea, Eb)) / w.n <= 1e-9
+
+
+def test_bonded_layout_sampled_rows_at_benchmark_point(gpu):
+    """The benchmark's configuration at full size: 4096 atoms, bonded rows,
+    Hotelling metric, L after the purified start and two CG iterations.  Rows
+    of G and F at that L, mapped back to atom order, against the row-wise
+    oracle fed the same L (rows of both ends and the middle of the cell)."""
+    import bench
+    from oracle import rows as orows
+    from paper_2002_07704_amd.pm import pm_initial_L
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.get("si4096_4x4")
+    s = LNVSystem(w, reorder="bonds")
+    pm_initial_L(s, 60)
+    s.cg_restart()
+    s.cg_step()
+    s.cg_step()
+    s.eval()
+    torch.cuda.synchronize()
+    rp, col = s.pL.host()
+    atom_of = s.atom_of.cpu().numpy()
+    rpa, cola, La = bench.atom_order(rp, col, s.L.val.cpu().numpy(), atom_of)
+    _, _, Ga = bench.atom_order(rp, col, s.G.val.cpu().numpy(), atom_of)
+    _, _, Fa = bench.atom_order(rp, col, s.F.val.cpu().numpy(), atom_of)
+    pS = ost.neighbours(w.pos, w.box, w.R_S)
+    pH = ost.neighbours(w.pos, w.box, w.R_H)
+    Sb = ost.synth_blocks(w, "S", *pS)
+    Hb = ost.synth_blocks(w, "H", *pH)
+    ro = orows.RowOracle(w, Sb, Hb, La, pS, pH, (rpa, cola))
+    gmax, fmax = np.abs(Ga).max(), np.abs(Fa).max()
+    for a in (0, 1, 777, 2048, 3000, 4095):
+        _, _, Gi, Fi, cols = ro.row(a)
+        assert np.array_equal(cols, cola[rpa[a]:rpa[a + 1]])
+        eg = np.abs(Ga[rpa[a]:rpa[a + 1]] - Gi).max()
+        ef = np.abs(Fa[rpa[a]:rpa[a + 1]] - Fi).max()
+        print(f"atom {a}: |dG| {eg:.1e} (max {gmax:.1e}) |dF| {ef:.1e} (max {fmax:.1e})", flush=True)
+        assert eg <= 1e-12 * gmax, a
+        assert ef <= 1e-12 * fmax, a
