@@ -233,21 +233,44 @@ def extra_configs(reps):
             t1 = time.perf_counter()
             pm_hist, _ = pm_initial_L(s, 60)
             pm_s = time.perf_counter() - t1
-            s.cg_restart()
-            s.cg_step()
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            n_cg = 3
-            for _ in range(n_cg):
+            L_pm = s.L.val.clone()
+
+            def cg_run():
+                # 1 untimed + 3 timed iterations from the purified start
+                s.L.val.copy_(L_pm)
+                s.cg_restart()
                 s.cg_step()
-            torch.cuda.synchronize()
-            ms_cg = (time.perf_counter() - t1) * 1e3 / n_cg
-            s.eval()
-            torch.cuda.synchronize()
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                for _ in range(3):
+                    s.cg_step()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t2) * 1e3 / 3
+                st = int(s.scalar("STATUS"))
+                s.eval()
+                torch.cuda.synchronize()
+                return ms, float(s.EN[0]), float(s.EN[1]), st
+
+            ms_cg, e_cg, n_cg4, st_cg = cg_run()
             cg = {"purification_steps": len(pm_hist), "purification_s": pm_s,
                   "cg_step_ms": ms_cg, "cg_steps_per_s": 1e3 / ms_cg,
-                  "E_per_atom_after_4_steps": float(s.EN[0]) / s.n,
-                  "N_after_4_steps": float(s.EN[1]), "n_elec": s.n_elec}
+                  "E_per_atom_after_4_steps": e_cg / s.n,
+                  "N_after_4_steps": n_cg4, "n_elec": s.n_elec, "cg_status_bits": st_cg}
+            # the same iterations with FP32 block products in the evaluation (the
+            # mixed-precision tuner's shape: FP32 MFMA atom tiles where offered);
+            # metric, line search and electron-number correction stay FP64
+            s.set_cluster(shape32)
+            s.opts.mixed = True
+            try:
+                ms_m, e_m, n_m, st_m = cg_run()
+            finally:
+                s.opts.mixed = False
+                s.set_cluster(shape)
+            cg["mixed"] = {"cluster_shape": str(shape32), "cg_step_ms": ms_m,
+                           "cg_steps_per_s": 1e3 / ms_m, "speedup_vs_fp64_step": ms_cg / ms_m,
+                           "E_per_atom_after_4_steps": e_m / s.n,
+                           "dE_per_atom_vs_fp64_cg": abs(e_m - e_cg) / s.n,
+                           "N_after_4_steps": n_m, "cg_status_bits": st_m}
         res[name] = {"what": what, "atoms": s.n,
                      "orbitals": int(sum(int(c.nfun.sum()) for c in (w if batch else [w]))),
                      "rows": s.n_rows, "setup_s": setup, "row_order": order or "cell",
