@@ -154,6 +154,38 @@ def test_tile_cg_trajectory(cells, name):
     s.set_cluster((4, 1))
 
 
+@pytest.mark.parametrize("acc", [ACC_F32, ACC_F16X3], ids=["fp32", "fp16x3"])
+def test_tile_mixed_cg_tracks_fp64(cells, acc):
+    """CG iterations whose evaluation runs on the FP32 (or FP16 hi/lo) atom
+    tiles, bonded rows, against the same iterations in FP64 from the same
+    start: every iteration's energy within 1e-6 Ha/atom of the FP64
+    trajectory, no failed line search."""
+    s, ref, lay = cells["si64_13b"]
+    w = s.w
+    steps = 6
+    s.set_cluster((16, 4))
+    hist = []
+    try:
+        for mixed in (False, True):
+            L_.call("lnv_set_f32_accumulation", acc)
+            s.opts.mixed = mixed
+            s.cg_init()
+            run = []
+            for _ in range(steps):
+                s.cg_step()
+                run.append(s.scalars_host())
+            hist.append(run)
+    finally:
+        s.opts.mixed = False
+        L_.call("lnv_set_f32_accumulation", ACC_F32)
+        s.set_cluster((4, 1))
+    for k, (a, b) in enumerate(zip(*hist)):
+        print(f"acc {acc} k={k} E/atom fp64 {a['E'] / w.n:.12f} mixed {b['E'] / w.n:.12f}",
+              flush=True)
+        assert abs(a["E"] - b["E"]) / w.n <= 1e-6, k
+        assert int(b["STATUS"]) & 3 == 0, k
+
+
 def test_tile_adjoint(cells):
     s, ref, lay = cells["si64_13"]
     s.set_cluster((16, 4))
