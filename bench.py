@@ -345,8 +345,8 @@ def main():
         summarize_pmc(*args.summarize_pmc, args.traffic_json, args.workload, args.row_order)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library drives one device per process "
+              "and has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -20,8 +20,8 @@ geometry; the history starts at rest (X(-m dt) = L(0)S(0)).
 
 Each minimisation runs at most cg_steps CG iterations and stops after the
 iteration whose projected gradient has ||g||_F <= 1e-6 sqrt(entries of L)
-(survey reading 10: iterated on rounding noise past convergence, the CG
-eventually leaves the minimum).
+(a convergence test the paper leaves undefined: iterated on rounding noise
+past convergence, the CG eventually leaves the minimum).
 
 Ions: velocity Verlet with the forces of the synthetic S(x), H(x) at the
 minimised L in the constrained form -(dE/dx - mu dN/dx) (oracle.forces), mu
