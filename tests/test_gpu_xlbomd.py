@@ -14,12 +14,16 @@ from oracle import xlbomd as ox
 pytestmark = pytest.mark.gpu
 
 
-def test_xlbomd_matches_oracle_si64(gpu):
+@pytest.mark.parametrize("order", [None, "bonds"], ids=["atoms", "bonds"])
+def test_xlbomd_matches_oracle_si64(gpu, order):
+    """Three MD steps against the oracle's, with the rows in the atoms' own
+    order and in groups of four bonded atoms (positions, velocities and forces
+    stay in atom order; the row order only relabels the matrices)."""
     from paper_2002_07704_amd.xlbomd import XLBOMD
     w = W.get("si64_4x4")
     m, v = W.masses(w), W.thermal_velocities(w, 300.0, 1)
     ref = ox.run(w, m, v, 20.0, 3, cg_steps=25)
-    md = XLBOMD(w, m, v, 20.0, cg_steps=25)
+    md = XLBOMD(w, m, v, 20.0, cg_steps=25, reorder=order)
     for k, r in enumerate(ref):
         o = md.step()
         print(f"step {k}: E gpu {o['E']:.12f} oracle {r['E']:.12f} ekin {o['ekin']:.9e} "
@@ -36,7 +40,8 @@ def test_xlbomd_energy_conservation_si4096(gpu):
     import time
     from paper_2002_07704_amd.xlbomd import XLBOMD
     w = W.get("si4096_4x4")
-    md = XLBOMD(w, W.masses(w), W.thermal_velocities(w, 300.0, 1), 20.0, cg_steps=25)
+    md = XLBOMD(w, W.masses(w), W.thermal_velocities(w, 300.0, 1), 20.0, cg_steps=25,
+                reorder="bonds")
     out = []
     for k in range(4):
         t0 = time.perf_counter()
