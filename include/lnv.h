@@ -636,8 +636,12 @@ typedef struct lnv_opts {
    * lnv_eval_mixed on this workspace (FP32 block products under the FP32
    * accumulation mode, FP64 assembly and traces; its partials and scalars
    * are not used: the step's own are), and S.L is widened to FP64 from the
-   * FP32 product for the line search; every other product of the step stays
-   * FP64. */
+   * FP32 product for the line search.  With a metric, P_L(T G T) and
+   * P_L(T F T) (the preconditioner) are formed in FP32 as well, in the
+   * workspace's buffers after the evaluation has used them (its pattern of
+   * X must hold pat(L.L), which then needs lut, and Lu, Vu must be set;
+   * otherwise they stay FP64).  The line search, the electron-number check
+   * and correction stay FP64. */
   const struct lnv_eval32_ws* eval32;
   /* Runaway guard (always on): two consecutive rises of E by more than
    * 1e-11 |E|, or occupation bounds of L S outside [-0.5, 1.5], restart the

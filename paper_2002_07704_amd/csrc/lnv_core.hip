@@ -1397,6 +1397,42 @@ int metric_apply_pair(const lnv_bsm* T, const double* V1, double* out1, const do
   return sym_product_pair(&ws->LL, T, &O1, &ev.Lu, &LL2, T, &O2, &U2, s);
 }
 
+// The metric products of a mixed-precision step in FP32 (the metric is a
+// preconditioner: the projection keeps <D, F> = 0 in FP64 whatever the
+// precision of F_c, and the line search and electron-number correction stay
+// FP64).  T, G, F are rounded to FP32 into buffers the FP32 evaluation has
+// finished with (its L copy, YT, W), the natural intermediates G T and F T
+// go to its X and XT, the halves to its Lu and Vu, the mirrored results to
+// YT and W (G and F in FP32 are dead by then), and G_c, F_c come back in
+// FP64.  LNV_EUNSUPPORTED when a buffer or table does not fit: the caller
+// then forms the products in FP64.
+int metric_apply_pair32(const lnv_bsm* T, const double* G, double* Gc, const double* F,
+                        double* Fc, const lnv_cg_ws* ws, const lnv_eval32_ws* w32,
+                        hipStream_t s) {
+  const lnv_pattern* pl = T->pat;
+  const lnv_pattern* pll = ws->LL.pat;
+  const lnv_pattern* pu = w32->Lu.pat;
+  if (!pll || !pll->lut || !w32->X.val || !w32->XT.val || !w32->X.pat || !w32->XT.pat ||
+      pll->nnzb > w32->X.pat->nnzb || pll->nnzb > w32->XT.pat->nnzb || !pu || !w32->Lu.val ||
+      !w32->Vu || !w32->YT || !w32->W || !w32->L.val || w32->L.pat != pl || pu->n != pl->n ||
+      w32->Lu.dtype != LNV_F32)
+    return LNV_EUNSUPPORTED;
+  lnv_bsm T32{pl, 4, LNV_F32, w32->L.val};
+  lnv_bsm G64{pl, 4, LNV_F64, const_cast<double*>(G)}, F64{pl, 4, LNV_F64, const_cast<double*>(F)};
+  lnv_bsm G32{pl, 4, LNV_F32, w32->YT}, F32{pl, 4, LNV_F32, w32->W};
+  LNV_TRY(convert_launch(T, &T32, s));
+  LNV_TRY(convert_launch(&G64, &G32, s));
+  LNV_TRY(convert_launch(&F64, &F32, s));
+  lnv_bsm GT{pll, 4, LNV_F32, w32->X.val}, FT{pll, 4, LNV_F32, w32->XT.val};
+  LNV_TRY(multiply_pair_launch(&G32, &T32, &GT, &F32, &T32, &FT, 1, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, s));
+  lnv_bsm U1{pu, 4, LNV_F32, w32->Lu.val}, U2{pu, 4, LNV_F32, w32->Vu};
+  LNV_TRY(sym_product_pair(&T32, &GT, &G32, &U1, &T32, &FT, &F32, &U2, s));
+  lnv_bsm Gc64{pl, 4, LNV_F64, Gc}, Fc64{pl, 4, LNV_F64, Fc};
+  LNV_TRY(convert_launch(&G32, &Gc64, s));
+  return convert_launch(&F32, &Fc64, s);
+}
+
 }  // namespace
 
 extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws,
@@ -1546,7 +1582,13 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   const double* Fc = ws->F;
   double* gcur = ws->g;
   if (metric) {
-    LNV_TRY(metric_apply_pair(T, ws->G, ws->Gc, ws->F, ws->Fc, ws, s));
+    int st = LNV_EUNSUPPORTED;
+    if (opts->eval32)
+      st = metric_apply_pair32(T, ws->G, ws->Gc, ws->F, ws->Fc, ws, opts->eval32, s);
+    if (st == LNV_EUNSUPPORTED)
+      LNV_TRY(metric_apply_pair(T, ws->G, ws->Gc, ws->F, ws->Fc, ws, s));
+    else
+      LNV_TRY(st);
     Gc = ws->Gc;
     Fc = ws->Fc;
     gcur = ws->gc;
