@@ -410,7 +410,8 @@ def main():
     ms_per_step = dt * 1e3 / args.steps
     status = int(sysg.scalar("STATUS"))
     n_corr = int(sysg.scalar("NCORR"))
-    flops_run = args.steps * sysg.flops("step_base") + n_corr * sysg.flops("ncorr")
+    flops_run = (args.steps * sysg.flops("step_base") + sysg.flops("first_extra")
+                 + n_corr * sysg.flops("ncorr"))
     flops_step = flops_run / args.steps
     sysg.eval()
     torch.cuda.synchronize()

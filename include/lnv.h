@@ -696,6 +696,12 @@ int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, l
  * method's electron-number constraint (Sec. II.C.2).  Every decision is
  * taken on the device: the call never synchronises.  Diagnostics are in
  * scalars (E, N at the start of the step, mu, beta, alpha, delta, ...).
+ * For k > 0, L must be the previous call's result (as the direction
+ * history already assumes; restart with k = 0 after changing L): the step
+ * leaves S.L of its final L in ws->SL2 (S.L_new = S.L + alpha S.D from the
+ * line search's S.D, plus delta S.F_c from the correction's, by linearity)
+ * and an FP64 step with k > 0 starts its evaluation from it instead of
+ * forming S.L again.
  */
 int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
                 double n_elec, int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);

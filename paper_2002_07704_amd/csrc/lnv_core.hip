@@ -782,6 +782,15 @@ __global__ __launch_bounds__(256) void k_vec_axpy(int64_t nv, const double* __re
     L[q] = L[q] + a * D[q];
 }
 
+// Y = X + sc[idx] * Y
+__global__ __launch_bounds__(256) void k_vec_xpay(int64_t nv, const double* __restrict__ X,
+                                                  const double* __restrict__ sc, int idx,
+                                                  double* __restrict__ Y) {
+  const double a = sc[idx];
+  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256)
+    Y[q] = fma(a, Y[q], X[q]);
+}
+
 // ------------------------------------------------------------------ host helpers
 // n_items_L: the larger of L's n_items and n_cl_items
 int64_t slot_len(int n_items_L) {
@@ -872,6 +881,7 @@ struct EvalOps {
   double* scalars;
   const lnv_bsm *Zu, *Lu;
   void* Vu;
+  const void* SLcarry;   // S.L already formed for this L (copied instead of multiplied)
 };
 
 }  // namespace
@@ -939,7 +949,13 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
   const lnv_pattern* pl = L64->pat;
   const int dt = o.SL->dtype;
   lnv_bsm YT{pl, 4, dt, o.YT}, Wm{pl, 4, dt, o.W}, Vm{pl, 4, dt, o.V};
-  LNV_TRY(multiply_launch(1.0, o.S, o.L, 0, 0.0, o.SL, 1, nullptr, nullptr, nullptr, nullptr, s));
+  if (o.SLcarry) {
+    const size_t bytes = (size_t)o.SL->pat->nnzb * 16 * sizeof(T);
+    LNV_HIP(hipMemcpyAsync(o.SL->val, o.SLcarry, bytes, hipMemcpyDeviceToDevice, s));
+  } else {
+    LNV_TRY(multiply_launch(1.0, o.S, o.L, 0, 0.0, o.SL, 1, nullptr, nullptr, nullptr, nullptr,
+                            s));
+  }
   LNV_TRY(transpose_launch(o.SL, o.perm_SL, o.LS->val, s));
   LNV_TRY(multiply_launch(1.0, o.H, o.LS, 0, 0.0, o.X, 1, nullptr, nullptr, nullptr, nullptr, s));
   // Z = SLS, W = P_L(SLHLS) and V = P_L(SLSLS) are symmetric (formed on
@@ -973,10 +989,12 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
 }
 
 int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, double* F,
-              double* EN, const lnv_eval_ws* ws, hipStream_t s) {
+              double* EN, const lnv_eval_ws* ws, hipStream_t s,
+              const double* sl_carry = nullptr) {
   EvalOps o{L,       S,           H,          &ws->SL,     &ws->LS, &ws->X,
             &ws->XT, &ws->Z,      ws->perm_SL, ws->perm_X,  ws->YT,  ws->W,
-            ws->V,   ws->partials, ws->scalars, &ws->Zu,    &ws->Lu, ws->Vu};
+            ws->V,   ws->partials, ws->scalars, &ws->Zu,    &ws->Lu, ws->Vu,
+            sl_carry};
   return eval_products<double>(L, o, G, F, EN, s);
 }
 
@@ -1570,7 +1588,8 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     lnv_bsm SL64 = ev.SL;
     LNV_TRY(convert_launch(&w32->SL, &SL64, s));
   } else {
-    LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s));
+    // k > 0: L is the previous step's result, whose S.L that step left in SL2
+    LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s, k > 0 ? ws->SL2 : nullptr));
   }
   // occupation bounds of L S for the runaway guard (every occ_every-th step)
   if (opts->occ_every > 0 && ws->lanczos && k % opts->occ_every == 0) {
@@ -1647,7 +1666,16 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   // 6. electron number at the new L; cubic correction along F_c when needed
   lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
   lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
-  LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
+  const int64_t nsl = ev.SL.pat->nnzb * 16;
+  if (opts->eval32) {
+    LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
+  } else {
+    // S.L_new = S.L + alpha S.D: the evaluation's S.L (FP64) and the line
+    // search's S.D, which it left in SL2
+    k_vec_xpay<<<kVecGrid, 256, 0, s>>>(nsl, static_cast<const double*>(ev.SL.val), sc,
+                                        LNV_SC_ALPHA, ws->SL2);
+    LNV_LAUNCH_CHECK();
+  }
   LNV_TRY(transpose_launch(&SL2, ev.perm_SL, static_cast<double*>(ev.LS.val), s));
   lnv_bsm Vu{ev.Lu.pat, 4, LNV_F64, ev.Vu};
   LNV_TRY(sym_product(S, &ev.LS, &ev.Z, &ev.Zu, s));
@@ -1678,6 +1706,10 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     LNV_TRY(scalar_stage(part, rl, sc, ST_DELTA, sa, s));
   }
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, Fc, sc, LNV_SC_DELTA, skip, Lv);
+  LNV_LAUNCH_CHECK();
+  // S.L of the final L for the next step: + delta S.F_c (A_F^T, in ev.SL)
+  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nsl, static_cast<const double*>(ev.SL.val), sc,
+                                      LNV_SC_DELTA, skip, ws->SL2);
   LNV_LAUNCH_CHECK();
   if (metric)
     std::swap(ws->gc, ws->gc_prev);

@@ -923,10 +923,14 @@ class LNVSystem:
 
     def flops(self, what="eval", padded=False):
         """Algorithmic flops (2 n_i n_k n_j per block triple, the functions
-        present) of one piece of work: "eval", "init" (L0), "step_base" (a CG
-        step without the electron-number correction), "ncorr" (that
-        correction), "step" (both).  padded=True: 2 * 4^3 per stored triple,
-        the arithmetic the kernels do (the same unless atoms are split)."""
+        present) of one piece of work: "eval", "init" (L0), "step_base" (an
+        FP64 CG step after the first of a minimisation, without the
+        electron-number correction: its S.L comes from the previous step and
+        the check's S.L_new from the line search's S.D, both by linearity),
+        "first_extra" (the S.L product the first step forms), "ncorr" (the
+        correction), "step" (step_base + ncorr).  padded=True: 2 * 4^3 per
+        stored triple, the arithmetic the kernels do (the same unless atoms
+        are split)."""
         t = self._weights(padded)
         ev = t["SL"] + t["X"] + t["Z"] + t["YT"] + t["W"] + t["V"]
         nchk = t["SL"] + t["Z"] + t["V"]
@@ -942,8 +946,9 @@ class LNVSystem:
             init = t["SL"] + t["Z"] + t["Vf"]
         met = 2 * (t["TG"] + t["TGT"]) if self.metric is not None else 0
         tot = {"eval": ev, "init": init,
-               "step_base": ev + met + line + nchk, "ncorr": ncor,
-               "step": ev + met + line + nchk + ncor}[what]
+               "step_base": ev + met + line + nchk - 2 * t["SL"], "ncorr": ncor,
+               "first_extra": t["SL"],
+               "step": ev + met + line + nchk - 2 * t["SL"] + ncor}[what]
         return tot
 
     # ----------------------------------------------------------- hot path
