@@ -700,8 +700,9 @@ int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, l
  * history already assumes; restart with k = 0 after changing L): the step
  * leaves S.L of its final L in ws->SL2 (S.L_new = S.L + alpha S.D from the
  * line search's S.D, plus delta S.F_c from the correction's, by linearity)
- * and an FP64 step with k > 0 starts its evaluation from it instead of
- * forming S.L again.
+ * and S.L.S in ws->ev.Z (the check's S.L_new.S plus delta S.F_c.S), and an
+ * FP64 step with k > 0 not divisible by reset_period starts its evaluation
+ * from them instead of forming S.L and S.L.S again.
  */
 int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
                 double n_elec, int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);

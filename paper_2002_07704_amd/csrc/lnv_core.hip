@@ -882,6 +882,7 @@ struct EvalOps {
   const lnv_bsm *Zu, *Lu;
   void* Vu;
   const void* SLcarry;   // S.L already formed for this L (copied instead of multiplied)
+  bool Zcarry;           // Z = S.L.S already in Z for this L (not formed again)
 };
 
 }  // namespace
@@ -962,7 +963,7 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
   // their halves when the workspace carries them); YT = P_L(SLSLH) is not
   const lnv_bsm* Lu = o.Lu;
   lnv_bsm Vu{Lu ? Lu->pat : nullptr, 4, dt, o.Vu};
-  LNV_TRY(sym_product(o.S, o.LS, o.Z, o.Zu, s));
+  if (!o.Zcarry) LNV_TRY(sym_product(o.S, o.LS, o.Z, o.Zu, s));
   LNV_TRY(transpose_launch(o.X, o.perm_X, o.XT->val, s));
   LNV_TRY(multiply_launch(1.0, o.SL, o.XT, 0, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(sym_product_pair(o.SL, o.X, &Wm, Lu, o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
@@ -990,11 +991,11 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
 
 int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, double* F,
               double* EN, const lnv_eval_ws* ws, hipStream_t s,
-              const double* sl_carry = nullptr) {
+              const double* sl_carry = nullptr, bool z_carry = false) {
   EvalOps o{L,       S,           H,          &ws->SL,     &ws->LS, &ws->X,
             &ws->XT, &ws->Z,      ws->perm_SL, ws->perm_X,  ws->YT,  ws->W,
             ws->V,   ws->partials, ws->scalars, &ws->Zu,    &ws->Lu, ws->Vu,
-            sl_carry};
+            sl_carry, z_carry};
   return eval_products<double>(L, o, G, F, EN, s);
 }
 
@@ -1588,8 +1589,11 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     lnv_bsm SL64 = ev.SL;
     LNV_TRY(convert_launch(&w32->SL, &SL64, s));
   } else {
-    // k > 0: L is the previous step's result, whose S.L that step left in SL2
-    LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s, k > 0 ? ws->SL2 : nullptr));
+    // k > 0: L is the previous step's result, whose S.L and S.L.S that step
+    // left in SL2 and Z; formed afresh at the resets (k % reset_period == 0)
+    // so that the rounding of the carried sums does not build up
+    const bool carry = k > 0 && k % opts->reset_period != 0;
+    LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s, carry ? ws->SL2 : nullptr, carry));
   }
   // occupation bounds of L S for the runaway guard (every occ_every-th step)
   if (opts->occ_every > 0 && ws->lanczos && k % opts->occ_every == 0) {
@@ -1707,9 +1711,13 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   }
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, Fc, sc, LNV_SC_DELTA, skip, Lv);
   LNV_LAUNCH_CHECK();
-  // S.L of the final L for the next step: + delta S.F_c (A_F^T, in ev.SL)
+  // S.L and S.L.S of the final L for the next step: + delta S.F_c (A_F^T,
+  // in ev.SL) and + delta S.F_c.S (Z_F, in X's buffer)
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nsl, static_cast<const double*>(ev.SL.val), sc,
                                       LNV_SC_DELTA, skip, ws->SL2);
+  LNV_LAUNCH_CHECK();
+  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(ev.Z.pat->nnzb * 16, static_cast<const double*>(ev.X.val),
+                                      sc, LNV_SC_DELTA, skip, static_cast<double*>(ev.Z.val));
   LNV_LAUNCH_CHECK();
   if (metric)
     std::swap(ws->gc, ws->gc_prev);

@@ -925,9 +925,10 @@ class LNVSystem:
         """Algorithmic flops (2 n_i n_k n_j per block triple, the functions
         present) of one piece of work: "eval", "init" (L0), "step_base" (an
         FP64 CG step after the first of a minimisation, without the
-        electron-number correction: its S.L comes from the previous step and
-        the check's S.L_new from the line search's S.D, both by linearity),
-        "first_extra" (the S.L product the first step forms), "ncorr" (the
+        electron-number correction: its S.L and S.L.S come from the previous
+        step and the check's S.L_new from the line search's S.D, by
+        linearity), "first_extra" (the S.L and S.L.S products the first step
+        and each reset step form), "ncorr" (the
         correction), "step" (step_base + ncorr).  padded=True: 2 * 4^3 per
         stored triple, the arithmetic the kernels do (the same unless atoms
         are split)."""
@@ -946,9 +947,9 @@ class LNVSystem:
             init = t["SL"] + t["Z"] + t["Vf"]
         met = 2 * (t["TG"] + t["TGT"]) if self.metric is not None else 0
         tot = {"eval": ev, "init": init,
-               "step_base": ev + met + line + nchk - 2 * t["SL"], "ncorr": ncor,
-               "first_extra": t["SL"],
-               "step": ev + met + line + nchk - 2 * t["SL"] + ncor}[what]
+               "step_base": ev + met + line + nchk - 2 * t["SL"] - t["Z"], "ncorr": ncor,
+               "first_extra": t["SL"] + t["Z"],
+               "step": ev + met + line + nchk - 2 * t["SL"] - t["Z"] + ncor}[what]
         return tot
 
     # ----------------------------------------------------------- hot path
