@@ -1573,6 +1573,10 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   sa.reset_period = opts->reset_period;
 
   // 1. E, N, G, F (FP64, or FP32 products); metric gradients G_c, F_c; mu
+  // k > 0: L is the previous step's result, whose S.L and S.L.S that step
+  // left in SL2 and Z; formed afresh at the resets (k % reset_period == 0)
+  // so that the rounding of the carried sums does not build up
+  const bool carry = k > 0 && k % opts->reset_period != 0;
   if (opts->eval32) {
     const lnv_eval32_ws* w32 = opts->eval32;
     lnv_bsm Gm{pl, 4, LNV_F64, ws->G}, Fm{pl, 4, LNV_F64, ws->F};
@@ -1586,13 +1590,15 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
               &w32->XT, &w32->Z,  w32->perm_SL, w32->perm_X,  w32->YT,  w32->W,
               w32->V,   part,     sc,           &w32->Zu,     &w32->Lu, w32->Vu};
     LNV_TRY(eval_products<float>(L, o, ws->G, ws->F, nullptr, s));
-    lnv_bsm SL64 = ev.SL;
-    LNV_TRY(convert_launch(&w32->SL, &SL64, s));
+    // S.L in FP64 for the line search: the carried one, else the FP32 product widened
+    if (carry) {
+      LNV_HIP(hipMemcpyAsync(ev.SL.val, ws->SL2, sizeof(double) * (size_t)ev.SL.pat->nnzb * 16,
+                             hipMemcpyDeviceToDevice, s));
+    } else {
+      lnv_bsm SL64 = ev.SL;
+      LNV_TRY(convert_launch(&w32->SL, &SL64, s));
+    }
   } else {
-    // k > 0: L is the previous step's result, whose S.L and S.L.S that step
-    // left in SL2 and Z; formed afresh at the resets (k % reset_period == 0)
-    // so that the rounding of the carried sums does not build up
-    const bool carry = k > 0 && k % opts->reset_period != 0;
     LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s, carry ? ws->SL2 : nullptr, carry));
   }
   // occupation bounds of L S for the runaway guard (every occ_every-th step)
@@ -1671,11 +1677,12 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
   lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
   const int64_t nsl = ev.SL.pat->nnzb * 16;
-  if (opts->eval32) {
+  if (opts->eval32 && !carry) {
+    // the FP64 S.L of this step was widened from an FP32 product
     LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
   } else {
-    // S.L_new = S.L + alpha S.D: the evaluation's S.L (FP64) and the line
-    // search's S.D, which it left in SL2
+    // S.L_new = S.L + alpha S.D: this step's FP64 S.L and the line search's
+    // S.D, which it left in SL2
     k_vec_xpay<<<kVecGrid, 256, 0, s>>>(nsl, static_cast<const double*>(ev.SL.val), sc,
                                         LNV_SC_ALPHA, ws->SL2);
     LNV_LAUNCH_CHECK();
