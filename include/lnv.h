@@ -391,6 +391,13 @@ typedef struct lnv_eval_ws {
   lnv_bsm Zu;
   lnv_bsm Lu;
   void* Vu;
+  /* Host flag, owned by the library: nonzero while SL2 of the enclosing
+   * lnv_cg_ws and Z hold S.L and S.L.S of the L that the last lnv_cg_step
+   * on this workspace left (see lnv_cg_step).  lnv_cg_step sets it;
+   * lnv_eval, lnv_hotelling and lnv_cg_init on this workspace clear it.  A
+   * caller that changes L or S (or the buffers) itself between steps must
+   * clear it, or restart with k = 0.  Initialise to 0. */
+  int32_t carry;
 } lnv_eval_ws;
 
 #define LNV_NSLOTS 12
@@ -430,7 +437,7 @@ enum {
  * Hot path: allocates nothing, no host synchronisation.
  */
 int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
-             lnv_bsm* F, double* EN, const lnv_eval_ws* ws, hipStream_t s);
+             lnv_bsm* F, double* EN, lnv_eval_ws* ws, hipStream_t s);
 
 /* ------------------------------------------------------------ batches of cells
  * A batch of independent periodic cells is one block-diagonal system: the
@@ -697,12 +704,17 @@ int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, l
  * taken on the device: the call never synchronises.  Diagnostics are in
  * scalars (E, N at the start of the step, mu, beta, alpha, delta, ...).
  * For k > 0, L must be the previous call's result (as the direction
- * history already assumes; restart with k = 0 after changing L): the step
- * leaves S.L of its final L in ws->SL2 (S.L_new = S.L + alpha S.D from the
- * line search's S.D, plus delta S.F_c from the correction's, by linearity)
- * and S.L.S in ws->ev.Z (the check's S.L_new.S plus delta S.F_c.S), and an
- * FP64 step with k > 0 not divisible by reset_period starts its evaluation
- * from them instead of forming S.L and S.L.S again.
+ * history already assumes; restart with k = 0 after changing L), and S and
+ * the workspace must be unchanged since that call: the step leaves S.L of
+ * its final L in ws->SL2 (S.L_new = S.L + alpha S.D from the line search's
+ * S.D, plus delta S.F_c from the correction's, by linearity) and S.L.S in
+ * ws->ev.Z (the check's S.L_new.S plus delta S.F_c.S) and sets
+ * ws->ev.carry.  A step with k > 0 not divisible by reset_period and
+ * ws->ev.carry set starts from them: an FP64 step's evaluation forms
+ * neither S.L nor S.L.S, and a mixed step (opts->eval32) takes the carried
+ * FP64 S.L for its line search and electron-number check.  Otherwise (a
+ * reset step, or the flag cleared by another call on the workspace) both
+ * are formed afresh.
  */
 int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
                 double n_elec, int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);

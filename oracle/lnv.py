@@ -165,6 +165,14 @@ def initial_L(S, maskL, n_elec, T=None):
 
 
 # ------------------------------------------------------------------ CG
+def pr_plus_beta(g, gc, g_prev, gc_prev):
+    """Polak-Ribiere coefficient clamped at zero (PR+) in the metric of the
+    preconditioner: beta = max(0, <g, g_c - g_c,prev> / <g_prev, g_c,prev>),
+    g the projected gradient and g_c = P_L(T g T) its preconditioned form.
+    With T = I this is the textbook PR+ of nonlinear CG."""
+    return max(0.0, dot(g, gc - gc_prev) / dot(g_prev, gc_prev))
+
+
 def occupations(L, S):
     """Occupation numbers: the eigenvalues of L S, ascending.  L S is similar
     to C^T L C with S = C C^T (Cholesky), which is symmetric."""
@@ -197,7 +205,8 @@ def guard_step(state, k, E, occ, reset_period):
 
 
 def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
-       n_tol=1e-11, step_cap=0.1, stop_g=None, stop_de=None, n_atoms=None, occ_every=0):
+       n_tol=1e-11, step_cap=0.1, stop_g=None, stop_de=None, n_atoms=None, occ_every=0,
+       beta_rule=pr_plus_beta, callback=None):
     """Conjugate-gradient LNV minimisation; returns (L, history).
 
     Iteration k at the current L:
@@ -215,6 +224,10 @@ def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
     Between 3 and 4 the runaway guard (guard_step) may force beta = 0, with
     the exact occupations of L S every occ_every-th iteration (0: never).
     History entries carry guard (the direction was restarted) and runaway.
+    beta_rule(g, g_c, g_prev, g_c,prev) gives beta outside the resets
+    (pr_plus_beta; other rules only serve tests that tell them apart);
+    callback(entry, G, F), if given, sees each history entry with the
+    gradients of that iteration's evaluation (before its step).
     """
     if L0 is None:
         L, _ = initial_L(S, maskL, n_elec, T)
@@ -244,7 +257,7 @@ def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
         if k % reset_period == 0 or force_reset or guard or g_prev is None:
             beta = 0.0
         else:
-            beta = max(0.0, dot(g, gc - gc_prev) / dot(g_prev, gc_prev))
+            beta = beta_rule(g, gc, g_prev, gc_prev)
         D = -gc + beta * D_prev if beta != 0.0 else -gc
         D = D - (dot(D, F) / FF) * Fc
         c = line_coeffs(L, D, S, H - mu * S)
@@ -266,6 +279,8 @@ def cg(S, H, maskL, n_elec, n_iter, L0=None, T=None, reset_period=40,
         hist.append(dict(k=k, E=E, N=N, mu=mu, beta=beta, alpha=alpha, delta=delta,
                          c=c.tolist(), nc=nc.tolist(), gnorm=gnorm, N_after_step=N1,
                          guard=guard, runaway=runaway, occ=occ))
+        if callback is not None:
+            callback(hist[-1], G, F)
         if stop_g is not None and gnorm <= stop_g:
             break
         if stop_de is not None and n_atoms:

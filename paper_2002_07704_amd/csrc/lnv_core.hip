@@ -1148,9 +1148,10 @@ extern "C" int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials,
 }
 
 extern "C" int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
-                        lnv_bsm* F, double* EN, const lnv_eval_ws* ws, hipStream_t s) {
+                        lnv_bsm* F, double* EN, lnv_eval_ws* ws, hipStream_t s) {
   if (!G || !F) return LNV_EINVAL;
   LNV_TRY(check_eval(L, S, H, G, F, ws));
+  ws->carry = 0;   // Z (and S.L) now belong to this L
   return eval_core(L, S, H, static_cast<double*>(G->val), static_cast<double*>(F->val), EN, ws,
                    s);
 }
@@ -1466,6 +1467,7 @@ extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_c
       !pattern_ready(ev.SL.pat, true, false, true))
     return LNV_EPATTERN;
   if (ev.partials_len < pt->n) return LNV_EINVAL;
+  ws->ev.carry = 0;
   double* part = ev.partials;
   double* sc = ev.scalars;
   const size_t bytes = sizeof(double) * (size_t)pt->nnzb * 16;
@@ -1510,6 +1512,7 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
     return LNV_EPATTERN;
   if (T && (!bsm_ok(T) || T->pat != L->pat || T->blk != 4)) return LNV_EPATTERN;
   if (ev.partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
+  ws->ev.carry = 0;   // SL2 and Z are scratch here
   const lnv_pattern* pl = L->pat;
   const int64_t nv = pl->nnzb * 16;
   const int ni = pl->n_items;
@@ -1574,9 +1577,11 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
 
   // 1. E, N, G, F (FP64, or FP32 products); metric gradients G_c, F_c; mu
   // k > 0: L is the previous step's result, whose S.L and S.L.S that step
-  // left in SL2 and Z; formed afresh at the resets (k % reset_period == 0)
-  // so that the rounding of the carried sums does not build up
-  const bool carry = k > 0 && k % opts->reset_period != 0;
+  // left in SL2 and Z (ev.carry set, and cleared by any other call that
+  // writes them); formed afresh at the resets (k % reset_period == 0) so
+  // that the rounding of the carried sums does not build up
+  const bool carry = k > 0 && k % opts->reset_period != 0 && ev.carry != 0;
+  ws->ev.carry = 0;   // until this step has left S.L and S.L.S of its final L
   if (opts->eval32) {
     const lnv_eval32_ws* w32 = opts->eval32;
     lnv_bsm Gm{pl, 4, LNV_F64, ws->G}, Fm{pl, 4, LNV_F64, ws->F};
@@ -1731,6 +1736,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   else
     std::swap(ws->g, ws->gc_prev);
   std::swap(ws->D, ws->D_prev);
+  ws->ev.carry = 1;
   return LNV_OK;
 }
 

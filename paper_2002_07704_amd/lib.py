@@ -48,7 +48,7 @@ class LnvEvalWs(ctypes.Structure):
                 ("perm_SL", c_void_p), ("perm_X", c_void_p), ("YT", c_void_p),
                 ("W", c_void_p), ("V", c_void_p), ("partials", c_void_p),
                 ("partials_len", c_int64), ("scalars", c_void_p), ("Zu", LnvBsm), ("Lu", LnvBsm),
-                ("Vu", c_void_p)]
+                ("Vu", c_void_p), ("carry", c_int32)]
 
 
 class LnvCgWs(ctypes.Structure):

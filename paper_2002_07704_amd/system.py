@@ -873,6 +873,7 @@ class LNVSystem:
         self.pos.copy_(torch.as_tensor(np.ascontiguousarray(rows)))
         self.S.rebind(self.synth_values(0, self.pS, self.R_S, 3.0).val)
         self.H.rebind(self.synth_values(1, self.pH, self.R_H, 2.5).val)
+        self.ws.ev.carry = 0     # S.L and S.L.S of the old S are stale
 
     def eval_values(self, L, S, H, G, F, EN):
         """lnv_eval at the given value tensors (on this system's patterns)."""
@@ -976,6 +977,7 @@ class LNVSystem:
         self.scalars[L_.SC["E_PREV"]] = float("nan")
         self.scalars[L_.SC["RISES"]] = 0.0
         self.scalars[L_.SC["GUARD_K"]] = -1e9
+        self.ws.ev.carry = 0
         self.k = 0
 
     def cg_check(self):

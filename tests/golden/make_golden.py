@@ -7,6 +7,16 @@ stored instead of recomputed inside the GPU tests.
 
 usage: python tests/golden/make_golden.py si4096_4x4 [n_cg_steps]
        python tests/golden/make_golden.py rows siOH8192_mixed
+       python tests/golden/make_golden.py cgtraj si4096_4x4 [n_cg_steps]
+
+The third form writes <workload>_cg.json and <workload>_cg_rows.npz: the
+minimisation the benchmark times, from the oracle alone -- Hotelling's
+approximate inverse overlap T (16 steps) as the metric, the canonical
+purification start (oracle/pm.py, at most 60 steps), then CG iterations in
+that metric -- with every iteration's scalars (E, N, mu, beta, alpha, delta)
+and the G and F rows of a few atoms at selected iterations.  Each iteration
+is written as soon as it is done (a dense step at 16384 orbitals takes about
+20 minutes on 8 cores), so an interrupted run still leaves its first steps.
 
 The second form writes <workload>_rows.npz: the row-wise oracle's G and F
 rows (and per-atom energy / electron contributions) of a few sampled atoms at
@@ -74,9 +84,60 @@ def rows_main(name):
     print("wrote", path, flush=True)
 
 
+CG_ROW_ATOMS = (0, 1365, 2730, 4095)
+CG_ROW_ITERS = (0, 4, 9)
+
+
+def cgtraj_main(name, steps):
+    from oracle import pm as opm
+    w = W.get(name)
+    here = os.path.dirname(os.path.abspath(__file__))
+    jpath = os.path.join(here, f"{name}_cg.json")
+    npath = os.path.join(here, f"{name}_cg_rows.npz")
+    t0 = time.time()
+    sy = ost.System(w)
+    T = olnv.hotelling(sy.S, sy.maskL, 16)
+    print(f"system + metric {time.time() - t0:.1f}s", flush=True)
+    K, pm_hist, info = opm.purify(sy.S, sy.H, T, sy.maskL, w.n_elec, 60)
+    print(f"purification: {len(pm_hist)} entries {time.time() - t0:.1f}s", flush=True)
+    out = {"workload": name, "n_atoms": w.n, "metric": "hotelling 16", "start": "purify 60",
+           "pm_steps": len(pm_hist), "pm_lambda": info["lam"], "cg": [],
+           "row_atoms": [a for a in CG_ROW_ATOMS if a < w.n], "row_iters": list(CG_ROW_ITERS)}
+    rows = {}
+    off = ost.offsets(w.nfun)
+    rp, col = ost.neighbours(w.pos, w.box, w.R_L)
+
+    def save():
+        out["seconds"] = time.time() - t0
+        with open(jpath + ".tmp", "w") as f:
+            json.dump(out, f, indent=1)
+        os.replace(jpath + ".tmp", jpath)
+        if rows:
+            np.savez_compressed(npath + ".tmp.npz", **rows)
+            os.replace(npath + ".tmp.npz", npath)
+
+    def callback(h, G, F):
+        out["cg"].append({k: h[k] for k in ("k", "E", "N", "mu", "beta", "alpha", "delta",
+                                            "gnorm", "N_after_step")})
+        if h["k"] in CG_ROW_ITERS:
+            for a in out["row_atoms"]:
+                cols = col[rp[a]:rp[a + 1]]
+                r = slice(off[a], off[a + 1])
+                rows[f"G_{h['k']}_{a}"] = np.stack([G[r, off[j]:off[j + 1]] for j in cols])
+                rows[f"F_{h['k']}_{a}"] = np.stack([F[r, off[j]:off[j + 1]] for j in cols])
+                rows[f"cols_{a}"] = cols
+        save()
+        print(h["k"], h["E"] / w.n, h["alpha"], h["delta"], f"{time.time() - t0:.0f}s", flush=True)
+
+    olnv.cg(sy.S, sy.H, sy.maskL, w.n_elec, steps, L0=K, T=T, callback=callback)
+    print("wrote", jpath, npath, flush=True)
+
+
 def main():
     if len(sys.argv) > 2 and sys.argv[1] == "rows":
         return rows_main(sys.argv[2])
+    if len(sys.argv) > 2 and sys.argv[1] == "cgtraj":
+        return cgtraj_main(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 10)
     name = sys.argv[1] if len(sys.argv) > 1 else "si4096_4x4"
     steps = int(sys.argv[2]) if len(sys.argv) > 2 else 2
     w = W.get(name)
