@@ -279,6 +279,28 @@ int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32
                          double beta, lnv_bsm* C, int32_t store, const lnv_bsm* M1,
                          const lnv_bsm* M2, double* partials, double* out, hipStream_t s);
 
+/* lnv_bsm_multiply_dot_noalloc -- lnv_bsm_multiply_dot for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc): the trace partials live in a fixed
+ * scratch array of LNV_NOALLOC_PARTIALS doubles (4 MiB) that the library
+ * holds on each GPU it runs on until the process ends, instead of the
+ * caller's partials buffer.  Same arguments and results otherwise; M1 and
+ * out are required (the call exists for the traces).  The call allocates
+ * nothing (no hipMalloc, no library allocation; the device address of the
+ * scratch is looked up once per device on the first call made with that
+ * device current).  Errors: LNV_ECAPACITY when the product has more than
+ * LNV_NOALLOC_PARTIALS / 2 work pieces (lnv_pattern n_cl_items, or n_items
+ * without a cluster plan); LNV_EUNSUPPORTED while the multiply timing is on
+ * (it creates events).  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap on one device (concurrent streams, or host threads)
+ * race, and must be serialised by the caller.  Every work piece writes its
+ * partials before they are reduced, so the scratch needs no clearing. */
+#define LNV_NOALLOC_PARTIALS (1 << 19)
+int lnv_bsm_multiply_dot_noalloc(double alpha, const lnv_bsm* A, const lnv_bsm* B,
+                                 int32_t transB, double beta, lnv_bsm* C, int32_t store,
+                                 const lnv_bsm* M1, const lnv_bsm* M2, double* out,
+                                 hipStream_t s);
+
 /* lnv_bsm_transpose -- AT = A^T: block p of A, transposed, goes to position
  * perm[p] of AT (perm from lnv_pattern_transpose_map).  Needs A.items.
  * A and AT of one dtype.  Hot path (HBM-bound copy). */

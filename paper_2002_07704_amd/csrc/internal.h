@@ -137,6 +137,10 @@ int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bs
 int occupation_bounds(const lnv_bsm* L, const lnv_bsm* S, int steps, double* work, double* out,
                       hipStream_t s);
 
+// Whether the optional multiply timing (lnv_timing_enable) is on: it creates
+// HIP events as launches need them.
+bool timing_on();
+
 inline int32_t partial_items(const lnv_pattern* p) {
   return p->n_items > p->n_cl_items ? p->n_items : p->n_cl_items;
 }

@@ -15,6 +15,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 #include <utility>
 
 #include "internal.h"
@@ -1119,6 +1120,51 @@ extern "C" int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bs
   k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
+}
+
+// Scratch of lnv_bsm_multiply_dot_noalloc: the trace partials of the
+// multiply's work pieces, in device memory the library holds for the life of
+// the process (one copy per GPU, each at its own address).  Host code names
+// it only through hipGetSymbolAddress, once per device.
+static __device__ __align__(256) double scratch[LNV_NOALLOC_PARTIALS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (the current device), looked up on
+// the first call made with that device current.
+int scratch_address(double** out) {
+  int dev = -1;
+  LNV_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return LNV_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    LNV_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return LNV_EHIP;
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
+  return LNV_OK;
+}
+}  // namespace
+
+extern "C" int lnv_bsm_multiply_dot_noalloc(double alpha, const lnv_bsm* A, const lnv_bsm* B,
+                                            int32_t transB, double beta, lnv_bsm* C,
+                                            int32_t store, const lnv_bsm* M1, const lnv_bsm* M2,
+                                            double* out, hipStream_t s) {
+  if (!M1 || !out) return LNV_EINVAL;
+  if (!bsm_ok_any(A) || !bsm_ok_any(B) || !bsm_ok_any(C)) return LNV_EINVAL;
+  if (timing_on()) return LNV_EUNSUPPORTED;   // the timing creates events
+  // every work piece writes its two partials before the reduction reads
+  // them, so nothing in the scratch needs clearing between calls
+  const int64_t need = 2 * (int64_t)multiply_nparts(A, B, transB, C);
+  if (need > LNV_NOALLOC_PARTIALS) return LNV_ECAPACITY;
+  double* part = nullptr;
+  LNV_TRY(scratch_address(&part));
+  return lnv_bsm_multiply_dot(alpha, A, B, transB, beta, C, store, M1, M2, part, out, s);
 }
 
 extern "C" int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* out,

@@ -1029,6 +1029,12 @@ struct Timer {
 };
 Timer g_timer;
 
+}  // namespace
+
+bool timing_on() { return g_timer.on; }
+
+namespace {
+
 int timer_begin(hipStream_t s, hipEvent_t* stop) {
   if (!g_timer.on) return LNV_OK;
   if (g_timer.used == g_timer.ev.size()) {

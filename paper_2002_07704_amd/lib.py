@@ -17,6 +17,7 @@ OK, EINVAL, ECAPACITY, EPATTERN, EHIP, ENUMERIC, EUNSUPPORTED = range(7)
 F64 = 0
 F32 = 1
 DOT_PARTIALS = 1024
+NOALLOC_PARTIALS = 1 << 19
 NSLOTS = 12
 
 # device scalar block indices (LNV_SC_*)
@@ -107,6 +108,8 @@ SIGNATURES = {
     "lnv_bsm_multiply": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_void_p]),
     "lnv_bsm_multiply_dot": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_int32,
                                      PBsm, PBsm, c_void_p, c_void_p, c_void_p]),
+    "lnv_bsm_multiply_dot_noalloc": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm,
+                                             c_int32, PBsm, PBsm, c_void_p, c_void_p]),
     "lnv_bsm_dot": (c_int, [PBsm, PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_partials_len": (c_int64, [c_int32]),
     "lnv_eval": (c_int, [PBsm, PBsm, PBsm, PBsm, PBsm, c_void_p, POINTER(LnvEvalWs), c_void_p]),
