@@ -64,33 +64,64 @@ enum { LNV_F64 = 0, LNV_F32 = 1 };
 #define LNV_MAX_ATOMS 262144
 
 /*
+ * Spatial index of a pattern: where block (i, j) is stored, found in O(1)
+ * with memory linear in the number of rows.  The paper's linear-scaling
+ * multiplies rest on locality: a block exists only for atoms within the
+ * matrix's range (Sec. II.C.2), so the columns of a row lie in the cells of
+ * space near the row's own cell.  The periodic box is cut into g[0] x g[1] x
+ * g[2] cells (lnv_cells); every unit (a row, or with qs = 2 an atom of four
+ * rows, see below) gets its cell (packed x | y << 10 | z << 20) and its slot,
+ * the rank of the unit among the units of its cell (at most occ per cell).
+ * A pattern's window is the box of cells within r[a] of a row's cell along
+ * each axis (r the largest offset any block of the pattern has; w[a] =
+ * min(2 r[a] + 1, g[a]) cells), and its table holds, per row unit, one entry
+ * per (window cell, slot):
+ *   d_a  = (cell_a(j) - cell_a(i) + r_a) mod g_a     (valid iff d_a < w_a)
+ *   pos(i, j) = tab[unit(i) * stride + ((d_0 w_1 + d_1) w_2 + d_2) occ + slot(j)]
+ * (-1: no block), stride = w_0 w_1 w_2 occ.  With qs = 2 the units are the
+ * atoms of a tile4 pattern (4 rows with the same columns, in aligned runs
+ * 4b..4b+3, see lnv_pattern_tile4): the table holds the position of block
+ * (4a, 4b), and block (4a + s, 4b + t) is at that + s * len + t, len the
+ * length of the atom's rows.  One cell (g = 1, 1, 1) makes the table the
+ * dense n x n one; cells of about the shortest range keep it a few times
+ * the pattern's own size.
+ */
+typedef struct lnv_index {
+  const int32_t* tab;      /* device [n_units * stride + 1] (last entry -1) or NULL */
+  const int32_t* cell;     /* device [n_units]: packed cell of each unit */
+  const int32_t* slot;     /* device [n_units]: rank of each unit in its cell */
+  int32_t g[3];            /* cells along each axis (each <= 1024) */
+  int32_t r[3];            /* window half widths, cells */
+  int32_t w[3];            /* window widths, min(2 r + 1, g) */
+  int32_t occ;             /* largest number of units in one cell */
+  int32_t qs;              /* log2 of rows per unit: 0 (rows) or 2 (atoms of 4 rows) */
+  int64_t stride;          /* table entries per unit, w0 w1 w2 occ */
+} lnv_index;
+
+/*
  * Atom-block sparsity pattern.  row_ptr/col is CSR over atoms with columns
- * ascending in each row.  The optional index tables make a block findable in
- * O(1): lut[i*n + j] is the position of block (i, j) or -1, lut_t[i*n + j] is
- * the position of block (j, i) or -1 (n*n int32 each: 64 MiB at 4096 atoms,
- * 1 GiB at 16384 -- the HBM of one MI355X holds them with room to spare).
- * items lists the work pieces of the row-parallel kernels: item q covers row
- * items[2q] from position items[2q+1] for up to 64 blocks (never past the
- * end of the row).
+ * ascending in each row.  The optional index ix (lnv_pattern_index) finds a
+ * block in O(1).  items lists the work pieces of the row-parallel kernels:
+ * item q covers row items[2q] from position items[2q+1] for up to 64 blocks
+ * (never past the end of the row).
  *
  * Cluster plan (optional; used by the multiply when both A and C carry one
  * with the same cl_m): rows are grouped into clusters of cl_m consecutive
  * atoms (consecutive atoms are spatial neighbours when atoms are numbered
  * cell by cell), and for each cluster c the sorted union of its rows'
  * columns is cl_col[cl_ptr[c] .. cl_ptr[c+1]); cl_pos[t*cl_m + r] is the
- * position of block (c*cl_m + r, cl_col[t]) or -1.  As the left operand A
- * this is the contraction list of a cluster; as the output C its columns
- * are split into work pieces of 64/cl_g columns, cl_items[2q] = cluster,
- * cl_items[2q+1] = first position in cl_col.
+ * position of block (c*cl_m + r, cl_col[t]) or -1, and cl_cell[2t],
+ * cl_cell[2t+1] the packed cell and the slot of column cl_col[t]'s unit in
+ * the pattern's index (the contraction's k when P is the left operand).  As
+ * the left operand A this is the contraction list of a cluster; as the
+ * output C its columns are split into work pieces of 64/cl_g columns,
+ * cl_items[2q] = cluster, cl_items[2q+1] = first position in cl_col.
  *
  * Atom tiles: atoms with 13 support functions are stored as 4 consecutive
  * 4x4-blocked rows (see lnv_synth_blocks), so an atom pair is a dense 16x16
- * tile.  With 16-row cluster plans (cl_m = 16: 4 such atoms) on A and C,
- * tile4 = 1 on A and B and tile4 >= 1 on C, the multiply forms whole
- * 16x16x16 atom products on the matrix cores (lnv_pattern_cluster,
- * lnv_pattern_tile4); with 16-row plans on other patterns (4-function
- * atoms) it multiplies 16x16 tiles of 4 x 4 atom blocks (16 atoms per
- * wavefront).
+ * tile.  With 16-row cluster plans (cl_m = 16: 4 such atoms) on A and C and
+ * tile4 = 1 on A, B and C, the multiply forms whole 16x16x16 atom products
+ * on the matrix cores (lnv_pattern_cluster, lnv_pattern_tile4).
  */
 typedef struct lnv_pattern {
   int32_t n;               /* atoms (block rows = block columns) */
@@ -98,17 +129,17 @@ typedef struct lnv_pattern {
   int64_t nnzb;            /* stored blocks */
   const int32_t* row_ptr;  /* device [n+1] */
   const int32_t* col;      /* device [nnzb] */
-  const int32_t* lut;      /* device [n*n] or NULL */
-  const int32_t* lut_t;    /* device [n*n] or NULL */
+  lnv_index ix;            /* spatial index (ix.tab == NULL: none) */
   const int32_t* items;    /* device [2*n_items] or NULL */
   int32_t cl_m;            /* rows per cluster (0: no cluster plan) */
-  int32_t cl_g;            /* lanes sharing one output column (1 or 2) */
+  int32_t cl_g;            /* lanes sharing one output column (1, or 4 and 8 for tiles) */
   int32_t n_cl_items;      /* entries of cl_items */
-  int32_t tile4;           /* grade from lnv_pattern_tile4 (1 tile4, 2 tile-complete, 0) */
+  int32_t tile4;           /* grade from lnv_pattern_tile4 (1 tile4, 0 not) */
   const int32_t* cl_ptr;   /* device [ceil(n/cl_m)+1] */
   const int32_t* cl_col;   /* device [cl_ptr[last]] */
   const int32_t* cl_pos;   /* device [cl_ptr[last]*cl_m] */
   const int32_t* cl_items; /* device [2*n_cl_items] */
+  const int32_t* cl_cell;  /* device [2*cl_ptr[last]] */
 } lnv_pattern;
 
 /* Block-sparse matrix: a pattern (host descriptor) plus block values. */
@@ -174,53 +205,77 @@ int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B, const lnv_patt
                       const int32_t* row_fun, int64_t* flops_out, hipStream_t s);
 
 /* lnv_pattern_half -- the half of a symmetric pattern P that holds each pair
- * {i, j} once, balanced over the rows: rows are grouped in fours (singly when
- * n is not a multiple of 4); block (i, j) is kept when i and j fall in one
- * group and j >= i, or, for groups A != B of m groups, when the cyclic offset
- * D = (B - A) mod m has 2D < m (ties 2D = m: A < B).  Every row keeps about
- * half of its columns (the upper triangle j >= i of a periodic cell keeps
- * nearly all of an early row's columns and few of a late one's, which leaves
- * the multiply's last wave of work pieces nearly empty), and atoms stored as
- * 4 rows keep or drop whole 16x16 tiles.  Columns ascending; two-phase like
- * lnv_neighbours (col == NULL counts).  Synchronises s. */
+ * {i, j} of different row groups once, balanced over the rows: rows are
+ * grouped in fours (singly when n is not a multiple of 4); block (i, j) is
+ * kept when i and j fall in one group (both orders: a symmetric product
+ * formed on the half then has both (i, j) and (j, i) of a group, which its
+ * mirror averages), or, for groups A != B of m groups, when the cyclic
+ * offset D = (B - A) mod m has 2D < m (ties 2D = m: A < B).  Every row keeps
+ * about half of its columns (the upper triangle j >= i of a periodic cell
+ * keeps nearly all of an early row's columns and few of a late one's, which
+ * leaves the multiply's last wave of work pieces nearly empty), and atoms
+ * stored as 4 rows keep or drop whole 16x16 tiles, so the half of a tile4
+ * pattern is tile4.  Columns ascending; two-phase like lnv_neighbours
+ * (col == NULL counts).  Synchronises s. */
 int lnv_pattern_half(const lnv_pattern* P, int32_t* row_ptr, int32_t* col, int64_t cap,
                      int64_t* nnz_out, hipStream_t s);
 
-/* lnv_pattern_lut -- fill the index tables of P (either may be NULL). */
-int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t, hipStream_t s);
+/* lnv_cells -- the cells of the spatial index (see lnv_index): n_units
+ * positions (device [n_units][3], FP64, in the periodic box, host [3]), the
+ * grid g (host [3], each 1..1024) and the grid's origin (host [3]); unit u
+ * lies in cell floor(frac(((x - origin) / box)) * g) per axis, and its slot
+ * is its rank among the units of that cell in unit order.  Writes cell and
+ * slot (device [n_units]) and *occ_out (host: the fullest cell's count).
+ * Set-up call: copies the positions to the host, synchronises s. */
+int lnv_cells(const double* pos, int32_t n_units, const double* box, const int32_t* g,
+              const double* origin, int32_t* cell, int32_t* slot, int32_t* occ_out,
+              hipStream_t s);
+
+/* lnv_pattern_index -- the spatial index of P (see lnv_index) on the cells
+ * (cell, slot: device [n >> qs], from lnv_cells over P's units; g, occ as
+ * lnv_cells gave them).  qs = 2 needs a tile4 pattern (lnv_pattern_tile4).
+ * Two-phase: with tab == NULL only the window is measured -- P->ix is filled
+ * (r, w, stride, cell, slot, g, occ, qs; tab NULL) and *len_out (host) is
+ * the table's length, n_units * stride + 1 (a trailing -1 that lookups
+ * outside the window may read); then with tab (device [cap]) the
+ * table is written and P->ix.tab set (LNV_ECAPACITY if cap < *len_out).
+ * Synchronises s. */
+int lnv_pattern_index(lnv_pattern* P, const int32_t* cell, const int32_t* slot,
+                      const int32_t* g, int32_t occ, int32_t qs, int32_t* tab, int64_t cap,
+                      int64_t* len_out, hipStream_t s);
 
 /* lnv_pattern_transpose_map -- perm[p] = position in PT of the transpose of
- * block p of P (PT must hold the transposed pattern and have its lut);
+ * block p of P (PT must hold the transposed pattern and have its index);
  * LNV_EPATTERN when a block has no transpose in PT. */
 int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT, int32_t* perm,
                               hipStream_t s);
 
 /* lnv_pattern_cluster -- cluster plan of P (see lnv_pattern) for clusters of
- * m rows with g lanes per output column, each lane accumulating 4 rows:
- * (m, g) = (4, 1) or (8, 2); or atom-tile plans, m = 16 (4 atoms of 4 rows)
- * with pieces of 64/g = 16 or 8 union columns (4 or 2 column atoms per
- * wavefront), (m, g) = (16, 4) or (16, 8).  The atom-tile multiply needs the
- * unions in aligned runs of 4 columns, which holds for tile4 patterns and
- * for the halves (lnv_pattern_half) of symmetric tile4 patterns.  P needs lut.  Two-phase like lnv_neighbours: with
- * cl_col == NULL only *len_out (union length) and *n_items_out are
- * reported; cl_ptr is always written (device [ceil(n/m)+1]).  Synchronises s. */
+ * m rows with g lanes per output column: (m, g) = (4, 1), one lane per
+ * column accumulating the cluster's 4 rows; or atom-tile plans, m = 16 (4
+ * atoms of 4 rows) with pieces of 64/g = 16 or 8 union columns (4 or 2
+ * column atoms per wavefront), (m, g) = (16, 4) or (16, 8), whose unions
+ * come in aligned runs of 4 columns (tile4 patterns).  P needs its index
+ * (the positions and cells come from it).  Two-phase like lnv_neighbours:
+ * with cl_col == NULL only *len_out (union length) and *n_items_out are
+ * reported; cl_ptr is always written (device [ceil(n/m)+1]); cl_cell (device
+ * [2*cap]) receives the packed cell and slot of each union column.
+ * Synchronises s. */
 int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_ptr,
-                        int32_t* cl_col, int32_t* cl_pos, int64_t cap, int32_t* cl_items,
-                        int64_t items_cap, int64_t* len_out, int32_t* n_items_out,
-                        hipStream_t s);
+                        int32_t* cl_col, int32_t* cl_pos, int32_t* cl_cell, int64_t cap,
+                        int32_t* cl_items, int64_t items_cap, int64_t* len_out,
+                        int32_t* n_items_out, hipStream_t s);
 
-/* lnv_pattern_tile4 -- grade of P for the atom-tile multiply, in *ok_out
- * (host): 1 when P is a tile4 pattern: n is a multiple of 4, rows 4a..4a+3
- * hold the same columns, and every row's columns come in aligned runs 4b,
- * 4b+1, 4b+2, 4b+3 -- the layout of atoms stored as 4 rows each with
- * patterns built from atom distances; then the 16 blocks of an atom tile are
- * found from the position p of its first one as p + s*len + t (sub-row s,
- * sub-column t, len the row length), as operands need.  2 when P is only
- * tile-complete (as outputs need): a column c in any row r brings the whole
- * run (c & ~3) .. (c & ~3) + 3 into row r & ~3 -- the halves of symmetric
- * tile4 patterns (lnv_pattern_half).  0 otherwise (4-function atoms, mixed
- * atom sizes).  The value belongs in lnv_pattern.tile4.  Set-up call:
- * allocates flags, synchronises s. */
+/* lnv_pattern_tile4 -- grade of P for the atom-tile multiply and the atom
+ * index (qs = 2), in *ok_out (host): 1 when P is a tile4 pattern: n is a
+ * multiple of 4, rows 4a..4a+3 hold the same columns, and every row's
+ * columns come in aligned runs 4b, 4b+1, 4b+2, 4b+3 -- the layout of atoms
+ * stored as 4 rows each with patterns built from atom distances, their
+ * products and the halves of symmetric ones (lnv_pattern_half); then the 16
+ * blocks of an atom tile are found from the position p of its first one as
+ * p + s*len + t (sub-row s, sub-column t, len the row length).  0 otherwise
+ * (4-function atoms, mixed atom sizes).  The value belongs in
+ * lnv_pattern.tile4.  Set-up call: allocates flags, synchronises s. */
 int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStream_t s);
 
 /* lnv_pattern_items -- work list of P: with items == NULL only counts.
@@ -260,7 +315,7 @@ int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
  * lnv_bsm_multiply -- C = alpha * A * op(B) + beta * C on C's pattern only
  * (blocks of the product outside C's pattern are not formed: a range
  * truncated product).  op(B) = B (transB = 0) or B^T (transB = 1).
- * Needs A.row_ptr/col, B.lut (transB = 0) or B.lut_t (transB = 1) and C.items.
+ * Needs A.row_ptr/col, B's spatial index (either orientation) and C.items.
  * A, B and C share one dtype: FP64, or FP32 with FP32 products and FP32
  * accumulation (LNV_EUNSUPPORTED for a mix).  Hot path: allocates nothing.
  */
@@ -270,9 +325,7 @@ int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t t
 /* lnv_bsm_multiply_dot -- as lnv_bsm_multiply, and in the same pass
  * out[d] = <M_d, C> for the given partners M_1, M_2 (NULL to skip; both on
  * C's pattern); with store == 0 the finished product is not written back
- * (only the traces are wanted), but C.val still serves as scratch for partial
- * sums when the contraction is split into slabs (see lnv_set_kslabs), so it
- * must be a writable buffer of C's size.  partials: device
+ * (only the traces are wanted; C.val is not touched).  partials: device
  * [2 * max(C.n_items, C.n_cl_items)] scratch; out: device.
  */
 int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
@@ -318,7 +371,7 @@ int lnv_bsm_lincomb(double a, const lnv_bsm* X, double b, const lnv_bsm* Y, doub
 
 /* lnv_bsm_remap -- B = A carried over to B's pattern (same atoms, e.g. the
  * range pattern of a new geometry): blocks of B present in A's pattern are
- * copied, the others are zero.  A's pattern needs lut.  FP64, blk 4. */
+ * copied, the others are zero.  A's pattern needs its index.  FP64, blk 4. */
 int lnv_bsm_remap(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
 
 /* lnv_bsm_norm_inf -- out[0] = max_a sum_b |A_ab| (the matrix infinity norm,
@@ -340,16 +393,9 @@ int lnv_bsm_norm_inf(const lnv_bsm* A, double* partials, double* out, hipStream_
 enum { LNV_ACC_F32 = 0, LNV_ACC_F64 = 1, LNV_ACC_F16X3 = 2 };
 int lnv_set_f32_accumulation(int32_t acc);
 
-/* lnv_set_kslabs -- split every multiply's contraction index k into n
- * atom-index slabs, one launch per slab accumulating into C (n <= 0: the
- * default, a single launch; the atom-tile multiply always runs whole).
- * Trace-only products (multiply_dot with store == 0) then use C's buffer
- * for the partial sums.  Process-wide setting. */
-int lnv_set_kslabs(int32_t n);
-
 /* lnv_bsm_dot -- <A, B> = sum over A's blocks of A_ij . B_ij (Frobenius),
  * with B_ij taken at the same position when B shares A's pattern object,
- * otherwise through B.lut (absent blocks count as zero).
+ * otherwise through B's spatial index (absent blocks count as zero).
  * partials: device [LNV_DOT_PARTIALS] scratch; out: device [1].  Hot path.
  */
 #define LNV_DOT_PARTIALS 1024
@@ -366,11 +412,11 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  *   F = dN/dL = 12 P_L[Z - A^T Z]
  * which follow from K = 3LSL - 2LSLSL and E = 2 Tr[KH] (Sec. II.C.2) by
  * differentiating each stored entry of L.
- *  SL  values on pat(S.L)   (pattern needs items; lut for the metric)
- *  LS  values on pat(L.S)   (pattern needs lut)
- *  X   values on pat(H.L.S) (pattern needs lut and items)
- *  XT  values on pat(S.L.H) (pattern needs lut)
- *  Z   values on pat(S.L.S) (pattern needs lut and items)
+ *  SL  values on pat(S.L)   (pattern needs items; its index for the metric)
+ *  LS  values on pat(L.S)   (pattern needs its index)
+ *  X   values on pat(H.L.S) (pattern needs its index and items)
+ *  XT  values on pat(S.L.H) (pattern needs its index)
+ *  Z   values on pat(S.L.S) (pattern needs its index and items)
  *  perm_SL, perm_X  transpose maps SL -> LS and X -> XT
  * Every operand B of the products is read in its stored orientation: a
  * transposed read would gather 64 blocks from 64 distant rows per step.
@@ -382,7 +428,7 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  * and V = P_L(SLSLS) are symmetric for symmetric L, S, H, so only their
  * blocks in one half of their pattern need forming; the rest is their
  * transpose.
- *  Zu  values on the half of Z's pattern (lnv_pattern_half; needs lut,
+ *  Zu  values on the half of Z's pattern (lnv_pattern_half; needs its index,
  *      items, and the cluster plan of the other outputs), dtype of Z
  *  Lu  values on the half of L's pattern (same needs): W's blocks there;
  *      Vu (device [nnzb of Lu * 16], dtype of W) V's
@@ -455,7 +501,7 @@ enum {
 /*
  * lnv_eval -- E, N (written to EN[0], EN[1], device, and to
  * scalars[LNV_SC_E/N]), G = dE/dL and F = dN/dL on L's pattern.  L, S, H,
- * G, F are FP64 with blk 4; L's pattern needs lut and items, S's needs lut.
+ * G, F are FP64 with blk 4; L's pattern needs its index and items, S's needs its index.
  * Hot path: allocates nothing, no host synchronisation.
  */
 int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
@@ -541,11 +587,11 @@ int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm
  * (dE/dL is lnv_eval's G).  L, S and H must be symmetric and stored in both
  * triangles, as for lnv_eval.  The natural-range intermediates are formed
  * anew on every call (nothing is carried over from lnv_eval):
- *  SL   values on pat(S.L)   (pattern needs lut and items)
+ *  SL   values on pat(S.L)   (pattern needs its index and items)
  *  LSL  values on pat(L.S.L) (pattern needs items)
- *  HL   values on pat(H.L)   (pattern needs lut and items; used only for dS)
+ *  HL   values on pat(H.L)   (pattern needs its index and items; used only for dS)
  *  YS   device [nnzb_S * 16] scratch (used only for dS)
- * dS is on S's pattern (needs lut and items), dH on H's pattern (needs
+ * dS is on S's pattern (needs its index and items), dH on H's pattern (needs
  * items); dNS = dN/dS = 12 P_S(LSL - LSLSL) on S's pattern (N = 2 Tr[KS],
  * for forces under the electron-number constraint).  Any of the three may be
  * NULL, not all.  FP64, blk 4.  Hot path: allocates nothing, no host
@@ -557,7 +603,7 @@ int lnv_eval_mixed(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm
  *  LSLu  values on the half of pat(L.S.L)
  *  Hu    values on the half of H's pattern
  *  Su    values on the half of S's pattern
- * (each half pattern with lut, items and the cluster plan of the other
+ * (each half pattern with its index, items and the cluster plan of the other
  * outputs).
  */
 typedef struct lnv_adj_ws {
@@ -574,7 +620,7 @@ typedef struct lnv_adj_ws {
    * products put the shorter range on the left: P_H(LS.LSL) for P_H(LSL.SL)
    * (the same matrix L S L S L) and P_S(LH.LSL) = Y^T for Y = P_S(LSL.HL)
    * (dS takes Y + Y^T), so the contraction runs over LS's or LH's rows with
-   * the natural-range L.S.L on the right, whose pattern then needs lut; the
+   * the natural-range L.S.L on the right, whose pattern then needs its index; the
    * left patterns need items (and the cluster plans of the other left
    * operands). */
   lnv_bsm LS;
@@ -597,7 +643,7 @@ int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* d
  * fixed L; with GNS = dN/dS and mu the chemical potential of a minimum under
  * N = N_e, the force of that constrained minimum.  GNS may be NULL.
  *  pos, box, nfun, atom_of, off_of, seed, scale: as given to lnv_synth_blocks
- *  GS, GNS on S's pattern, GH on H's pattern (FP64; patterns need lut)
+ *  GS, GNS on S's pattern, GH on H's pattern (FP64; patterns need index)
  *  seg_ptr, seg_atom (device [n_seg+1], [n_seg]): atom seg_atom[s] owns the
  *      stored rows seg_ptr[s] .. seg_ptr[s+1]-1
  *  acc: device [3 n] scratch;  F: device [3 n_atoms] output (Hartree/bohr)
@@ -634,7 +680,7 @@ int lnv_cg_check(const double* scalars, int32_t* status_out, hipStream_t s);
  * stated).  gc/gc_prev (metric runs) or g/gc_prev (identity metric) and
  * D/D_prev are swapped by lnv_cg_step after each step.
  *  LL  values on pat(L.L) (pattern needs items): G T and F T of the metric
- *      products P_L(T (G T)), P_L(T (F T)) when the pattern has lut (T G and
+ *      products P_L(T (G T)), P_L(T (F T)) when the pattern has its index (T G and
  *      T F of P_L((T G) T) otherwise: the same triples, but the restricted
  *      product then contracts over the long rows of T G).  May share memory
  *      with ev.XT (dead at that point) when pat(L.L) has no more blocks than
@@ -668,7 +714,7 @@ typedef struct lnv_opts {
    * FP32 product for the line search.  With a metric, P_L(T G T) and
    * P_L(T F T) (the preconditioner) are formed in FP32 as well, in the
    * workspace's buffers after the evaluation has used them (its pattern of
-   * X must hold pat(L.L), which then needs lut, and Lu, Vu must be set;
+   * X must hold pat(L.L), which then needs its index, and Lu, Vu must be set;
    * otherwise they stay FP64).  The line search, the electron-number check
    * and correction stay FP64. */
   const struct lnv_eval32_ws* eval32;
@@ -684,12 +730,12 @@ typedef struct lnv_opts {
 
 /*
  * lnv_hotelling -- sparse approximate inverse of the overlap on T's pattern,
- * (identity of the orbitals present, as in lnv_cg_init; S's pattern needs lut),
+ * (identity of the orbitals present, as in lnv_cg_init; S's pattern needs its index),
  * the metric of the minimisation (Sec. II.C.2 uses an approximate sparse
  * S^-1 from Hotelling's iteration):  T0 = sigma I with
  * sigma = 1 / max_a sum_b |S_ab| (a Gershgorin bound, so ||I - T0 S|| < 1),
  * T_{n+1} = P_T(2 T_n - T_n S T_n), n_iter steps.  T's pattern (L's in the
- * CG) needs lut and items; scratch: ws->ev.SL (pattern pat(S.T) with lut and
+ * CG) needs its index and items; scratch: ws->ev.SL (pattern pat(S.T) with its index and
  * items), ws->Gc, ws->ev.partials, ws->ev.scalars (sigma in LNV_SC_SIGMA).
  */
 int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, hipStream_t s);
@@ -702,7 +748,7 @@ int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, h
  * start used here.  Writes L and scalars[LNV_SC_LAMBDA].  The identity is
  * that of the orbitals present: diagonal entries whose S_aa is zero (padded
  * rows, see lnv_synth_blocks) are left at zero, and so stay zero through the
- * CG (their gradient vanishes).  S's pattern needs lut.
+ * CG (their gradient vanishes).  S's pattern needs its index.
  */
 int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, lnv_cg_ws* ws,
                 hipStream_t s);

@@ -1,8 +1,8 @@
 """Work-decomposition autotuner for the block multiply.
 
 The multiply's one tunable is the row-cluster shape of its output-stationary
-work decomposition (how many output rows a wavefront accumulates per
-gathered right-operand block, and how many lanes share a column), and, for
+work decomposition (4-row clusters, one lane per output column, or one row
+per wavefront), and, for
 cells whose atoms all carry 13 support functions (4 stored rows each), the
 atom-tile shapes that multiply whole 16x16 atom tiles on the matrix cores.
 Which one is fastest depends on the register budget of the value type, the
@@ -18,7 +18,7 @@ import time
 
 import torch
 
-CANDIDATES = ((4, 1), (8, 2), None)
+CANDIDATES = ((4, 1), None)
 _CACHE: dict = {}
 
 

@@ -36,7 +36,7 @@ namespace {
 __global__ __launch_bounds__(256) void k_sym_update(int n, const int* __restrict__ items,
                                                     const int* __restrict__ rp,
                                                     const int* __restrict__ col,
-                                                    const int* __restrict__ lut,
+                                                    Ix x,
                                                     const double* __restrict__ Y, double c,
                                                     double* __restrict__ dS) {
   const int item = blockIdx.x;
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_sym_update(int n, const int* __restrict
   const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
   if (b >= cnt) return;
   const int p = c0 + b;
-  const int q = lut[(size_t)col[p] * n + i];
+  const int q = ix_find(x, col[p], i);
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const double yt = q >= 0 ? Y[(size_t)q * 16 + k * 4 + r] : 0.0;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_sym_update(int n, const int* __restrict
 }
 
 bool has(const lnv_pattern* p, bool lut, bool items) {
-  return p && p->row_ptr && p->col && (!lut || p->lut) && (!items || p->items);
+  return p && p->row_ptr && p->col && (!lut || has_ix(p)) && (!items || p->items);
 }
 
 int check_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* dS,
@@ -86,13 +86,13 @@ int check_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const ln
   if (ws->LS.val) {
     if (!bsm_ok(&ws->LS) || !ws->perm_SL) return LNV_EINVAL;
     if (ws->LS.blk != 4) return LNV_EUNSUPPORTED;
-    if (ws->LS.pat->n != n || !has(ws->LS.pat, false, false) || !ws->LSL.pat->lut)
+    if (ws->LS.pat->n != n || !has(ws->LS.pat, false, false) || !has_ix(ws->LSL.pat))
       return LNV_EPATTERN;
   }
   if (ws->LH.val && dS) {
     if (!bsm_ok(&ws->LH) || !ws->perm_HL) return LNV_EINVAL;
     if (ws->LH.blk != 4) return LNV_EUNSUPPORTED;
-    if (ws->LH.pat->n != n || !has(ws->LH.pat, false, false) || !ws->LSL.pat->lut)
+    if (ws->LH.pat->n != n || !has(ws->LH.pat, false, false) || !has_ix(ws->LSL.pat))
       return LNV_EPATTERN;
   }
   return LNV_OK;
@@ -157,7 +157,7 @@ extern "C" int lnv_adjoint(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
                               s));
     }
     if (ps->n_items > 0) {
-      k_sym_update<<<ps->n_items, 256, 0, s>>>(ps->n, ps->items, ps->row_ptr, ps->col, ps->lut,
+      k_sym_update<<<ps->n_items, 256, 0, s>>>(ps->n, ps->items, ps->row_ptr, ps->col, make_ix(ps),
                                                ws->YS, -4.0, static_cast<double*>(dS->val));
       LNV_LAUNCH_CHECK();
     }

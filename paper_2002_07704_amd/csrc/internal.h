@@ -68,21 +68,95 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // ---------------------------------------------------------------- symmetric halves
-// Half of a symmetric pattern holding each pair {r, c} once, balanced over the
-// rows.  Rows are grouped in fours (singly when n is not a multiple of 4); in
-// one group the block is kept when c >= r; for groups A != B (m groups) when
-// the cyclic group offset D = (B - A) mod m has 2D < m, ties 2D = m by A < B.
+// Half of a symmetric pattern holding each pair {r, c} of different row groups
+// once, balanced over the rows.  Rows are grouped in fours (singly when n is
+// not a multiple of 4); inside one group every block is kept (both (r, c) and
+// (c, r), which the mirror averages); for groups A != B (m groups) when the
+// cyclic group offset D = (B - A) mod m has 2D < m, ties 2D = m by A < B.
 // Every row keeps about half of its columns (the plain upper triangle c >= r
 // keeps nearly all of an early row's columns and few of a late row's), and an
 // atom stored as 4 rows keeps or drops a whole 4x4-blocked tile with another
-// atom.
+// atom, so the half of a tile4 pattern is tile4.
 __host__ __device__ inline bool in_half(int n, int r, int c) {
   const int g = (n & 3) == 0 ? 2 : 0;
   const int A = r >> g, B = c >> g, m = n >> g;
-  if (A == B) return c >= r;
+  if (A == B) return true;
   int D = B - A;
   if (D < 0) D += m;
   return 2 * D < m || (2 * D == m && A < B);
+}
+
+// Whether rows r and c fall in one group of the half's row grouping (then
+// both (r, c) and (c, r) are in the half).
+__host__ __device__ inline bool same_group(int n, int r, int c) {
+  const int g = (n & 3) == 0 ? 2 : 0;
+  return (r >> g) == (c >> g);
+}
+
+// ---------------------------------------------------------------- spatial index
+// Kernel-side view of a pattern's lnv_index (passed by value).
+struct Ix {
+  const int* tab;
+  const int* cell;
+  const int* slot;
+  const int* rp;      // the pattern's row_ptr (sub-row offsets of atom units)
+  int g0, g1, g2, r0, r1, r2, w0, w1, w2, occ, qs;
+  long long stride;
+  long long sent;     // index of the table's trailing -1 entry (n_units * stride)
+};
+
+inline Ix make_ix(const lnv_pattern* p) {
+  const lnv_index& x = p->ix;
+  Ix v;
+  v.tab = x.tab;
+  v.cell = x.cell;
+  v.slot = x.slot;
+  v.rp = p->row_ptr;
+  v.g0 = x.g[0]; v.g1 = x.g[1]; v.g2 = x.g[2];
+  v.r0 = x.r[0]; v.r1 = x.r[1]; v.r2 = x.r[2];
+  v.w0 = x.w[0]; v.w1 = x.w[1]; v.w2 = x.w[2];
+  v.occ = x.occ;
+  v.qs = x.qs;
+  v.stride = x.stride;
+  v.sent = (long long)(p->n >> x.qs) * x.stride;
+  return v;
+}
+
+inline bool has_ix(const lnv_pattern* p) { return p && p->ix.tab != nullptr; }
+
+// Wrapped window coordinate of cell coordinate cb seen from ca (both in
+// [0, g)), r <= g - 1: in [0, g), valid when below the window width w.
+__device__ __forceinline__ int ix_axis(int cb, int ca, int r, int g) {
+  int d = cb - ca + r;
+  d += d < 0 ? g : 0;
+  d -= d >= g ? g : 0;
+  return d;
+}
+
+// Offset in a row unit's table of the unit with packed cell cb and slot sb,
+// seen from a row unit in packed cell ca; -1 outside the window.
+__device__ __forceinline__ int ix_off(const Ix& x, int ca, int cb, int sb) {
+  const int d0 = ix_axis(cb & 1023, ca & 1023, x.r0, x.g0);
+  const int d1 = ix_axis((cb >> 10) & 1023, (ca >> 10) & 1023, x.r1, x.g1);
+  const int d2 = ix_axis(cb >> 20, ca >> 20, x.r2, x.g2);
+  if (d0 >= x.w0 || d1 >= x.w1 || d2 >= x.w2) return -1;
+  return ((d0 * x.w1 + d1) * x.w2 + d2) * x.occ + sb;
+}
+
+// Position of the block of unit row a, unit column b (the block of their
+// first rows), or -1.
+__device__ __forceinline__ int ix_unit(const Ix& x, int a, int b) {
+  const int o = ix_off(x, x.cell[a], x.cell[b], x.slot[b]);
+  return o < 0 ? -1 : x.tab[(size_t)a * x.stride + o];
+}
+
+// Position of block (i, j), or -1.
+__device__ __forceinline__ int ix_find(const Ix& x, int i, int j) {
+  const int e = ix_unit(x, i >> x.qs, j >> x.qs);
+  if (e < 0 || x.qs == 0) return e;
+  const int m = (1 << x.qs) - 1;
+  const int i0 = i & ~m;
+  return e + (i & m) * (x.rp[i0 + 1] - x.rp[i0]) + (j & m);
 }
 
 // ---------------------------------------------------------------- checks

@@ -330,11 +330,11 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
 template <typename T>
 __global__ __launch_bounds__(256) void k_assemble(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
-    const int* __restrict__ col, const int* __restrict__ l_lut,
-    const double* __restrict__ L, const int* __restrict__ x_lut,
-    const T* __restrict__ X, const int* __restrict__ xt_lut,
+    const int* __restrict__ col, Ix lx,
+    const double* __restrict__ L, Ix xx,
+    const T* __restrict__ X, Ix xtx,
     const T* __restrict__ XT, const T* __restrict__ YT,
-    const T* __restrict__ Wv, const int* __restrict__ z_lut,
+    const T* __restrict__ Wv, Ix zx,
     const T* __restrict__ Z, const T* __restrict__ V, double* __restrict__ G,
     double* __restrict__ F, double* __restrict__ partials) {
   __shared__ double sh[16];
@@ -346,15 +346,17 @@ __global__ __launch_bounds__(256) void k_assemble(
   if (b < cnt) {
     const int p = c0 + b;
     const int j = col[p];
-    const int xp = x_lut[(size_t)i * n + j];
-    const int xtp = xt_lut[(size_t)i * n + j];
-    const int ytp = l_lut[(size_t)j * n + i];
-    const int zp = z_lut[(size_t)i * n + j];
+    const int xp = ix_find(xx, i, j);
+    // X^T_ij: stored, or block (j, i) of X transposed
+    const int xtp = XT ? ix_find(xtx, i, j) : ix_find(xx, j, i);
+    const T* __restrict__ xtv = XT ? XT : X;
+    const int ytp = ix_find(lx, j, i);
+    const int zp = ix_find(zx, i, j);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int e = r * 4 + c, et = c * 4 + r;
       const double x = xp >= 0 ? (double)X[(size_t)xp * 16 + e] : 0.0;
-      const double xt = xtp >= 0 ? (double)XT[(size_t)xtp * 16 + e] : 0.0;
+      const double xt = xtp >= 0 ? (double)xtv[(size_t)xtp * 16 + (XT ? e : et)] : 0.0;
       const double yt = (double)YT[(size_t)p * 16 + e];
       const double ytt = ytp >= 0 ? (double)YT[(size_t)ytp * 16 + et] : 0.0;
       const double w = (double)Wv[(size_t)p * 16 + e];
@@ -382,7 +384,7 @@ __global__ __launch_bounds__(256) void k_assemble(
 // Electron number at the current L: partials <L,Z>, <L,V>, <12(Z-V), F>, <L,L>.
 __global__ __launch_bounds__(256) void k_nassemble(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
-    const int* __restrict__ col, const double* __restrict__ L, const int* __restrict__ z_lut,
+    const int* __restrict__ col, const double* __restrict__ L, Ix zx,
     const double* __restrict__ Z, const double* __restrict__ V,
     const double* __restrict__ Fc, double* __restrict__ partials) {
   __shared__ double sh[16];
@@ -394,7 +396,7 @@ __global__ __launch_bounds__(256) void k_nassemble(
   if (b < cnt) {
     const int p = c0 + b;
     const int j = col[p];
-    const int zp = z_lut[(size_t)i * n + j];
+    const int zp = ix_find(zx, i, j);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int e = r * 4 + c;
@@ -419,26 +421,25 @@ __global__ __launch_bounds__(256) void k_nassemble(
 // B, 16 threads per block.
 __global__ __launch_bounds__(256) void k_remap(int n, const int* __restrict__ b_rp,
                                                const int* __restrict__ b_col,
-                                               const int* __restrict__ a_lut,
-                                               const double* __restrict__ A,
+                                               Ix ax, const double* __restrict__ A,
                                                double* __restrict__ B) {
   const int i = blockIdx.x;
   const int e = threadIdx.x & 15;
   for (int p = b_rp[i] + (threadIdx.x >> 4); p < b_rp[i + 1]; p += 16) {
-    const int q = a_lut[(size_t)i * n + b_col[p]];
+    const int q = ix_find(ax, i, b_col[p]);
     B[(size_t)p * 16 + e] = q >= 0 ? A[(size_t)q * 16 + e] : 0.0;
   }
 }
 
 // Full symmetric matrix F from the blocks U of its half (in_half): F_ij =
-// U_ij when (i, j) is in the half, U_ji^T otherwise, (U_ii + U_ii^T)/2 on the
-// diagonal; U's blocks are found through U's own lut.  Workgroup per item of
-// F, 4 threads per block (thread r writes row r).
+// U_ij when only (i, j) is in the half, U_ji^T when only (j, i) is, and
+// (U_ij + U_ji^T)/2 when both are (i and j in one row group, the diagonal
+// included), so F is exactly symmetric; U's blocks are found through U's own
+// index.  Workgroup per item of F, 4 threads per block (thread r writes row r).
 template <typename T>
 __global__ __launch_bounds__(256) void k_mirror(int n, const int* __restrict__ items,
                                                 const int* __restrict__ rpF,
-                                                const int* __restrict__ colF,
-                                                const int* __restrict__ lutU,
+                                                const int* __restrict__ colF, Ix ux,
                                                 const T* __restrict__ U, T* __restrict__ F,
                                                 const double* __restrict__ skip) {
   if (skip != nullptr && *skip != 0.0) return;
@@ -449,33 +450,42 @@ __global__ __launch_bounds__(256) void k_mirror(int n, const int* __restrict__ i
   if (b >= cnt) return;
   const int p = c0 + b;
   const int j = colF[p];
+  if (same_group(n, i, j)) {  // both in the half: the symmetric part of the pair
+    const int q = ix_find(ux, i, j), qt = ix_find(ux, j, i);
+    if (q < 0 || qt < 0) {  // F's pattern not symmetric: poison the block
+#pragma unroll
+      for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = T(NAN);
+      return;
+    }
+    const T* u = U + (size_t)q * 16;
+    const T* ut = U + (size_t)qt * 16;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      F[(size_t)p * 16 + r * 4 + c] = T(0.5) * (u[r * 4 + c] + ut[c * 4 + r]);
+    return;
+  }
   const bool tr = !in_half(n, i, j);
-  const int q = tr ? lutU[(size_t)j * n + i] : lutU[(size_t)i * n + j];
+  const int q = tr ? ix_find(ux, j, i) : ix_find(ux, i, j);
   if (q < 0) {  // F's pattern not symmetric: poison the block
 #pragma unroll
     for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = T(NAN);
     return;
   }
   const T* u = U + (size_t)q * 16;
-  if (j == i) {  // diagonal block: its symmetric part (the rest is rounding)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = T(0.5) * (u[r * 4 + c] + u[c * 4 + r]);
-    return;
-  }
 #pragma unroll
   for (int c = 0; c < 4; ++c) F[(size_t)p * 16 + r * 4 + c] = tr ? u[c * 4 + r] : u[r * 4 + c];
 }
 
 // Weighted halves of two matrices on L's (symmetric) pattern: for every block
 // (i, j) of the half in_half, at position q of U's pattern, dst[q] = w src[p]
-// with p its position in the full pattern and w = 1 on the diagonal, 2 off
-// it.  For symmetric X and a symmetric product Q formed only on the half,
-// sum over the half of <dst_q, Q_q> is the full <X, Q>: the blocks left out
-// are the transposes of those kept.
+// with p its position in the full pattern and w = 1 when (j, i) is in the
+// half too (i and j in one row group), 2 otherwise.  For symmetric X and a
+// symmetric product Q formed only on the half, sum over the half of
+// <dst_q, Q_q> is the full <X, Q>: the blocks left out are the transposes of
+// those kept.
 __global__ __launch_bounds__(256) void k_half_weighted(int n, const int* __restrict__ items,
                                                        const int* __restrict__ rpF,
-                                                       const int* __restrict__ colF,
-                                                       const int* __restrict__ lutU,
+                                                       const int* __restrict__ colF, Ix ux,
                                                        const double* __restrict__ src1,
                                                        const double* __restrict__ src2,
                                                        double* __restrict__ dst1,
@@ -490,9 +500,9 @@ __global__ __launch_bounds__(256) void k_half_weighted(int n, const int* __restr
   const int p = c0 + b;
   const int j = colF[p];
   if (!in_half(n, i, j)) return;
-  const int q = lutU[(size_t)i * n + j];
+  const int q = ix_find(ux, i, j);
   if (q < 0) return;  // U's pattern misses a block of the half: checked on the host
-  const double w = j == i ? 1.0 : 2.0;
+  const double w = same_group(n, i, j) ? 1.0 : 2.0;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const size_t e = (size_t)r * 4 + c;
@@ -541,7 +551,7 @@ __global__ __launch_bounds__(256) void k_cell_traces(const double* __restrict__ 
 // <A, B> with B located through B's index table (or at A's positions).
 __global__ __launch_bounds__(256) void k_dot_items(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ rp,
-    const int* __restrict__ col, const double* __restrict__ A, const int* __restrict__ b_lut,
+    const int* __restrict__ col, const double* __restrict__ A, Ix bx, int same,
     const double* __restrict__ B, double* __restrict__ partials,
     const double* __restrict__ skip) {
   __shared__ double sh[16];
@@ -553,7 +563,7 @@ __global__ __launch_bounds__(256) void k_dot_items(
     const int cnt = min(kWave, rp[i + 1] - c0);
     if (b < cnt) {
       const int p = c0 + b;
-      const int q = b_lut ? b_lut[(size_t)i * n + col[p]] : p;
+      const int q = same ? p : ix_find(bx, i, col[p]);
       if (q >= 0)
 #pragma unroll
         for (int c = 0; c < 4; ++c)
@@ -568,8 +578,7 @@ __global__ __launch_bounds__(256) void k_dot_items(
 __global__ __launch_bounds__(256) void k_hprime(int n, const int* __restrict__ items,
                                                 const int* __restrict__ rp,
                                                 const int* __restrict__ col,
-                                                const double* __restrict__ H,
-                                                const int* __restrict__ s_lut,
+                                                const double* __restrict__ H, Ix sx,
                                                 const double* __restrict__ S,
                                                 const double* __restrict__ sc,
                                                 double* __restrict__ Hp) {
@@ -580,7 +589,7 @@ __global__ __launch_bounds__(256) void k_hprime(int n, const int* __restrict__ i
   if (b >= cnt) return;
   const double mu = sc[LNV_SC_MU];
   const int p = c0 + b;
-  const int q = s_lut[(size_t)i * n + col[p]];
+  const int q = ix_find(sx, i, col[p]);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int e = r * 4 + c;
@@ -595,8 +604,7 @@ __global__ __launch_bounds__(256) void k_hprime(int n, const int* __restrict__ i
 // minimisation never moves such rows.  v = sc[idx] (sc == nullptr: 1).
 __global__ __launch_bounds__(256) void k_identity(int n, const int* __restrict__ items,
                                                   const int* __restrict__ rp,
-                                                  const int* __restrict__ col,
-                                                  const int* __restrict__ s_lut,
+                                                  const int* __restrict__ col, Ix sx,
                                                   const double* __restrict__ S,
                                                   const double* __restrict__ sc, int idx,
                                                   double* __restrict__ D) {
@@ -610,7 +618,7 @@ __global__ __launch_bounds__(256) void k_identity(int n, const int* __restrict__
   const double v = sc ? sc[idx] : 1.0;
   bool present = false;
   if (diag) {
-    const int q = s_lut[(size_t)i * n + i];
+    const int q = ix_find(sx, i, i);
     present = q >= 0 && S[(size_t)q * 16 + r * 5] != 0.0;
   }
 #pragma unroll
@@ -815,9 +823,10 @@ void add(RedList& rl, int64_t off, int count, int stride, int dst, int op = 0) {
   rl.r[rl.nr++] = Red{(int)off, count, stride, dst, op};
 }
 
-bool pattern_ready(const lnv_pattern* p, bool lut, bool lut_t, bool items) {
-  return p && p->row_ptr && p->col && (!lut || p->lut) && (!lut_t || p->lut_t) &&
-         (!items || p->items);
+// ix: the pattern must carry its spatial index (for lookups in either
+// orientation); items: its row work list.
+bool pattern_ready(const lnv_pattern* p, bool ix, bool ix_t, bool items) {
+  return p && p->row_ptr && p->col && (!(ix || ix_t) || has_ix(p)) && (!items || p->items);
 }
 
 // AT: values of A's dtype.
@@ -894,7 +903,7 @@ int transpose_values(const lnv_bsm* A, const int32_t* perm, void* AT, hipStream_
 
 bool sym_ready(const lnv_bsm* U, const lnv_bsm* C) {
   return U && U->val && U->pat && U->pat->n == C->pat->n && U->pat->items && U->pat->row_ptr &&
-         U->pat->lut && U->dtype == C->dtype && C->pat->items;
+         has_ix(U->pat) && U->dtype == C->dtype && C->pat->items;
 }
 
 // C (full symmetric pattern) from the blocks U of its half (skip: as in
@@ -903,11 +912,11 @@ int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s, const doubl
   const lnv_pattern *pf = C->pat, *pu = U->pat;
   if (pf->n_items == 0) return LNV_OK;
   if (C->dtype == LNV_F32)
-    k_mirror<float><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pu->lut,
+    k_mirror<float><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, make_ix(pu),
                                                 static_cast<const float*>(U->val),
                                                 static_cast<float*>(C->val), skip);
   else
-    k_mirror<double><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, pu->lut,
+    k_mirror<double><<<pf->n_items, 256, 0, s>>>(pf->n, pf->items, pf->row_ptr, pf->col, make_ix(pu),
                                                  static_cast<const double*>(U->val),
                                                  static_cast<double*>(C->val), skip);
   LNV_LAUNCH_CHECK();
@@ -970,12 +979,12 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
   LNV_TRY(sym_product_pair(o.SL, o.X, &Wm, Lu, o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
   const int ni = pl->n_items;
   double* part = o.partials;
-  k_assemble<T><<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, pl->lut,
-                                   static_cast<const double*>(L64->val), o.X->pat->lut,
-                                   static_cast<const T*>(o.X->val), o.XT->pat->lut,
+  k_assemble<T><<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, make_ix(pl),
+                                   static_cast<const double*>(L64->val), make_ix(o.X->pat),
+                                   static_cast<const T*>(o.X->val), make_ix(o.XT->pat),
                                    static_cast<const T*>(o.XT->val),
                                    static_cast<const T*>(o.YT), static_cast<const T*>(o.W),
-                                   o.Z->pat->lut, static_cast<const T*>(o.Z->val),
+                                   make_ix(o.Z->pat), static_cast<const T*>(o.Z->val),
                                    static_cast<const T*>(o.V), G, F, part);
   LNV_LAUNCH_CHECK();
   RedList rl = reds();
@@ -1174,7 +1183,7 @@ extern "C" int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials,
   const lnv_pattern *pa = A->pat, *pb = B->pat;
   if (pa->n != pb->n) return LNV_EPATTERN;
   const bool same = pa == pb;
-  if (!pattern_ready(pa, false, false, true) || (!same && !pb->lut)) return LNV_EPATTERN;
+  if (!pattern_ready(pa, false, false, true) || (!same && !has_ix(pb))) return LNV_EPATTERN;
   const int ni = pa->n_items;
   if (ni == 0) {
     LNV_HIP(hipMemsetAsync(out, 0, sizeof(double), s));
@@ -1182,7 +1191,7 @@ extern "C" int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials,
   }
   const int grid = ni < LNV_DOT_PARTIALS ? ni : LNV_DOT_PARTIALS;
   k_dot_items<<<grid, 256, 0, s>>>(pa->n, ni, pa->items, pa->row_ptr, pa->col,
-                                   static_cast<const double*>(A->val), same ? nullptr : pb->lut,
+                                   static_cast<const double*>(A->val), make_ix(pb), same ? 1 : 0,
                                    static_cast<const double*>(B->val), partials, nullptr);
   LNV_LAUNCH_CHECK();
   RedList rl = reds();
@@ -1236,9 +1245,9 @@ extern "C" int lnv_bsm_lincomb(double a, const lnv_bsm* X, double b, const lnv_b
 extern "C" int lnv_bsm_remap(const lnv_bsm* A, lnv_bsm* B, hipStream_t s) {
   if (!bsm_ok(A) || !bsm_ok(B)) return LNV_EINVAL;
   if (A->blk != 4 || B->blk != 4) return LNV_EUNSUPPORTED;
-  if (A->pat->n != B->pat->n || !A->pat->lut || !B->pat->row_ptr || !B->pat->col)
+  if (A->pat->n != B->pat->n || !has_ix(A->pat) || !B->pat->row_ptr || !B->pat->col)
     return LNV_EPATTERN;
-  k_remap<<<B->pat->n, 256, 0, s>>>(B->pat->n, B->pat->row_ptr, B->pat->col, A->pat->lut,
+  k_remap<<<B->pat->n, 256, 0, s>>>(B->pat->n, B->pat->row_ptr, B->pat->col, make_ix(A->pat),
                                     static_cast<const double*>(A->val),
                                     static_cast<double*>(B->val));
   LNV_LAUNCH_CHECK();
@@ -1340,8 +1349,8 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, bool m_is
   }
   const int ni = pl->n_items;
   // one workgroup per item: partial q belongs to item q
-  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, XP.pat->lut,
-                                 static_cast<const double*>(XP.val), partials + 0 * slot, skip);
+  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, make_ix(XP.pat),
+                                 0, static_cast<const double*>(XP.val), partials + 0 * slot, skip);
   LNV_LAUNCH_CHECK();
   tp->off[0] = 0;
   tp->n[0] = ni;
@@ -1350,7 +1359,7 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, bool m_is
   // needs a buffer of its own (ev.YT is dead outside the evaluation)
   lnv_bsm scratchC{pl, 4, LNV_F64, ev.YT};
   const lnv_pattern* pu = ev.Lu.pat;
-  const bool half = pu && ev.Lu.val && ev.Vu && pu->n == pl->n && pu->lut && pu->row_ptr &&
+  const bool half = pu && ev.Lu.val && ev.Vu && pu->n == pl->n && has_ix(pu) && pu->row_ptr &&
                     pu->col && pl->items && ev.Lu.dtype == LNV_F64 &&
                     2 * pu->nnzb == pl->nnzb + pl->n && (m_is_s || SLcur);
   if (half) {
@@ -1360,7 +1369,7 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, bool m_is
     if (2 * (int64_t)nq <= slot && 2 * (int64_t)nr <= slot) {
       double* Lh = static_cast<double*>(ev.Lu.val);
       double* Ph = static_cast<double*>(ev.Vu);
-      k_half_weighted<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, pu->lut,
+      k_half_weighted<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, make_ix(pu),
                                          static_cast<const double*>(L->val), P, Lh, Ph, skip);
       LNV_LAUNCH_CHECK();
       // <L, Q> -> T3 (even partials), <P, Q> -> T2 (odd)
@@ -1425,7 +1434,7 @@ int metric_apply(const lnv_bsm* T, const double* V, double* out, lnv_cg_ws* ws, 
   lnv_bsm Vm{pl, 4, LNV_F64, const_cast<double*>(V)};
   lnv_bsm Om{pl, 4, LNV_F64, out};
   // P_L(T V T) is symmetric for symmetric T and V
-  if (ws->LL.pat->lut) {
+  if (has_ix(ws->LL.pat)) {
     LNV_TRY(multiply_launch(1.0, &Vm, T, 0, 0.0, &ws->LL, 1, nullptr, nullptr, nullptr, nullptr,
                             s));
     return sym_product(T, &ws->LL, &Om, &ws->ev.Lu, s);
@@ -1453,7 +1462,7 @@ int metric_apply_pair(const lnv_bsm* T, const double* V1, double* out1, const do
   lnv_bsm O1{pl, 4, LNV_F64, out1}, O2{pl, 4, LNV_F64, out2};
   lnv_bsm LL2{ws->LL.pat, 4, LNV_F64, ev.X.val};
   lnv_bsm U2{ev.Lu.pat, 4, LNV_F64, ev.Vu};
-  if (ws->LL.pat->lut) {
+  if (has_ix(ws->LL.pat)) {
     LNV_TRY(multiply_pair_launch(&V1m, T, &ws->LL, &V2m, T, &LL2, 1, nullptr, nullptr, nullptr,
                                  nullptr, nullptr, nullptr, nullptr, s));
     return sym_product_pair(T, &ws->LL, &O1, &ev.Lu, T, &LL2, &O2, &U2, s);
@@ -1478,7 +1487,7 @@ int metric_apply_pair32(const lnv_bsm* T, const double* G, double* Gc, const dou
   const lnv_pattern* pl = T->pat;
   const lnv_pattern* pll = ws->LL.pat;
   const lnv_pattern* pu = w32->Lu.pat;
-  if (!pll || !pll->lut || !w32->X.val || !w32->XT.val || !w32->X.pat || !w32->XT.pat ||
+  if (!pll || !has_ix(pll) || !w32->X.val || !w32->XT.val || !w32->X.pat || !w32->XT.pat ||
       pll->nnzb > w32->X.pat->nnzb || pll->nnzb > w32->XT.pat->nnzb || !pu || !w32->Lu.val ||
       !w32->Vu || !w32->YT || !w32->W || !w32->L.val || w32->L.pat != pl || pu->n != pl->n ||
       w32->Lu.dtype != LNV_F32)
@@ -1523,7 +1532,7 @@ extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_c
   add(rl, 0, S->pat->n, 1, LNV_SC_T4, 1);
   StageArgs sa{};
   LNV_TRY(scalar_stage(part, rl, sc, ST_SIGMA, sa, s));
-  k_identity<<<pt->n_items, 256, 0, s>>>(pt->n, pt->items, pt->row_ptr, pt->col, S->pat->lut,
+  k_identity<<<pt->n_items, 256, 0, s>>>(pt->n, pt->items, pt->row_ptr, pt->col, make_ix(S->pat),
                                          static_cast<const double*>(S->val), sc, LNV_SC_SIGMA,
                                          static_cast<double*>(T->val));
   LNV_LAUNCH_CHECK();
@@ -1576,7 +1585,7 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   if (T) {
     LNV_HIP(hipMemcpyAsync(ws->D, T->val, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
   } else {
-    k_identity<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, S->pat->lut,
+    k_identity<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, make_ix(S->pat),
                                   static_cast<const double*>(S->val), nullptr, 0, ws->D);
     LNV_LAUNCH_CHECK();
   }
@@ -1708,7 +1717,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   }
   // 5. exact cubic line minimisation of E - mu N along D
   k_hprime<<<ph->n_items, 256, 0, s>>>(ph->n, ph->items, ph->row_ptr, ph->col,
-                                       static_cast<const double*>(H->val), S->pat->lut,
+                                       static_cast<const double*>(H->val), make_ix(S->pat),
                                        static_cast<const double*>(S->val), sc, ws->Hp);
   LNV_LAUNCH_CHECK();
   lnv_bsm Hp{ph, 4, LNV_F64, ws->Hp};
@@ -1742,7 +1751,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   lnv_bsm Vu{ev.Lu.pat, 4, LNV_F64, ev.Vu};
   LNV_TRY(sym_product(S, &ev.LS, &ev.Z, &ev.Zu, s));
   LNV_TRY(sym_product(&SL2, &ev.Z, &Vm, &Vu, s));
-  k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, ev.Z.pat->lut,
+  k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, make_ix(ev.Z.pat),
                                  static_cast<const double*>(ev.Z.val), ev.V, Fc, part);
   LNV_LAUNCH_CHECK();
   {

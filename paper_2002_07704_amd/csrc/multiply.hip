@@ -11,9 +11,11 @@
 //  * The k loop runs over A's row i, identical for every lane, so the A block
 //    is wave-uniform and lives in scalar registers (one s_load per block,
 //    broadcast to all 64 lanes by the VALU's scalar operand).
-//  * Each lane finds B_kj in O(1) through the dense atom-pair index table of
-//    B's pattern (lut[k*n + j]) and streams the 128-byte block as 8 dwordx4
-//    loads; index loads run two steps ahead and block loads one step ahead.
+//  * Each lane finds B_kj in O(1) through the spatial index of B's pattern
+//    (one table entry per window cell and slot, see lnv_index; the lane's
+//    column is fixed, so only the step's row k changes the entry) and
+//    streams the 128-byte block as 8 dwordx4 loads; index loads run ahead of
+//    the block loads.
 //  * Products are 64 v_fma_f64 per (i,k,j) triple on the FP64 VALU, which on
 //    MI355X has the same 78.6 TFLOP/s peak as the FP64 matrix cores; a 4x4
 //    block triple is far smaller than an MFMA tile and packing several atoms
@@ -118,14 +120,67 @@ __device__ __forceinline__ void finish_block(const Acc (&acc)[16], T* __restrict
   }
 }
 
+// Lookups of B's blocks for a lane whose output column j is fixed for the
+// whole contraction: the column's half of the window lookup (its cell, slot
+// and sub-column) is taken once, the step's row k supplies the rest.
+struct ColKey {
+  int cb, sb, jt;
+};
+
+__device__ __forceinline__ ColKey col_key(const Ix& x, int j) {
+  const int b = j >> x.qs;
+  return ColKey{x.cell[b], x.slot[b], j & ((1 << x.qs) - 1)};
+}
+
+// Position of B's block (k, j), or -1.
+__device__ __forceinline__ int find_kj(const Ix& x, const ColKey& c, int k) {
+  const int a = k >> x.qs;
+  const int o = ix_off(x, x.cell[a], c.cb, c.sb);
+  if (o < 0) return -1;
+  const int e = x.tab[(size_t)a * x.stride + o];
+  if (e < 0 || x.qs == 0) return e;
+  const int k0 = k & ~3;
+  return e + (k & 3) * (x.rp[k0 + 1] - x.rp[k0]) + c.jt;
+}
+
+// The transposed read op(B) = B^T needs block (j, k): row j is the lane's.
+struct RowKey {
+  int ca, it, len;
+  size_t base;
+};
+
+__device__ __forceinline__ RowKey row_key(const Ix& x, int j) {
+  const int a = j >> x.qs;
+  const int j0 = j & ~((1 << x.qs) - 1);
+  return RowKey{x.cell[a], j & ((1 << x.qs) - 1), x.qs ? x.rp[j0 + 1] - x.rp[j0] : 0,
+                (size_t)a * x.stride};
+}
+
+__device__ __forceinline__ int find_jk(const Ix& x, const RowKey& r, int k) {
+  const int b = k >> x.qs;
+  const int o = ix_off(x, r.ca, x.cell[b], x.slot[b]);
+  if (o < 0) return -1;
+  const int e = x.tab[r.base + o];
+  if (e < 0 || x.qs == 0) return e;
+  return e + r.it * r.len + (k & 3);
+}
+
+// Table entry address of block (k, j) for the index loads of the pipelined
+// kernels (column j fixed per lane, row k's packed cell ck uniform per step):
+// the sentinel entry (-1) when j is outside the window of k or the lane idle.
+__device__ __forceinline__ const int* entry_kj(const Ix& x, int k, int ck, int cb, int sb,
+                                               bool act) {
+  const int o = act ? ix_off(x, ck, cb, sb) : -1;
+  return x.tab + (o < 0 ? (size_t)x.sent : (size_t)(k >> x.qs) * x.stride + o);
+}
+
 template <int TRANS_B, int STORE, int NDOT, typename T, typename Acc>
 __global__ __launch_bounds__(256) void k_mul44(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ a_rp,
-    const int* __restrict__ a_col, const T* __restrict__ a_val,
-    const int* __restrict__ b_lut, const T* __restrict__ b_val,
-    const int* __restrict__ c_rp, const int* __restrict__ c_col, T* __restrict__ c_val,
-    double alpha, double beta, const T* __restrict__ m1, const T* __restrict__ m2,
-    double* __restrict__ partials, const double* __restrict__ skip, int k_lo, int k_hi) {
+    const int* __restrict__ a_col, const T* __restrict__ a_val, Ix bx,
+    const T* __restrict__ b_val, const int* __restrict__ c_rp, const int* __restrict__ c_col,
+    T* __restrict__ c_val, double alpha, double beta, const T* __restrict__ m1,
+    const T* __restrict__ m2, double* __restrict__ partials, const double* __restrict__ skip) {
   if (skip != nullptr && *skip != 0.0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
@@ -136,25 +191,11 @@ __global__ __launch_bounds__(256) void k_mul44(
   const int cnt = min(kWave, c_rp[i + 1] - c0);
   const bool act = lane < cnt;
   const int j = act ? c_col[c0 + lane] : 0;
-  const int* __restrict__ lcol = b_lut + j;
-  const size_t ns = (size_t)n;
-  // contraction range: the k in [k_lo, k_hi) of A's sorted row i
-  int t0 = a_rp[i], t1 = a_rp[i + 1];
-  if (k_lo > 0 || k_hi < n) {
-    int lo = t0, hi = t1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (a_col[mid] < k_lo) lo = mid + 1; else hi = mid;
-    }
-    const int tb = lo;
-    hi = t1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (a_col[mid] < k_hi) lo = mid + 1; else hi = mid;
-    }
-    t0 = tb;
-    t1 = lo;
-  }
+  // op(B)_kj: B's block (k, j), or for the transposed read block (j, k)
+  const ColKey ck = col_key(bx, j);
+  const RowKey rk = row_key(bx, j);
+  auto bpos = [&](int k) -> int { return TRANS_B ? find_jk(bx, rk, k) : find_kj(bx, ck, k); };
+  const int t0 = a_rp[i], t1 = a_rp[i + 1];
 
   Acc acc[16];
 #pragma unroll
@@ -162,14 +203,14 @@ __global__ __launch_bounds__(256) void k_mul44(
 
   T bA[16], bB[16], a[16];
   int pA = -1, pB = -1;
-  if (act && t0 < t1) pA = lcol[(size_t)a_col[t0] * ns];
-  if (act && t0 + 1 < t1) pB = lcol[(size_t)a_col[t0 + 1] * ns];
+  if (act && t0 < t1) pA = bpos(a_col[t0]);
+  if (act && t0 + 1 < t1) pB = bpos(a_col[t0 + 1]);
   if (pA >= 0) load_block(bA, b_val + (size_t)pA * 16);
 
   for (int t = t0; t < t1; t += 2) {
     // step t: consume bA, fetch bB (step t+1) and the index of step t+2
     int pA2 = -1;
-    if (act && t + 2 < t1) pA2 = lcol[(size_t)a_col[t + 2] * ns];
+    if (act && t + 2 < t1) pA2 = bpos(a_col[t + 2]);
     if (pB >= 0) load_block(bB, b_val + (size_t)pB * 16);
     {
       const T* ap = a_val + (size_t)t * 16;
@@ -180,7 +221,7 @@ __global__ __launch_bounds__(256) void k_mul44(
     if (t + 1 >= t1) break;
     // step t+1: consume bB, fetch bA (step t+2) and the index of step t+3
     int pB2 = -1;
-    if (act && t + 3 < t1) pB2 = lcol[(size_t)a_col[t + 3] * ns];
+    if (act && t + 3 < t1) pB2 = bpos(a_col[t + 3]);
     if (pA2 >= 0) load_block(bA, b_val + (size_t)pA2 * 16);
     {
       const T* ap = a_val + (size_t)(t + 1) * 16;
@@ -204,142 +245,21 @@ __global__ __launch_bounds__(256) void k_mul44(
   }
 }
 
-// Clustered variant: a workgroup item covers a cluster of M = 4G consecutive
-// output rows and up to 64/G columns of the union of their patterns.  Lane
-// (q, g) owns column q of the piece for the 4 rows g*4 .. g*4+3 of the
-// cluster (G lanes share a column: their identical B loads coalesce), so
-// one gathered B_kj block feeds up to M accumulators instead of one.  The k
-// loop runs over the union of the cluster's A rows; the A blocks of the rows
-// present are wave-uniform scalar loads.  Blocks of the union outside a row's
-// pattern are accumulated and dropped at the store (cheap: the kernel is
-// bound by the B gathers, not by the FP64 FMAs).
-// A-side of one contraction step: the 4 rows' A blocks are wave-uniform; they
-// are fetched two rows at a time (64 scalar registers) so that two scalar
-// round trips, not four, are exposed per step.
-template <int G, typename T, typename Acc>
-__device__ __forceinline__ void cluster_fma(Acc (&acc)[4][16], const T (&b)[16],
-                                            const int* __restrict__ apos,
-                                            const T* __restrict__ a_val, int g) {
-  int pos[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) pos[r] = (G == 1 || g == 0) ? apos[r] : apos[4 + r];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int p0 = pos[2 * h], p1 = pos[2 * h + 1];
-    T a0[16], a1[16];
-    if (p0 >= 0) {
-      const T* ap = a_val + (size_t)p0 * 16;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) a0[q] = ap[q];
-    }
-    if (p1 >= 0) {
-      const T* ap = a_val + (size_t)p1 * 16;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) a1[q] = ap[q];
-    }
-    if (p0 >= 0) block_fma<0>(acc[2 * h], a0, b);
-    if (p1 >= 0) block_fma<0>(acc[2 * h + 1], a1, b);
-  }
-}
-
-template <int G, int STORE, int NDOT, typename T, typename Acc>
-__global__ __launch_bounds__(256) void k_mul44c(
-    int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
-    const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
-    const T* __restrict__ a_val, const int* __restrict__ b_lut,
-    const T* __restrict__ b_val, const int* __restrict__ jc_ptr,
-    const int* __restrict__ jc_col, const int* __restrict__ jc_pos, T* __restrict__ c_val,
-    double alpha, double beta, const T* __restrict__ m1, const T* __restrict__ m2,
-    double* __restrict__ partials, const double* __restrict__ skip) {
-  constexpr int M = 4 * G;
-  constexpr int COLS = kWave / G;
-  if (skip != nullptr && *skip != 0.0) return;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (item >= n_items) return;
-  const int lane = threadIdx.x & 63;
-  const int q = lane / G, g = lane % G;
-  const int c = items[2 * item];
-  const int p0 = items[2 * item + 1];
-  const int cnt = min(COLS, jc_ptr[c + 1] - p0);
-  const bool act = q < cnt;
-  const int j = act ? jc_col[p0 + q] : 0;
-  int opos[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) opos[r] = act ? jc_pos[(size_t)(p0 + q) * M + g * 4 + r] : -1;
-  const int* __restrict__ lcol = b_lut + j;
-  const size_t ns = (size_t)n;
-  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
-
-  Acc acc[4][16];
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[r][e] = 0;
-
-  // three rotating B buffers: while step t is consumed, the blocks of steps
-  // t+1 and t+2 are in flight; block indices run three steps ahead
-  T b0[16], b1[16], b2[16];
-  int p[3] = {-1, -1, -1};
-  int pn = -1;
-#pragma unroll
-  for (int u = 0; u < 3; ++u)
-    if (act && t0 + u < t1) p[u] = lcol[(size_t)ka_col[t0 + u] * ns];
-  if (act && t0 + 3 < t1) pn = lcol[(size_t)ka_col[t0 + 3] * ns];
-  if (p[0] >= 0) load_block(b0, b_val + (size_t)p[0] * 16);
-  if (p[1] >= 0) load_block(b1, b_val + (size_t)p[1] * 16);
-  for (int t = t0; t < t1; t += 3) {
-    // step t (b0), prefetch step t+2 into b2
-    if (p[2] >= 0) load_block(b2, b_val + (size_t)p[2] * 16);
-    int pn2 = -1;
-    if (act && t + 4 < t1) pn2 = lcol[(size_t)ka_col[t + 4] * ns];
-    if (p[0] >= 0) cluster_fma<G>(acc, b0, ka_pos + (size_t)t * M, a_val, g);
-    if (t + 1 >= t1) break;
-    // step t+1 (b1), prefetch step t+3 into b0
-    if (pn >= 0) load_block(b0, b_val + (size_t)pn * 16);
-    int pn3 = -1;
-    if (act && t + 5 < t1) pn3 = lcol[(size_t)ka_col[t + 5] * ns];
-    if (p[1] >= 0) cluster_fma<G>(acc, b1, ka_pos + (size_t)(t + 1) * M, a_val, g);
-    if (t + 2 >= t1) break;
-    // step t+2 (b2), prefetch step t+4 into b1
-    if (pn2 >= 0) load_block(b1, b_val + (size_t)pn2 * 16);
-    int pn4 = -1;
-    if (act && t + 6 < t1) pn4 = lcol[(size_t)ka_col[t + 6] * ns];
-    if (p[2] >= 0) cluster_fma<G>(acc, b2, ka_pos + (size_t)(t + 2) * M, a_val, g);
-    p[0] = pn;
-    p[1] = pn2;
-    p[2] = pn3;
-    pn = pn4;
-  }
-
-  double d1 = 0.0, d2 = 0.0;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-    if (opos[r] >= 0)
-      finish_block<STORE, NDOT>(acc[r], c_val, (size_t)opos[r] * 16, alpha, beta, m1, m2, d1, d2);
-  if (NDOT >= 1) {
-    d1 = wave_sum(d1);
-    if (NDOT >= 2) d2 = wave_sum(d2);
-    if (lane == 0) {
-      partials[2 * item] = d1;
-      partials[2 * item + 1] = d2;
-    }
-  }
-}
-
 // Clustered variant with one lane per column (G = 1), software-pipelined so
 // that the only memory round trips a contraction step exposes are its A
 // blocks' (scalar loads, shared by the 4 waves of a cluster).  Per step t a
 // wave issues, in this order: one index load (lanes 0-3: the 4 rows' A
-// positions of step t+1, lanes 4-7: those of step t+3, the other lanes: k of
-// step t+4), the B index (lut entry) of step t+3, the B block of step t+2 and
+// positions of step t+1, lanes 4-7: those of step t+3, lanes 8-31: k of step
+// t+4, lanes 32-63: the packed cell of that k), the B index (the table entry
+// of B's spatial index) of step t+3, the B block of step t+2 and
 // a vector load of the 4 A blocks of step t+2 (one element per lane; it only
 // brings them into L2 ahead of the scalar loads, which then hit there); it
 // then multiplies B(t) into the rows present.  Every vector load is issued
 // unconditionally -- steps before the first or past the last read clamped
 // indices, idle lanes column 0's entry, missing B blocks block 0 -- so each
 // iteration issues the same loads in the same order and the waits count them
-// exactly: step t waits for the previous step's index loads and for B(t),
+// exactly (idle lanes and columns outside the window of k read the index's
+// trailing -1): step t waits for the previous step's index loads and for B(t),
 // never for B(t+1), B(t+2) in flight.  The loop starts two steps early, so
 // the first blocks are fetched by the loop body itself.
 template <typename T, typename Acc>
@@ -372,18 +292,18 @@ template <int PAIR, int STORE, int NDOT, typename T, typename Acc>
 __global__ __launch_bounds__(256) void k_mul44c1(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
     const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
-    const T* __restrict__ a_val1, const int* __restrict__ b_lut1,
+    const int* __restrict__ ka_key, const T* __restrict__ a_val1, Ix bx1,
     const T* __restrict__ b_val1, const int* __restrict__ jc_ptr,
     const int* __restrict__ jc_col, const int* __restrict__ jc_pos, T* __restrict__ c_val1,
     double alpha, double beta, const T* __restrict__ m1_1, const T* __restrict__ m2_1,
     double* __restrict__ partials1, const double* __restrict__ skip,
-    const T* __restrict__ a_val2, const int* __restrict__ b_lut2,
+    const T* __restrict__ a_val2, Ix bx2,
     const T* __restrict__ b_val2, T* __restrict__ c_val2, const T* __restrict__ m1_2,
-    const T* __restrict__ m2_2, double* __restrict__ partials2, int k_lo, int k_hi) {
+    const T* __restrict__ m2_2, double* __restrict__ partials2) {
   if (skip != nullptr && *skip != 0.0) return;
   const bool second = PAIR && blockIdx.y != 0;
   const T* __restrict__ a_val = second ? a_val2 : a_val1;
-  const int* __restrict__ b_lut = second ? b_lut2 : b_lut1;
+  const Ix bx = second ? bx2 : bx1;
   const T* __restrict__ b_val = second ? b_val2 : b_val1;
   T* __restrict__ c_val = second ? c_val2 : c_val1;
   const T* __restrict__ m1 = second ? m1_2 : m1_1;
@@ -401,25 +321,9 @@ __global__ __launch_bounds__(256) void k_mul44c1(
   int opos[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) opos[r] = act ? jc_pos[(size_t)(p0 + lane) * 4 + r] : -1;
-  const int* __restrict__ lcol = b_lut + j;
-  const size_t ns = (size_t)n;
-  int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
-  if (k_lo > 0 || k_hi < n) {
-    // contraction slab: the union entries with k in [k_lo, k_hi) (ascending)
-    int lo = t0, hi = t1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (ka_col[mid] < k_lo) lo = mid + 1; else hi = mid;
-    }
-    const int tb = lo;
-    hi = t1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (ka_col[mid] < k_hi) lo = mid + 1; else hi = mid;
-    }
-    t0 = tb;
-    t1 = lo;
-  }
+  // the column's half of B's window lookup (B's units are rows here)
+  const int cb = bx.cell[j], sb = bx.slot[j];
+  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
 
   Acc acc[4][16];
 #pragma unroll
@@ -430,11 +334,12 @@ __global__ __launch_bounds__(256) void k_mul44c1(
   if (t0 < t1) {
     const int tl = t1 - 1;
     // index loads of step t: A positions of steps t+1 (lanes 0-3) and t+3
-    // (lanes 4-7), k of step t+4 (lanes 8-63)
+    // (lanes 4-7), k of step t+4 (lanes 8-31) and its cell (lanes 32-63)
     auto idx_src = [&](int t) -> const int* {
-      return lane < 4   ? ka_pos + (size_t)min(max(t + 1, t0), tl) * 4 + lane
-             : lane < 8 ? ka_pos + (size_t)min(max(t + 3, t0), tl) * 4 + (lane - 4)
-                        : ka_col + min(t + 4, tl);
+      return lane < 4    ? ka_pos + (size_t)min(max(t + 1, t0), tl) * 4 + lane
+             : lane < 8  ? ka_pos + (size_t)min(max(t + 3, t0), tl) * 4 + (lane - 4)
+             : lane < 32 ? ka_col + min(t + 4, tl)
+                         : ka_key + 2 * (size_t)min(t + 4, tl);
     };
     // A element of step t+2 this lane loads ahead (row lane/16, entry lane%16)
     const int ar = (lane >> 4) & 3, ae = lane & 15;
@@ -444,8 +349,8 @@ __global__ __launch_bounds__(256) void k_mul44c1(
     // (block 0, never used).  The block's offset is an opaque zero computed
     // from the index vector, so it is issued last, as in every loop step, and
     // the counts of loads in flight at the loop head agree on both paths.
-    int l0 = -1, l1 = -1;                      // B indices (raw lut entries)
-    int l2 = lcol[(size_t)ka_col[t0] * ns];
+    int l0 = -1, l1 = -1;                      // B positions (index table entries)
+    int l2 = *entry_kj(bx, ka_col[t0], ka_key[2 * (size_t)t0], cb, sb, act);
     int iv = *idx_src(ts - 1);
     T b0[16], b1[16], b2[16];
     int zero = 0;
@@ -459,13 +364,14 @@ __global__ __launch_bounds__(256) void k_mul44c1(
   {                                                                            \
     const int ivn = *idx_src(t);                                               \
     const int k3 = __builtin_amdgcn_readlane(iv, 8);                           \
+    const int c3 = __builtin_amdgcn_readlane(iv, 32);                          \
     int pos[4], pf[4];                                                         \
     _Pragma("unroll") for (int r = 0; r < 4; ++r) {                            \
       pos[r] = __builtin_amdgcn_readlane(iv, r);                               \
       pf[r] = __builtin_amdgcn_readlane(iv, 4 + r);                            \
     }                                                                          \
     const bool use = act && (t) >= t0 && (t) < t1 && LC >= 0;                  \
-    LC = lcol[(size_t)k3 * ns];                                                \
+    LC = *entry_kj(bx, k3, c3, cb, sb, act);                                   \
     load_block(BN, b_val + (size_t)max(L2, 0) * 16);                           \
     asm volatile("" ::"v"(XC));                                                \
     {                                                                          \
@@ -508,7 +414,7 @@ __global__ __launch_bounds__(256) void k_mul44c1(
 // rows of an atom hold the same columns, in aligned runs 4b..4b+3, so a tile's
 // 16 sub-blocks sit at pos(sub-row 0) + s*len + t), A and C carry 16-row
 // cluster plans (4 atoms per cluster, the union of their columns in aligned
-// runs of 4), B carries lut.
+// runs of 4), B carries its spatial index over atoms (qs = 2).
 //
 // A wavefront owns 4 cluster atoms x NB column atoms, i.e. 4*NB accumulator
 // tiles (4 values per lane per tile), and runs the k loop over the cluster's
@@ -539,7 +445,7 @@ __global__ __launch_bounds__(256) void k_mul44c1(
 // Index pipeline (as in k_mul44c1): per step one vector load fetches, for two
 // steps ahead, the 4 cluster atoms' A positions (lanes 0-3), B's row pointers
 // of that step's k (lanes 4-5), the k of three steps ahead (lane 6) and the
-// NB B positions from B's lut (lanes 8..); the fragments of the next step are
+// NB B positions from B's index (lanes 8..); the fragments of the next step are
 // loaded before the current step's products, all unconditionally from clamped
 // positions, so the compiler's wait counts stay exact.
 enum { TM_F32 = 0, TM_F64 = 1, TM_F16X3 = 2 };
@@ -575,10 +481,13 @@ __device__ __forceinline__ void split_f16(const float (&x)[4], f16x4_t& hi, f16x
 // missing; rowA[ar] = (lane's sub-row) * A's row length of that atom).  Lane
 // l = i + 16c holds a[ar][w] = A[i][4c + w] (row i of the tile: one 4-value
 // row of block (i>>2, c)) and b[q][w] = B[4c + w][i] (column i of block
-// (c, i>>2)), w = 0..3.
-template <int NB, typename T>
+// (c, i>>2)), w = 0..3.  TB = 1 reads B as the transpose of the stored
+// matrix B': B[4c + w][i] = B'[i][4c + w], row i of the tile (j, k) of B',
+// a 4-value row of its block (i>>2, c); lenB then holds, per column atom q,
+// the row length of that atom in B' (lenBq), else lenB is the step's.
+template <int NB, int TB, typename T>
 __device__ __forceinline__ void tile_load(T (&a)[4][4], T (&b)[NB][4], const int (&pa)[4],
-                                          const int (&pb)[NB], int lenB,
+                                          const int (&pb)[NB], int lenB, const int (&lenBq)[NB],
                                           const T* __restrict__ a_val,
                                           const T* __restrict__ b_val, const int (&rowA)[4],
                                           int li, int lq, int amax, int bmax) {
@@ -591,10 +500,17 @@ __device__ __forceinline__ void tile_load(T (&a)[4][4], T (&b)[NB][4], const int
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int blk = min(max(pb[q], 0) + lq * lenB + (li >> 2), bmax);
-    const T* bp = b_val + (size_t)blk * 16 + (li & 3);
+    if constexpr (TB) {
+      const int blk = min(max(pb[q], 0) + (li >> 2) * lenBq[q] + lq, bmax);
+      const T* bp = b_val + (size_t)blk * 16 + (li & 3) * 4;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) b[q][w] = bp[w * 4];
+      for (int w = 0; w < 4; ++w) b[q][w] = bp[w];
+    } else {
+      const int blk = min(max(pb[q], 0) + lq * lenB + (li >> 2), bmax);
+      const T* bp = b_val + (size_t)blk * 16 + (li & 3);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) b[q][w] = bp[w * 4];
+    }
   }
 }
 
@@ -646,12 +562,12 @@ __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
   }
 }
 
-template <int NB, int MODE, int STORE, int NDOT, typename T>
+template <int NB, int MODE, int TB, int STORE, int NDOT, typename T>
 __global__ __launch_bounds__(256) void k_tile16(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
-    const int* __restrict__ ka_col, const int* __restrict__ ka_pos, const int* __restrict__ a_rp,
-    const T* __restrict__ a_val, int a_nnzb, const int* __restrict__ b_rp,
-    const int* __restrict__ b_lut, const T* __restrict__ b_val, int b_nnzb,
+    const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
+    const int* __restrict__ ka_key, const int* __restrict__ a_rp, const T* __restrict__ a_val,
+    int a_nnzb, Ix bx, const T* __restrict__ b_val, int b_nnzb,
     const int* __restrict__ jc_ptr, const int* __restrict__ jc_col,
     const int* __restrict__ jc_pos, T* __restrict__ c_val, double alpha, double beta,
     const T* __restrict__ m1, const T* __restrict__ m2, double* __restrict__ partials,
@@ -668,16 +584,26 @@ __global__ __launch_bounds__(256) void k_tile16(
   const int ncol = min(4 * NB, jc_ptr[c + 1] - p0);
   const int r0 = c * 16;
   // output tiles present (bit 4q + ar): sub-row 0 / sub-column 0 of the tile
-  // is present whenever any of its blocks is (full patterns or their halves)
+  // is present whenever any of its blocks is (tile4 outputs)
   int here = 0;
   if (lane < 4 * NB) {
     const int ar = lane & 3, q = lane >> 2;
     here = 4 * q < ncol && jc_pos[(size_t)(p0 + 4 * q) * 16 + 4 * ar] >= 0;
   }
   const uint64_t cmask = __ballot(here);
-  // this lane's column atom for the lut lanes (4b, the first of its rows)
-  const int my_b = (lane >= 8 && lane < 8 + NB && 4 * (lane - 8) < ncol)
-                       ? jc_col[p0 + 4 * (lane - 8)] : 0;
+  // the index lanes 8 .. 8+NB-1: column atom q = lane - 8 of the piece (its
+  // unit in B's index), with the cell and slot its lookups need
+  const bool bl = lane >= 8 && lane < 8 + NB && 4 * (lane - 8) < ncol;
+  const int my_b = bl ? jc_col[p0 + 4 * (lane - 8)] >> 2 : 0;
+  const int my_cell = bx.cell[my_b], my_slot = bx.slot[my_b];
+  // TB: row lengths in B' of the piece's column atoms
+  int lenBq[NB];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int e = min(4 * q, max(ncol - 4, 0));
+    const int jr = jc_col[p0 + e];
+    lenBq[q] = TB ? bx.rp[jr + 1] - bx.rp[jr] : 0;
+  }
   int rowA[4];
 #pragma unroll
   for (int ar = 0; ar < 4; ++ar) {
@@ -699,18 +625,30 @@ __global__ __launch_bounds__(256) void k_tile16(
   const int nsteps = (t1 - t0) >> 2;  // atoms of the contraction union
   if (nsteps > 0) {
     const int tl = t0 + 4 * (nsteps - 1);
-    // index vector for the step whose entries start at te (k row 4k = kk)
-    auto iv_src = [&](int te, int kk) -> const int* {
+    // index vector for the step whose entries start at te (k row 4k = kk,
+    // packed cell ck and slot sk of atom k): lanes 0-3 the cluster atoms' A
+    // positions, 4-5 B's row pointers of row kk, 6 / 7 / 12 the k, cell and
+    // slot of the next step, 8.. the table entries of B's tiles (k, j_q)
+    // (TB: of B''s tiles (j_q, k)), the index's trailing -1 outside the window
+    auto iv_src = [&](int te, int kk, int ck, int sk) -> const int* {
       const int tc = min(max(te, t0), tl);
+      const int tn = min(max(te + 4, t0), tl);
       if (lane < 4) return ka_pos + (size_t)tc * 16 + 4 * lane;
-      if (lane < 6) return b_rp + kk + (lane - 4);
-      if (lane == 6) return ka_col + min(max(te + 4, t0), tl);
-      if (lane >= 8 && lane < 8 + NB) return b_lut + (size_t)kk * n + my_b;
+      if (lane < 6) return bx.rp + kk + (lane - 4);
+      if (lane == 6) return ka_col + tn;
+      if (lane == 7) return ka_key + 2 * (size_t)tn;
+      if (lane == 12) return ka_key + 2 * (size_t)tn + 1;
+      if (lane >= 8 && lane < 8 + NB) {
+        const int o = !bl ? -1 : TB ? ix_off(bx, my_cell, ck, sk) : ix_off(bx, ck, my_cell, my_slot);
+        if (o < 0) return bx.tab + bx.sent;
+        return bx.tab + (size_t)(TB ? my_b : kk >> 2) * bx.stride + o;
+      }
       return ka_col + tl;
     };
     // before the first iteration: the index vector of step -1 (clamped to
-    // step 0's entries; never multiplied), whose lane 6 gives step 0's k
-    int ivp = *iv_src(t0 - 4, ka_col[t0]);
+    // step 0's entries; never multiplied), whose lanes 6, 7, 12 give step 0's
+    // k, cell and slot
+    int ivp = *iv_src(t0 - 4, ka_col[t0], ka_key[2 * (size_t)t0], ka_key[2 * (size_t)t0 + 1]);
     int pa0[4], pb0[NB];
 #pragma unroll
     for (int ar = 0; ar < 4; ++ar) pa0[ar] = -1;
@@ -726,10 +664,13 @@ __global__ __launch_bounds__(256) void k_tile16(
         __builtin_amdgcn_readlane(ivp, ar);                                      \
     const int lenB1 = __builtin_amdgcn_readlane(ivp, 5) - __builtin_amdgcn_readlane(ivp, 4); \
     const int kk2 = __builtin_amdgcn_readlane(ivp, 6);                           \
+    const int ck2 = __builtin_amdgcn_readlane(ivp, 7);                           \
+    const int sk2 = __builtin_amdgcn_readlane(ivp, 12);                          \
     _Pragma("unroll") for (int q = 0; q < NB; ++q) pb1[q] =                      \
         __builtin_amdgcn_readlane(ivp, 8 + q);                                   \
-    const int ivn = *iv_src(t0 + 4 * ((u) + 2), kk2);                            \
-    tile_load<NB, T>(FN_A, FN_B, pa1, pb1, lenB1, a_val, b_val, rowA, li, lq, amax, bmax); \
+    const int ivn = *iv_src(t0 + 4 * ((u) + 2), kk2, ck2, sk2);                  \
+    tile_load<NB, TB, T>(FN_A, FN_B, pa1, pb1, lenB1, lenBq, a_val, b_val, rowA, li, lq, \
+                         amax, bmax);                                            \
     if ((u) >= 0 && (u) < nsteps) tile_mma<MODE, NB>(acc, FC_A, FC_B, pa0, pb0, cmask); \
     _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) pa0[ar] = pa1[ar];          \
     _Pragma("unroll") for (int q = 0; q < NB; ++q) pb0[q] = pb1[q];              \
@@ -780,219 +721,32 @@ __global__ __launch_bounds__(256) void k_tile16(
 
 template <typename T>
 using KernelT16Fn = void (*)(int, int, const int*, const int*, const int*, const int*,
-                             const int*, const T*, int, const int*, const int*, const T*, int,
+                             const int*, const int*, const T*, int, Ix, const T*, int,
                              const int*, const int*, const int*, T*, double, double, const T*,
                              const T*, double*, const double*);
 
-template <int NB, int MODE, typename T>
+template <int NB, int MODE, int TB, typename T>
 KernelT16Fn<T> pick_t16(int store, int ndot) {
   if (store) {
-    if (ndot == 0) return k_tile16<NB, MODE, 1, 0, T>;
-    if (ndot == 1) return k_tile16<NB, MODE, 1, 1, T>;
-    return k_tile16<NB, MODE, 1, 2, T>;
+    if (ndot == 0) return k_tile16<NB, MODE, TB, 1, 0, T>;
+    if (ndot == 1) return k_tile16<NB, MODE, TB, 1, 1, T>;
+    return k_tile16<NB, MODE, TB, 1, 2, T>;
   }
-  if (ndot == 1) return k_tile16<NB, MODE, 0, 1, T>;
-  return k_tile16<NB, MODE, 0, 2, T>;
-}
-
-// Atom quads: 4-function atoms (4x4 blocks) multiplied 16 atom rows at a
-// time on the matrix cores.  A 16x16 MFMA tile holds 4 x 4 atom blocks: row
-// tile ar = cluster atoms 4ar..4ar+3 (16-row cluster plans: 16 atoms), column
-// group q = 4 consecutive entries of the output union; one contraction step
-// is one atom k (one union entry of A's plan), i.e. one 16x16x4 instruction
-// per (ar, q).  A wavefront keeps 4 x NB tiles in the accumulation registers
-// (the VALU kernel's 4-row clusters hold 64 accumulators per lane in
-// ordinary registers already), so every gathered B block feeds 16 rows
-// instead of 4.  Blocks missing from A or B enter as zeros; (ar, q) tiles
-// with no block of A, of B or of the output at a step are skipped by
-// wave-uniform branches.  Positions: lanes 0-15 of the step's index vector
-// hold the 16 cluster atoms' A positions, lanes 16.. the B positions of the
-// piece's column atoms (lut lookups), lane 15 + 4 NB + 1 the k of a later
-// step; each lane then picks its block's position by a lane permute.
-// Operand layout of v_mfma_*_16x16x4: lane l = i + 16c supplies A[i][c] and
-// B[c][i]; here row i = 4u + r is function r of tile atom u (A block
-// (4ar + u, k), element (r, c)), and column i = 4t + c' of group q is function
-// c' of column atom t (B block (k, col), element (c, c')).
-template <int NB, int MODE, int STORE, int NDOT, typename T>
-__global__ __launch_bounds__(256) void k_quad16(
-    int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
-    const int* __restrict__ ka_col, const int* __restrict__ ka_pos, const int* __restrict__ a_rp,
-    const T* __restrict__ a_val, int a_nnzb, const int* __restrict__ b_rp,
-    const int* __restrict__ b_lut, const T* __restrict__ b_val, int b_nnzb,
-    const int* __restrict__ jc_ptr, const int* __restrict__ jc_col,
-    const int* __restrict__ jc_pos, T* __restrict__ c_val, double alpha, double beta,
-    const T* __restrict__ m1, const T* __restrict__ m2, double* __restrict__ partials,
-    const double* __restrict__ skip) {
-  using AccT = typename TileAcc<MODE>::type;
-  using E = typename std::conditional<MODE == TM_F64, double, float>::type;
-  constexpr int KL = 16 + 4 * NB;  // index-vector lane holding the k of a later step
-  if (skip != nullptr && *skip != 0.0) return;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-  if (item >= n_items) return;
-  const int lane = threadIdx.x & 63;
-  const int li = lane & 15, lq = lane >> 4;
-  const int c = items[2 * item];
-  const int p0 = items[2 * item + 1];
-  const int ncol = min(4 * NB, jc_ptr[c + 1] - p0);
-  // output tiles present: lane l checks row atom (l & 15) against the 4
-  // entries of group l >> 4 (bit 16q + 4ar + u of the ballot)
-  int here = 0;
-  if (lq < NB) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int e = 4 * lq + t;
-      here |= (e < ncol && jc_pos[(size_t)(p0 + e) * 16 + li] >= 0) ? 1 : 0;
-    }
-  }
-  const uint64_t cb = __ballot(here);
-  uint32_t cmask = 0;  // bit 4q + ar
-#pragma unroll
-  for (int q = 0; q < NB; ++q)
-#pragma unroll
-    for (int ar = 0; ar < 4; ++ar)
-      if ((cb >> (16 * q + 4 * ar)) & 0xFull) cmask |= 1u << (4 * q + ar);
-  // the lut lanes' column atoms (entries 0 .. 4NB-1 of the piece)
-  const int my_e = lane - 16;
-  const bool b_lane = lane >= 16 && lane < 16 + 4 * NB;
-  const int my_col = (b_lane && my_e < ncol) ? jc_col[p0 + my_e] : 0;
-  const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
-  const int amax = a_nnzb - 1, bmax = b_nnzb - 1;
-
-  AccT acc[4][NB];
-#pragma unroll
-  for (int ar = 0; ar < 4; ++ar)
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[ar][q][v] = 0;
-
-  const int nsteps = t1 - t0;
-  if (nsteps > 0) {
-    const int tl = t1 - 1;
-    // index vector of the step at union entry t (its k = kk)
-    auto iv_src = [&](int t, int kk) -> const int* {
-      const int tc = min(max(t, t0), tl);
-      if (lane < 16) return ka_pos + (size_t)tc * 16 + lane;
-      if (b_lane) return b_lut + (size_t)kk * n + my_col;
-      if (lane == KL) return ka_col + min(max(t + 1, t0), tl);
-      return ka_col + tl;
-    };
-    int ivp = *iv_src(t0 - 1, ka_col[t0]);
-    int pa0 = -1, pb0 = -1;            // this lane's A and B positions, current step
-    uint32_t am0 = 0, bm0 = 0;         // present A tiles (bit ar), B groups (bit q)
-    E fa0[4] = {}, fb0[NB] = {}, fa1[4], fb1[NB];
-    const int ua = li >> 2;            // tile atom of this lane's A row / B column
-#define LNV_Q16_STEP(u, FCA, FCB, FNA, FNB)                                      \
-  {                                                                              \
-    const uint64_t ok = __ballot(ivp >= 0 && (lane < 16 || (b_lane && my_e < ncol))); \
-    uint32_t am1 = 0, bm1 = 0;                                                   \
-    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) if ((ok >> (4 * ar)) & 0xFull) am1 |= 1u << ar; \
-    _Pragma("unroll") for (int q = 0; q < NB; ++q) if ((ok >> (16 + 4 * q)) & 0xFull) bm1 |= 1u << q; \
-    const int kk2 = __builtin_amdgcn_readlane(ivp, KL);                          \
-    const int ivn = *iv_src(t0 + (u) + 2, kk2);                                  \
-    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) {                           \
-      const int pa = __shfl(ivp, 4 * ar + ua, kWave);                            \
-      const T v = a_val[(size_t)min(max(pa, 0), amax) * 16 + (li & 3) * 4 + lq]; \
-      FNA[ar] = pa >= 0 ? (E)v : (E)0;                                           \
-    }                                                                            \
-    _Pragma("unroll") for (int q = 0; q < NB; ++q) {                             \
-      const int pb = __shfl(ivp, 16 + 4 * q + ua, kWave);                        \
-      const bool okb = pb >= 0 && 4 * q + ua < ncol;                             \
-      const T v = b_val[(size_t)min(max(pb, 0), bmax) * 16 + lq * 4 + (li & 3)]; \
-      FNB[q] = okb ? (E)v : (E)0;                                                \
-    }                                                                            \
-    if ((u) >= 0 && (u) < nsteps) {                                              \
-      _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) {                         \
-        if (!((am0 >> ar) & 1u)) continue;                                       \
-        _Pragma("unroll") for (int q = 0; q < NB; ++q) {                         \
-          if (!((bm0 >> q) & 1u) || !((cmask >> (4 * q + ar)) & 1u)) continue;   \
-          if constexpr (MODE == TM_F64)                                          \
-            acc[ar][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(FCA[ar], FCB[q], acc[ar][q], 0, 0, 0); \
-          else                                                                   \
-            acc[ar][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(FCA[ar], FCB[q], acc[ar][q], 0, 0, 0); \
-        }                                                                        \
-      }                                                                          \
-    }                                                                            \
-    am0 = am1;                                                                   \
-    bm0 = bm1;                                                                   \
-    ivp = ivn;                                                                   \
-  }
-    for (int u = -2; u < nsteps; u += 2) {
-      LNV_Q16_STEP(u, fa0, fb0, fa1, fb1)
-      LNV_Q16_STEP(u + 1, fa1, fb1, fa0, fb0)
-    }
-#undef LNV_Q16_STEP
-    (void)pa0;
-    (void)pb0;
-  }
-
-  // epilogue as in k_tile16: lane (n + 16g) holds column n of each tile
-  // (column n&3 of the block of entry 4q + (n>>2)), register v the tile row
-  // 4g + v (FP32) or 4v + g (FP64): row atom (row >> 2), row (row & 3)
-  const int g = lq, nn = li;
-  double d1 = 0.0, d2 = 0.0;
-#pragma unroll
-  for (int ar = 0; ar < 4; ++ar)
-#pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int e = p0 + 4 * q + (nn >> 2);
-      if (!((cmask >> (4 * q + ar)) & 1u) || e >= p0 + ncol) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = MODE == TM_F64 ? 4 * v + g : 4 * g + v;
-        const int pos = jc_pos[(size_t)e * 16 + 4 * ar + (row >> 2)];
-        if (pos < 0) continue;
-        const size_t at = (size_t)pos * 16 + (row & 3) * 4 + (nn & 3);
-        const double val = alpha * (double)acc[ar][q][v];
-        const T out = (T)(beta != 0.0 ? val + beta * (double)c_val[at] : val);
-        if (STORE) c_val[at] = out;
-        if (NDOT >= 1) d1 = fma((double)m1[at], (double)out, d1);
-        if (NDOT >= 2) d2 = fma((double)m2[at], (double)out, d2);
-      }
-    }
-  if (NDOT >= 1) {
-    d1 = wave_sum(d1);
-    if (NDOT >= 2) d2 = wave_sum(d2);
-    if (lane == 0) {
-      partials[2 * item] = d1;
-      partials[2 * item + 1] = d2;
-    }
-  }
+  if (ndot == 1) return k_tile16<NB, MODE, TB, 0, 1, T>;
+  return k_tile16<NB, MODE, TB, 0, 2, T>;
 }
 
 template <int NB, int MODE, typename T>
-KernelT16Fn<T> pick_q16(int store, int ndot) {
-  if (store) {
-    if (ndot == 0) return k_quad16<NB, MODE, 1, 0, T>;
-    if (ndot == 1) return k_quad16<NB, MODE, 1, 1, T>;
-    return k_quad16<NB, MODE, 1, 2, T>;
-  }
-  if (ndot == 1) return k_quad16<NB, MODE, 0, 1, T>;
-  return k_quad16<NB, MODE, 0, 2, T>;
+KernelT16Fn<T> pick_t16_tb(int transB, int store, int ndot) {
+  return transB ? pick_t16<NB, MODE, 1, T>(store, ndot) : pick_t16<NB, MODE, 0, T>(store, ndot);
 }
 
 template <typename T>
-using KernelCFn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
-                           const int*, const T*, const int*, const int*, const int*, T*, double,
-                           double, const T*, const T*, double*, const double*);
-
-template <int G, typename T, typename Acc>
-KernelCFn<T> pick_c(int store, int ndot) {
-  if (store) {
-    if (ndot == 0) return k_mul44c<G, 1, 0, T, Acc>;
-    if (ndot == 1) return k_mul44c<G, 1, 1, T, Acc>;
-    return k_mul44c<G, 1, 2, T, Acc>;
-  }
-  if (ndot == 1) return k_mul44c<G, 0, 1, T, Acc>;
-  return k_mul44c<G, 0, 2, T, Acc>;
-}
-
-template <typename T>
-using KernelC1Fn = void (*)(int, int, const int*, const int*, const int*, const int*, const T*,
-                            const int*, const T*, const int*, const int*, const int*, T*, double,
-                            double, const T*, const T*, double*, const double*, const T*,
-                            const int*, const T*, T*, const T*, const T*, double*, int, int);
+using KernelC1Fn = void (*)(int, int, const int*, const int*, const int*, const int*,
+                            const int*, const T*, Ix, const T*, const int*, const int*,
+                            const int*, T*, double, double, const T*, const T*, double*,
+                            const double*, const T*, Ix, const T*, T*, const T*, const T*,
+                            double*);
 
 template <int PAIR, typename T, typename Acc>
 KernelC1Fn<T> pick_c1(int store, int ndot) {
@@ -1006,9 +760,9 @@ KernelC1Fn<T> pick_c1(int store, int ndot) {
 }
 
 template <typename T>
-using KernelFn = void (*)(int, int, const int*, const int*, const int*, const T*, const int*,
-                          const T*, const int*, const int*, T*, double, double, const T*,
-                          const T*, double*, const double*, int, int);
+using KernelFn = void (*)(int, int, const int*, const int*, const int*, const T*, Ix, const T*,
+                          const int*, const int*, T*, double, double, const T*, const T*,
+                          double*, const double*);
 
 template <int TB, typename T, typename Acc>
 KernelFn<T> pick_store(int store, int ndot) {
@@ -1049,62 +803,39 @@ int timer_begin(hipStream_t s, hipEvent_t* stop) {
   return LNV_OK;
 }
 
-int g_kslab_override = -1;  // < 0: automatic
 int g_f32_acc = LNV_ACC_F32;  // accumulation of the FP32 products
 
-// Number of contraction slabs (atom-index ranges of k, one launch each,
-// accumulating into C).  Atoms numbered cell by cell make an index range a
-// spatial slab, which bounds the rows of B one launch gathers (for the
-// 256 MB Infinity Cache).  Measured on MI355X at 4096 atoms with the
-// pipelined clustered kernel, a CG iteration takes 1.8x (2 slabs), 2.5x (4)
-// and 3.1x (8) the single-launch time: the clusters far from a slab have no
-// work in it, so every launch keeps only part of the device busy.  The
-// default is a single launch; the split remains available for contractions
-// that must be partitioned.
-int kslabs_for(const lnv_bsm* B) {
-  if (g_kslab_override > 0) return g_kslab_override < B->pat->n ? g_kslab_override : B->pat->n;
-  return 1;
+bool plan_ok(const lnv_pattern* p) {
+  return p->cl_ptr && p->cl_col && p->cl_pos && p->cl_cell;
 }
 
 }  // namespace
 
+// The pipelined 4-row kernel: 4-row cluster plans on A and C (one lane per
+// output column), B indexed by rows (4x4-blocked atoms, or rows of atoms
+// split over several rows).
 bool use_clustered(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
-  const lnv_pattern *pa = A->pat, *pc = C->pat;
-  return !transB && (kslabs_for(B) == 1 || C->pat->cl_g == 1) && pa->cl_m > 0 && pa->cl_m != 16 &&
-         pa->cl_m == pc->cl_m && pa->cl_ptr &&
-         pa->cl_col && pa->cl_pos && pc->cl_ptr && pc->cl_col && pc->cl_pos && pc->cl_items &&
-         pc->cl_g * 4 == pc->cl_m;
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
+  return !transB && pa->cl_m == 4 && pc->cl_m == 4 && pc->cl_g == 1 && plan_ok(pa) &&
+         plan_ok(pc) && pc->cl_items && has_ix(pb) && pb->ix.qs == 0 && pb->nnzb > 0;
 }
 
 // Atom-tile (MFMA) multiply: 16-row cluster plans on A and C, tile4 patterns
-// on A and B and a tile-complete C (lnv_pattern_tile4 grade 1 or 2; see
-// k_tile16), B's lut, row count a multiple of 4.
+// on A, B and C (see k_tile16), B's index over atoms, row count a multiple
+// of 4; op(B) = B^T reads B's tiles transposed.
 bool use_tiles(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
   const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
-  return !transB && kslabs_for(B) == 1 && pa->cl_m == 16 && pc->cl_m == 16 &&
-         (pc->cl_g == 4 || pc->cl_g == 8) && pa->tile4 == 1 && pb->tile4 == 1 &&
-         (pc->tile4 == 1 || pc->tile4 == 2) && pb->lut &&
-         pa->n % 4 == 0 && pa->cl_ptr && pa->cl_col && pa->cl_pos && pc->cl_ptr &&
-         pc->cl_col && pc->cl_pos && pc->cl_items && pa->row_ptr && pb->row_ptr &&
-         pa->nnzb > 0 && pb->nnzb > 0 && pa->nnzb < INT32_MAX && pb->nnzb < INT32_MAX;
-}
-
-// Atom-quad (MFMA) multiply of 4-function atoms: 16-row cluster plans on A
-// and C on patterns that are not tile4, B's lut (see k_quad16).
-bool use_quads(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
-  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
-  return !transB && kslabs_for(B) == 1 && pa->cl_m == 16 && pc->cl_m == 16 &&
-         (pc->cl_g == 4 || pc->cl_g == 8) && !use_tiles(A, B, transB, C) && pb->lut &&
-         pa->cl_ptr && pa->cl_col && pa->cl_pos && pc->cl_ptr && pc->cl_col && pc->cl_pos &&
-         pc->cl_items && pa->nnzb > 0 && pb->nnzb > 0 && pa->nnzb < INT32_MAX &&
+  (void)transB;
+  return pa->cl_m == 16 && pc->cl_m == 16 && (pc->cl_g == 4 || pc->cl_g == 8) &&
+         pa->tile4 == 1 && pb->tile4 == 1 && pc->tile4 == 1 && has_ix(pb) && pb->ix.qs == 2 &&
+         pa->n % 4 == 0 && plan_ok(pa) && plan_ok(pc) && pc->cl_items && pa->row_ptr &&
+         pb->row_ptr && pa->nnzb > 0 && pb->nnzb > 0 && pa->nnzb < INT32_MAX &&
          pb->nnzb < INT32_MAX;
 }
 
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
-  return use_clustered(A, B, transB, C) || use_tiles(A, B, transB, C) ||
-                 use_quads(A, B, transB, C)
-             ? C->pat->n_cl_items
-             : C->pat->n_items;
+  return use_clustered(A, B, transB, C) || use_tiles(A, B, transB, C) ? C->pat->n_cl_items
+                                                                      : C->pat->n_items;
 }
 
 namespace {
@@ -1118,39 +849,37 @@ int tile_mode() {
 }
 
 template <typename T>
-int launch_tiles(double alpha, const lnv_bsm* A, const lnv_bsm* B, double beta,
+int launch_tiles(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, double beta,
                  const lnv_bsm* C, int store, const T* m1, const T* m2, double* partials,
-                 const double* skip, int ndot, hipStream_t s, bool quads = false) {
+                 const double* skip, int ndot, hipStream_t s) {
   const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
   if (pc->n_cl_items == 0) return LNV_OK;
   const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
   const bool nb4 = pc->cl_g == 4;  // 4 column atoms per wave (cl_g 8: 2)
   KernelT16Fn<T> fn = nullptr;
   const int mode = tile_mode<T>();
-  if (quads) {
-    // 4-function atoms: FP64 or FP32 matrix instructions (no FP16 split)
-    if (mode == TM_F64)
-      fn = nb4 ? pick_q16<4, TM_F64, T>(store, ndot) : pick_q16<2, TM_F64, T>(store, ndot);
-    else if constexpr (std::is_same<T, float>::value)
-      fn = nb4 ? pick_q16<4, TM_F32, T>(store, ndot) : pick_q16<2, TM_F32, T>(store, ndot);
-  } else if (mode == TM_F64) {
-    fn = nb4 ? pick_t16<4, TM_F64, T>(store, ndot) : pick_t16<2, TM_F64, T>(store, ndot);
+  const int tb = transB ? 1 : 0;
+  if (mode == TM_F64) {
+    fn = nb4 ? pick_t16_tb<4, TM_F64, T>(tb, store, ndot)
+             : pick_t16_tb<2, TM_F64, T>(tb, store, ndot);
   } else {
     if constexpr (std::is_same<T, float>::value) {
       if (mode == TM_F16X3)
-        fn = nb4 ? pick_t16<4, TM_F16X3, T>(store, ndot) : pick_t16<2, TM_F16X3, T>(store, ndot);
+        fn = nb4 ? pick_t16_tb<4, TM_F16X3, T>(tb, store, ndot)
+                 : pick_t16_tb<2, TM_F16X3, T>(tb, store, ndot);
       else
-        fn = nb4 ? pick_t16<4, TM_F32, T>(store, ndot) : pick_t16<2, TM_F32, T>(store, ndot);
+        fn = nb4 ? pick_t16_tb<4, TM_F32, T>(tb, store, ndot)
+                 : pick_t16_tb<2, TM_F32, T>(tb, store, ndot);
     }
   }
   if (!fn) return LNV_EUNSUPPORTED;
   hipEvent_t stop = nullptr;
   LNV_TRY(timer_begin(s, &stop));
   fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
-                         pa->cl_pos, pa->row_ptr, static_cast<const T*>(A->val), (int)pa->nnzb,
-                         pb->row_ptr, pb->lut, static_cast<const T*>(B->val), (int)pb->nnzb,
-                         pc->cl_ptr, pc->cl_col, pc->cl_pos, static_cast<T*>(C->val), alpha,
-                         beta, m1, m2, partials, skip);
+                         pa->cl_pos, pa->cl_cell, pa->row_ptr, static_cast<const T*>(A->val),
+                         (int)pa->nnzb, make_ix(pb), static_cast<const T*>(B->val),
+                         (int)pb->nnzb, pc->cl_ptr, pc->cl_col, pc->cl_pos,
+                         static_cast<T*>(C->val), alpha, beta, m1, m2, partials, skip);
   LNV_LAUNCH_CHECK();
   if (stop) LNV_HIP(hipEventRecord(stop, s));
   return LNV_OK;
@@ -1159,45 +888,25 @@ int launch_tiles(double alpha, const lnv_bsm* A, const lnv_bsm* B, double beta,
 template <typename T, typename Acc>
 int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, double beta,
                  const lnv_bsm* C, int store, const void* m1v, const void* m2v,
-                 double* partials, const double* skip, int ndot, const int32_t* lut,
-                 hipStream_t s) {
-  const lnv_pattern *pa = A->pat, *pc = C->pat;
+                 double* partials, const double* skip, int ndot, hipStream_t s) {
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
   const T* av = static_cast<const T*>(A->val);
   const T* bv = static_cast<const T*>(B->val);
   T* cv = static_cast<T*>(C->val);
   const T* m1 = static_cast<const T*>(m1v);
   const T* m2 = static_cast<const T*>(m2v);
-  const int nslab = kslabs_for(B);
   if (use_tiles(A, B, transB, C))
-    return launch_tiles<T>(alpha, A, B, beta, C, store, m1, m2, partials, skip, ndot, s);
-  if (use_quads(A, B, transB, C))
-    return launch_tiles<T>(alpha, A, B, beta, C, store, m1, m2, partials, skip, ndot, s, true);
+    return launch_tiles<T>(alpha, A, B, transB, beta, C, store, m1, m2, partials, skip, ndot, s);
   if (use_clustered(A, B, transB, C)) {
     if (pc->n_cl_items == 0) return LNV_OK;
     const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
     hipEvent_t stop = nullptr;
     LNV_TRY(timer_begin(s, &stop));
-    // the pipelined kernel reads block 0 of B in place of missing blocks
-    if (pc->cl_g == 1 && B->pat->nnzb > 0) {
-      const int n = pa->n;
-      for (int c = 0; c < nslab; ++c) {
-        // slabs of k accumulate into C; the last applies the store / traces
-        const bool last = c == nslab - 1;
-        const int k_lo = (int)((int64_t)c * n / nslab), k_hi = (int)((int64_t)(c + 1) * n / nslab);
-        KernelC1Fn<T> fn = pick_c1<0, T, Acc>(last ? store : 1, last ? ndot : 0);
-        fn<<<wgs, 256, 0, s>>>(n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
-                               pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
-                               alpha, c == 0 ? beta : 1.0, m1, m2, partials, skip, nullptr,
-                               nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, k_lo, k_hi);
-        LNV_LAUNCH_CHECK();
-      }
-    } else {
-      KernelCFn<T> fn =
-          pc->cl_g == 2 ? pick_c<2, T, Acc>(store, ndot) : pick_c<1, T, Acc>(store, ndot);
-      fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
-                             pa->cl_pos, av, lut, bv, pc->cl_ptr, pc->cl_col, pc->cl_pos, cv,
-                             alpha, beta, m1, m2, partials, skip);
-    }
+    KernelC1Fn<T> fn = pick_c1<0, T, Acc>(store, ndot);
+    fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col,
+                           pa->cl_pos, pa->cl_cell, av, make_ix(pb), bv, pc->cl_ptr, pc->cl_col,
+                           pc->cl_pos, cv, alpha, beta, m1, m2, partials, skip, nullptr,
+                           make_ix(pb), nullptr, nullptr, nullptr, nullptr, nullptr);
     LNV_LAUNCH_CHECK();
     if (stop) LNV_HIP(hipEventRecord(stop, s));
     return LNV_OK;
@@ -1206,20 +915,11 @@ int launch_typed(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
   const int wgs = round_up((pc->n_items + 3) / 4, kNumXcd);
   hipEvent_t stop = nullptr;
   LNV_TRY(timer_begin(s, &stop));
-  const int n = pa->n;
-  for (int c = 0; c < nslab; ++c) {
-    // every slab but the last accumulates into C (stored); the last applies
-    // the caller's store / trace choice to the finished sum
-    const bool last = c == nslab - 1;
-    const int k_lo = (int)((int64_t)c * n / nslab), k_hi = (int)((int64_t)(c + 1) * n / nslab);
-    const int st = last ? store : 1;
-    const int nd = last ? ndot : 0;
-    KernelFn<T> fn = transB ? pick_store<1, T, Acc>(st, nd) : pick_store<0, T, Acc>(st, nd);
-    fn<<<wgs, 256, 0, s>>>(n, pc->n_items, pc->items, pa->row_ptr, pa->col, av, lut, bv,
-                           pc->row_ptr, pc->col, cv, alpha, c == 0 ? beta : 1.0, m1, m2,
-                           partials, skip, k_lo, k_hi);
-    LNV_LAUNCH_CHECK();
-  }
+  KernelFn<T> fn =
+      transB ? pick_store<1, T, Acc>(store, ndot) : pick_store<0, T, Acc>(store, ndot);
+  fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_items, pc->items, pa->row_ptr, pa->col, av, make_ix(pb),
+                         bv, pc->row_ptr, pc->col, cv, alpha, beta, m1, m2, partials, skip);
+  LNV_LAUNCH_CHECK();
   if (stop) LNV_HIP(hipEventRecord(stop, s));
   return LNV_OK;
 }
@@ -1238,22 +938,15 @@ int launch_pair_typed(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1,
   const int wgs = round_up((pc->n_cl_items + 3) / 4, kNumXcd);
   hipEvent_t stop = nullptr;
   LNV_TRY(timer_begin(s, &stop));
-  const int n = pa->n;
-  const int nslab = kslabs_for(B1);
-  for (int c = 0; c < nslab; ++c) {
-    const bool last = c == nslab - 1;
-    const int k_lo = (int)((int64_t)c * n / nslab), k_hi = (int)((int64_t)(c + 1) * n / nslab);
-    KernelC1Fn<T> fn = pick_c1<1, T, Acc>(last ? store : 1, last ? ndot : 0);
-    fn<<<dim3(wgs, 2), 256, 0, s>>>(
-        n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col, pa->cl_pos,
-        static_cast<const T*>(A1->val), B1->pat->lut, static_cast<const T*>(B1->val),
-        pc->cl_ptr, pc->cl_col, pc->cl_pos, static_cast<T*>(C1->val), 1.0, c == 0 ? 0.0 : 1.0,
-        static_cast<const T*>(m11), static_cast<const T*>(m12), part1, skip,
-        static_cast<const T*>(A2->val), B2->pat->lut, static_cast<const T*>(B2->val),
-        static_cast<T*>(C2->val), static_cast<const T*>(m21), static_cast<const T*>(m22), part2,
-        k_lo, k_hi);
-    LNV_LAUNCH_CHECK();
-  }
+  KernelC1Fn<T> fn = pick_c1<1, T, Acc>(store, ndot);
+  fn<<<dim3(wgs, 2), 256, 0, s>>>(
+      pa->n, pc->n_cl_items, pc->cl_items, pa->cl_ptr, pa->cl_col, pa->cl_pos, pa->cl_cell,
+      static_cast<const T*>(A1->val), make_ix(B1->pat), static_cast<const T*>(B1->val),
+      pc->cl_ptr, pc->cl_col, pc->cl_pos, static_cast<T*>(C1->val), 1.0, 0.0,
+      static_cast<const T*>(m11), static_cast<const T*>(m12), part1, skip,
+      static_cast<const T*>(A2->val), make_ix(B2->pat), static_cast<const T*>(B2->val),
+      static_cast<T*>(C2->val), static_cast<const T*>(m21), static_cast<const T*>(m22), part2);
+  LNV_LAUNCH_CHECK();
   if (stop) LNV_HIP(hipEventRecord(stop, s));
   return LNV_OK;
 }
@@ -1270,11 +963,9 @@ int multiply_pair_launch(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1
       bsm_ok_any(C2) && A1->pat == A2->pat && C1->pat == C2->pat && A1->dtype == C1->dtype &&
       B1->dtype == C1->dtype && A2->dtype == C1->dtype && B2->dtype == C1->dtype &&
       C2->dtype == C1->dtype && A1->blk == 4 && B1->blk == 4 && C1->blk == 4 && B2->blk == 4 &&
-      use_clustered(A1, B1, 0, C1) && use_clustered(A2, B2, 0, C2) && C1->pat->cl_g == 1 &&
-      B1->pat->nnzb > 0 && B2->pat->nnzb > 0 && B1->pat->lut && B2->pat->lut &&
+      use_clustered(A1, B1, 0, C1) && use_clustered(A2, B2, 0, C2) &&
       B1->pat->n == C1->pat->n && B2->pat->n == C1->pat->n &&
-      ndot == (m22 ? 2 : (m21 ? 1 : 0)) && (ndot == 0 || (part1 && part2)) && (store || ndot > 0) &&
-      (store || kslabs_for(B1) == 1 || C1->val != C2->val);
+      ndot == (m22 ? 2 : (m21 ? 1 : 0)) && (ndot == 0 || (part1 && part2)) && (store || ndot > 0);
   if (!pairable) {  // two launches
     LNV_TRY(multiply_launch(1.0, A1, B1, 0, 0.0, C1, store, m11, m12, part1, skip, s));
     return multiply_launch(1.0, A2, B2, 0, 0.0, C2, store, m21, m22, part2, skip, s);
@@ -1300,8 +991,7 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
   const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
   if (pa->n != pb->n || pa->n != pc->n) return LNV_EPATTERN;
   if (!pa->row_ptr || !pa->col || !pc->row_ptr || !pc->col || !pc->items) return LNV_EPATTERN;
-  const int32_t* lut = transB ? pb->lut_t : pb->lut;
-  if (!lut) return LNV_EPATTERN;
+  if (!has_ix(pb)) return LNV_EPATTERN;
   const int ndot = m2 ? 2 : (m1 ? 1 : 0);
   if (m2 && !m1) return LNV_EINVAL;
   if (ndot > 0 && !partials) return LNV_EINVAL;
@@ -1309,12 +999,12 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
   if (C->dtype == LNV_F32) {
     if (g_f32_acc == LNV_ACC_F64)
       return launch_typed<float, double>(alpha, A, B, transB, beta, C, store, m1, m2, partials,
-                                         skip, ndot, lut, s);
+                                         skip, ndot, s);
     return launch_typed<float, float>(alpha, A, B, transB, beta, C, store, m1, m2, partials,
-                                      skip, ndot, lut, s);
+                                      skip, ndot, s);
   }
   return launch_typed<double, double>(alpha, A, B, transB, beta, C, store, m1, m2, partials,
-                                      skip, ndot, lut, s);
+                                      skip, ndot, s);
 }
 
 }  // namespace lnv
@@ -1330,11 +1020,6 @@ extern "C" int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B
 extern "C" int lnv_set_f32_accumulation(int32_t acc) {
   if (acc != LNV_ACC_F32 && acc != LNV_ACC_F64 && acc != LNV_ACC_F16X3) return LNV_EINVAL;
   g_f32_acc = acc;
-  return LNV_OK;
-}
-
-extern "C" int lnv_set_kslabs(int32_t n) {
-  g_kslab_override = n;
   return LNV_OK;
 }
 

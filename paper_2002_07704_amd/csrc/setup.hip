@@ -5,8 +5,10 @@
 //   index tables and work lists of a pattern
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <vector>
 
 #include "internal.h"
 
@@ -203,27 +205,73 @@ __global__ __launch_bounds__(256) void k_half(int n, const int* __restrict__ rp,
     if (in_half(n, i, col[p])) out_col[q++] = col[p];
 }
 
-// ------------------------------------------------------------------ index tables
-__global__ __launch_bounds__(256) void k_lut(int n, const int* __restrict__ rp,
-                                             const int* __restrict__ col, int* __restrict__ lut,
-                                             int* __restrict__ lut_t) {
-  const int i = blockIdx.x;
+// ------------------------------------------------------------------ spatial index
+// Largest wrapped cell offset, per axis, between a unit row and the units of
+// its columns (only the first row of a unit and the first column of each
+// unit count: the others repeat them).  ext[0..2] receive the maxima
+// (atomicMax), ext[3] is set when a row unit's first row does not start a
+// unit (a pattern qs cannot describe).
+__global__ __launch_bounds__(256) void k_ix_extent(int n_units, int qs,
+                                                   const int* __restrict__ rp,
+                                                   const int* __restrict__ col,
+                                                   const int* __restrict__ cell, int g0, int g1,
+                                                   int g2, int* __restrict__ ext) {
+  const int a = blockIdx.x;
+  const int i = a << qs;
+  const int m = (1 << qs) - 1;
+  const int ca = cell[a];
+  int e0 = 0, e1 = 0, e2 = 0;
   for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 256) {
     const int j = col[p];
-    if (lut) lut[(size_t)i * n + j] = p;
-    if (lut_t) lut_t[(size_t)j * n + i] = p;
+    if (j & m) continue;
+    const int cb = cell[j >> qs];
+    int o[3] = {(cb & 1023) - (ca & 1023), ((cb >> 10) & 1023) - ((ca >> 10) & 1023),
+                (cb >> 20) - (ca >> 20)};
+    const int g[3] = {g0, g1, g2};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      int v = o[d];
+      if (v < 0) v += g[d];
+      v = min(v, g[d] - v);   // wrapped distance along the axis
+      o[d] = v;
+    }
+    e0 = max(e0, o[0]);
+    e1 = max(e1, o[1]);
+    e2 = max(e2, o[2]);
+  }
+  if (e0) atomicMax(ext + 0, e0);
+  if (e1) atomicMax(ext + 1, e1);
+  if (e2) atomicMax(ext + 2, e2);
+}
+
+// tab[a * stride + window offset of unit b] = position of block (a<<qs, b<<qs).
+__global__ __launch_bounds__(256) void k_ix_fill(int n_units, Ix x, const int* __restrict__ col,
+                                                 int* __restrict__ tab, int* __restrict__ bad) {
+  const int a = blockIdx.x;
+  const int i = a << x.qs;
+  const int m = (1 << x.qs) - 1;
+  const int ca = x.cell[a];
+  for (int p = x.rp[i] + threadIdx.x; p < x.rp[i + 1]; p += 256) {
+    const int j = col[p];
+    if (j & m) continue;
+    const int b = j >> x.qs;
+    const int o = ix_off(x, ca, x.cell[b], x.slot[b]);
+    if (o < 0) {
+      atomicOr(bad, 1);
+      continue;
+    }
+    tab[(size_t)a * x.stride + o] = p;
   }
 }
 
 // perm[p] = position in PT of the transpose of block p of P; bad[0] set to
 // 1 when a block has no transpose.
 __global__ __launch_bounds__(256) void k_tmap(int n, const int* __restrict__ rp,
-                                              const int* __restrict__ col,
-                                              const int* __restrict__ lut_pt,
+                                              const int* __restrict__ col, Ix xpt,
                                               int* __restrict__ perm, int* __restrict__ bad) {
   const int i = blockIdx.x;
   for (int p = rp[i] + threadIdx.x; p < rp[i + 1]; p += 256) {
-    const int q = lut_pt[(size_t)col[p] * n + i];
+    const int q = ix_find(xpt, col[p], i);
     perm[p] = q;
     if (q < 0) bad[0] = 1;
   }
@@ -231,14 +279,16 @@ __global__ __launch_bounds__(256) void k_tmap(int n, const int* __restrict__ rp,
 
 // Cluster unions: one workgroup per cluster of m rows; the union of their
 // columns is collected in an LDS bitmap, then counted or emitted in
-// ascending order together with each row's block position (lut) or -1.
+// ascending order together with each row's block position (from the
+// pattern's index) or -1, and the packed cell and the slot of the column's
+// unit.
 __global__ __launch_bounds__(256) void k_cluster_union(int n, int m, const int* __restrict__ rp,
-                                                       const int* __restrict__ col,
-                                                       const int* __restrict__ lut,
+                                                       const int* __restrict__ col, Ix px,
                                                        int* __restrict__ counts,
                                                        const int* __restrict__ out_ptr,
                                                        int* __restrict__ out_col,
-                                                       int* __restrict__ out_pos, int fill) {
+                                                       int* __restrict__ out_pos,
+                                                       int* __restrict__ out_cell, int fill) {
   extern __shared__ unsigned int bits[];
   __shared__ int scan[256];
   const int W = (n + 31) >> 5;
@@ -279,9 +329,11 @@ __global__ __launch_bounds__(256) void k_cluster_union(int n, int m, const int* 
       const int b = __ffs(x) - 1;
       const int j = (w << 5) + b;
       out_col[t] = j;
+      out_cell[2 * (size_t)t] = px.cell[j >> px.qs];
+      out_cell[2 * (size_t)t + 1] = px.slot[j >> px.qs];
       for (int r = 0; r < m; ++r) {
         const int i = c * m + r;
-        out_pos[(size_t)t * m + r] = i < n ? lut[(size_t)i * n + j] : -1;
+        out_pos[(size_t)t * m + r] = i < n ? ix_find(px, i, j) : -1;
       }
       ++t;
       x &= x - 1u;
@@ -333,26 +385,6 @@ __global__ __launch_bounds__(256) void k_tile4(int n, const int* __restrict__ rp
 // Output-grade tile check, one workgroup per row r: every column c of row r
 // has the whole run (c & ~3) .. (c & ~3) + 3 in row r & ~3 (the first row
 // of r's group).  Any violation sets *bad.
-__global__ __launch_bounds__(256) void k_tile4_out(int n, const int* __restrict__ rp,
-                                                   const int* __restrict__ col,
-                                                   int* __restrict__ bad) {
-  const int r = blockIdx.x;
-  const int r0 = r & ~3;
-  const int q0 = rp[r0], q1 = rp[r0 + 1];
-  for (int p = rp[r] + threadIdx.x; p < rp[r + 1]; p += 256) {
-    const int c0 = col[p] & ~3;
-    bool ok = c0 + 3 < n;
-    for (int t = 0; t < 4 && ok; ++t) {
-      int lo = q0, hi = q1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (col[mid] < c0 + t) lo = mid + 1; else hi = mid;
-      }
-      ok = lo < q1 && col[lo] == c0 + t;
-    }
-    if (!ok) atomicOr(bad, 1);
-  }
-}
 
 __global__ __launch_bounds__(256) void k_items(int n, const int* __restrict__ rp,
                                                int* __restrict__ counts,
@@ -487,7 +519,7 @@ __global__ __launch_bounds__(128) void k_pos_grad(
     const double* __restrict__ pos, double bx, double by, double bz,
     const int* __restrict__ nfun, const int* __restrict__ atom_of, const int* __restrict__ off_of,
     int blk, int n, const int* __restrict__ rp, const int* __restrict__ col,
-    const int* __restrict__ lut, const double* __restrict__ G, const double* __restrict__ GN,
+    Ix x, const double* __restrict__ G, const double* __restrict__ GN,
     double mu, int kind, double R, double decay, uint64_t seed, double scale,
     double* __restrict__ acc) {
 #pragma clang fp contract(off)
@@ -507,7 +539,7 @@ __global__ __launch_bounds__(128) void k_pos_grad(
     if (aj == ai) continue;
     const int oj = off_of ? off_of[j] : 0;
     const int nj = nfun ? nfun[aj] : blk;
-    const int q = lut[(size_t)j * n + i];
+    const int q = ix_find(x, j, i);
     double c = 0.0;
     for (int r = 0; r < blk; ++r)
       for (int cc = 0; cc < blk; ++cc) {
@@ -723,15 +755,111 @@ extern "C" int lnv_pattern_half(const lnv_pattern* P, int32_t* row_ptr, int32_t*
   return LNV_OK;
 }
 
-extern "C" int lnv_pattern_lut(const lnv_pattern* P, int32_t* lut, int32_t* lut_t,
-                               hipStream_t s) {
-  if (!P || !P->row_ptr || !P->col || P->n <= 0) return LNV_EPATTERN;
-  if (!lut && !lut_t) return LNV_OK;
-  const size_t bytes = (size_t)P->n * (size_t)P->n * sizeof(int32_t);
-  if (lut) LNV_HIP(hipMemsetAsync(lut, 0xFF, bytes, s));
-  if (lut_t) LNV_HIP(hipMemsetAsync(lut_t, 0xFF, bytes, s));
-  k_lut<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, lut, lut_t);
-  LNV_LAUNCH_CHECK();
+extern "C" int lnv_cells(const double* pos, int32_t n_units, const double* box,
+                         const int32_t* g, const double* origin, int32_t* cell, int32_t* slot,
+                         int32_t* occ_out, hipStream_t s) {
+  if (!pos || !box || !g || !origin || !cell || !slot || !occ_out || n_units <= 0)
+    return LNV_EINVAL;
+  for (int d = 0; d < 3; ++d)
+    if (g[d] < 1 || g[d] > 1024 || !(box[d] > 0.0)) return LNV_EINVAL;
+  std::vector<double> hp((size_t)n_units * 3);
+  LNV_HIP(hipMemcpyAsync(hp.data(), pos, hp.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  LNV_HIP(hipStreamSynchronize(s));
+  const int64_t ncell = (int64_t)g[0] * g[1] * g[2];
+  if (ncell > ((int64_t)1 << 26)) return LNV_EINVAL;
+  std::vector<int32_t> hc(n_units), hs(n_units), fill((size_t)ncell, 0);
+  int32_t occ = 0;
+  for (int u = 0; u < n_units; ++u) {
+    int c[3];
+    for (int d = 0; d < 3; ++d) {
+      double f = (hp[(size_t)u * 3 + d] - origin[d]) / box[d];
+      f -= std::floor(f);
+      c[d] = std::min(g[d] - 1, std::max(0, (int)(f * g[d])));
+    }
+    hc[u] = c[0] | (c[1] << 10) | (c[2] << 20);
+    const int64_t k = ((int64_t)c[0] * g[1] + c[1]) * g[2] + c[2];
+    hs[u] = fill[(size_t)k]++;
+    occ = std::max(occ, fill[(size_t)k]);
+  }
+  LNV_HIP(hipMemcpyAsync(cell, hc.data(), sizeof(int32_t) * n_units, hipMemcpyHostToDevice, s));
+  LNV_HIP(hipMemcpyAsync(slot, hs.data(), sizeof(int32_t) * n_units, hipMemcpyHostToDevice, s));
+  LNV_HIP(hipStreamSynchronize(s));
+  *occ_out = occ;
+  return LNV_OK;
+}
+
+extern "C" int lnv_pattern_index(lnv_pattern* P, const int32_t* cell, const int32_t* slot,
+                                 const int32_t* g, int32_t occ, int32_t qs, int32_t* tab,
+                                 int64_t cap, int64_t* len_out, hipStream_t s) {
+  if (!P || !cell || !slot || !g || !len_out || occ <= 0 || (qs != 0 && qs != 2))
+    return LNV_EINVAL;
+  if (!P->row_ptr || !P->col || P->n <= 0) return LNV_EPATTERN;
+  if ((P->n & ((1 << qs) - 1)) != 0) return LNV_EPATTERN;
+  for (int d = 0; d < 3; ++d)
+    if (g[d] < 1 || g[d] > 1024) return LNV_EINVAL;
+  if (qs == 2) {  // atom units describe tile4 patterns only
+    int32_t t4 = 0;
+    LNV_TRY(lnv_pattern_tile4(P, &t4, s));
+    if (t4 != 1) return LNV_EPATTERN;
+  }
+  const int nu = P->n >> qs;
+  // window: the largest wrapped offset along each axis
+  int32_t* ext = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&ext), 4 * sizeof(int32_t), s));
+  int32_t hext[4] = {0, 0, 0, 0};
+  hipError_t e = hipMemsetAsync(ext, 0, 4 * sizeof(int32_t), s);
+  if (e == hipSuccess) {
+    k_ix_extent<<<nu, 256, 0, s>>>(nu, qs, P->row_ptr, P->col, cell, g[0], g[1], g[2], ext);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(hext, ext, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t ef = hipFreeAsync(ext, s);
+  if (e == hipSuccess) e = ef;
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return LNV_EHIP;
+  }
+  lnv_index& x = P->ix;
+  x.tab = nullptr;
+  x.cell = cell;
+  x.slot = slot;
+  x.occ = occ;
+  x.qs = qs;
+  int64_t stride = occ;
+  for (int d = 0; d < 3; ++d) {
+    x.g[d] = g[d];
+    x.r[d] = std::min(hext[d], g[d] - 1);
+    x.w[d] = std::min(2 * x.r[d] + 1, g[d]);
+    stride *= x.w[d];
+  }
+  x.stride = stride;
+  *len_out = (int64_t)nu * stride + 1;   // + the trailing -1 entry
+  if (!tab) return LNV_OK;
+  if (cap < *len_out) return LNV_ECAPACITY;
+  int32_t* bad = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int32_t), s));
+  int32_t hbad = 0;
+  e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
+  if (e == hipSuccess) e = hipMemsetAsync(tab, 0xFF, sizeof(int32_t) * (size_t)*len_out, s);
+  if (e == hipSuccess) {
+    x.tab = tab;
+    k_ix_fill<<<nu, 256, 0, s>>>(nu, make_ix(P), P->col, tab, bad);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  const hipError_t ef2 = hipFreeAsync(bad, s);
+  if (e == hipSuccess) e = ef2;
+  if (e != hipSuccess) {
+    x.tab = nullptr;
+    set_hip_error(e);
+    return LNV_EHIP;
+  }
+  if (hbad) {
+    x.tab = nullptr;
+    return LNV_EPATTERN;
+  }
   return LNV_OK;
 }
 
@@ -742,19 +870,15 @@ extern "C" int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStrea
     *ok_out = 0;
     return LNV_OK;
   }
-  int32_t* bad = nullptr;  // [0]: operand grade fails, [1]: output grade fails
-  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), 2 * sizeof(int32_t), s));
-  int32_t hbad[2] = {1, 1};
-  hipError_t e = hipMemsetAsync(bad, 0, 2 * sizeof(int32_t), s);
+  int32_t* bad = nullptr;
+  LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int32_t), s));
+  int32_t hbad[1] = {1};
+  hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
   if (e == hipSuccess) {
     k_tile4<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, bad);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) {
-    k_tile4_out<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, bad + 1);
-    e = hipGetLastError();
-  }
-  if (e == hipSuccess) e = hipMemcpyAsync(hbad, bad, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   const hipError_t ef = hipFreeAsync(bad, s);
   if (e == hipSuccess) e = ef;
@@ -762,7 +886,7 @@ extern "C" int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStrea
     set_hip_error(e);
     return LNV_EHIP;
   }
-  *ok_out = hbad[0] == 0 ? 1 : (hbad[1] == 0 ? 2 : 0);
+  *ok_out = hbad[0] == 0 ? 1 : 0;
   return LNV_OK;
 }
 
@@ -842,16 +966,17 @@ extern "C" int lnv_forces(const double* pos, const double* box, const int32_t* n
   if (GNS && (!bsm_ok(GNS) || GNS->pat != GS->pat)) return LNV_EPATTERN;
   const lnv_pattern *ps = GS->pat, *ph = GH->pat;
   if (GS->blk != GH->blk || GS->blk <= 0 || GS->blk > 16) return LNV_EUNSUPPORTED;
-  if (ps->n != ph->n || !ps->lut || !ph->lut || !ps->row_ptr || !ph->row_ptr) return LNV_EPATTERN;
+  if (ps->n != ph->n || !has_ix(ps) || !has_ix(ph) || !ps->row_ptr || !ph->row_ptr)
+    return LNV_EPATTERN;
   const int n = ps->n;
   LNV_HIP(hipMemsetAsync(acc, 0, sizeof(double) * 3 * (size_t)n, s));
   k_pos_grad<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, atom_of, off_of, GS->blk, n,
-                               ps->row_ptr, ps->col, ps->lut, static_cast<const double*>(GS->val),
+                               ps->row_ptr, ps->col, make_ix(ps), static_cast<const double*>(GS->val),
                                GNS ? static_cast<const double*>(GNS->val) : nullptr, mu, 0, R_S,
                                decay_S, seed, scale, acc);
   LNV_LAUNCH_CHECK();
   k_pos_grad<<<n, 128, 0, s>>>(pos, box[0], box[1], box[2], nfun, atom_of, off_of, GH->blk, n,
-                               ph->row_ptr, ph->col, ph->lut, static_cast<const double*>(GH->val),
+                               ph->row_ptr, ph->col, make_ix(ph), static_cast<const double*>(GH->val),
                                nullptr, 0.0, 1, R_H, decay_H, seed, scale, acc);
   LNV_LAUNCH_CHECK();
   k_seg_force<<<(n_seg + 63) / 64, 64, 0, s>>>(n_seg, seg_ptr, seg_atom, acc, F);
@@ -880,14 +1005,14 @@ extern "C" int lnv_synth_blocks_cells(const double* pos, const int32_t* cell_of,
 extern "C" int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT,
                                          int32_t* perm, hipStream_t s) {
   if (!P || !PT || !perm) return LNV_EINVAL;
-  if (!P->row_ptr || !P->col || !PT->lut || P->n != PT->n || P->n <= 0 ||
+  if (!P->row_ptr || !P->col || !has_ix(PT) || P->n != PT->n || P->n <= 0 ||
       P->nnzb != PT->nnzb)
     return LNV_EPATTERN;
   int32_t* bad = nullptr;
   LNV_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int32_t), s));
   hipError_t e = hipMemsetAsync(bad, 0, sizeof(int32_t), s);
   if (e == hipSuccess) {
-    k_tmap<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, PT->lut, perm, bad);
+    k_tmap<<<P->n, 256, 0, s>>>(P->n, P->row_ptr, P->col, make_ix(PT), perm, bad);
     e = hipGetLastError();
   }
   int32_t hbad = 0;
@@ -906,18 +1031,18 @@ extern "C" int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern
 }
 
 extern "C" int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_ptr,
-                                   int32_t* cl_col, int32_t* cl_pos, int64_t cap,
-                                   int32_t* cl_items, int64_t items_cap, int64_t* len_out,
-                                   int32_t* n_items_out, hipStream_t s) {
+                                   int32_t* cl_col, int32_t* cl_pos, int32_t* cl_cell,
+                                   int64_t cap, int32_t* cl_items, int64_t items_cap,
+                                   int64_t* len_out, int32_t* n_items_out, hipStream_t s) {
   if (!P || !cl_ptr || !len_out || !n_items_out) return LNV_EINVAL;
-  if (!((m == 4 && g == 1) || (m == 8 && g == 2) || (m == 16 && (g == 4 || g == 8))))
-    return LNV_EUNSUPPORTED;
-  if (!P->row_ptr || !P->col || !P->lut || P->n <= 0 || P->n > LNV_MAX_ATOMS) return LNV_EPATTERN;
+  if (!((m == 4 && g == 1) || (m == 16 && (g == 4 || g == 8)))) return LNV_EUNSUPPORTED;
+  if (!P->row_ptr || !P->col || !has_ix(P) || P->n <= 0 || P->n > LNV_MAX_ATOMS)
+    return LNV_EPATTERN;
   const int n = P->n;
   const int nc = (n + m - 1) / m;
   const size_t lds = (size_t)((n + 31) / 32) * sizeof(unsigned int);
-  k_cluster_union<<<nc, 256, lds, s>>>(n, m, P->row_ptr, P->col, P->lut, cl_ptr, nullptr,
-                                       nullptr, nullptr, 0);
+  k_cluster_union<<<nc, 256, lds, s>>>(n, m, P->row_ptr, P->col, make_ix(P), cl_ptr, nullptr,
+                                       nullptr, nullptr, nullptr, 0);
   LNV_LAUNCH_CHECK();
   k_scan<int32_t><<<1, 1024, 0, s>>>(cl_ptr, nc);
   LNV_LAUNCH_CHECK();
@@ -943,13 +1068,13 @@ extern "C" int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, i
   } else {
     *n_items_out = nit;
     if (cl_col) {
-      if (!cl_pos || !cl_items) {
+      if (!cl_pos || !cl_items || !cl_cell) {
         st = LNV_EINVAL;
       } else if (cap < *len_out || items_cap < nit) {
         st = LNV_ECAPACITY;
       } else {
-        k_cluster_union<<<nc, 256, lds, s>>>(n, m, P->row_ptr, P->col, P->lut, nullptr, cl_ptr,
-                                             cl_col, cl_pos, 1);
+        k_cluster_union<<<nc, 256, lds, s>>>(n, m, P->row_ptr, P->col, make_ix(P), nullptr,
+                                             cl_ptr, cl_col, cl_pos, cl_cell, 1);
         e = hipGetLastError();
         if (e == hipSuccess) {
           k_cluster_items<<<gi, 256, 0, s>>>(nc, piece, cl_ptr, nullptr, cnt, cl_items);

@@ -30,13 +30,19 @@ ST_NONFINITE, ST_NO_ALPHA, ST_NO_DELTA, ST_DELTA_CAPPED = 1, 2, 4, 8
 ST_GUARD, ST_RUNAWAY = 16, 32
 
 
+class LnvIndex(ctypes.Structure):
+    _fields_ = [("tab", c_void_p), ("cell", c_void_p), ("slot", c_void_p),
+                ("g", c_int32 * 3), ("r", c_int32 * 3), ("w", c_int32 * 3),
+                ("occ", c_int32), ("qs", c_int32), ("stride", c_int64)]
+
+
 class LnvPattern(ctypes.Structure):
     _fields_ = [("n", c_int32), ("n_items", c_int32), ("nnzb", c_int64),
-                ("row_ptr", c_void_p), ("col", c_void_p), ("lut", c_void_p),
-                ("lut_t", c_void_p), ("items", c_void_p),
+                ("row_ptr", c_void_p), ("col", c_void_p), ("ix", LnvIndex),
+                ("items", c_void_p),
                 ("cl_m", c_int32), ("cl_g", c_int32), ("n_cl_items", c_int32), ("tile4", c_int32),
                 ("cl_ptr", c_void_p), ("cl_col", c_void_p), ("cl_pos", c_void_p),
-                ("cl_items", c_void_p)]
+                ("cl_items", c_void_p), ("cl_cell", c_void_p)]
 
 
 class LnvBsm(ctypes.Structure):
@@ -93,14 +99,17 @@ SIGNATURES = {
                                c_void_p, c_int64, POINTER(c_int64), c_void_p]),
     "lnv_pattern_product": (c_int, [PPat, PPat, PPat, c_void_p, c_void_p, c_int64,
                                     POINTER(c_int64), c_void_p, POINTER(c_int64), c_void_p]),
-    "lnv_pattern_lut": (c_int, [PPat, c_void_p, c_void_p, c_void_p]),
+    "lnv_cells": (c_int, [c_void_p, c_int32, POINTER(c_double), POINTER(c_int32),
+                          POINTER(c_double), c_void_p, c_void_p, POINTER(c_int32), c_void_p]),
+    "lnv_pattern_index": (c_int, [PPat, c_void_p, c_void_p, POINTER(c_int32), c_int32, c_int32,
+                                  c_void_p, c_int64, POINTER(c_int64), c_void_p]),
     "lnv_pattern_half": (c_int, [PPat, c_void_p, c_void_p, c_int64, POINTER(c_int64), c_void_p]),
     "lnv_pattern_flops": (c_int, [PPat, PPat, PPat, c_void_p, POINTER(c_int64), c_void_p]),
     "lnv_pattern_items": (c_int, [PPat, c_void_p, c_int64, POINTER(c_int32), c_void_p]),
     "lnv_pattern_transpose_map": (c_int, [PPat, PPat, c_void_p, c_void_p]),
-    "lnv_pattern_cluster": (c_int, [PPat, c_int32, c_int32, c_void_p, c_void_p, c_void_p, c_int64,
-                                    c_void_p, c_int64, POINTER(c_int64), POINTER(c_int32),
-                                    c_void_p]),
+    "lnv_pattern_cluster": (c_int, [PPat, c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+                                    c_void_p, c_int64, c_void_p, c_int64, POINTER(c_int64),
+                                    POINTER(c_int32), c_void_p]),
     "lnv_pattern_tile4": (c_int, [PPat, POINTER(c_int32), c_void_p]),
     "lnv_bsm_transpose": (c_int, [PBsm, c_void_p, PBsm, c_void_p]),
     "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, c_void_p, c_void_p, PBsm,
@@ -134,7 +143,6 @@ SIGNATURES = {
     "lnv_bsm_lincomb": (c_int, [c_double, PBsm, c_double, PBsm, c_double, PBsm, PBsm, c_void_p]),
     "lnv_bsm_norm_inf": (c_int, [PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_bsm_remap": (c_int, [PBsm, PBsm, c_void_p]),
-    "lnv_set_kslabs": (c_int, [c_int32]),
     "lnv_set_f32_accumulation": (c_int, [c_int32]),
     "lnv_timing_enable": (c_int, [c_int32]),
     "lnv_timing_read": (c_int, [POINTER(c_double), POINTER(c_int64)]),

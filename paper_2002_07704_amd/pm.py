@@ -56,8 +56,7 @@ def pm_initial_L(system, n_iter=100, tol=1e-12):
     if system.metric is None:
         raise ValueError("canonical purification needs the metric T ~ S^-1")
     system.adjoint_setup()                       # pat(H.L) with index table and work list
-    if system.pH.lut is None:
-        system.pH.build_lut(lut=True)
+    system.pH.build_index()
     n = float(np.sum(system.w.nfun)) if system.w is not None else float(system.fun_rows.sum())
     theta = system.n_elec / 2.0
     T, S, H = system.T, system.S, system.H

@@ -29,19 +29,76 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+class Cells:
+    """The spatial cells of a system's units (rows, or with qs = 2 the atoms
+    of four rows): lnv_cells on a g[0] x g[1] x g[2] grid of the box.  Every
+    pattern of the system indexes its blocks through them (lnv_index)."""
+
+    def __init__(self, pos_units, box, g, qs, dev, origin=None):
+        pos_units = np.ascontiguousarray(pos_units, dtype=np.float64)
+        self.n_units = int(pos_units.shape[0])
+        self.qs = int(qs)
+        self.g = tuple(int(x) for x in g)
+        self.box = tuple(float(b) for b in box)
+        self.origin = tuple(float(o) for o in (origin if origin is not None else
+                                               [b / gg / 8.0 for b, gg in zip(self.box, self.g)]))
+        pos_d = torch.as_tensor(pos_units, device=dev)
+        self.cell = torch.empty(self.n_units, dtype=torch.int32, device=dev)
+        self.slot = torch.empty(self.n_units, dtype=torch.int32, device=dev)
+        occ = c_int32(0)
+        L_.call("lnv_cells", _ptr(pos_d), self.n_units, (c_double * 3)(*self.box),
+                (c_int32 * 3)(*self.g), (c_double * 3)(*self.origin), _ptr(self.cell),
+                _ptr(self.slot), byref(occ), _stream())
+        self.occ = int(occ.value)
+
+    @staticmethod
+    def single(n_units, dev):
+        """One cell holding every unit (the index is then the dense n x n
+        table): for patterns that come without positions."""
+        return Cells(np.zeros((n_units, 3)), (1.0, 1.0, 1.0), (1, 1, 1), 0, dev,
+                     origin=(0.0, 0.0, 0.0))
+
+    @staticmethod
+    def choose_grid(pos_units, box, ranges, max_g=1024):
+        """Grid of the spatial index: the cells (edge box/g per axis) that
+        minimise the summed table sizes of patterns with the given ranges --
+        per row unit, (window cells) x (fullest cell's count), the window
+        reaching floor(R/edge) + 1 cells each way, at most the whole axis.
+        One cell per axis is the dense table."""
+        pos = np.asarray(pos_units, dtype=np.float64)
+        box = np.asarray(box, dtype=np.float64)
+        best, best_cost = (1, 1, 1), None
+        kmax = int(min(max_g, max(1, np.floor(box.min() / 2.0))))
+        for k in range(1, kmax + 1):
+            g = np.maximum(1, np.round(box / (box.min() / k))).astype(np.int64)
+            if np.any(g > max_g):
+                break
+            edge = box / g
+            c = np.minimum((np.mod(pos / box, 1.0) * g).astype(np.int64), g - 1)
+            key = (c[:, 0] * g[1] + c[:, 1]) * g[2] + c[:, 2]
+            occ = int(np.bincount(key).max())
+            cost = 0
+            for R in ranges:
+                w = np.minimum(2 * (np.floor(R / edge) + 1) + 1, g)
+                cost += int(np.prod(w)) * occ
+            if best_cost is None or cost < best_cost:
+                best, best_cost = tuple(int(x) for x in g), cost
+        return best
+
+
 class Pattern:
     """Atom-block CSR pattern on the device plus its optional tables."""
 
-    def __init__(self, n, row_ptr, col):
+    def __init__(self, n, row_ptr, col, cells=None):
         self.n = int(n)
         self.row_ptr = row_ptr
         self.col = col
-        self.lut = None
-        self.lut_t = None
+        self.cells = cells      # the system's Cells (for the spatial index)
+        self.ix_tab = None      # lnv_index table (device)
         self.items = None
         self.triples = None
-        self.cl = None          # (m, g, cl_ptr, cl_col, cl_pos, cl_items)
-        self.tile4 = 0          # lnv_pattern_tile4 grade (1 tile4, 2 tile-complete, 0)
+        self.cl = None          # (m, g, cl_ptr, cl_col, cl_pos, cl_items, cl_cell)
+        self.tile4 = 0          # lnv_pattern_tile4 grade (1 tile4, 0)
         self.struct = L_.LnvPattern()
         self._sync()
 
@@ -49,45 +106,59 @@ class Pattern:
     def nnzb(self):
         return int(self.col.numel())
 
+    @property
+    def has_index(self):
+        return self.ix_tab is not None
+
     def _sync(self):
         s = self.struct
         s.n = self.n
         s.nnzb = self.nnzb
         s.row_ptr = self.row_ptr.data_ptr()
         s.col = self.col.data_ptr() if self.col.numel() else self.row_ptr.data_ptr()
-        s.lut = self.lut.data_ptr() if self.lut is not None else None
-        s.lut_t = self.lut_t.data_ptr() if self.lut_t is not None else None
+        s.ix.tab = self.ix_tab.data_ptr() if self.ix_tab is not None else None
         s.items = self.items.data_ptr() if self.items is not None else None
         s.n_items = 0 if self.items is None else self.items.numel() // 2
         if self.cl is not None:
-            m, g, cptr, ccol, cpos, citems = self.cl
+            m, g, cptr, ccol, cpos, citems, ccell = self.cl
             s.cl_m, s.cl_g, s.n_cl_items = m, g, citems.numel() // 2
             s.cl_ptr, s.cl_col = cptr.data_ptr(), ccol.data_ptr()
             s.cl_pos, s.cl_items = cpos.data_ptr(), citems.data_ptr()
+            s.cl_cell = ccell.data_ptr()
         else:
             s.cl_m = s.cl_g = s.n_cl_items = 0
         s.tile4 = self.tile4
 
     def check_tile4(self):
-        """lnv_pattern_tile4: may the atom-tile multiply read this pattern by
-        tiles (1: 4 rows per atom, columns in aligned runs of 4) or write it
-        (1, or 2: tile-complete, e.g. the half of a tile4 pattern)?"""
+        """lnv_pattern_tile4: may the atom-tile multiply read and write this
+        pattern by tiles (1: 4 rows per atom, columns in aligned runs of 4)?"""
         ok = c_int32(0)
         L_.call("lnv_pattern_tile4", byref(self.struct), byref(ok), _stream())
         self.tile4 = int(ok.value)
         self._sync()
         return self.tile4
 
-    def build_lut(self, lut=True, lut_t=False):
-        dev = self.row_ptr.device
-        if lut and self.lut is None:
-            self.lut = torch.empty(self.n * self.n, dtype=torch.int32, device=dev)
-        if lut_t and self.lut_t is None:
-            self.lut_t = torch.empty(self.n * self.n, dtype=torch.int32, device=dev)
+    def build_index(self):
+        """The spatial index of the pattern over its system's cells
+        (lnv_pattern_index, two-phase); idempotent."""
+        if self.ix_tab is not None:
+            return self
+        if self.cells is None:
+            self.cells = Cells.single(self.n, self.row_ptr.device)
+        c = self.cells
+        ln = c_int64(0)
+        g = (c_int32 * 3)(*c.g)
+        L_.call("lnv_pattern_index", byref(self.struct), _ptr(c.cell), _ptr(c.slot), g, c.occ,
+                c.qs, None, 0, byref(ln), _stream())
+        tab = torch.empty(ln.value, dtype=torch.int32, device=self.row_ptr.device)
+        L_.call("lnv_pattern_index", byref(self.struct), _ptr(c.cell), _ptr(c.slot), g, c.occ,
+                c.qs, _ptr(tab), tab.numel(), byref(ln), _stream())
+        self.ix_tab = tab
         self._sync()
-        L_.call("lnv_pattern_lut", byref(self.struct), _ptr(self.lut) if lut else None,
-                _ptr(self.lut_t) if lut_t else None, _stream())
         return self
+
+    def index_bytes(self):
+        return 0 if self.ix_tab is None else self.ix_tab.numel() * 4
 
     def build_items(self):
         cnt = c_int32(0)
@@ -102,20 +173,24 @@ class Pattern:
         return self
 
     def build_cluster(self, m, g):
-        """Cluster plan for clusters of m consecutive rows, g lanes per column."""
+        """Cluster plan for clusters of m consecutive rows, g lanes per column
+        (builds the pattern's index first)."""
+        self.build_index()
         dev = self.row_ptr.device
         nc = (self.n + m - 1) // m
         cptr = torch.empty(nc + 1, dtype=torch.int32, device=dev)
         ln = c_int64(0)
         ni = c_int32(0)
-        L_.call("lnv_pattern_cluster", byref(self.struct), m, g, _ptr(cptr), None, None, 0, None, 0,
-                byref(ln), byref(ni), _stream())
+        L_.call("lnv_pattern_cluster", byref(self.struct), m, g, _ptr(cptr), None, None, None, 0,
+                None, 0, byref(ln), byref(ni), _stream())
         ccol = torch.empty(max(1, ln.value), dtype=torch.int32, device=dev)
         cpos = torch.empty(max(1, ln.value * m), dtype=torch.int32, device=dev)
+        ccell = torch.empty(max(2, 2 * ln.value), dtype=torch.int32, device=dev)
         citems = torch.empty(max(2, 2 * ni.value), dtype=torch.int32, device=dev)
         L_.call("lnv_pattern_cluster", byref(self.struct), m, g, _ptr(cptr), _ptr(ccol), _ptr(cpos),
-                ccol.numel(), _ptr(citems), citems.numel() // 2, byref(ln), byref(ni), _stream())
-        self.cl = (m, g, cptr, ccol, cpos, citems[:2 * ni.value])
+                _ptr(ccell), ccol.numel(), _ptr(citems), citems.numel() // 2, byref(ln),
+                byref(ni), _stream())
+        self.cl = (m, g, cptr, ccol, cpos, citems[:2 * ni.value], ccell)
         self._sync()
         if m == 16:
             self.check_tile4()
@@ -213,7 +288,7 @@ def product_pattern(A, B, mask=None, triples=True):
     col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=dev)
     L_.call("lnv_pattern_product", byref(A.struct), byref(B.struct), mp, _ptr(rp), _ptr(col),
             col.numel(), byref(nnz), None, None, _stream())
-    P = Pattern(n, rp, col[:nnz.value])
+    P = Pattern(n, rp, col[:nnz.value], A.cells)
     P.triples = tr.value if triples else None
     return P
 
@@ -229,14 +304,13 @@ def half_pattern(P):
     col = torch.empty(max(1, nnz.value), dtype=torch.int32, device=dev)
     L_.call("lnv_pattern_half", byref(P.struct), _ptr(rp), _ptr(col), col.numel(), byref(nnz),
             _stream())
-    return Pattern(P.n, rp, col[:nnz.value]).build_items().build_lut(lut=True)
+    return Pattern(P.n, rp, col[:nnz.value], P.cells).build_items().build_index()
 
 
 def is_symmetric(P):
     """Whether every block (i, j) of P has its transpose (j, i) in P (on the
-    device, through the transpose map of P onto itself; builds P's lut)."""
-    if P.lut is None:
-        P.build_lut(lut=True)
+    device, through the transpose map of P onto itself; builds P's index)."""
+    P.build_index()
     try:
         transpose_map(P, P)
     except L_.LnvError as e:
@@ -380,16 +454,16 @@ class LNVSystem:
                 self.triples_upper["TGT"] = product_pattern(self.pL, self.pLL,
                                                             mask=self.pLu).triples
         # index tables and work lists
-        self.pL.build_lut(lut=True).build_items()
-        self.pS.build_lut(lut=True)
+        self.pL.build_index().build_items()
+        self.pS.build_index()
         self.pH.build_items()
-        self.pSL.build_lut(lut=metric is not None).build_items()
-        self.pLS.build_lut(lut=True)
-        self.pX.build_lut(lut=True).build_items()
-        self.pXT.build_lut(lut=True)
-        self.pZ.build_lut(lut=True).build_items()
+        self.pSL.build_index().build_items()
+        self.pLS.build_index()
+        self.pX.build_index().build_items()
+        self.pXT.build_index()
+        self.pZ.build_index().build_items()
         if metric is not None:
-            self.pLL.build_lut(lut=True).build_items()
+            self.pLL.build_index().build_items()
         assert self.pX.nnzb >= self.pZ.nnzb
         self.cluster = None
         if cluster is not None:
@@ -560,8 +634,8 @@ class LNVSystem:
 
     def set_cluster(self, shape):
         """Row-cluster shape of the multiply: (4, 1) (4 rows per wave, one lane
-        per output column), (8, 2) (8 rows, two lanes per column), None
-        (one row per wave), or the atom tiles (16, 4) / (16, 8) (16-row
+        per output column), None (one row per wave), or the atom tiles
+        (16, 4) / (16, 8) (16-row
         plans: 4 atoms of 4 rows, products of whole 16x16 atom tiles on the
         matrix cores; right operands need tile4).  Rebuilds the plans in
         place."""
@@ -573,13 +647,7 @@ class LNVSystem:
                 P.cl = None
                 P._sync()
                 continue
-            tmp = P.lut is None
-            if tmp:
-                P.build_lut(lut=True)
             P.build_cluster(*shape)
-            if tmp:
-                P.lut = None
-                P._sync()
         self.cluster = shape
         self._size_partials()
         torch.cuda.synchronize()
@@ -633,6 +701,14 @@ class LNVSystem:
         self.pS = neighbours(self.pos, self.box, self.R_S)
         self.pH = neighbours(self.pos, self.box, self.R_H)
         self.pL = neighbours(self.pos, self.box, self.R_L)
+        # cells of the spatial index: atoms of 4 rows each (13 support
+        # functions) are the index's units, else the rows
+        qs = 2 if self.split and self.n_rows == 4 * self.n else 0
+        units = pos_rows[::4] if qs else pos_rows
+        g = Cells.choose_grid(units, self.box, self._index_ranges())
+        self.ix_cells = Cells(units, self.box, g, qs, dev)
+        for P in (self.pS, self.pH, self.pL):
+            P.cells = self.ix_cells
         # a1: synthetic S, H
         self.S = self.synth_values(0, self.pS, self.R_S, 3.0, self.seed)
         self.H = self.synth_values(1, self.pH, self.R_H, 2.5, self.seed)
@@ -682,8 +758,24 @@ class LNVSystem:
         self.pS = self._neighbours_cells(self.R_S)
         self.pH = self._neighbours_cells(self.R_H)
         self.pL = self._neighbours_cells(self.R_L)
+        # spatial index: one index cell per batch cell (their patterns are
+        # block diagonal, so each row's window is its own cell)
+        nc = len(cells)
+        units = np.zeros((self.n_rows, 3))
+        units[:, 0] = np.repeat(np.arange(nc), np.diff(self.cell_rows)) + 0.5
+        units[:, 1:] = 0.5
+        self.ix_cells = Cells(units, (float(nc), 1.0, 1.0), (nc, 1, 1), 0, dev,
+                              origin=(0.0, 0.0, 0.0))
+        for P in (self.pS, self.pH, self.pL):
+            P.cells = self.ix_cells
         self.S = self.synth_values(0, self.pS, self.R_S, 3.0, None)
         self.H = self.synth_values(1, self.pH, self.R_H, 2.5, None)
+
+    def _index_ranges(self):
+        """Ranges of the patterns that get a spatial index (S, H, L and the
+        natural-range products), for the choice of its grid."""
+        rs, rh, rl = self.R_S, self.R_H, self.R_L
+        return (rs, rh, rl, rs + rl, rh + rl + rs, 2 * rs + rl, 2 * rl, 2 * rl + rs, rh + rl)
 
     def _neighbours_cells(self, R):
         n, nc = self.n_rows, len(self.cells)
@@ -727,7 +819,7 @@ class LNVSystem:
         self.pLSL = product_pattern(self.pL, self.pSL)           # L.S.L
         self.pHL = product_pattern(self.pH, self.pL)             # H.L
         self.pLH = product_pattern(self.pL, self.pH, triples=False)   # L.H = pat(H.L)^T
-        self.pLH.build_lut(lut=True)      # for the transpose map and the plan only
+        self.pLH.build_index()
         self.perm_HL = transpose_map(self.pHL, self.pLH)
         # the restricted products with L.S.L take it on the right: P_H(LS.LSL),
         # P_S(LH.LSL) (the transposes LS, LH are formed per call)
@@ -738,18 +830,18 @@ class LNVSystem:
             dS4=product_pattern(self.pLH, self.pLSL, mask=self.pS).triples,
             dS6=product_pattern(self.pL, self.pHL, mask=self.pS).triples,
         )
-        self.pSL.build_lut(lut=True)
-        self.pLSL.build_lut(lut=True).build_items()
+        self.pSL.build_index()
+        self.pLSL.build_index().build_items()
         self.pLS.build_items()
         self.pLH.build_items()
-        self.pHL.build_lut(lut=True).build_items()
-        self.pS.build_lut(lut=True).build_items()
+        self.pHL.build_index().build_items()
+        self.pS.build_index().build_items()
         adj_upper = []
         if self.symmetric:
             # halves of the symmetric adjoint products (L.S.L and H get index
             # tables)
-            self.pLSL.build_lut(lut=True)
-            self.pH.build_lut(lut=True)
+            self.pLSL.build_index()
+            self.pH.build_index()
             self.pLSLu, self.pHu, self.pSu = (half_pattern(P) for P in
                                               (self.pLSL, self.pH, self.pS))
             adj_upper = [self.pLSLu, self.pHu, self.pSu]
@@ -769,8 +861,6 @@ class LNVSystem:
                 self.pSL.check_tile4()
             for P in adj_upper:
                 P.build_cluster(*self.cluster)
-        self.pLH.lut = None
-        self.pLH._sync()
         self.LSL = Matrix(self.pLSL)
         self.HL = Matrix(self.pHL)
         self.YS = torch.zeros(self.pS.nnzb, BLK, BLK, dtype=torch.float64, device=dev)
@@ -840,8 +930,7 @@ class LNVSystem:
         if self.cells is not None:
             raise NotImplementedError("forces of a batch of cells")
         self.adjoint_setup()
-        if self.pH.lut is None:
-            self.pH.build_lut(lut=True)
+        self.pH.build_index()
         Lv = self.L.val if L is None else L
         dS = torch.empty_like(self.S.val)
         dH = torch.empty_like(self.H.val)

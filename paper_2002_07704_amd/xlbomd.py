@@ -113,8 +113,7 @@ class XLBOMD:
                     self.n_hotelling, ctypes.byref(s.ws), _stream())
         else:
             old_pLS, old_hist, old_LS = self.pLS, self.hist, self.LS
-            if old_pLS.lut is None:
-                old_pLS.build_lut(lut=True)
+            old_pLS.build_index()
             self.s = s = self._build(self.w)
             self.hist = [_remap(h, Matrix(self.pLS)) for h in old_hist]
             self.LS = _remap(old_LS, Matrix(self.pLS))

@@ -49,12 +49,13 @@ def test_host_side_argument_errors(lib):
     assert lib.lnv_neighbours(ctypes.c_void_p(8), 4, bad, 3.0, ctypes.c_void_p(8), None, 0, ctypes.byref(nnz), None) == L.EINVAL
     # multiply with missing matrices / unsupported block edge / missing tables
     assert lib.lnv_bsm_multiply(1.0, None, None, 0, 0.0, None, None) == L.EINVAL
-    p = L.LnvPattern(n=4, n_items=1, nnzb=4, row_ptr=8, col=8, lut=None, lut_t=None, items=8)
+    p = L.LnvPattern(n=4, n_items=1, nnzb=4, row_ptr=8, col=8, items=8)
     m = L.LnvBsm(pat=ctypes.pointer(p), blk=4, dtype=L.F64, val=8)
     m5 = L.LnvBsm(pat=ctypes.pointer(p), blk=5, dtype=L.F64, val=8)
     assert lib.lnv_bsm_multiply(1.0, ctypes.byref(m5), ctypes.byref(m), 0, 0.0, ctypes.byref(m), None) == L.EUNSUPPORTED
     assert lib.lnv_bsm_multiply(1.0, ctypes.byref(m), ctypes.byref(m), 0, 0.0, ctypes.byref(m), None) == L.EPATTERN
-    q = L.LnvPattern(n=5, n_items=1, nnzb=4, row_ptr=8, col=8, lut=8, lut_t=8, items=8)
+    q = L.LnvPattern(n=5, n_items=1, nnzb=4, row_ptr=8, col=8, items=8)
+    q.ix.tab = 8
     mq = L.LnvBsm(pat=ctypes.pointer(q), blk=4, dtype=L.F64, val=8)
     assert lib.lnv_bsm_multiply(1.0, ctypes.byref(m), ctypes.byref(mq), 0, 0.0, ctypes.byref(m), None) == L.EPATTERN
     # CG step: bad options are rejected before anything else

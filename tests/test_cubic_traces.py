@@ -4,7 +4,7 @@ Along a direction P the energy and the electron number are cubics whose
 coefficients need T0 = Tr[PMPS], T1 = Tr[LSPSPM], T2 = Tr[PSPSPM] and
 T3 = Tr[PSLSPM] (M = H - mu S, or S).  The device takes T3 = <L, Q>,
 T2 = <P, Q> and T1 = <P, S L X_P> with the symmetric Q = S P M P S formed on
-the half of L's pattern only (weight 2 off the diagonal).  Here the cubics so
+the half of L's pattern only (weight 2 for pairs of row groups).  Here the cubics so
 formed are checked against the oracle's E and N at points along the line.
 """
 import numpy as np
@@ -16,8 +16,9 @@ from oracle import structure as ost
 
 def _half_weights(rp, col, n):
     """Weight of each block of the symmetric pattern under the device's half:
-    2 for blocks in the half off the diagonal, 1 on the diagonal, 0 outside
-    (rows grouped in fours, cyclic group offset below m/2, as in_half)."""
+    1 inside a row group (both (i, j) and (j, i) kept), 2 for the kept block
+    of a pair from two groups, 0 outside (rows grouped in fours, cyclic group
+    offset below m/2, as in_half)."""
     g = 2 if n % 4 == 0 else 0
     m = n >> g
     wts = np.zeros((n, n))
@@ -25,12 +26,11 @@ def _half_weights(rp, col, n):
         for j in col[rp[i]:rp[i + 1]]:
             A, B = i >> g, j >> g
             if A == B:
-                keep = j >= i
-            else:
-                D = (B - A) % m
-                keep = 2 * D < m or (2 * D == m and A < B)
-            if keep:
-                wts[i, j] = 1.0 if i == j else 2.0
+                wts[i, j] = 1.0
+                continue
+            D = (B - A) % m
+            if 2 * D < m or (2 * D == m and A < B):
+                wts[i, j] = 2.0
     return wts
 
 

@@ -190,7 +190,7 @@ def test_cluster_shapes_agree_and_autotune(sioh48):
     Ld = _rand_sym(n, ref.maskL, 13) + 0.2 * np.eye(n) * ref.maskL
     sysg.L.val.copy_(lay.to_blocks(Ld, sysg.pL))
     out = {}
-    for shape in ((4, 1), (8, 2), None):
+    for shape in ((4, 1), None):
         sysg.set_cluster(shape)
         sysg.eval()
         torch.cuda.synchronize()

@@ -108,7 +108,7 @@ def test_tile_eval_matches_oracle(cells, name, shape):
     EN4, G4 = s.EN.clone(), s.G.val.clone()
     s.set_cluster(shape)
     assert s.pS.cl[0] == 16 and s.pS.tile4 == 1 and s.pLS.tile4 == 1 and s.pX.tile4 == 1
-    assert s.pLu.tile4 == 2 and s.pZu.tile4 == 2     # halves: outputs only
+    assert s.pLu.tile4 == 1 and s.pZu.tile4 == 1     # halves keep whole atom tiles
     print(f"{name} {shape}: {s.n} atoms, {s.n_rows} rows, pieces of L {s.pL.struct.n_cl_items}",
           flush=True)
     s.eval()
@@ -267,145 +267,3 @@ def test_tile_eval_at_scale(gpu, order):
         tol = _tol(s, acc)
         assert abs(E - E4) / w.n <= 1e-6 and abs(N - N4) <= tol * abs(N4)
         assert dG <= tol
-
-
-# ------------------------------------------------------------------ atom quads
-# 4-function atoms on 16-row plans: 16x16 matrix tiles of 4 x 4 atom blocks.
-
-def _w4(name, pos, box, seed):
-    n = pos.shape[0]
-    return W.Workload(name=name, pos=np.mod(pos, box), box=np.asarray(box, dtype=np.float64),
-                      nfun=np.full(n, 4, dtype=np.int32), species=np.zeros(n, dtype=np.int8),
-                      R_S=12.0, R_H=14.0, R_L=16.0, n_elec=4 * n, seed=seed, scale=1.0,
-                      blk_pad=4)
-
-
-class Layout4:
-    """Orbital <-> 4x4 block maps of a system with one row per atom."""
-
-    def __init__(self, s):
-        self.n_orb = 4 * s.n
-
-    def to_dense(self, V, pat):
-        rp, col = pat.host()
-        V = V.detach().cpu().double().numpy()
-        A = np.zeros((self.n_orb, self.n_orb))
-        for i in range(len(rp) - 1):
-            for p in range(rp[i], rp[i + 1]):
-                j = col[p]
-                A[4 * i:4 * i + 4, 4 * j:4 * j + 4] = V[p]
-        return A
-
-    def to_blocks(self, A, pat):
-        rp, col = pat.host()
-        out = np.zeros((len(col), 4, 4))
-        for i in range(len(rp) - 1):
-            for p in range(rp[i], rp[i + 1]):
-                j = col[p]
-                out[p] = A[4 * i:4 * i + 4, 4 * j:4 * j + 4]
-        return torch.as_tensor(out)
-
-
-@pytest.fixture(scope="module")
-def quads(gpu):
-    from paper_2002_07704_amd.system import LNVSystem
-    pos22, box22 = W.amorphous_positions(22, 0.0074, 3.0, seed=33)
-    out = {}
-    for name, w in (("si64", W.get("si64_4x4")), ("am22", _w4("am22_4f", pos22, box22, 33))):
-        s = LNVSystem(w, metric="hotelling", n_hotelling=16)
-        assert not s.split
-        out[name] = (s, ost.System(w), Layout4(s))
-    return out
-
-
-@pytest.mark.parametrize("shape", SHAPES)
-@pytest.mark.parametrize("name", ["si64", "am22"])
-def test_quad_eval_matches_oracle(quads, name, shape):
-    s, ref, lay = quads[name]
-    w = s.w
-    Ld = _seeded_L(s, ref, lay, 5)
-    s.set_cluster((4, 1))
-    s.eval()
-    torch.cuda.synchronize()
-    EN4, G4 = s.EN.clone(), s.G.val.clone()
-    s.set_cluster(shape)
-    assert s.pS.cl[0] == 16 and s.pL.tile4 != 1
-    s.eval()
-    torch.cuda.synchronize()
-    E, N = (float(x) for x in s.EN.cpu())
-    Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
-    print(f"quads {name} {shape}: |dE|/atom {abs(E - Er) / w.n:.2e}", flush=True)
-    assert abs(E - Er) / w.n <= 1e-10 and abs(N - Nr) / w.n <= 1e-10
-    G = lay.to_dense(s.G.val, s.pL)
-    F = lay.to_dense(s.F.val, s.pL)
-    assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
-    assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
-    assert torch.allclose(s.EN, EN4, rtol=1e-13, atol=0.0)
-    assert (s.G.val - G4).abs().max() <= 1e-13 * G4.abs().max()
-    s.set_cluster((4, 1))
-
-
-def test_quad_cg_trajectory(quads):
-    s, ref, lay = quads["si64"]
-    w = s.w
-    steps = 6
-    T = olnv.hotelling(ref.S, ref.maskL, 16)
-    _, hist = olnv.cg(ref.S, ref.H, ref.maskL, w.n_elec, steps, T=T)
-    s.set_cluster((16, 4))
-    s.cg_init()
-    for k in range(steps):
-        s.cg_step()
-        sc = s.scalars_host()
-        h = hist[k]
-        assert abs(sc["E"] - h["E"]) / w.n <= 1e-10, k
-        assert abs(sc["N"] - h["N"]) <= 1e-9 * max(1.0, w.n_elec / 64), k
-        assert abs(sc["ALPHA"] - h["alpha"]) <= 1e-8 * abs(h["alpha"]), k
-        assert int(sc["STATUS"]) & 3 == 0
-    s.set_cluster((4, 1))
-
-
-@pytest.mark.parametrize("acc", [ACC_F32, ACC_F64])
-def test_quad_mixed(quads, acc):
-    s, ref, lay = quads["si64"]
-    w = s.w
-    Ld = _seeded_L(s, ref, lay, 7)
-    Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
-    s.set_cluster((16, 4))
-    L_.call("lnv_set_f32_accumulation", acc)
-    try:
-        s.eval_mixed()
-        torch.cuda.synchronize()
-    finally:
-        L_.call("lnv_set_f32_accumulation", ACC_F32)
-    E, N = (float(x) for x in s.EN.cpu())
-    G = lay.to_dense(s.G.val, s.pL)
-    tol = _tol(s, acc)
-    assert abs(E - Er) / w.n <= 1e-6
-    assert abs(N - Nr) <= tol * abs(Nr)
-    assert np.abs(G - Gr).max() <= tol * np.abs(Gr).max()
-    s.set_cluster((4, 1))
-
-
-@pytest.mark.parametrize("shape", SHAPES)
-def test_quad_outputs_complete(quads, shape):
-    """Every block of every product's output is written: on the nearly dense
-    64-atom cell S.L and X^T pass the operand tile check while L's pattern is
-    not tile-complete, so P_L(SL.XT) must not take the 13-function tile path
-    (whose output tiles are judged by their first block).  Buffers filled with
-    NaN before the evaluation hold none after it."""
-    s, ref, lay = quads["si64"]
-    s.set_cluster(shape)
-    assert s.pSL.tile4 == 1 and s.pXT.tile4 == 1 and s.pL.tile4 == 0
-    Ld = _seeded_L(s, ref, lay, 11)
-    for v in (s.SL.val, s.LS.val, s.X.val, s.XT.val, s.Z.val, s.Zu.val, s.Lu.val, s.Vu,
-              s.YT, s.W, s.V, s.G.val, s.F.val):
-        v.fill_(float("nan"))
-    s.eval()
-    torch.cuda.synchronize()
-    for name in ("YT", "W", "V"):
-        assert not torch.isnan(getattr(s, name)).any(), name
-    Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
-    assert abs(float(s.EN[0]) - Er) / s.n <= 1e-10
-    G = lay.to_dense(s.G.val, s.pL)
-    assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
-    s.set_cluster((4, 1))
