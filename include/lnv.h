@@ -76,7 +76,8 @@ enum { LNV_F64 = 0, LNV_F32 = 1 };
  * each axis (r the largest offset any block of the pattern has; w[a] =
  * min(2 r[a] + 1, g[a]) cells), and its table holds, per row unit, one entry
  * per (window cell, slot):
- *   d_a  = (cell_a(j) - cell_a(i) + r_a) mod g_a     (valid iff d_a < w_a)
+ *   d_a  = (cell_a(j) - cell_a(i) + r_a) mod g_a     (valid iff d_a < w_a),
+ *          or cell_a(j) itself on an axis the window spans (w_a = g_a)
  *   pos(i, j) = tab[unit(i) * stride + ((d_0 w_1 + d_1) w_2 + d_2) occ + slot(j)]
  * (-1: no block), stride = w_0 w_1 w_2 occ.  With qs = 2 the units are the
  * atoms of a tile4 pattern (4 rows with the same columns, in aligned runs

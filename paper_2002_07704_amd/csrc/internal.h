@@ -103,6 +103,7 @@ struct Ix {
   int g0, g1, g2, r0, r1, r2, w0, w1, w2, occ, qs;
   long long stride;
   long long sent;     // index of the table's trailing -1 entry (n_units * stride)
+  int full;           // every axis's window is the whole axis
 };
 
 inline Ix make_ix(const lnv_pattern* p) {
@@ -119,14 +120,19 @@ inline Ix make_ix(const lnv_pattern* p) {
   v.qs = x.qs;
   v.stride = x.stride;
   v.sent = (long long)(p->n >> x.qs) * x.stride;
+  v.full = x.w[0] == x.g[0] && x.w[1] == x.g[1] && x.w[2] == x.g[2];
   return v;
 }
 
 inline bool has_ix(const lnv_pattern* p) { return p && p->ix.tab != nullptr; }
 
-// Wrapped window coordinate of cell coordinate cb seen from ca (both in
-// [0, g)), r <= g - 1: in [0, g), valid when below the window width w.
-__device__ __forceinline__ int ix_axis(int cb, int ca, int r, int g) {
+// Window coordinate of cell coordinate cb seen from ca (both in [0, g)),
+// r <= g - 1: the wrapped offset (cb - ca + r) mod g, valid when below the
+// window width w; when the window spans the whole axis (w == g) the absolute
+// coordinate cb itself (every cell is in the window, and the coordinate of
+// a column no longer depends on the row).
+__device__ __forceinline__ int ix_axis(int cb, int ca, int r, int g, int w) {
+  if (w == g) return cb;
   int d = cb - ca + r;
   d += d < 0 ? g : 0;
   d -= d >= g ? g : 0;
@@ -136,9 +142,9 @@ __device__ __forceinline__ int ix_axis(int cb, int ca, int r, int g) {
 // Offset in a row unit's table of the unit with packed cell cb and slot sb,
 // seen from a row unit in packed cell ca; -1 outside the window.
 __device__ __forceinline__ int ix_off(const Ix& x, int ca, int cb, int sb) {
-  const int d0 = ix_axis(cb & 1023, ca & 1023, x.r0, x.g0);
-  const int d1 = ix_axis((cb >> 10) & 1023, (ca >> 10) & 1023, x.r1, x.g1);
-  const int d2 = ix_axis(cb >> 20, ca >> 20, x.r2, x.g2);
+  const int d0 = ix_axis(cb & 1023, ca & 1023, x.r0, x.g0, x.w0);
+  const int d1 = ix_axis((cb >> 10) & 1023, (ca >> 10) & 1023, x.r1, x.g1, x.w1);
+  const int d2 = ix_axis(cb >> 20, ca >> 20, x.r2, x.g2, x.w2);
   if (d0 >= x.w0 || d1 >= x.w1 || d2 >= x.w2) return -1;
   return ((d0 * x.w1 + d1) * x.w2 + d2) * x.occ + sb;
 }
@@ -146,7 +152,8 @@ __device__ __forceinline__ int ix_off(const Ix& x, int ca, int cb, int sb) {
 // Position of the block of unit row a, unit column b (the block of their
 // first rows), or -1.
 __device__ __forceinline__ int ix_unit(const Ix& x, int a, int b) {
-  const int o = ix_off(x, x.cell[a], x.cell[b], x.slot[b]);
+  // with every window spanning its axis the row's cell does not matter
+  const int o = ix_off(x, x.full ? 0 : x.cell[a], x.cell[b], x.slot[b]);
   return o < 0 ? -1 : x.tab[(size_t)a * x.stride + o];
 }
 

@@ -1359,9 +1359,12 @@ int cubic_traces(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, bool m_is
   // needs a buffer of its own (ev.YT is dead outside the evaluation)
   lnv_bsm scratchC{pl, 4, LNV_F64, ev.YT};
   const lnv_pattern* pu = ev.Lu.pat;
+  // the half (in_half) of L's pattern holds every block of a row group and
+  // one block of each other pair: between half and all of L's blocks
   const bool half = pu && ev.Lu.val && ev.Vu && pu->n == pl->n && has_ix(pu) && pu->row_ptr &&
                     pu->col && pl->items && ev.Lu.dtype == LNV_F64 &&
-                    2 * pu->nnzb == pl->nnzb + pl->n && (m_is_s || SLcur);
+                    2 * pu->nnzb >= pl->nnzb + pl->n && pu->nnzb <= pl->nnzb &&
+                    (m_is_s || SLcur);
   if (half) {
     lnv_bsm Qh{pu, 4, LNV_F64, ev.YT};
     const int nq = multiply_nparts(&APT, &XP, 0, &Qh);

@@ -168,9 +168,11 @@ __device__ __forceinline__ int find_jk(const Ix& x, const RowKey& r, int k) {
 // Table entry address of block (k, j) for the index loads of the pipelined
 // kernels (column j fixed per lane, row k's packed cell ck uniform per step):
 // the sentinel entry (-1) when j is outside the window of k or the lane idle.
+// o_full: the lane's offset when every window spans its axis (then it does
+// not depend on k), -1 for an idle lane.
 __device__ __forceinline__ const int* entry_kj(const Ix& x, int k, int ck, int cb, int sb,
-                                               bool act) {
-  const int o = act ? ix_off(x, ck, cb, sb) : -1;
+                                               bool act, int o_full) {
+  const int o = x.full ? o_full : (act ? ix_off(x, ck, cb, sb) : -1);
   return x.tab + (o < 0 ? (size_t)x.sent : (size_t)(k >> x.qs) * x.stride + o);
 }
 
@@ -323,6 +325,7 @@ __global__ __launch_bounds__(256) void k_mul44c1(
   for (int r = 0; r < 4; ++r) opos[r] = act ? jc_pos[(size_t)(p0 + lane) * 4 + r] : -1;
   // the column's half of B's window lookup (B's units are rows here)
   const int cb = bx.cell[j], sb = bx.slot[j];
+  const int o_full = act ? ix_off(bx, 0, cb, sb) : -1;
   const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
 
   Acc acc[4][16];
@@ -350,7 +353,7 @@ __global__ __launch_bounds__(256) void k_mul44c1(
     // from the index vector, so it is issued last, as in every loop step, and
     // the counts of loads in flight at the loop head agree on both paths.
     int l0 = -1, l1 = -1;                      // B positions (index table entries)
-    int l2 = *entry_kj(bx, ka_col[t0], ka_key[2 * (size_t)t0], cb, sb, act);
+    int l2 = *entry_kj(bx, ka_col[t0], ka_key[2 * (size_t)t0], cb, sb, act, o_full);
     int iv = *idx_src(ts - 1);
     T b0[16], b1[16], b2[16];
     int zero = 0;
@@ -371,7 +374,7 @@ __global__ __launch_bounds__(256) void k_mul44c1(
       pf[r] = __builtin_amdgcn_readlane(iv, 4 + r);                            \
     }                                                                          \
     const bool use = act && (t) >= t0 && (t) < t1 && LC >= 0;                  \
-    LC = *entry_kj(bx, k3, c3, cb, sb, act);                                   \
+    LC = *entry_kj(bx, k3, c3, cb, sb, act, o_full);                           \
     load_block(BN, b_val + (size_t)max(L2, 0) * 16);                           \
     asm volatile("" ::"v"(XC));                                                \
     {                                                                          \
