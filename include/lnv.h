@@ -421,6 +421,12 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  *  perm_SL, perm_X  transpose maps SL -> LS and X -> XT
  * Every operand B of the products is read in its stored orientation: a
  * transposed read would gather 64 blocks from 64 distant rows per step.
+ * LS and XT may be left out together (both val NULL; their patterns and
+ * perm_SL, perm_X are then not used): the products read S.L and X
+ * transposed instead, which the atom-tile multiply does at full speed (a
+ * tile is read as 16 rows either way) -- for cells of 13-function atoms
+ * too large to hold both orientations of the natural-range intermediates.
+ * lnv_cg_step needs them (scratch of the line search).
  *  YT, W, V  device [nnzb_L * 16]: P_L(SLSLH), P_L(SLHLS), P_L(SLSLS)
  *  partials  device [partials_len] scratch, partials_len >=
  *            lnv_partials_len(max(n_items, n_cl_items) of L's pattern)

@@ -850,32 +850,46 @@ int transpose_launch(const lnv_bsm* A, const int32_t* perm, void* AT, hipStream_
   return transpose_skip_launch(A, perm, AT, nullptr, s);
 }
 
+// The intermediates' transposes L.S and X^T are optional as a pair (both
+// values NULL): the products then read S.L and X transposed.
+bool lean_ws(const lnv_bsm& LS, const lnv_bsm& XT) { return !LS.val && !XT.val; }
+
+// Checks of an evaluation's patterns and intermediates (FP64 or FP32 values,
+// per the caller's ok test).
+template <typename Ok>
+int check_products(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm& SL,
+                   const lnv_bsm& LS, const lnv_bsm& X, const lnv_bsm& XT, const lnv_bsm& Z,
+                   const int32_t* perm_SL, const int32_t* perm_X, Ok ok) {
+  const bool lean = lean_ws(LS, XT);
+  if (!ok(&SL) || !ok(&X) || !ok(&Z)) return LNV_EINVAL;
+  if (!lean && (!ok(&LS) || !ok(&XT) || !perm_SL || !perm_X)) return LNV_EINVAL;
+  const int n = L->pat->n;
+  if (S->pat->n != n || H->pat->n != n || SL.pat->n != n || X.pat->n != n || Z.pat->n != n)
+    return LNV_EPATTERN;
+  if (!lean && (LS.pat->n != n || XT.pat->n != n || SL.pat->nnzb != LS.pat->nnzb ||
+                X.pat->nnzb != XT.pat->nnzb))
+    return LNV_EPATTERN;
+  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
+      !pattern_ready(H->pat, false, false, false) || !pattern_ready(SL.pat, lean, false, true) ||
+      !pattern_ready(X.pat, true, false, true) || !pattern_ready(Z.pat, true, false, true))
+    return LNV_EPATTERN;
+  if (!lean && (!pattern_ready(LS.pat, true, false, false) ||
+                !pattern_ready(XT.pat, true, false, false)))
+    return LNV_EPATTERN;
+  return LNV_OK;
+}
+
 int check_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* G,
                const lnv_bsm* F, const lnv_eval_ws* ws) {
   if (!bsm_ok(L) || !bsm_ok(S) || !bsm_ok(H) || !ws || !ws->YT || !ws->W || !ws->V ||
-      !ws->partials || !ws->scalars || !ws->perm_SL || !ws->perm_X)
+      !ws->partials || !ws->scalars)
     return LNV_EINVAL;
   if ((G && !bsm_ok(G)) || (F && !bsm_ok(F))) return LNV_EINVAL;
-  if (!bsm_ok(&ws->SL) || !bsm_ok(&ws->LS) || !bsm_ok(&ws->X) || !bsm_ok(&ws->XT) ||
-      !bsm_ok(&ws->Z))
-    return LNV_EINVAL;
   if (L->blk != 4 || S->blk != 4 || H->blk != 4) return LNV_EUNSUPPORTED;
-  const int n = L->pat->n;
-  if (S->pat->n != n || H->pat->n != n || ws->SL.pat->n != n || ws->LS.pat->n != n ||
-      ws->X.pat->n != n || ws->XT.pat->n != n || ws->Z.pat->n != n)
-    return LNV_EPATTERN;
-  if (ws->SL.pat->nnzb != ws->LS.pat->nnzb || ws->X.pat->nnzb != ws->XT.pat->nnzb)
-    return LNV_EPATTERN;
+  LNV_TRY(check_products(L, S, H, ws->SL, ws->LS, ws->X, ws->XT, ws->Z, ws->perm_SL, ws->perm_X,
+                         [](const lnv_bsm* m) { return bsm_ok(m); }));
   if (G && G->pat != L->pat) return LNV_EPATTERN;
   if (F && F->pat != L->pat) return LNV_EPATTERN;
-  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
-      !pattern_ready(H->pat, false, false, false) ||
-      !pattern_ready(ws->SL.pat, false, false, true) ||
-      !pattern_ready(ws->LS.pat, true, false, false) ||
-      !pattern_ready(ws->X.pat, true, false, true) ||
-      !pattern_ready(ws->XT.pat, true, false, false) ||
-      !pattern_ready(ws->Z.pat, true, false, true))
-    return LNV_EPATTERN;
   if (ws->partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
   return LNV_OK;
 }
@@ -930,10 +944,10 @@ namespace {
 // multiplied, into U, and C is filled from them by a transposing copy;
 // otherwise C is formed in full.
 int sym_product(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C, const lnv_bsm* U,
-                hipStream_t s) {
+                hipStream_t s, int transB = 0) {
   if (!sym_ready(U, C))
-    return multiply_launch(1.0, A, B, 0, 0.0, C, 1, nullptr, nullptr, nullptr, nullptr, s);
-  LNV_TRY(multiply_launch(1.0, A, B, 0, 0.0, U, 1, nullptr, nullptr, nullptr, nullptr, s));
+    return multiply_launch(1.0, A, B, transB, 0.0, C, 1, nullptr, nullptr, nullptr, nullptr, s);
+  LNV_TRY(multiply_launch(1.0, A, B, transB, 0.0, U, 1, nullptr, nullptr, nullptr, nullptr, s));
   return mirror_launch(U, C, s);
 }
 
@@ -967,22 +981,31 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
     LNV_TRY(multiply_launch(1.0, o.S, o.L, 0, 0.0, o.SL, 1, nullptr, nullptr, nullptr, nullptr,
                             s));
   }
-  LNV_TRY(transpose_launch(o.SL, o.perm_SL, o.LS->val, s));
-  LNV_TRY(multiply_launch(1.0, o.H, o.LS, 0, 0.0, o.X, 1, nullptr, nullptr, nullptr, nullptr, s));
+  // L.S and X^T stored (read in their own orientation), or, without them,
+  // read transposed from S.L and X
+  const bool lean = lean_ws(*o.LS, *o.XT);
+  const lnv_bsm* LSop = lean ? o.SL : o.LS;
+  const lnv_bsm* XTop = lean ? o.X : o.XT;
+  const int tb = lean ? 1 : 0;
+  if (!lean) LNV_TRY(transpose_launch(o.SL, o.perm_SL, o.LS->val, s));
+  LNV_TRY(multiply_launch(1.0, o.H, LSop, tb, 0.0, o.X, 1, nullptr, nullptr, nullptr, nullptr,
+                          s));
   // Z = SLS, W = P_L(SLHLS) and V = P_L(SLSLS) are symmetric (formed on
   // their halves when the workspace carries them); YT = P_L(SLSLH) is not
   const lnv_bsm* Lu = o.Lu;
   lnv_bsm Vu{Lu ? Lu->pat : nullptr, 4, dt, o.Vu};
-  if (!o.Zcarry) LNV_TRY(sym_product(o.S, o.LS, o.Z, o.Zu, s));
-  LNV_TRY(transpose_launch(o.X, o.perm_X, o.XT->val, s));
-  LNV_TRY(multiply_launch(1.0, o.SL, o.XT, 0, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr, s));
+  if (!o.Zcarry) LNV_TRY(sym_product(o.S, LSop, o.Z, o.Zu, s, tb));
+  if (!lean) LNV_TRY(transpose_launch(o.X, o.perm_X, o.XT->val, s));
+  LNV_TRY(multiply_launch(1.0, o.SL, XTop, tb, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr,
+                          s));
   LNV_TRY(sym_product_pair(o.SL, o.X, &Wm, Lu, o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
   const int ni = pl->n_items;
   double* part = o.partials;
   k_assemble<T><<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, make_ix(pl),
                                    static_cast<const double*>(L64->val), make_ix(o.X->pat),
-                                   static_cast<const T*>(o.X->val), make_ix(o.XT->pat),
-                                   static_cast<const T*>(o.XT->val),
+                                   static_cast<const T*>(o.X->val),
+                                   lean ? make_ix(o.X->pat) : make_ix(o.XT->pat),
+                                   lean ? nullptr : static_cast<const T*>(o.XT->val),
                                    static_cast<const T*>(o.YT), static_cast<const T*>(o.W),
                                    make_ix(o.Z->pat), static_cast<const T*>(o.Z->val),
                                    static_cast<const T*>(o.V), G, F, part);
@@ -1036,29 +1059,13 @@ int check_eval32(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv
                  const lnv_bsm* F, const lnv_eval32_ws* ws) {
   if (!bsm_ok(L) || !bsm_ok(S) || !bsm_ok(H) || !ws || !G || !F || !bsm_ok(G) || !bsm_ok(F))
     return LNV_EINVAL;
-  if (!ws->YT || !ws->W || !ws->V || !ws->partials || !ws->scalars || !ws->perm_SL ||
-      !ws->perm_X)
-    return LNV_EINVAL;
-  if (!f32_ok(&ws->L) || !f32_ok(&ws->S) || !f32_ok(&ws->H) || !f32_ok(&ws->SL) ||
-      !f32_ok(&ws->LS) || !f32_ok(&ws->X) || !f32_ok(&ws->XT) || !f32_ok(&ws->Z))
-    return LNV_EINVAL;
+  if (!ws->YT || !ws->W || !ws->V || !ws->partials || !ws->scalars) return LNV_EINVAL;
+  if (!f32_ok(&ws->L) || !f32_ok(&ws->S) || !f32_ok(&ws->H)) return LNV_EINVAL;
   if (L->blk != 4 || S->blk != 4 || H->blk != 4) return LNV_EUNSUPPORTED;
   if (ws->L.pat != L->pat || ws->S.pat != S->pat || ws->H.pat != H->pat) return LNV_EPATTERN;
   if (G->pat != L->pat || F->pat != L->pat) return LNV_EPATTERN;
-  const int n = L->pat->n;
-  if (S->pat->n != n || H->pat->n != n || ws->SL.pat->n != n || ws->LS.pat->n != n ||
-      ws->X.pat->n != n || ws->XT.pat->n != n || ws->Z.pat->n != n)
-    return LNV_EPATTERN;
-  if (ws->SL.pat->nnzb != ws->LS.pat->nnzb || ws->X.pat->nnzb != ws->XT.pat->nnzb)
-    return LNV_EPATTERN;
-  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(S->pat, false, false, false) ||
-      !pattern_ready(H->pat, false, false, false) ||
-      !pattern_ready(ws->SL.pat, false, false, true) ||
-      !pattern_ready(ws->LS.pat, true, false, false) ||
-      !pattern_ready(ws->X.pat, true, false, true) ||
-      !pattern_ready(ws->XT.pat, true, false, false) ||
-      !pattern_ready(ws->Z.pat, true, false, true))
-    return LNV_EPATTERN;
+  LNV_TRY(check_products(L, S, H, ws->SL, ws->LS, ws->X, ws->XT, ws->Z, ws->perm_SL, ws->perm_X,
+                         [](const lnv_bsm* m) { return f32_ok(m); }));
   if (ws->partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
   return LNV_OK;
 }
@@ -1292,6 +1299,7 @@ int check_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm
              const lnv_cg_ws* ws) {
   if (!ws) return LNV_EINVAL;
   LNV_TRY(check_eval(L, S, H, nullptr, nullptr, &ws->ev));
+  if (lean_ws(ws->ev.LS, ws->ev.XT)) return LNV_EINVAL;   // the step's scratch buffers
   if (!ws->SL2 || !ws->Hp || !ws->G || !ws->F || !ws->g || !ws->gc_prev || !ws->D ||
       !ws->D_prev)
     return LNV_EINVAL;

@@ -26,7 +26,8 @@ import numpy as np
 import torch
 
 from . import lib as L_
-from .system import BLK, Matrix, _ptr, _stream, multiply, transpose, transpose_map
+from .system import (BLK, Matrix, _ptr, _stream, multiply, product_pattern, transpose,
+                     transpose_map)
 
 
 def _dot(system, A, B):
@@ -50,12 +51,22 @@ def _lincomb(a, X, b, Y, c, Z, out):
             ref[1], ctypes.byref(out.struct), _stream())
 
 
+def _pattern_HL(system):
+    """pat(H.L) with its index, work list and the system's cluster plan (the
+    adjoint's, when it has been set up)."""
+    if getattr(system, "pHL", None) is not None:
+        return system.pHL
+    P = product_pattern(system.pH, system.pL, triples=False).build_index().build_items()
+    if system.cluster is not None:
+        P.build_cluster(*system.cluster)
+    return P
+
+
 def pm_initial_L(system, n_iter=100, tol=1e-12):
     """Purified K written to system.L; returns the history [dict(c, t1, t2, t3)]
     and the start parameters (mu, b, lambda)."""
     if system.metric is None:
         raise ValueError("canonical purification needs the metric T ~ S^-1")
-    system.adjoint_setup()                       # pat(H.L) with index table and work list
     system.pH.build_index()
     n = float(np.sum(system.w.nfun)) if system.w is not None else float(system.fun_rows.sum())
     theta = system.n_elec / 2.0
@@ -63,7 +74,7 @@ def pm_initial_L(system, n_iter=100, tol=1e-12):
     mu = float(_dot(system, T, H)) / n
     b = float(_norm_inf(system, T)) * float(_norm_inf(system, H))
     lam = min(theta / (b - mu), (n - theta) / (mu + b))
-    HT = system.HL                               # H.T on pat(H.L)
+    HT = Matrix(_pattern_HL(system))             # H.T on pat(H.L), dropped after use
     multiply(1.0, H, T, 0, 0.0, HT)
     K = Matrix(system.pL)
     K2 = Matrix(system.pL)
@@ -71,6 +82,7 @@ def pm_initial_L(system, n_iter=100, tol=1e-12):
     KT = Matrix(system.pL)
     perm_L = transpose_map(system.pL, system.pL)
     multiply(1.0, T, HT, 0, 0.0, K2)             # P_L(T H T)
+    del HT
     _lincomb((lam * mu + theta) / n, T, -lam / n, K2, 0.0, None, K)
     SK = system.SL                               # S.K on pat(S.L)
     hist = []

@@ -407,11 +407,13 @@ class LNVSystem:
     P_L(SLHLS), P_L(SLSLS) and P_L(TGT) and copy the rest transposed (needs
     symmetric patterns, which L, S, H have).  reorder: the order of the atoms
     along the rows (row_order); every result is the same up to that
-    permutation, and atom_of maps rows back to atoms.
+    permutation, and atom_of maps rows back to atoms.  lean: evaluation only
+    (no stored L.S, X^T, no CG buffers).  grid: cells of the spatial index
+    per axis (default: Cells.choose_grid; (1, 1, 1) is the dense table).
     """
 
     def __init__(self, w, device="cuda", R_L=None, metric="hotelling", n_hotelling=16,
-                 cluster=(4, 1), reorder=None, symmetric=True):
+                 cluster=(4, 1), reorder=None, symmetric=True, lean=False, grid=None):
         if not torch.cuda.is_available():
             raise RuntimeError("LNVSystem needs a GPU (HIP device)")
         L_.load()
@@ -421,13 +423,17 @@ class LNVSystem:
         if self.cells is not None:
             self._layout_cells(self.cells, R_L)
         else:
-            self._layout_single(w, R_L, reorder)
+            self._layout_single(w, R_L, reorder, grid)
         # a2: natural product patterns (A = LS is stored as its transpose SL)
         self.pSL = product_pattern(self.pS, self.pL)            # S.L
         self.pLS = product_pattern(self.pL, self.pS, triples=False)   # L.S (row form of A)
         self.pX = product_pattern(self.pH, self.pLS)            # H.L.S
         self.pZ = product_pattern(self.pS, self.pLS)            # S.L.S
         self.pXT = product_pattern(self.pSL, self.pH, triples=False)   # S.L.H = pat(X)^T
+        # lean: evaluation only, without the stored transposes L.S and X^T (the
+        # atom-tile products read S.L and X transposed) and without the CG's
+        # buffers -- for cells whose natural-range intermediates fill the GPU
+        self.lean = bool(lean)
         self.triples = dict(
             SL=self.pSL.triples, X=self.pX.triples, Z=self.pZ.triples,
             YT=product_pattern(self.pSL, self.pXT, mask=self.pL).triples,
@@ -458,18 +464,26 @@ class LNVSystem:
         self.pS.build_index()
         self.pH.build_items()
         self.pSL.build_index().build_items()
-        self.pLS.build_index()
         self.pX.build_index().build_items()
-        self.pXT.build_index()
         self.pZ.build_index().build_items()
-        if metric is not None:
+        if not self.lean:
+            self.pLS.build_index()
+            self.pXT.build_index()
+        if metric is not None and not self.lean:
             self.pLL.build_index().build_items()
         assert self.pX.nnzb >= self.pZ.nnzb
         self.cluster = None
         if cluster is not None:
             self.set_cluster(cluster)
-        self.perm_SL = transpose_map(self.pSL, self.pLS)
-        self.perm_X = transpose_map(self.pX, self.pXT)
+        if self.lean:
+            # X^T's pattern only counted the triples of P_L(S.L X^T)
+            if self.split:
+                self._alg_flops(("YT",))
+            self.pXT = None
+            self.perm_SL = self.perm_X = None
+        else:
+            self.perm_SL = transpose_map(self.pSL, self.pLS)
+            self.perm_X = transpose_map(self.pX, self.pXT)
         # buffers
         nL = self.pL.nnzb
 
@@ -480,22 +494,25 @@ class LNVSystem:
         self.G = Matrix(self.pL)
         self.F = Matrix(self.pL)
         self.SL = Matrix(self.pSL)
-        self.LS = Matrix(self.pLS)
         self.X = Matrix(self.pX)
-        self.XT = Matrix(self.pXT)
         self.Z = Matrix(self.pZ)
+        self.LS = self.XT = None
+        if not self.lean:
+            self.LS = Matrix(self.pLS)
+            self.XT = Matrix(self.pXT)
         self.YT, self.W, self.V = lbuf(), lbuf(), lbuf()
         if self.symmetric:
             self.Zu, self.Lu = Matrix(self.pZu), Matrix(self.pLu)
             self.Vu = torch.zeros_like(self.Lu.val)
-        self.SL2 = torch.zeros_like(self.SL.val)
-        self.Hp = torch.zeros_like(self.H.val)
-        self.g, self.gc_prev, self.D, self.D_prev = lbuf(), lbuf(), lbuf(), lbuf()
-        self.gc = lbuf() if metric is not None else None
         self.Gc = Matrix(self.pL) if metric is not None else None
-        self.Fc = Matrix(self.pL) if metric is not None else None
         self.T = Matrix(self.pL) if metric is not None else None
-        if metric is not None:
+        if not self.lean:
+            self.SL2 = torch.zeros_like(self.SL.val)
+            self.Hp = torch.zeros_like(self.H.val)
+            self.g, self.gc_prev, self.D, self.D_prev = lbuf(), lbuf(), lbuf(), lbuf()
+            self.gc = lbuf() if metric is not None else None
+            self.Fc = Matrix(self.pL) if metric is not None else None
+        if metric is not None and not self.lean:
             # T G lives in XT's memory when it fits (XT is dead at that point)
             if self.pLL.nnzb <= self.pXT.nnzb:
                 llv = self.XT.val.view(-1)[:self.pLL.nnzb * BLK * BLK].view(-1, BLK, BLK)
@@ -509,34 +526,38 @@ class LNVSystem:
         self.ws = L_.LnvCgWs()
         ev = self.ws.ev
         ev.SL = self.SL.struct
-        ev.LS = self.LS.struct
         ev.X = self.X.struct
-        ev.XT = self.XT.struct
         ev.Z = self.Z.struct
-        ev.perm_SL = self.perm_SL.data_ptr()
-        ev.perm_X = self.perm_X.data_ptr()
+        if not self.lean:
+            ev.LS = self.LS.struct
+            ev.XT = self.XT.struct
+            ev.perm_SL = self.perm_SL.data_ptr()
+            ev.perm_X = self.perm_X.data_ptr()
         ev.YT, ev.W, ev.V = self.YT.data_ptr(), self.W.data_ptr(), self.V.data_ptr()
         ev.partials = self.partials.data_ptr()
         ev.partials_len = plen
         ev.scalars = self.scalars.data_ptr()
         if self.symmetric:
             ev.Zu, ev.Lu, ev.Vu = self.Zu.struct, self.Lu.struct, self.Vu.data_ptr()
-        self.ws.SL2 = self.SL2.data_ptr()
-        self.ws.Hp = self.Hp.data_ptr()
         self.ws.G = self.G.val.data_ptr()
         self.ws.F = self.F.val.data_ptr()
-        self._bufs = {t.data_ptr(): t for t in (self.g, self.gc_prev, self.D, self.D_prev)}
-        self.ws.g, self.ws.gc_prev = self.g.data_ptr(), self.gc_prev.data_ptr()
-        self.ws.D, self.ws.D_prev = self.D.data_ptr(), self.D_prev.data_ptr()
-        self.lanczos = torch.zeros(int(L_.load().lnv_lanczos_len(self.pL.n)), dtype=torch.float64,
-                                   device=dev)
-        self.ws.lanczos = self.lanczos.data_ptr()
+        self._bufs = {}
+        if not self.lean:
+            self.ws.SL2 = self.SL2.data_ptr()
+            self.ws.Hp = self.Hp.data_ptr()
+            self._bufs = {t.data_ptr(): t for t in (self.g, self.gc_prev, self.D, self.D_prev)}
+            self.ws.g, self.ws.gc_prev = self.g.data_ptr(), self.gc_prev.data_ptr()
+            self.ws.D, self.ws.D_prev = self.D.data_ptr(), self.D_prev.data_ptr()
+            self.lanczos = torch.zeros(int(L_.load().lnv_lanczos_len(self.pL.n)),
+                                       dtype=torch.float64, device=dev)
+            self.ws.lanczos = self.lanczos.data_ptr()
         if metric is not None:
-            self.ws.LL = self.LL.struct
             self.ws.Gc = self.Gc.val.data_ptr()
-            self.ws.Fc = self.Fc.val.data_ptr()
-            self.ws.gc = self.gc.data_ptr()
-            self._bufs[self.gc.data_ptr()] = self.gc
+            if not self.lean:
+                self.ws.LL = self.LL.struct
+                self.ws.Fc = self.Fc.val.data_ptr()
+                self.ws.gc = self.gc.data_ptr()
+                self._bufs[self.gc.data_ptr()] = self.gc
             L_.call("lnv_hotelling", byref(self.S.struct), byref(self.T.struct),
                     int(n_hotelling), byref(self.ws), _stream())
         self.opts = Opts()
@@ -569,31 +590,47 @@ class LNVSystem:
     # ----------------------------------------------------------- mixed precision
     def mixed_setup(self):
         """FP32 copies of L, S, H and FP32 intermediates for lnv_eval_mixed
-        (same patterns, tables and transpose maps as the FP64 evaluation)."""
+        (same patterns, tables and transpose maps as the FP64 evaluation).
+        A lean system keeps its FP32 intermediates in the memory of the FP64
+        ones (each evaluation forms all of its intermediates before reading
+        them, so FP64 and FP32 evaluations may alternate; a lean system runs
+        no CG, which would need both at once)."""
         if self.ws32 is not None:
             return
 
-        def f32(pat):
+        def f32(pat, share=None):
+            if share is not None and self.lean:
+                v = share.view(-1).view(torch.float32)[:max(1, pat.nnzb) * BLK * BLK]
+                return Matrix(pat, v.view(-1, BLK, BLK))
             return Matrix(pat, dtype=torch.float32)
 
         self.L32, self.S32, self.H32 = f32(self.pL), f32(self.pS), f32(self.pH)
-        self.SL32, self.LS32 = f32(self.pSL), f32(self.pLS)
-        self.X32, self.XT32, self.Z32 = f32(self.pX), f32(self.pXT), f32(self.pZ)
+        self.SL32 = f32(self.pSL, self.SL.val)
+        self.X32, self.Z32 = f32(self.pX, self.X.val), f32(self.pZ, self.Z.val)
+        self.LS32 = self.XT32 = None
+        if not self.lean:
+            self.LS32, self.XT32 = f32(self.pLS), f32(self.pXT)
         nL = self.pL.nnzb
-        self.YT32, self.W32, self.V32 = (torch.zeros(nL, BLK, BLK, dtype=torch.float32,
-                                                     device=self.dev) for _ in range(3))
+        if self.lean:
+            self.YT32, self.W32, self.V32 = (f32(self.pL, t).val for t in (self.YT, self.W, self.V))
+        else:
+            self.YT32, self.W32, self.V32 = (torch.zeros(nL, BLK, BLK, dtype=torch.float32,
+                                                         device=self.dev) for _ in range(3))
         ws = L_.LnvEval32Ws()
         ws.L, ws.S, ws.H = self.L32.struct, self.S32.struct, self.H32.struct
-        ws.SL, ws.LS = self.SL32.struct, self.LS32.struct
-        ws.X, ws.XT, ws.Z = self.X32.struct, self.XT32.struct, self.Z32.struct
-        ws.perm_SL, ws.perm_X = self.perm_SL.data_ptr(), self.perm_X.data_ptr()
+        ws.SL = self.SL32.struct
+        ws.X, ws.Z = self.X32.struct, self.Z32.struct
+        if not self.lean:
+            ws.LS, ws.XT = self.LS32.struct, self.XT32.struct
+            ws.perm_SL, ws.perm_X = self.perm_SL.data_ptr(), self.perm_X.data_ptr()
         ws.YT, ws.W, ws.V = self.YT32.data_ptr(), self.W32.data_ptr(), self.V32.data_ptr()
         ws.partials = self.partials.data_ptr()
         ws.partials_len = self.ws.ev.partials_len
         ws.scalars = self.scalars.data_ptr()
         if self.symmetric:
-            self.Zu32, self.Lu32 = f32(self.pZu), f32(self.pLu)
-            self.Vu32 = torch.zeros_like(self.Lu32.val)
+            self.Zu32, self.Lu32 = f32(self.pZu, self.Zu.val), f32(self.pLu, self.Lu.val)
+            self.Vu32 = (f32(self.pLu, self.Vu).val if self.lean
+                         else torch.zeros_like(self.Lu32.val))
             ws.Zu, ws.Lu, ws.Vu = self.Zu32.struct, self.Lu32.struct, self.Vu32.data_ptr()
         self.ws32 = ws
         torch.cuda.synchronize()
@@ -613,7 +650,7 @@ class LNVSystem:
         pats = [self.pS, self.pH, self.pL, self.pSL, self.pX, self.pZ]
         if getattr(self, "symmetric", False):
             pats += [self.pZu, self.pLu]
-        if self.metric is not None:
+        if self.metric is not None and not getattr(self, "lean", False):
             pats.append(self.pLL)
         if getattr(self, "adj_ws", None) is not None:
             pats += [self.pLSL, self.pHL, self.pLS, self.pLH]
@@ -668,7 +705,7 @@ class LNVSystem:
             self.ws32.partials_len = need
 
     # ----------------------------------------------------------- row layout
-    def _layout_single(self, w, R_L, reorder):
+    def _layout_single(self, w, R_L, reorder, grid=None):
         """a0/a1 of one periodic cell: range patterns and synthetic S, H."""
         dev = self.dev
         self.w = w
@@ -705,7 +742,7 @@ class LNVSystem:
         # functions) are the index's units, else the rows
         qs = 2 if self.split and self.n_rows == 4 * self.n else 0
         units = pos_rows[::4] if qs else pos_rows
-        g = Cells.choose_grid(units, self.box, self._index_ranges())
+        g = Cells.choose_grid(units, self.box, self._index_ranges()) if grid is None else grid
         self.ix_cells = Cells(units, self.box, g, qs, dev)
         for P in (self.pS, self.pH, self.pL):
             P.cells = self.ix_cells
@@ -985,7 +1022,9 @@ class LNVSystem:
             return {k: 2 * BLK ** 3 * v for k, v in t.items()}
         return self._alg_flops()
 
-    def _alg_flops(self):
+    def _alg_flops(self, only=None):
+        """Algorithmic flops per product (cached); only: the keys to compute
+        now (all by default)."""
         if getattr(self, "_alg", None) is None:
             self._alg = {}
         up = self.pLu if self.symmetric else self.pL     # symmetric products: halves
@@ -995,7 +1034,7 @@ class LNVSystem:
                  "Vf": (self.pSL, self.pZ, self.pL), "Wf": (self.pSL, self.pX, self.pL)}
         if self.metric is not None:
             specs.update(TG=(self.pL, self.pL, None), TGT=(self.pL, self.pLL, up))
-        if self.adj_ws is not None:
+        if getattr(self, "adj_ws", None) is not None:
             sym = self.symmetric
             mL, mH, mS = ((self.pLSLu, self.pHu, self.pSu) if sym else (None, self.pH, self.pS))
             specs.update(LSL=(self.pL, self.pSL, mL), HL=(self.pH, self.pL, None),
@@ -1003,6 +1042,8 @@ class LNVSystem:
                          dS4=(self.pLH, self.pLSL, self.pS), dS6=(self.pL, self.pHL, mS))
         fun = self.fun_rows
         for k, (A, B, M) in specs.items():
+            if only is not None and k not in only:
+                continue
             if k not in self._alg:
                 f = c_int64(0)
                 L_.call("lnv_pattern_flops", byref(A.struct), byref(B.struct),
@@ -1052,7 +1093,12 @@ class LNVSystem:
     def _T(self):
         return byref(self.T.struct) if self.metric is not None else None
 
+    def _need_cg(self):
+        if self.lean:
+            raise RuntimeError("a lean system is evaluated, not minimised (no CG buffers)")
+
     def cg_init(self):
+        self._need_cg()
         L_.call("lnv_cg_init", byref(self.L.struct), byref(self.S.struct), self._T(),
                 self.n_elec, byref(self.ws), _stream())
         self.k = 0
@@ -1087,6 +1133,7 @@ class LNVSystem:
         return tuple(float(x) for x in out.cpu())
 
     def cg_step(self):
+        self._need_cg()
         if self.cells is not None:
             raise NotImplementedError("a batch of cells is evaluated, not minimised, as one system")
         o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap, None,

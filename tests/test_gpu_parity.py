@@ -397,3 +397,39 @@ def test_symmetric_products_half(gpu):
     torch.cuda.synchronize()
     assert abs(float(a.EN[0]) - float(b.EN[0])) / w.n <= 1e-6
     assert abs(float(a.EN[1]) - float(b.EN[1])) / w.n <= 1e-6
+
+
+@pytest.mark.parametrize("name", ["si4096", "si8192_13f"])
+def test_spatial_index_grid_does_not_change_results(gpu, name):
+    """The spatial index only locates blocks: the dense table (one cell) and
+    windowed ones (10.26-bohr cells, where L's and S's windows cover part of
+    the box) give bit-identical evaluations (4x4 blocks with the pipelined
+    multiply and 3 CG iterations; 13-function atoms, atom units, on the
+    matrix-core tiles)."""
+    from paper_2002_07704_amd.system import LNVSystem
+    if name == "si4096":
+        w = W.get("si4096_4x4")
+        grids, shape, steps = ((8, 8, 8), (1, 1, 1)), (4, 1), 3
+    else:
+        w = W.diamond_workload("si8192_13f", (16, 16, 4), seed=3, nfun=13, R=(12.0, 14.0, 10.0))
+        grids, shape, steps = ((16, 16, 4), (1, 1, 1)), (16, 4), 0
+    runs = []
+    for grid in grids:
+        s = LNVSystem(w, metric="hotelling", n_hotelling=16, reorder="bonds", grid=grid,
+                      cluster=None)
+        s.set_cluster(shape)
+        ix = s.pL.struct.ix
+        print(f"{name}: grid {s.ix_cells.g}, occ {s.ix_cells.occ}, L's window "
+              f"{tuple(ix.w)}, stride {ix.stride} for {s.ix_cells.n_units} units", flush=True)
+        s.cg_init()
+        s.eval()
+        torch.cuda.synchronize()
+        out = [s.EN.clone(), s.G.val.clone(), s.F.val.clone()]
+        for _ in range(steps):
+            s.cg_step()
+        torch.cuda.synchronize()
+        out.append(s.L.val.clone())
+        runs.append(out)
+        del s
+        torch.cuda.empty_cache()
+    assert all(torch.equal(a, b) for a, b in zip(*runs))

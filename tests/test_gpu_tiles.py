@@ -267,3 +267,59 @@ def test_tile_eval_at_scale(gpu, order):
         tol = _tol(s, acc)
         assert abs(E - E4) / w.n <= 1e-6 and abs(N - N4) <= tol * abs(N4)
         assert dG <= tol
+
+
+# ------------------------------------------------------------------ lean systems
+@pytest.mark.parametrize("name", ["si64_13b", "si64_4x4"])
+def test_lean_evaluation_reads_transposes(cells, name):
+    """A lean system (no stored L.S and X^T: the products read S.L and X
+    transposed; FP32 intermediates in the FP64 ones' memory) against the full
+    system at the same L: FP64 evaluation to rounding, and the mixed-precision
+    evaluations (FP32 MFMA, FP16 hi/lo on the atom tiles) identical to the
+    full system's own.  The 4-function cell runs the transposed reads on the
+    row kernel, the 13-function cell on the atom tiles."""
+    from paper_2002_07704_amd.system import LNVSystem
+    if name in cells:
+        full, _, _ = cells[name]
+        w = full.w
+        kw = dict(reorder="bonds")
+    else:
+        w = W.get(name)
+        full = LNVSystem(w, metric="hotelling", n_hotelling=16)
+        kw = {}
+    lean = LNVSystem(w, metric="hotelling", n_hotelling=16, lean=True, cluster=None, **kw)
+    assert lean.LS is None and lean.XT is None and lean.pXT is None
+    shape = (16, 4) if full.tile_shapes() else (4, 1)
+    for s in (full, lean):
+        s.set_cluster(shape)
+    full.cg_init()
+    lean.L.val.copy_(full.L.val)
+    with pytest.raises(RuntimeError):
+        lean.cg_init()
+    res = {}
+    for s in (full, lean):
+        s.eval()
+        torch.cuda.synchronize()
+        res[id(s)] = [(s.EN.clone(), s.G.val.clone(), s.F.val.clone())]
+        s.mixed_setup()
+        for acc in ((ACC_F32, ACC_F16X3) if shape[0] == 16 else (ACC_F32,)):
+            L_.call("lnv_set_f32_accumulation", acc)
+            s.eval_mixed()
+            torch.cuda.synchronize()
+            res[id(s)].append((s.EN.clone(), s.G.val.clone(), s.F.val.clone()))
+        L_.call("lnv_set_f32_accumulation", ACC_F32)
+        s.eval()          # FP64 again after the FP32 ones (shared memory in the lean system)
+        torch.cuda.synchronize()
+        res[id(s)].append((s.EN.clone(), s.G.val.clone(), s.F.val.clone()))
+    a, b = res[id(full)], res[id(lean)]
+    for k, ((E1, G1, F1), (E2, G2, F2)) in enumerate(zip(a, b)):
+        tol = 1e-12 if k in (0, len(a) - 1) else 1e-5
+        print(f"{name} {k}: dE/atom {abs(float(E1[0] - E2[0])) / w.n:.2e} "
+              f"dG {float((G1 - G2).abs().max() / G1.abs().max()):.2e}", flush=True)
+        assert abs(float(E1[0] - E2[0])) / w.n <= tol * 1e2, k
+        assert abs(float(E1[1] - E2[1])) <= tol * float(E1[1]), k
+        assert (G1 - G2).abs().max() <= tol * G1.abs().max(), k
+        assert (F1 - F2).abs().max() <= tol * F1.abs().max(), k
+    assert torch.equal(b[0][0], b[-1][0])
+    for s in (full, lean):
+        s.set_cluster((4, 1))
