@@ -104,3 +104,33 @@ class RowOracle:
             Gb[t, :, :nj] = Gi[:, self.off[j]:self.off[j + 1]]
             Fb[t, :, :nj] = Fi[:, self.off[j]:self.off[j + 1]]
         return e, nn, Gb, Fb, cols
+
+
+def reach(w):
+    """Distance from a row's atom within which `RowOracle.row` reads matrix
+    rows: the chain M1 M2 ... Mm applied to row i of M1 reads the rows of
+    M(k+1) within R1 + ... + Rk of atom i (minimum-image distances obey the
+    triangle inequality), and the longest chains are S.L.H.L.S and H.L.S.L.S
+    (in G) and L.S.L.S.L (in K): R_H + R_S + 2 R_L."""
+    return w.R_H + w.R_S + 2.0 * w.R_L
+
+
+def region_patterns(w, atoms):
+    """Range patterns (S, H, L) whose rows are those of the full patterns for
+    every atom within reach(w) + 1 bohr of the given atoms and empty
+    elsewhere: a RowOracle on them gives exactly the rows of those atoms, at
+    a fraction of the set-up cost of the full patterns on large cells.
+    Returns ((pS, pH, pL), number of rows kept)."""
+    d = w.pos[None, :, :] - w.pos[np.asarray(atoms)][:, None, :]
+    d = d - w.box * np.rint(d / w.box)
+    near = np.nonzero(((d * d).sum(-1) <= (reach(w) + 1.0) ** 2).any(0))[0]
+    out = []
+    for R in (w.R_S, w.R_H, w.R_L):
+        cols = st.neighbours(w.pos, w.box, R, rows=near)
+        lens = np.zeros(w.n, dtype=np.int64)
+        lens[near] = [len(c) for c in cols]
+        rp = np.zeros(w.n + 1, dtype=np.int64)
+        rp[1:] = np.cumsum(lens)
+        out.append((rp.astype(np.int32), np.concatenate(cols).astype(np.int32)))
+    return tuple(out), len(near)
+

@@ -7,6 +7,7 @@ stored instead of recomputed inside the GPU tests.
 
 usage: python tests/golden/make_golden.py si4096_4x4 [n_cg_steps]
        python tests/golden/make_golden.py rows siOH8192_mixed
+       python tests/golden/make_golden.py rows si32768_13f
        python tests/golden/make_golden.py cgtraj si4096_4x4 [n_cg_steps]
 
 The third form writes <workload>_cg.json and <workload>_cg_rows.npz: the
@@ -22,7 +23,10 @@ The second form writes <workload>_rows.npz: the row-wise oracle's G and F
 rows (and per-atom energy / electron contributions) of a few sampled atoms at
 the seeded test matrix L = 0.1 (w M + 2I) on L's range -- the synthetic
 overlap generator with master seed + 1000, range R_L and decay 3 bohr -- for
-the 78646-orbital Si/O/H cell, where no dense matrix fits.
+the cells where no dense matrix fits (the 78646-orbital Si/O/H cell, the
+425984-orbital 13-function cell); the oracle's matrices hold only the rows
+within reach of the sampled atoms (region_patterns), which the sampled rows
+depend on (oracle/rows.py, region_patterns).
 """
 from __future__ import annotations
 
@@ -64,13 +68,11 @@ def rows_main(name):
     from oracle import rows as orows
     w = W.get(name)
     t0 = time.time()
-    pS = ost.neighbours(w.pos, w.box, w.R_S)
-    pH = ost.neighbours(w.pos, w.box, w.R_H)
-    pL = ost.neighbours(w.pos, w.box, w.R_L)
+    atoms = sample_atoms(w)
+    (pS, pH, pL), nrow = orows.region_patterns(w, atoms)
     ro = orows.RowOracle(w, ost.synth_blocks(w, "S", *pS), ost.synth_blocks(w, "H", *pH),
                          test_L_blocks(w, pL), pS, pH, pL)
-    print(f"set-up {time.time() - t0:.1f}s", flush=True)
-    atoms = sample_atoms(w)
+    print(f"set-up {time.time() - t0:.1f}s ({nrow} of {w.n} rows in reach)", flush=True)
     out = {"atoms": np.array(atoms), "e": [], "n": []}
     for i in atoms:
         e, nn, Gb, Fb, cols = ro.row(i)

@@ -1,10 +1,16 @@
-"""The 78646-orbital amorphous Si/O/H cell (8192 atoms, 13/9/4 functions) on
-the GPU, in the row layout and launch configuration bench.py uses for it.
+"""The cells with atoms of several stored rows at scale, on the GPU, in the
+row layout and launch configuration bench.py uses for them:
 
-The dense oracle does not fit at this size; the row-wise oracle's G and F
-rows of six sampled atoms (every species included) at a seeded L are stored
-in tests/golden/siOH8192_mixed_rows.npz, written by
-`tests/golden/make_golden.py rows siOH8192_mixed` from the oracle only.  The
+* the 78646-orbital amorphous Si/O/H cell (8192 atoms, 13/9/4 functions;
+  rows in spatial cells, 4-row clusters);
+* the 425984-orbital 13-function diamond cell (32768 atoms, 131072 rows;
+  rows in bonded groups, a lean system -- no stored L.S and X^T -- on the
+  FP64 atom tiles (16, 4), as benchmarked).
+
+The dense oracle does not fit at these sizes; the row-wise oracle's G and F
+rows of sampled atoms (every species included) at a seeded L are stored in
+tests/golden/<workload>_rows.npz, written by
+`tests/golden/make_golden.py rows <workload>` from the oracle only.  The
 seeded L = 0.1 (w M + 2I) on L's range is generated on each side from the
 same counter definition (the synthetic overlap generator, master seed + 1000,
 range R_L, decay 3 bohr).  Tolerance: 1e-12 of the row's largest entry, as
@@ -20,15 +26,21 @@ import lnv_workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                    "siOH8192_mixed_rows.npz")
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "{}_rows.npz")
 
 
-def test_split_eval_at_scale_sampled_rows(gpu):
+@pytest.mark.parametrize("name", ["siOH8192_mixed", "si32768_13f"])
+def test_split_eval_at_scale_sampled_rows(gpu, name):
     from paper_2002_07704_amd.system import LNVSystem
-    w = W.get("siOH8192_mixed")
-    gold = np.load(GOLD)
-    s = LNVSystem(w, metric=None)
+    w = W.get(name)
+    gold = np.load(GOLD.format(name))
+    if name == "si32768_13f":
+        s = LNVSystem(w, metric=None, reorder="bonds", lean=True, cluster=None)
+        s.set_cluster((16, 4))
+        print(f"{name}: {s.n_rows} rows, grid {s.ix_cells.g}, device memory "
+              f"{torch.cuda.memory_allocated() / 2**30:.1f} GiB", flush=True)
+    else:
+        s = LNVSystem(w, metric=None)
     Lm = s.synth_values(0, s.pL, w.R_L, 3.0, w.seed + 1000)
     s.L.val.copy_(0.1 * Lm.val)
     del Lm
@@ -63,3 +75,5 @@ def test_split_eval_at_scale_sampled_rows(gpu):
         ef = np.abs(Fg - Fr).max() / np.abs(Fr).max()
         print(f"atom {i} (nfun {nfun[i]}): |dG|/max {eg:.1e} |dF|/max {ef:.1e}", flush=True)
         assert eg <= 1e-12 and ef <= 1e-12
+    del s
+    torch.cuda.empty_cache()

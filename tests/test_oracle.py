@@ -569,3 +569,31 @@ def test_cg_direction_rule_sets_the_convergence_rate():
     for name, rule in wrong.items():
         e_w, _ = err30(rule)
         assert e_w > 5e-6, (name, e_w)
+
+
+def test_row_oracle_region_patterns_give_the_same_rows():
+    """The row-wise oracle on patterns holding only the rows within reach of
+    the sampled atoms (region_patterns) gives exactly the rows it gives on the
+    full patterns: every row its product chains read is kept.  A 216-atom cell
+    with short ranges, so that the reach (R_H + R_S + 2 R_L) covers only part
+    of the box."""
+    import dataclasses
+    from oracle import rows as orows
+    w = dataclasses.replace(W.diamond_workload("si216", (3, 3, 3), seed=7),
+                            R_S=4.5, R_H=5.0, R_L=4.0)
+    atoms = [0, 100]
+    (rS, rH, rL), nrow = orows.region_patterns(w, atoms)
+    assert 0 < nrow < w.n
+    full = [st.neighbours(w.pos, w.box, R) for R in (w.R_S, w.R_H, w.R_L)]
+
+    def oracle(pS, pH, pL):
+        Lb = 0.1 * st.synth_blocks(dataclasses.replace(w, seed=w.seed + 1000, R_S=w.R_L), "S", *pL)
+        return orows.RowOracle(w, st.synth_blocks(w, "S", *pS), st.synth_blocks(w, "H", *pH),
+                               Lb, pS, pH, pL)
+
+    a, b = oracle(rS, rH, rL), oracle(*full)
+    for i in atoms:
+        ra, rb = a.row(i), b.row(i)
+        assert np.array_equal(ra[4], rb[4])
+        for x, y in zip(ra[:4], rb[:4]):
+            assert np.allclose(x, y, rtol=1e-14, atol=1e-14 * np.abs(y).max())

@@ -46,23 +46,3 @@ def test_row_order_choices():
     assert wa.groups is None
     with pytest.raises(ValueError):
         row_order(wa, "bonds", True)
-
-
-def test_atom_order_maps_permuted_rows_back():
-    """The range pattern of the atoms in the bonded order, with blocks tagged
-    by their atom pair, maps back to the pattern of the atoms' own order with
-    each block at its pair."""
-    import bench
-    w = W.get("si64_4x4")
-    g = np.asarray(w.groups)
-    rp, col = ost.neighbours(w.pos, w.box, w.R_L)
-    rpp, colp = ost.neighbours(w.pos[g], w.box, w.R_L)
-    blocks = np.zeros((len(colp), 4, 4))
-    for r in range(w.n):
-        for t in range(rpp[r], rpp[r + 1]):
-            blocks[t] = g[r] * 1000 + g[colp[t]]
-    rp2, col2, b2 = bench.atom_order(rpp, colp, blocks, g)
-    assert np.array_equal(rp2, rp) and np.array_equal(col2, col)
-    for a in range(w.n):
-        for t in range(rp[a], rp[a + 1]):
-            assert np.all(b2[t] == a * 1000 + col[t])
