@@ -195,7 +195,8 @@ def summarize_pmc(fetch_dir, write_dir, out_path, key, kernel, row_order):
         copies = [(i, v) for (i, n), v in per.items() if "copyBuffer" in n and v > 0.25 * COPY_BYTES]
         if not copies:
             raise SystemExit(f"no calibration copy found in {d}")
-        copy_id, copy_v = max(copies, key=lambda x: x[1])
+        # the calibration copy is the last large copy before the timed work
+        copy_id, copy_v = max(copies, key=lambda x: x[0])
         factor = COPY_BYTES / copy_v
         mul = [v for (i, n), v in per.items() if kernel in n and i > copy_id]
         out[counter] = {"factor": factor, "launches": len(mul),
