@@ -517,10 +517,12 @@ __device__ __forceinline__ void tile_load(T (&a)[4][4], T (&b)[NB][4], const int
   }
 }
 
+// Products of one step on the matrix cores: act bit 4q + ar set where A's
+// tile of cluster atom ar, B's tile of column atom q and the output tile all
+// exist (the other pairs are not multiplied).
 template <int MODE, int NB, typename T, typename AccT>
 __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
-                                         const T (&b)[NB][4], const int (&pa)[4],
-                                         const int (&pb)[NB], uint64_t cmask) {
+                                         const T (&b)[NB][4], int act) {
   if constexpr (MODE == TM_F16X3) {
     f16x4_t ah[4], al[4], bh[NB], bl[NB];
 #pragma unroll
@@ -529,10 +531,9 @@ __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
     for (int q = 0; q < NB; ++q) split_f16(b[q], bh[q], bl[q]);
 #pragma unroll
     for (int ar = 0; ar < 4; ++ar) {
-      if (pa[ar] < 0) continue;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        if (pb[q] < 0 || !((cmask >> (4 * q + ar)) & 1u)) continue;
+        if (!((act >> (4 * q + ar)) & 1)) continue;
         // the step's three products start from zero and join the running sum
         // through a rounded VALU add, so rounding in the matrix unit's own
         // accumulation does not build up over the contraction
@@ -546,10 +547,9 @@ __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
   } else {
 #pragma unroll
     for (int ar = 0; ar < 4; ++ar) {
-      if (pa[ar] < 0) continue;
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
-        if (pb[q] < 0 || !((cmask >> (4 * q + ar)) & 1u)) continue;
+        if (!((act >> (4 * q + ar)) & 1)) continue;
         // instruction p contracts k = 4c + p over the lane groups c
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -565,6 +565,30 @@ __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
   }
 }
 
+// One step of a piece's contraction: the cluster atoms' A tile positions,
+// the column atoms' B tile positions (-1: missing), B's row length of the
+// step's atom, the pairs to multiply (tile_mma).
+template <int NB>
+struct TileStep {
+  int pa[4], pb[NB], lenB, act;
+};
+
+// Atom-tile multiply on the matrix cores.  A wave owns one piece: the 4
+// atoms of a 16-row cluster c (4 rows each) times NB column atoms of the
+// cluster's output list, 4 x NB output tiles of 16 x 16 held in the matrix
+// accumulators; the contraction runs over the atoms k of the cluster's
+// contraction list (the union of its rows' columns of A).
+//
+// The list is scanned 64 steps at a time, one step per lane: each lane looks
+// up its step's A tiles (the cluster plan) and B tiles (B's spatial index,
+// cell window of atom k against each column atom's cell), and a ballot keeps
+// the steps with at least one pair to multiply -- with finite ranges most
+// steps of a piece meet none of its column atoms.  The kept steps are then
+// taken in order (lowest lane first), their positions read from the owning
+// lane, the fragments of the next kept step loaded while the current one
+// multiplies.  Lookups are independent per lane, so a chunk costs one
+// round of memory latency rather than one per step; the products and their
+// order are those of the full list.
 template <int NB, int MODE, int TB, int STORE, int NDOT, typename T>
 __global__ __launch_bounds__(256) void k_tile16(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
@@ -594,17 +618,16 @@ __global__ __launch_bounds__(256) void k_tile16(
     here = 4 * q < ncol && jc_pos[(size_t)(p0 + 4 * q) * 16 + 4 * ar] >= 0;
   }
   const uint64_t cmask = __ballot(here);
-  // the index lanes 8 .. 8+NB-1: column atom q = lane - 8 of the piece (its
-  // unit in B's index), with the cell and slot its lookups need
-  const bool bl = lane >= 8 && lane < 8 + NB && 4 * (lane - 8) < ncol;
-  const int my_b = bl ? jc_col[p0 + 4 * (lane - 8)] >> 2 : 0;
-  const int my_cell = bx.cell[my_b], my_slot = bx.slot[my_b];
-  // TB: row lengths in B' of the piece's column atoms
-  int lenBq[NB];
+  // the piece's column atoms: unit in B's index, cell (-1 past the piece's
+  // end), slot; TB: row lengths in B' of those atoms
+  int jb[NB], jcell[NB], jslot[NB], lenBq[NB];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int e = min(4 * q, max(ncol - 4, 0));
-    const int jr = jc_col[p0 + e];
+    const bool ok = 4 * q < ncol;
+    const int jr = jc_col[p0 + (ok ? 4 * q : 0)];
+    jb[q] = jr >> 2;
+    jcell[q] = ok ? bx.cell[jb[q]] : -1;
+    jslot[q] = bx.slot[jb[q]];
     lenBq[q] = TB ? bx.rp[jr + 1] - bx.rp[jr] : 0;
   }
   int rowA[4];
@@ -615,6 +638,7 @@ __global__ __launch_bounds__(256) void k_tile16(
     rowA[ar] = (li >> 2) * len;  // this lane's sub-row of the tile
   }
   const int t0 = ka_ptr[c], t1 = ka_ptr[c + 1];
+  const int nsteps = (t1 - t0) >> 2;  // atoms of the contraction union
   const int amax = a_nnzb - 1, bmax = b_nnzb - 1;
 
   AccT acc[4][NB];
@@ -625,65 +649,87 @@ __global__ __launch_bounds__(256) void k_tile16(
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[ar][q][v] = 0;
 
-  const int nsteps = (t1 - t0) >> 2;  // atoms of the contraction union
-  if (nsteps > 0) {
-    const int tl = t0 + 4 * (nsteps - 1);
-    // index vector for the step whose entries start at te (k row 4k = kk,
-    // packed cell ck and slot sk of atom k): lanes 0-3 the cluster atoms' A
-    // positions, 4-5 B's row pointers of row kk, 6 / 7 / 12 the k, cell and
-    // slot of the next step, 8.. the table entries of B's tiles (k, j_q)
-    // (TB: of B''s tiles (j_q, k)), the index's trailing -1 outside the window
-    auto iv_src = [&](int te, int kk, int ck, int sk) -> const int* {
-      const int tc = min(max(te, t0), tl);
-      const int tn = min(max(te + 4, t0), tl);
-      if (lane < 4) return ka_pos + (size_t)tc * 16 + 4 * lane;
-      if (lane < 6) return bx.rp + kk + (lane - 4);
-      if (lane == 6) return ka_col + tn;
-      if (lane == 7) return ka_key + 2 * (size_t)tn;
-      if (lane == 12) return ka_key + 2 * (size_t)tn + 1;
-      if (lane >= 8 && lane < 8 + NB) {
-        const int o = !bl ? -1 : TB ? ix_off(bx, my_cell, ck, sk) : ix_off(bx, ck, my_cell, my_slot);
-        if (o < 0) return bx.tab + bx.sent;
-        return bx.tab + (size_t)(TB ? my_b : kk >> 2) * bx.stride + o;
-      }
-      return ka_col + tl;
-    };
-    // before the first iteration: the index vector of step -1 (clamped to
-    // step 0's entries; never multiplied), whose lanes 6, 7, 12 give step 0's
-    // k, cell and slot
-    int ivp = *iv_src(t0 - 4, ka_col[t0], ka_key[2 * (size_t)t0], ka_key[2 * (size_t)t0 + 1]);
-    int pa0[4], pb0[NB];
+  // this lane's step of the current chunk (positions as in TileStep) and the
+  // chunk's kept steps not yet taken
+  int cpa[4], cpb[NB], clen = 0, cact = 0;
+  uint64_t rem = 0;
+  int base = -64;
+  auto scan = [&]() {
+    const int s = min(base + lane, nsteps - 1);
+    const int t = t0 + 4 * s;
+    const int kk = ka_col[t];  // B's row 4k of the step's atom k
+    const int ck = ka_key[2 * (size_t)t], sk = ka_key[2 * (size_t)t + 1];
 #pragma unroll
-    for (int ar = 0; ar < 4; ++ar) pa0[ar] = -1;
+    for (int ar = 0; ar < 4; ++ar) cpa[ar] = ka_pos[(size_t)t * 16 + 4 * ar];
+    clen = TB ? 0 : bx.rp[kk + 1] - bx.rp[kk];
+    int act = 0;
 #pragma unroll
-    for (int q = 0; q < NB; ++q) pb0[q] = -1;
-    T fa0[4][4] = {}, fb0[NB][4] = {}, fa1[4][4], fb1[NB][4];
-    // iteration u: read the indices of step u+1 (issued at u-1), issue those
-    // of step u+2, load the fragments of step u+1, multiply step u
-#define LNV_T16_STEP(u, FC_A, FC_B, FN_A, FN_B)                                  \
-  {                                                                              \
-    int pa1[4], pb1[NB];                                                         \
-    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) pa1[ar] =                   \
-        __builtin_amdgcn_readlane(ivp, ar);                                      \
-    const int lenB1 = __builtin_amdgcn_readlane(ivp, 5) - __builtin_amdgcn_readlane(ivp, 4); \
-    const int kk2 = __builtin_amdgcn_readlane(ivp, 6);                           \
-    const int ck2 = __builtin_amdgcn_readlane(ivp, 7);                           \
-    const int sk2 = __builtin_amdgcn_readlane(ivp, 12);                          \
-    _Pragma("unroll") for (int q = 0; q < NB; ++q) pb1[q] =                      \
-        __builtin_amdgcn_readlane(ivp, 8 + q);                                   \
-    const int ivn = *iv_src(t0 + 4 * ((u) + 2), kk2, ck2, sk2);                  \
-    tile_load<NB, TB, T>(FN_A, FN_B, pa1, pb1, lenB1, lenBq, a_val, b_val, rowA, li, lq, \
-                         amax, bmax);                                            \
-    if ((u) >= 0 && (u) < nsteps) tile_mma<MODE, NB>(acc, FC_A, FC_B, pa0, pb0, cmask); \
-    _Pragma("unroll") for (int ar = 0; ar < 4; ++ar) pa0[ar] = pa1[ar];          \
-    _Pragma("unroll") for (int q = 0; q < NB; ++q) pb0[q] = pb1[q];              \
-    ivp = ivn;                                                                   \
-  }
-    for (int u = -2; u < nsteps; u += 2) {
-      LNV_T16_STEP(u, fa0, fb0, fa1, fb1)
-      LNV_T16_STEP(u + 1, fa1, fb1, fa0, fb0)
+    for (int q = 0; q < NB; ++q) {
+      // tile (k, j_q) of B, TB: tile (j_q, k) of B'; the index's trailing -1
+      // outside the window
+      const int o = jcell[q] < 0 ? -1
+                    : TB         ? ix_off(bx, jcell[q], ck, sk)
+                                 : ix_off(bx, ck, jcell[q], jslot[q]);
+      const int* src = o < 0 ? bx.tab + bx.sent
+                             : bx.tab + (size_t)(TB ? jb[q] : kk >> 2) * bx.stride + o;
+      cpb[q] = *src;
+#pragma unroll
+      for (int ar = 0; ar < 4; ++ar)
+        if (cpa[ar] >= 0 && cpb[q] >= 0 && ((cmask >> (4 * q + ar)) & 1u))
+          act |= 1 << (4 * q + ar);
     }
-#undef LNV_T16_STEP
+    cact = act;
+    rem = __ballot(base + lane < nsteps && act != 0);
+  };
+  // the next kept step (false past the list's end: e then names no tile,
+  // its loads stay in bounds and nothing is multiplied)
+  auto next = [&](TileStep<NB>& e) -> bool {
+    while (rem == 0) {
+      base += 64;
+      if (base >= nsteps) {
+#pragma unroll
+        for (int ar = 0; ar < 4; ++ar) e.pa[ar] = -1;
+#pragma unroll
+        for (int q = 0; q < NB; ++q) e.pb[q] = -1;
+        e.lenB = 0;
+        e.act = 0;
+        return false;
+      }
+      scan();
+    }
+    const int m = __builtin_ctzll(rem);
+    rem &= rem - 1;
+#pragma unroll
+    for (int ar = 0; ar < 4; ++ar) e.pa[ar] = __builtin_amdgcn_readlane(cpa[ar], m);
+#pragma unroll
+    for (int q = 0; q < NB; ++q) e.pb[q] = __builtin_amdgcn_readlane(cpb[q], m);
+    e.lenB = __builtin_amdgcn_readlane(clen, m);
+    e.act = __builtin_amdgcn_readlane(cact, m);
+    return true;
+  };
+
+  if (nsteps > 0) {
+    T fa0[4][4], fb0[NB][4], fa1[4][4], fb1[NB][4];
+    TileStep<NB> e0, e1;
+    if (next(e0)) {
+      tile_load<NB, TB, T>(fa0, fb0, e0.pa, e0.pb, e0.lenB, lenBq, a_val, b_val, rowA, li, lq,
+                           amax, bmax);
+      // two kept steps per turn, fragments double-buffered; the loads of the
+      // step after the one multiplied are issued first (unconditionally, so
+      // the wait before each product covers the older loads only)
+      for (;;) {
+        const bool h1 = next(e1);
+        tile_load<NB, TB, T>(fa1, fb1, e1.pa, e1.pb, e1.lenB, lenBq, a_val, b_val, rowA, li,
+                             lq, amax, bmax);
+        tile_mma<MODE, NB>(acc, fa0, fb0, e0.act);
+        if (!h1) break;
+        const bool h0 = next(e0);
+        tile_load<NB, TB, T>(fa0, fb0, e0.pa, e0.pb, e0.lenB, lenBq, a_val, b_val, rowA, li,
+                             lq, amax, bmax);
+        tile_mma<MODE, NB>(acc, fa1, fb1, e1.act);
+        if (!h0) break;
+      }
+    }
   }
 
   // epilogue: lane (n + 16g) holds column n of each tile (column n&3 of
