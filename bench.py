@@ -292,6 +292,17 @@ def build_headline():
     return s, setup, {"steps": len(pm_hist), "s": time.perf_counter() - t0}
 
 
+def headline_shape(s, acc):
+    """Atom-tile shape of the headline cell for an arithmetic (acc -1 FP64,
+    else the FP32 accumulation mode, which the caller has set): 4 x 4 tiles
+    per wave (16, 4) or 4 x 2 (16, 8), whichever evaluates faster; (shape,
+    {shape: ms})."""
+    from paper_2002_07704_amd import autotune
+    shp, tried = autotune.tune(s, candidates=s.tile_shapes(), reps=2, mixed=acc >= 0,
+                               acc=max(acc, 0))
+    return shp, {str(k): v for k, v in tried.items()}
+
+
 def bench_headline(args, lib):
     import torch
 
@@ -300,6 +311,10 @@ def bench_headline(args, lib):
     w = s.w
     torch.cuda.reset_peak_memory_stats()
     f_alg, f_pad = s.flops("eval"), s.flops("eval", padded=True)
+    # atom-tile shape per arithmetic (timed here, outside the timed steps)
+    shapes = {}
+    shape64, tried = headline_shape(s, -1)
+    shapes["f64"] = {"shape": str(shape64), "eval_ms": tried}
     for _ in range(args.warmup):
         s.eval()
     ms64 = wall_timed(s.eval, args.steps)
@@ -308,7 +323,8 @@ def bench_headline(args, lib):
     ms_k, nl = event_timed(lib, s.eval, args.steps)
     rl64 = roofline("k_tile16 (16x16 atom tiles, FP64 MFMA v_mfma_f64_16x16x4_f64; the six "
                     "multiply launches of each timed evaluation)", args.steps * f_alg, ms_k, nl,
-                    PEAK_FP64, "mfma", traffic_record(args.traffic_json, HEADLINE + ":f64", "bonds"))
+                    PEAK_FP64, "mfma", traffic_record(args.traffic_json, f"{HEADLINE}:f64:{shape64}",
+                                                 "bonds"))
     rl64["padded_tflops"] = args.steps * f_pad / (ms_k * 1e-3) / 1e12
     s.mixed_setup()
     mixed = {}
@@ -316,6 +332,8 @@ def bench_headline(args, lib):
     for acc, label, peak, mult in modes:
         L_.call("lnv_set_f32_accumulation", acc)
         try:
+            shp, tried = headline_shape(s, acc)
+            shapes[label] = {"shape": str(shp), "eval_ms": tried}
             for _ in range(max(1, args.warmup)):
                 s.eval_mixed()
             ms = wall_timed(s.eval_mixed, args.steps)
@@ -326,7 +344,7 @@ def bench_headline(args, lib):
         finally:
             L_.call("lnv_set_f32_accumulation", 0)
         rl = roofline(f"k_tile16 ({label})", args.steps * f_alg, msk, nlk, peak, "mfma",
-                      traffic_record(args.traffic_json, f"{HEADLINE}:{label}", "bonds"))
+                      traffic_record(args.traffic_json, f"{HEADLINE}:{label}:{shp}", "bonds"))
         # matrix-core utilisation: padded tile flops (x3 for the hi/lo split's
         # three products) against the mode's matrix peak
         rl["mfma_util"] = mult * args.steps * f_pad / (msk * 1e-3) / peak
@@ -336,7 +354,7 @@ def bench_headline(args, lib):
                         "dE_per_atom": abs(E - E64) / w.n, "dN_rel": abs(N - N64) / N64,
                         "dG_rel": dG, "dF_rel": dF,
                         "within_1e-6_Ha_per_atom": abs(E - E64) / w.n <= 1e-6,
-                        "roofline": rl}
+                        "tile_shape": str(shp), "roofline": rl}
     rl64["mfma_util"] = args.steps * f_pad / (ms_k * 1e-3) / PEAK_FP64
     out = {
         "metric": METRIC,
@@ -358,7 +376,7 @@ def bench_headline(args, lib):
                         f"bohr, natural-range products",
             "step": "one energy+gradient evaluation (E, N, G = dE/dL, F = dN/dL: six block-sparse "
                     "products on the FP64 atom tiles, FP64 assembly and traces) at the purified L",
-            "row_order": "bonds", "tile_shape": "(16, 4)", "lean": True,
+            "row_order": "bonds", "tile_shape": str(shape64), "lean": True,
             "metric_T": "Hotelling T ~ S^-1 on L's range (16 steps, set-up)",
             "start": f"canonical purification, {pm['steps']} steps, {pm['s']:.1f} s (set-up)",
             "spatial_index_grid": list(s.ix_cells.g),
@@ -369,6 +387,7 @@ def bench_headline(args, lib):
         "gflop_per_eval_padded": f_pad / 1e9,
         "gflops_per_s": f_alg / (ms64 * 1e-3) / 1e9,
         "setup_s": setup_s,
+        "tile_shapes_tried": shapes,
         "mixed": mixed,
         "peak_device_memory_GiB": torch.cuda.max_memory_allocated() / 2**30,
         "roofline": rl64,
@@ -623,6 +642,9 @@ def profile_headline(acc, reps=3):
     if acc >= 0:
         s.mixed_setup()
         L_.call("lnv_set_f32_accumulation", acc)
+    shp, _ = headline_shape(s, acc)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_headline": acc, "tile_shape": str(shp), "reps": reps}), flush=True)
     for _ in range(reps):
         s.eval_mixed() if acc >= 0 else s.eval()
     torch.cuda.synchronize()
@@ -643,6 +665,8 @@ def pmc_probe(args, acc):
         if acc >= 0:
             s.mixed_setup()
             L_.call("lnv_set_f32_accumulation", acc)
+        shp, _ = headline_shape(s, acc)
+        print(json.dumps({"pmc_probe_tile_shape": str(shp)}), flush=True)
         fn = s.eval_mixed if acc >= 0 else s.eval
         fn()
     else:

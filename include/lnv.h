@@ -25,10 +25,12 @@
  *    gives its hipError_t.  Errors of already enqueued kernels surface at
  *    the next synchronising call or at lnv_sync_check().
  *  - Blocks are stored row-major, one after another in pattern order
- *    (row by row, ascending column), blk*blk values per block.  The FP64
- *    kernels of this version take blk == 4 (4 support functions per atom,
- *    the SZ silicon basis of Sec. II.B); other block edges return
- *    LNV_EUNSUPPORTED.
+ *    (row by row, ascending column), blk*blk values per block, blk == 4
+ *    (other block edges return LNV_EUNSUPPORTED).  An atom with n_i
+ *    support functions (Sec. II.B: 4 for the SZ silicon basis, 9 or 13 for
+ *    larger ones) spans ceil(n_i / 4) consecutive stored rows, the layout of
+ *    lnv_atoms_layout; callers that hold atom blocks of n_i x n_j values
+ *    (lnv_vbsm) convert with lnv_vbsm_pack and lnv_vbsm_unpack.
  *  - Reductions (traces, dot products) are computed in FP64 with a fixed
  *    order that does not depend on timing: results are bitwise
  *    reproducible run to run on the same device and grid.
@@ -151,10 +153,88 @@ typedef struct lnv_bsm {
   void* val;               /* device [pat->nnzb * blk * blk] */
 } lnv_bsm;
 
-/* ------------------------------------------------------------ errors */
+/* ------------------------------------------------------------ atoms
+ * Atoms and their support functions (Sec. II.B: the density matrix and the
+ * Hamiltonian are written in the support functions of the atoms, element
+ * (i alpha, j beta), atom i carrying n_i functions).  lnv_atoms is the
+ * library's map from atoms to stored rows: atom a spans rows row_start[a] ..
+ * row_start[a+1]-1 (ceil(nfun[a]/4) rows); row r holds functions off_of[r]
+ * .. off_of[r]+3 of atom atom_of[r] (those past nfun[a] are zero padding).
+ * Atoms may be stored in any order (order in lnv_atoms_layout), e.g.
+ * spatially sorted so that neighbouring rows are neighbouring atoms.
+ */
+typedef struct lnv_atoms {
+  int32_t n_atoms;
+  int32_t n_rows;             /* stored rows, sum of ceil(nfun[a] / 4) */
+  const int32_t* nfun;        /* device [n_atoms]: support functions n_a (1..64) */
+  const int32_t* row_start;   /* device [n_atoms+1]: first stored row of each atom */
+  const int32_t* atom_of;     /* device [n_rows] */
+  const int32_t* off_of;      /* device [n_rows] */
+} lnv_atoms;
+
+/* Atom-blocked matrix with blocks of each atom pair's own size: the form in
+ * which the paper states the matrices (Sec. II.B).  row_ptr/col is CSR over
+ * atoms (columns ascending); block p (atoms i, j) holds n_i x n_j values,
+ * row-major, at val[val_off[p] ..] (lnv_vbsm_offsets). */
+typedef struct lnv_vbsm {
+  const lnv_atoms* atoms;     /* host pointer */
+  const int32_t* row_ptr;     /* device [n_atoms+1] */
+  const int32_t* col;         /* device [nnz] */
+  const int64_t* val_off;     /* device [nnz+1] */
+  int64_t nnz;                /* atom blocks */
+  int32_t dtype;              /* LNV_F64 or LNV_F32 */
+  void* val;                  /* device [val_off[nnz]] */
+} lnv_vbsm;
+
+/* lnv_atoms_layout -- the stored-row layout of atoms with nfun[a] support
+ * functions (device [n_atoms], each 1..64; Sec. II.B), atoms stored in the
+ * order order[0], order[1], ... (device [n_atoms], a permutation; NULL: atom
+ * order).  Two-phase: always writes row_start (device [n_atoms+1]) and
+ * *n_rows_out (host); with atom_of != NULL also atom_of and off_of (device
+ * [cap] each; LNV_ECAPACITY when cap < *n_rows_out).  LNV_EINVAL for an
+ * order that is not a permutation, LNV_EUNSUPPORTED for a function count
+ * outside 1..64 or more than LNV_MAX_ATOMS rows.  Set-up call: synchronises
+ * s. */
+int lnv_atoms_layout(const int32_t* nfun, int32_t n_atoms, const int32_t* order,
+                     int32_t* row_start, int32_t* atom_of, int32_t* off_of, int64_t cap,
+                     int32_t* n_rows_out, hipStream_t s);
+
+/* lnv_atoms_rows -- row_pos (device [n_rows][3]) = the position of each
+ * stored row's atom (atom_pos: device [n_atoms][3]), the positions that
+ * lnv_neighbours, lnv_cells and lnv_synth_blocks take for split atoms (the
+ * ranges of Sec. II.C.2 are atom distances, so every row of an atom shares
+ * its neighbours). */
+int lnv_atoms_rows(const lnv_atoms* A, const double* atom_pos, double* row_pos, hipStream_t s);
+
+/* lnv_vbsm_offsets -- val_off (device [nnz+1]) of an atom pattern (row_ptr,
+ * col: device, atom CSR with nnz blocks): block p of atoms (i, j) starts at
+ * the sum of n_i' n_j' over the blocks before it; *len_out (host, may be
+ * NULL) = val_off[nnz], the values to allocate.  Set-up call: synchronises
+ * s; LNV_EPATTERN for a malformed pattern. */
+int lnv_vbsm_offsets(const lnv_atoms* A, const int32_t* row_ptr, const int32_t* col,
+                     int64_t nnz, int64_t* val_off, int64_t* len_out, hipStream_t s);
+
+/* lnv_vbsm_pack -- B = A in the stored-row layout (Sec. II.B blocks to 4x4
+ * storage): element (s, t) of B's block (r, c) is element (off_of[r] + s,
+ * off_of[c] + t) of A's block (atom_of[r], atom_of[c]); zero past either
+ * atom's functions or where A has no block.  B's pattern is over the rows of
+ * A.atoms (n = n_rows), blk 4, same dtype as A.  Every block of B is
+ * written. */
+int lnv_vbsm_pack(const lnv_vbsm* A, lnv_bsm* B, hipStream_t s);
+
+/* lnv_vbsm_unpack -- A = B back in atom blocks: element (x, y) of A's block
+ * (i, j) is element (x mod 4, y mod 4) of B's block (row_start[i] + x/4,
+ * row_start[j] + y/4), zero where B has no block.  B's pattern needs its
+ * index; same dtype.  Every value of A is written. */
+int lnv_vbsm_unpack(const lnv_bsm* B, lnv_vbsm* A, hipStream_t s);
+
+/* ------------------------------------------------------------ errors
+ * Library infrastructure (error reporting); the paper has no counterpart.
+ */
 const char* lnv_strerror(int status);
 int lnv_last_hip_error(void);
-/* Synchronise s and report any asynchronous kernel error as LNV_EHIP. */
+/* Synchronise s and report any asynchronous kernel error as LNV_EHIP
+ * (library infrastructure). */
 int lnv_sync_check(hipStream_t s);
 
 /* ------------------------------------------------------------ a0: ranges
@@ -201,7 +281,9 @@ int lnv_pattern_product(const lnv_pattern* A, const lnv_pattern* B,
  * pattern (mask == NULL) or on mask: sum over the kept triples (i,k,j) of
  * 2 f_i f_k f_j, f = row_fun (device [n]: support functions present in each
  * stored row, so padded rows count only what they hold).  Host result in
- * *flops_out.  Set-up call: allocates temporaries, synchronises s. */
+ * *flops_out.  Set-up call: allocates temporaries, synchronises s.
+ * Cost of the range-truncated products of Sec. II.C.2.
+ */
 int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B, const lnv_pattern* mask,
                       const int32_t* row_fun, int64_t* flops_out, hipStream_t s);
 
@@ -217,7 +299,9 @@ int lnv_pattern_flops(const lnv_pattern* A, const lnv_pattern* B, const lnv_patt
  * leaves the multiply's last wave of work pieces nearly empty), and atoms
  * stored as 4 rows keep or drop whole 16x16 tiles, so the half of a tile4
  * pattern is tile4.  Columns ascending; two-phase like lnv_neighbours
- * (col == NULL counts).  Synchronises s. */
+ * (col == NULL counts).  Synchronises s.
+ * Uses the symmetry of L, S and H (Sec. II.C.2); a work-saving layout, not a step of the paper.
+ */
 int lnv_pattern_half(const lnv_pattern* P, int32_t* row_ptr, int32_t* col, int64_t cap,
                      int64_t* nnz_out, hipStream_t s);
 
@@ -227,7 +311,9 @@ int lnv_pattern_half(const lnv_pattern* P, int32_t* row_ptr, int32_t* col, int64
  * lies in cell floor(frac(((x - origin) / box)) * g) per axis, and its slot
  * is its rank among the units of that cell in unit order.  Writes cell and
  * slot (device [n_units]) and *occ_out (host: the fullest cell's count).
- * Set-up call: copies the positions to the host, synchronises s. */
+ * Set-up call: copies the positions to the host, synchronises s.
+ * Rests on the locality of the ranges of Sec. II.C.2 (a block exists only within its cutoff).
+ */
 int lnv_cells(const double* pos, int32_t n_units, const double* box, const int32_t* g,
               const double* origin, int32_t* cell, int32_t* slot, int32_t* occ_out,
               hipStream_t s);
@@ -240,14 +326,18 @@ int lnv_cells(const double* pos, int32_t n_units, const double* box, const int32
  * the table's length, n_units * stride + 1 (a trailing -1 that lookups
  * outside the window may read); then with tab (device [cap]) the
  * table is written and P->ix.tab set (LNV_ECAPACITY if cap < *len_out).
- * Synchronises s. */
+ * Synchronises s.
+ * Rests on the locality of the ranges of Sec. II.C.2.
+ */
 int lnv_pattern_index(lnv_pattern* P, const int32_t* cell, const int32_t* slot,
                       const int32_t* g, int32_t occ, int32_t qs, int32_t* tab, int64_t cap,
                       int64_t* len_out, hipStream_t s);
 
 /* lnv_pattern_transpose_map -- perm[p] = position in PT of the transpose of
  * block p of P (PT must hold the transposed pattern and have its index);
- * LNV_EPATTERN when a block has no transpose in PT. */
+ * LNV_EPATTERN when a block has no transpose in PT.
+ * Transposes needed by G of Sec. II.C.2 (X + X^T).
+ */
 int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT, int32_t* perm,
                               hipStream_t s);
 
@@ -261,7 +351,9 @@ int lnv_pattern_transpose_map(const lnv_pattern* P, const lnv_pattern* PT, int32
  * with cl_col == NULL only *len_out (union length) and *n_items_out are
  * reported; cl_ptr is always written (device [ceil(n/m)+1]); cl_cell (device
  * [2*cap]) receives the packed cell and slot of each union column.
- * Synchronises s. */
+ * Synchronises s.
+ * Work decomposition of the products of Sec. II.C.2 on the GPU (the paper's partitions and processes are not reproduced).
+ */
 int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_ptr,
                         int32_t* cl_col, int32_t* cl_pos, int32_t* cl_cell, int64_t cap,
                         int32_t* cl_items, int64_t items_cap, int64_t* len_out,
@@ -276,12 +368,16 @@ int lnv_pattern_cluster(const lnv_pattern* P, int32_t m, int32_t g, int32_t* cl_
  * blocks of an atom tile are found from the position p of its first one as
  * p + s*len + t (sub-row s, sub-column t, len the row length).  0 otherwise
  * (4-function atoms, mixed atom sizes).  The value belongs in
- * lnv_pattern.tile4.  Set-up call: allocates flags, synchronises s. */
+ * lnv_pattern.tile4.  Set-up call: allocates flags, synchronises s.
+ * Atom tiles of 13-function atoms (Sec. II.B); layout for the products of Sec. II.C.2.
+ */
 int lnv_pattern_tile4(const lnv_pattern* P, int32_t* ok_out, hipStream_t s);
 
 /* lnv_pattern_items -- work list of P: with items == NULL only counts.
  *  n_items_out  host: number of items (LNV_ECAPACITY if cap is smaller).
- * Synchronises s. */
+ * Synchronises s.
+ * Work decomposition of the products of Sec. II.C.2 on the GPU.
+ */
 int lnv_pattern_items(const lnv_pattern* P, int32_t* items, int64_t cap,
                       int32_t* n_items_out, hipStream_t s);
 
@@ -306,6 +402,7 @@ int lnv_pattern_items(const lnv_pattern* P, int32_t* items, int64_t cap,
  * block, so the values do not depend on the split.  Such padded rows and
  * columns are zero in S and H; the CG's identity and Hotelling start leave
  * them at zero (see lnv_cg_init).
+ * Stands in for H and S of Sec. II.B (no real integrals here).
  */
 int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
                      const int32_t* atom_of, const int32_t* off_of, const lnv_bsm* M,
@@ -315,19 +412,35 @@ int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
 /* ------------------------------------------------------------ a3: multiply
  * lnv_bsm_multiply -- C = alpha * A * op(B) + beta * C on C's pattern only
  * (blocks of the product outside C's pattern are not formed: a range
- * truncated product).  op(B) = B (transB = 0) or B^T (transB = 1).
+ * truncated product).  op(B) = B (transB = 0) or B^T (transB = 1).  These
+ * are the sparse matrix products of Sec. II.C.2: with every matrix range
+ * truncated, each product costs a bounded number of block triples per row,
+ * so its cost is linear in the number of atoms.
  * Needs A.row_ptr/col, B's spatial index (either orientation) and C.items.
- * A, B and C share one dtype: FP64, or FP32 with FP32 products and FP32
- * accumulation (LNV_EUNSUPPORTED for a mix).  Hot path: allocates nothing.
+ * dtypes: all FP64; all FP32 (FP32 products and accumulation, or as set by
+ * lnv_set_f32_accumulation); or FP32 A and B with an FP64 C (FP64
+ * multiply-add: the products of FP32 values are exact in FP64, the sums
+ * round in FP64; beta scales the FP64 C).  Other mixes: LNV_EUNSUPPORTED.
+ * Hot path: allocates nothing and needs no workspace
+ * (lnv_multiply_ws_bytes).
  */
 int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
                      double beta, lnv_bsm* C, hipStream_t s);
+
+/* lnv_multiply_ws_bytes -- device workspace in bytes of the product C =
+ * A op(B) (Sec. II.C.2): 0 for lnv_bsm_multiply (with_dot = 0); with
+ * with_dot != 0 the partials buffer of lnv_bsm_multiply_dot (two doubles per
+ * work piece: the cluster pieces when the product runs on cluster plans,
+ * else C's row items).  Host result in *bytes_out; no device work. */
+int lnv_multiply_ws_bytes(const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
+                          const lnv_bsm* C, int32_t with_dot, int64_t* bytes_out);
 
 /* lnv_bsm_multiply_dot -- as lnv_bsm_multiply, and in the same pass
  * out[d] = <M_d, C> for the given partners M_1, M_2 (NULL to skip; both on
  * C's pattern); with store == 0 the finished product is not written back
  * (only the traces are wanted; C.val is not touched).  partials: device
  * [2 * max(C.n_items, C.n_cl_items)] scratch; out: device.
+ * The products and traces of Sec. II.C.2 (E = 2 Tr[KH] and N = 2 Tr[KS] are sums of such traces).
  */
 int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
                          double beta, lnv_bsm* C, int32_t store, const lnv_bsm* M1,
@@ -348,7 +461,9 @@ int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bsm* B, int32
  * (it creates events).  Every call on one GPU shares that GPU's scratch:
  * calls that overlap on one device (concurrent streams, or host threads)
  * race, and must be serialised by the caller.  Every work piece writes its
- * partials before they are reduced, so the scratch needs no clearing. */
+ * partials before they are reduced, so the scratch needs no clearing.
+ * Same operation as lnv_bsm_multiply_dot (Sec. II.C.2).
+ */
 #define LNV_NOALLOC_PARTIALS (1 << 19)
 int lnv_bsm_multiply_dot_noalloc(double alpha, const lnv_bsm* A, const lnv_bsm* B,
                                  int32_t transB, double beta, lnv_bsm* C, int32_t store,
@@ -357,27 +472,37 @@ int lnv_bsm_multiply_dot_noalloc(double alpha, const lnv_bsm* A, const lnv_bsm* 
 
 /* lnv_bsm_transpose -- AT = A^T: block p of A, transposed, goes to position
  * perm[p] of AT (perm from lnv_pattern_transpose_map).  Needs A.items.
- * A and AT of one dtype.  Hot path (HBM-bound copy). */
+ * A and AT of one dtype.  Hot path (HBM-bound copy).
+ * Transposes needed by G of Sec. II.C.2 (X + X^T, A^T X).
+ */
 int lnv_bsm_transpose(const lnv_bsm* A, const int32_t* perm, lnv_bsm* AT, hipStream_t s);
 
 /* lnv_bsm_convert -- B = A converted elementwise to B's dtype (FP64 <-> FP32,
  * round to nearest), A and B on the same pattern (or patterns with the same
- * number of blocks).  Hot path (HBM-bound). */
+ * number of blocks).  Hot path (HBM-bound).
+ * Feeds the mixed-precision products (not in the paper, which works in FP64).
+ */
 int lnv_bsm_convert(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
 
 /* lnv_bsm_lincomb -- out = a X + b Y + c Z elementwise on one pattern (Y, Z
- * may be NULL; out may alias any input).  FP64.  Hot path (HBM-bound). */
+ * may be NULL; out may alias any input).  FP64.  Hot path (HBM-bound).
+ * Updates of L and of the search vectors in the minimisation of Sec. II.C.2.
+ */
 int lnv_bsm_lincomb(double a, const lnv_bsm* X, double b, const lnv_bsm* Y, double c,
                     const lnv_bsm* Z, lnv_bsm* out, hipStream_t s);
 
 /* lnv_bsm_remap -- B = A carried over to B's pattern (same atoms, e.g. the
  * range pattern of a new geometry): blocks of B present in A's pattern are
- * copied, the others are zero.  A's pattern needs its index.  FP64, blk 4. */
+ * copied, the others are zero.  A's pattern needs its index.  FP64, blk 4.
+ * Carries L to a new geometry (molecular dynamics, Sec. III.C).
+ */
 int lnv_bsm_remap(const lnv_bsm* A, lnv_bsm* B, hipStream_t s);
 
 /* lnv_bsm_norm_inf -- out[0] = max_a sum_b |A_ab| (the matrix infinity norm,
  * over orbital rows).  partials: device [A.pat->n] scratch; out: device.
- * FP64, blk 4. */
+ * FP64, blk 4.
+ * Gershgorin bound of the start of Hotelling's iteration (Sec. II.C.2).
+ */
 int lnv_bsm_norm_inf(const lnv_bsm* A, double* partials, double* out, hipStream_t s);
 
 /* lnv_set_f32_accumulation -- arithmetic of the FP32 products (process-wide):
@@ -390,7 +515,9 @@ int lnv_bsm_norm_inf(const lnv_bsm* A, double* partials, double* out, hipStream_
  * in FP16 and form Ah.Bh + Ah.Bl + Al.Bh on v_mfma_f32_16x16x16_f16 with
  * FP32 accumulation (about FP32 accuracy for |x| >= 5e-4; entries must stay
  * below 255 in magnitude); the 4x4 multiplies run as LNV_ACC_F32.
- * Either way the operands and the result are stored in FP32. */
+ * Either way the operands and the result are stored in FP32.
+ * Not in the paper (which works in FP64): arithmetic of this library's FP32 products.
+ */
 enum { LNV_ACC_F32 = 0, LNV_ACC_F64 = 1, LNV_ACC_F16X3 = 2 };
 int lnv_set_f32_accumulation(int32_t acc);
 
@@ -398,6 +525,7 @@ int lnv_set_f32_accumulation(int32_t acc);
  * with B_ij taken at the same position when B shares A's pattern object,
  * otherwise through B's spatial index (absent blocks count as zero).
  * partials: device [LNV_DOT_PARTIALS] scratch; out: device [1].  Hot path.
+ * The traces of Sec. II.C.2: for symmetric matrices Tr[AB] = <A, B>.
  */
 #define LNV_DOT_PARTIALS 1024
 int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* out,
@@ -471,7 +599,9 @@ typedef struct lnv_eval_ws {
    * on this workspace left (see lnv_cg_step).  lnv_cg_step sets it;
    * lnv_eval, lnv_hotelling and lnv_cg_init on this workspace clear it.  A
    * caller that changes L or S (or the buffers) itself between steps must
-   * clear it, or restart with k = 0.  Initialise to 0. */
+   * clear it, or restart with k = 0.  Initialise to 0.
+ * Sizing helper (library infrastructure).
+ */
   int32_t carry;
 } lnv_eval_ws;
 
@@ -510,6 +640,7 @@ enum {
  * scalars[LNV_SC_E/N]), G = dE/dL and F = dN/dL on L's pattern.  L, S, H,
  * G, F are FP64 with blk 4; L's pattern needs its index and items, S's needs its index.
  * Hot path: allocates nothing, no host synchronisation.
+ * Sec. II.C.2, Eq. (4).
  */
 int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
              lnv_bsm* F, double* EN, lnv_eval_ws* ws, hipStream_t s);
@@ -524,6 +655,7 @@ int lnv_eval(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, lnv_bsm* G,
  * lnv_neighbours_cells -- lnv_neighbours with each row tested only against
  * the rows of its own cell, in its cell's box (device arrays: cell_start
  * [n_cells+1], cell_of [n], boxes [n_cells*3]).  Same two-phase protocol.
+ * Ranges of Sec. II.C.2 applied per cell; batching itself is not in the paper.
  */
 int lnv_neighbours_cells(const double* pos, int32_t n, int32_t n_cells,
                          const int32_t* cell_start, const int32_t* cell_of, const double* boxes,
@@ -533,7 +665,9 @@ int lnv_neighbours_cells(const double* pos, int32_t n, int32_t n_cells,
 /* lnv_synth_blocks_cells -- lnv_synth_blocks for a batch: row i uses its
  * cell's box and seed (cell_of, boxes, seeds: device), atom_of[i] is the
  * row's atom index within its cell (the counter key), fun_of[i] that atom's
- * function count and off_of[i] the row's first function (all device [n]). */
+ * function count and off_of[i] the row's first function (all device [n]).
+ * As lnv_synth_blocks (Sec. II.B stand-ins), per cell.
+ */
 int lnv_synth_blocks_cells(const double* pos, const int32_t* cell_of, const double* boxes,
                            const uint64_t* seeds, const int32_t* atom_of, const int32_t* fun_of,
                            const int32_t* off_of, const lnv_bsm* M, int32_t kind, double R,
@@ -544,7 +678,9 @@ int lnv_synth_blocks_cells(const double* pos, const int32_t* cell_of, const doub
  * ws->partials; call it right after that evaluation, on the same stream and
  * workspace.  cell_item_ptr (device [n_cells+1]): the work items of L's
  * pattern that belong to each cell (items are in row order, so each cell's
- * items are one range).  Fixed reduction order. */
+ * items are one range).  Fixed reduction order.
+ * Per-cell E = 2 Tr[KH] and N = 2 Tr[KS] (Sec. II.C.2).
+ */
 int lnv_cell_traces(const lnv_pattern* PL, const lnv_eval_ws* ws, int32_t n_cells,
                     const int32_t* cell_item_ptr, double* EN_cells, hipStream_t s);
 
@@ -577,7 +713,9 @@ typedef struct lnv_eval32_ws {
   double* partials;
   int64_t partials_len;
   double* scalars;
-  lnv_bsm Zu;   /* optional half products, as in lnv_eval_ws (FP32) */
+  lnv_bsm Zu;   /* optional half products, as in lnv_eval_ws (FP32)
+ * Sec. II.C.2, Eq. (4), with FP32 products (not in the paper).
+ */
   lnv_bsm Lu;
   void* Vu;
 } lnv_eval32_ws;
@@ -629,7 +767,9 @@ typedef struct lnv_adj_ws {
    * (dS takes Y + Y^T), so the contraction runs over LS's or LH's rows with
    * the natural-range L.S.L on the right, whose pattern then needs its index; the
    * left patterns need items (and the cluster plans of the other left
-   * operands). */
+   * operands).
+ * Forces need dE/dS and dE/dH (Sec. III.A).
+ */
   lnv_bsm LS;
   const int32_t* perm_SL;
   lnv_bsm LH;
@@ -679,7 +819,9 @@ int lnv_occupation_bounds(const lnv_bsm* L, const lnv_bsm* S, int32_t steps, dou
 /* lnv_cg_check -- synchronise s and report the sticky status of a
  * minimisation (scalars: device [LNV_NSCALARS]): LNV_ENUMERIC when
  * LNV_ST_NONFINITE or LNV_ST_RUNAWAY is set, else LNV_OK; *status_out
- * (host, may be NULL) receives the bits. */
+ * (host, may be NULL) receives the bits.
+ * Guards the minimisation of Sec. II.C.2 (weak idempotency: occupations in [0, 1]).
+ */
 int lnv_cg_check(const double* scalars, int32_t* status_out, hipStream_t s);
 
 /* ------------------------------------------------------------ a5-a7: CG
@@ -756,6 +898,7 @@ int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, h
  * that of the orbitals present: diagonal entries whose S_aa is zero (padded
  * rows, see lnv_synth_blocks) are left at zero, and so stay zero through the
  * CG (their gradient vanishes).  S's pattern needs its index.
+ * Start of the minimisation of Sec. II.C.2.
  */
 int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, lnv_cg_ws* ws,
                 hipStream_t s);
@@ -798,7 +941,9 @@ int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T
  * Optional HIP-event timing of the block multiply kernel: while enabled,
  * every multiply launch is bracketed by events on its stream.
  * lnv_timing_read synchronises the recorded events and returns the summed
- * kernel time (ms) and launch count since the last reset. */
+ * kernel time (ms) and launch count since the last reset.
+ * Library infrastructure (measurement).
+ */
 int lnv_timing_enable(int32_t on);
 int lnv_timing_read(double* ms_total, int64_t* launches);
 int lnv_timing_reset(void);

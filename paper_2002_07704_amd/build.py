@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblnv.so")
-SOURCES = ["setup.hip", "multiply.hip", "lnv_core.hip", "adjoint.hip", "guard.hip"]
+SOURCES = ["setup.hip", "multiply.hip", "lnv_core.hip", "adjoint.hip", "guard.hip", "atoms.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -176,13 +176,15 @@ __device__ __forceinline__ const int* entry_kj(const Ix& x, int k, int ck, int c
   return x.tab + (o < 0 ? (size_t)x.sent : (size_t)(k >> x.qs) * x.stride + o);
 }
 
-template <int TRANS_B, int STORE, int NDOT, typename T, typename Acc>
+// One row piece per wave, one lane per output column (TC: C's value type,
+// T: A's and B's).
+template <int TRANS_B, int STORE, int NDOT, typename T, typename Acc, typename TC = T>
 __global__ __launch_bounds__(256) void k_mul44(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ a_rp,
     const int* __restrict__ a_col, const T* __restrict__ a_val, Ix bx,
     const T* __restrict__ b_val, const int* __restrict__ c_rp, const int* __restrict__ c_col,
-    T* __restrict__ c_val, double alpha, double beta, const T* __restrict__ m1,
-    const T* __restrict__ m2, double* __restrict__ partials, const double* __restrict__ skip) {
+    TC* __restrict__ c_val, double alpha, double beta, const TC* __restrict__ m1,
+    const TC* __restrict__ m2, double* __restrict__ partials, const double* __restrict__ skip) {
   if (skip != nullptr && *skip != 0.0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int item = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
@@ -813,6 +815,22 @@ using KernelFn = void (*)(int, int, const int*, const int*, const int*, const T*
                           const int*, const int*, T*, double, double, const T*, const T*,
                           double*, const double*);
 
+// FP32 A and B, FP64 C: FP64 multiply-add (exact FP32 products, FP64 sums).
+using KernelMixFn = void (*)(int, int, const int*, const int*, const int*, const float*, Ix,
+                             const float*, const int*, const int*, double*, double, double,
+                             const double*, const double*, double*, const double*);
+
+template <int TB>
+KernelMixFn pick_mix(int store, int ndot) {
+  if (store) {
+    if (ndot == 0) return k_mul44<TB, 1, 0, float, double, double>;
+    if (ndot == 1) return k_mul44<TB, 1, 1, float, double, double>;
+    return k_mul44<TB, 1, 2, float, double, double>;
+  }
+  if (ndot == 1) return k_mul44<TB, 0, 1, float, double, double>;
+  return k_mul44<TB, 0, 2, float, double, double>;
+}
+
 template <int TB, typename T, typename Acc>
 KernelFn<T> pick_store(int store, int ndot) {
   if (store) {
@@ -883,6 +901,7 @@ bool use_tiles(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C)
 }
 
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
+  if (A->dtype != C->dtype) return C->pat->n_items;  // FP32 into FP64: row kernel
   return use_clustered(A, B, transB, C) || use_tiles(A, B, transB, C) ? C->pat->n_cl_items
                                                                       : C->pat->n_items;
 }
@@ -1030,12 +1049,38 @@ int multiply_pair_launch(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1
                                            m22, part2, skip, ndot, s);
 }
 
+namespace {
+
+// FP32 A and B into an FP64 C (row kernel).
+int launch_mix(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, double beta,
+               const lnv_bsm* C, int store, const void* m1, const void* m2, double* partials,
+               const double* skip, int ndot, hipStream_t s) {
+  const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
+  if (pc->n_items == 0) return LNV_OK;
+  const int wgs = round_up((pc->n_items + 3) / 4, kNumXcd);
+  hipEvent_t stop = nullptr;
+  LNV_TRY(timer_begin(s, &stop));
+  KernelMixFn fn = transB ? pick_mix<1>(store, ndot) : pick_mix<0>(store, ndot);
+  fn<<<wgs, 256, 0, s>>>(pa->n, pc->n_items, pc->items, pa->row_ptr, pa->col,
+                         static_cast<const float*>(A->val), make_ix(pb),
+                         static_cast<const float*>(B->val), pc->row_ptr, pc->col,
+                         static_cast<double*>(C->val), alpha, beta,
+                         static_cast<const double*>(m1), static_cast<const double*>(m2),
+                         partials, skip);
+  LNV_LAUNCH_CHECK();
+  if (stop) LNV_HIP(hipEventRecord(stop, s));
+  return LNV_OK;
+}
+
+}  // namespace
+
 int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB,
                     double beta, const lnv_bsm* C, int store, const void* m1,
                     const void* m2, double* partials, const double* skip,
                     hipStream_t s) {
   if (!bsm_ok_any(A) || !bsm_ok_any(B) || !bsm_ok_any(C)) return LNV_EINVAL;
-  if (A->dtype != C->dtype || B->dtype != C->dtype) return LNV_EUNSUPPORTED;
+  const bool mix = A->dtype == LNV_F32 && B->dtype == LNV_F32 && C->dtype == LNV_F64;
+  if (!mix && (A->dtype != C->dtype || B->dtype != C->dtype)) return LNV_EUNSUPPORTED;
   if (A->blk != 4 || B->blk != 4 || C->blk != 4) return LNV_EUNSUPPORTED;
   const lnv_pattern *pa = A->pat, *pb = B->pat, *pc = C->pat;
   if (pa->n != pb->n || pa->n != pc->n) return LNV_EPATTERN;
@@ -1045,6 +1090,7 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
   if (m2 && !m1) return LNV_EINVAL;
   if (ndot > 0 && !partials) return LNV_EINVAL;
   if (!store && ndot == 0) return LNV_EINVAL;
+  if (mix) return launch_mix(alpha, A, B, transB, beta, C, store, m1, m2, partials, skip, ndot, s);
   if (C->dtype == LNV_F32) {
     if (g_f32_acc == LNV_ACC_F64)
       return launch_typed<float, double>(alpha, A, B, transB, beta, C, store, m1, m2, partials,
@@ -1064,6 +1110,14 @@ extern "C" int lnv_bsm_multiply(double alpha, const lnv_bsm* A, const lnv_bsm* B
                                 int32_t transB, double beta, lnv_bsm* C, hipStream_t s) {
   return multiply_launch(alpha, A, B, transB, beta, C, 1, nullptr, nullptr, nullptr, nullptr,
                          s);
+}
+
+extern "C" int lnv_multiply_ws_bytes(const lnv_bsm* A, const lnv_bsm* B, int32_t transB,
+                                     const lnv_bsm* C, int32_t with_dot, int64_t* bytes_out) {
+  if (!bsm_ok_any(A) || !bsm_ok_any(B) || !bsm_ok_any(C) || !bytes_out) return LNV_EINVAL;
+  *bytes_out = with_dot ? 2 * (int64_t)multiply_nparts(A, B, transB, C) * (int64_t)sizeof(double)
+                        : 0;
+  return LNV_OK;
 }
 
 extern "C" int lnv_set_f32_accumulation(int32_t acc) {

@@ -84,8 +84,20 @@ class LnvOpts(ctypes.Structure):
                 ("eval32", c_void_p), ("occ_every", c_int32), ("occ_iter", c_int32)]
 
 
+class LnvAtoms(ctypes.Structure):
+    _fields_ = [("n_atoms", c_int32), ("n_rows", c_int32), ("nfun", c_void_p),
+                ("row_start", c_void_p), ("atom_of", c_void_p), ("off_of", c_void_p)]
+
+
+class LnvVbsm(ctypes.Structure):
+    _fields_ = [("atoms", POINTER(LnvAtoms)), ("row_ptr", c_void_p), ("col", c_void_p),
+                ("val_off", c_void_p), ("nnz", c_int64), ("dtype", c_int32), ("val", c_void_p)]
+
+
 PPat = POINTER(LnvPattern)
 PBsm = POINTER(LnvBsm)
+PAtoms = POINTER(LnvAtoms)
+PVbsm = POINTER(LnvVbsm)
 
 # name -> (restype, argtypes); the exported symbols of include/lnv.h
 SIGNATURES = {
@@ -112,6 +124,14 @@ SIGNATURES = {
                                     POINTER(c_int32), c_void_p]),
     "lnv_pattern_tile4": (c_int, [PPat, POINTER(c_int32), c_void_p]),
     "lnv_bsm_transpose": (c_int, [PBsm, c_void_p, PBsm, c_void_p]),
+    "lnv_atoms_layout": (c_int, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                                 c_int64, POINTER(c_int32), c_void_p]),
+    "lnv_atoms_rows": (c_int, [PAtoms, c_void_p, c_void_p, c_void_p]),
+    "lnv_vbsm_offsets": (c_int, [PAtoms, c_void_p, c_void_p, c_int64, c_void_p,
+                                 POINTER(c_int64), c_void_p]),
+    "lnv_vbsm_pack": (c_int, [PVbsm, PBsm, c_void_p]),
+    "lnv_vbsm_unpack": (c_int, [PBsm, PVbsm, c_void_p]),
+    "lnv_multiply_ws_bytes": (c_int, [PBsm, PBsm, c_int32, PBsm, c_int32, POINTER(c_int64)]),
     "lnv_synth_blocks": (c_int, [c_void_p, POINTER(c_double), c_void_p, c_void_p, c_void_p, PBsm,
                                  c_int32, c_double, c_double, c_uint64, c_double, c_void_p]),
     "lnv_bsm_multiply": (c_int, [c_double, PBsm, PBsm, c_int32, c_double, PBsm, c_void_p]),

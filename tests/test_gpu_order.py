@@ -157,12 +157,31 @@ def test_bonded_layout_cg_from_purified_start_at_scale(gpu):
     assert max(abs(a - b) for a, b in zip(Ea, Eb)) / w.n <= 1e-9
 
 
+def atom_order(rp, col, blocks, atom_of):
+    """A block pattern and its 4x4 blocks with rows in the atoms' own order
+    (one row per atom, row r holding atom atom_of[r])."""
+    n = len(rp) - 1
+    lens = np.diff(rp)
+    inv = np.empty(n, dtype=np.int64)
+    inv[atom_of] = np.arange(n)
+    rp2 = np.zeros(n + 1, dtype=np.int64)
+    rp2[1:] = np.cumsum(lens[inv])
+    col2 = np.empty_like(col)
+    out = np.empty_like(blocks)
+    for a in range(n):
+        r = inv[a]
+        c = atom_of[col[rp[r]:rp[r + 1]]]
+        o = np.argsort(c, kind="stable")
+        col2[rp2[a]:rp2[a + 1]] = c[o]
+        out[rp2[a]:rp2[a + 1]] = blocks[rp[r]:rp[r + 1]][o]
+    return rp2.astype(rp.dtype), col2, out
+
+
 def test_bonded_layout_sampled_rows_at_benchmark_point(gpu):
     """The benchmark's configuration at full size: 4096 atoms, bonded rows,
     Hotelling metric, L after the purified start and two CG iterations.  Rows
     of G and F at that L, mapped back to atom order, against the row-wise
     oracle fed the same L (rows of both ends and the middle of the cell)."""
-    import bench
     from oracle import rows as orows
     from paper_2002_07704_amd.pm import pm_initial_L
     from paper_2002_07704_amd.system import LNVSystem
@@ -176,9 +195,9 @@ def test_bonded_layout_sampled_rows_at_benchmark_point(gpu):
     torch.cuda.synchronize()
     rp, col = s.pL.host()
     atom_of = s.atom_of.cpu().numpy()
-    rpa, cola, La = bench.atom_order(rp, col, s.L.val.cpu().numpy(), atom_of)
-    _, _, Ga = bench.atom_order(rp, col, s.G.val.cpu().numpy(), atom_of)
-    _, _, Fa = bench.atom_order(rp, col, s.F.val.cpu().numpy(), atom_of)
+    rpa, cola, La = atom_order(rp, col, s.L.val.cpu().numpy(), atom_of)
+    _, _, Ga = atom_order(rp, col, s.G.val.cpu().numpy(), atom_of)
+    _, _, Fa = atom_order(rp, col, s.F.val.cpu().numpy(), atom_of)
     pS = ost.neighbours(w.pos, w.box, w.R_S)
     pH = ost.neighbours(w.pos, w.box, w.R_H)
     Sb = ost.synth_blocks(w, "S", *pS)
