@@ -937,6 +937,64 @@ int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec, l
 int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
                 double n_elec, int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);
 
+/* ------------------------------------------------------------ batches of cells
+ * lnv_batch -- many independent cells minimised together: the cells are one
+ * block-diagonal system (lnv_neighbours_cells, lnv_synth_blocks_cells), every
+ * block product one launch for all of them, and every scalar of the
+ * minimisation (E, N, mu, beta, alpha, delta, the guard's state) taken per
+ * cell.  The rows of a cell are consecutive, so its work items of L's
+ * pattern and its values are ranges.  All pointers are device memory owned
+ * by the caller:
+ *  item_ptr  int32 [n_cells+1]: first work item of L's pattern (items are in
+ *            row order) of each cell, item_ptr[n_cells] = L's n_items
+ *  val_ptr   int64 [n_cells+1]: first value of each cell in L's values
+ *            (16 x the first block of its first row), val_ptr[n_cells] = 16 nnzb
+ *  row_cell  int32 [n_rows]: the cell of each block row
+ *  n_elec    FP64 [n_cells]: electron count of each cell
+ *  scalars   FP64 [n_cells * LNV_NSCALARS]: cell c's scalar block (LNV_SC_*,
+ *            status bits included) at c * LNV_NSCALARS; lnv_cg_check takes
+ *            one cell's block
+ * 1 <= n_cells <= 1024 (LNV_EUNSUPPORTED beyond).  The minimisation of
+ * Sec. II.C.2, per cell; the paper runs one system at a time (running many
+ * small systems in one launch is this library's addition).
+ */
+typedef struct lnv_batch {
+  int32_t n_cells;
+  const int32_t* item_ptr;
+  const int64_t* val_ptr;
+  const int32_t* row_cell;
+  const double* n_elec;
+  double* scalars;
+} lnv_batch;
+
+/* lnv_cg_init_batch -- lnv_cg_init (identity metric) per cell: L0 = lambda_c I
+ * on each cell's rows, lambda_c the smallest positive root of that cell's
+ * N(lambda I) = n_elec[c].  Clears every cell's scalar block (the
+ * correction counter too) and the direction history; writes L and
+ * LNV_SC_LAMBDA per cell.  Workspace as for lnv_cg_init (S's pattern needs
+ * its index).  Start of the minimisation of Sec. II.C.2, per cell.
+ */
+int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_batch* b, lnv_cg_ws* ws,
+                      hipStream_t s);
+
+/* lnv_cg_step_batch -- lnv_cg_step (identity metric, FP64) for every cell of
+ * a batch at once: the six products of the evaluation, the line search's and
+ * the electron-number check's and correction's products are one launch each
+ * for all cells; the traces are reduced per cell (fixed order) and mu,
+ * beta, alpha, the check and delta are taken per cell (a cell within the
+ * electron-number tolerance keeps delta = 0 while others are corrected).
+ * Differences from lnv_cg_step: no metric, no mixed-precision evaluation
+ * (opts->eval32 must be NULL: LNV_EUNSUPPORTED), no occupation bounds (the
+ * E-rise guard stays), S.L and S.L.S formed afresh every step, and the
+ * traces of the line search taken from stored products (a product's fused
+ * trace partials cover row clusters that may straddle two cells).  The
+ * workspace is lnv_cg_step's without a metric (ev.YT and ev.W serve as
+ * product scratch).  For k > 0, L and the workspace must be those the
+ * previous step left.  Sec. II.C.2 / Sec. V.C as lnv_cg_step, per cell.
+ */
+int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_batch* b,
+                      int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);
+
 /* ------------------------------------------------------------ timing
  * Optional HIP-event timing of the block multiply kernel: while enabled,
  * every multiply launch is bracketed by events on its stream.

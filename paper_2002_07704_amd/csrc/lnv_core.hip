@@ -33,6 +33,7 @@ namespace {
 // ------------------------------------------------------------------ reductions
 struct Red {
   int off, count, stride, dst, op;  // op 0: sum, 1: max
+  int kind;  // batch stages: 1 partials per work item of L's pattern, 2 per vector workgroup
 };
 struct RedList {
   Red r[8];
@@ -42,6 +43,20 @@ struct RedList {
 enum Stage {
   ST_NONE = 0, ST_EVAL, ST_BETA, ST_PROJ, ST_ALPHA, ST_NCHK, ST_DELTA, ST_INIT, ST_MU, ST_SIGMA
 };
+
+// A batch of independent cells minimised together (lnv_batch): cell c owns
+// L's work items item_ptr[c] .. item_ptr[c+1]-1 and values val_ptr[c] ..
+// val_ptr[c+1]-1 (rows of a cell are consecutive, so both are ranges), its
+// scalars at sc + c * LNV_NSCALARS.  The vector kernels give each cell `per`
+// workgroups (partial c * per + q); n = 0 is the plain one-system path.
+struct Seg {
+  int n = 0, per = 0;
+  const int* item_ptr = nullptr;
+  const int64_t* val_ptr = nullptr;
+  const int* row_cell = nullptr;
+  const double* n_elec = nullptr;
+};
+enum { RK_ALL = 0, RK_ITEMS = 1, RK_VEC = 2 };
 
 struct StageArgs {
   double n_elec, n_tol, step_cap;
@@ -150,13 +165,28 @@ __device__ bool cubic_min(double c1, double c2, double c3, double* alpha) {
   return true;
 }
 
+// One workgroup per system (a batch: workgroup c takes cell c's partials,
+// scalars and electron count).
 __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ partials,
                                                 RedList rl, double* __restrict__ sc,
-                                                int stage, StageArgs sa) {
+                                                int stage, StageArgs sa, Seg sg) {
   __shared__ double sh[16];
   __shared__ double shm[256];
+  const int cell = blockIdx.x;
+  if (sg.n > 0) {
+    sc += (size_t)cell * LNV_NSCALARS;
+    sa.n_elec = sg.n_elec[cell];
+    sa.en_out = nullptr;
+  }
   for (int q = 0; q < rl.nr; ++q) {
-    const Red rd = rl.r[q];
+    Red rd = rl.r[q];
+    if (sg.n > 0 && rd.kind == RK_ITEMS) {
+      rd.off += sg.item_ptr[cell] * rd.stride;
+      rd.count = sg.item_ptr[cell + 1] - sg.item_ptr[cell];
+    } else if (sg.n > 0 && rd.kind == RK_VEC) {
+      rd.off += cell * sg.per * rd.stride;
+      rd.count = sg.per;
+    }
     if (rd.op == 0) {
       double v = 0.0;
       for (int t = threadIdx.x; t < rd.count; t += 256) v += partials[rd.off + (size_t)t * rd.stride];
@@ -581,13 +611,13 @@ __global__ __launch_bounds__(256) void k_hprime(int n, const int* __restrict__ i
                                                 const double* __restrict__ H, Ix sx,
                                                 const double* __restrict__ S,
                                                 const double* __restrict__ sc,
-                                                double* __restrict__ Hp) {
+                                                double* __restrict__ Hp, Seg sg) {
   const int item = blockIdx.x;
   const int i = items[2 * item], c0 = items[2 * item + 1];
   const int cnt = min(kWave, rp[i + 1] - c0);
   const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
   if (b >= cnt) return;
-  const double mu = sc[LNV_SC_MU];
+  const double mu = sc[(sg.n > 0 ? (size_t)sg.row_cell[i] * LNV_NSCALARS : 0) + LNV_SC_MU];
   const int p = c0 + b;
   const int q = ix_find(sx, i, col[p]);
 #pragma unroll
@@ -661,7 +691,25 @@ __global__ __launch_bounds__(256) void k_convert(int64_t nv, const S* __restrict
 
 // ------------------------------------------------------------------ vector kernels
 // Fixed grid of kVecGrid workgroups, grid-stride over the nv values of L's
-// pattern; partial q of component c goes to partials[c * kVecGrid + q].
+// pattern; partial q of component c goes to partials[c * kVecGrid + q].  A
+// batch (Seg) gives cell c the workgroups c * per .. c * per + per - 1, which
+// stride over the cell's values with the cell's scalars.
+
+// This workgroup's value range, stride and scalars.
+struct VecRange {
+  int64_t lo, hi, start, step;
+  const double* sc;
+};
+
+__device__ __forceinline__ VecRange vec_range(int64_t nv, const double* sc, const Seg& sg) {
+  if (sg.n > 0) {
+    const int c = blockIdx.x / sg.per, q = blockIdx.x % sg.per;
+    const int64_t lo = sg.val_ptr[c];
+    return VecRange{lo, sg.val_ptr[c + 1], lo + (int64_t)q * 256 + threadIdx.x,
+                    (int64_t)sg.per * 256, sc + (size_t)c * LNV_NSCALARS};
+  }
+  return VecRange{0, nv, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256, sc};
+}
 
 // g = G - mu F and (metric runs) g_c = G_c - mu F_c;
 // partials <g, g_c>, <g, g_c_prev>, <g, g>
@@ -672,11 +720,12 @@ __global__ __launch_bounds__(256) void k_vec_g(int64_t nv, const double* __restr
                                                const double* __restrict__ gcprev,
                                                const double* __restrict__ sc,
                                                double* __restrict__ g, double* __restrict__ gc,
-                                               double* __restrict__ partials) {
+                                               double* __restrict__ partials, Seg sg) {
   __shared__ double sh[16];
-  const double mu = sc[LNV_SC_MU];
+  const VecRange vr = vec_range(nv, sc, sg);
+  const double mu = vr.sc[LNV_SC_MU];
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+  for (int64_t q = vr.start; q < vr.hi; q += vr.step) {
     const double v = G[q] - mu * F[q];
     g[q] = v;
     double vc = v;
@@ -748,11 +797,12 @@ __global__ __launch_bounds__(256) void k_vec_dir(int64_t nv, const double* __res
                                                  const double* __restrict__ F,
                                                  const double* __restrict__ sc,
                                                  double* __restrict__ D,
-                                                 double* __restrict__ partials) {
+                                                 double* __restrict__ partials, Seg sg) {
   __shared__ double sh[16];
-  const double beta = sc[LNV_SC_BETA];
+  const VecRange vr = vec_range(nv, sc, sg);
+  const double beta = vr.sc[LNV_SC_BETA];
   double s0 = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+  for (int64_t q = vr.start; q < vr.hi; q += vr.step) {
     const double v = beta != 0.0 ? -g[q] + beta * Dprev[q] : -g[q];
     D[q] = v;
     s0 = fma(v, F[q], s0);
@@ -766,11 +816,12 @@ __global__ __launch_bounds__(256) void k_vec_proj(int64_t nv, const double* __re
                                                   const double* __restrict__ g,
                                                   const double* __restrict__ sc,
                                                   double* __restrict__ D,
-                                                  double* __restrict__ partials) {
+                                                  double* __restrict__ partials, Seg sg) {
   __shared__ double sh[16];
-  const double coef = sc[LNV_SC_T5];
+  const VecRange vr = vec_range(nv, sc, sg);
+  const double coef = vr.sc[LNV_SC_T5];
   double s0 = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+  for (int64_t q = vr.start; q < vr.hi; q += vr.step) {
     const double v = D[q] - coef * F[q];
     D[q] = v;
     s0 = fma(g[q], v, s0);
@@ -783,12 +834,12 @@ __global__ __launch_bounds__(256) void k_vec_proj(int64_t nv, const double* __re
 __global__ __launch_bounds__(256) void k_vec_axpy(int64_t nv, const double* __restrict__ D,
                                                   const double* __restrict__ sc, int idx,
                                                   const double* __restrict__ skip,
-                                                  double* __restrict__ L) {
+                                                  double* __restrict__ L, Seg sg) {
   if (skip != nullptr && *skip != 0.0) return;
-  const double a = sc[idx];
+  const VecRange vr = vec_range(nv, sc, sg);
+  const double a = vr.sc[idx];
   if (a == 0.0) return;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256)
-    L[q] = L[q] + a * D[q];
+  for (int64_t q = vr.start; q < vr.hi; q += vr.step) L[q] = L[q] + a * D[q];
 }
 
 // Y = X + sc[idx] * Y
@@ -808,8 +859,8 @@ int64_t slot_len(int n_items_L) {
 }
 
 int scalar_stage(const double* partials, const RedList& rl, double* sc, int stage,
-                 const StageArgs& sa, hipStream_t s) {
-  k_scalar<<<1, 256, 0, s>>>(partials, rl, sc, stage, sa);
+                 const StageArgs& sa, hipStream_t s, const Seg& sg = Seg{}) {
+  k_scalar<<<sg.n > 0 ? sg.n : 1, 256, 0, s>>>(partials, rl, sc, stage, sa, sg);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
@@ -819,8 +870,9 @@ RedList reds() {
   r.nr = 0;
   return r;
 }
-void add(RedList& rl, int64_t off, int count, int stride, int dst, int op = 0) {
-  rl.r[rl.nr++] = Red{(int)off, count, stride, dst, op};
+void add(RedList& rl, int64_t off, int count, int stride, int dst, int op = 0,
+         int kind = RK_ALL) {
+  rl.r[rl.nr++] = Red{(int)off, count, stride, dst, op, kind};
 }
 
 // ix: the pattern must carry its spatial index (for lookups in either
@@ -970,7 +1022,7 @@ int sym_product_pair(const lnv_bsm* A1, const lnv_bsm* B1, const lnv_bsm* C1, co
 // traces (FP64, with the FP64 L64 on the left of every trace).
 template <typename T>
 int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, double* EN,
-                  hipStream_t s) {
+                  hipStream_t s, const Seg& sg = Seg{}) {
   const lnv_pattern* pl = L64->pat;
   const int dt = o.SL->dtype;
   lnv_bsm YT{pl, 4, dt, o.YT}, Wm{pl, 4, dt, o.W}, Vm{pl, 4, dt, o.V};
@@ -1011,25 +1063,26 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
                                    static_cast<const T*>(o.V), G, F, part);
   LNV_LAUNCH_CHECK();
   RedList rl = reds();
-  add(rl, 0 * (int64_t)ni, ni, 1, LNV_SC_T0);
-  add(rl, 1 * (int64_t)ni, ni, 1, LNV_SC_T1);
-  add(rl, 2 * (int64_t)ni, ni, 1, LNV_SC_T2);
-  add(rl, 3 * (int64_t)ni, ni, 1, LNV_SC_T3);
-  add(rl, 4 * (int64_t)ni, ni, 1, LNV_SC_FF);
-  add(rl, 5 * (int64_t)ni, ni, 1, LNV_SC_GF);
+  add(rl, 0 * (int64_t)ni, ni, 1, LNV_SC_T0, 0, RK_ITEMS);
+  add(rl, 1 * (int64_t)ni, ni, 1, LNV_SC_T1, 0, RK_ITEMS);
+  add(rl, 2 * (int64_t)ni, ni, 1, LNV_SC_T2, 0, RK_ITEMS);
+  add(rl, 3 * (int64_t)ni, ni, 1, LNV_SC_T3, 0, RK_ITEMS);
+  add(rl, 4 * (int64_t)ni, ni, 1, LNV_SC_FF, 0, RK_ITEMS);
+  add(rl, 5 * (int64_t)ni, ni, 1, LNV_SC_GF, 0, RK_ITEMS);
   StageArgs sa{};
   sa.en_out = EN;
-  return scalar_stage(part, rl, o.scalars, ST_EVAL, sa, s);
+  return scalar_stage(part, rl, o.scalars, ST_EVAL, sa, s, sg);
 }
 
 int eval_core(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, double* G, double* F,
               double* EN, const lnv_eval_ws* ws, hipStream_t s,
-              const double* sl_carry = nullptr, bool z_carry = false) {
+              const double* sl_carry = nullptr, bool z_carry = false,
+              double* scalars = nullptr, const Seg& sg = Seg{}) {
   EvalOps o{L,       S,           H,          &ws->SL,     &ws->LS, &ws->X,
             &ws->XT, &ws->Z,      ws->perm_SL, ws->perm_X,  ws->YT,  ws->W,
-            ws->V,   ws->partials, ws->scalars, &ws->Zu,    &ws->Lu, ws->Vu,
+            ws->V,   ws->partials, scalars ? scalars : ws->scalars, &ws->Zu,    &ws->Lu, ws->Vu,
             sl_carry, z_carry};
-  return eval_products<double>(L, o, G, F, EN, s);
+  return eval_products<double>(L, o, G, F, EN, s, sg);
 }
 
 int convert_launch(const lnv_bsm* A, lnv_bsm* B, hipStream_t s) {
@@ -1133,7 +1186,7 @@ extern "C" int lnv_bsm_multiply_dot(double alpha, const lnv_bsm* A, const lnv_bs
   add(rl, 0, ni, 2, 0);
   if (M2) add(rl, 1, ni, 2, 1);
   StageArgs sa{};
-  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa);
+  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa, Seg{});
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
@@ -1204,7 +1257,7 @@ extern "C" int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials,
   RedList rl = reds();
   add(rl, 0, grid, 1, 0);
   StageArgs sa{};
-  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa);
+  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa, Seg{});
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
@@ -1271,7 +1324,7 @@ extern "C" int lnv_bsm_norm_inf(const lnv_bsm* A, double* partials, double* out,
   RedList rl = reds();
   add(rl, 0, pa->n, 1, 0, 1);
   StageArgs sa{};
-  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa);
+  k_scalar<<<1, 256, 0, s>>>(partials, rl, out, ST_NONE, sa, Seg{});
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
@@ -1613,7 +1666,7 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
   sa.n_elec = n_elec;
   LNV_TRY(scalar_stage(part, rl, sc, ST_INIT, sa, s));
   k_vec_axpy<<<vec_grid(), 256, 0, s>>>(nv, ws->D, sc, LNV_SC_LAMBDA, nullptr,
-                                        static_cast<double*>(L->val));
+                                        static_cast<double*>(L->val), Seg{});
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
@@ -1702,7 +1755,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   }
   // 2-3. g = G - mu F, g_c = G_c - mu F_c, Polak-Ribiere beta with resets
   k_vec_g<<<kVecGrid, 256, 0, s>>>(nv, ws->G, ws->F, Gc, Fc, ws->gc_prev, sc, ws->g,
-                                   metric ? ws->gc : nullptr, part);
+                                   metric ? ws->gc : nullptr, part, Seg{});
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
@@ -1712,14 +1765,14 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     LNV_TRY(scalar_stage(part, rl, sc, ST_BETA, sa, s));
   }
   // 4. D = -g_c + beta D_prev, projected: D <- D - (<D,F>/<F,F_c>) F_c
-  k_vec_dir<<<kVecGrid, 256, 0, s>>>(nv, gcur, ws->D_prev, ws->F, sc, ws->D, part);
+  k_vec_dir<<<kVecGrid, 256, 0, s>>>(nv, gcur, ws->D_prev, ws->F, sc, ws->D, part, Seg{});
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
     add(rl, 0, kVecGrid, 1, LNV_SC_DF);
     LNV_TRY(scalar_stage(part, rl, sc, ST_PROJ, sa, s));
   }
-  k_vec_proj<<<kVecGrid, 256, 0, s>>>(nv, Fc, ws->g, sc, ws->D, part);
+  k_vec_proj<<<kVecGrid, 256, 0, s>>>(nv, Fc, ws->g, sc, ws->D, part, Seg{});
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
@@ -1729,7 +1782,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
   // 5. exact cubic line minimisation of E - mu N along D
   k_hprime<<<ph->n_items, 256, 0, s>>>(ph->n, ph->items, ph->row_ptr, ph->col,
                                        static_cast<const double*>(H->val), make_ix(S->pat),
-                                       static_cast<const double*>(S->val), sc, ws->Hp);
+                                       static_cast<const double*>(S->val), sc, ws->Hp, Seg{});
   LNV_LAUNCH_CHECK();
   lnv_bsm Hp{ph, 4, LNV_F64, ws->Hp};
   lnv_bsm XD{ev.X.pat, 4, LNV_F64, ev.X.val};
@@ -1742,7 +1795,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     for (int t = 0; t < 4; ++t) add(rl, tp.off[t], tp.n[t], tp.stride[t], LNV_SC_T0 + t);
     LNV_TRY(scalar_stage(part, rl, sc, ST_ALPHA, sa, s));
   }
-  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv);
+  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv, Seg{});
   LNV_LAUNCH_CHECK();
   // 6. electron number at the new L; cubic correction along F_c when needed
   lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
@@ -1787,15 +1840,15 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     // the reductions read stale partials when skipped; ST_DELTA ignores them
     LNV_TRY(scalar_stage(part, rl, sc, ST_DELTA, sa, s));
   }
-  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, Fc, sc, LNV_SC_DELTA, skip, Lv);
+  k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nv, Fc, sc, LNV_SC_DELTA, skip, Lv, Seg{});
   LNV_LAUNCH_CHECK();
   // S.L and S.L.S of the final L for the next step: + delta S.F_c (A_F^T,
   // in ev.SL) and + delta S.F_c.S (Z_F, in X's buffer)
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(nsl, static_cast<const double*>(ev.SL.val), sc,
-                                      LNV_SC_DELTA, skip, ws->SL2);
+                                      LNV_SC_DELTA, skip, ws->SL2, Seg{});
   LNV_LAUNCH_CHECK();
   k_vec_axpy<<<kVecGrid, 256, 0, s>>>(ev.Z.pat->nnzb * 16, static_cast<const double*>(ev.X.val),
-                                      sc, LNV_SC_DELTA, skip, static_cast<double*>(ev.Z.val));
+                                      sc, LNV_SC_DELTA, skip, static_cast<double*>(ev.Z.val), Seg{});
   LNV_LAUNCH_CHECK();
   if (metric)
     std::swap(ws->gc, ws->gc_prev);
@@ -1803,6 +1856,239 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     std::swap(ws->g, ws->gc_prev);
   std::swap(ws->D, ws->D_prev);
   ws->ev.carry = 1;
+  return LNV_OK;
+}
+
+// ------------------------------------------------------------------ batches of cells
+namespace {
+
+// Validation of a batch descriptor against L's pattern (host side; the
+// device tables themselves are the caller's).
+int check_batch(const lnv_batch* b, const lnv_pattern* pl) {
+  if (!b || b->n_cells < 1 || !b->item_ptr || !b->val_ptr || !b->row_cell || !b->n_elec ||
+      !b->scalars)
+    return LNV_EINVAL;
+  if (b->n_cells > pl->n) return LNV_EPATTERN;
+  if (b->n_cells > kVecGrid) return LNV_EUNSUPPORTED;   // one vector workgroup per cell at least
+  return LNV_OK;
+}
+
+Seg make_seg(const lnv_batch* b) {
+  Seg sg;
+  sg.n = b->n_cells;
+  sg.per = kVecGrid / b->n_cells;
+  sg.item_ptr = b->item_ptr;
+  sg.val_ptr = b->val_ptr;
+  sg.row_cell = b->row_cell;
+  sg.n_elec = b->n_elec;
+  return sg;
+}
+
+// Vector-kernel grid of a batch (cell c: workgroups c * per ...).
+int seg_grid(const Seg& sg) { return sg.n > 0 ? sg.n * sg.per : kVecGrid; }
+
+// The traces T0..T3 of cubic_traces for a batch: every product is stored
+// and traced per work item of L's pattern (k_dot_items), so each partial
+// belongs to one cell (a fused trace partial of the multiply covers a piece
+// of a row cluster, which may straddle two cells).  T0 = <P, X_P>,
+// Q = P_L(A_P^T X_P^T) = P_L(S P S P M): T1 = <L, Q>, T2 = <P, Q>;
+// T3 = <P, P_L(S L X_P^T)> = Tr[P S L S P M] (T3 = T1 when M = S).
+// Partials: T_t at partials + t * slot, one per item.
+int cubic_traces_batch(const lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* M, bool m_is_s,
+                       const double* P, const lnv_eval_ws& ev, double* apt, double* ap,
+                       const lnv_bsm* SLcur, lnv_bsm XP, const lnv_bsm* XPT, double* partials,
+                       int64_t slot, hipStream_t s) {
+  const lnv_pattern* pl = L->pat;
+  const int ni = pl->n_items;
+  lnv_bsm Pm{pl, 4, LNV_F64, const_cast<double*>(P)};
+  lnv_bsm APT{ev.SL.pat, 4, LNV_F64, apt};
+  lnv_bsm AP{ev.LS.pat, 4, LNV_F64, ap};
+  LNV_TRY(multiply_launch(1.0, S, &Pm, 0, 0.0, &APT, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(transpose_launch(&APT, ev.perm_SL, ap, s));
+  LNV_TRY(multiply_launch(1.0, M, &AP, 0, 0.0, &XP, 1, nullptr, nullptr, nullptr, nullptr, s));
+  const lnv_bsm* B = &XP;
+  if (!m_is_s) {
+    if (!XPT || !SLcur) return LNV_EINVAL;
+    LNV_TRY(transpose_launch(&XP, ev.perm_X, static_cast<double*>(XPT->val), s));
+    B = XPT;
+  }
+  const Ix lx = make_ix(pl);
+  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, make_ix(XP.pat),
+                                 0, static_cast<const double*>(XP.val), partials, nullptr);
+  LNV_LAUNCH_CHECK();
+  lnv_bsm Q{pl, 4, LNV_F64, ev.YT};
+  LNV_TRY(multiply_launch(1.0, &APT, B, 0, 0.0, &Q, 1, nullptr, nullptr, nullptr, nullptr, s));
+  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col,
+                                 static_cast<const double*>(L->val), lx, 1,
+                                 static_cast<const double*>(ev.YT), partials + 1 * slot, nullptr);
+  LNV_LAUNCH_CHECK();
+  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, lx, 1,
+                                 static_cast<const double*>(ev.YT), partials + 2 * slot, nullptr);
+  LNV_LAUNCH_CHECK();
+  if (m_is_s) return LNV_OK;
+  lnv_bsm R{pl, 4, LNV_F64, ev.W};
+  LNV_TRY(multiply_launch(1.0, SLcur, B, 0, 0.0, &R, 1, nullptr, nullptr, nullptr, nullptr, s));
+  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, P, lx, 1,
+                                 static_cast<const double*>(ev.W), partials + 3 * slot, nullptr);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+// Reductions T0..T3 of cubic_traces_batch (T3 from T1's partials when M = S).
+RedList batch_trace_reds(int ni, int64_t slot, bool m_is_s) {
+  RedList rl = reds();
+  add(rl, 0, ni, 1, LNV_SC_T0, 0, RK_ITEMS);
+  add(rl, 1 * slot, ni, 1, LNV_SC_T1, 0, RK_ITEMS);
+  add(rl, 2 * slot, ni, 1, LNV_SC_T2, 0, RK_ITEMS);
+  add(rl, (m_is_s ? 1 : 3) * slot, ni, 1, LNV_SC_T3, 0, RK_ITEMS);
+  return rl;
+}
+
+int check_batch_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_batch* b, lnv_cg_ws* ws) {
+  if (!bsm_ok(L) || !bsm_ok(S) || !ws) return LNV_EINVAL;
+  if (L->blk != 4 || S->blk != 4) return LNV_EUNSUPPORTED;
+  LNV_TRY(check_batch(b, L->pat));
+  const lnv_eval_ws& ev = ws->ev;
+  if (!ev.partials || !ws->D || !ws->D_prev || !ws->gc_prev || !ws->SL2 || !ev.YT || !ev.W)
+    return LNV_EINVAL;
+  if (!bsm_ok(&ev.SL) || !bsm_ok(&ev.LS) || !bsm_ok(&ev.X) || !bsm_ok(&ev.Z) || !ev.perm_SL)
+    return LNV_EINVAL;
+  if (!pattern_ready(L->pat, true, false, true) || !pattern_ready(ev.SL.pat, false, false, true) ||
+      !pattern_ready(ev.LS.pat, true, false, false) || !pattern_ready(ev.Z.pat, true, false, true) ||
+      !pattern_ready(S->pat, true, false, false))
+    return LNV_EPATTERN;
+  if (ev.partials_len < lnv_partials_len(partial_items(L->pat))) return LNV_EINVAL;
+  return LNV_OK;
+}
+
+}  // namespace
+
+extern "C" int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_batch* b,
+                                 lnv_cg_ws* ws, hipStream_t s) {
+  LNV_TRY(check_batch_cg(L, S, b, ws));
+  const lnv_eval_ws& ev = ws->ev;
+  ws->ev.carry = 0;
+  const lnv_pattern* pl = L->pat;
+  const int64_t nv = pl->nnzb * 16;
+  const int ni = pl->n_items;
+  const int64_t slot = slot_len(partial_items(pl));
+  const Seg sg = make_seg(b);
+  double* part = ev.partials;
+  double* sc = b->scalars;
+  LNV_HIP(hipMemsetAsync(sc, 0, sizeof(double) * LNV_NSCALARS * (size_t)b->n_cells, s));
+  LNV_HIP(hipMemsetAsync(ws->gc_prev, 0, sizeof(double) * nv, s));
+  LNV_HIP(hipMemsetAsync(ws->D_prev, 0, sizeof(double) * nv, s));
+  LNV_HIP(hipMemsetAsync(L->val, 0, sizeof(double) * nv, s));
+  k_identity<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, make_ix(S->pat),
+                                static_cast<const double*>(S->val), nullptr, 0, ws->D);
+  LNV_LAUNCH_CHECK();
+  // per cell: N(lambda I) = 6 Tr[SS] lambda^2 - 4 Tr[SSS] lambda^3 at L = 0
+  lnv_bsm ZD{ev.Z.pat, 4, LNV_F64, ev.Z.val};
+  LNV_TRY(cubic_traces_batch(L, S, S, true, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val),
+                             nullptr, ZD, nullptr, part, slot, s));
+  StageArgs sa{};
+  LNV_TRY(scalar_stage(part, batch_trace_reds(ni, slot, true), sc, ST_INIT, sa, s, sg));
+  k_vec_axpy<<<seg_grid(sg), 256, 0, s>>>(nv, ws->D, sc, LNV_SC_LAMBDA, nullptr,
+                                          static_cast<double*>(L->val), sg);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
+                                 const lnv_batch* b, int64_t k, const lnv_opts* opts,
+                                 lnv_cg_ws* ws, hipStream_t s) {
+  if (!opts || opts->reset_period <= 0 || k < 0) return LNV_EINVAL;
+  if (opts->eval32) return LNV_EUNSUPPORTED;
+  LNV_TRY(check_batch_cg(L, S, b, ws));
+  LNV_TRY(check_cg(L, S, H, nullptr, ws));
+  const lnv_eval_ws& ev = ws->ev;
+  const lnv_pattern* pl = L->pat;
+  const lnv_pattern* ph = H->pat;
+  const int64_t nv = pl->nnzb * 16;
+  const int ni = pl->n_items;
+  const int64_t slot = slot_len(partial_items(pl));
+  const Seg sg = make_seg(b);
+  const int vg = seg_grid(sg);
+  double* part = ev.partials;
+  double* sc = b->scalars;
+  double* Lv = static_cast<double*>(L->val);
+  StageArgs sa{};
+  sa.n_tol = opts->n_tol;
+  sa.step_cap = opts->step_cap;
+  sa.reset = (k % opts->reset_period) == 0;
+  sa.k = (int)k;
+  sa.reset_period = opts->reset_period;
+  ws->ev.carry = 0;   // S.L and S.L.S are formed afresh every step here
+  // 1. per cell E, N, G, F and mu = <G,F>/<F,F> (identity metric)
+  LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s, nullptr, false, sc, sg));
+  // 2-3. g = G - mu F, PR+ beta per cell
+  k_vec_g<<<vg, 256, 0, s>>>(nv, ws->G, ws->F, ws->G, ws->F, ws->gc_prev, sc, ws->g, nullptr,
+                             part, sg);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0, vg, 1, LNV_SC_GG, 0, RK_VEC);
+    add(rl, kVecGrid, vg, 1, LNV_SC_GGP, 0, RK_VEC);
+    add(rl, 2 * kVecGrid, vg, 1, LNV_SC_GGN, 0, RK_VEC);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_BETA, sa, s, sg));
+  }
+  // 4. D = -g + beta D_prev, projected on <D, F> = 0
+  k_vec_dir<<<vg, 256, 0, s>>>(nv, ws->g, ws->D_prev, ws->F, sc, ws->D, part, sg);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0, vg, 1, LNV_SC_DF, 0, RK_VEC);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_PROJ, sa, s, sg));
+  }
+  k_vec_proj<<<vg, 256, 0, s>>>(nv, ws->F, ws->g, sc, ws->D, part, sg);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0, vg, 1, LNV_SC_C1, 0, RK_VEC);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_NONE, sa, s, sg));
+  }
+  // 5. exact cubic line minimisation of E - mu N along D, per cell
+  k_hprime<<<ph->n_items, 256, 0, s>>>(ph->n, ph->items, ph->row_ptr, ph->col,
+                                       static_cast<const double*>(H->val), make_ix(S->pat),
+                                       static_cast<const double*>(S->val), sc, ws->Hp, sg);
+  LNV_LAUNCH_CHECK();
+  lnv_bsm Hp{ph, 4, LNV_F64, ws->Hp};
+  lnv_bsm XD{ev.X.pat, 4, LNV_F64, ev.X.val};
+  lnv_bsm XDT{ev.XT.pat, 4, LNV_F64, ev.XT.val};
+  LNV_TRY(cubic_traces_batch(L, S, &Hp, false, ws->D, ev, ws->SL2,
+                             static_cast<double*>(ev.LS.val), &ev.SL, XD, &XDT, part, slot, s));
+  LNV_TRY(scalar_stage(part, batch_trace_reds(ni, slot, false), sc, ST_ALPHA, sa, s, sg));
+  k_vec_axpy<<<vg, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv, sg);
+  LNV_LAUNCH_CHECK();
+  // 6. electron number at the new L; the cubic correction along F per cell
+  // (cells within tolerance keep delta = 0)
+  lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
+  lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
+  lnv_bsm Vu{ev.Lu.pat, 4, LNV_F64, ev.Vu};
+  LNV_TRY(multiply_launch(1.0, S, L, 0, 0.0, &SL2, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(transpose_launch(&SL2, ev.perm_SL, static_cast<double*>(ev.LS.val), s));
+  LNV_TRY(sym_product(S, &ev.LS, &ev.Z, &ev.Zu, s));
+  LNV_TRY(sym_product(&SL2, &ev.Z, &Vm, &Vu, s));
+  k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, make_ix(ev.Z.pat),
+                                 static_cast<const double*>(ev.Z.val), ev.V, ws->F, part);
+  LNV_LAUNCH_CHECK();
+  {
+    RedList rl = reds();
+    add(rl, 0 * (int64_t)ni, ni, 1, LNV_SC_T0, 0, RK_ITEMS);
+    add(rl, 1 * (int64_t)ni, ni, 1, LNV_SC_T1, 0, RK_ITEMS);
+    add(rl, 2 * (int64_t)ni, ni, 1, LNV_SC_T2, 0, RK_ITEMS);
+    add(rl, 3 * (int64_t)ni, ni, 1, LNV_SC_LL, 0, RK_ITEMS);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_NCHK, sa, s, sg));
+  }
+  lnv_bsm ZF{ev.Z.pat, 4, LNV_F64, ev.X.val};
+  LNV_TRY(cubic_traces_batch(L, S, S, true, ws->F, ev, static_cast<double*>(ev.SL.val),
+                             static_cast<double*>(ev.LS.val), nullptr, ZF, nullptr, part, slot,
+                             s));
+  LNV_TRY(scalar_stage(part, batch_trace_reds(ni, slot, true), sc, ST_DELTA, sa, s, sg));
+  k_vec_axpy<<<vg, 256, 0, s>>>(nv, ws->F, sc, LNV_SC_DELTA, nullptr, Lv, sg);
+  LNV_LAUNCH_CHECK();
+  std::swap(ws->g, ws->gc_prev);
+  std::swap(ws->D, ws->D_prev);
   return LNV_OK;
 }
 

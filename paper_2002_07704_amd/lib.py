@@ -94,6 +94,11 @@ class LnvVbsm(ctypes.Structure):
                 ("val_off", c_void_p), ("nnz", c_int64), ("dtype", c_int32), ("val", c_void_p)]
 
 
+class LnvBatch(ctypes.Structure):
+    _fields_ = [("n_cells", c_int32), ("item_ptr", c_void_p), ("val_ptr", c_void_p),
+                ("row_cell", c_void_p), ("n_elec", c_void_p), ("scalars", c_void_p)]
+
+
 PPat = POINTER(LnvPattern)
 PBsm = POINTER(LnvBsm)
 PAtoms = POINTER(LnvAtoms)
@@ -160,6 +165,9 @@ SIGNATURES = {
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
                             POINTER(LnvCgWs), c_void_p]),
+    "lnv_cg_init_batch": (c_int, [PBsm, PBsm, POINTER(LnvBatch), POINTER(LnvCgWs), c_void_p]),
+    "lnv_cg_step_batch": (c_int, [PBsm, PBsm, PBsm, POINTER(LnvBatch), c_int64, POINTER(LnvOpts),
+                                  POINTER(LnvCgWs), c_void_p]),
     "lnv_bsm_lincomb": (c_int, [c_double, PBsm, c_double, PBsm, c_double, PBsm, PBsm, c_void_p]),
     "lnv_bsm_norm_inf": (c_int, [PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_bsm_remap": (c_int, [PBsm, PBsm, c_void_p]),

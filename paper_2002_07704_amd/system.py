@@ -1097,10 +1097,39 @@ class LNVSystem:
         if self.lean:
             raise RuntimeError("a lean system is evaluated, not minimised (no CG buffers)")
 
+    def batch(self):
+        """The lnv_batch descriptor of a batch of cells (built once): L's work
+        items and values per cell, the cell of each row, each cell's electron
+        count and its scalar block (cell_scalars)."""
+        if self.cells is None:
+            raise ValueError("not a batch of cells")
+        if getattr(self, "_batch", None) is None:
+            rp = self.pL.row_ptr.cpu().numpy().astype(np.int64)
+            self._val_ptr = torch.as_tensor(16 * rp[self.cell_rows], device=self.dev)
+            self._n_elec_cells = torch.as_tensor(
+                np.array([c.n_elec for c in self.cells], dtype=np.float64), device=self.dev)
+            self.cell_scalars = torch.zeros(len(self.cells), L_.NSCALARS, dtype=torch.float64,
+                                            device=self.dev)
+            b = L_.LnvBatch()
+            b.n_cells = len(self.cells)
+            b.item_ptr = self.cell_item_ptr().data_ptr()
+            b.val_ptr = self._val_ptr.data_ptr()
+            b.row_cell = self.cell_of.data_ptr()
+            b.n_elec = self._n_elec_cells.data_ptr()
+            b.scalars = self.cell_scalars.data_ptr()
+            self._batch = b
+        return self._batch
+
     def cg_init(self):
+        """L0 = lambda T (lnv_cg_init); for a batch of cells lambda_c I per cell
+        (lnv_cg_init_batch)."""
         self._need_cg()
-        L_.call("lnv_cg_init", byref(self.L.struct), byref(self.S.struct), self._T(),
-                self.n_elec, byref(self.ws), _stream())
+        if self.cells is not None:
+            L_.call("lnv_cg_init_batch", byref(self.L.struct), byref(self.S.struct),
+                    byref(self.batch()), byref(self.ws), _stream())
+        else:
+            L_.call("lnv_cg_init", byref(self.L.struct), byref(self.S.struct), self._T(),
+                    self.n_elec, byref(self.ws), _stream())
         self.k = 0
 
     def cg_restart(self):
@@ -1134,10 +1163,17 @@ class LNVSystem:
 
     def cg_step(self):
         self._need_cg()
-        if self.cells is not None:
-            raise NotImplementedError("a batch of cells is evaluated, not minimised, as one system")
         o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap, None,
                        int(self.opts.occ_every), int(self.opts.occ_iter))
+        if self.cells is not None:
+            # every cell minimised at once, its own scalars (identity metric, FP64)
+            if self.opts.mixed:
+                raise NotImplementedError("a batch of cells is minimised in FP64")
+            L_.call("lnv_cg_step_batch", byref(self.L.struct), byref(self.S.struct),
+                    byref(self.H.struct), byref(self.batch()), self.k, byref(o), byref(self.ws),
+                    _stream())
+            self.k += 1
+            return
         if self.opts.mixed:
             self.mixed_setup()
             o.eval32 = ctypes.addressof(self.ws32)
@@ -1151,6 +1187,11 @@ class LNVSystem:
     def scalars_host(self):
         v = self.scalars.cpu().numpy()
         return {k: float(v[i]) for k, i in L_.SC.items()}
+
+    def cell_scalars_host(self):
+        """Per-cell scalar blocks of a batch minimisation (list of dicts)."""
+        v = self.cell_scalars.cpu().numpy()
+        return [{k: float(r[i]) for k, i in L_.SC.items()} for r in v]
 
     def buffer(self, ptr):
         return self._bufs[ptr]

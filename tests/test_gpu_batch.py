@@ -112,3 +112,65 @@ def test_batch_of_32_cells(gpu):
               f"{Er / cw.n:.13f}", flush=True)
         assert abs(EN[c, 0] - Er) / cw.n <= 1e-10
         assert abs(EN[c, 1] - Nr) / cw.n <= 1e-10
+
+
+def _batch_cg_against_oracle(cells, steps):
+    """Minimise a batch of cells together (lnv_cg_init_batch, lnv_cg_step_batch)
+    and compare every cell's lambda and every iteration's E, N, mu, beta,
+    alpha and delta with the oracle's CG of that cell alone (identity
+    metric, L0 = lambda I); then each cell's final L."""
+    from paper_2002_07704_amd.system import LNVSystem
+    sysg = LNVSystem(cells, metric=None)
+    sysg.cg_init()
+    refs, hists, Lfin = [], [], []
+    for cw in cells:
+        ref = ost.System(cw)
+        _, lam = olnv.initial_L(ref.S, ref.maskL, cw.n_elec)
+        Lo, hist = olnv.cg(ref.S, ref.H, ref.maskL, cw.n_elec, steps)
+        refs.append((ref, lam))
+        hists.append(hist)
+        Lfin.append(Lo)
+    sc0 = sysg.cell_scalars_host()
+    for c, cw in enumerate(cells):
+        lam = refs[c][1]
+        assert abs(sc0[c]["LAMBDA"] - lam) <= 1e-11 * lam, c
+    for k in range(steps):
+        sysg.cg_step()
+        scs = sysg.cell_scalars_host()
+        for c, cw in enumerate(cells):
+            sc, h = scs[c], hists[c][k]
+            print(f"k={k} cell {c} ({cw.n} atoms) E/atom gpu {sc['E'] / cw.n:.13f} oracle "
+                  f"{h['E'] / cw.n:.13f} alpha {sc['ALPHA']:.6e} delta {sc['DELTA']:.3e} "
+                  f"status {int(sc['STATUS'])}", flush=True)
+            assert abs(sc["E"] - h["E"]) / cw.n <= 1e-10, (k, c)
+            assert abs(sc["N"] - h["N"]) <= 1e-9 * max(1.0, cw.n_elec / 64), (k, c)
+            assert abs(sc["MU"] - h["mu"]) <= 1e-9 * max(1.0, abs(h["mu"])), (k, c)
+            assert abs(sc["BETA"] - h["beta"]) <= 1e-7, (k, c)
+            assert abs(sc["ALPHA"] - h["alpha"]) <= 1e-8 * abs(h["alpha"]), (k, c)
+            assert abs(sc["DELTA"] - h["delta"]) <= 1e-8 * max(abs(h["delta"]), 1e-6), (k, c)
+            # only the capped-correction bit may be set (the oracle skips the
+            # same corrections: delta 0 on both sides)
+            assert int(sc["STATUS"]) & ~8 == 0, (k, c)
+    for c, cw in enumerate(cells):
+        Lg = _cell_dense(sysg, sysg.L.val, sysg.pL, c, cw)
+        assert np.abs(Lg - Lfin[c]).max() <= 1e-9, c
+    return sysg
+
+
+def test_batch_cg_diamond_cells(gpu):
+    """Four diamond cells of 64, 16, 32 and 24 atoms minimised as one batch,
+    12 iterations: two cells keep N exact by the cubic correction every step,
+    in the other two the correction exceeds its cap and is skipped, so the
+    cells take different decisions in the same launches."""
+    cells = [W.diamond_workload("d64", (2, 2, 2), seed=1),
+             W.diamond_workload("d16", (2, 1, 1), seed=21),
+             W.diamond_workload("d32", (1, 2, 2), seed=22),
+             W.diamond_workload("d24", (3, 1, 1), seed=23)]
+    _batch_cg_against_oracle(cells, 12)
+
+
+def test_batch_cg_uneven_cells(gpu):
+    """The six amorphous Si/O/H cells of 16-48 atoms (13/9/4 support
+    functions, atoms split over 4x4-blocked rows), 6 iterations."""
+    cells = W.batch_cells("b6", 6, seed=9, n_lo=16, n_hi=48)
+    _batch_cg_against_oracle(cells, 6)
