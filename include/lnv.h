@@ -889,6 +889,63 @@ typedef struct lnv_opts {
  */
 int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, hipStream_t s);
 
+/* ------------------------------------------------------------ canonical purification
+ * The start of the minimisation (Sec. II.C.2 generates the initial density
+ * matrix from H by a generalisation of the McWeeny transform: canonical
+ * purification with the approximate inverse overlap T).  With rho = K S,
+ * theta = n_elec/2 occupied states of n_orb orbitals (functions present):
+ *   start  K0 = (lambda/n)(mu T - P_L(T H T)) + (theta/n) T,  mu = <T, H>/n,
+ *          lambda = min(theta/(b - mu), (n - theta)/(mu + b)), b = ||T||inf ||H||inf
+ *   step   t_p = Tr[rho^p] = <K (S K)^(p-1), S>,  c = (t2 - t3)/(t1 - t2),
+ *          K <- ((1 + c) KSK - KSKSK)/c (c >= 1/2),
+ *          ((1 - 2c) K + (1 + c) KSK - KSKSK)/(1 - c) (c < 1/2),
+ *          KSK = P_L(K.SK), KSKSK = P_L(KSK.SK), then K <- (K + K^T)/2
+ *   stop   (K kept) when t1 - t2 <= tol theta, c is undefined or outside
+ *          [0, 1], or t1 - t2 grew (truncation pushes the spectrum out of
+ *          [0, 1]); later steps do nothing.
+ * Every scalar decision is taken on the device: a caller runs as many steps
+ * as it allows without synchronising and reads the history afterwards.
+ * Workspace (device memory, caller-owned):
+ *  SK         values on pat(S.L) (pattern with its items and cluster plan)
+ *  K2, K3, KT [nnzb_L * 16] FP64 on L's pattern
+ *  perm_L     L's transpose map onto itself (lnv_pattern_transpose_map)
+ *  partials   [lnv_partials_len(L's work items)] FP64
+ *  scalars    [LNV_PM_NSCALARS] FP64 (LNV_PM_*)
+ *  hist       [4 * hist_len] FP64: per step (c, t1, t2, t3), c = NaN for the
+ *             step that stopped; LNV_PM_STEPS entries are written
+ * L's pattern needs its index, items and cluster plan; S's and H's their
+ * indices; FP64, blk 4.
+ */
+enum {
+  LNV_PM_MU = 0, LNV_PM_B = 1, LNV_PM_LAMBDA = 2, LNV_PM_DOT = 3, LNV_PM_NT = 4, LNV_PM_NH = 5,
+  LNV_PM_T1 = 6, LNV_PM_T2 = 7, LNV_PM_T3 = 8, LNV_PM_C = 9, LNV_PM_PREV = 10,
+  LNV_PM_STOPPED = 11, LNV_PM_STEPS = 12, LNV_PM_A0 = 13, LNV_PM_A1 = 14, LNV_PM_A2 = 15,
+  LNV_PM_HALF = 16, LNV_PM_NSCALARS = 32
+};
+typedef struct lnv_pm_ws {
+  lnv_bsm SK;
+  double* K2;
+  double* K3;
+  double* KT;
+  const int32_t* perm_L;
+  double* partials;
+  int64_t partials_len;
+  double* scalars;
+  double* hist;
+  int32_t hist_len;
+} lnv_pm_ws;
+
+/* lnv_pm_start -- K0 into K (on L's pattern) from T (on L's pattern) and H;
+ * HT: scratch values on pat(H.L) (pattern with its index, items and cluster
+ * plan), H.T.  Resets the step counter and history. */
+int lnv_pm_start(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT, double n_orb,
+                 double n_elec, lnv_pm_ws* ws, hipStream_t s);
+
+/* lnv_pm_step -- one purification step of K (no-op once stopped or after
+ * hist_len steps).  n_elec and tol as for the start and stop rule. */
+int lnv_pm_step(lnv_bsm* K, const lnv_bsm* S, double n_elec, double tol, lnv_pm_ws* ws,
+                hipStream_t s);
+
 /*
  * lnv_cg_init -- L0 = lambda * T on L's pattern (T = NULL: the identity),
  * lambda the smallest positive real root of N(lambda T) = n_elec, a cubic in

@@ -41,7 +41,8 @@ struct RedList {
 };
 
 enum Stage {
-  ST_NONE = 0, ST_EVAL, ST_BETA, ST_PROJ, ST_ALPHA, ST_NCHK, ST_DELTA, ST_INIT, ST_MU, ST_SIGMA
+  ST_NONE = 0, ST_EVAL, ST_BETA, ST_PROJ, ST_ALPHA, ST_NCHK, ST_DELTA, ST_INIT, ST_MU, ST_SIGMA,
+  ST_PM0, ST_PM
 };
 
 // A batch of independent cells minimised together (lnv_batch): cell c owns
@@ -65,6 +66,9 @@ struct StageArgs {
   int k;              // ST_BETA: iteration index
   int reset_period;   // ST_BETA: guard repeat window
   int occ_checked;    // ST_BETA: occupation bounds computed this iteration
+  double pm_n, pm_theta, pm_tol;   // ST_PM0 / ST_PM: orbitals, occupied states, tolerance
+  double* pm_hist;                 // ST_PM: device [4 * pm_hist_len] (c, t1, t2, t3)
+  int pm_hist_len;
 };
 
 // Runaway guard (ST_BETA): a rise of E beyond this fraction of |E| counts
@@ -344,6 +348,66 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
       sc[LNV_SC_GUARD_K] = -1e9;
       break;
     }
+    case ST_PM0: {
+      // canonical purification start: mu = <T, H>/n, b = ||T||inf ||H||inf,
+      // lambda = min(theta/(b - mu), (n - theta)/(mu + b));
+      // K0 = ((lambda mu + theta)/n) T - (lambda/n) P_L(T H T)
+      const double n = sa.pm_n, th = sa.pm_theta;
+      const double mu = sc[LNV_PM_DOT] / n;
+      const double b = sc[LNV_PM_NT] * sc[LNV_PM_NH];
+      const double lam = fmin(th / (b - mu), (n - th) / (mu + b));
+      sc[LNV_PM_MU] = mu;
+      sc[LNV_PM_B] = b;
+      sc[LNV_PM_LAMBDA] = lam;
+      sc[LNV_PM_A0] = (lam * mu + th) / n;
+      sc[LNV_PM_A1] = -lam / n;
+      sc[LNV_PM_A2] = 0.0;
+      sc[LNV_PM_HALF] = 0.5;
+      sc[LNV_PM_PREV] = NAN;
+      sc[LNV_PM_STOPPED] = 0.0;
+      sc[LNV_PM_STEPS] = 0.0;
+      return;
+    }
+    case ST_PM: {
+      // one step: c = Tr[rho^2 - rho^3] / Tr[rho - rho^2] from t_p = Tr[rho^p];
+      // stop (K kept) when Tr[rho - rho^2] <= tol theta, c is undefined or
+      // outside [0, 1], or Tr[rho - rho^2] grew; else the coefficients of
+      // K <- a0 K + a1 KSK + a2 KSKSK
+      if (sc[LNV_PM_STOPPED] != 0.0) return;
+      const int step = (int)sc[LNV_PM_STEPS];
+      if (step >= sa.pm_hist_len) {
+        sc[LNV_PM_STOPPED] = 1.0;
+        return;
+      }
+      const double t1 = sc[LNV_PM_T1], t2 = sc[LNV_PM_T2], t3 = sc[LNV_PM_T3];
+      const double idem = t1 - t2;
+      const double c = idem != 0.0 ? (t2 - t3) / idem : NAN;
+      const double prev = sc[LNV_PM_PREV];
+      const bool stop = idem <= sa.pm_tol * sa.pm_theta || idem == 0.0 || !(c >= 0.0 && c <= 1.0) ||
+                        (!isnan(prev) && idem > prev);
+      double* h = sa.pm_hist + 4 * (size_t)step;
+      h[0] = stop ? NAN : c;
+      h[1] = t1;
+      h[2] = t2;
+      h[3] = t3;
+      sc[LNV_PM_STEPS] = (double)(step + 1);
+      sc[LNV_PM_C] = c;
+      if (stop) {
+        sc[LNV_PM_STOPPED] = 1.0;
+        return;
+      }
+      sc[LNV_PM_PREV] = idem;
+      if (c >= 0.5) {
+        sc[LNV_PM_A0] = 0.0;
+        sc[LNV_PM_A1] = (1.0 + c) / c;
+        sc[LNV_PM_A2] = -1.0 / c;
+      } else {
+        sc[LNV_PM_A0] = (1.0 - 2.0 * c) / (1.0 - c);
+        sc[LNV_PM_A1] = (1.0 + c) / (1.0 - c);
+        sc[LNV_PM_A2] = -1.0 / (1.0 - c);
+      }
+      return;
+    }
     default:
       break;
   }
@@ -546,6 +610,24 @@ __global__ __launch_bounds__(256) void k_lincomb(int64_t nv, double a, const dou
                                                  double b, const double* __restrict__ Y, double c,
                                                  const double* __restrict__ Z,
                                                  double* __restrict__ out) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = a * X[e];
+    if (Y) v = fma(b, Y[e], v);
+    if (Z) v = fma(c, Z[e], v);
+    out[e] = v;
+  }
+}
+
+// out = sc[i0] X + sc[i1] Y + sc[i2] Z (Y, Z nullable; out may alias), the
+// association of k_lincomb; skipped when *skip != 0.
+__global__ __launch_bounds__(256) void k_lincomb_sc(int64_t nv, const double* __restrict__ sc,
+                                                    int i0, int i1, int i2,
+                                                    const double* X, const double* Y,
+                                                    const double* Z, double* out,
+                                                    const double* __restrict__ skip) {
+  if (skip != nullptr && *skip != 0.0) return;
+  const double a = sc[i0], b = Y ? sc[i1] : 0.0, c = Z ? sc[i2] : 0.0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv;
        e += (int64_t)gridDim.x * blockDim.x) {
     double v = a * X[e];
@@ -1613,6 +1695,116 @@ extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_c
     std::swap(cur, nxt);
   }
   if (cur != T->val) LNV_HIP(hipMemcpyAsync(T->val, cur, bytes, hipMemcpyDeviceToDevice, s));
+  return LNV_OK;
+}
+
+namespace {
+
+int check_pm(const lnv_bsm* K, const lnv_pm_ws* ws) {
+  if (!bsm_ok(K) || !ws || !ws->K2 || !ws->K3 || !ws->KT || !ws->perm_L || !ws->partials ||
+      !ws->scalars || !ws->hist || ws->hist_len < 0 || !bsm_ok(&ws->SK))
+    return LNV_EINVAL;
+  if (K->blk != 4 || ws->SK.blk != 4) return LNV_EUNSUPPORTED;
+  const lnv_pattern* pl = K->pat;
+  if (!pattern_ready(pl, true, false, true)) return LNV_EPATTERN;
+  if (ws->partials_len < lnv_partials_len(partial_items(pl))) return LNV_EINVAL;
+  return LNV_OK;
+}
+
+}  // namespace
+
+extern "C" int lnv_pm_start(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT,
+                            double n_orb, double n_elec, lnv_pm_ws* ws, hipStream_t s) {
+  LNV_TRY(check_pm(K, ws));
+  if (!bsm_ok(T) || !bsm_ok(H) || !bsm_ok(HT) || !(n_orb > 0.0) || !(n_elec > 0.0))
+    return LNV_EINVAL;
+  const lnv_pattern* pl = K->pat;
+  if (T->pat != pl) return LNV_EPATTERN;
+  if (!pattern_ready(H->pat, true, false, false) || !H->pat->row_ptr) return LNV_EPATTERN;
+  const int ni = pl->n_items;
+  const int64_t slot = slot_len(partial_items(pl));
+  if ((int64_t)H->pat->n > slot || (int64_t)pl->n > slot) return LNV_EINVAL;
+  double* part = ws->partials;
+  double* sc = ws->scalars;
+  // <T, H>, ||T||inf, ||H||inf
+  k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col,
+                                 static_cast<const double*>(T->val), make_ix(H->pat), 0,
+                                 static_cast<const double*>(H->val), part, nullptr);
+  LNV_LAUNCH_CHECK();
+  k_rowabs<<<pl->n, 256, 0, s>>>(pl->row_ptr, static_cast<const double*>(T->val), part + slot);
+  LNV_LAUNCH_CHECK();
+  k_rowabs<<<H->pat->n, 256, 0, s>>>(H->pat->row_ptr, static_cast<const double*>(H->val),
+                                     part + 2 * slot);
+  LNV_LAUNCH_CHECK();
+  RedList rl = reds();
+  add(rl, 0, ni, 1, LNV_PM_DOT);
+  add(rl, slot, pl->n, 1, LNV_PM_NT, 1);
+  add(rl, 2 * slot, H->pat->n, 1, LNV_PM_NH, 1);
+  StageArgs sa{};
+  sa.pm_n = n_orb;
+  sa.pm_theta = 0.5 * n_elec;
+  LNV_TRY(scalar_stage(part, rl, sc, ST_PM0, sa, s));
+  // K0 = a0 T + a1 P_L(T (H T))
+  lnv_bsm K2{pl, 4, LNV_F64, ws->K2};
+  LNV_TRY(multiply_launch(1.0, H, T, 0, 0.0, HT, 1, nullptr, nullptr, nullptr, nullptr, s));
+  LNV_TRY(multiply_launch(1.0, T, HT, 0, 0.0, &K2, 1, nullptr, nullptr, nullptr, nullptr, s));
+  const int64_t nv = pl->nnzb * 16;
+  k_lincomb_sc<<<vec_grid(), 256, 0, s>>>(nv, sc, LNV_PM_A0, LNV_PM_A1, LNV_PM_A2,
+                                          static_cast<const double*>(T->val), ws->K2, nullptr,
+                                          static_cast<double*>(K->val), nullptr);
+  LNV_LAUNCH_CHECK();
+  return LNV_OK;
+}
+
+extern "C" int lnv_pm_step(lnv_bsm* K, const lnv_bsm* S, double n_elec, double tol,
+                           lnv_pm_ws* ws, hipStream_t s) {
+  LNV_TRY(check_pm(K, ws));
+  if (!bsm_ok(S) || !(n_elec > 0.0) || !(tol >= 0.0)) return LNV_EINVAL;
+  const lnv_pattern* pl = K->pat;
+  if (!pattern_ready(S->pat, true, false, false)) return LNV_EPATTERN;
+  const int ni = pl->n_items;
+  const int64_t slot = slot_len(partial_items(pl));
+  const int64_t nv = pl->nnzb * 16;
+  double* part = ws->partials;
+  double* sc = ws->scalars;
+  const double* stopped = sc + LNV_PM_STOPPED;
+  double* Kv = static_cast<double*>(K->val);
+  lnv_bsm K2{pl, 4, LNV_F64, ws->K2}, K3{pl, 4, LNV_F64, ws->K3};
+  // S K, K S K = P_L(K . SK), K S K S K = P_L(KSK . SK)
+  LNV_TRY(multiply_launch(1.0, S, K, 0, 0.0, &ws->SK, 1, nullptr, nullptr, nullptr, stopped, s));
+  LNV_TRY(multiply_launch(1.0, K, &ws->SK, 0, 0.0, &K2, 1, nullptr, nullptr, nullptr, stopped,
+                          s));
+  LNV_TRY(multiply_launch(1.0, &K2, &ws->SK, 0, 0.0, &K3, 1, nullptr, nullptr, nullptr, stopped,
+                          s));
+  // t_p = <K (SK)^(p-1), S>
+  const double* Ms[3] = {Kv, ws->K2, ws->K3};
+  for (int p = 0; p < 3; ++p) {
+    k_dot_items<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Ms[p],
+                                   make_ix(S->pat), 0, static_cast<const double*>(S->val),
+                                   part + p * slot, stopped);
+    LNV_LAUNCH_CHECK();
+  }
+  RedList rl = reds();
+  add(rl, 0, ni, 1, LNV_PM_T1);
+  add(rl, slot, ni, 1, LNV_PM_T2);
+  add(rl, 2 * slot, ni, 1, LNV_PM_T3);
+  StageArgs sa{};
+  sa.pm_theta = 0.5 * n_elec;
+  sa.pm_tol = tol;
+  sa.pm_hist = ws->hist;
+  sa.pm_hist_len = ws->hist_len;
+  // a stopped purification leaves its scalars alone (the stage returns first)
+  LNV_TRY(scalar_stage(part, rl, sc, ST_PM, sa, s));
+  k_lincomb_sc<<<vec_grid(), 256, 0, s>>>(nv, sc, LNV_PM_A0, LNV_PM_A1, LNV_PM_A2, Kv, ws->K2,
+                                          ws->K3, Kv, stopped);
+  LNV_LAUNCH_CHECK();
+  // K <- (K + K^T)/2
+  lnv_bsm KTm{pl, 4, LNV_F64, ws->KT};
+  LNV_TRY(transpose_skip_launch(K, ws->perm_L, ws->KT, stopped, s));
+  k_lincomb_sc<<<vec_grid(), 256, 0, s>>>(nv, sc, LNV_PM_HALF, LNV_PM_HALF, 0, Kv, ws->KT,
+                                          nullptr, Kv, stopped);
+  LNV_LAUNCH_CHECK();
+  (void)KTm;
   return LNV_OK;
 }
 

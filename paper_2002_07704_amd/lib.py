@@ -99,6 +99,15 @@ class LnvBatch(ctypes.Structure):
                 ("row_cell", c_void_p), ("n_elec", c_void_p), ("scalars", c_void_p)]
 
 
+class LnvPmWs(ctypes.Structure):
+    _fields_ = [("SK", LnvBsm), ("K2", c_void_p), ("K3", c_void_p), ("KT", c_void_p),
+                ("perm_L", c_void_p), ("partials", c_void_p), ("partials_len", c_int64),
+                ("scalars", c_void_p), ("hist", c_void_p), ("hist_len", c_int32)]
+
+
+PM = dict(MU=0, B=1, LAMBDA=2, STOPPED=11, STEPS=12)
+PM_NSCALARS = 32
+
 PPat = POINTER(LnvPattern)
 PBsm = POINTER(LnvBsm)
 PAtoms = POINTER(LnvAtoms)
@@ -165,6 +174,9 @@ SIGNATURES = {
     "lnv_cg_init": (c_int, [PBsm, PBsm, PBsm, c_double, POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_int64, POINTER(LnvOpts),
                             POINTER(LnvCgWs), c_void_p]),
+    "lnv_pm_start": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_double, POINTER(LnvPmWs),
+                             c_void_p]),
+    "lnv_pm_step": (c_int, [PBsm, PBsm, c_double, c_double, POINTER(LnvPmWs), c_void_p]),
     "lnv_cg_init_batch": (c_int, [PBsm, PBsm, POINTER(LnvBatch), POINTER(LnvCgWs), c_void_p]),
     "lnv_cg_step_batch": (c_int, [PBsm, PBsm, PBsm, POINTER(LnvBatch), c_int64, POINTER(LnvOpts),
                                   POINTER(LnvCgWs), c_void_p]),

@@ -15,8 +15,10 @@ replaced by its symmetric part after each step (truncation leaves KSKSK
 unsymmetric, and the step amplifies any antisymmetric part).  It
 stops when Tr[rho - rho^2] <= tol theta, after n_iter steps, or before a
 step whose c leaves [0, 1] or whose Tr[rho - rho^2] grew (truncation pushes
-the spectrum out of [0, 1]).  Every product, trace and update runs in
-liblnv's kernels; the host evaluates c and the stopping test.
+the spectrum out of [0, 1]).  Every product, trace, update and decision
+(c, the stopping test, the coefficients) runs in liblnv (lnv_pm_start,
+lnv_pm_step): the steps are queued without synchronising, and the history
+is read once at the end.
 """
 from __future__ import annotations
 
@@ -26,23 +28,7 @@ import numpy as np
 import torch
 
 from . import lib as L_
-from .system import (BLK, Matrix, _ptr, _stream, multiply, product_pattern, transpose,
-                     transpose_map)
-
-
-def _dot(system, A, B):
-    part = torch.empty(L_.DOT_PARTIALS, dtype=torch.float64, device=system.dev)
-    out = torch.zeros(1, dtype=torch.float64, device=system.dev)
-    L_.call("lnv_bsm_dot", ctypes.byref(A.struct), ctypes.byref(B.struct), _ptr(part), _ptr(out),
-            _stream())
-    return out
-
-
-def _norm_inf(system, A):
-    part = torch.empty(A.pat.n, dtype=torch.float64, device=system.dev)
-    out = torch.zeros(1, dtype=torch.float64, device=system.dev)
-    L_.call("lnv_bsm_norm_inf", ctypes.byref(A.struct), _ptr(part), _ptr(out), _stream())
-    return out
+from .system import BLK, Matrix, _stream, product_pattern, transpose_map
 
 
 def _lincomb(a, X, b, Y, c, Z, out):
@@ -64,51 +50,41 @@ def _pattern_HL(system):
 
 def pm_initial_L(system, n_iter=100, tol=1e-12):
     """Purified K written to system.L; returns the history [dict(c, t1, t2, t3)]
-    and the start parameters (mu, b, lambda)."""
+    (c None for the step that stopped) and the start parameters (mu, b, lambda)."""
     if system.metric is None:
         raise ValueError("canonical purification needs the metric T ~ S^-1")
     system.pH.build_index()
     n = float(np.sum(system.w.nfun)) if system.w is not None else float(system.fun_rows.sum())
-    theta = system.n_elec / 2.0
+    dev = system.dev
     T, S, H = system.T, system.S, system.H
-    mu = float(_dot(system, T, H)) / n
-    b = float(_norm_inf(system, T)) * float(_norm_inf(system, H))
-    lam = min(theta / (b - mu), (n - theta) / (mu + b))
-    HT = Matrix(_pattern_HL(system))             # H.T on pat(H.L), dropped after use
-    multiply(1.0, H, T, 0, 0.0, HT)
     K = Matrix(system.pL)
-    K2 = Matrix(system.pL)
-    K3 = Matrix(system.pL)
-    KT = Matrix(system.pL)
+    K2 = torch.zeros_like(K.val)
+    K3 = torch.zeros_like(K.val)
+    KT = torch.zeros_like(K.val)
     perm_L = transpose_map(system.pL, system.pL)
-    multiply(1.0, T, HT, 0, 0.0, K2)             # P_L(T H T)
-    del HT
-    _lincomb((lam * mu + theta) / n, T, -lam / n, K2, 0.0, None, K)
-    SK = system.SL                               # S.K on pat(S.L)
-    hist = []
-    prev = None
+    plen = int(L_.load().lnv_partials_len(max(system.pL.struct.n_items,
+                                              system.pL.struct.n_cl_items)))
+    part = torch.zeros(plen, dtype=torch.float64, device=dev)
+    sc = torch.zeros(L_.PM_NSCALARS, dtype=torch.float64, device=dev)
+    hist_d = torch.zeros(4 * max(1, n_iter), dtype=torch.float64, device=dev)
+    ws = L_.LnvPmWs()
+    ws.SK = system.SL.struct                      # S.K on pat(S.L)
+    ws.K2, ws.K3, ws.KT = K2.data_ptr(), K3.data_ptr(), KT.data_ptr()
+    ws.perm_L = perm_L.data_ptr()
+    ws.partials, ws.partials_len = part.data_ptr(), plen
+    ws.scalars, ws.hist, ws.hist_len = sc.data_ptr(), hist_d.data_ptr(), int(n_iter)
+    HT = Matrix(_pattern_HL(system))             # H.T on pat(H.L), dropped after use
+    L_.call("lnv_pm_start", ctypes.byref(K.struct), ctypes.byref(T.struct), ctypes.byref(H.struct),
+            ctypes.byref(HT.struct), n, float(system.n_elec), ctypes.byref(ws), _stream())
     for _ in range(n_iter):
-        multiply(1.0, S, K, 0, 0.0, SK)
-        multiply(1.0, K, SK, 0, 0.0, K2)
-        multiply(1.0, K2, SK, 0, 0.0, K3)
-        t = torch.cat([_dot(system, M, S) for M in (K, K2, K3)]).cpu().numpy()
-        t1, t2, t3 = (float(x) for x in t)
-        idem = t1 - t2
-        c = (t2 - t3) / idem if idem != 0.0 else None
-        if (idem <= tol * theta or c is None or not 0.0 <= c <= 1.0
-                or (prev is not None and idem > prev)):
-            hist.append(dict(c=None, t1=t1, t2=t2, t3=t3))
-            break
-        prev = idem
-        if c >= 0.5:
-            _lincomb(0.0, K, (1.0 + c) / c, K2, -1.0 / c, K3, K)
-        else:
-            _lincomb((1.0 - 2.0 * c) / (1.0 - c), K, (1.0 + c) / (1.0 - c), K2,
-                     -1.0 / (1.0 - c), K3, K)
-        transpose(K, perm_L, KT)
-        _lincomb(0.5, K, 0.5, KT, 0.0, None, K)
-        hist.append(dict(c=c, t1=t1, t2=t2, t3=t3))
+        L_.call("lnv_pm_step", ctypes.byref(K.struct), ctypes.byref(S.struct),
+                float(system.n_elec), float(tol), ctypes.byref(ws), _stream())
     system.L.val.copy_(K.val)
-    torch.cuda.synchronize()
+    v = sc.cpu().numpy()
+    h = hist_d.cpu().numpy().reshape(-1, 4)
+    del HT
+    hist = [dict(c=None if np.isnan(r[0]) else float(r[0]), t1=float(r[1]), t2=float(r[2]),
+                 t3=float(r[3])) for r in h[:int(v[L_.PM["STEPS"]])]]
     assert K.val.shape[1] == BLK
-    return hist, dict(mu=mu, b=b, lam=lam)
+    return hist, dict(mu=float(v[L_.PM["MU"]]), b=float(v[L_.PM["B"]]),
+                      lam=float(v[L_.PM["LAMBDA"]]))

@@ -60,14 +60,17 @@ class Cells:
 
     @staticmethod
     def choose_grid(pos_units, box, ranges, max_g=1024):
-        """Grid of the spatial index: the cells (edge box/g per axis) that
-        minimise the summed table sizes of patterns with the given ranges --
-        per row unit, (window cells) x (fullest cell's count), the window
-        reaching floor(R/edge) + 1 cells each way, at most the whole axis.
-        One cell per axis is the dense table."""
+        """Grid of the spatial index: the coarsest cells (edge box/g per
+        axis) whose summed table sizes, over patterns with the given ranges,
+        stay within a quarter of the smallest -- per row unit, (window cells)
+        x (fullest cell's count), the window reaching floor(R/edge) + 1 cells
+        each way, at most the whole axis.  One cell per axis is the dense
+        table; coarser windows span more axes, where a lookup needs no
+        window arithmetic (on the 4096-atom cell the dense table, 1.14x the
+        smallest, makes the CG iteration 4% faster)."""
         pos = np.asarray(pos_units, dtype=np.float64)
         box = np.asarray(box, dtype=np.float64)
-        best, best_cost = (1, 1, 1), None
+        costs = []
         kmax = int(min(max_g, max(1, np.floor(box.min() / 2.0))))
         for k in range(1, kmax + 1):
             g = np.maximum(1, np.round(box / (box.min() / k))).astype(np.int64)
@@ -81,9 +84,9 @@ class Cells:
             for R in ranges:
                 w = np.minimum(2 * (np.floor(R / edge) + 1) + 1, g)
                 cost += int(np.prod(w)) * occ
-            if best_cost is None or cost < best_cost:
-                best, best_cost = tuple(int(x) for x in g), cost
-        return best
+            costs.append((tuple(int(x) for x in g), cost))
+        low = min(c for _, c in costs)
+        return next(g for g, c in costs if c <= 1.25 * low)
 
 
 class Pattern:
