@@ -724,12 +724,13 @@ __global__ __launch_bounds__(256) void k_tile16(
     return true;
   };
 
-  if (nsteps > 0 && MODE == TM_F64 && NB == 2) {
-    // FP64, 4 x 2 tiles: the A fragments single-buffered (loaded after the
-    // products that read them), the B fragments double-buffered -- 32
-    // registers fewer, so three waves fit a SIMD instead of two (measured on
-    // the 32768-atom cell: 4% faster; with 4 x 4 tiles, one wave per SIMD
-    // either way, 7% slower, so that shape keeps both double-buffered)
+  if (nsteps > 0 && ((MODE == TM_F64 && NB == 2) || (MODE == TM_F16X3 && NB == 4))) {
+    // the A fragments single-buffered (loaded after the products that read
+    // them), the B fragments double-buffered: one more wave fits a SIMD --
+    // FP64 4 x 2 tiles three instead of two, the FP16 split's 4 x 4 tiles
+    // three instead of two (measured on the 32768-atom cell: 4% and 12%
+    // faster; where the wave count does not change, the exposed A loads
+    // cost 5-7%, so the other shapes keep both double-buffered)
     T fa[4][4], fb0[NB][4], fb1[NB][4];
     TileStep<NB> e0, e1;
     if (next(e0)) {
