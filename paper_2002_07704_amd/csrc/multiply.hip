@@ -606,7 +606,7 @@ struct TileStep {
 // round of memory latency rather than one per step; the products and their
 // order are those of the full list.
 template <int NB, int MODE, int TB, int STORE, int NDOT, typename T>
-__global__ __launch_bounds__(256) void k_tile16(
+__global__ __launch_bounds__(256, 2) void k_tile16(
     int n, int n_items, const int* __restrict__ items, const int* __restrict__ ka_ptr,
     const int* __restrict__ ka_col, const int* __restrict__ ka_pos,
     const int* __restrict__ ka_key, const int* __restrict__ a_rp, const T* __restrict__ a_val,
@@ -724,13 +724,15 @@ __global__ __launch_bounds__(256) void k_tile16(
     return true;
   };
 
-  if (nsteps > 0 && ((MODE == TM_F64 && NB == 2) || (MODE == TM_F16X3 && NB == 4))) {
+  if (nsteps > 0 && (MODE == TM_F64 || (MODE == TM_F16X3 && NB == 4))) {
     // the A fragments single-buffered (loaded after the products that read
     // them), the B fragments double-buffered: one more wave fits a SIMD --
-    // FP64 4 x 2 tiles three instead of two, the FP16 split's 4 x 4 tiles
-    // three instead of two (measured on the 32768-atom cell: 4% and 12%
-    // faster; where the wave count does not change, the exposed A loads
-    // cost 5-7%, so the other shapes keep both double-buffered)
+    // FP64 4 x 2 tiles three instead of two, FP64 4 x 4 tiles (accumulators
+    // in the architectural registers under the two-wave launch bound) two
+    // instead of one, the FP16 split's 4 x 4 tiles three instead of two
+    // (measured on the 32768-atom cell: 4%, 14% and 12% faster; where the
+    // wave count does not change the exposed A loads cost 5-7%, so the
+    // other shapes keep both double-buffered)
     T fa[4][4], fb0[NB][4], fb1[NB][4];
     TileStep<NB> e0, e1;
     if (next(e0)) {
