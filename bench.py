@@ -192,7 +192,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, key, kernel, row_order):
     out = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         per = load(d, counter)
-        copies = [(i, v) for (i, n), v in per.items() if "copyBuffer" in n and v > 0.25 * COPY_BYTES]
+        copies = [(i, v) for (i, n), v in per.items() if "copyBuffer" in n and v > 0.4 * COPY_BYTES]
         if not copies:
             raise SystemExit(f"no calibration copy found in {d}")
         # the calibration copy is the last large copy before the timed work
