@@ -1011,6 +1011,8 @@ int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T
  *  scalars   FP64 [n_cells * LNV_NSCALARS]: cell c's scalar block (LNV_SC_*,
  *            status bits included) at c * LNV_NSCALARS; lnv_cg_check takes
  *            one cell's block
+ *  row_off   int32 [n_cells+1]: first block row of each cell
+ *  n_orb     FP64 [n_cells]: orbitals (support functions present) of each cell
  * 1 <= n_cells <= 1024 (LNV_EUNSUPPORTED beyond).  The minimisation of
  * Sec. II.C.2, per cell; the paper runs one system at a time (running many
  * small systems in one launch is this library's addition).
@@ -1022,35 +1024,58 @@ typedef struct lnv_batch {
   const int32_t* row_cell;
   const double* n_elec;
   double* scalars;
+  const int32_t* row_off;
+  const double* n_orb;
 } lnv_batch;
 
-/* lnv_cg_init_batch -- lnv_cg_init (identity metric) per cell: L0 = lambda_c I
- * on each cell's rows, lambda_c the smallest positive root of that cell's
- * N(lambda I) = n_elec[c].  Clears every cell's scalar block (the
- * correction counter too) and the direction history; writes L and
- * LNV_SC_LAMBDA per cell.  Workspace as for lnv_cg_init (S's pattern needs
- * its index).  Start of the minimisation of Sec. II.C.2, per cell.
- */
-int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_batch* b, lnv_cg_ws* ws,
-                      hipStream_t s);
+/* lnv_hotelling_batch -- lnv_hotelling per cell: each cell's sigma from its
+ * own rows (LNV_SC_SIGMA of its scalar block), T0 = sigma_c I on its rows,
+ * then the products of the iteration for all cells at once (T's pattern is
+ * block diagonal).  Workspace as for lnv_hotelling.  The metric of
+ * Sec. II.C.2, per cell. */
+int lnv_hotelling_batch(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, const lnv_batch* b,
+                        lnv_cg_ws* ws, hipStream_t s);
 
-/* lnv_cg_step_batch -- lnv_cg_step (identity metric, FP64) for every cell of
- * a batch at once: the six products of the evaluation, the line search's and
- * the electron-number check's and correction's products are one launch each
- * for all cells; the traces are reduced per cell (fixed order) and mu,
- * beta, alpha, the check and delta are taken per cell (a cell within the
- * electron-number tolerance keeps delta = 0 while others are corrected).
- * Differences from lnv_cg_step: no metric, no mixed-precision evaluation
- * (opts->eval32 must be NULL: LNV_EUNSUPPORTED), no occupation bounds (the
- * E-rise guard stays), S.L and S.L.S formed afresh every step, and the
- * traces of the line search taken from stored products (a product's fused
- * trace partials cover row clusters that may straddle two cells).  The
- * workspace is lnv_cg_step's without a metric (ev.YT and ev.W serve as
- * product scratch).  For k > 0, L and the workspace must be those the
- * previous step left.  Sec. II.C.2 / Sec. V.C as lnv_cg_step, per cell.
+/* lnv_pm_start_batch, lnv_pm_step_batch -- canonical purification per cell
+ * (lnv_pm_start, lnv_pm_step) with each cell's n_orb, n_elec, mu, b, lambda,
+ * c and stopping test; ws->scalars holds n_cells blocks of LNV_PM_NSCALARS
+ * and ws->hist n_cells blocks of 4 hist_len (cell c's at c times the block).
+ * Every launch runs for all cells: a cell that has stopped takes the update
+ * coefficients (1, 0, 0), which leave its K unchanged.  The start of
+ * Sec. II.C.2, per cell. */
+int lnv_pm_start_batch(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT,
+                       const lnv_batch* b, lnv_pm_ws* ws, hipStream_t s);
+int lnv_pm_step_batch(lnv_bsm* K, const lnv_bsm* S, const lnv_batch* b, double tol,
+                      lnv_pm_ws* ws, hipStream_t s);
+
+/* lnv_cg_init_batch -- lnv_cg_init per cell: L0 = lambda_c T (T = NULL: the
+ * identity) on each cell's rows, lambda_c the smallest positive root of that
+ * cell's N(lambda T) = n_elec[c].  Clears every cell's scalar block but its
+ * sigma (the correction counter too) and the direction history; writes L
+ * and LNV_SC_LAMBDA per cell.  Workspace as for lnv_cg_init (S's pattern
+ * needs its index).  Start of the minimisation of Sec. II.C.2, per cell.
  */
-int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_batch* b,
-                      int64_t k, const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s);
+int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, const lnv_batch* b,
+                      lnv_cg_ws* ws, hipStream_t s);
+
+/* lnv_cg_step_batch -- lnv_cg_step (FP64, metric T or the identity) for every
+ * cell of a batch at once: the six products of the evaluation, the metric's,
+ * the line search's and the electron-number check's and correction's
+ * products are one launch each for all cells; the traces are reduced per
+ * cell (fixed order) and mu, beta, alpha, the check and delta are taken per
+ * cell (a cell within the electron-number tolerance keeps delta = 0 while
+ * others are corrected).  Differences from lnv_cg_step: no mixed-precision
+ * evaluation (opts->eval32 must be NULL: LNV_EUNSUPPORTED), no occupation
+ * bounds (the E-rise guard stays), S.L and S.L.S formed afresh every step,
+ * and the traces of the line search taken from stored products (a
+ * product's fused trace partials cover row clusters that may straddle two
+ * cells).  The workspace is lnv_cg_step's (ev.YT and ev.W serve as product
+ * scratch).  For k > 0, L and the workspace must be those the previous step
+ * left.  Sec. II.C.2 / Sec. V.C as lnv_cg_step, per cell.
+ */
+int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const lnv_bsm* T,
+                      const lnv_batch* b, int64_t k, const lnv_opts* opts, lnv_cg_ws* ws,
+                      hipStream_t s);
 
 /* ------------------------------------------------------------ timing
  * Optional HIP-event timing of the block multiply kernel: while enabled,

@@ -56,8 +56,11 @@ struct Seg {
   const int64_t* val_ptr = nullptr;
   const int* row_cell = nullptr;
   const double* n_elec = nullptr;
+  const int* row_off = nullptr;     // [n+1] first row of each cell
+  const double* n_orb = nullptr;    // [n] orbitals (functions present) of each cell
+  int sc_stride = LNV_NSCALARS;     // scalars per cell
 };
-enum { RK_ALL = 0, RK_ITEMS = 1, RK_VEC = 2 };
+enum { RK_ALL = 0, RK_ITEMS = 1, RK_VEC = 2, RK_ROWS = 3 };
 
 struct StageArgs {
   double n_elec, n_tol, step_cap;
@@ -69,6 +72,7 @@ struct StageArgs {
   double pm_n, pm_theta, pm_tol;   // ST_PM0 / ST_PM: orbitals, occupied states, tolerance
   double* pm_hist;                 // ST_PM: device [4 * pm_hist_len] (c, t1, t2, t3)
   int pm_hist_len;
+  int pm_batch;                    // ST_PM: a stopped cell keeps K (coefficients 1, 0, 0)
 };
 
 // Runaway guard (ST_BETA): a rise of E beyond this fraction of |E| counts
@@ -178,8 +182,13 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
   __shared__ double shm[256];
   const int cell = blockIdx.x;
   if (sg.n > 0) {
-    sc += (size_t)cell * LNV_NSCALARS;
-    sa.n_elec = sg.n_elec[cell];
+    sc += (size_t)cell * sg.sc_stride;
+    if (sg.n_elec) {
+      sa.n_elec = sg.n_elec[cell];
+      sa.pm_theta = 0.5 * sg.n_elec[cell];
+    }
+    if (sg.n_orb) sa.pm_n = sg.n_orb[cell];
+    if (sa.pm_hist) sa.pm_hist += (size_t)cell * 4 * sa.pm_hist_len;
     sa.en_out = nullptr;
   }
   for (int q = 0; q < rl.nr; ++q) {
@@ -190,6 +199,9 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
     } else if (sg.n > 0 && rd.kind == RK_VEC) {
       rd.off += cell * sg.per * rd.stride;
       rd.count = sg.per;
+    } else if (sg.n > 0 && rd.kind == RK_ROWS) {
+      rd.off += sg.row_off[cell] * rd.stride;
+      rd.count = sg.row_off[cell + 1] - sg.row_off[cell];
     }
     if (rd.op == 0) {
       double v = 0.0;
@@ -377,6 +389,10 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
       const int step = (int)sc[LNV_PM_STEPS];
       if (step >= sa.pm_hist_len) {
         sc[LNV_PM_STOPPED] = 1.0;
+        if (sa.pm_batch) {
+          sc[LNV_PM_A0] = 1.0;
+          sc[LNV_PM_A1] = sc[LNV_PM_A2] = 0.0;
+        }
         return;
       }
       const double t1 = sc[LNV_PM_T1], t2 = sc[LNV_PM_T2], t3 = sc[LNV_PM_T3];
@@ -394,6 +410,11 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
       sc[LNV_PM_C] = c;
       if (stop) {
         sc[LNV_PM_STOPPED] = 1.0;
+        if (sa.pm_batch) {
+          // the cell's products still run with the others': keep K
+          sc[LNV_PM_A0] = 1.0;
+          sc[LNV_PM_A1] = sc[LNV_PM_A2] = 0.0;
+        }
         return;
       }
       sc[LNV_PM_PREV] = idem;
@@ -619,24 +640,6 @@ __global__ __launch_bounds__(256) void k_lincomb(int64_t nv, double a, const dou
   }
 }
 
-// out = sc[i0] X + sc[i1] Y + sc[i2] Z (Y, Z nullable; out may alias), the
-// association of k_lincomb; skipped when *skip != 0.
-__global__ __launch_bounds__(256) void k_lincomb_sc(int64_t nv, const double* __restrict__ sc,
-                                                    int i0, int i1, int i2,
-                                                    const double* X, const double* Y,
-                                                    const double* Z, double* out,
-                                                    const double* __restrict__ skip) {
-  if (skip != nullptr && *skip != 0.0) return;
-  const double a = sc[i0], b = Y ? sc[i1] : 0.0, c = Z ? sc[i2] : 0.0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nv;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double v = a * X[e];
-    if (Y) v = fma(b, Y[e], v);
-    if (Z) v = fma(c, Z[e], v);
-    out[e] = v;
-  }
-}
-
 // Per-cell energy and electron number of a batch of independent cells from
 // the trace partials k_assemble leaves (slots 0..3 = <L,X>, <L,Y>, <L,Z>,
 // <L,V> per item of L's pattern): workgroup c sums the items of cell c,
@@ -699,7 +702,7 @@ __global__ __launch_bounds__(256) void k_hprime(int n, const int* __restrict__ i
   const int cnt = min(kWave, rp[i + 1] - c0);
   const int b = threadIdx.x >> 2, r = threadIdx.x & 3;
   if (b >= cnt) return;
-  const double mu = sc[(sg.n > 0 ? (size_t)sg.row_cell[i] * LNV_NSCALARS : 0) + LNV_SC_MU];
+  const double mu = sc[(sg.n > 0 ? (size_t)sg.row_cell[i] * sg.sc_stride : 0) + LNV_SC_MU];
   const int p = c0 + b;
   const int q = ix_find(sx, i, col[p]);
 #pragma unroll
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(256) void k_identity(int n, const int* __restrict__
                                                   const int* __restrict__ col, Ix sx,
                                                   const double* __restrict__ S,
                                                   const double* __restrict__ sc, int idx,
-                                                  double* __restrict__ D) {
+                                                  double* __restrict__ D, Seg sg) {
   const int item = blockIdx.x;
   const int i = items[2 * item], c0 = items[2 * item + 1];
   const int cnt = min(kWave, rp[i + 1] - c0);
@@ -727,7 +730,7 @@ __global__ __launch_bounds__(256) void k_identity(int n, const int* __restrict__
   if (b >= cnt) return;
   const int p = c0 + b;
   const bool diag = col[p] == i;
-  const double v = sc ? sc[idx] : 1.0;
+  const double v = sc ? sc[(sg.n > 0 ? (size_t)sg.row_cell[i] * sg.sc_stride : 0) + idx] : 1.0;
   bool present = false;
   if (diag) {
     const int q = ix_find(sx, i, i);
@@ -788,7 +791,7 @@ __device__ __forceinline__ VecRange vec_range(int64_t nv, const double* sc, cons
     const int c = blockIdx.x / sg.per, q = blockIdx.x % sg.per;
     const int64_t lo = sg.val_ptr[c];
     return VecRange{lo, sg.val_ptr[c + 1], lo + (int64_t)q * 256 + threadIdx.x,
-                    (int64_t)sg.per * 256, sc + (size_t)c * LNV_NSCALARS};
+                    (int64_t)sg.per * 256, sc ? sc + (size_t)c * sg.sc_stride : nullptr};
   }
   return VecRange{0, nv, (int64_t)blockIdx.x * 256 + threadIdx.x, (int64_t)gridDim.x * 256, sc};
 }
@@ -831,10 +834,11 @@ __global__ __launch_bounds__(256) void k_vec_g(int64_t nv, const double* __restr
 __global__ __launch_bounds__(256) void k_vec_metric_dots(int64_t nv, const double* __restrict__ G,
                                                          const double* __restrict__ F,
                                                          const double* __restrict__ Fc,
-                                                         double* __restrict__ partials) {
+                                                         double* __restrict__ partials, Seg sg) {
   __shared__ double sh[16];
+  const VecRange vr = vec_range(nv, nullptr, sg);
   double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-  for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < nv; q += (int64_t)gridDim.x * 256) {
+  for (int64_t q = vr.start; q < vr.hi; q += vr.step) {
     const double fc = Fc[q];
     s0 = fma(F[q], fc, s0);
     s1 = fma(G[q], fc, s1);
@@ -924,6 +928,33 @@ __global__ __launch_bounds__(256) void k_vec_axpy(int64_t nv, const double* __re
   for (int64_t q = vr.start; q < vr.hi; q += vr.step) L[q] = L[q] + a * D[q];
 }
 
+// out = sc[i0] X + sc[i1] Y + sc[i2] Z (Y, Z nullable; out may alias), the
+// association of k_lincomb, per cell of a batch with the cell's scalars;
+// skipped when *skip != 0.
+__global__ __launch_bounds__(256) void k_lincomb_sc(int64_t nv, const double* __restrict__ sc,
+                                                    int i0, int i1, int i2,
+                                                    const double* X, const double* Y,
+                                                    const double* Z, double* out,
+                                                    const double* __restrict__ skip, Seg sg) {
+  if (skip != nullptr && *skip != 0.0) return;
+  const VecRange vr = vec_range(nv, sc, sg);
+  const double a = vr.sc[i0], b = Y ? vr.sc[i1] : 0.0, c = Z ? vr.sc[i2] : 0.0;
+  for (int64_t e = vr.start; e < vr.hi; e += vr.step) {
+    double v = a * X[e];
+    if (Y) v = fma(b, Y[e], v);
+    if (Z) v = fma(c, Z[e], v);
+    out[e] = v;
+  }
+}
+
+// Zero the scalar block of each cell (blockIdx.x) except entry keep.
+__global__ __launch_bounds__(64) void k_clear_scalars(double* __restrict__ sc, int stride,
+                                                      int keep) {
+  double* c = sc + (size_t)blockIdx.x * stride;
+  for (int q = threadIdx.x; q < stride; q += blockDim.x)
+    if (q != keep) c[q] = 0.0;
+}
+
 // Y = X + sc[idx] * Y
 __global__ __launch_bounds__(256) void k_vec_xpay(int64_t nv, const double* __restrict__ X,
                                                   const double* __restrict__ sc, int idx,
@@ -956,6 +987,33 @@ void add(RedList& rl, int64_t off, int count, int stride, int dst, int op = 0,
          int kind = RK_ALL) {
   rl.r[rl.nr++] = Red{(int)off, count, stride, dst, op, kind};
 }
+
+// Validation of a batch descriptor against L's pattern (host side; the
+// device tables themselves are the caller's).
+int check_batch(const lnv_batch* b, const lnv_pattern* pl) {
+  if (!b || b->n_cells < 1 || !b->item_ptr || !b->val_ptr || !b->row_cell || !b->n_elec ||
+      !b->scalars || !b->row_off || !b->n_orb)
+    return LNV_EINVAL;
+  if (b->n_cells > pl->n) return LNV_EPATTERN;
+  if (b->n_cells > kVecGrid) return LNV_EUNSUPPORTED;   // one vector workgroup per cell at least
+  return LNV_OK;
+}
+
+Seg make_seg(const lnv_batch* b) {
+  Seg sg;
+  sg.n = b->n_cells;
+  sg.per = kVecGrid / b->n_cells;
+  sg.item_ptr = b->item_ptr;
+  sg.val_ptr = b->val_ptr;
+  sg.row_cell = b->row_cell;
+  sg.n_elec = b->n_elec;
+  sg.row_off = b->row_off;
+  sg.n_orb = b->n_orb;
+  return sg;
+}
+
+// Vector-kernel grid of a batch (cell c: workgroups c * per ...).
+int seg_grid(const Seg& sg) { return sg.n > 0 ? sg.n * sg.per : kVecGrid; }
 
 // ix: the pattern must carry its spatial index (for lookups in either
 // orientation); items: its row work list.
@@ -1656,12 +1714,16 @@ int metric_apply_pair32(const lnv_bsm* T, const double* G, double* Gc, const dou
 
 }  // namespace
 
-extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws,
-                             hipStream_t s) {
+namespace {
+
+// Hotelling's iteration; sc: the scalar block(s) (a batch: sigma per cell,
+// from each cell's rows).
+int hotelling_impl(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws, double* sc,
+                   const Seg& sg, hipStream_t s) {
   if (!bsm_ok(S) || !bsm_ok(T) || !ws || n_iter < 0) return LNV_EINVAL;
   if (S->blk != 4 || T->blk != 4) return LNV_EUNSUPPORTED;
   const lnv_eval_ws& ev = ws->ev;
-  if (!ws->Gc || !ev.partials || !ev.scalars || !bsm_ok(&ev.SL)) return LNV_EINVAL;
+  if (!ws->Gc || !ev.partials || !sc || !bsm_ok(&ev.SL)) return LNV_EINVAL;
   const lnv_pattern* pt = T->pat;
   if (S->pat->n != pt->n || ev.SL.pat->n != pt->n) return LNV_EPATTERN;
   if (!pattern_ready(pt, true, false, true) || !pattern_ready(S->pat, true, false, false) ||
@@ -1670,17 +1732,16 @@ extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_c
   if (ev.partials_len < pt->n) return LNV_EINVAL;
   ws->ev.carry = 0;
   double* part = ev.partials;
-  double* sc = ev.scalars;
   const size_t bytes = sizeof(double) * (size_t)pt->nnzb * 16;
   k_rowabs<<<S->pat->n, 256, 0, s>>>(S->pat->row_ptr, static_cast<const double*>(S->val), part);
   LNV_LAUNCH_CHECK();
   RedList rl = reds();
-  add(rl, 0, S->pat->n, 1, LNV_SC_T4, 1);
+  add(rl, 0, S->pat->n, 1, LNV_SC_T4, 1, RK_ROWS);
   StageArgs sa{};
-  LNV_TRY(scalar_stage(part, rl, sc, ST_SIGMA, sa, s));
+  LNV_TRY(scalar_stage(part, rl, sc, ST_SIGMA, sa, s, sg));
   k_identity<<<pt->n_items, 256, 0, s>>>(pt->n, pt->items, pt->row_ptr, pt->col, make_ix(S->pat),
                                          static_cast<const double*>(S->val), sc, LNV_SC_SIGMA,
-                                         static_cast<double*>(T->val));
+                                         static_cast<double*>(T->val), sg);
   LNV_LAUNCH_CHECK();
   // T_{n+1} = 2 T_n - T_n (S T_n) on T's pattern; ST lives on pat(S.T)
   lnv_bsm ST{ev.SL.pat, 4, LNV_F64, ev.SL.val};
@@ -1698,6 +1759,14 @@ extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_c
   return LNV_OK;
 }
 
+}  // namespace
+
+extern "C" int lnv_hotelling(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter, lnv_cg_ws* ws,
+                             hipStream_t s) {
+  if (!ws) return LNV_EINVAL;
+  return hotelling_impl(S, T, n_iter, ws, ws->ev.scalars, Seg{}, s);
+}
+
 namespace {
 
 int check_pm(const lnv_bsm* K, const lnv_pm_ws* ws) {
@@ -1713,10 +1782,16 @@ int check_pm(const lnv_bsm* K, const lnv_pm_ws* ws) {
 
 }  // namespace
 
-extern "C" int lnv_pm_start(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT,
-                            double n_orb, double n_elec, lnv_pm_ws* ws, hipStream_t s) {
+namespace {
+
+// Purification start and step; a batch (sg.n > 0) takes n_orb and n_elec per
+// cell from sg, reduces per cell (scalars and history per cell at stride
+// LNV_PM_NSCALARS and 4 hist_len) and never skips a launch: a stopped cell
+// gets the coefficients (1, 0, 0), which leave its K unchanged.
+int pm_start_impl(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT, double n_orb,
+                  double n_elec, lnv_pm_ws* ws, const Seg& sg, hipStream_t s) {
   LNV_TRY(check_pm(K, ws));
-  if (!bsm_ok(T) || !bsm_ok(H) || !bsm_ok(HT) || !(n_orb > 0.0) || !(n_elec > 0.0))
+  if (!bsm_ok(T) || !bsm_ok(H) || !bsm_ok(HT) || (sg.n == 0 && !(n_orb > 0.0 && n_elec > 0.0)))
     return LNV_EINVAL;
   const lnv_pattern* pl = K->pat;
   if (T->pat != pl) return LNV_EPATTERN;
@@ -1737,29 +1812,29 @@ extern "C" int lnv_pm_start(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_
                                      part + 2 * slot);
   LNV_LAUNCH_CHECK();
   RedList rl = reds();
-  add(rl, 0, ni, 1, LNV_PM_DOT);
-  add(rl, slot, pl->n, 1, LNV_PM_NT, 1);
-  add(rl, 2 * slot, H->pat->n, 1, LNV_PM_NH, 1);
+  add(rl, 0, ni, 1, LNV_PM_DOT, 0, RK_ITEMS);
+  add(rl, slot, pl->n, 1, LNV_PM_NT, 1, RK_ROWS);
+  add(rl, 2 * slot, H->pat->n, 1, LNV_PM_NH, 1, RK_ROWS);
   StageArgs sa{};
   sa.pm_n = n_orb;
   sa.pm_theta = 0.5 * n_elec;
-  LNV_TRY(scalar_stage(part, rl, sc, ST_PM0, sa, s));
+  LNV_TRY(scalar_stage(part, rl, sc, ST_PM0, sa, s, sg));
   // K0 = a0 T + a1 P_L(T (H T))
   lnv_bsm K2{pl, 4, LNV_F64, ws->K2};
   LNV_TRY(multiply_launch(1.0, H, T, 0, 0.0, HT, 1, nullptr, nullptr, nullptr, nullptr, s));
   LNV_TRY(multiply_launch(1.0, T, HT, 0, 0.0, &K2, 1, nullptr, nullptr, nullptr, nullptr, s));
   const int64_t nv = pl->nnzb * 16;
-  k_lincomb_sc<<<vec_grid(), 256, 0, s>>>(nv, sc, LNV_PM_A0, LNV_PM_A1, LNV_PM_A2,
-                                          static_cast<const double*>(T->val), ws->K2, nullptr,
-                                          static_cast<double*>(K->val), nullptr);
+  k_lincomb_sc<<<seg_grid(sg), 256, 0, s>>>(nv, sc, LNV_PM_A0, LNV_PM_A1, LNV_PM_A2,
+                                            static_cast<const double*>(T->val), ws->K2, nullptr,
+                                            static_cast<double*>(K->val), nullptr, sg);
   LNV_LAUNCH_CHECK();
   return LNV_OK;
 }
 
-extern "C" int lnv_pm_step(lnv_bsm* K, const lnv_bsm* S, double n_elec, double tol,
-                           lnv_pm_ws* ws, hipStream_t s) {
+int pm_step_impl(lnv_bsm* K, const lnv_bsm* S, double n_elec, double tol, lnv_pm_ws* ws,
+                 const Seg& sg, hipStream_t s) {
   LNV_TRY(check_pm(K, ws));
-  if (!bsm_ok(S) || !(n_elec > 0.0) || !(tol >= 0.0)) return LNV_EINVAL;
+  if (!bsm_ok(S) || (sg.n == 0 && !(n_elec > 0.0)) || !(tol >= 0.0)) return LNV_EINVAL;
   const lnv_pattern* pl = K->pat;
   if (!pattern_ready(S->pat, true, false, false)) return LNV_EPATTERN;
   const int ni = pl->n_items;
@@ -1767,7 +1842,8 @@ extern "C" int lnv_pm_step(lnv_bsm* K, const lnv_bsm* S, double n_elec, double t
   const int64_t nv = pl->nnzb * 16;
   double* part = ws->partials;
   double* sc = ws->scalars;
-  const double* stopped = sc + LNV_PM_STOPPED;
+  // one system: a stopped purification turns every launch into a no-op
+  const double* stopped = sg.n > 0 ? nullptr : sc + LNV_PM_STOPPED;
   double* Kv = static_cast<double*>(K->val);
   lnv_bsm K2{pl, 4, LNV_F64, ws->K2}, K3{pl, 4, LNV_F64, ws->K3};
   // S K, K S K = P_L(K . SK), K S K S K = P_L(KSK . SK)
@@ -1785,27 +1861,39 @@ extern "C" int lnv_pm_step(lnv_bsm* K, const lnv_bsm* S, double n_elec, double t
     LNV_LAUNCH_CHECK();
   }
   RedList rl = reds();
-  add(rl, 0, ni, 1, LNV_PM_T1);
-  add(rl, slot, ni, 1, LNV_PM_T2);
-  add(rl, 2 * slot, ni, 1, LNV_PM_T3);
+  add(rl, 0, ni, 1, LNV_PM_T1, 0, RK_ITEMS);
+  add(rl, slot, ni, 1, LNV_PM_T2, 0, RK_ITEMS);
+  add(rl, 2 * slot, ni, 1, LNV_PM_T3, 0, RK_ITEMS);
   StageArgs sa{};
   sa.pm_theta = 0.5 * n_elec;
   sa.pm_tol = tol;
   sa.pm_hist = ws->hist;
   sa.pm_hist_len = ws->hist_len;
+  sa.pm_batch = sg.n > 0;
   // a stopped purification leaves its scalars alone (the stage returns first)
-  LNV_TRY(scalar_stage(part, rl, sc, ST_PM, sa, s));
-  k_lincomb_sc<<<vec_grid(), 256, 0, s>>>(nv, sc, LNV_PM_A0, LNV_PM_A1, LNV_PM_A2, Kv, ws->K2,
-                                          ws->K3, Kv, stopped);
+  LNV_TRY(scalar_stage(part, rl, sc, ST_PM, sa, s, sg));
+  const int vg = seg_grid(sg);
+  k_lincomb_sc<<<vg, 256, 0, s>>>(nv, sc, LNV_PM_A0, LNV_PM_A1, LNV_PM_A2, Kv, ws->K2, ws->K3,
+                                  Kv, stopped, sg);
   LNV_LAUNCH_CHECK();
   // K <- (K + K^T)/2
-  lnv_bsm KTm{pl, 4, LNV_F64, ws->KT};
   LNV_TRY(transpose_skip_launch(K, ws->perm_L, ws->KT, stopped, s));
-  k_lincomb_sc<<<vec_grid(), 256, 0, s>>>(nv, sc, LNV_PM_HALF, LNV_PM_HALF, 0, Kv, ws->KT,
-                                          nullptr, Kv, stopped);
+  k_lincomb_sc<<<vg, 256, 0, s>>>(nv, sc, LNV_PM_HALF, LNV_PM_HALF, 0, Kv, ws->KT, nullptr, Kv,
+                                  stopped, sg);
   LNV_LAUNCH_CHECK();
-  (void)KTm;
   return LNV_OK;
+}
+
+}  // namespace
+
+extern "C" int lnv_pm_start(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT,
+                            double n_orb, double n_elec, lnv_pm_ws* ws, hipStream_t s) {
+  return pm_start_impl(K, T, H, HT, n_orb, n_elec, ws, Seg{}, s);
+}
+
+extern "C" int lnv_pm_step(lnv_bsm* K, const lnv_bsm* S, double n_elec, double tol,
+                           lnv_pm_ws* ws, hipStream_t s) {
+  return pm_step_impl(K, S, n_elec, tol, ws, Seg{}, s);
 }
 
 extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, double n_elec,
@@ -1842,7 +1930,7 @@ extern "C" int lnv_cg_init(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T, doubl
     LNV_HIP(hipMemcpyAsync(ws->D, T->val, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
   } else {
     k_identity<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, make_ix(S->pat),
-                                  static_cast<const double*>(S->val), nullptr, 0, ws->D);
+                                  static_cast<const double*>(S->val), nullptr, 0, ws->D, Seg{});
     LNV_LAUNCH_CHECK();
   }
   // N(lambda T) = 6 Tr[TSTS] lambda^2 - 4 Tr[TSTSTS] lambda^3 at L = 0:
@@ -1937,7 +2025,7 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
     Gc = ws->Gc;
     Fc = ws->Fc;
     gcur = ws->gc;
-    k_vec_metric_dots<<<kVecGrid, 256, 0, s>>>(nv, ws->G, ws->F, ws->Fc, part);
+    k_vec_metric_dots<<<kVecGrid, 256, 0, s>>>(nv, ws->G, ws->F, ws->Fc, part, Seg{});
     LNV_LAUNCH_CHECK();
     RedList rl = reds();
     add(rl, 0, kVecGrid, 1, LNV_SC_FF);
@@ -2054,30 +2142,6 @@ extern "C" int lnv_cg_step(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H, const
 // ------------------------------------------------------------------ batches of cells
 namespace {
 
-// Validation of a batch descriptor against L's pattern (host side; the
-// device tables themselves are the caller's).
-int check_batch(const lnv_batch* b, const lnv_pattern* pl) {
-  if (!b || b->n_cells < 1 || !b->item_ptr || !b->val_ptr || !b->row_cell || !b->n_elec ||
-      !b->scalars)
-    return LNV_EINVAL;
-  if (b->n_cells > pl->n) return LNV_EPATTERN;
-  if (b->n_cells > kVecGrid) return LNV_EUNSUPPORTED;   // one vector workgroup per cell at least
-  return LNV_OK;
-}
-
-Seg make_seg(const lnv_batch* b) {
-  Seg sg;
-  sg.n = b->n_cells;
-  sg.per = kVecGrid / b->n_cells;
-  sg.item_ptr = b->item_ptr;
-  sg.val_ptr = b->val_ptr;
-  sg.row_cell = b->row_cell;
-  sg.n_elec = b->n_elec;
-  return sg;
-}
-
-// Vector-kernel grid of a batch (cell c: workgroups c * per ...).
-int seg_grid(const Seg& sg) { return sg.n > 0 ? sg.n * sg.per : kVecGrid; }
 
 // The traces T0..T3 of cubic_traces for a batch: every product is stored
 // and traced per work item of L's pattern (k_dot_items), so each partial
@@ -2155,9 +2219,35 @@ int check_batch_cg(const lnv_bsm* L, const lnv_bsm* S, const lnv_batch* b, lnv_c
 
 }  // namespace
 
-extern "C" int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_batch* b,
-                                 lnv_cg_ws* ws, hipStream_t s) {
+extern "C" int lnv_hotelling_batch(const lnv_bsm* S, lnv_bsm* T, int32_t n_iter,
+                                   const lnv_batch* b, lnv_cg_ws* ws, hipStream_t s) {
+  if (!T || !bsm_ok(T)) return LNV_EINVAL;
+  LNV_TRY(check_batch(b, T->pat));
+  return hotelling_impl(S, T, n_iter, ws, b->scalars, make_seg(b), s);
+}
+
+extern "C" int lnv_pm_start_batch(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT,
+                                  const lnv_batch* b, lnv_pm_ws* ws, hipStream_t s) {
+  if (!K || !bsm_ok(K)) return LNV_EINVAL;
+  LNV_TRY(check_batch(b, K->pat));
+  Seg sg = make_seg(b);
+  sg.sc_stride = LNV_PM_NSCALARS;
+  return pm_start_impl(K, T, H, HT, 0.0, 0.0, ws, sg, s);
+}
+
+extern "C" int lnv_pm_step_batch(lnv_bsm* K, const lnv_bsm* S, const lnv_batch* b, double tol,
+                                 lnv_pm_ws* ws, hipStream_t s) {
+  if (!K || !bsm_ok(K)) return LNV_EINVAL;
+  LNV_TRY(check_batch(b, K->pat));
+  Seg sg = make_seg(b);
+  sg.sc_stride = LNV_PM_NSCALARS;
+  return pm_step_impl(K, S, 0.0, tol, ws, sg, s);
+}
+
+extern "C" int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* T,
+                                 const lnv_batch* b, lnv_cg_ws* ws, hipStream_t s) {
   LNV_TRY(check_batch_cg(L, S, b, ws));
+  if (T && (!bsm_ok(T) || T->pat != L->pat || T->blk != 4)) return LNV_EPATTERN;
   const lnv_eval_ws& ev = ws->ev;
   ws->ev.carry = 0;
   const lnv_pattern* pl = L->pat;
@@ -2167,14 +2257,20 @@ extern "C" int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_batch* 
   const Seg sg = make_seg(b);
   double* part = ev.partials;
   double* sc = b->scalars;
-  LNV_HIP(hipMemsetAsync(sc, 0, sizeof(double) * LNV_NSCALARS * (size_t)b->n_cells, s));
+  // every cell's scalars but its sigma (from lnv_hotelling_batch) start at zero
+  k_clear_scalars<<<b->n_cells, 64, 0, s>>>(sc, LNV_NSCALARS, LNV_SC_SIGMA);
+  LNV_LAUNCH_CHECK();
   LNV_HIP(hipMemsetAsync(ws->gc_prev, 0, sizeof(double) * nv, s));
   LNV_HIP(hipMemsetAsync(ws->D_prev, 0, sizeof(double) * nv, s));
   LNV_HIP(hipMemsetAsync(L->val, 0, sizeof(double) * nv, s));
-  k_identity<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, make_ix(S->pat),
-                                static_cast<const double*>(S->val), nullptr, 0, ws->D);
-  LNV_LAUNCH_CHECK();
-  // per cell: N(lambda I) = 6 Tr[SS] lambda^2 - 4 Tr[SSS] lambda^3 at L = 0
+  if (T) {
+    LNV_HIP(hipMemcpyAsync(ws->D, T->val, sizeof(double) * nv, hipMemcpyDeviceToDevice, s));
+  } else {
+    k_identity<<<ni, 256, 0, s>>>(pl->n, pl->items, pl->row_ptr, pl->col, make_ix(S->pat),
+                                  static_cast<const double*>(S->val), nullptr, 0, ws->D, sg);
+    LNV_LAUNCH_CHECK();
+  }
+  // per cell: N(lambda P) = 6 Tr[PSPS] lambda^2 - 4 Tr[PSPSPS] lambda^3 at L = 0, P = T or I
   lnv_bsm ZD{ev.Z.pat, 4, LNV_F64, ev.Z.val};
   LNV_TRY(cubic_traces_batch(L, S, S, true, ws->D, ev, ws->SL2, static_cast<double*>(ev.LS.val),
                              nullptr, ZD, nullptr, part, slot, s));
@@ -2187,12 +2283,12 @@ extern "C" int lnv_cg_init_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_batch* 
 }
 
 extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
-                                 const lnv_batch* b, int64_t k, const lnv_opts* opts,
-                                 lnv_cg_ws* ws, hipStream_t s) {
+                                 const lnv_bsm* T, const lnv_batch* b, int64_t k,
+                                 const lnv_opts* opts, lnv_cg_ws* ws, hipStream_t s) {
   if (!opts || opts->reset_period <= 0 || k < 0) return LNV_EINVAL;
   if (opts->eval32) return LNV_EUNSUPPORTED;
   LNV_TRY(check_batch_cg(L, S, b, ws));
-  LNV_TRY(check_cg(L, S, H, nullptr, ws));
+  LNV_TRY(check_cg(L, S, H, T, ws));
   const lnv_eval_ws& ev = ws->ev;
   const lnv_pattern* pl = L->pat;
   const lnv_pattern* ph = H->pat;
@@ -2201,6 +2297,7 @@ extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
   const int64_t slot = slot_len(partial_items(pl));
   const Seg sg = make_seg(b);
   const int vg = seg_grid(sg);
+  const bool metric = T != nullptr;
   double* part = ev.partials;
   double* sc = b->scalars;
   double* Lv = static_cast<double*>(L->val);
@@ -2211,11 +2308,28 @@ extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
   sa.k = (int)k;
   sa.reset_period = opts->reset_period;
   ws->ev.carry = 0;   // S.L and S.L.S are formed afresh every step here
-  // 1. per cell E, N, G, F and mu = <G,F>/<F,F> (identity metric)
+  // 1. per cell E, N, G, F; metric gradients G_c = P_L(T G T), F_c = P_L(T F T);
+  // mu = <G,F_c>/<F,F_c>
   LNV_TRY(eval_core(L, S, H, ws->G, ws->F, nullptr, &ev, s, nullptr, false, sc, sg));
-  // 2-3. g = G - mu F, PR+ beta per cell
-  k_vec_g<<<vg, 256, 0, s>>>(nv, ws->G, ws->F, ws->G, ws->F, ws->gc_prev, sc, ws->g, nullptr,
-                             part, sg);
+  const double* Gc = ws->G;
+  const double* Fc = ws->F;
+  double* gcur = ws->g;
+  if (metric) {
+    LNV_TRY(metric_apply_pair(T, ws->G, ws->Gc, ws->F, ws->Fc, ws, s));
+    Gc = ws->Gc;
+    Fc = ws->Fc;
+    gcur = ws->gc;
+    k_vec_metric_dots<<<vg, 256, 0, s>>>(nv, ws->G, ws->F, ws->Fc, part, sg);
+    LNV_LAUNCH_CHECK();
+    RedList rl = reds();
+    add(rl, 0, vg, 1, LNV_SC_FF, 0, RK_VEC);
+    add(rl, kVecGrid, vg, 1, LNV_SC_GF, 0, RK_VEC);
+    add(rl, 2 * kVecGrid, vg, 1, LNV_SC_FCFC, 0, RK_VEC);
+    LNV_TRY(scalar_stage(part, rl, sc, ST_MU, sa, s, sg));
+  }
+  // 2-3. g = G - mu F (g_c = G_c - mu F_c), PR+ beta per cell
+  k_vec_g<<<vg, 256, 0, s>>>(nv, ws->G, ws->F, Gc, Fc, ws->gc_prev, sc, ws->g,
+                             metric ? ws->gc : nullptr, part, sg);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
@@ -2224,15 +2338,15 @@ extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
     add(rl, 2 * kVecGrid, vg, 1, LNV_SC_GGN, 0, RK_VEC);
     LNV_TRY(scalar_stage(part, rl, sc, ST_BETA, sa, s, sg));
   }
-  // 4. D = -g + beta D_prev, projected on <D, F> = 0
-  k_vec_dir<<<vg, 256, 0, s>>>(nv, ws->g, ws->D_prev, ws->F, sc, ws->D, part, sg);
+  // 4. D = -g_c + beta D_prev, projected on <D, F> = 0 along F_c
+  k_vec_dir<<<vg, 256, 0, s>>>(nv, gcur, ws->D_prev, ws->F, sc, ws->D, part, sg);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
     add(rl, 0, vg, 1, LNV_SC_DF, 0, RK_VEC);
     LNV_TRY(scalar_stage(part, rl, sc, ST_PROJ, sa, s, sg));
   }
-  k_vec_proj<<<vg, 256, 0, s>>>(nv, ws->F, ws->g, sc, ws->D, part, sg);
+  k_vec_proj<<<vg, 256, 0, s>>>(nv, Fc, ws->g, sc, ws->D, part, sg);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
@@ -2252,7 +2366,7 @@ extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
   LNV_TRY(scalar_stage(part, batch_trace_reds(ni, slot, false), sc, ST_ALPHA, sa, s, sg));
   k_vec_axpy<<<vg, 256, 0, s>>>(nv, ws->D, sc, LNV_SC_ALPHA, nullptr, Lv, sg);
   LNV_LAUNCH_CHECK();
-  // 6. electron number at the new L; the cubic correction along F per cell
+  // 6. electron number at the new L; the cubic correction along F_c per cell
   // (cells within tolerance keep delta = 0)
   lnv_bsm SL2{ev.SL.pat, 4, LNV_F64, ws->SL2};
   lnv_bsm Vm{pl, 4, LNV_F64, ev.V};
@@ -2262,7 +2376,7 @@ extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
   LNV_TRY(sym_product(S, &ev.LS, &ev.Z, &ev.Zu, s));
   LNV_TRY(sym_product(&SL2, &ev.Z, &Vm, &Vu, s));
   k_nassemble<<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, Lv, make_ix(ev.Z.pat),
-                                 static_cast<const double*>(ev.Z.val), ev.V, ws->F, part);
+                                 static_cast<const double*>(ev.Z.val), ev.V, Fc, part);
   LNV_LAUNCH_CHECK();
   {
     RedList rl = reds();
@@ -2273,13 +2387,16 @@ extern "C" int lnv_cg_step_batch(lnv_bsm* L, const lnv_bsm* S, const lnv_bsm* H,
     LNV_TRY(scalar_stage(part, rl, sc, ST_NCHK, sa, s, sg));
   }
   lnv_bsm ZF{ev.Z.pat, 4, LNV_F64, ev.X.val};
-  LNV_TRY(cubic_traces_batch(L, S, S, true, ws->F, ev, static_cast<double*>(ev.SL.val),
+  LNV_TRY(cubic_traces_batch(L, S, S, true, Fc, ev, static_cast<double*>(ev.SL.val),
                              static_cast<double*>(ev.LS.val), nullptr, ZF, nullptr, part, slot,
                              s));
   LNV_TRY(scalar_stage(part, batch_trace_reds(ni, slot, true), sc, ST_DELTA, sa, s, sg));
-  k_vec_axpy<<<vg, 256, 0, s>>>(nv, ws->F, sc, LNV_SC_DELTA, nullptr, Lv, sg);
+  k_vec_axpy<<<vg, 256, 0, s>>>(nv, Fc, sc, LNV_SC_DELTA, nullptr, Lv, sg);
   LNV_LAUNCH_CHECK();
-  std::swap(ws->g, ws->gc_prev);
+  if (metric)
+    std::swap(ws->gc, ws->gc_prev);
+  else
+    std::swap(ws->g, ws->gc_prev);
   std::swap(ws->D, ws->D_prev);
   return LNV_OK;
 }

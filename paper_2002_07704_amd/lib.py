@@ -96,7 +96,8 @@ class LnvVbsm(ctypes.Structure):
 
 class LnvBatch(ctypes.Structure):
     _fields_ = [("n_cells", c_int32), ("item_ptr", c_void_p), ("val_ptr", c_void_p),
-                ("row_cell", c_void_p), ("n_elec", c_void_p), ("scalars", c_void_p)]
+                ("row_cell", c_void_p), ("n_elec", c_void_p), ("scalars", c_void_p),
+                ("row_off", c_void_p), ("n_orb", c_void_p)]
 
 
 class LnvPmWs(ctypes.Structure):
@@ -177,9 +178,16 @@ SIGNATURES = {
     "lnv_pm_start": (c_int, [PBsm, PBsm, PBsm, PBsm, c_double, c_double, POINTER(LnvPmWs),
                              c_void_p]),
     "lnv_pm_step": (c_int, [PBsm, PBsm, c_double, c_double, POINTER(LnvPmWs), c_void_p]),
-    "lnv_cg_init_batch": (c_int, [PBsm, PBsm, POINTER(LnvBatch), POINTER(LnvCgWs), c_void_p]),
-    "lnv_cg_step_batch": (c_int, [PBsm, PBsm, PBsm, POINTER(LnvBatch), c_int64, POINTER(LnvOpts),
-                                  POINTER(LnvCgWs), c_void_p]),
+    "lnv_hotelling_batch": (c_int, [PBsm, PBsm, c_int32, POINTER(LnvBatch), POINTER(LnvCgWs),
+                                    c_void_p]),
+    "lnv_pm_start_batch": (c_int, [PBsm, PBsm, PBsm, PBsm, POINTER(LnvBatch), POINTER(LnvPmWs),
+                                   c_void_p]),
+    "lnv_pm_step_batch": (c_int, [PBsm, PBsm, POINTER(LnvBatch), c_double, POINTER(LnvPmWs),
+                                  c_void_p]),
+    "lnv_cg_init_batch": (c_int, [PBsm, PBsm, PBsm, POINTER(LnvBatch), POINTER(LnvCgWs),
+                                  c_void_p]),
+    "lnv_cg_step_batch": (c_int, [PBsm, PBsm, PBsm, PBsm, POINTER(LnvBatch), c_int64,
+                                  POINTER(LnvOpts), POINTER(LnvCgWs), c_void_p]),
     "lnv_bsm_lincomb": (c_int, [c_double, PBsm, c_double, PBsm, c_double, PBsm, PBsm, c_void_p]),
     "lnv_bsm_norm_inf": (c_int, [PBsm, c_void_p, c_void_p, c_void_p]),
     "lnv_bsm_remap": (c_int, [PBsm, PBsm, c_void_p]),

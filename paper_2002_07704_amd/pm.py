@@ -50,10 +50,15 @@ def _pattern_HL(system):
 
 def pm_initial_L(system, n_iter=100, tol=1e-12):
     """Purified K written to system.L; returns the history [dict(c, t1, t2, t3)]
-    (c None for the step that stopped) and the start parameters (mu, b, lambda)."""
+    (c None for the step that stopped) and the start parameters (mu, b, lambda).
+    For a batch of cells every cell is purified with its own scalars
+    (lnv_pm_start_batch, lnv_pm_step_batch), and both are lists, one entry
+    per cell."""
     if system.metric is None:
         raise ValueError("canonical purification needs the metric T ~ S^-1")
     system.pH.build_index()
+    batch = system.cells is not None
+    ncell = len(system.cells) if batch else 1
     n = float(np.sum(system.w.nfun)) if system.w is not None else float(system.fun_rows.sum())
     dev = system.dev
     T, S, H = system.T, system.S, system.H
@@ -65,8 +70,8 @@ def pm_initial_L(system, n_iter=100, tol=1e-12):
     plen = int(L_.load().lnv_partials_len(max(system.pL.struct.n_items,
                                               system.pL.struct.n_cl_items)))
     part = torch.zeros(plen, dtype=torch.float64, device=dev)
-    sc = torch.zeros(L_.PM_NSCALARS, dtype=torch.float64, device=dev)
-    hist_d = torch.zeros(4 * max(1, n_iter), dtype=torch.float64, device=dev)
+    sc = torch.zeros(ncell, L_.PM_NSCALARS, dtype=torch.float64, device=dev)
+    hist_d = torch.zeros(ncell, 4 * max(1, n_iter), dtype=torch.float64, device=dev)
     ws = L_.LnvPmWs()
     ws.SK = system.SL.struct                      # S.K on pat(S.L)
     ws.K2, ws.K3, ws.KT = K2.data_ptr(), K3.data_ptr(), KT.data_ptr()
@@ -74,17 +79,30 @@ def pm_initial_L(system, n_iter=100, tol=1e-12):
     ws.partials, ws.partials_len = part.data_ptr(), plen
     ws.scalars, ws.hist, ws.hist_len = sc.data_ptr(), hist_d.data_ptr(), int(n_iter)
     HT = Matrix(_pattern_HL(system))             # H.T on pat(H.L), dropped after use
-    L_.call("lnv_pm_start", ctypes.byref(K.struct), ctypes.byref(T.struct), ctypes.byref(H.struct),
-            ctypes.byref(HT.struct), n, float(system.n_elec), ctypes.byref(ws), _stream())
-    for _ in range(n_iter):
-        L_.call("lnv_pm_step", ctypes.byref(K.struct), ctypes.byref(S.struct),
-                float(system.n_elec), float(tol), ctypes.byref(ws), _stream())
+    ref = ctypes.byref
+    if batch:
+        b = ref(system.batch())
+        L_.call("lnv_pm_start_batch", ref(K.struct), ref(T.struct), ref(H.struct), ref(HT.struct),
+                b, ref(ws), _stream())
+        for _ in range(n_iter):
+            L_.call("lnv_pm_step_batch", ref(K.struct), ref(S.struct), b, float(tol), ref(ws),
+                    _stream())
+    else:
+        L_.call("lnv_pm_start", ref(K.struct), ref(T.struct), ref(H.struct), ref(HT.struct), n,
+                float(system.n_elec), ref(ws), _stream())
+        for _ in range(n_iter):
+            L_.call("lnv_pm_step", ref(K.struct), ref(S.struct), float(system.n_elec),
+                    float(tol), ref(ws), _stream())
     system.L.val.copy_(K.val)
     v = sc.cpu().numpy()
-    h = hist_d.cpu().numpy().reshape(-1, 4)
+    h = hist_d.cpu().numpy().reshape(ncell, -1, 4)
     del HT
-    hist = [dict(c=None if np.isnan(r[0]) else float(r[0]), t1=float(r[1]), t2=float(r[2]),
-                 t3=float(r[3])) for r in h[:int(v[L_.PM["STEPS"]])]]
     assert K.val.shape[1] == BLK
-    return hist, dict(mu=float(v[L_.PM["MU"]]), b=float(v[L_.PM["B"]]),
-                      lam=float(v[L_.PM["LAMBDA"]]))
+    hists, infos = [], []
+    for c in range(ncell):
+        hists.append([dict(c=None if np.isnan(r[0]) else float(r[0]), t1=float(r[1]),
+                           t2=float(r[2]), t3=float(r[3]))
+                      for r in h[c][:int(v[c, L_.PM["STEPS"]])]])
+        infos.append(dict(mu=float(v[c, L_.PM["MU"]]), b=float(v[c, L_.PM["B"]]),
+                          lam=float(v[c, L_.PM["LAMBDA"]])))
+    return (hists, infos) if batch else (hists[0], infos[0])

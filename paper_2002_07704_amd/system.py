@@ -561,8 +561,13 @@ class LNVSystem:
                 self.ws.Fc = self.Fc.val.data_ptr()
                 self.ws.gc = self.gc.data_ptr()
                 self._bufs[self.gc.data_ptr()] = self.gc
-            L_.call("lnv_hotelling", byref(self.S.struct), byref(self.T.struct),
-                    int(n_hotelling), byref(self.ws), _stream())
+            if self.cells is not None:
+                # each cell's own sigma, the products for all cells at once
+                L_.call("lnv_hotelling_batch", byref(self.S.struct), byref(self.T.struct),
+                        int(n_hotelling), byref(self.batch()), byref(self.ws), _stream())
+            else:
+                L_.call("lnv_hotelling", byref(self.S.struct), byref(self.T.struct),
+                        int(n_hotelling), byref(self.ws), _stream())
         self.opts = Opts()
         self.k = 0
         self.adj_ws = None
@@ -1111,6 +1116,9 @@ class LNVSystem:
             self._val_ptr = torch.as_tensor(16 * rp[self.cell_rows], device=self.dev)
             self._n_elec_cells = torch.as_tensor(
                 np.array([c.n_elec for c in self.cells], dtype=np.float64), device=self.dev)
+            self._n_orb_cells = torch.as_tensor(
+                np.array([float(np.sum(c.nfun)) for c in self.cells], dtype=np.float64),
+                device=self.dev)
             self.cell_scalars = torch.zeros(len(self.cells), L_.NSCALARS, dtype=torch.float64,
                                             device=self.dev)
             b = L_.LnvBatch()
@@ -1120,15 +1128,17 @@ class LNVSystem:
             b.row_cell = self.cell_of.data_ptr()
             b.n_elec = self._n_elec_cells.data_ptr()
             b.scalars = self.cell_scalars.data_ptr()
+            b.row_off = self.cell_start.data_ptr()
+            b.n_orb = self._n_orb_cells.data_ptr()
             self._batch = b
         return self._batch
 
     def cg_init(self):
-        """L0 = lambda T (lnv_cg_init); for a batch of cells lambda_c I per cell
-        (lnv_cg_init_batch)."""
+        """L0 = lambda T (lnv_cg_init; T = I without a metric); for a batch of
+        cells lambda_c T per cell (lnv_cg_init_batch)."""
         self._need_cg()
         if self.cells is not None:
-            L_.call("lnv_cg_init_batch", byref(self.L.struct), byref(self.S.struct),
+            L_.call("lnv_cg_init_batch", byref(self.L.struct), byref(self.S.struct), self._T(),
                     byref(self.batch()), byref(self.ws), _stream())
         else:
             L_.call("lnv_cg_init", byref(self.L.struct), byref(self.S.struct), self._T(),
@@ -1139,11 +1149,16 @@ class LNVSystem:
         """Start a new minimisation from the current L (e.g. a purified start):
         the next step is iteration 0 (steepest descent, no history) with the
         status bits cleared."""
-        self.scalars[L_.SC["STATUS"]] = 0.0
-        self.scalars[L_.SC["FORCE_RESET"]] = 0.0
-        self.scalars[L_.SC["E_PREV"]] = float("nan")
-        self.scalars[L_.SC["RISES"]] = 0.0
-        self.scalars[L_.SC["GUARD_K"]] = -1e9
+        blocks = [self.scalars]
+        if self.cells is not None:
+            self.batch()
+            blocks = [self.cell_scalars[c] for c in range(len(self.cells))]
+        for sc in blocks:
+            sc[L_.SC["STATUS"]] = 0.0
+            sc[L_.SC["FORCE_RESET"]] = 0.0
+            sc[L_.SC["E_PREV"]] = float("nan")
+            sc[L_.SC["RISES"]] = 0.0
+            sc[L_.SC["GUARD_K"]] = -1e9
         self.ws.ev.carry = 0
         self.k = 0
 
@@ -1169,12 +1184,12 @@ class LNVSystem:
         o = L_.LnvOpts(self.opts.reset_period, self.opts.n_tol, self.opts.step_cap, None,
                        int(self.opts.occ_every), int(self.opts.occ_iter))
         if self.cells is not None:
-            # every cell minimised at once, its own scalars (identity metric, FP64)
+            # every cell minimised at once with its own scalars (FP64)
             if self.opts.mixed:
                 raise NotImplementedError("a batch of cells is minimised in FP64")
             L_.call("lnv_cg_step_batch", byref(self.L.struct), byref(self.S.struct),
-                    byref(self.H.struct), byref(self.batch()), self.k, byref(o), byref(self.ws),
-                    _stream())
+                    byref(self.H.struct), self._T(), byref(self.batch()), self.k, byref(o),
+                    byref(self.ws), _stream())
             self.k += 1
             return
         if self.opts.mixed:

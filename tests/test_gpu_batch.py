@@ -174,3 +174,59 @@ def test_batch_cg_uneven_cells(gpu):
     functions, atoms split over 4x4-blocked rows), 6 iterations."""
     cells = W.batch_cells("b6", 6, seed=9, n_lo=16, n_hi=48)
     _batch_cg_against_oracle(cells, 6)
+
+
+def test_batch_hotelling_purification_cg(gpu):
+    """Four truncated diamond cells (64, 24, 48 and 32 atoms) as one batch in
+    the Hotelling metric: each cell's T (its own sigma), its canonical
+    purification (every step's c and traces, the stopping step) and 8 CG
+    iterations from its purified start (E, N, mu, beta, alpha, delta per
+    iteration) against the oracle of that cell alone; final L per cell."""
+    from paper_2002_07704_amd.pm import pm_initial_L
+    from paper_2002_07704_amd.system import LNVSystem
+    from oracle import pm as opm
+    cells = [W.diamond_workload("d64", (2, 2, 2), seed=1),
+             W.diamond_workload("d24", (3, 1, 1), seed=23),
+             W.diamond_workload("d48", (3, 2, 1), seed=25),
+             W.diamond_workload("d32", (4, 1, 1), seed=28)]
+    steps = 8
+    sysg = LNVSystem(cells, metric="hotelling", n_hotelling=16)
+    hists, infos = pm_initial_L(sysg, 60)
+    sysg.cg_restart()
+    refs = []
+    for c, cw in enumerate(cells):
+        ref = ost.System(cw)
+        T = olnv.hotelling(ref.S, ref.maskL, 16)
+        Tg = _cell_dense(sysg, sysg.T.val, sysg.pL, c, cw)
+        assert np.abs(Tg - T).max() <= 1e-13 * np.abs(T).max(), c
+        K, ho, info = opm.purify(ref.S, ref.H, T, ref.maskL, cw.n_elec, 60)
+        assert abs(infos[c]["lam"] - info["lam"]) <= 1e-13 * abs(info["lam"]), c
+        assert len(hists[c]) == len(ho), (c, len(hists[c]), len(ho))
+        for k, (a, b) in enumerate(zip(hists[c], ho)):
+            for key in ("t1", "t2", "t3"):
+                assert abs(a[key] - b[key]) <= 1e-10 * abs(b[key]), (c, k, key)
+            assert (a["c"] is None) == (b["c"] is None), (c, k)
+            if b["c"] is not None:
+                assert abs(a["c"] - b["c"]) <= 1e-9 + 1e-13 * b["t1"] / (b["t1"] - b["t2"]), (c, k)
+        Kg = _cell_dense(sysg, sysg.L.val, sysg.pL, c, cw)
+        assert np.abs(Kg - K).max() <= 1e-10 * np.abs(K).max(), c
+        Lo, hist = olnv.cg(ref.S, ref.H, ref.maskL, cw.n_elec, steps, L0=K, T=T)
+        refs.append((hist, Lo))
+    for k in range(steps):
+        sysg.cg_step()
+        scs = sysg.cell_scalars_host()
+        for c, cw in enumerate(cells):
+            sc, h = scs[c], refs[c][0][k]
+            print(f"k={k} cell {c} ({cw.n} atoms) E/atom gpu {sc['E'] / cw.n:.13f} oracle "
+                  f"{h['E'] / cw.n:.13f} alpha {sc['ALPHA']:.6e} delta {sc['DELTA']:.3e} "
+                  f"status {int(sc['STATUS'])}", flush=True)
+            assert abs(sc["E"] - h["E"]) / cw.n <= 1e-10, (k, c)
+            assert abs(sc["N"] - h["N"]) <= 1e-9 * max(1.0, cw.n_elec / 64), (k, c)
+            assert abs(sc["MU"] - h["mu"]) <= 1e-9 * max(1.0, abs(h["mu"])), (k, c)
+            assert abs(sc["BETA"] - h["beta"]) <= 1e-7, (k, c)
+            assert abs(sc["ALPHA"] - h["alpha"]) <= 1e-8 * abs(h["alpha"]), (k, c)
+            assert abs(sc["DELTA"] - h["delta"]) <= 1e-8 * max(abs(h["delta"]), 1e-6), (k, c)
+            assert int(sc["STATUS"]) == 0, (k, c)
+    for c, cw in enumerate(cells):
+        Lg = _cell_dense(sysg, sysg.L.val, sysg.pL, c, cw)
+        assert np.abs(Lg - refs[c][1]).max() <= 1e-9, c
