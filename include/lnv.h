@@ -412,7 +412,13 @@ int lnv_synth_blocks(const double* pos, const double* box, const int32_t* nfun,
 /* ------------------------------------------------------------ a3: multiply
  * lnv_bsm_multiply -- C = alpha * A * op(B) + beta * C on C's pattern only
  * (blocks of the product outside C's pattern are not formed: a range
- * truncated product).  op(B) = B (transB = 0) or B^T (transB = 1).  These
+ * truncated product).  op(B) = B (transB = 0) or B^T (transB = 1); with
+ * transB = 2, B is symmetric and B.val holds only the blocks of its half
+ * (B on a pattern from lnv_pattern_half, with its index): blocks outside the
+ * half are read as the transposes of their mirror blocks.  transB = 2 runs on
+ * the atom-tile path only (16-row cluster plans on A and C, tile4 patterns,
+ * FP64 or all-FP32 storage); elsewhere, and for lnv_bsm_multiply_dot, it
+ * returns LNV_EUNSUPPORTED.  These
  * are the sparse matrix products of Sec. II.C.2: with every matrix range
  * truncated, each product costs a bounded number of block triples per row,
  * so its cost is linear in the number of atoms.

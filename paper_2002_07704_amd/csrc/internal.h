@@ -209,6 +209,10 @@ int mirror_launch(const lnv_bsm* U, const lnv_bsm* C, hipStream_t s,
 // of A goes, transposed, to position perm[p] (lnv_pattern_transpose_map).
 int transpose_values(const lnv_bsm* A, const int32_t* perm, void* AT, hipStream_t s);
 
+// Whether multiply_launch takes transB = 2 (B symmetric, its half stored)
+// for these operands with store and no traces: the atom-tile path.
+bool half_b_ok(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C);
+
 // Number of dot partials (work items) multiply_launch writes for C.
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C);
 

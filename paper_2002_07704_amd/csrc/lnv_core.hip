@@ -451,7 +451,7 @@ __global__ __launch_bounds__(256) void k_assemble(
     const T* __restrict__ XT, const T* __restrict__ YT,
     const T* __restrict__ Wv, Ix zx,
     const T* __restrict__ Z, const T* __restrict__ V, double* __restrict__ G,
-    double* __restrict__ F, double* __restrict__ partials) {
+    double* __restrict__ F, double* __restrict__ partials, int zhalf) {
   __shared__ double sh[16];
   const int item = blockIdx.x;
   const int i = items[2 * item], c0 = items[2 * item + 1];
@@ -466,7 +466,9 @@ __global__ __launch_bounds__(256) void k_assemble(
     const int xtp = XT ? ix_find(xtx, i, j) : ix_find(xx, j, i);
     const T* __restrict__ xtv = XT ? XT : X;
     const int ytp = ix_find(lx, j, i);
-    const int zp = ix_find(zx, i, j);
+    // zhalf: Z holds the blocks of its half (in_half) only, Z_ij = Z_ji^T
+    const bool zt = zhalf && !in_half(n, i, j);
+    const int zp = zt ? ix_find(zx, j, i) : ix_find(zx, i, j);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int e = r * 4 + c, et = c * 4 + r;
@@ -475,7 +477,7 @@ __global__ __launch_bounds__(256) void k_assemble(
       const double yt = (double)YT[(size_t)p * 16 + e];
       const double ytt = ytp >= 0 ? (double)YT[(size_t)ytp * 16 + et] : 0.0;
       const double w = (double)Wv[(size_t)p * 16 + e];
-      const double z = zp >= 0 ? (double)Z[(size_t)zp * 16 + e] : 0.0;
+      const double z = zp >= 0 ? (double)Z[(size_t)zp * 16 + (zt ? et : e)] : 0.0;
       const double v = (double)V[(size_t)p * 16 + e];
       const double l = L[(size_t)p * 16 + e];
       const double g = 2.0 * (3.0 * (x + xt) - 2.0 * (yt + ytt + w));
@@ -1186,11 +1188,25 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
   // their halves when the workspace carries them); YT = P_L(SLSLH) is not
   const lnv_bsm* Lu = o.Lu;
   lnv_bsm Vu{Lu ? Lu->pat : nullptr, 4, dt, o.Vu};
-  if (!o.Zcarry) LNV_TRY(sym_product(o.S, LSop, o.Z, o.Zu, s, tb));
+  // on the atom tiles, Z formed afresh stays on its half: V reads it there
+  // (transB = 2) and so does the assembly, and Z is never filled in full
+  const bool zhalf = lean && !o.Zcarry && Lu && o.Vu && sym_ready(o.Zu, o.Z) &&
+                     sym_ready(&Vu, &Vm) && half_b_ok(o.SL, o.Zu, &Vu);
+  if (zhalf)
+    LNV_TRY(multiply_launch(1.0, o.S, LSop, tb, 0.0, o.Zu, 1, nullptr, nullptr, nullptr, nullptr,
+                            s));
+  else if (!o.Zcarry)
+    LNV_TRY(sym_product(o.S, LSop, o.Z, o.Zu, s, tb));
   if (!lean) LNV_TRY(transpose_launch(o.X, o.perm_X, o.XT->val, s));
   LNV_TRY(multiply_launch(1.0, o.SL, XTop, tb, 0.0, &YT, 1, nullptr, nullptr, nullptr, nullptr,
                           s));
-  LNV_TRY(sym_product_pair(o.SL, o.X, &Wm, Lu, o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
+  if (zhalf) {
+    LNV_TRY(sym_product(o.SL, o.X, &Wm, Lu, s));
+    LNV_TRY(sym_product(o.SL, o.Zu, &Vm, &Vu, s, 2));
+  } else {
+    LNV_TRY(sym_product_pair(o.SL, o.X, &Wm, Lu, o.SL, o.Z, &Vm, Lu ? &Vu : nullptr, s));
+  }
+  const lnv_bsm* Zr = zhalf ? o.Zu : o.Z;
   const int ni = pl->n_items;
   double* part = o.partials;
   k_assemble<T><<<ni, 256, 0, s>>>(pl->n, ni, pl->items, pl->row_ptr, pl->col, make_ix(pl),
@@ -1199,8 +1215,8 @@ int eval_products(const lnv_bsm* L64, const EvalOps& o, double* G, double* F, do
                                    lean ? make_ix(o.X->pat) : make_ix(o.XT->pat),
                                    lean ? nullptr : static_cast<const T*>(o.XT->val),
                                    static_cast<const T*>(o.YT), static_cast<const T*>(o.W),
-                                   make_ix(o.Z->pat), static_cast<const T*>(o.Z->val),
-                                   static_cast<const T*>(o.V), G, F, part);
+                                   make_ix(Zr->pat), static_cast<const T*>(Zr->val),
+                                   static_cast<const T*>(o.V), G, F, part, zhalf ? 1 : 0);
   LNV_LAUNCH_CHECK();
   RedList rl = reds();
   add(rl, 0 * (int64_t)ni, ni, 1, LNV_SC_T0, 0, RK_ITEMS);

@@ -490,6 +490,10 @@ __device__ __forceinline__ void split_f16(const float (&x)[4], f16x4_t& hi, f16x
 // matrix B': B[4c + w][i] = B'[i][4c + w], row i of the tile (j, k) of B',
 // a 4-value row of its block (i>>2, c); lenB then holds, per column atom q,
 // the row length of that atom in B' (lenBq), else lenB is the step's.
+// TB = 2: B is symmetric and stored as the blocks of its half (in_half):
+// tile (k, j_q) is read as stored when (k, j_q) is in the half and as the
+// transpose of tile (j_q, k) otherwise (bit q of tmask), each in the layout
+// above.
 template <typename T>
 __device__ __forceinline__ void tile_load_a(T (&a)[4][4], const int (&pa)[4],
                                             const T* __restrict__ a_val, const int (&rowA)[4],
@@ -506,10 +510,10 @@ __device__ __forceinline__ void tile_load_a(T (&a)[4][4], const int (&pa)[4],
 template <int NB, int TB, typename T>
 __device__ __forceinline__ void tile_load_b(T (&b)[NB][4], const int (&pb)[NB], int lenB,
                                             const int (&lenBq)[NB], const T* __restrict__ b_val,
-                                            int li, int lq, int bmax) {
+                                            int li, int lq, int bmax, int tmask = 0) {
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    if constexpr (TB) {
+    if (TB == 1 || (TB == 2 && ((tmask >> q) & 1))) {
       const int blk = min(max(pb[q], 0) + (li >> 2) * lenBq[q] + lq, bmax);
       const T* bp = b_val + (size_t)blk * 16 + (li & 3) * 4;
 #pragma unroll
@@ -528,9 +532,9 @@ __device__ __forceinline__ void tile_load(T (&a)[4][4], T (&b)[NB][4], const int
                                           const int (&pb)[NB], int lenB, const int (&lenBq)[NB],
                                           const T* __restrict__ a_val,
                                           const T* __restrict__ b_val, const int (&rowA)[4],
-                                          int li, int lq, int amax, int bmax) {
+                                          int li, int lq, int amax, int bmax, int tmask) {
   tile_load_a<T>(a, pa, a_val, rowA, li, lq, amax);
-  tile_load_b<NB, TB, T>(b, pb, lenB, lenBq, b_val, li, lq, bmax);
+  tile_load_b<NB, TB, T>(b, pb, lenB, lenBq, b_val, li, lq, bmax, tmask);
 }
 
 // Products of one step on the matrix cores: act bit 4q + ar set where A's
@@ -586,7 +590,7 @@ __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
 // step's atom, the pairs to multiply (tile_mma).
 template <int NB>
 struct TileStep {
-  int pa[4], pb[NB], lenB, act;
+  int pa[4], pb[NB], lenB, act, tmask;
 };
 
 // Atom-tile multiply on the matrix cores.  A wave owns one piece: the 4
@@ -644,7 +648,7 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
     jb[q] = jr >> 2;
     jcell[q] = ok ? bx.cell[jb[q]] : -1;
     jslot[q] = bx.slot[jb[q]];
-    lenBq[q] = TB ? bx.rp[jr + 1] - bx.rp[jr] : 0;
+    lenBq[q] = TB ? bx.rp[jr + 1] - bx.rp[jr] : 0;   // TB = 2: B's own rows (B = B')
   }
   int rowA[4];
 #pragma unroll
@@ -667,7 +671,7 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
 
   // this lane's step of the current chunk (positions as in TileStep) and the
   // chunk's kept steps not yet taken
-  int cpa[4], cpb[NB], clen = 0, cact = 0;
+  int cpa[4], cpb[NB], clen = 0, cact = 0, ctr = 0;
   uint64_t rem = 0;
   int base = -64;
   auto scan = [&]() {
@@ -677,17 +681,20 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
     const int ck = ka_key[2 * (size_t)t], sk = ka_key[2 * (size_t)t + 1];
 #pragma unroll
     for (int ar = 0; ar < 4; ++ar) cpa[ar] = ka_pos[(size_t)t * 16 + 4 * ar];
-    clen = TB ? 0 : bx.rp[kk + 1] - bx.rp[kk];
-    int act = 0;
+    clen = TB == 1 ? 0 : bx.rp[kk + 1] - bx.rp[kk];
+    int act = 0, tr = 0;
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
-      // tile (k, j_q) of B, TB: tile (j_q, k) of B'; the index's trailing -1
-      // outside the window
+      // tile (k, j_q) of B, TB = 1: tile (j_q, k) of B'; TB = 2: the stored
+      // one of the pair (the half's); the index's trailing -1 outside the
+      // window
+      const bool tq = TB == 1 || (TB == 2 && !in_half(n, kk, 4 * jb[q]));
+      tr |= (int)tq << q;
       const int o = jcell[q] < 0 ? -1
-                    : TB         ? ix_off(bx, jcell[q], ck, sk)
+                    : tq         ? ix_off(bx, jcell[q], ck, sk)
                                  : ix_off(bx, ck, jcell[q], jslot[q]);
       const int* src = o < 0 ? bx.tab + bx.sent
-                             : bx.tab + (size_t)(TB ? jb[q] : kk >> 2) * bx.stride + o;
+                             : bx.tab + (size_t)(tq ? jb[q] : kk >> 2) * bx.stride + o;
       cpb[q] = *src;
 #pragma unroll
       for (int ar = 0; ar < 4; ++ar)
@@ -695,6 +702,7 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
           act |= 1 << (4 * q + ar);
     }
     cact = act;
+    ctr = tr;
     rem = __ballot(base + lane < nsteps && act != 0);
   };
   // the next kept step (false past the list's end: e then names no tile,
@@ -709,6 +717,7 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
         for (int q = 0; q < NB; ++q) e.pb[q] = -1;
         e.lenB = 0;
         e.act = 0;
+        e.tmask = 0;
         return false;
       }
       scan();
@@ -721,6 +730,7 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
     for (int q = 0; q < NB; ++q) e.pb[q] = __builtin_amdgcn_readlane(cpb[q], m);
     e.lenB = __builtin_amdgcn_readlane(clen, m);
     e.act = __builtin_amdgcn_readlane(cact, m);
+    e.tmask = TB == 2 ? __builtin_amdgcn_readlane(ctr, m) : 0;
     return true;
   };
 
@@ -737,15 +747,15 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
     TileStep<NB> e0, e1;
     if (next(e0)) {
       tile_load_a<T>(fa, e0.pa, a_val, rowA, li, lq, amax);
-      tile_load_b<NB, TB, T>(fb0, e0.pb, e0.lenB, lenBq, b_val, li, lq, bmax);
+      tile_load_b<NB, TB, T>(fb0, e0.pb, e0.lenB, lenBq, b_val, li, lq, bmax, e0.tmask);
       for (;;) {
         const bool h1 = next(e1);
-        tile_load_b<NB, TB, T>(fb1, e1.pb, e1.lenB, lenBq, b_val, li, lq, bmax);
+        tile_load_b<NB, TB, T>(fb1, e1.pb, e1.lenB, lenBq, b_val, li, lq, bmax, e1.tmask);
         tile_mma<MODE, NB>(acc, fa, fb0, e0.act);
         tile_load_a<T>(fa, e1.pa, a_val, rowA, li, lq, amax);
         if (!h1) break;
         const bool h0 = next(e0);
-        tile_load_b<NB, TB, T>(fb0, e0.pb, e0.lenB, lenBq, b_val, li, lq, bmax);
+        tile_load_b<NB, TB, T>(fb0, e0.pb, e0.lenB, lenBq, b_val, li, lq, bmax, e0.tmask);
         tile_mma<MODE, NB>(acc, fa, fb1, e1.act);
         tile_load_a<T>(fa, e0.pa, a_val, rowA, li, lq, amax);
         if (!h0) break;
@@ -756,19 +766,19 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
     TileStep<NB> e0, e1;
     if (next(e0)) {
       tile_load<NB, TB, T>(fa0, fb0, e0.pa, e0.pb, e0.lenB, lenBq, a_val, b_val, rowA, li, lq,
-                           amax, bmax);
+                           amax, bmax, e0.tmask);
       // two kept steps per turn, fragments double-buffered; the loads of the
       // step after the one multiplied are issued first (unconditionally, so
       // the wait before each product covers the older loads only)
       for (;;) {
         const bool h1 = next(e1);
         tile_load<NB, TB, T>(fa1, fb1, e1.pa, e1.pb, e1.lenB, lenBq, a_val, b_val, rowA, li,
-                             lq, amax, bmax);
+                             lq, amax, bmax, e1.tmask);
         tile_mma<MODE, NB>(acc, fa0, fb0, e0.act);
         if (!h1) break;
         const bool h0 = next(e0);
         tile_load<NB, TB, T>(fa0, fb0, e0.pa, e0.pb, e0.lenB, lenBq, a_val, b_val, rowA, li,
-                             lq, amax, bmax);
+                             lq, amax, bmax, e0.tmask);
         tile_mma<MODE, NB>(acc, fa1, fb1, e1.act);
         if (!h0) break;
       }
@@ -830,6 +840,8 @@ KernelT16Fn<T> pick_t16(int store, int ndot) {
 
 template <int NB, int MODE, typename T>
 KernelT16Fn<T> pick_t16_tb(int transB, int store, int ndot) {
+  if (transB == 2)   // B symmetric, stored as its half: stored products only
+    return store && ndot == 0 ? k_tile16<NB, MODE, 2, 1, 0, T> : nullptr;
   return transB ? pick_t16<NB, MODE, 1, T>(store, ndot) : pick_t16<NB, MODE, 0, T>(store, ndot);
 }
 
@@ -941,6 +953,12 @@ bool use_tiles(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C)
          pb->nnzb < INT32_MAX;
 }
 
+bool half_b_ok(const lnv_bsm* A, const lnv_bsm* B, const lnv_bsm* C) {
+  return bsm_ok_any(A) && bsm_ok_any(B) && bsm_ok_any(C) && A->dtype == C->dtype &&
+         B->dtype == C->dtype && A->blk == 4 && B->blk == 4 && C->blk == 4 &&
+         A->pat->n == B->pat->n && A->pat->n == C->pat->n && use_tiles(A, B, 2, C);
+}
+
 int multiply_nparts(const lnv_bsm* A, const lnv_bsm* B, int transB, const lnv_bsm* C) {
   if (A->dtype != C->dtype) return C->pat->n_items;  // FP32 into FP64: row kernel
   return use_clustered(A, B, transB, C) || use_tiles(A, B, transB, C) ? C->pat->n_cl_items
@@ -967,7 +985,7 @@ int launch_tiles(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB, d
   const bool nb4 = pc->cl_g == 4;  // 4 column atoms per wave (cl_g 8: 2)
   KernelT16Fn<T> fn = nullptr;
   const int mode = tile_mode<T>();
-  const int tb = transB ? 1 : 0;
+  const int tb = transB;
   if (mode == TM_F64) {
     fn = nb4 ? pick_t16_tb<4, TM_F64, T>(tb, store, ndot)
              : pick_t16_tb<2, TM_F64, T>(tb, store, ndot);
@@ -1131,6 +1149,10 @@ int multiply_launch(double alpha, const lnv_bsm* A, const lnv_bsm* B, int transB
   if (m2 && !m1) return LNV_EINVAL;
   if (ndot > 0 && !partials) return LNV_EINVAL;
   if (!store && ndot == 0) return LNV_EINVAL;
+  if (transB < 0 || transB > 2) return LNV_EINVAL;
+  // B symmetric and stored as its half: atom tiles only (a tile4 half keeps
+  // or drops whole atom tiles), stored products without dots
+  if (transB == 2 && (mix || !use_tiles(A, B, transB, C) || ndot > 0)) return LNV_EUNSUPPORTED;
   if (mix) return launch_mix(alpha, A, B, transB, beta, C, store, m1, m2, partials, skip, ndot, s);
   if (C->dtype == LNV_F32) {
     if (g_f32_acc == LNV_ACC_F64)

@@ -129,6 +129,37 @@ def test_tile_eval_matches_oracle(cells, name, shape):
     s.set_cluster((4, 1))
 
 
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("name", ["si64_13b", "am22_13", "one13"])
+def test_tile_half_symmetric_operand(cells, name, shape):
+    """transB = 2: the symmetric S.L.S given by the blocks of its half only
+    (Z's half pattern), read as stored inside the half and transposed outside
+    it.  S.L times it on L's pattern against the oracle's P_L(S L S L S) and
+    against the product with the full S.L.S; outside the atom tiles the
+    half operand is refused."""
+    from paper_2002_07704_amd.system import Matrix, multiply
+    s, ref, lay = cells[name]
+    Ld = _seeded_L(s, ref, lay, 7)
+    s.set_cluster(shape)
+    s.eval()                                  # S.L, and S.L.S in full and on its half
+    torch.cuda.synchronize()
+    Vh, Vf = Matrix(s.pL), Matrix(s.pL)
+    multiply(1.0, s.SL, s.Zu, 2, 0.0, Vh)
+    multiply(1.0, s.SL, s.Z, 0, 0.0, Vf)
+    torch.cuda.synchronize()
+    Sd = ref.S
+    Vr = (Sd @ Ld @ Sd @ Ld @ Sd) * ref.maskL
+    V = lay.to_dense(Vh.val, s.pL)
+    err = np.abs(V - Vr).max() / np.abs(Vr).max()
+    print(f"{name} {shape}: half operand vs oracle {err:.2e}", flush=True)
+    assert err <= 1e-12
+    assert (Vh.val - Vf.val).abs().max() <= 1e-13 * Vf.val.abs().max()
+    s.set_cluster((4, 1))
+    with pytest.raises(L_.LnvError) as e:
+        multiply(1.0, s.SL, s.Zu, 2, 0.0, Vh)
+    assert e.value.status == L_.EUNSUPPORTED
+
+
 @pytest.mark.parametrize("name", ["si64_13", "si64_13b"])
 def test_tile_cg_trajectory(cells, name):
     s, ref, lay = cells[name]
