@@ -4,19 +4,20 @@ Headline workload (the largest configuration, the one the FP64-vs-mixed
 metric is about): 32768-atom periodic diamond-Si cell (16x16x16 conventional
 cubes, a = 10.26 bohr, +-0.1 bohr seeded displacements), 13 support
 functions per atom stored as 4 rows of 4 (16x16 padded atom tiles, 425984
-orbitals, 131072 block rows), ranges S/H/L = 12/14/10 bohr, products at
-natural range, rows in groups of four bonded atoms.  Set-up per geometry
+orbitals, 131072 block rows), ranges S/H/L = 12/14/10 bohr, H.L.S and
+S.L.S formed within R_S + 2 R_L = 32 bohr (every entry that the products
+onto L's range read), rows in groups of four bonded atoms.  Set-up per geometry
 (not timed): neighbour lists, synthetic S and H, symbolic products, spatial
 index, Hotelling metric, canonical-purification start.  One step = one
 energy + gradient evaluation at that L: E, N, G = dE/dL and F = dN/dL from
-the six block-sparse products (S.L, H.L.S and the half of S.L.S at natural
-range; L-restricted S.L.S.L.H, halves of S.L.H.L.S and S.L.S.L.S) on the
+the six block-sparse products (S.L, H.L.S and the half of S.L.S within 32
+bohr; L-restricted S.L.S.L.H, halves of S.L.H.L.S and S.L.S.L.S) on the
 atom tiles and their FP64 assembly and traces.  `value` is FP64 evaluations
 per second (FP64 matrix-core tiles); the same evaluation with FP32 MFMA and
 with the FP16 hi/lo split is timed beside it, with its energy, electron
 number and gradient errors against the FP64 evaluation at the same L (the
 1e-6 Ha/atom gate).  The system is "lean" (no stored L.S and X^T, FP32
-intermediates in the FP64 ones' memory): both orientations of the natural
+intermediates in the FP64 ones' memory): both orientations of the
 intermediates would not fit in the GPU's memory.
 
 `si4096_cg` reports the 4096-atom, 4-function cell (the plain-FP64 workload
@@ -373,7 +374,7 @@ def bench_headline(args, lib):
             "workload": f"{w.name}: {w.n}-atom diamond Si (16x16x16 cubes), 13 support "
                         f"functions/atom as 16x16 padded atom tiles ({w.n_orb} orbitals, "
                         f"{s.n_rows} block rows), R_S/R_H/R_L {w.R_S:g}/{w.R_H:g}/{w.R_L:g} "
-                        f"bohr, natural-range products",
+                        f"bohr, H.L.S and S.L.S within R_S + 2 R_L",
             "step": "one energy+gradient evaluation (E, N, G = dE/dL, F = dN/dL: six block-sparse "
                     "products on the FP64 atom tiles, FP64 assembly and traces) at the purified L",
             "row_order": "bonds", "tile_shape": str(shape64), "lean": True,

@@ -539,8 +539,10 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
 
 /* ------------------------------------------------------------ a4: evaluation
  * Intermediates of one evaluation.  With A = LS (stored in both orientations,
- * SL and LS), X = HLS (stored with its transpose XT) and Z = SLS at their
- * natural ranges:
+ * SL and LS), X = HLS (stored with its transpose XT) and Z = SLS on patterns
+ * that hold every entry the projections below read (X_kj and Z_kj with some
+ * i for which (i, k) is in pat(S.L) and (i, j) in L's pattern: the natural
+ * ranges, or those cut to atoms within R_S + 2 R_L of each other):
  *   E = 2 (3 <L, X> - 2 <L, P_L(X A)>)
  *   N = 2 (3 <L, Z> - 2 <L, P_L(A^T Z)>)
  *   G = dE/dL = 2 P_L[3 (X + X^T) - 2 (Y + Y^T + A^T X)],   Y = P_L(X A)
@@ -550,8 +552,9 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  *  SL  values on pat(S.L)   (pattern needs items; its index for the metric)
  *  LS  values on pat(L.S)   (pattern needs its index)
  *  X   values on pat(H.L.S) (pattern needs its index and items)
- *  XT  values on pat(S.L.H) (pattern needs its index)
+ *  XT  values on X's pattern transposed (pattern needs its index)
  *  Z   values on pat(S.L.S) (pattern needs its index and items)
+ *  (pat(.) above: either range, the same cut for X, XT and Z)
  *  perm_SL, perm_X  transpose maps SL -> LS and X -> XT
  * Every operand B of the products is read in its stored orientation: a
  * transposed read would gather 64 blocks from 64 distant rows per step.
@@ -559,7 +562,7 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  * perm_SL, perm_X are then not used): the products read S.L and X
  * transposed instead, which the atom-tile multiply does at full speed (a
  * tile is read as 16 rows either way) -- for cells of 13-function atoms
- * too large to hold both orientations of the natural-range intermediates.
+ * too large to hold both orientations of the intermediates.
  * lnv_cg_step needs them (scratch of the line search).
  *  YT, W, V  device [nnzb_L * 16]: P_L(SLSLH), P_L(SLHLS), P_L(SLSLS)
  *  partials  device [partials_len] scratch, partials_len >=

@@ -277,6 +277,13 @@ def neighbours(pos_dev, box, R):
     return Pattern(n, rp, col)
 
 
+def xz_range(R_S, R_L):
+    """Cutoff of the stored X = H.L.S and Z = S.L.S: the farthest pair that a
+    product onto L's range with S.L on the left reads, R_S + 2 R_L, with a
+    margin of 1e-9 relative for the rounding of the distances."""
+    return (float(R_S) + 2.0 * float(R_L)) * (1.0 + 1e-9)
+
+
 def product_pattern(A, B, mask=None, triples=True):
     """a2: pattern of A.B (natural range) or of P_mask(A.B), with triple count."""
     n = A.n
@@ -427,12 +434,21 @@ class LNVSystem:
             self._layout_cells(self.cells, R_L)
         else:
             self._layout_single(w, R_L, reorder, grid)
-        # a2: natural product patterns (A = LS is stored as its transpose SL)
+        # a2: product patterns (A = LS is stored as its transpose SL).  X =
+        # H.L.S and Z = S.L.S are read only by products onto L's range with
+        # S.L on the left, and by L's own blocks: entry (k, j) is read when
+        # some i has (i, k) in S.L and (i, j) in L, so the distance of k and
+        # j is at most R_S + 2 R_L (triangle inequality over the nearest
+        # images).  Both are formed on that ball within their natural range
+        # (a margin of 1e-9 relative covers the rounding of the distances).
         self.pSL = product_pattern(self.pS, self.pL)            # S.L
         self.pLS = product_pattern(self.pL, self.pS, triples=False)   # L.S (row form of A)
-        self.pX = product_pattern(self.pH, self.pLS)            # H.L.S
-        self.pZ = product_pattern(self.pS, self.pLS)            # S.L.S
-        self.pXT = product_pattern(self.pSL, self.pH, triples=False)   # S.L.H = pat(X)^T
+        self.R_XZ = xz_range(self.R_S, self.R_L)
+        pM = self._range_pattern(self.R_XZ)
+        self.pX = product_pattern(self.pH, self.pLS, mask=pM)   # H.L.S
+        self.pZ = product_pattern(self.pS, self.pLS, mask=pM)   # S.L.S
+        self.pXT = product_pattern(self.pSL, self.pH, mask=pM, triples=False)   # pat(X)^T
+        del pM
         # lean: evaluation only, without the stored transposes L.S and X^T (the
         # atom-tile products read S.L and X transposed) and without the CG's
         # buffers -- for cells whose natural-range intermediates fill the GPU
@@ -818,9 +834,18 @@ class LNVSystem:
 
     def _index_ranges(self):
         """Ranges of the patterns that get a spatial index (S, H, L and the
-        natural-range products), for the choice of its grid."""
+        products), for the choice of its grid."""
         rs, rh, rl = self.R_S, self.R_H, self.R_L
-        return (rs, rh, rl, rs + rl, rh + rl + rs, 2 * rs + rl, 2 * rl, 2 * rl + rs, rh + rl)
+        rxz = rs + 2 * rl
+        return (rs, rh, rl, rs + rl, min(rh + rl + rs, rxz), min(2 * rs + rl, rxz), 2 * rl,
+                2 * rl + rs, rh + rl)
+
+    def _range_pattern(self, R):
+        """Range pattern of cutoff R over the system's rows (one cell, or
+        every cell of a batch on its own)."""
+        if self.cells is not None:
+            return self._neighbours_cells(R)
+        return neighbours(self.pos, self.box, R)
 
     def _neighbours_cells(self, R):
         n, nc = self.n_rows, len(self.cells)
@@ -1036,7 +1061,7 @@ class LNVSystem:
         if getattr(self, "_alg", None) is None:
             self._alg = {}
         up = self.pLu if self.symmetric else self.pL     # symmetric products: halves
-        specs = {"SL": (self.pS, self.pL, None), "X": (self.pH, self.pLS, None),
+        specs = {"SL": (self.pS, self.pL, None), "X": (self.pH, self.pLS, self.pX),
                  "Z": (self.pS, self.pLS, self.pZu), "YT": (self.pSL, self.pXT, self.pL),
                  "W": (self.pSL, self.pX, up), "V": (self.pSL, self.pZ, up),
                  "Vf": (self.pSL, self.pZ, self.pL), "Wf": (self.pSL, self.pX, self.pL)}

@@ -122,8 +122,12 @@ def test_product_patterns_and_triples(fx, request):
     Lp = ost.pattern_matrix(*ref.pat["L"], n)
     SL, tSL = ost.pattern_product(S, Lp)
     LS, _ = ost.pattern_product(Lp, S)
-    X, tX = ost.pattern_product(H, LS)
-    Z, tZ = ost.pattern_product(S, LS)
+    # X and Z within R_S + 2 R_L (what products onto L's range with S.L on
+    # the left read), margin 1e-9 relative
+    w = ref.w
+    M = ost.pattern_matrix(*ost.neighbours(w.pos, w.box, (w.R_S + 2 * w.R_L) * (1 + 1e-9)), n)
+    X, tX = ost.pattern_product(H, LS, M)
+    Z, tZ = ost.pattern_product(S, LS, M)
     for P, R in ((sysg.pSL, SL), (sysg.pX, X), (sysg.pZ, Z)):
         rp, col = P.host()
         assert np.array_equal(rp, R.indptr) and np.array_equal(col, R.indices)
