@@ -447,12 +447,10 @@ __global__ __launch_bounds__(256) void k_mul44c1(
 //            their products here).
 // Output tile: lane l = n + 16g holds column n, rows 4g..4g+3 (FP32
 // accumulators) or rows g, g+4, g+8, g+12 (FP64), as measured on gfx950.
-// Index pipeline (as in k_mul44c1): per step one vector load fetches, for two
-// steps ahead, the 4 cluster atoms' A positions (lanes 0-3), B's row pointers
-// of that step's k (lanes 4-5), the k of three steps ahead (lane 6) and the
-// NB B positions from B's index (lanes 8..); the fragments of the next step are
-// loaded before the current step's products, all unconditionally from clamped
-// positions, so the compiler's wait counts stay exact.
+// Steps: a ballot scan finds the steps with a pair to multiply, 64 at a time
+// (one step per lane, see k_tile16); the fragments of the next kept step are
+// loaded before the current step's products, all unconditionally from
+// clamped positions, so the compiler's wait counts stay exact.
 enum { TM_F32 = 0, TM_F64 = 1, TM_F16X3 = 2 };
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
@@ -788,20 +786,41 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
   // epilogue: lane (n + 16g) holds column n of each tile (column n&3 of
   // block n>>2), in register v the tile row 4g + v (FP32 accumulators) or
   // 4v + g (v_mfma_f64_16x16x4_f64), i.e. sub-row (row >> 2), row (row & 3)
-  // of that 4x4 block
+  // of that 4x4 block.  The output positions are loaded first, all at once
+  // (unconditionally, a missing tile reading the piece's first entry), so
+  // their latency is paid once per wave instead of once per element.
   const double sc = MODE == TM_F16X3 ? kF16Unscale : 1.0;
   const int g = lq, nn = li;
-  double d1 = 0.0, d2 = 0.0;
+  // FP64: the four sub-rows v of the lane's rows (4 consecutive entries);
+  // FP32 accumulators: sub-row g for every v
+  int opos[4][NB][MODE == TM_F64 ? 4 : 1];
 #pragma unroll
   for (int ar = 0; ar < 4; ++ar)
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
       const int e = p0 + 4 * q + (nn >> 2);
-      if (!((cmask >> (4 * q + ar)) & 1u) || e >= p0 + ncol) continue;
+      const bool ok = ((cmask >> (4 * q + ar)) & 1u) && e < p0 + ncol;
+      const int* src = jc_pos + (size_t)(ok ? e : p0) * 16 + 4 * ar;
+      if constexpr (MODE == TM_F64) {
+        const int4 v4 = *reinterpret_cast<const int4*>(src);
+        opos[ar][q][0] = ok ? v4.x : -1;
+        opos[ar][q][1] = ok ? v4.y : -1;
+        opos[ar][q][2] = ok ? v4.z : -1;
+        opos[ar][q][3] = ok ? v4.w : -1;
+      } else {
+        const int pp = src[g];
+        opos[ar][q][0] = ok ? pp : -1;
+      }
+    }
+  double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+  for (int ar = 0; ar < 4; ++ar)
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = MODE == TM_F64 ? 4 * v + g : 4 * g + v;
-        const int pos = jc_pos[(size_t)e * 16 + 4 * ar + (row >> 2)];
+        const int pos = opos[ar][q][MODE == TM_F64 ? v : 0];
         if (pos < 0) continue;
         const size_t at = (size_t)pos * 16 + (row & 3) * 4 + (nn & 3);
         const double val = alpha * (sc * (double)acc[ar][q][v]);
