@@ -493,16 +493,20 @@ __device__ __forceinline__ void split_f16(const float (&x)[4], f16x4_t& hi, f16x
 // transpose of tile (j_q, k) otherwise (bit q of tmask), each in the layout
 // above.
 template <typename T>
+__device__ __forceinline__ void tile_load_a_row(T (&a)[4], int pa, const T* __restrict__ a_val,
+                                                int rowA, int li, int lq, int amax) {
+  const int blk = min(max(pa, 0) + rowA + lq, amax);
+  const T* ap = a_val + (size_t)blk * 16 + (li & 3) * 4;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) a[w] = ap[w];
+}
+
+template <typename T>
 __device__ __forceinline__ void tile_load_a(T (&a)[4][4], const int (&pa)[4],
                                             const T* __restrict__ a_val, const int (&rowA)[4],
                                             int li, int lq, int amax) {
 #pragma unroll
-  for (int ar = 0; ar < 4; ++ar) {
-    const int blk = min(max(pa[ar], 0) + rowA[ar] + lq, amax);
-    const T* ap = a_val + (size_t)blk * 16 + (li & 3) * 4;
-#pragma unroll
-    for (int w = 0; w < 4; ++w) a[ar][w] = ap[w];
-  }
+  for (int ar = 0; ar < 4; ++ar) tile_load_a_row<T>(a[ar], pa[ar], a_val, rowA[ar], li, lq, amax);
 }
 
 template <int NB, int TB, typename T>
@@ -538,9 +542,18 @@ __device__ __forceinline__ void tile_load(T (&a)[4][4], T (&b)[NB][4], const int
 // Products of one step on the matrix cores: act bit 4q + ar set where A's
 // tile of cluster atom ar, B's tile of column atom q and the output tile all
 // exist (the other pairs are not multiplied).
-template <int MODE, int NB, typename T, typename AccT>
+// done(ar) runs once the products no longer read A's fragment ar (FP64 and
+// FP32: after its row of products; FP16 split: after all of them), so the
+// caller can load the next step's fragment into it while the later rows
+// multiply.
+struct NoRowDone {
+  __device__ void operator()(int) const {}
+};
+
+template <int MODE, int NB, typename T, typename AccT, typename RowDone = NoRowDone>
 __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
-                                         const T (&b)[NB][4], int act) {
+                                         const T (&b)[NB][4], int act,
+                                         RowDone done = RowDone{}) {
   if constexpr (MODE == TM_F16X3) {
     f16x4_t ah[4], al[4], bh[NB], bl[NB];
 #pragma unroll
@@ -562,6 +575,10 @@ __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
         acc[ar][q] += t;
       }
     }
+    // the next step's A loads after all products (issued right after the
+    // split they made the split's step 9% slower on the 32768-atom cell)
+#pragma unroll
+    for (int ar = 0; ar < 4; ++ar) done(ar);
   } else {
 #pragma unroll
     for (int ar = 0; ar < 4; ++ar) {
@@ -579,6 +596,7 @@ __device__ __forceinline__ void tile_mma(AccT (&acc)[4][NB], const T (&a)[4][4],
                                                              acc[ar][q], 0, 0, 0);
         }
       }
+      done(ar);
     }
   }
 }
@@ -746,16 +764,20 @@ __global__ __launch_bounds__(256, 2) void k_tile16(
     if (next(e0)) {
       tile_load_a<T>(fa, e0.pa, a_val, rowA, li, lq, amax);
       tile_load_b<NB, TB, T>(fb0, e0.pb, e0.lenB, lenBq, b_val, li, lq, bmax, e0.tmask);
+      // each A row of the next step is loaded as soon as the current step's
+      // products are done with that row
       for (;;) {
         const bool h1 = next(e1);
         tile_load_b<NB, TB, T>(fb1, e1.pb, e1.lenB, lenBq, b_val, li, lq, bmax, e1.tmask);
-        tile_mma<MODE, NB>(acc, fa, fb0, e0.act);
-        tile_load_a<T>(fa, e1.pa, a_val, rowA, li, lq, amax);
+        tile_mma<MODE, NB>(acc, fa, fb0, e0.act, [&](int ar) {
+          tile_load_a_row<T>(fa[ar], e1.pa[ar], a_val, rowA[ar], li, lq, amax);
+        });
         if (!h1) break;
         const bool h0 = next(e0);
         tile_load_b<NB, TB, T>(fb0, e0.pb, e0.lenB, lenBq, b_val, li, lq, bmax, e0.tmask);
-        tile_mma<MODE, NB>(acc, fa, fb1, e1.act);
-        tile_load_a<T>(fa, e0.pa, a_val, rowA, li, lq, amax);
+        tile_mma<MODE, NB>(acc, fa, fb1, e1.act, [&](int ar) {
+          tile_load_a_row<T>(fa[ar], e0.pa[ar], a_val, rowA[ar], li, lq, amax);
+        });
         if (!h0) break;
       }
     }
