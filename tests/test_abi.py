@@ -58,6 +58,13 @@ def test_host_side_argument_errors(lib):
     q.ix.tab = 8
     mq = L.LnvBsm(pat=ctypes.pointer(q), blk=4, dtype=L.F64, val=8)
     assert lib.lnv_bsm_multiply(1.0, ctypes.byref(m), ctypes.byref(mq), 0, 0.0, ctypes.byref(m), None) == L.EPATTERN
+    # op(B): 0, 1, or 2 (B symmetric, its half stored: atom tiles only, no traces)
+    pb = L.LnvPattern(n=4, n_items=1, nnzb=4, row_ptr=8, col=8, items=8)
+    pb.ix.tab = 8
+    mb = L.LnvBsm(pat=ctypes.pointer(pb), blk=4, dtype=L.F64, val=8)
+    for tb in (-1, 3):
+        assert lib.lnv_bsm_multiply(1.0, ctypes.byref(m), ctypes.byref(mb), tb, 0.0, ctypes.byref(m), None) == L.EINVAL
+    assert lib.lnv_bsm_multiply(1.0, ctypes.byref(m), ctypes.byref(mb), 2, 0.0, ctypes.byref(m), None) == L.EUNSUPPORTED
     # CG step: bad options are rejected before anything else
     o = L.LnvOpts(0, 1e-11, 0.1)
     assert lib.lnv_cg_step(None, None, None, None, 8.0, 0, ctypes.byref(o), None, None) == L.EINVAL
