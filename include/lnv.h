@@ -210,7 +210,8 @@ int lnv_atoms_rows(const lnv_atoms* A, const double* atom_pos, double* row_pos, 
  * col: device, atom CSR with nnz blocks): block p of atoms (i, j) starts at
  * the sum of n_i' n_j' over the blocks before it; *len_out (host, may be
  * NULL) = val_off[nnz], the values to allocate.  Set-up call: synchronises
- * s; LNV_EPATTERN for a malformed pattern. */
+ * s; LNV_EPATTERN for a malformed pattern.  Storage of the atom blocks of
+ * Sec. II.B (n_i x n_j per atom pair). */
 int lnv_vbsm_offsets(const lnv_atoms* A, const int32_t* row_ptr, const int32_t* col,
                      int64_t nnz, int64_t* val_off, int64_t* len_out, hipStream_t s);
 
@@ -225,7 +226,8 @@ int lnv_vbsm_pack(const lnv_vbsm* A, lnv_bsm* B, hipStream_t s);
 /* lnv_vbsm_unpack -- A = B back in atom blocks: element (x, y) of A's block
  * (i, j) is element (x mod 4, y mod 4) of B's block (row_start[i] + x/4,
  * row_start[j] + y/4), zero where B has no block.  B's pattern needs its
- * index; same dtype.  Every value of A is written. */
+ * index; same dtype.  Every value of A is written.  Back to the atom blocks
+ * of Sec. II.B. */
 int lnv_vbsm_unpack(const lnv_bsm* B, lnv_vbsm* A, hipStream_t s);
 
 /* ------------------------------------------------------------ errors
@@ -946,12 +948,14 @@ typedef struct lnv_pm_ws {
 
 /* lnv_pm_start -- K0 into K (on L's pattern) from T (on L's pattern) and H;
  * HT: scratch values on pat(H.L) (pattern with its index, items and cluster
- * plan), H.T.  Resets the step counter and history. */
+ * plan), H.T.  Resets the step counter and history.  First iterate of the
+ * canonical purification that starts the minimisation (Sec. II.C.2). */
 int lnv_pm_start(lnv_bsm* K, const lnv_bsm* T, const lnv_bsm* H, lnv_bsm* HT, double n_orb,
                  double n_elec, lnv_pm_ws* ws, hipStream_t s);
 
 /* lnv_pm_step -- one purification step of K (no-op once stopped or after
- * hist_len steps).  n_elec and tol as for the start and stop rule. */
+ * hist_len steps).  n_elec and tol as for the start and stop rule.  The
+ * generalised McWeeny step of the canonical purification (Sec. II.C.2). */
 int lnv_pm_step(lnv_bsm* K, const lnv_bsm* S, double n_elec, double tol, lnv_pm_ws* ws,
                 hipStream_t s);
 
