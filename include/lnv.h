@@ -580,7 +580,9 @@ int lnv_bsm_dot(const lnv_bsm* A, const lnv_bsm* B, double* partials, double* ou
  *      Vu (device [nnzb of Lu * 16], dtype of W) V's
  * Z, W, V are then filled by a transposing copy (Z's and L's patterns need
  * items and must be symmetric; a block whose transpose is missing comes out
- * NaN).  lnv_cg_step uses the same buffers for the electron-number
+ * NaN).  Exception: in a lean workspace (LS and XT left out) whose products
+ * run on the atom tiles, Z stays on its half -- V and the assembly read it
+ * there (lnv_bsm_multiply's transB = 2) -- and Z.val is not written.  lnv_cg_step uses the same buffers for the electron-number
  * check (Z, V at the new L) and Lu for the metric products P_L(T G T); in
  * the line search and the electron-number correction Lu and Vu hold L and
  * the direction on the half (weight 2 off the diagonal), the partners of
