@@ -272,6 +272,36 @@ def test_eval_matches_oracle(fx, request):
         assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
 
 
+def test_eval_with_cut_intermediates_matches_oracle(gpu):
+    """A 512-atom cell with a long H range (S/H/L 8/14/5 bohr), where cutting
+    X = H.L.S and Z = S.L.S to R_S + 2 R_L removes more than half of X's
+    natural-range blocks (57 %) and 8 % of Z's: E, N, G and F still equal
+    those of the dense oracle, which forms every product in full."""
+    from paper_2002_07704_amd.system import LNVSystem
+    w = W.diamond_workload("si512_cut", (4, 4, 4), seed=7, nfun=4, R=(8.0, 14.0, 5.0))
+    sysg, ref = LNVSystem(w, metric=None), ost.System(w)
+    n = ref.S.shape[0]
+    P = lambda R: ost.pattern_matrix(*ost.neighbours(w.pos, w.box, R), w.n)  # noqa: E731
+    LS, _ = ost.pattern_product(P(w.R_L), P(w.R_S))
+    Xn, _ = ost.pattern_product(P(w.R_H), LS)
+    Zn, _ = ost.pattern_product(P(w.R_S), LS)
+    assert sysg.pX.nnzb < 0.8 * Xn.nnz and sysg.pZ.nnzb < Zn.nnz
+    Ld = _rand_sym(n, ref.maskL, 9) + 0.2 * np.eye(n) * ref.maskL
+    _set(sysg, sysg.L, sysg.pL, Ld)
+    sysg.eval()
+    torch.cuda.synchronize()
+    E, N = (float(x) for x in sysg.EN.cpu())
+    Er, Nr, Gr, Fr = olnv.evaluate(Ld, ref.S, ref.H, ref.maskL)
+    print(f"X blocks {sysg.pX.nnzb} of {Xn.nnz}, Z {sysg.pZ.nnzb} of {Zn.nnz}; "
+          f"|dE|/atom {abs(E - Er) / w.n:.1e}", flush=True)
+    assert abs(E - Er) / w.n <= 1e-10, (E, Er)
+    assert abs(N - Nr) / w.n <= 1e-10, (N, Nr)
+    G = _dense(sysg, sysg.G, sysg.pL)
+    F = _dense(sysg, sysg.F, sysg.pL)
+    assert np.abs(G - Gr).max() <= 1e-12 * np.abs(Gr).max()
+    assert np.abs(F - Fr).max() <= 1e-12 * np.abs(Fr).max()
+
+
 def test_eval_is_bitwise_reproducible(si64):
     sysg, _ = si64
     sysg.cg_init()
