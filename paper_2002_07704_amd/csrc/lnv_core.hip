@@ -204,8 +204,17 @@ __global__ __launch_bounds__(256) void k_scalar(const double* __restrict__ parti
       rd.count = sg.row_off[cell + 1] - sg.row_off[cell];
     }
     if (rd.op == 0) {
-      double v = 0.0;
-      for (int t = threadIdx.x; t < rd.count; t += 256) v += partials[rd.off + (size_t)t * rd.stride];
+      // eight independent partial sums per thread, so eight loads are in
+      // flight at a time (one workgroup reads every partial of the stage);
+      // the order is fixed, so the result is reproducible bit for bit
+      double v8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int t = threadIdx.x;
+      for (; t + 7 * 256 < rd.count; t += 8 * 256) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v8[u] += partials[rd.off + (size_t)(t + u * 256) * rd.stride];
+      }
+      for (; t < rd.count; t += 256) v8[0] += partials[rd.off + (size_t)t * rd.stride];
+      double v = ((v8[0] + v8[1]) + (v8[2] + v8[3])) + ((v8[4] + v8[5]) + (v8[6] + v8[7]));
       v = block_sum(v, sh);
       if (threadIdx.x == 0) sc[rd.dst] = v;
     } else {
