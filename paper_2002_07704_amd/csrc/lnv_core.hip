@@ -461,7 +461,6 @@ __global__ __launch_bounds__(256) void k_assemble(
     const T* __restrict__ Wv, Ix zx,
     const T* __restrict__ Z, const T* __restrict__ V, double* __restrict__ G,
     double* __restrict__ F, double* __restrict__ partials, int zhalf) {
-  __shared__ double sh[16];
   const int item = blockIdx.x;
   const int i = items[2 * item], c0 = items[2 * item + 1];
   const int cnt = min(kWave, rp[i + 1] - c0);
@@ -501,9 +500,22 @@ __global__ __launch_bounds__(256) void k_assemble(
       s[5] = fma(g, f, s[5]);
     }
   }
-  for (int c = 0; c < 6; ++c) {
-    const double t = block_sum(s[c], sh);
-    if (threadIdx.x == 0) partials[(size_t)c * n_items + item] = t;
+  // the six partials in one exchange: wave sums, then the four waves' sums
+  // added in wave order by one thread each (block_sum's order, one barrier
+  // instead of twelve)
+  __shared__ double sh6[6][4];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s[c] = wave_sum(s[c]);
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sh6[c][threadIdx.x >> 6] = s[c];
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int c = threadIdx.x;
+    double t = 0.0;
+    for (int q = 0; q < 4; ++q) t += sh6[c][q];
+    partials[(size_t)c * n_items + item] = t;
   }
 }
 
